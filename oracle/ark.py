@@ -1,0 +1,142 @@
+"""ARS tableaux and the geometry-split IMEX step (oracle; test infrastructure only).
+
+Sec. 4.2.2 and App. C (Alg. imex_scheme_update): the explicit (s+1)-stage ERK
+and the s-stage SDIRK are synchronised by padding (cbar_{i+1} = c_i).  Per
+stage i: R^DG_i = R^DG(y^ex_i, y^im_{i-1}); y^ex_{i+1} from eq. erk_stage_update;
+then the implicit stage y^im_i from eqs. dirk_stage_update_* with interface
+data y^ex_{i+1}.  After the loop: the final explicit update (eq.
+erk_solution_update) unless the ERK is FSAL, and U^im_{n+1} = y^im_s when the
+SDIRK is stiffly accurate (eq. dirk_solution_update otherwise).
+
+The ARS schemes are those of Ascher, Ruuth and Spiteri (1997) that the paper
+adopts (Sec. 4.2.2); their constants are not printed in the paper and are
+written here from that reference.  For ARS(3,4,3) the published 10-digit
+decimals are used with the explicit row sums made exact (c-bar consistency).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import physics as ph
+from .basis import Basis
+from .dg import Geometry, apply_minv, dg_residual, mass_matrix
+from .hdg import HDGSystem, init_facets, init_mixed
+from .mesh import Mesh
+
+
+class Tableau:
+    def __init__(self, name: str):
+        self.name = name
+        if name == "ARS222":
+            g = 1.0 - 1.0 / math.sqrt(2.0)
+            d = 1.0 - 1.0 / (2.0 * g)
+            self.s = 2
+            self.Ae = np.array([[0.0, 0.0, 0.0], [g, 0.0, 0.0], [d, 1.0 - d, 0.0]])
+            self.be = np.array([d, 1.0 - d, 0.0])
+            self.Ai = np.array([[g, 0.0], [1.0 - g, g]])
+            self.bi = np.array([1.0 - g, g])
+        elif name == "ARS343":
+            r = np.roots([6.0, -18.0, 9.0, -1.0])
+            r = np.real(r[(np.abs(np.imag(r)) < 1e-12)])
+            g = float(r[(r > 0.4) & (r < 0.5)][0])
+            b1 = -1.5 * g * g + 4.0 * g - 0.25
+            b2 = 1.5 * g * g - 5.0 * g + 1.25
+            a32 = 0.3966543747
+            a42 = a43 = 0.5529291479
+            self.s = 3
+            self.Ae = np.array([[0.0, 0.0, 0.0, 0.0],
+                                [g, 0.0, 0.0, 0.0],
+                                [(1.0 + g) / 2.0 - a32, a32, 0.0, 0.0],
+                                [1.0 - a42 - a43, a42, a43, 0.0]])
+            self.be = np.array([0.0, b1, b2, g])
+            self.Ai = np.array([[g, 0.0, 0.0], [(1.0 - g) / 2.0, g, 0.0], [b1, b2, g]])
+            self.bi = np.array([b1, b2, g])
+        else:
+            raise ValueError(name)
+        self.ce = self.Ae.sum(axis=1)
+        self.ci = self.Ai.sum(axis=1)
+        self.fsal = bool(np.array_equal(self.be, self.Ae[-1])) and self.ce[-1] == 1.0
+        self.stiffly_accurate = bool(np.array_equal(self.bi, self.Ai[-1])) and self.ci[-1] == 1.0
+
+
+class IMEXSolver:
+    """The oracle's full IMEX integrator on one workload."""
+
+    def __init__(self, wl, U0=None):
+        self.wl = wl
+        self.mesh = Mesh(wl)
+        self.basis = Basis(wl.degree)
+        self.gas = ph.Gas(wl.gamma, wl.R, wl.mu, wl.Pr)
+        self.geo = Geometry(self.mesh, self.basis)
+        self.tab = Tableau(wl.tableau)
+        self.system = HDGSystem(wl, self.mesh, self.basis, self.gas)
+        self.M = mass_matrix(self.basis, self.geo)
+        if U0 is None:
+            U0 = self.initial_state()
+        self.U = np.array(U0, dtype=float)
+        self.Uhat = init_facets(self.U, self.mesh, self.basis)
+        self.Q = init_mixed(self.U, self.Uhat, self.system)
+        self.newton_its = []
+
+    def initial_state(self):
+        X, Y = self.mesh.node_coords(self.basis)
+        E, nn = X.shape
+        elem = np.repeat(np.arange(E)[:, None], nn, axis=1)
+        node = np.repeat(np.arange(nn)[None, :], E, axis=0)
+        U = self.wl.ic(X, Y, elem, node)                # (4, E, nn)
+        return np.moveaxis(U, 0, 1).copy()
+
+    def mass_apply(self, U):
+        return np.einsum("enm,evm->evn", self.M, U)
+
+    def dg(self, Y, Q):
+        return dg_residual(Y, Q, self.wl, self.mesh, self.basis, self.gas)
+
+    def step(self):
+        tab, dt = self.tab, self.wl.dt
+        ex, im = self.mesh.ex_elems, self.mesh.im_elems
+        Un = self.U.copy()
+        Y = self.U.copy()
+        Rdg, Rhdg = [], []
+        its = []
+        for i in range(1, tab.s + 1):
+            Rdg.append(self.dg(Y, self.Q))
+            acc = sum(tab.Ae[i, j] * Rdg[j] for j in range(i))
+            Y[ex] = Un[ex] - dt * apply_minv(acc[ex], self.basis, _sub(self.geo, ex))
+            if len(im):
+                rhs = self.mass_apply(Un)[im]
+                for j in range(i - 1):
+                    rhs = rhs - dt * tab.Ai[i - 1, j] * Rhdg[j]
+                n_it, Rh = self.system.newton(Y, self.Q, self.Uhat, dt * tab.Ai[i - 1, i - 1], rhs)
+                its.append(n_it)
+                Rhdg.append(Rh)
+        if tab.fsal:
+            self.U[ex] = Y[ex]
+        else:
+            Rdg.append(self.dg(Y, self.Q))
+            acc = sum(tab.be[j] * Rdg[j] for j in range(tab.s + 1))
+            self.U[ex] = Un[ex] - dt * apply_minv(acc[ex], self.basis, _sub(self.geo, ex))
+        if len(im):
+            if tab.stiffly_accurate:
+                self.U[im] = Y[im]
+            else:
+                acc = sum(tab.bi[j] * Rhdg[j] for j in range(tab.s))
+                self.U[im] = Un[im] - dt * apply_minv(acc, self.basis, _sub(self.geo, im))
+        self.newton_its.append(its)
+
+    def run(self, steps=None):
+        for _ in range(self.wl.steps if steps is None else steps):
+            self.step()
+        return self.U
+
+
+class _sub:
+    """Geometry restricted to a subset of elements."""
+
+    def __init__(self, geo: Geometry, elems):
+        self.jac = geo.jac[elems]
+        self.sx = geo.sx[elems]
+        self.sy = geo.sy[elems]
+        self.fjac = geo.fjac[elems]
