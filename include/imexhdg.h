@@ -1,0 +1,182 @@
+/*
+ * imexhdg.h -- C ABI of the MI355X (gfx950) engine for the geometry-split
+ * additive Runge-Kutta IMEX scheme with explicit DG-IP and implicit HDG-IP /
+ * HDG-MX of Ellmenreich, Shehadi and Lederer ("IMEX Schemes for Compressible
+ * Flow using Hybridizable Discontinuous Galerkin Methods").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: imex_status; 0 on success, < 0 on error.  No entry point
+ *   throws or aborts; on error imex_last_error() holds a message and no output
+ *   has been modified unless stated otherwise.
+ * - Pointers named "dev" are device pointers (hipMalloc'd or from torch) on the
+ *   device the context was created on; all work is queued on the context's
+ *   stream and the call returns once that work is complete.  Pointers named
+ *   "host" are host memory.  The caller owns every pointer it passes; the
+ *   library owns its workspaces (allocated in imex_create / imex_set_regions,
+ *   freed in imex_destroy).
+ * - Mesh (Sec. 3.1): 2D tensor-product mesh of nx x ny axis-aligned quads;
+ *   element e = i + nx*j covers [x_i, x_{i+1}] x [y_j, y_{j+1}].
+ * - Element state layout: U[e][v][n], e over ALL elements, v = 0..3 for
+ *   (rho, rho u, rho v, rho E), n = a + (k+1) b the nodal index of the
+ *   Gauss-Legendre node (xi_a, xi_b), x fastest.  FP64.
+ * - Facet state layout: Uhat[f][v][m], f over the HDG facets (facets touching
+ *   an implicit element) in the library's order (vertical facets first, then
+ *   horizontal, each lexicographic), m = facet node in increasing coordinate.
+ * - A context is not safe for concurrent use from several threads.
+ */
+#ifndef IMEXHDG_H
+#define IMEXHDG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IMEX_OK = 0,
+  IMEX_EINVAL = -1,      /* bad argument: sizes, flags, null pointer            */
+  IMEX_ENOMEM = -2,      /* device allocation failed                             */
+  IMEX_EDEVICE = -3,     /* a HIP call failed                                    */
+  IMEX_ENOCONV = -4,     /* Newton did not converge; state left at last iterate  */
+  IMEX_ENONFINITE = -5,  /* a non-finite value appeared in the Newton iteration  */
+  IMEX_ENOTIMPL = -6,    /* option combination not implemented                   */
+  IMEX_ESTATE = -7       /* call order violated (e.g. solve before set_regions)  */
+} imex_status;
+
+enum { IMEX_BC_PERIODIC = 0, IMEX_BC_FARFIELD = 1, IMEX_BC_WALL = 2 };
+enum { IMEX_FLUX_VIJAYASUNDARAM = 0, IMEX_FLUX_LAX_FRIEDRICHS = 1 };   /* DG convective flux        */
+enum { IMEX_HDG_FLUX_FVS = 0, IMEX_HDG_FLUX_LF = 1 };                  /* HDG stabilisation S_c     */
+enum { IMEX_HDG_IP = 0, IMEX_HDG_MX = 1 };                             /* implicit formulation      */
+enum { IMEX_FP64 = 0, IMEX_FP32_REFINE = 1 };                          /* implicit linear algebra   */
+
+typedef struct imex_ctx imex_ctx;
+
+/* Mesh and degree (Sec. 3.1).  bc[] for the sides -x, +x, -y, +y; periodic must
+ * be set on both sides of an axis.  degree k in 1..4; the volume and facet rules
+ * use ceil((3k+1)/2) Gauss points per direction (over-integration, Sec. 5). */
+typedef struct {
+  int nx, ny;
+  const double* xgrid;   /* host, nx+1 strictly increasing */
+  const double* ygrid;   /* host, ny+1 strictly increasing */
+  int bc[4];
+  int degree;
+} imex_mesh_desc;
+
+/* Gas model (Sec. 2): ideal gas p = rho R theta, constant mu, kappa = c_p mu / Pr,
+ * lambda = -2 mu / 3.  viscous = 0 gives the Euler equations.  u_inf is the
+ * conservative far-field state (App. B). */
+typedef struct {
+  double gamma, R, mu, Pr;
+  int viscous;
+  double u_inf[4];
+} imex_physics;
+
+typedef struct {
+  int dg_flux;           /* IMEX_FLUX_*                                                     */
+  int hdg_flux;          /* IMEX_HDG_FLUX_*                                                 */
+  int hdg_variant;       /* IMEX_HDG_IP | IMEX_HDG_MX                                       */
+  double alpha_dg;       /* IP penalty factor of DG (1 in the paper, Sec. 3.3)              */
+  double alpha_hdg;      /* IP penalty factor of HDG-IP (10 in the paper, Sec. 3.4)         */
+  int precision;         /* IMEX_FP64 | IMEX_FP32_REFINE                                    */
+  double newton_rtol;    /* stop when max|dU| <= rtol max|U| and max|dUhat| <= rtol max|Uhat| */
+  int newton_maxit;
+  double gmres_rtol;     /* relative residual of the condensed facet solve                  */
+  int gmres_restart;     /* 1..64                                                           */
+  int gmres_maxit;
+} imex_options;
+
+/* ARK pair synchronised by padding (Sec. 4.2.2): explicit (s+1)x(s+1) tableau Ae
+ * (row-major in a 4x4 array), weights be[s+1]; implicit s x s tableau Ai (row-major
+ * in a 3x3 array), weights bi[s].  s in 1..3. */
+typedef struct {
+  int s;
+  double Ae[16];
+  double be[4];
+  double Ai[9];
+  double bi[3];
+  int fsal;              /* be == last row of Ae and c = 1: U^ex_{n+1} = y^ex_{s+1}       */
+  int stiffly_accurate;  /* bi == last row of Ai and c = 1: U^im_{n+1} = y^im_s           */
+} imex_tableau;
+
+typedef struct {
+  int newton_its;        /* Newton iterations (summed over stages for a step)             */
+  int gmres_its;         /* GMRES iterations (summed)                                     */
+  double newton_last_du; /* last max|dU| / max|U|                                         */
+  double t_assemble_ms;  /* device time in assembly + condensation                        */
+  double t_solve_ms;     /* device time in the facet solve                                */
+} imex_stats;
+
+/* Create a context for one mesh on the current HIP device.  stream: hipStream_t
+ * or NULL for the default stream.  Errors: EINVAL (bad mesh, degree, options),
+ * ENOMEM, EDEVICE. */
+imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, const imex_options* opt,
+                        void* stream, imex_ctx** out);
+
+/* Geometry split T = T^im U T^ex (Sec. 4, eq. union_mesh): implicit_flag[e] != 0
+ * marks element e implicit.  host, n_elem bytes.  Builds the HDG facet set and
+ * allocates the implicit workspaces.  Errors: EINVAL (explicit element on a wall
+ * boundary), ENOMEM. */
+imex_status imex_set_regions(imex_ctx* ctx, const unsigned char* implicit_flag);
+
+/* out[0..7] = n_elem, n_implicit, n_explicit, nodes per element, n_hdg_facets,
+ *             unknowns per facet (4(k+1)), quadrature points per direction,
+ *             workspace bytes.  host. */
+imex_status imex_query_sizes(const imex_ctx* ctx, long long out[8]);
+
+/* Physical coordinates of the element nodes, host arrays x[n_elem*nn], y[n_elem*nn]. */
+imex_status imex_node_coords(const imex_ctx* ctx, double* x_host, double* y_host);
+
+/* Facet state from element traces: mean of the adjacent traces at the facet nodes,
+ * the explicit trace on interface facets (their Dirichlet value, eq.
+ * interface_bilinearform_implicit_facet).  U dev (all elements), Uhat dev (out). */
+imex_status imex_init_facets(imex_ctx* ctx, const double* U, double* Uhat);
+
+/* Explicit DG-IP residual R^DG (Sec. 3.3, eq. bilinear_form_interior_sdg with the
+ * far-field form of App. B.1.1 and the interface form of eq.
+ * interface_bilinearform_explicit), with M dU/dt = -R.  U dev, all elements
+ * (implicit entries supply the interface traces y^im); Uhat dev, used only for
+ * HDG-MX coupling (the implicit side's mixed variables are lifted from U, Uhat),
+ * may be NULL otherwise; R dev out, rows of explicit elements written, rows of
+ * implicit elements set to zero. */
+imex_status imex_dg_residual(imex_ctx* ctx, const double* U, const double* Uhat, double* R);
+
+/* One SDIRK stage of the implicit region (eqs. dirk_stage_update_solution /
+ * _facet / _mixed) solved by Newton (Sec. 4.3) with static condensation
+ * (eqs. statically_condensed_system, SchurCompliment, local_solve_static_condensation)
+ * and a GMRES facet solve:
+ *   M y + dt_aii R^HDG(y, yhat) - rhs = 0,  Rhat(y, yhat, U^ex) = 0.
+ * rhs dev [e][v][n] (implicit rows read); U dev inout: explicit rows are the
+ * interface data y^ex_{i+1} (read), implicit rows the initial guess on entry and
+ * the stage solution on exit; Uhat dev inout; R_out dev (nullable): R^HDG at the
+ * converged state in implicit rows.  st host (nullable).
+ * Errors: ESTATE (no implicit region), ENOCONV, ENONFINITE. */
+imex_status imex_implicit_stage_solve(imex_ctx* ctx, double dt_aii, const double* rhs, double* U,
+                                      double* Uhat, double* R_out, imex_stats* st);
+
+/* One time step of Alg. imex_scheme_update (App. C) from t_n to t_n + dt:
+ * U dev inout (all elements), Uhat dev inout.  st host (nullable). */
+imex_status imex_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt, double* U, double* Uhat,
+                          imex_stats* st);
+
+/* out[v] = sum over elements of int_T U_v (host, 4 doubles); U dev. */
+imex_status imex_conservation_sums(imex_ctx* ctx, const double* U, double out[4]);
+
+/* Element-local Newton system of the implicit stage (inspection of the assembly):
+ * for each implicit element (in increasing element index) the residual rows f
+ * [NU], facet rows h [NF] and the blocks K [NU x NU], C [NU x NF], D [NF x NU],
+ * E [NF x NF] (row-major) of the linearisation in (U_T, Uhat on dT), with the
+ * mixed variables eliminated for HDG-MX.  NU = 4 (k+1)^2, NF = 16 (k+1), facet
+ * unknowns of an element ordered face 0..3 (x-, x+, y-, y+), then variable, then
+ * node.  All pointers dev, sized for n_implicit elements. */
+imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, const double* U,
+                              const double* Uhat, double* f, double* h, double* K, double* C, double* D,
+                              double* E);
+
+const char* imex_status_str(imex_status s);
+const char* imex_last_error(const imex_ctx* ctx);
+void imex_destroy(imex_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMEXHDG_H */

@@ -83,32 +83,46 @@ def mixed_traces(Q, f, basis: Basis):
     return val[:3], val[3:]
 
 
-def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas):
-    """R^DG on every explicit element (zero rows on implicit elements).
+class _Subset:
+    """Geometry of a subset of elements."""
+
+    def __init__(self, geo: Geometry, idx):
+        self.jac = geo.jac[idx]
+        self.sx = geo.sx[idx]
+        self.sy = geo.sy[idx]
+        self.fjac = geo.fjac[idx]
+
+
+def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas, elems=None):
+    """R^DG on explicit elements (zero rows on implicit elements).
 
     U:     (E, 4, nn) all elements; implicit entries are the implicit stage state y^im.
     Qmix:  (E, 5, nn) mixed variables of implicit elements (HDG-MX coupling) or None.
+    elems: optional subset of element indices; the result then has one row per entry.
     """
-    geo = Geometry(mesh, basis)
+    geo_all = Geometry(mesh, basis)
+    sel = np.arange(mesh.E) if elems is None else np.asarray(elems)
+    geo = _Subset(geo_all, sel)
+    lchar = mesh.lchar[sel]
     k = basis.k
-    Uq, Gq = vol_eval(U, basis, geo)
+    Us = U[sel]
+    Uq, Gq = vol_eval(Us, basis, geo)
     vol = -ph.convective_flux(Uq, gas)
     if wl.viscous:
         vol = vol + ph.viscous_flux(Uq, Gq, gas)
     R = test_volume(vol, basis, geo)
     uinf = wl.u_inf.reshape(4, 1, 1)
+    implicit_sel = mesh.implicit[sel]
     for f in range(4):
         n = Basis.NORMALS[f]
-        Uf, Gf = face_eval(U, f, basis, geo)
-        nb = mesh.nbr[:, f]
+        Uf, Gf = face_eval(Us, f, basis, geo)
+        nb = mesh.nbr[sel, f]
         has_nb = nb >= 0
         nbs = np.where(has_nb, nb, 0)
-        UNall, GNall = face_eval(U, OPPOSITE[f], basis, geo)
-        UN = UNall[:, nbs]
-        GN = GNall[:, :, nbs]
+        UN, GN = face_eval(U[nbs], OPPOSITE[f], basis, _Subset(geo_all, nbs))
         nb_implicit = has_nb & mesh.implicit[nbs]
-        interface = nb_implicit & ~mesh.implicit
-        farfield = (~has_nb) & (mesh.bctype[:, f] == BC_FARFIELD)
+        interface = nb_implicit & ~implicit_sel
+        farfield = (~has_nb) & (mesh.bctype[sel, f] == BC_FARFIELD)
         # convective numerical flux
         if wl.dg_flux == FLUX_LAX_FRIEDRICHS:
             Fint = ph.flux_lax_friedrichs(Uf, UN, n, gas)
@@ -121,12 +135,12 @@ def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas):
             # neighbour viscous flux: DG side uses grad U^-, an HDG-MX neighbour its mixed variables
             FvN = ph.viscous_flux(UN, GN, gas)
             if wl.hdg_variant == HDG_MX and Qmix is not None:
-                eps, phi = mixed_traces(Qmix, OPPOSITE[f], basis)
-                FvN_mx = ph.viscous_flux_mixed(UN, eps[:, nbs], phi[:, nbs], gas)
+                eps, phi = mixed_traces(Qmix[nbs], OPPOSITE[f], basis)
+                FvN_mx = ph.viscous_flux_mixed(UN, eps, phi, gas)
                 FvN = np.where(nb_implicit[None, None, :, None], FvN_mx, FvN)
             Fv = ph.viscous_flux(Uf, Gf, gas)
-            tau_int = wl.alpha_dg * (k + 1) ** 2 / np.minimum(mesh.lchar, mesh.lchar[nbs])
-            tau_own = wl.alpha_dg * (k + 1) ** 2 / mesh.lchar
+            tau_int = wl.alpha_dg * (k + 1) ** 2 / np.minimum(lchar, mesh.lchar[nbs])
+            tau_own = wl.alpha_dg * (k + 1) ** 2 / lchar
             tau = np.where(interface | ~has_nb, tau_own, tau_int)[None, :, None]
             # interior / interface
             dU = Uf - UN
@@ -148,7 +162,7 @@ def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas):
             s = s + np.where(farfield[None, :, None], cons_far + pen_far, cons + pen)
             g = np.where(farfield[None, None, :, None], adj_far, adj)
         R += test_face(s, g, f, basis, geo)
-    R[mesh.implicit] = 0.0
+    R[implicit_sel] = 0.0
     return R
 
 

@@ -1,0 +1,236 @@
+"""ctypes binding of libimexhdg.so (argument marshalling only).
+
+Every numerical step runs in the HIP kernels behind the C ABI declared in
+include/imexhdg.h; this module converts torch tensors to device pointers and
+Python values to the ABI's structs.  There is no fallback: if the library is
+missing or the device is not a HIP GPU, construction fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import tableaux
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libimexhdg.so")
+
+IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ENONFINITE",
+               -6: "ENOTIMPL", -7: "ESTATE"}
+
+EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
+           "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
+           "imex_local_system", "imex_status_str", "imex_last_error", "imex_destroy"]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("xgrid", ctypes.POINTER(ctypes.c_double)),
+                ("ygrid", ctypes.POINTER(ctypes.c_double)), ("bc", ctypes.c_int * 4), ("degree", ctypes.c_int)]
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("viscous", ctypes.c_int), ("u_inf", ctypes.c_double * 4)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("dg_flux", ctypes.c_int), ("hdg_flux", ctypes.c_int), ("hdg_variant", ctypes.c_int),
+                ("alpha_dg", ctypes.c_double), ("alpha_hdg", ctypes.c_double), ("precision", ctypes.c_int),
+                ("newton_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
+                ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int)]
+
+
+class Tableau(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("Ae", ctypes.c_double * 16), ("be", ctypes.c_double * 4),
+                ("Ai", ctypes.c_double * 9), ("bi", ctypes.c_double * 3), ("fsal", ctypes.c_int),
+                ("stiffly_accurate", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int), ("gmres_its", ctypes.c_int), ("newton_last_du", ctypes.c_double),
+                ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libimexhdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not built: run paper_2607_16044_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    lib.imex_create.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(Physics), ctypes.POINTER(Options), P,
+                                ctypes.POINTER(P)]
+    lib.imex_set_regions.argtypes = [P, ctypes.POINTER(ctypes.c_ubyte)]
+    lib.imex_query_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.imex_node_coords.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.imex_init_facets.argtypes = [P, P, P]
+    lib.imex_dg_residual.argtypes = [P, P, P, P]
+    lib.imex_implicit_stage_solve.argtypes = [P, D, P, P, P, P, ctypes.POINTER(Stats)]
+    lib.imex_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, ctypes.POINTER(Stats)]
+    lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
+    lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
+    lib.imex_status_str.argtypes = [ctypes.c_int]
+    lib.imex_status_str.restype = ctypes.c_char_p
+    lib.imex_last_error.argtypes = [P]
+    lib.imex_last_error.restype = ctypes.c_char_p
+    lib.imex_destroy.argtypes = [P]
+    lib.imex_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("imex_status_str", "imex_last_error", "imex_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class IMEXError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{IMEX_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Engine:
+    """One mesh and region split on the current HIP device."""
+
+    def __init__(self, wl, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
+                 gmres_rtol: float = 1e-13, gmres_restart: int = 60, gmres_maxit: int = 600,
+                 device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the engine runs only on the GPU")
+        self.lib = load_library()
+        self.wl = wl
+        self.device = torch.device("cuda") if device is None else device
+        self._xg = np.ascontiguousarray(wl.xgrid, dtype=np.float64)
+        self._yg = np.ascontiguousarray(wl.ygrid, dtype=np.float64)
+        mesh = MeshDesc(wl.nx, wl.ny, self._xg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        self._yg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), (ctypes.c_int * 4)(*wl.bc),
+                        wl.degree)
+        phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
+        opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != 0:
+            raise IMEXError(st, self.lib.imex_last_error(None).decode())
+        self.ctx = ctx
+        self.set_regions(wl.implicit_flags())
+        self.tableau = tableaux.get(wl.tableau)
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st: int):
+        if st != 0:
+            raise IMEXError(st, self.lib.imex_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.imex_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI -----------------------------------------------------------------
+    def set_regions(self, flags: np.ndarray):
+        f = np.ascontiguousarray(flags, dtype=np.uint8)
+        self._check(self.lib.imex_set_regions(self.ctx, f.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+        self.sizes = self.query_sizes()
+
+    def query_sizes(self):
+        out = (ctypes.c_longlong * 8)()
+        self._check(self.lib.imex_query_sizes(self.ctx, out))
+        keys = ["n_elem", "n_implicit", "n_explicit", "nodes_per_elem", "n_hdg_facets", "facet_unknowns",
+                "quad_points", "workspace_bytes"]
+        return dict(zip(keys, list(out)))
+
+    def node_coords(self):
+        n = self.sizes["n_elem"] * self.sizes["nodes_per_elem"]
+        x = np.zeros(n)
+        y = np.zeros(n)
+        self._check(self.lib.imex_node_coords(self.ctx, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        nn = self.sizes["nodes_per_elem"]
+        return x.reshape(-1, nn), y.reshape(-1, nn)
+
+    def state_shape(self):
+        return (self.sizes["n_elem"], 4, self.sizes["nodes_per_elem"])
+
+    def facet_shape(self):
+        return (self.sizes["n_hdg_facets"], 4, self.sizes["facet_unknowns"] // 4)
+
+    def initial_state(self) -> torch.Tensor:
+        """Nodal interpolation of the workload's initial condition at this library's nodes."""
+        X, Y = self.node_coords()
+        E, nn = X.shape
+        elem = np.repeat(np.arange(E)[:, None], nn, axis=1)
+        node = np.repeat(np.arange(nn)[None, :], E, axis=0)
+        U = np.moveaxis(self.wl.ic(X, Y, elem, node), 0, 1)
+        return torch.tensor(np.ascontiguousarray(U), dtype=torch.float64, device=self.device)
+
+    def init_facets(self, U: torch.Tensor) -> torch.Tensor:
+        Uhat = torch.zeros(self.facet_shape(), dtype=torch.float64, device=self.device)
+        if Uhat.numel():
+            self._check(self.lib.imex_init_facets(self.ctx, _ptr(U), _ptr(Uhat)))
+        return Uhat
+
+    def dg_residual(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None) -> torch.Tensor:
+        R = torch.empty_like(U)
+        self._check(self.lib.imex_dg_residual(self.ctx, _ptr(U), _ptr(Uhat), _ptr(R)))
+        return R
+
+    def implicit_stage_solve(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):
+        R = torch.zeros_like(U)
+        st = Stats()
+        self._check(self.lib.imex_implicit_stage_solve(self.ctx, dt_a, _ptr(rhs), _ptr(U), _ptr(Uhat), _ptr(R),
+                                                       ctypes.byref(st)))
+        return R, st.as_dict()
+
+    def ark_step(self, dt: float, U: torch.Tensor, Uhat: Optional[torch.Tensor]):
+        st = Stats()
+        tab = self.tableau.to_ctypes(Tableau)
+        self._check(self.lib.imex_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat), ctypes.byref(st)))
+        return st.as_dict()
+
+    def conservation_sums(self, U: torch.Tensor):
+        out = (ctypes.c_double * 4)()
+        self._check(self.lib.imex_conservation_sums(self.ctx, _ptr(U), out))
+        return np.array(list(out))
+
+    def local_system(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):
+        n_im = self.sizes["n_implicit"]
+        k1 = self.wl.degree + 1
+        NU, NF = 4 * k1 * k1, 16 * k1
+        kw = dict(dtype=torch.float64, device=self.device)
+        f = torch.zeros(n_im, NU, **kw)
+        h = torch.zeros(n_im, NF, **kw)
+        K = torch.zeros(n_im, NU, NU, **kw)
+        C = torch.zeros(n_im, NU, NF, **kw)
+        D = torch.zeros(n_im, NF, NU, **kw)
+        E = torch.zeros(n_im, NF, NF, **kw)
+        self._check(self.lib.imex_local_system(self.ctx, dt_a, _ptr(rhs), _ptr(U), _ptr(Uhat), _ptr(f), _ptr(h),
+                                               _ptr(K), _ptr(C), _ptr(D), _ptr(E)))
+        return f, h, K, C, D, E

@@ -1,0 +1,515 @@
+// C ABI of the IMEX DG/HDG engine: context set-up, region split and the ARK
+// step driver (Alg. imex_scheme_update of App. C).  All arithmetic runs in the
+// kernels of dg.hip and hdg.hip; this file only builds tables, owns memory and
+// sequences launches on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace imex;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+imex_status fail(imex_ctx* c, imex_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+#define HIP_TRY(c, expr)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(c, IMEX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+// Gauss-Legendre points and weights on [-1,1] by Newton's method on P_n.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) { p1 = z; p0 = 1.0; }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;                       // ascending order
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+double lag(const double* nodes, int np, int a, double x) {
+  double r = 1.0;
+  for (int b = 0; b < np; ++b)
+    if (b != a) r *= (x - nodes[b]) / (nodes[a] - nodes[b]);
+  return r;
+}
+
+double dlag(const double* nodes, int np, int a, double x) {
+  double s = 0.0;
+  for (int c = 0; c < np; ++c) {
+    if (c == a) continue;
+    double t = 1.0 / (nodes[a] - nodes[c]);
+    for (int b = 0; b < np; ++b)
+      if (b != a && b != c) t *= (x - nodes[b]) / (nodes[a] - nodes[b]);
+    s += t;
+  }
+  return s;
+}
+
+void build_table(int K, BasisTable& T) {
+  std::memset(&T, 0, sizeof(T));
+  const int np = K + 1, nq = (3 * K + 2) / 2;
+  double nodes[MAXNP], nw[MAXNP], z[MAXNQ], w[MAXNQ];
+  gauss_legendre(np, nodes, nw);
+  gauss_legendre(nq, z, w);
+  for (int a = 0; a < np; ++a) {
+    T.NW[a] = nw[a];
+    for (int q = 0; q < nq; ++q) {
+      T.L[q][a] = lag(nodes, np, a, z[q]);
+      T.D[q][a] = dlag(nodes, np, a, z[q]);
+    }
+    T.LE[0][a] = lag(nodes, np, a, -1.0);
+    T.LE[1][a] = lag(nodes, np, a, 1.0);
+    T.DE[0][a] = dlag(nodes, np, a, -1.0);
+    T.DE[1][a] = dlag(nodes, np, a, 1.0);
+  }
+  for (int q = 0; q < nq; ++q) T.W[q] = w[q];
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) { *dst = nullptr; return hipSuccess; }
+  hipError_t e = hipMalloc(dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+void free_regions(imex_ctx* c) {
+  for (int** p : {&c->d_im_list, &c->d_ex_list, &c->d_face_kind, &c->d_efacet, &c->d_hf_side, &c->d_hf_face,
+                  &c->d_hf_elem}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  Workspace& w = c->ws;
+  for (double** p : {&w.blk, &w.scr, &w.X, &w.y, &w.S, &w.r, &w.Pinv, &w.gm, &w.red}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  for (float** p : {&w.X32, &w.S32}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  if (w.hred) hipHostFree(w.hred);
+  w.hred = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* imex_status_str(imex_status s) {
+  switch (s) {
+    case IMEX_OK: return "ok";
+    case IMEX_EINVAL: return "invalid argument";
+    case IMEX_ENOMEM: return "out of device memory";
+    case IMEX_EDEVICE: return "HIP error";
+    case IMEX_ENOCONV: return "Newton did not converge";
+    case IMEX_ENONFINITE: return "non-finite value";
+    case IMEX_ENOTIMPL: return "not implemented";
+    case IMEX_ESTATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* imex_last_error(const imex_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, const imex_options* opt, void* stream,
+                        imex_ctx** out) {
+  if (!mesh || !phys || !opt || !out) return fail(nullptr, IMEX_EINVAL, "null argument");
+  *out = nullptr;
+  if (mesh->nx < 1 || mesh->ny < 1 || !mesh->xgrid || !mesh->ygrid)
+    return fail(nullptr, IMEX_EINVAL, "mesh needs nx, ny >= 1 and both grids");
+  if (mesh->degree < 1 || mesh->degree > 4) return fail(nullptr, IMEX_EINVAL, "degree must be in 1..4");
+  for (int a = 0; a < 2; ++a) {
+    const bool p0 = mesh->bc[2 * a] == IMEX_BC_PERIODIC, p1 = mesh->bc[2 * a + 1] == IMEX_BC_PERIODIC;
+    if (p0 != p1) return fail(nullptr, IMEX_EINVAL, "periodic boundaries must pair");
+  }
+  for (int s = 0; s < 4; ++s)
+    if (mesh->bc[s] < 0 || mesh->bc[s] > 2) return fail(nullptr, IMEX_EINVAL, "unknown boundary type");
+  for (int i = 0; i < mesh->nx; ++i)
+    if (!(mesh->xgrid[i + 1] > mesh->xgrid[i])) return fail(nullptr, IMEX_EINVAL, "xgrid not increasing");
+  for (int j = 0; j < mesh->ny; ++j)
+    if (!(mesh->ygrid[j + 1] > mesh->ygrid[j])) return fail(nullptr, IMEX_EINVAL, "ygrid not increasing");
+  if (!(phys->gamma > 1.0) || !(phys->R > 0.0) || phys->mu < 0.0 || !(phys->Pr > 0.0))
+    return fail(nullptr, IMEX_EINVAL, "bad gas constants");
+  if (opt->hdg_variant != IMEX_HDG_IP && opt->hdg_variant != IMEX_HDG_MX)
+    return fail(nullptr, IMEX_EINVAL, "hdg_variant");
+  if (opt->precision != IMEX_FP64 && opt->precision != IMEX_FP32_REFINE)
+    return fail(nullptr, IMEX_EINVAL, "precision");
+  if (opt->newton_maxit < 1 || opt->gmres_restart < 1 || opt->gmres_restart > 64 || opt->gmres_maxit < 1 || !(opt->newton_rtol > 0.0) ||
+      !(opt->gmres_rtol > 0.0))
+    return fail(nullptr, IMEX_EINVAL, "solver options");
+
+  imex_ctx* c = new (std::nothrow) imex_ctx();
+  if (!c) return fail(nullptr, IMEX_ENOMEM, "host allocation");
+  hipGetDevice(&c->device);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->nx = mesh->nx;
+  c->ny = mesh->ny;
+  c->E = c->nx * c->ny;
+  c->K = mesh->degree;
+  c->NP = c->K + 1;
+  c->NQ = (3 * c->K + 2) / 2;
+  c->NN = c->NP * c->NP;
+  std::memcpy(c->bc, mesh->bc, sizeof(c->bc));
+  c->xg.assign(mesh->xgrid, mesh->xgrid + c->nx + 1);
+  c->yg.assign(mesh->ygrid, mesh->ygrid + c->ny + 1);
+  c->opt = *opt;
+  Gas& g = c->gas;
+  g.gamma = phys->gamma;
+  g.R = phys->R;
+  g.mu = phys->viscous ? phys->mu : 0.0;
+  g.Pr = phys->Pr;
+  g.cv = g.R / (g.gamma - 1.0);
+  g.cp = g.gamma * g.cv;
+  g.kappa = g.cp * g.mu / g.Pr;
+  g.lam = -2.0 * g.mu / 3.0;
+  g.viscous = phys->viscous ? 1 : 0;
+  for (int v = 0; v < 4; ++v) g.uinf[v] = phys->u_inf[v];
+  build_table(c->K, c->tab);
+
+  // geometry and neighbours
+  const int nx = c->nx, ny = c->ny, E = c->E;
+  std::vector<double> hx(E), hy(E);
+  c->nbr.assign(4 * E, -1);
+  c->bcf.assign(4 * E, -1);
+  const bool px = mesh->bc[0] == IMEX_BC_PERIODIC, py = mesh->bc[2] == IMEX_BC_PERIODIC;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int e = i + nx * j;
+      hx[e] = c->xg[i + 1] - c->xg[i];
+      hy[e] = c->yg[j + 1] - c->yg[j];
+      const int ci[4] = {i - 1, i + 1, i, i};
+      const int cj[4] = {j, j, j - 1, j + 1};
+      for (int f = 0; f < 4; ++f) {
+        int a = ci[f], b = cj[f];
+        const bool in = a >= 0 && a < nx && b >= 0 && b < ny;
+        if (!in) {
+          if (f < 2 && px) a = (a + nx) % nx;
+          else if (f >= 2 && py) b = (b + ny) % ny;
+          else { c->bcf[4 * e + f] = mesh->bc[f]; continue; }
+        }
+        c->nbr[4 * e + f] = a + nx * b;
+      }
+    }
+  c->imp.assign(E, 0);
+  c->err.clear();
+  hipStream_t s = c->stream;
+  hipError_t he = hipSuccess;
+  if ((he = upload(&c->d_hx, hx, s)) != hipSuccess || (he = upload(&c->d_hy, hy, s)) != hipSuccess ||
+      (he = upload(&c->d_nbr, c->nbr, s)) != hipSuccess || (he = upload(&c->d_bcf, c->bcf, s)) != hipSuccess ||
+      (he = upload(&c->d_imp, c->imp, s)) != hipSuccess) {
+    imex_destroy(c);
+    return fail(nullptr, IMEX_ENOMEM, std::string("device tables: ") + hipGetErrorString(he));
+  }
+  he = hipMalloc(&c->d_tab, sizeof(BasisTable));
+  if (he == hipSuccess) he = hipMemcpyAsync(c->d_tab, &c->tab, sizeof(BasisTable), hipMemcpyHostToDevice, s);
+  // element-sized work arrays
+  const size_t es = (size_t)E * 4 * c->NN;
+  Workspace& w = c->ws;
+  if (he == hipSuccess) he = hipMalloc(&w.trace, (size_t)E * 4 * c->NQ * 8 * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc(&w.Q, (size_t)E * 5 * c->NN * sizeof(double));
+  if (he == hipSuccess) he = hipMemsetAsync(w.Q, 0, (size_t)E * 5 * c->NN * sizeof(double), s);
+  for (int r = 0; r < 8 && he == hipSuccess; ++r) he = hipMalloc(&w.Rstage[r], es * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc(&w.Un, es * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc(&w.Y, es * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc(&w.rhs, es * sizeof(double));
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    imex_destroy(c);
+    return fail(nullptr, IMEX_ENOMEM, std::string("workspace: ") + hipGetErrorString(he));
+  }
+  w.bytes = (size_t)E * 4 * c->NQ * 8 * 8 + (size_t)E * 5 * c->NN * 8 + 11 * es * 8;
+  *out = c;
+  return IMEX_OK;
+}
+
+imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
+  if (!c || !flag) return fail(c, IMEX_EINVAL, "null argument");
+  const int E = c->E, nx = c->nx, ny = c->ny;
+  c->imp.assign(flag, flag + E);
+  for (int e = 0; e < E; ++e) c->imp[e] = c->imp[e] ? 1 : 0;
+  c->im_list.clear();
+  c->ex_list.clear();
+  for (int e = 0; e < E; ++e) (c->imp[e] ? c->im_list : c->ex_list).push_back(e);
+  for (int e : c->ex_list)
+    for (int f = 0; f < 4; ++f)
+      if (c->nbr[4 * e + f] < 0 && c->bcf[4 * e + f] == IMEX_BC_WALL)
+        return fail(c, IMEX_EINVAL, "adiabatic walls are supported on implicit elements only");
+  c->n_im = (int)c->im_list.size();
+  c->n_ex = (int)c->ex_list.size();
+  std::vector<int> im_pos(E, -1);
+  for (int p = 0; p < c->n_im; ++p) im_pos[c->im_list[p]] = p;
+  // global facets: vertical (x = x_i) then horizontal (y = y_j); keep those touching an implicit element
+  const bool px = c->bc[0] == IMEX_BC_PERIODIC, py = c->bc[2] == IMEX_BC_PERIODIC;
+  c->hf_side.clear();
+  c->hf_face.clear();
+  c->hf_elem.clear();
+  c->efacet.assign(4 * c->n_im, -1);
+  auto add = [&](int eL, int fL, int eR, int fR) {
+    const bool keep = (eL >= 0 && c->imp[eL]) || (eR >= 0 && c->imp[eR]);
+    if (!keep) return;
+    const int id = (int)(c->hf_side.size() / 2);
+    const int ee[2] = {eL, eR}, ff[2] = {fL, fR};
+    for (int s = 0; s < 2; ++s) {
+      const int e = ee[s];
+      c->hf_elem.push_back(e);
+      c->hf_face.push_back(ff[s]);
+      c->hf_side.push_back(e >= 0 ? im_pos[e] : -1);
+      if (e >= 0 && im_pos[e] >= 0) c->efacet[4 * im_pos[e] + ff[s]] = id;
+    }
+  };
+  const int nvx = px ? nx : nx + 1, nhy = py ? ny : ny + 1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nvx; ++i) {
+      const int eR = i < nx ? i + nx * j : -1;
+      const int eL = i > 0 ? (i - 1) + nx * j : (px ? (nx - 1) + nx * j : -1);
+      add(eL, 1, eR, 0);
+    }
+  for (int j = 0; j < nhy; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int eR = j < ny ? i + nx * j : -1;
+      const int eL = j > 0 ? i + nx * (j - 1) : (py ? i + nx * (ny - 1) : -1);
+      add(eL, 3, eR, 2);
+    }
+  c->n_hf = (int)(c->hf_side.size() / 2);
+  c->face_kind.assign(4 * c->n_im, 0);
+  for (int p = 0; p < c->n_im; ++p) {
+    const int e = c->im_list[p];
+    for (int f = 0; f < 4; ++f) {
+      const int nb = c->nbr[4 * e + f];
+      int k;
+      if (nb >= 0) k = c->imp[nb] ? FK_INTERIOR : FK_INTERFACE;
+      else k = (c->bcf[4 * e + f] == IMEX_BC_FARFIELD) ? FK_FARFIELD : FK_WALL;
+      c->face_kind[4 * p + f] = k;
+    }
+  }
+  free_regions(c);
+  hipStream_t s = c->stream;
+  hipError_t he = hipMemcpyAsync(c->d_imp, c->imp.data(), E, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) he = upload(&c->d_im_list, c->im_list, s);
+  if (he == hipSuccess) he = upload(&c->d_ex_list, c->ex_list, s);
+  if (he == hipSuccess) he = upload(&c->d_face_kind, c->face_kind, s);
+  if (he == hipSuccess) he = upload(&c->d_efacet, c->efacet, s);
+  if (he == hipSuccess) he = upload(&c->d_hf_side, c->hf_side, s);
+  if (he == hipSuccess) he = upload(&c->d_hf_face, c->hf_face, s);
+  if (he == hipSuccess) he = upload(&c->d_hf_elem, c->hf_elem, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return fail(c, IMEX_ENOMEM, std::string("region tables: ") + hipGetErrorString(he));
+  imex_status st = hdg_alloc(c);
+  if (st != IMEX_OK) return st;
+  c->regions_set = true;
+  return IMEX_OK;
+}
+
+imex_status imex_query_sizes(const imex_ctx* c, long long out[8]) {
+  if (!c || !out) return IMEX_EINVAL;
+  out[0] = c->E;
+  out[1] = c->n_im;
+  out[2] = c->regions_set ? c->n_ex : c->E;
+  out[3] = c->NN;
+  out[4] = c->n_hf;
+  out[5] = 4 * c->NP;
+  out[6] = c->NQ;
+  out[7] = (long long)c->ws.bytes;
+  return IMEX_OK;
+}
+
+imex_status imex_node_coords(const imex_ctx* c, double* x, double* y) {
+  if (!c || !x || !y) return IMEX_EINVAL;
+  double nodes[MAXNP], nw[MAXNP];
+  gauss_legendre(c->NP, nodes, nw);
+  for (int j = 0; j < c->ny; ++j)
+    for (int i = 0; i < c->nx; ++i) {
+      const int e = i + c->nx * j;
+      const double hx = c->xg[i + 1] - c->xg[i], hy = c->yg[j + 1] - c->yg[j];
+      for (int n = 0; n < c->NN; ++n) {
+        x[(size_t)e * c->NN + n] = c->xg[i] + 0.5 * (nodes[n % c->NP] + 1.0) * hx;
+        y[(size_t)e * c->NN + n] = c->yg[j] + 0.5 * (nodes[n / c->NP] + 1.0) * hy;
+      }
+    }
+  return IMEX_OK;
+}
+
+imex_status imex_init_facets(imex_ctx* c, const double* U, double* Uhat) {
+  if (!c || !U || !Uhat) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (c->n_hf == 0) return IMEX_OK;
+  HIP_TRY(c, launch_init_facets(c, U, Uhat));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
+static imex_status dg_residual_async(imex_ctx* c, const double* U, const double* Uhat, double* R) {
+  const bool mx = c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
+  if (mx && Uhat) HIP_TRY(c, launch_lift_mixed(c, U, Uhat, c->ws.Q));
+  HIP_TRY(c, launch_dg_trace(c, U, mx ? c->ws.Q : nullptr, c->ws.trace));
+  HIP_TRY(c, hipMemsetAsync(R, 0, (size_t)c->E * 4 * c->NN * sizeof(double), c->stream));
+  HIP_TRY(c, launch_dg_residual(c, U, c->ws.trace, R));
+  return IMEX_OK;
+}
+
+imex_status imex_dg_residual(imex_ctx* c, const double* U, const double* Uhat, double* R) {
+  if (!c || !U || !R) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  imex_status st = dg_residual_async(c, U, Uhat, R);
+  if (st != IMEX_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
+imex_status imex_implicit_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double* U, double* Uhat,
+                                      double* R_out, imex_stats* st) {
+  if (!c || !rhs || !U || !Uhat) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set || c->n_im == 0) return fail(c, IMEX_ESTATE, "no implicit region");
+  if (!(dt_a > 0.0)) return fail(c, IMEX_EINVAL, "dt_aii must be positive");
+  if (st) std::memset(st, 0, sizeof(*st));
+  return hdg_stage_solve(c, dt_a, rhs, U, Uhat, R_out, st);
+}
+
+imex_status imex_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
+                              double* f, double* h, double* K, double* C, double* D, double* E) {
+  if (!c || !rhs || !U || !Uhat || !f || !h || !K || !C || !D || !E) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set || c->n_im == 0) return fail(c, IMEX_ESTATE, "no implicit region");
+  return hdg_local_system(c, dt_a, rhs, U, Uhat, f, h, K, C, D, E);
+}
+
+imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, double* U, double* Uhat, imex_stats* st) {
+  if (!c || !tab || !U) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  if (c->n_im > 0 && !Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
+  if (st) std::memset(st, 0, sizeof(*st));
+  Workspace& w = c->ws;
+  const int s = tab->s;
+  const size_t n = (size_t)c->E * 4 * c->NN;
+  hipStream_t hs = c->stream;
+  const bool mx = c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
+  double* Rdg[4] = {w.Rstage[0], w.Rstage[1], w.Rstage[2], w.Rstage[3]};
+  double* Rhdg[3] = {w.Rstage[4], w.Rstage[5], w.Rstage[6]};
+  HIP_TRY(c, hipMemcpyAsync(w.Un, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  HIP_TRY(c, hipMemcpyAsync(w.Y, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  if (mx) HIP_TRY(c, launch_lift_mixed(c, w.Y, Uhat, w.Q));   // Q^im_0 = Q(U_n, Uhat_n)
+  for (int i = 1; i <= s; ++i) {
+    // R^DG(y^ex_i, y^im_{i-1}); the mixed variables in w.Q belong to y^im_{i-1}
+    // (rows of implicit elements in Rdg are never read)
+    HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
+    HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[i - 1]));
+    double coef[4];
+    const double* Rs[4];
+    for (int j = 0; j < i; ++j) { coef[j] = tab->Ae[4 * i + j]; Rs[j] = Rdg[j]; }
+    HIP_TRY(c, launch_erk_combine(c, w.Un, i, Rs, coef, dt, w.Y));
+    if (c->n_im > 0) {
+      const double* Rh[3];
+      double ch[3];
+      for (int j = 0; j < i - 1; ++j) { ch[j] = dt * tab->Ai[3 * (i - 1) + j]; Rh[j] = Rhdg[j]; }
+      // rhs = M U_n - dt sum_{j<i} a_ij R^HDG_j
+      HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
+      for (int j = 0; j < i - 1; ++j)
+        HIP_TRY(c, launch_scale_copy(c, w.rhs, w.rhs, 1.0, Rh[j], -ch[j], n));
+      imex_stats sst{};
+      imex_status r = hdg_stage_solve(c, dt * tab->Ai[3 * (i - 1) + (i - 1)], w.rhs, w.Y, Uhat, Rhdg[i - 1], &sst);
+      if (st) {
+        st->newton_its += sst.newton_its;
+        st->gmres_its += sst.gmres_its;
+        st->newton_last_du = sst.newton_last_du;
+        st->t_assemble_ms += sst.t_assemble_ms;
+        st->t_solve_ms += sst.t_solve_ms;
+      }
+      if (r != IMEX_OK) return r;
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  if (!tab->fsal) {
+    HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
+    HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[s]));
+    double coef[4];
+    const double* Rs[4];
+    for (int j = 0; j <= s; ++j) { coef[j] = tab->be[j]; Rs[j] = Rdg[j]; }
+    HIP_TRY(c, launch_erk_combine(c, w.Un, s + 1, Rs, coef, dt, U));
+  }
+  if (c->n_im > 0 && !tab->stiffly_accurate)
+    return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
+  HIP_TRY(c, hipStreamSynchronize(hs));
+  return IMEX_OK;
+}
+
+imex_status imex_conservation_sums(imex_ctx* c, const double* U, double out[4]) {
+  if (!c || !U || !out) return fail(c, IMEX_EINVAL, "null argument");
+  int nb = 0;
+  HIP_TRY(c, launch_mass_sums(c, U, c->ws.Rstage[7], &nb));
+  std::vector<double> part((size_t)nb * 4);
+  HIP_TRY(c, hipMemcpyAsync(part.data(), c->ws.Rstage[7], part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * 4 + v];
+    out[v] = s;
+  }
+  return IMEX_OK;
+}
+
+void imex_destroy(imex_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_regions(c);
+  Workspace& w = c->ws;
+  for (double** p : {&w.trace, &w.Q, &w.Un, &w.Y, &w.rhs}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  for (int r = 0; r < 8; ++r) {
+    if (w.Rstage[r]) hipFree(w.Rstage[r]);
+    w.Rstage[r] = nullptr;
+  }
+  for (double** p : {&c->d_hx, &c->d_hy}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  for (int** p : {&c->d_nbr, &c->d_bcf}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  if (c->d_imp) hipFree(c->d_imp);
+  if (c->d_tab) hipFree(c->d_tab);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal state of an imex_ctx and the launch interfaces of the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/imexhdg.h"
+#include "device_common.h"
+
+namespace imex {
+
+// HDG facet kinds as seen from an implicit element's face
+enum FaceKind { FK_INTERIOR = 0, FK_INTERFACE = 1, FK_FARFIELD = 2, FK_WALL = 3 };
+
+struct DeviceMesh {
+  int E, nx, ny, K;
+  const double* hx;         // [E]
+  const double* hy;         // [E]
+  const int* nbr;           // [E][4] neighbour element or -1
+  const int* bcf;           // [E][4] boundary type where nbr == -1
+  const unsigned char* imp; // [E]
+  const BasisTable* tab;
+};
+
+// Implicit-region tables (device)
+struct DeviceHDG {
+  int n_im, n_hf;
+  const int* im_list;       // [n_im] element ids
+  const int* face_kind;     // [n_im][4]
+  const int* efacet;        // [n_im][4] HDG facet index of each face
+  const int* hf_side;       // [n_hf][2] implicit-list position of the (lower, upper) side or -1
+  const int* hf_face;       // [n_hf][2] local face of that side
+  const int* hf_elem;       // [n_hf][2] element id of each side or -1
+};
+
+struct Workspace {
+  double* trace = nullptr;      // [E][4][NQ][8] face traces: U and F^nu . n
+  double* Q = nullptr;          // [E][5][NN] mixed variables of implicit elements (HDG-MX)
+  double* Rstage[8] = {};       // ARK stage residuals, [E][4][NN] each
+  double* Un = nullptr;         // copy of U at t_n
+  double* Y = nullptr;          // stage state
+  double* rhs = nullptr;        // implicit stage right-hand side
+  // implicit Newton
+  double* blk = nullptr;        // per implicit element: f, h, K, C, D, E (FP64)
+  double* scr = nullptr;        // per implicit element: assembly scratch (A-blocks of HDG-MX)
+  double* X = nullptr;          // per implicit element: K^-1 C  [NU][NF]
+  double* y = nullptr;          // per implicit element: K^-1 f  [NU]
+  double* S = nullptr;          // per implicit element: E - D X [NF][NF]
+  double* r = nullptr;          // per implicit element: D K^-1 f [NF]
+  float* X32 = nullptr;         // mixed-precision copies
+  float* S32 = nullptr;
+  double* Pinv = nullptr;       // per HDG facet: block-Jacobi inverse [NFF][NFF]
+  double* gm = nullptr;         // GMRES basis and vectors
+  double* red = nullptr;        // reduction scratch
+  double* hred = nullptr;       // pinned host reduction buffer
+  size_t bytes = 0;
+};
+
+}  // namespace imex
+
+struct imex_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int nx = 0, ny = 0, E = 0, K = 0, NP = 0, NQ = 0, NN = 0;
+  int bc[4] = {0, 0, 0, 0};
+  std::vector<double> xg, yg;
+  imex::Gas gas{};
+  imex_options opt{};
+  imex::BasisTable tab{};
+  // host tables
+  std::vector<int> nbr, bcf;
+  std::vector<unsigned char> imp;
+  std::vector<int> im_list, ex_list, face_kind, efacet, hf_side, hf_face, hf_elem;
+  int n_im = 0, n_ex = 0, n_hf = 0;
+  bool regions_set = false;
+  // device copies
+  double *d_hx = nullptr, *d_hy = nullptr;
+  int *d_nbr = nullptr, *d_bcf = nullptr;
+  unsigned char* d_imp = nullptr;
+  imex::BasisTable* d_tab = nullptr;
+  int *d_im_list = nullptr, *d_ex_list = nullptr, *d_face_kind = nullptr, *d_efacet = nullptr;
+  int *d_hf_side = nullptr, *d_hf_face = nullptr, *d_hf_elem = nullptr;
+  imex::Workspace ws;
+  std::string err;
+  imex::DeviceMesh dmesh() const {
+    return imex::DeviceMesh{E, nx, ny, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab};
+  }
+  imex::DeviceHDG dhdg() const {
+    return imex::DeviceHDG{n_im, n_hf, d_im_list, d_face_kind, d_efacet, d_hf_side, d_hf_face, d_hf_elem};
+  }
+};
+
+// kernel launchers (dg.hip)
+namespace imex {
+hipError_t launch_dg_trace(const imex_ctx* c, const double* U, const double* Q, double* trace);
+hipError_t launch_dg_residual(const imex_ctx* c, const double* U, const double* trace, double* R);
+hipError_t launch_erk_combine(const imex_ctx* c, const double* Un, int nterms, const double* const* R,
+                              const double* coef, double dt, double* Y);
+hipError_t launch_mass_sums(const imex_ctx* c, const double* U, double* partial, int* nblocks);
+hipError_t launch_scale_copy(const imex_ctx* c, const double* src, double* dst, double a, const double* add,
+                             double b, size_t n);
+// hdg.hip
+hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
+hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
+hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);
+imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double* U, double* Uhat, double* R_out,
+                            imex_stats* st);
+imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
+                             double* f, double* h, double* K, double* C, double* D, double* E);
+size_t hdg_workspace_bytes(const imex_ctx* c);
+imex_status hdg_alloc(imex_ctx* c);
+}  // namespace imex

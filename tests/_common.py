@@ -1,0 +1,57 @@
+"""Helpers shared by the tests: library availability and workload variants."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2607_16044_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2607_16044_amd", "libimexhdg.so")
+
+
+def ensure_built():
+    if not os.path.exists(LIB):
+        from paper_2607_16044_amd import build
+        build.build()
+    return LIB
+
+
+def gpu_engine(wl, **kw):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    ensure_built()
+    from paper_2607_16044_amd.binding import Engine
+    return Engine(wl, **kw)
+
+
+def smooth_square(n=4, k=2, viscous=True, mu=0.02, variant=W.HDG_IP, implicit_rows=(), lf=False,
+                  bc=(W.BC_PERIODIC,) * 4, tableau="ARS222", dt=1e-3):
+    """Periodic unit square with a smooth non-trivial state (used for parity checks)."""
+    x = np.linspace(0.0, 1.0, n + 1)
+    implicit = np.zeros((n, n), dtype=bool)
+    for j in implicit_rows:
+        implicit[j, :] = True
+
+    def ic(X, Y, elem=None, node=None):
+        tp = 2.0 * math.pi
+        rho = 1.0 + 0.2 * np.sin(tp * X) * np.cos(tp * Y)
+        u = 0.3 + 0.1 * np.cos(tp * (X + Y))
+        v = 0.2 - 0.1 * np.sin(tp * X)
+        p = 2.5 + 0.3 * np.cos(tp * Y)
+        return np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    uinf = np.array([1.0, 0.3, 0.2, 2.5 / 0.4 + 0.5 * (0.09 + 0.04)])
+    return W.Workload(name="square", xgrid=x, ygrid=x.copy(), bc=bc, implicit=implicit, degree=k, gamma=1.4, R=1.0,
+                      mu=mu if viscous else 0.0, Pr=0.72, viscous=viscous, u_inf=uinf,
+                      dg_flux=W.FLUX_LAX_FRIEDRICHS if lf else W.FLUX_VIJAYASUNDARAM,
+                      hdg_flux=W.HDG_FLUX_LF if lf else W.HDG_FLUX_FVS, hdg_variant=variant, tableau=tableau, dt=dt,
+                      steps=1, ic=ic)
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = np.maximum(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)

@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI: the library builds, loads and exports every
+symbol the header declares; argument validation needs no GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+from _common import ROOT, ensure_built
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "imexhdg.h")).read()
+    decl = r"^(?:imex_status|const char\*|void)\s+(imex_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_exports_match_header():
+    lib = ctypes.CDLL(ensure_built())
+    syms = header_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(lib, s), s
+    from paper_2607_16044_amd.binding import EXPORTS
+    assert sorted(EXPORTS) == syms
+
+
+def test_status_strings_and_validation():
+    from paper_2607_16044_amd.binding import MeshDesc, Options, Physics, load_library
+    lib = load_library()
+    assert lib.imex_status_str(0) == b"ok"
+    assert lib.imex_status_str(-4) == b"Newton did not converge"
+    x = np.array([0.0, 1.0, 0.5])          # not increasing
+    y = np.array([0.0, 1.0])
+    P = ctypes.POINTER(ctypes.c_double)
+    mesh = MeshDesc(2, 1, x.ctypes.data_as(P), y.ctypes.data_as(P), (ctypes.c_int * 4)(0, 0, 0, 0), 2)
+    phys = Physics(1.4, 1.0, 0.0, 0.72, 0, (ctypes.c_double * 4)(1, 0, 0, 2.5))
+    opt = Options(0, 0, 0, 1.0, 10.0, 0, 1e-12, 20, 1e-12, 30, 300)
+    ctx = ctypes.c_void_p()
+    st = lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt), None, ctypes.byref(ctx))
+    assert st == -1 and not ctx.value
+    assert b"xgrid" in lib.imex_last_error(None)
+    mesh.degree = 7
+    st = lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt), None, ctypes.byref(ctx))
+    assert st == -1
+    x2 = np.array([0.0, 0.5, 1.0])
+    mesh = MeshDesc(2, 1, x2.ctypes.data_as(P), y.ctypes.data_as(P), (ctypes.c_int * 4)(0, 1, 0, 0), 2)
+    st = lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt), None, ctypes.byref(ctx))
+    assert st == -1 and b"periodic" in lib.imex_last_error(None)
+
+
+def test_tableaux_match_order_conditions():
+    from paper_2607_16044_amd import tableaux
+    for name, order in (("ARS222", 2), ("ARS343", 3)):
+        t = tableaux.get(name)
+        c = t.Ae.sum(1)
+        assert np.allclose(c[1:], t.Ai.sum(1), atol=1e-15)
+        assert abs(t.be.sum() - 1) < 1e-14 and abs(t.bi.sum() - 1) < 1e-14
+        assert abs(t.be @ c - 0.5) < 2e-10
+        if order == 3:
+            assert abs(t.be @ c ** 2 - 1 / 3) < 2e-10
+        assert t.stiffly_accurate
+        assert t.fsal == (name == "ARS222")
