@@ -172,6 +172,14 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
                               const double* Uhat, double* f, double* h, double* K, double* C, double* D,
                               double* E);
 
+/* Accumulated device time per phase, measured with hipEvents on the context's
+ * stream: out[2t] = milliseconds, out[2t+1] = number of timed launches for
+ * t = 0 explicit DG residual (trace + residual kernels), 1 element assembly
+ * kernel, 2 mixed-block elimination, 3 LU + condensation, 4 facet right-hand
+ * side and block-Jacobi set-up, 5 GMRES, 6 back-substitution and update,
+ * 7 reserved.  host out[16]; reset != 0 clears the counters after reading. */
+imex_status imex_kernel_times(imex_ctx* ctx, double out[16], int reset);
+
 const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);
 void imex_destroy(imex_ctx* ctx);

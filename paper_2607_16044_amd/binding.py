@@ -24,7 +24,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
-           "imex_local_system", "imex_status_str", "imex_last_error", "imex_destroy"]
+           "imex_local_system", "imex_kernel_times", "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, ctypes.POINTER(Stats)]
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
+    lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_status_str.argtypes = [ctypes.c_int]
     lib.imex_status_str.restype = ctypes.c_char_p
     lib.imex_last_error.argtypes = [P]
@@ -219,6 +220,20 @@ class Engine:
         out = (ctypes.c_double * 4)()
         self._check(self.lib.imex_conservation_sums(self.ctx, _ptr(U), out))
         return np.array(list(out))
+
+    TIMER_NAMES = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "reserved"]
+
+    def timers(self, reset: bool = False):
+        out = (ctypes.c_double * 16)()
+        self._check(self.lib.imex_kernel_times(self.ctx, out, int(reset)))
+        r = {}
+        for i, name in enumerate(self.TIMER_NAMES):
+            r[name + "_ms"] = out[2 * i]
+            r[name + "_launches"] = int(out[2 * i + 1])
+        return r
+
+    def reset_timers(self):
+        self.timers(reset=True)
 
     def local_system(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):
         n_im = self.sizes["n_implicit"]

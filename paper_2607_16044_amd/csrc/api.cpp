@@ -131,6 +131,38 @@ void free_regions(imex_ctx* c) {
 
 }  // namespace
 
+int imex_ctx::timer_begin(int tag) {
+  hipEvent_t a, b;
+  if (ev_free.size() >= 2) {
+    a = ev_free.back(); ev_free.pop_back();
+    b = ev_free.back(); ev_free.pop_back();
+  } else {
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return -1; }
+  }
+  hipEventRecord(a, stream);
+  ev_pending.push_back({tag, a, b});
+  return (int)ev_pending.size() - 1;
+}
+
+void imex_ctx::timer_end(int idx) {
+  if (idx < 0 || idx >= (int)ev_pending.size()) return;
+  hipEventRecord(ev_pending[idx].b, stream);
+}
+
+void imex_ctx::timers_resolve() {
+  for (const Pending& p : ev_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      tm_ms[p.tag] += ms;
+      tm_n[p.tag] += 1;
+    }
+    ev_free.push_back(p.a);
+    ev_free.push_back(p.b);
+  }
+  ev_pending.clear();
+}
+
 extern "C" {
 
 const char* imex_status_str(imex_status s) {
@@ -429,8 +461,10 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   for (int i = 1; i <= s; ++i) {
     // R^DG(y^ex_i, y^im_{i-1}); the mixed variables in w.Q belong to y^im_{i-1}
     // (rows of implicit elements in Rdg are never read)
+    const int tdg = c->timer_begin(TM_DG);
     HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
     HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[i - 1]));
+    c->timer_end(tdg);
     double coef[4];
     const double* Rs[4];
     for (int j = 0; j < i; ++j) { coef[j] = tab->Ae[4 * i + j]; Rs[j] = Rdg[j]; }
@@ -457,8 +491,10 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   }
   HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   if (!tab->fsal) {
+    const int tdg = c->timer_begin(TM_DG);
     HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
     HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[s]));
+    c->timer_end(tdg);
     double coef[4];
     const double* Rs[4];
     for (int j = 0; j <= s; ++j) { coef[j] = tab->be[j]; Rs[j] = Rdg[j]; }
@@ -467,6 +503,19 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   if (c->n_im > 0 && !tab->stiffly_accurate)
     return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
   HIP_TRY(c, hipStreamSynchronize(hs));
+  c->timers_resolve();
+  return IMEX_OK;
+}
+
+imex_status imex_kernel_times(imex_ctx* c, double out[16], int reset) {
+  if (!c || !out) return fail(c, IMEX_EINVAL, "null argument");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timers_resolve();
+  for (int t = 0; t < imex_ctx::NTIMER; ++t) {
+    out[2 * t] = c->tm_ms[t];
+    out[2 * t + 1] = (double)c->tm_n[t];
+    if (reset) { c->tm_ms[t] = 0.0; c->tm_n[t] = 0; }
+  }
   return IMEX_OK;
 }
 
@@ -489,6 +538,9 @@ imex_status imex_conservation_sums(imex_ctx* c, const double* U, double out[4]) 
 void imex_destroy(imex_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
+  c->timers_resolve();
+  for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
+  c->ev_free.clear();
   free_regions(c);
   Workspace& w = c->ws;
   for (double** p : {&w.trace, &w.Q, &w.Un, &w.Y, &w.rhs}) {

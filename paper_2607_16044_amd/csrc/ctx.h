@@ -83,6 +83,16 @@ struct imex_ctx {
   int *d_hf_side = nullptr, *d_hf_face = nullptr, *d_hf_elem = nullptr;
   imex::Workspace ws;
   std::string err;
+  // device-time accounting per phase (hipEvents resolved at synchronisation points)
+  static constexpr int NTIMER = 8;
+  double tm_ms[NTIMER] = {};
+  long long tm_n[NTIMER] = {};
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int tag; hipEvent_t a, b; };
+  std::vector<Pending> ev_pending;
+  int timer_begin(int tag);
+  void timer_end(int idx);
+  void timers_resolve();
   imex::DeviceMesh dmesh() const {
     return imex::DeviceMesh{E, nx, ny, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab};
   }
@@ -90,6 +100,12 @@ struct imex_ctx {
     return imex::DeviceHDG{n_im, n_hf, d_im_list, d_face_kind, d_efacet, d_hf_side, d_hf_face, d_hf_elem};
   }
 };
+
+// timer tags
+namespace imex {
+enum TimerTag { TM_DG = 0, TM_ASSEMBLE = 1, TM_ELIMINATE = 2, TM_CONDENSE = 3, TM_FACET = 4, TM_GMRES = 5,
+                TM_BACKSUB = 6, TM_ERK = 7 };
+}
 
 // kernel launchers (dg.hip)
 namespace imex {

@@ -1238,21 +1238,27 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
   const bool mx = use_mx(c);
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
+    const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
     if (mx) {
       const size_t shm = sizeof(AsmShared<KK, true>);
       hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       hipLaunchKernelGGL((hdg_assemble_kernel<KK, true>), dim3(c->n_im), dim3(256), shm, c->stream, c->dmesh(),
                          c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, w.Q, Rh);
-      if (jacobian)
+      c->timer_end(ta);
+      if (jacobian) {
+        const int te = c->timer_begin(TM_ELIMINATE);
         hipLaunchKernelGGL(hdg_eliminate_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
                            w.blk, w.scr);
+        c->timer_end(te);
+      }
     } else {
       const size_t shm = sizeof(AsmShared<KK, false>);
       hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       hipLaunchKernelGGL((hdg_assemble_kernel<KK, false>), dim3(c->n_im), dim3(256), shm, c->stream, c->dmesh(),
                          c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, nullptr, Rh);
+      c->timer_end(ta);
     }
   });
   return hipGetLastError();
@@ -1434,18 +1440,27 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
     newton = it;
     HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
+    int tt = c->timer_begin(TM_CONDENSE);
     HTRY(launch_condense(c));
+    c->timer_end(tt);
+    tt = c->timer_begin(TM_FACET);
     HTRY(launch_facet_setup(c, b));
+    c->timer_end(tt);
     int its = 0;
+    tt = c->timer_begin(TM_GMRES);
     imex_status s = gmres(c, b, dx, &its);
+    c->timer_end(tt);
     if (s != IMEX_OK) return s;
     gm_total += its;
+    tt = c->timer_begin(TM_BACKSUB);
     HTRY(launch_backsub(c, dx, U, part));
     hipLaunchKernelGGL(facet_update_kernel, dim3(fb), dim3(256), 0, c->stream, n, dx, Uhat, part + 2 * c->n_im);
+    c->timer_end(tt);
     HTRY(hipGetLastError());
     const size_t np = 2 * ((size_t)c->n_im + fb);
     HTRY(hipMemcpyAsync(w.hred, part, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
     HTRY(hipStreamSynchronize(c->stream));
+    c->timers_resolve();
     double du = 0.0, uu = 0.0, dh = 0.0, hh = 0.0;
     for (int i = 0; i < c->n_im; ++i) { du = std::fmax(du, w.hred[2 * i]); uu = std::fmax(uu, w.hred[2 * i + 1]); }
     for (int i = 0; i < fb; ++i) {
