@@ -43,8 +43,8 @@ def parse():
 
 
 def cpu_baseline(seconds_budget: float = 25.0):
-    """The oracle on a bounded sample of the boundary-layer workload: a 2x32 strip of the
-    same mesh family (k=4, ARS(3,4,3), HDG-MX on the 4 wall rows = 1/8 implicit like the
+    """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
+    same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
     full mesh), one step, single thread."""
     try:
         from threadpoolctl import threadpool_limits
@@ -52,7 +52,7 @@ def cpu_baseline(seconds_budget: float = 25.0):
         threadpool_limits = None
     from paper_2607_16044_amd import workloads
     from oracle.ark import IMEXSolver
-    wl = workloads.boundary_layer(nx=2, ny=32, k=4, implicit_rows=4, Lx=2 * 2.0 / 256, height=None, steps=1,
+    wl = workloads.boundary_layer(nx=2, ny=16, k=4, implicit_rows=2, Lx=2 * 2.0 / 256, height=None, steps=1,
                                   name="boundary_layer_sample")
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
@@ -65,7 +65,20 @@ def cpu_baseline(seconds_budget: float = 25.0):
             ctx.unregister() if hasattr(ctx, "unregister") else None
     dof_stage = wl.n_dof * wl.stages
     return {"value": dof_stage / dt, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"boundary layer 2x32 strip (k=4, 4 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
+            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
+
+
+def assembly_flops(wl):
+    """Dense element-Jacobian contraction flops per implicit element."""
+    k = wl.degree
+    nq = (3 * k + 2) // 2
+    nn, nqv = (k + 1) ** 2, nq * nq
+    nu, nf = 4 * nn, 16 * (k + 1)
+    nqm = 5 * nn
+    # volume and face sandwich products B^T J B for the blocks K, A12, A21 (+ C, D, E, A23, A32 on faces)
+    vol = 2 * nqv * (nu * nu * 2 + nu * nqm * 2 + nqm * nu * 2)
+    face = 2 * 4 * nq * (nu * nu + nu * nqm) + 2 * nq * (nu * nf + nf * nu + nf * nf + nqm * nf + nf * nqm)
+    return vol + face
 
 
 def main():
@@ -98,6 +111,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timers = eng.timers()
+    phases = {k[:-3]: round(v / args.steps, 3) for k, v in timers.items() if k.endswith("_ms") and v > 0}
     n_dof = wl.n_dof
     s = wl.stages
     value = n_dof * s * args.steps / elapsed
@@ -105,7 +119,7 @@ def main():
     roof = None
     if timers["assemble_launches"] > 0:
         avg_ms = timers["assemble_ms"] / timers["assemble_launches"]
-        flops = eng.assembly_flops_per_launch()
+        flops = assembly_flops(wl) * eng.sizes["n_implicit"]
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma" if False else "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
@@ -128,6 +142,7 @@ def main():
                    "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": args.precision,
                    "newton_its_per_step": newton / args.steps, "gmres_its_per_step": gmres / args.steps},
         "roofline": roof,
+        "phases_ms_per_step": phases,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -114,7 +114,7 @@ class Engine:
     """One mesh and region split on the current HIP device."""
 
     def __init__(self, wl, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
-                 gmres_rtol: float = 1e-13, gmres_restart: int = 60, gmres_maxit: int = 600,
+                 gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
                  device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")

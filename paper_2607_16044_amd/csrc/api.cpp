@@ -112,12 +112,12 @@ hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 void free_regions(imex_ctx* c) {
   for (int** p : {&c->d_im_list, &c->d_ex_list, &c->d_face_kind, &c->d_efacet, &c->d_hf_side, &c->d_hf_face,
-                  &c->d_hf_elem}) {
+                  &c->d_hf_elem, &c->d_win_off, &c->d_win_slot, &c->d_win_own}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.blk, &w.scr, &w.X, &w.y, &w.S, &w.r, &w.Pinv, &w.gm, &w.red}) {
+  for (double** p : {&w.blk, &w.scr, &w.Kinv, &w.X, &w.Wd, &w.Wg, &w.Wc, &w.Wy, &w.gH, &w.gm, &w.red}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
@@ -341,6 +341,83 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       add(eL, 3, eR, 2);
     }
   c->n_hf = (int)(c->hf_side.size() / 2);
+  // Two-column Schwarz windows for the facet preconditioner.  Window w covers element
+  // columns c0 = w and c1 = w + 1 (wrapping when periodic in x); its unknowns are the
+  // HDG facets of those columns, grouped in super-rows r (element rows) with slots
+  // [H(c0, r), H(c1, r), V(x_c0, r), V(x_c0+1, r), V(x_c1+1, r)], plus a last super-row
+  // holding the top horizontal facets.  A window writes only the facets it owns (column
+  // c0's horizontal facets and left vertical facets; the last window of a non-periodic
+  // mesh also owns its second column), so every facet is written exactly once.
+  {
+    std::vector<int> vid((nx + 1) * ny, -1), hid(nx * (ny + 1), -1);
+    int id = 0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nvx; ++i) {
+        const int eR = i < nx ? i + nx * j : -1;
+        const int eL = i > 0 ? (i - 1) + nx * j : (px ? (nx - 1) + nx * j : -1);
+        if ((eL >= 0 && c->imp[eL]) || (eR >= 0 && c->imp[eR])) vid[i + (nx + 1) * j] = id++;
+      }
+    for (int j = 0; j < nhy; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int eR = j < ny ? i + nx * j : -1;
+        const int eL = j > 0 ? i + nx * (j - 1) : (py ? i + nx * (ny - 1) : -1);
+        if ((eL >= 0 && c->imp[eL]) || (eR >= 0 && c->imp[eR])) hid[i + nx * j] = id++;
+      }
+    auto V = [&](int xi, int j) -> int {          // vertical facet at x_xi, row j
+      if (px) xi = ((xi % nx) + nx) % nx;
+      if (xi < 0 || xi > nx || j < 0 || j >= ny) return -1;
+      return vid[xi + (nx + 1) * j];
+    };
+    auto H = [&](int i, int j) -> int {           // horizontal facet of column i at y_j
+      if (i < 0 || i >= nx || j < 0) return -1;
+      if (py) j = j % ny;
+      if (j > (py ? ny - 1 : ny)) return -1;
+      return hid[i + nx * j];
+    };
+    c->win_off.assign(1, 0);
+    c->win_slot.clear();
+    c->win_own.clear();
+    std::vector<int> owned(c->n_hf, 0);
+    const int nwin = (nx == 1) ? 1 : (px ? nx : nx - 1);
+    for (int w = 0; w < nwin; ++w) {
+      const int c0 = w;
+      const int c1 = (nx == 1) ? -1 : (px ? (w + 1) % nx : w + 1);
+      const bool last = !px && (w == nwin - 1);
+      int rlo = ny, rhi = -1;
+      for (int j = 0; j < ny; ++j)
+        for (int col : {c0, c1})
+          if (col >= 0 && c->imp[col + nx * j]) { rlo = std::min(rlo, j); rhi = std::max(rhi, j); }
+      if (rhi < 0) { c->win_off.push_back((int)(c->win_slot.size() / 5)); continue; }
+      for (int r = rlo; r <= rhi + 1; ++r) {
+        int f[5] = {H(c0, r), c1 >= 0 ? H(c1, r) : -1, -1, -1, -1};
+        if (r <= rhi) {
+          f[2] = V(c0, r);
+          f[3] = V(c0 + 1, r);
+          f[4] = c1 >= 0 ? V(c1 + 1, r) : -1;
+        }
+        if (py && r == rhi + 1 && rhi == ny - 1 && rlo == 0) { f[0] = -1; f[1] = -1; }   // wrapped top row
+        for (int a = 0; a < 5; ++a)
+          for (int b2 = 0; b2 < a; ++b2)
+            if (f[a] >= 0 && f[a] == f[b2]) f[a] = -1;
+        for (int a = 0; a < 5; ++a) {
+          const bool own = f[a] >= 0 && (a == 0 || a == 2 || last || c1 < 0) && !owned[f[a]];
+          if (own) owned[f[a]] = 1;
+          c->win_slot.push_back(f[a]);
+          c->win_own.push_back(own ? 1 : 0);
+        }
+      }
+      c->win_off.push_back((int)(c->win_slot.size() / 5));
+    }
+    c->n_win = nwin;
+    c->n_superrows = (int)(c->win_slot.size() / 5);
+    // facets of implicit regions with ragged column extents: first occurrence owns them
+    for (size_t q = 0; q < c->win_slot.size(); ++q) {
+      const int f = c->win_slot[q];
+      if (f >= 0 && !owned[f]) { owned[f] = 1; c->win_own[q] = 1; }
+    }
+    for (int f = 0; f < c->n_hf; ++f)
+      if (!owned[f]) return fail(c, IMEX_EINVAL, "facet preconditioner windows do not cover every facet");
+  }
   c->face_kind.assign(4 * c->n_im, 0);
   for (int p = 0; p < c->n_im; ++p) {
     const int e = c->im_list[p];
@@ -362,6 +439,9 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   if (he == hipSuccess) he = upload(&c->d_hf_side, c->hf_side, s);
   if (he == hipSuccess) he = upload(&c->d_hf_face, c->hf_face, s);
   if (he == hipSuccess) he = upload(&c->d_hf_elem, c->hf_elem, s);
+  if (he == hipSuccess) he = upload(&c->d_win_off, c->win_off, s);
+  if (he == hipSuccess) he = upload(&c->d_win_slot, c->win_slot, s);
+  if (he == hipSuccess) he = upload(&c->d_win_own, c->win_own, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return fail(c, IMEX_ENOMEM, std::string("region tables: ") + hipGetErrorString(he));
   imex_status st = hdg_alloc(c);

@@ -32,6 +32,11 @@ struct DeviceHDG {
   const int* hf_side;       // [n_hf][2] implicit-list position of the (lower, upper) side or -1
   const int* hf_face;       // [n_hf][2] local face of that side
   const int* hf_elem;       // [n_hf][2] element id of each side or -1
+  // two-column Schwarz windows of the facet preconditioner
+  int n_win;
+  const int* win_off;       // [n_win+1] offsets (in super-rows) of each window
+  const int* win_slot;      // [n_superrows][5] HDG facet of each slot or -1
+  const int* win_own;       // [n_superrows][5] 1 if the window writes that facet's result
 };
 
 struct Workspace {
@@ -42,15 +47,17 @@ struct Workspace {
   double* Y = nullptr;          // stage state
   double* rhs = nullptr;        // implicit stage right-hand side
   // implicit Newton
-  double* blk = nullptr;        // per implicit element: f, h, K, C, D, E (FP64)
-  double* scr = nullptr;        // per implicit element: assembly scratch (A-blocks of HDG-MX)
-  double* X = nullptr;          // per implicit element: K^-1 C  [NU][NF]
-  double* y = nullptr;          // per implicit element: K^-1 f  [NU]
-  double* S = nullptr;          // per implicit element: E - D X [NF][NF]
-  double* r = nullptr;          // per implicit element: D K^-1 f [NF]
+  double* blk = nullptr;        // per implicit element: augmented system [[K C f],[D E h]] (becomes [[. . .],[D S h-DK^-1f]])
+  double* scr = nullptr;        // per implicit element: HDG-MX mixed blocks [A12; A32] and M_Q^-1 [A21 A23]
+  double* Kinv = nullptr;       // per implicit element: K^-1 [NU][NU]
+  double* X = nullptr;          // per implicit element: K^-1 [C f]  [NU][NF+1]
   float* X32 = nullptr;         // mixed-precision copies
   float* S32 = nullptr;
-  double* Pinv = nullptr;       // per HDG facet: block-Jacobi inverse [NFF][NFF]
+  double* Wd = nullptr;         // per window super-row: inverse of the eliminated diagonal block
+  double* Wg = nullptr;         // per window super-row: B_r D_{r-1}^-1 (facet rows x previous super-row)
+  double* Wc = nullptr;         // per window super-row: coupling to the next super-row
+  double* Wy = nullptr;         // per window super-row: forward-sweep vector
+  double* gH = nullptr;         // GMRES Hessenberg, rotations, g, residual history, scalars (device)
   double* gm = nullptr;         // GMRES basis and vectors
   double* red = nullptr;        // reduction scratch
   double* hred = nullptr;       // pinned host reduction buffer
@@ -72,6 +79,8 @@ struct imex_ctx {
   std::vector<int> nbr, bcf;
   std::vector<unsigned char> imp;
   std::vector<int> im_list, ex_list, face_kind, efacet, hf_side, hf_face, hf_elem;
+  std::vector<int> win_off, win_slot, win_own;
+  int n_win = 0, n_superrows = 0;
   int n_im = 0, n_ex = 0, n_hf = 0;
   bool regions_set = false;
   // device copies
@@ -81,6 +90,7 @@ struct imex_ctx {
   imex::BasisTable* d_tab = nullptr;
   int *d_im_list = nullptr, *d_ex_list = nullptr, *d_face_kind = nullptr, *d_efacet = nullptr;
   int *d_hf_side = nullptr, *d_hf_face = nullptr, *d_hf_elem = nullptr;
+  int *d_win_off = nullptr, *d_win_slot = nullptr, *d_win_own = nullptr;
   imex::Workspace ws;
   std::string err;
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
@@ -97,7 +107,8 @@ struct imex_ctx {
     return imex::DeviceMesh{E, nx, ny, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab};
   }
   imex::DeviceHDG dhdg() const {
-    return imex::DeviceHDG{n_im, n_hf, d_im_list, d_face_kind, d_efacet, d_hf_side, d_hf_face, d_hf_elem};
+    return imex::DeviceHDG{n_im,     n_hf,          d_im_list,  d_face_kind,  d_efacet,  d_hf_side, d_hf_face,
+                           d_hf_elem, n_win, d_win_off, d_win_slot, d_win_own};
   }
 };
 

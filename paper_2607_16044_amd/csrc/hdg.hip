@@ -18,6 +18,7 @@
 //                    the stored S_T blocks of the (at most two) adjacent elements.
 //  5. hdg_backsub    dU_T = -y_T - X_T dUhat_T (eq. local_solve_static_condensation),
 //                    update and increment norms.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -36,8 +37,9 @@ template <int K, bool MX> struct HS {
   static constexpr int NIV = MX ? 9 : 12;     // volume point inputs: U + (Q | grad U)
   static constexpr int NIF = MX ? 13 : 16;    // face point inputs: U + Uhat + (Q | grad U)
   static constexpr int NOF = MX ? 8 : 16;     // face point outputs: s + t (+ g for IP)
-  static constexpr size_t BLK = (size_t)NU + NF + (size_t)NU * NU + 2 * (size_t)NU * NF + (size_t)NF * NF;
-  static constexpr size_t SCR = MX ? (2 * (size_t)NU * NQM + 2 * (size_t)NQM * NF) : 0;
+  static constexpr int NR = NU + NF, NC = NU + NF + 1;       // augmented local system [[K C f],[D E h]]
+  static constexpr size_t BLK = (size_t)NR * NC;
+  static constexpr size_t SCR = MX ? 2 * (size_t)NR * NQM : 0;  // L = [A12; A32], R = M_Q^-1 [A21 A23]
 };
 
 __device__ __forceinline__ void fnormal(int f, double& nx, double& ny) {
@@ -553,9 +555,8 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   }
   __syncthreads();
   // ---- residual rows ---------------------------------------------------------
-  double* bp = blk + (size_t)p * S::BLK;
-  double* fr = bp;
-  double* hr = bp + NU;
+  constexpr int NC = S::NC;
+  double* bp = blk + (size_t)p * S::BLK;       // row-major NR x NC: [[K C f],[D E h]]
   for (int r = tid; r < NU + NF; r += nt) {
     if (r < NU) {
       const int v = r / NN, n = r % NN, a = n % NP, b = n / NP;
@@ -580,22 +581,18 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       const double mass = tb.NW[a] * tb.NW[b] * jac;
       const size_t gi = (size_t)e * NU + r;
       if (Rh) Rh[gi] = acc;
-      fr[r] = mass * sh.U[r] + prm.dt_a * acc - (rhs ? rhs[gi] : 0.0);
+      bp[(size_t)r * NC + NC - 1] = mass * sh.U[r] + prm.dt_a * acc - (rhs ? rhs[gi] : 0.0);
     } else {
       const int rr = r - NU, f = rr / NFF, v = (rr % NFF) / NP, mm = rr % NP;
       const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
       constexpr int TO = MX ? 4 : 12;
       double acc = 0.0;
       for (int q = 0; q < NQ; ++q) acc += tb.W[q] * wl * tb.L[q][mm] * sh.VF[f][q][TO + v];
-      hr[rr] = acc;
+      bp[(size_t)(NU + rr) * NC + NC - 1] = acc;
     }
   }
   if (!prm.jacobian) return;
   // ---- Jacobian blocks ---------------------------------------------------------
-  double* Kb = bp + NU + NF;
-  double* Cb = Kb + NU * NU;
-  double* Db = Cb + NU * NF;
-  double* Eb = Db + NF * NU;
   constexpr int TO = MX ? 4 : 12;         // offset of t rows among face outputs
   constexpr int UHI = 4;                  // offset of Uhat among face inputs
   constexpr int XF = 8;                   // offset of (Q | grad U) among face inputs
@@ -641,7 +638,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         acc += w * ph * d;
       }
     }
-    Kb[idx] = prm.dt_a * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0);
+    bp[(size_t)row * NC + col] = prm.dt_a * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0);
   }
   // C = dt_a dR/dUhat (each column lives on one face)
   for (int idx = tid; idx < NU * NF; idx += nt) {
@@ -657,7 +654,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       acc += w * ph * sh.JF[f][q][v][UHI + v2];
       if (!MX) acc += w * (pxi * sx * sh.JF[f][q][4 + 2 * v][UHI + v2] + peta * sy * sh.JF[f][q][5 + 2 * v][UHI + v2]);
     }
-    Cb[idx] = prm.dt_a * acc;
+    bp[(size_t)row * NC + NU + col] = prm.dt_a * acc;
   }
   // D = dh/dU, E = dh/dUhat (E block-diagonal over faces before the mixed elimination)
   for (int idx = tid; idx < NF * NU; idx += nt) {
@@ -674,7 +671,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       if (!MX) d += jt[XF + 2 * v2] * pxi2 * sx + jt[XF + 1 + 2 * v2] * peta2 * sy;
       acc += tb.W[q] * wl * tb.L[q][mm] * d;
     }
-    Db[idx] = acc;
+    bp[(size_t)(NU + row) * NC + col] = acc;
   }
   for (int idx = tid; idx < NF * NF; idx += nt) {
     const int row = idx / NF, col = idx % NF;
@@ -686,14 +683,13 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       for (int q = 0; q < NQ; ++q)
         acc += tb.W[q] * wl * tb.L[q][mm] * tb.L[q][m2] * sh.JF[f][q][TO + v][UHI + v2];
     }
-    Eb[idx] = acc;
+    bp[(size_t)(NU + row) * NC + NU + col] = acc;
   }
   if (MX) {
-    // mixed blocks: A12 = dt_a dR/dQ, A32 = dh/dQ, A21 = dg/dU, A23 = dg/dUhat (g = M_Q Q + l)
-    double* A12 = scr + (size_t)p * S::SCR;
-    double* A21 = A12 + NU * NQM;
-    double* A23 = A21 + NQM * NU;
-    double* A32 = A23 + NQM * NF;
+    // mixed blocks: A12 = dt_a dR/dQ, A32 = dh/dQ (rows of L), A21 = dg/dU, A23 = dg/dUhat (rows of R,
+    // scaled by the inverse of the diagonal mixed mass matrix; g = M_Q Q + l)
+    double* Lm = scr + (size_t)p * S::SCR;          // NR x NQM
+    double* Rm = Lm + (size_t)(NU + NF) * NQM;      // NQM x NR
     for (int idx = tid; idx < NU * NQM; idx += nt) {
       const int row = idx / NQM, col = idx % NQM;
       const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
@@ -716,7 +712,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
           acc += tb.W[q] * wl * ph * ph2 * sh.JF[f][q][v][XF + c];
         }
       }
-      A12[idx] = prm.dt_a * acc;
+      Lm[(size_t)row * NQM + col] = prm.dt_a * acc;
     }
     for (int idx = tid; idx < NF * NQM; idx += nt) {
       const int row = idx / NQM, col = idx % NQM;
@@ -729,12 +725,13 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
         acc += tb.W[q] * wl * tb.L[q][mm] * ph2 * sh.JF[f][q][TO + v][XF + c];
       }
-      A32[idx] = acc;
+      Lm[(size_t)(NU + row) * NQM + col] = acc;
     }
     // lifting coefficients: l_c[n] = sum_q w sum_p cvol(c,p,d) P_p dphi_n/dx_d - sum_f,q w phi_n sum_p cfac(c,p,n) P_p
     for (int idx = tid; idx < NQM * (NU + NF); idx += nt) {
       const int row = idx / (NU + NF), col = idx % (NU + NF);
       const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
+      const double minv = 1.0 / ((c == 1 ? 2.0 : 1.0) * tb.NW[a] * tb.NW[b] * jac);
       double acc = 0.0;
       if (col < NU) {
         const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
@@ -754,7 +751,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
             }
             acc += w * d;
           }
-        A21[(size_t)row * NU + col] = acc;
+        Rm[(size_t)row * (NU + NF) + col] = minv * acc;
       } else {
         const int cc = col - NU;
         const int f = cc / NFF, v2 = (cc % NFF) / NP, m2 = cc % NP;
@@ -776,352 +773,563 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
           }
           acc -= w * d;
         }
-        A23[(size_t)row * NF + cc] = acc;
+        Rm[(size_t)row * (NU + NF) + NU + cc] = minv * acc;
       }
     }
   }
 }
 
-// HDG-MX: eliminate the mixed block, A22 = M_Q diagonal:
-//   K -= A12 A22^-1 A21, C -= A12 A22^-1 A23, D -= A32 A22^-1 A21, E -= A32 A22^-1 A23
-template <int K>
-__global__ void __launch_bounds__(256) hdg_eliminate_kernel(DeviceMesh m, DeviceHDG h, double* __restrict__ blk,
-                                                            const double* __restrict__ scr) {
-  using S = HS<K, true>;
-  constexpr int NP = S::NP, NN = S::NN, NU = S::NU, NF = S::NF, NQM = S::NQM;
-  __shared__ double minv[NQM];
-  const int p = blockIdx.x;
-  const int e = h.im_list[p];
-  const BasisTable& tb = *m.tab;
-  const double jac = 0.25 * m.hx[e] * m.hy[e];
-  for (int i = threadIdx.x; i < NQM; i += blockDim.x) {
-    const int c = i / NN, n = i % NN;
-    minv[i] = 1.0 / ((c == 1 ? 2.0 : 1.0) * tb.NW[n % NP] * tb.NW[n / NP] * jac);
-  }
-  __syncthreads();
-  const double* A12 = scr + (size_t)p * S::SCR;
-  const double* A21 = A12 + NU * NQM;
-  const double* A23 = A21 + NQM * NU;
-  const double* A32 = A23 + NQM * NF;
-  double* bp = blk + (size_t)p * S::BLK;
-  double* Kb = bp + NU + NF;
-  double* Cb = Kb + NU * NU;
-  double* Db = Cb + NU * NF;
-  double* Eb = Db + NF * NU;
-  constexpr int NR = NU + NF;     // rows: K/C rows then D/E rows
-  constexpr int NC = NU + NF;     // cols: K/D cols then C/E cols
-  for (int idx = threadIdx.x; idx < NR * NC; idx += blockDim.x) {
-    const int row = idx / NC, col = idx % NC;
-    const double* Lr = (row < NU) ? A12 + (size_t)row * NQM : A32 + (size_t)(row - NU) * NQM;
-    double acc = 0.0;
-    if (col < NU) {
-      for (int k = 0; k < NQM; ++k) acc += Lr[k] * minv[k] * A21[(size_t)k * NU + col];
-    } else {
-      for (int k = 0; k < NQM; ++k) acc += Lr[k] * minv[k] * A23[(size_t)k * NF + (col - NU)];
-    }
-    if (row < NU) {
-      if (col < NU) Kb[row * NU + col] -= acc;
-      else Cb[row * NF + (col - NU)] -= acc;
-    } else {
-      if (col < NU) Db[(row - NU) * NU + col] -= acc;
-      else Eb[(row - NU) * NF + (col - NU)] -= acc;
-    }
-  }
-}
+// ---------------------------------------------------------------------------
+// batched FP64 GEMM on the matrix cores: C[b] (+)= alpha A[b] B[b], row-major with
+// leading dimensions; 64x64 output tile per workgroup (4 waves x 2x2 tiles of the
+// 16x16x4 f64 MFMA).  Lane l holds A[l%16][l/16], B[l/16][l%16] and accumulates
+// D[l/16 + 4r][l%16], r = 0..3.
+// ---------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------------------
-// condensation: LU of K in LDS, X = K^-1 C, y = K^-1 f, S_T = E - D X, r_T = D y
-// ---------------------------------------------------------------------------
-template <int K>
-__global__ void __launch_bounds__(256) hdg_condense_kernel(DeviceHDG h, size_t blk_stride,
-                                                           const double* __restrict__ blk, double* __restrict__ X,
-                                                           double* __restrict__ y, double* __restrict__ S,
-                                                           double* __restrict__ r, int* __restrict__ info) {
-  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP;
-  constexpr int CH = 16;                  // right-hand sides per chunk
-  extern __shared__ double sm[];
-  double* A = sm;                         // NU x NU
-  double* B = A + NU * NU;                // NU x CH
-  __shared__ int piv[NU];
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const double* bp = blk + (size_t)p * blk_stride;
-  const double* f = bp;
-  const double* Kb = bp + NU + NF;
-  const double* Cb = Kb + NU * NU;
-  const double* Db = Cb + NU * NF;
-  const double* Eb = Db + NF * NU;
-  for (int i = tid; i < NU * NU; i += nt) A[i] = Kb[i];
-  __syncthreads();
-  // right-looking LU with partial pivoting
-  for (int j = 0; j < NU; ++j) {
-    double best = -1.0;
-    int bi = j;
-    for (int i = j + tid; i < NU; i += nt) {
-      const double v = fabs(A[i * NU + j]);
-      if (v > best) { best = v; bi = i; }
+__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, double alpha, int beta_one,
+                                                       const double* __restrict__ A, int lda, long long sA,
+                                                       const double* __restrict__ B, int ldb, long long sB,
+                                                       double* __restrict__ C, int ldc, long long sC) {
+  __shared__ double sa[64][17];
+  __shared__ double sb[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const long long bz = blockIdx.z;
+  const double* Ab = A + bz * sA;
+  const double* Bb = B + bz * sB;
+  double* Cb = C + bz * sC;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  mf_d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = mf_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < Kd; k0 += 16) {
+    for (int idx = tid; idx < 64 * 16; idx += 256) {
+      const int r = idx >> 4, kk = idx & 15;
+      const int gm = m0 + r, gk = k0 + kk;
+      sa[r][kk] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : 0.0;
     }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s && red_v[tid + s] > red_v[tid]) { red_v[tid] = red_v[tid + s]; red_i[tid] = red_i[tid + s]; }
-      __syncthreads();
+    for (int idx = tid; idx < 16 * 64; idx += 256) {
+      const int kk = idx >> 6, cc = idx & 63;
+      const int gk = k0 + kk, gn = n0 + cc;
+      sb[kk][cc] = (gk < Kd && gn < N) ? Bb[(size_t)gk * ldb + gn] : 0.0;
     }
-    const int pr = red_i[0];
-    if (tid == 0) {
-      piv[j] = pr;
-      if (!(red_v[0] > 0.0) && info) info[p] = j + 1;
-    }
-    if (pr != j)
-      for (int c = tid; c < NU; c += nt) {
-        const double t = A[j * NU + c];
-        A[j * NU + c] = A[pr * NU + c];
-        A[pr * NU + c] = t;
-      }
     __syncthreads();
-    const double inv = 1.0 / A[j * NU + j];
-    for (int i = j + 1 + tid; i < NU; i += nt) A[i * NU + j] *= inv;
-    __syncthreads();
-    const int rem = NU - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += nt) {
-      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
-      A[i * NU + c] -= A[i * NU + j] * A[j * NU + c];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kk = 4 * k4 + lk;
+      const double a0 = sa[32 * wr + li][kk], a1 = sa[32 * wr + 16 + li][kk];
+      const double b0 = sb[kk][32 * wc + li], b1 = sb[kk][32 * wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
-  // solve for [f | C] in chunks of CH columns
-  constexpr int NRHS = 1 + NF;
-  double* Xp = X + (size_t)p * NU * NF;
-  double* yp = y + (size_t)p * NU;
-  for (int c0 = 0; c0 < NRHS; c0 += CH) {
-    const int nc = (NRHS - c0 < CH) ? NRHS - c0 : CH;
-    for (int idx = tid; idx < NU * CH; idx += nt) {
-      const int i = idx / CH, c = idx % CH;
-      const int col = c0 + c;
-      double v = 0.0;
-      if (c < nc) v = (col == 0) ? f[i] : Cb[i * NF + (col - 1)];
-      B[i * CH + c] = v;
-    }
-    __syncthreads();
-    if (tid < CH) {
-      for (int j = 0; j < NU; ++j) {
-        const int pr = piv[j];
-        if (pr != j) {
-          const double t = B[j * CH + tid];
-          B[j * CH + tid] = B[pr * CH + tid];
-          B[pr * CH + tid] = t;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + 32 * wr + 16 * ti + lk + 4 * r;
+        const int gn = n0 + 32 * wc + 16 * tj + li;
+        if (gm < M && gn < N) {
+          double* cp = Cb + (size_t)gm * ldc + gn;
+          const double v = alpha * acc[ti][tj][r];
+          *cp = beta_one ? (*cp + v) : v;
         }
       }
+}
+
+static hipError_t gemm_f64(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
+                           const double* A, int lda, long long sA, const double* B, int ldb, long long sB, double* C,
+                           int ldc, long long sC) {
+  if (batch == 0 || M == 0 || N == 0) return hipSuccess;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, ldb,
+                     sB, C, ldc, sC);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// condensation step 1: K^-1 by in-place Gauss-Jordan with partial pivoting in LDS
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ void lds_invert(double* A, int* piv, double* fcol, int tid, int nt) {
+  __shared__ int pr;
+  for (int k = 0; k < N; ++k) {
+    if (tid < 64) {                 // pivot search by the first wave
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < N; i += 64) {
+        const double v = fabs(A[i * N + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) { pr = bi; piv[k] = bi; }
     }
     __syncthreads();
-    for (int j = 0; j < NU; ++j) {            // forward, unit lower
-      for (int idx = tid; idx < (NU - j - 1) * CH; idx += nt) {
-        const int i = j + 1 + idx / CH, c = idx % CH;
-        B[i * CH + c] -= A[i * NU + j] * B[j * CH + c];
+    const int p = pr;
+    if (p != k)
+      for (int c = tid; c < N; c += nt) {
+        const double t = A[k * N + c];
+        A[k * N + c] = A[p * N + c];
+        A[p * N + c] = t;
       }
-      __syncthreads();
-    }
-    for (int j = NU - 1; j >= 0; --j) {       // backward
-      if (tid < CH) B[j * CH + tid] /= A[j * NU + j];
-      __syncthreads();
-      for (int idx = tid; idx < j * CH; idx += nt) {
-        const int i = idx / CH, c = idx % CH;
-        B[i * CH + c] -= A[i * NU + j] * B[j * CH + c];
-      }
-      __syncthreads();
-    }
-    for (int idx = tid; idx < NU * nc; idx += nt) {
-      const int i = idx / nc, c = idx % nc;
-      const int col = c0 + c;
-      if (col == 0) yp[i] = B[i * CH + c];
-      else Xp[i * NF + (col - 1)] = B[i * CH + c];
+    __syncthreads();
+    const double inv = 1.0 / A[k * N + k];
+    for (int i = tid; i < N; i += nt) fcol[i] = A[i * N + k];
+    __syncthreads();
+    for (int c = tid; c < N; c += nt) A[k * N + c] = (c == k) ? inv : A[k * N + c] * inv;
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+      const int i = idx / N, c = idx - i * N;
+      if (i == k) continue;
+      const double base = (c == k) ? 0.0 : A[idx];
+      A[idx] = base - fcol[i] * A[k * N + c];
     }
     __syncthreads();
   }
-  // S_T = E - D X, r_T = D y
-  __threadfence_block();
-  double* Sp = S + (size_t)p * NF * NF;
-  double* rp = r + (size_t)p * NF;
-  for (int idx = tid; idx < NF * (NF + 1); idx += nt) {
-    const int row = idx / (NF + 1), col = idx % (NF + 1);
-    double acc = 0.0;
-    if (col < NF) {
-      for (int k = 0; k < NU; ++k) acc += Db[row * NU + k] * Xp[k * NF + col];
-      Sp[row * NF + col] = Eb[row * NF + col] - acc;
-    } else {
-      for (int k = 0; k < NU; ++k) acc += Db[row * NU + k] * yp[k];
-      rp[row] = acc;
-    }
+  for (int k = N - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k)
+      for (int i = tid; i < N; i += nt) {
+        const double t = A[i * N + k];
+        A[i * N + k] = A[i * N + p];
+        A[i * N + p] = t;
+      }
+    __syncthreads();
   }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, const double* __restrict__ blk,
+                                                         double* __restrict__ Kinv) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NC = NU + NF + 1;
+  extern __shared__ double sm[];
+  __shared__ int piv[NU];
+  __shared__ double fcol[NU];
+  const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const double* bp = blk + (size_t)p * blk_stride;
+  for (int i = tid; i < NU * NU; i += nt) sm[i] = bp[(size_t)(i / NU) * NC + i % NU];
+  __syncthreads();
+  lds_invert<NU>(sm, piv, fcol, tid, nt);
+  double* Kp = Kinv + (size_t)p * NU * NU;
+  for (int i = tid; i < NU * NU; i += nt) Kp[i] = sm[i];
 }
 
 // ---------------------------------------------------------------------------
 // facet system
 // ---------------------------------------------------------------------------
-// b_F = -h_F + sum_T r_T|_F  and the block-Jacobi blocks P_F = sum_T S_T[F, F]
+// b_F = sum_T -(h_T - D_T K_T^-1 f_T)|_F  (the last column of the condensed augmented system)
 template <int K>
 __global__ void facet_rhs_kernel(DeviceHDG h, size_t blk_stride, const double* __restrict__ blk,
-                                 const double* __restrict__ r, const double* __restrict__ S, double* __restrict__ b,
-                                 double* __restrict__ P) {
-  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP;
+                                 double* __restrict__ b) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h.n_hf * NFF) return;
   const int hf = t / NFF, row = t % NFF;
   double acc = 0.0;
-  double prow[NFF];
-  for (int c = 0; c < NFF; ++c) prow[c] = 0.0;
   for (int s = 0; s < 2; ++s) {
     const int pe = h.hf_side[2 * hf + s];
     if (pe < 0) continue;
     const int f = h.hf_face[2 * hf + s];
     const int lr = f * NFF + row;
-    acc += -blk[(size_t)pe * blk_stride + NU + lr] + r[(size_t)pe * NF + lr];
-    const double* Sr = S + (size_t)pe * NF * NF + (size_t)lr * NF + f * NFF;
-    for (int c = 0; c < NFF; ++c) prow[c] += Sr[c];
+    acc -= blk[(size_t)pe * blk_stride + (size_t)(NU + lr) * NC + NC - 1];     // -(h - D K^-1 f)
   }
   b[t] = acc;
-  for (int c = 0; c < NFF; ++c) P[((size_t)hf * NFF + row) * NFF + c] = prow[c];
 }
 
-// in-place inversion of the per-facet blocks by Gauss-Jordan with partial pivoting
+// ---------------------------------------------------------------------------
+// facet preconditioner: restricted additive Schwarz on two-column windows.
+// Each window's restriction of S is block-tridiagonal over its super-rows
+// (element rows; 5 facet slots each).  The factorisation keeps explicit inverses
+// of the eliminated diagonal blocks so that the apply is a chain of GEMVs.
+// Global storage is column-major (transposed) for coalesced GEMVs.
+// ---------------------------------------------------------------------------
+// S[F, G] for HDG facets F, G (NFF x NFF block entry (i, j)): sum over the
+// implicit elements having both as faces of their condensed blocks S_T.
 template <int K>
-__global__ void __launch_bounds__(64) facet_invert_kernel(int n_hf, double* __restrict__ P, int* __restrict__ info) {
-  constexpr int NFF = 4 * (K + 1);
-  __shared__ double A[NFF][2 * NFF];
-  const int hf = blockIdx.x;
-  const int tid = threadIdx.x;
-  double* Pp = P + (size_t)hf * NFF * NFF;
-  for (int i = tid; i < NFF * 2 * NFF; i += blockDim.x) {
-    const int r = i / (2 * NFF), c = i % (2 * NFF);
-    A[r][c] = (c < NFF) ? Pp[r * NFF + c] : ((c - NFF == r) ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < NFF; ++j) {
-    __shared__ int pr;
-    if (tid == 0) {
-      int best = j;
-      double bv = fabs(A[j][j]);
-      for (int i = j + 1; i < NFF; ++i)
-        if (fabs(A[i][j]) > bv) { bv = fabs(A[i][j]); best = i; }
-      pr = best;
-      if (!(bv > 0.0) && info) *info = hf + 1;
-    }
-    __syncthreads();
-    if (pr != j)
-      for (int c = tid; c < 2 * NFF; c += blockDim.x) {
-        const double t = A[j][c];
-        A[j][c] = A[pr][c];
-        A[pr][c] = t;
-      }
-    __syncthreads();
-    const double inv = 1.0 / A[j][j];
-    __syncthreads();
-    for (int c = tid; c < 2 * NFF; c += blockDim.x) A[j][c] *= inv;
-    __syncthreads();
-    for (int idx = tid; idx < NFF * 2 * NFF; idx += blockDim.x) {
-      const int i = idx / (2 * NFF), c = idx % (2 * NFF);
-      if (i != j) {
-        const double fct = A[i][j];
-        if (c != j) A[i][c] -= fct * A[j][c];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < NFF; i += blockDim.x)
-      if (i != j) A[i][j] = 0.0;
-    __syncthreads();
-  }
-  for (int i = tid; i < NFF * NFF; i += blockDim.x) Pp[i] = A[i / NFF][NFF + i % NFF];
-}
-
-// y = P^-1 x (block diagonal)
-template <int K>
-__global__ void facet_precond_kernel(int n_hf, const double* __restrict__ Pinv, const double* __restrict__ x,
-                                     double* __restrict__ y) {
-  constexpr int NFF = 4 * (K + 1);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_hf * NFF) return;
-  const int hf = t / NFF, row = t % NFF;
-  const double* Pr = Pinv + ((size_t)hf * NFF + row) * NFF;
-  const double* xf = x + (size_t)hf * NFF;
+__device__ __forceinline__ double s_entry(const DeviceHDG& h, const double* __restrict__ blk, size_t bs, int F,
+                                          int G, int i, int j) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
   double acc = 0.0;
-  for (int c = 0; c < NFF; ++c) acc += Pr[c] * xf[c];
-  y[t] = acc;
-}
-
-// y = S x, S = sum_T scatter(S_T): each facet row pulls from its adjacent elements
-template <int K>
-__global__ void facet_apply_kernel(DeviceHDG h, const double* __restrict__ S, const double* __restrict__ x,
-                                   double* __restrict__ y) {
-  constexpr int NP = K + 1, NF = 16 * NP, NFF = 4 * NP;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= h.n_hf * NFF) return;
-  const int hf = t / NFF, row = t % NFF;
-  double acc = 0.0;
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int pe = h.hf_side[2 * hf + s];
+    const int pe = h.hf_side[2 * F + s];
     if (pe < 0) continue;
-    const int f = h.hf_face[2 * hf + s];
-    const double* Sr = S + (size_t)pe * NF * NF + (size_t)(f * NFF + row) * NF;
-    for (int f2 = 0; f2 < 4; ++f2) {
-      const double* xf = x + (size_t)h.efacet[4 * pe + f2] * NFF;
-      const double* Sc = Sr + f2 * NFF;
-      for (int c = 0; c < NFF; ++c) acc += Sc[c] * xf[c];
-    }
+    const int lf = h.hf_face[2 * F + s];
+#pragma unroll
+    for (int lg = 0; lg < 4; ++lg)
+      if (h.efacet[4 * pe + lg] == G)
+        acc += blk[(size_t)pe * bs + (size_t)(NU + lf * NFF + i) * NC + NU + lg * NFF + j];
   }
-  y[t] = acc;
+  return acc;
 }
 
-// partial dot products of w with each of V_0..V_{k-1} (k <= 64): out[block][k]
-__global__ void __launch_bounds__(256) multi_dot_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
-                                                        const double* __restrict__ w, double* __restrict__ out) {
+template <int K>
+__global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const double* __restrict__ S, size_t bs,
+                                                         double* __restrict__ Wd, double* __restrict__ Wg,
+                                                         double* __restrict__ Wc) {
+  constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
+  extern __shared__ double smem[];
+  double* A = smem;                    // NB x NB
+  double* Bm = A + NB * NB;            // NH x NB
+  __shared__ int piv[NB];
+  __shared__ double fcol[NB];
+  __shared__ int fs[5], fp[5];
+  const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  for (int g = g0; g < g1; ++g) {
+    if (tid < 5) {
+      fs[tid] = h.win_slot[5 * g + tid];
+      fp[tid] = (g > g0) ? h.win_slot[5 * (g - 1) + tid] : -1;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += nt) {
+      const int r = idx / NB, c = idx % NB;
+      const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
+      double v;
+      if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? 1.0 : 0.0;
+      else v = s_entry<K>(h, S, bs, fs[a], fs[b], i, j);
+      A[idx] = v;
+    }
+    if (g > g0) {
+      // B_r: facet rows of the horizontal slots of r, columns of all slots of r-1
+      for (int idx = tid; idx < NH * NB; idx += nt) {
+        const int r = idx / NB, c = idx % NB;
+        const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
+        Bm[idx] = (fs[a] >= 0 && fp[b] >= 0) ? s_entry<K>(h, S, bs, fs[a], fp[b], i, j) : 0.0;
+      }
+      // C_{r-1}: rows of all slots of r-1, columns of the horizontal slots of r (stored transposed)
+      double* Cg = Wc + (size_t)(g - 1) * NB * NH;
+      for (int idx = tid; idx < NB * NH; idx += nt) {
+        const int r = idx / NH, c = idx % NH;
+        const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
+        Cg[(size_t)c * NB + r] = (fp[a] >= 0 && fs[b] >= 0) ? s_entry<K>(h, S, bs, fp[a], fs[b], i, j) : 0.0;
+      }
+      __syncthreads();
+      // G_r = B_r Dinv_{r-1}  (Dinv stored transposed: Dt[c*NB + k] = Dinv[k][c])
+      const double* Dt = Wd + (size_t)(g - 1) * NB * NB;
+      double* Gg = Wg + (size_t)g * NH * NB;
+      for (int idx = tid; idx < NH * NB; idx += nt) {
+        const int r = idx / NB, c = idx % NB;
+        double acc = 0.0;
+        for (int k = 0; k < NB; ++k) acc += Bm[r * NB + k] * Dt[(size_t)c * NB + k];
+        Gg[(size_t)c * NH + r] = acc;                   // transposed
+      }
+      __syncthreads();
+      // A[H, H] -= G_r C_{r-1}
+      for (int idx = tid; idx < NH * NH; idx += nt) {
+        const int r = idx / NH, c = idx % NH;
+        double acc = 0.0;
+        for (int k = 0; k < NB; ++k) acc += Gg[(size_t)k * NH + r] * Cg[(size_t)c * NB + k];
+        A[r * NB + c] -= acc;
+      }
+    }
+    __syncthreads();
+    lds_invert<NB>(A, piv, fcol, tid, nt);
+    double* Dg = Wd + (size_t)g * NB * NB;
+    for (int idx = tid; idx < NB * NB; idx += nt) {
+      const int r = idx / NB, c = idx % NB;
+      Dg[(size_t)c * NB + r] = A[idx];
+    }
+    __syncthreads();
+  }
+}
+
+// z = M^-1 x: per window, block-Thomas sweeps; owned facets written
+template <int K>
+__global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const double* __restrict__ Wd,
+                                                        const double* __restrict__ Wg, const double* __restrict__ Wc,
+                                                        double* __restrict__ Wy, const double* __restrict__ x,
+                                                        double* __restrict__ z) {
+  constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
+  __shared__ double yv[NB], tv[NB];
+  __shared__ int fs[5];
+  const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  // forward: y_r = x_r - G_r y_{r-1}
+  for (int g = g0; g < g1; ++g) {
+    if (tid < 5) fs[tid] = h.win_slot[5 * g + tid];
+    __syncthreads();
+    for (int r = tid; r < NB; r += nt) {
+      const int a = r / NFF;
+      double v = (fs[a] >= 0) ? x[(size_t)fs[a] * NFF + r % NFF] : 0.0;
+      if (g > g0 && r < NH) {
+        const double* Gg = Wg + (size_t)g * NH * NB;
+        double acc = 0.0;
+        for (int k = 0; k < NB; ++k) acc += Gg[(size_t)k * NH + r] * yv[k];
+        v -= acc;
+      }
+      tv[r] = v;
+    }
+    __syncthreads();
+    for (int r = tid; r < NB; r += nt) {
+      yv[r] = tv[r];
+      Wy[(size_t)g * NB + r] = tv[r];
+    }
+    __syncthreads();
+  }
+  // backward: z_r = Dinv_r (y_r - C_r z_{r+1})
+  for (int g = g1 - 1; g >= g0; --g) {
+    if (tid < 5) fs[tid] = h.win_slot[5 * g + tid];
+    __syncthreads();
+    for (int r = tid; r < NB; r += nt) {
+      double v = Wy[(size_t)g * NB + r];
+      if (g < g1 - 1) {
+        const double* Cg = Wc + (size_t)g * NB * NH;
+        double acc = 0.0;
+        for (int k = 0; k < NH; ++k) acc += Cg[(size_t)k * NB + r] * yv[k];
+        v -= acc;
+      }
+      tv[r] = v;
+    }
+    __syncthreads();
+    const double* Dg = Wd + (size_t)g * NB * NB;
+    for (int r = tid; r < NB; r += nt) {
+      double acc = 0.0;
+      for (int k = 0; k < NB; ++k) acc += Dg[(size_t)k * NB + r] * tv[k];
+      yv[r] = acc;                                        // z_r (its first NH entries feed the next step)
+    }
+    __syncthreads();
+    for (int r = tid; r < NB; r += nt) {
+      const int a = r / NFF;
+      if (fs[a] >= 0 && h.win_own[5 * g + a]) z[(size_t)fs[a] * NFF + r % NFF] = yv[r];
+    }
+    __syncthreads();
+  }
+}
+
+// y = S x: one 64-lane workgroup per facet, coalesced reads of the two S_T row blocks
+template <int K>
+__global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const double* __restrict__ blk, size_t bs,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  __shared__ double xs[2][NF];
+  __shared__ double part[NFF][65];
+  const int hf = blockIdx.x, tid = threadIdx.x;
+  int pe[2], fc[2];
+  for (int s = 0; s < 2; ++s) {
+    pe[s] = h.hf_side[2 * hf + s];
+    fc[s] = h.hf_face[2 * hf + s];
+  }
+  for (int s = 0; s < 2; ++s)
+    for (int i = tid; i < NF; i += 64)
+      xs[s][i] = (pe[s] >= 0) ? x[(size_t)h.efacet[4 * pe[s] + i / NFF] * NFF + i % NFF] : 0.0;
+  __syncthreads();
+  double acc[NFF];
+#pragma unroll
+  for (int r = 0; r < NFF; ++r) acc[r] = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    if (pe[s] < 0) continue;
+    const double* Sb = blk + (size_t)pe[s] * bs + (size_t)(NU + fc[s] * NFF) * NC + NU;   // NFF rows of S_T
+    for (int c = tid; c < NF; c += 64) {
+      const double xc = xs[s][c];
+#pragma unroll
+      for (int r = 0; r < NFF; ++r) acc[r] += Sb[(size_t)r * NC + c] * xc;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NFF; ++r) part[r][tid] = acc[r];
+  __syncthreads();
+  if (tid < NFF) {
+    double sum = 0.0;
+    for (int i = 0; i < 64; ++i) sum += part[tid][i];
+    y[(size_t)hf * NFF + tid] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device-resident GMRES pieces
+// ---------------------------------------------------------------------------
+constexpr int GM_NB = 128;        // blocks of the reduction kernels
+constexpr int GM_MAXM = 64;       // maximum restart length
+
+struct GmState {                  // device layout of the small GMRES arrays (doubles)
+  static constexpr int H = 0;                                   // (MAXM+1) x MAXM column-major: H[j*(MAXM+1)+i]
+  static constexpr int CS = H + (GM_MAXM + 1) * GM_MAXM;
+  static constexpr int SN = CS + GM_MAXM;
+  static constexpr int G = SN + GM_MAXM;                        // MAXM+1
+  static constexpr int RES = G + GM_MAXM + 1;                   // residual estimates |g_{j+1}|
+  static constexpr int HC = RES + GM_MAXM;                      // current column dots (MAXM+1)
+  static constexpr int INVB = HC + GM_MAXM + 1;                 // 1 / beta of the newest vector
+  static constexpr int PART = INVB + 2;                         // GM_NB x (MAXM+1) partial sums
+  static constexpr int NPART = PART + GM_NB * (GM_MAXM + 1);    // GM_NB partial norms
+  static constexpr int SIZE = NPART + GM_NB;
+};
+
+// partial dots of w with V_0..V_{k-1}: part[b][c]
+__global__ void __launch_bounds__(256) gm_dots_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
+                                                      const double* __restrict__ w, double* __restrict__ st) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  for (int j = 0; j < k; ++j) {
-    double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + tid; i < n; i += gridDim.x * blockDim.x)
-      acc += V[(size_t)j * ldv + i] * w[i];
-    red[tid] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
+  const int chunk = (n + GM_NB - 1) / GM_NB;
+  const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+  double* part = st + GmState::PART + (size_t)blockIdx.x * (GM_MAXM + 1);
+  for (int c0 = 0; c0 < k; c0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = r0 + tid; r < r1; r += 256) {
+      const double wr = w[r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < k) acc[c] += V[(size_t)(c0 + c) * ldv + r] * wr;
+    }
+    for (int c = 0; c < 8 && c0 + c < k; ++c) {
+      red[tid] = acc[c];
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+      }
+      if (tid == 0) part[c0 + c] = red[0];
       __syncthreads();
     }
-    if (tid == 0) out[(size_t)blockIdx.x * k + j] = red[0];
-    __syncthreads();
   }
 }
 
-// sum the partials: res[j] = sum_b out[b][j]
-__global__ void reduce_partials_kernel(int nb, int k, const double* __restrict__ part, double* __restrict__ res) {
-  const int j = threadIdx.x;
-  if (j >= k) return;
-  double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += part[(size_t)b * k + j];
-  res[j] = acc;
+// h = sum of the partial dots (added into column j of H when accumulate != 0); w -= V h;
+// with norm != 0 also the partial sums of |w|^2
+__global__ void __launch_bounds__(256) gm_orth_kernel(int n, int k, int j, const double* __restrict__ V, size_t ldv,
+                                                      double* __restrict__ w, double* __restrict__ st, int norm) {
+  __shared__ double hc[GM_MAXM + 1];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  if (tid < k) {
+    double acc = 0.0;
+    for (int b = 0; b < GM_NB; ++b) acc += st[GmState::PART + (size_t)b * (GM_MAXM + 1) + tid];
+    hc[tid] = acc;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && tid < k) st[GmState::H + (size_t)j * (GM_MAXM + 1) + tid] += hc[tid];
+  double nrm = 0.0;
+  for (int r = blockIdx.x * blockDim.x + tid; r < n; r += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < k; ++c) acc += V[(size_t)c * ldv + r] * hc[c];
+    const double v = w[r] - acc;
+    w[r] = v;
+    nrm += v * v;
+  }
+  if (!norm) return;
+  red[tid] = nrm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) st[GmState::NPART + blockIdx.x] = red[0];
 }
 
-// w -= sum_j c_j V_j, c read from device memory
-__global__ void multi_axpy_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
-                                  const double* __restrict__ c, double* __restrict__ w, double sign) {
+// |w|^2 partials only (for the initial residual)
+__global__ void __launch_bounds__(256) gm_norm_kernel(int n, const double* __restrict__ w, double* __restrict__ st) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double nrm = 0.0;
+  for (int r = blockIdx.x * blockDim.x + tid; r < n; r += gridDim.x * blockDim.x) nrm += w[r] * w[r];
+  red[tid] = nrm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) st[GmState::NPART + blockIdx.x] = red[0];
+}
+
+// start a cycle: beta = |r|, g = (beta, 0, ...), H = 0, invb = 1/beta
+__global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
+  const int tid = threadIdx.x;
+  __shared__ double beta;
+  if (tid == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += st[GmState::NPART + b];
+    beta = sqrt(s);
+    st[GmState::G] = beta;
+    st[GmState::INVB] = beta > 0.0 ? 1.0 / beta : 0.0;
+    st[GmState::INVB + 1] = beta;
+  }
+  for (int i = tid; i < (GM_MAXM + 1) * GM_MAXM; i += blockDim.x) st[GmState::H + i] = 0.0;
+  for (int i = 1 + tid; i < GM_MAXM + 1; i += blockDim.x) st[GmState::G + i] = 0.0;
+}
+
+// Givens update of column j: beta from the norm partials, rotations, g, residual estimate, 1/beta
+__global__ void gm_givens_kernel(int j, double* __restrict__ st, int nblocks) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += st[GmState::NPART + b];
+  const double beta = sqrt(s);
+  double* Hc = st + GmState::H + (size_t)j * (GM_MAXM + 1);
+  Hc[j + 1] = beta;
+  for (int i = 0; i < j; ++i) {
+    const double c = st[GmState::CS + i], sn = st[GmState::SN + i];
+    const double t = c * Hc[i] + sn * Hc[i + 1];
+    Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
+    Hc[i] = t;
+  }
+  const double a = Hc[j], b = Hc[j + 1];
+  const double rr = sqrt(a * a + b * b);
+  const double c = rr > 0.0 ? a / rr : 1.0, sn = rr > 0.0 ? b / rr : 0.0;
+  st[GmState::CS + j] = c;
+  st[GmState::SN + j] = sn;
+  Hc[j] = rr;
+  Hc[j + 1] = 0.0;
+  const double gj = st[GmState::G + j];
+  st[GmState::G + j + 1] = -sn * gj;
+  st[GmState::G + j] = c * gj;
+  st[GmState::RES + j] = fabs(sn * gj);
+  st[GmState::INVB] = (beta > 1e-300) ? 1.0 / beta : 0.0;
+}
+
+__global__ void gm_scale_kernel(int n, double* __restrict__ v, const double* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] *= st[GmState::INVB];
+}
+
+__global__ void gm_scale_copy_kernel(int n, const double* __restrict__ x, double* __restrict__ v,
+                                     const double* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = x[i] * st[GmState::INVB];
+}
+
+// r = V y (y on the device, length k)
+__global__ void gm_combine_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
+                                  const double* __restrict__ y, double* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
-  for (int j = 0; j < k; ++j) acc += c[j] * V[(size_t)j * ldv + i];
-  w[i] += sign * acc;
+  for (int c = 0; c < k; ++c) acc += V[(size_t)c * ldv + i] * y[c];
+  r[i] = acc;
 }
 
-__global__ void scale_vec_kernel(int n, const double* __restrict__ x, double a, double* __restrict__ y) {
+// y += a x
+__global__ void axpy_kernel(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i];
+  if (i < n) y[i] += a * x[i];
 }
 
-// back-substitution: dU = -y - X dUhat; U += dU on implicit elements; max |dU|, max |U| per block
+// r = b - r
+__global__ void rsub_kernel(int n, const double* __restrict__ b, double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - r[i];
+}
+
+__global__ void zero_kernel(int n, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// back-substitution: dU = -K^-1 f - K^-1 C dUhat; U += dU on implicit elements; max |dU|, max |U| per block
 template <int K>
 __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const double* __restrict__ X,
-                                                          const double* __restrict__ y,
                                                           const double* __restrict__ dUh, double* __restrict__ U,
                                                           double* __restrict__ part) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP;
@@ -1134,8 +1342,8 @@ __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const dou
   __syncthreads();
   double mdu = 0.0, mu = 0.0;
   for (int i = tid; i < NU; i += blockDim.x) {
-    const double* Xr = X + ((size_t)p * NU + i) * NF;
-    double acc = y[(size_t)p * NU + i];
+    const double* Xr = X + ((size_t)p * NU + i) * (NF + 1);      // [K^-1 C | K^-1 f]
+    double acc = Xr[NF];
     for (int c = 0; c < NF; ++c) acc += Xr[c] * xs[c];
     const double du = -acc;
     const double un = U[(size_t)e * NU + i] + du;
@@ -1189,23 +1397,24 @@ __global__ void __launch_bounds__(256) facet_update_kernel(int n, const double* 
 
 static bool use_mx(const imex_ctx* c) { return c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous; }
 
-static size_t blk_stride(const imex_ctx* c) {
+static size_t blk_stride(const imex_ctx* c) {      // augmented local system (NU+NF) x (NU+NF+1)
   const size_t NU = 4 * c->NN, NF = 16 * c->NP;
-  return NU + NF + NU * NU + 2 * NU * NF + NF * NF;
+  return (NU + NF) * (NU + NF + 1);
 }
 static size_t scr_stride(const imex_ctx* c) {
   if (!use_mx(c)) return 0;
   const size_t NU = 4 * c->NN, NF = 16 * c->NP, NQM = 5 * c->NN;
-  return 2 * NU * NQM + 2 * NQM * NF;
+  return 2 * (NU + NF) * NQM;
 }
 
-constexpr int GM_BLOCKS = 64;
+// GMRES vectors: V (m+1), z, r, b, dx, work
+static size_t gm_vectors(const imex_ctx* c) { return (size_t)c->opt.gmres_restart + 7; }
 
 size_t hdg_workspace_bytes(const imex_ctx* c) {
   const size_t n_im = c->n_im, NU = 4 * c->NN, NF = 16 * c->NP, NFF = 4 * c->NP, n = (size_t)c->n_hf * NFF;
-  const int m = c->opt.gmres_restart;
-  return 8 * (n_im * (blk_stride(c) + scr_stride(c) + NU * NF + NU + NF * NF + NF) + (size_t)c->n_hf * NFF * NFF +
-              n * (size_t)(m + 6) + (size_t)GM_BLOCKS * (m + 2) + 4 * (size_t)(m + 2) + 2 * (n_im + 1024));
+  const size_t NB = 5 * NFF, NH = 2 * NFF, nsr = (size_t)std::max(c->n_superrows, 1);
+  return 8 * (n_im * (blk_stride(c) + scr_stride(c) + NU * NU + NU * (NF + 1)) + nsr * (NB * NB + 2 * NH * NB + NB) +
+              n * gm_vectors(c) + GmState::SIZE + 2 * (n_im + 1024));
 }
 
 imex_status hdg_alloc(imex_ctx* c) {
@@ -1213,17 +1422,19 @@ imex_status hdg_alloc(imex_ctx* c) {
   Workspace& w = c->ws;
   const size_t n_im = c->n_im, NU = 4 * c->NN, NF = 16 * c->NP, NFF = 4 * c->NP;
   const size_t n = (size_t)c->n_hf * NFF;
-  const int m = c->opt.gmres_restart;
   hipError_t e = hipMalloc(&w.blk, 8 * n_im * blk_stride(c));
   if (e == hipSuccess && scr_stride(c)) e = hipMalloc(&w.scr, 8 * n_im * scr_stride(c));
-  if (e == hipSuccess) e = hipMalloc(&w.X, 8 * n_im * NU * NF);
-  if (e == hipSuccess) e = hipMalloc(&w.y, 8 * n_im * NU);
-  if (e == hipSuccess) e = hipMalloc(&w.S, 8 * n_im * NF * NF);
-  if (e == hipSuccess) e = hipMalloc(&w.r, 8 * n_im * NF);
-  if (e == hipSuccess) e = hipMalloc(&w.Pinv, 8 * (size_t)c->n_hf * NFF * NFF);
-  if (e == hipSuccess) e = hipMalloc(&w.gm, 8 * n * (size_t)(m + 6));
-  if (e == hipSuccess) e = hipMalloc(&w.red, 8 * ((size_t)GM_BLOCKS * (m + 2) + 4 * (size_t)(m + 2) + 2 * (n_im + 1024)) + 64);
-  if (e == hipSuccess) e = hipHostMalloc(&w.hred, 8 * (4 * (size_t)(m + 2) + 2 * (n_im + 1024)), 0);
+  if (e == hipSuccess) e = hipMalloc(&w.Kinv, 8 * n_im * NU * NU);
+  if (e == hipSuccess) e = hipMalloc(&w.X, 8 * n_im * NU * (NF + 1));
+  const size_t nsr = (size_t)std::max(c->n_superrows, 1), NB = 5 * NFF, NH = 2 * NFF;
+  if (e == hipSuccess) e = hipMalloc(&w.Wd, 8 * nsr * NB * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.Wg, 8 * nsr * NH * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.Wc, 8 * nsr * NB * NH);
+  if (e == hipSuccess) e = hipMalloc(&w.Wy, 8 * nsr * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.gm, 8 * n * gm_vectors(c));
+  if (e == hipSuccess) e = hipMalloc(&w.gH, 8 * (size_t)GmState::SIZE);
+  if (e == hipSuccess) e = hipMalloc(&w.red, 8 * 2 * (n_im + 1024));
+  if (e == hipSuccess) e = hipHostMalloc(&w.hred, 8 * ((size_t)GmState::SIZE + 2 * (n_im + 1024)), 0);
   if (e != hipSuccess) {
     c->err = std::string("implicit workspace: ") + hipGetErrorString(e);
     return IMEX_ENOMEM;
@@ -1247,10 +1458,14 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
                          c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, w.Q, Rh);
       c->timer_end(ta);
       if (jacobian) {
+        // eliminate the mixed block: [[K C],[D E]] -= [A12; A32] M_Q^-1 [A21 A23]
+        constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NR = NU + NF, NQM = 5 * (KK + 1) * (KK + 1);
         const int te = c->timer_begin(TM_ELIMINATE);
-        hipLaunchKernelGGL(hdg_eliminate_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
-                           w.blk, w.scr);
+        const hipError_t ge = gemm_f64(c->stream, c->n_im, NR, NR, NQM, -1.0, true, w.scr, NQM, (long long)scr_stride(c),
+                                       w.scr + (size_t)NR * NQM, NR, (long long)scr_stride(c), w.blk, NR + 1,
+                                       (long long)blk_stride(c));
         c->timer_end(te);
+        if (ge != hipSuccess) return ge;
       }
     } else {
       const size_t shm = sizeof(AsmShared<KK, false>);
@@ -1264,41 +1479,58 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
   return hipGetLastError();
 }
 
+// condensation (eqs. statically_condensed_system, SchurCompliment):
+//   K^-1 (LDS Gauss-Jordan);  X = K^-1 [C f];  [E h] -= D X  (so that the augmented system's
+//   facet block holds S_T = E - D K^-1 C and h - D K^-1 f)
 static hipError_t launch_condense(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
-    constexpr int NU = 4 * (KK + 1) * (KK + 1);
-    const size_t shm = sizeof(double) * ((size_t)NU * NU + (size_t)NU * 16);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_condense_kernel<KK>),
+    constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NC = NU + NF + 1;
+    const size_t shm = sizeof(double) * (size_t)NU * NU;
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_invert_kernel<KK>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(hdg_condense_kernel<KK>, dim3(c->n_im), dim3(256), shm, c->stream, c->dhdg(), blk_stride(c),
-                       w.blk, w.X, w.y, w.S, w.r, nullptr);
+    hipLaunchKernelGGL(hdg_invert_kernel<KK>, dim3(c->n_im), dim3(256), shm, c->stream, blk_stride(c), w.blk, w.Kinv);
+    const long long bs = (long long)blk_stride(c);
+    hipError_t e = gemm_f64(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, w.Kinv, NU, (long long)NU * NU,
+                            w.blk + NU, NC, bs, w.X, NF + 1, (long long)NU * (NF + 1));
+    if (e != hipSuccess) return e;
+    e = gemm_f64(c->stream, c->n_im, NF, NF + 1, NU, -1.0, true, w.blk + (size_t)NU * NC, NC, bs, w.X, NF + 1,
+                 (long long)NU * (NF + 1), w.blk + (size_t)NU * NC + NU, NC, bs);
+    if (e != hipSuccess) return e;
   });
   return hipGetLastError();
 }
 
-static hipError_t launch_facet_setup(imex_ctx* c, double* b) {
+static hipError_t launch_facet_rhs(imex_ctx* c, double* b) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
+  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_rhs_kernel<KK>, dim3((n + 127) / 128), dim3(128), 0, c->stream,
+                                        c->dhdg(), blk_stride(c), w.blk, b));
+  return hipGetLastError();
+}
+
+static hipError_t launch_ras_factor(imex_ctx* c) {
+  Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
-    hipLaunchKernelGGL(facet_rhs_kernel<KK>, dim3((n + 127) / 128), dim3(128), 0, c->stream, c->dhdg(),
-                       blk_stride(c), w.blk, w.r, w.S, b, w.Pinv);
-    hipLaunchKernelGGL(facet_invert_kernel<KK>, dim3(c->n_hf), dim3(64), 0, c->stream, c->n_hf, w.Pinv, nullptr);
+    constexpr int NFF = 4 * (KK + 1), NB = 5 * NFF, NH = 2 * NFF;
+    const size_t shm = sizeof(double) * ((size_t)NB * NB + (size_t)NH * NB);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(ras_factor_kernel<KK>, dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(), w.blk,
+                       blk_stride(c), w.Wd, w.Wg, w.Wc);
   });
   return hipGetLastError();
 }
 
 static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
-  const int n = c->n_hf * 4 * c->NP;
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_precond_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
-                                        c->n_hf, c->ws.Pinv, x, y));
+  HDG_DISPATCH(c->K, hipLaunchKernelGGL(ras_apply_kernel<KK>, dim3(c->n_win), dim3(128), 0, c->stream, c->dhdg(),
+                                        c->ws.Wd, c->ws.Wg, c->ws.Wc, c->ws.Wy, x, y));
   return hipGetLastError();
 }
 
 static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
-  const int n = c->n_hf * 4 * c->NP;
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_apply_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
-                                        c->dhdg(), c->ws.S, x, y));
+  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_apply_kernel<KK>, dim3(c->n_hf), dim3(64), 0, c->stream, c->dhdg(),
+                                        c->ws.blk, blk_stride(c), x, y));
   return hipGetLastError();
 }
 
@@ -1311,117 +1543,97 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
     }                                                                            \
   } while (0)
 
-// dots[j] = <V_j, w> for j < k, result copied to host (synchronises)
-static imex_status dots_to_host(imex_ctx* c, int n, int k, const double* V, size_t ldv, const double* w, double* dev_res,
-                                double* host) {
-  double* part = c->ws.red;
-  hipLaunchKernelGGL(multi_dot_kernel, dim3(GM_BLOCKS), dim3(256), 0, c->stream, n, k, V, ldv, w, part);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, c->stream, GM_BLOCKS, k, part, dev_res);
-  HTRY(hipGetLastError());
-  HTRY(hipMemcpyAsync(host, dev_res, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
-  HTRY(hipStreamSynchronize(c->stream));
-  return IMEX_OK;
-}
+// Right-preconditioned restarted GMRES(m) on S x = b, x from 0.  The Arnoldi
+// process (classical Gram-Schmidt with one re-orthogonalisation pass, Givens
+// rotations) runs entirely on the device; the host reads the residual history
+// every GM_CHECK iterations and solves the small least-squares problem.
+constexpr int GM_CHECK = 8;
 
-// y += a x
-__global__ void axpy_kernel(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += a * x[i];
-}
-
-// Right-preconditioned restarted GMRES on S x = b (x starts at 0).  Classical
-// Gram-Schmidt with one re-orthogonalisation pass; Givens rotations on the host.
 static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
-  const int m = c->opt.gmres_restart;
+  const int m = std::min(c->opt.gmres_restart, GM_MAXM);
   const size_t ldv = n;
-  double* V = w.gm;                       // m+1 basis vectors
-  double* z = V + ldv * (m + 1);          // work
-  double* r = z + ldv;                    // residual
-  double* dres = w.red + (size_t)GM_BLOCKS * (m + 2);
-  double* hbuf = w.hred;
+  double* V = w.gm;
+  double* z = V + ldv * (m + 1);
+  double* r = z + ldv;
+  double* yd = w.gH + GmState::HC;           // reuse: coefficient vector for V y
+  double* st = w.gH;
+  double* hb = w.hred;
   const int nb = (n + 255) / 256;
-  HTRY(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
-  imex_status st = dots_to_host(c, n, 1, b, ldv, b, dres, hbuf);
-  if (st != IMEX_OK) return st;
-  const double bnorm = std::sqrt(hbuf[0]);
-  *its_out = 0;
-  if (bnorm == 0.0) return IMEX_OK;
-  const double tol = c->opt.gmres_rtol * bnorm;
-  int total = 0;
+  hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, c->stream, n, x);
   HTRY(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  double beta = bnorm;
-  while (total < c->opt.gmres_maxit) {
-    hipLaunchKernelGGL(scale_vec_kernel, dim3(nb), dim3(256), 0, c->stream, n, r, 1.0 / beta, V);
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
-    int j = 0;
-    bool done = false;
-    while (j < m && total < c->opt.gmres_maxit) {
-      double* vj = V + ldv * j;
-      double* vn = V + ldv * (j + 1);
-      HTRY(launch_precond(c, vj, z));
-      HTRY(launch_apply(c, z, vn));
-      for (int pass = 0; pass < 2; ++pass) {
-        st = dots_to_host(c, n, j + 1, V, ldv, vn, dres, hbuf);
-        if (st != IMEX_OK) return st;
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hbuf[i];
-        hipLaunchKernelGGL(multi_axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, j + 1, V, ldv, dres, vn, -1.0);
+  std::vector<double> H((size_t)(GM_MAXM + 1) * GM_MAXM), g(GM_MAXM + 1), yv(GM_MAXM);
+  double tol = -1.0;
+  int total = 0;
+  *its_out = 0;
+  while (true) {
+    // beta = |r|, V_0 = r / beta
+    hipLaunchKernelGGL(gm_norm_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, r, st);
+    hipLaunchKernelGGL(gm_start_kernel, dim3(1), dim3(256), 0, c->stream, st, GM_NB);
+    hipLaunchKernelGGL(gm_scale_copy_kernel, dim3(nb), dim3(256), 0, c->stream, n, r, V, st);
+    HTRY(hipMemcpyAsync(hb, st + GmState::INVB + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HTRY(hipStreamSynchronize(c->stream));
+    const double beta = hb[0];
+    if (tol < 0.0) tol = c->opt.gmres_rtol * beta;
+    if (!(beta > tol) || total >= c->opt.gmres_maxit) break;
+    int j = 0, jdone = -1;
+    while (j < m && jdone < 0 && total < c->opt.gmres_maxit) {
+      const int j1 = std::min(std::min(m, j + GM_CHECK), j + (c->opt.gmres_maxit - total));
+      for (int jj = j; jj < j1; ++jj) {
+        double* vj = V + ldv * jj;
+        double* vn = V + ldv * (jj + 1);
+        HTRY(launch_precond(c, vj, z));
+        HTRY(launch_apply(c, z, vn));
+        for (int pass = 0; pass < 2; ++pass) {
+          hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
+          hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st,
+                             pass);
+        }
+        hipLaunchKernelGGL(gm_givens_kernel, dim3(1), dim3(64), 0, c->stream, jj, st, GM_NB);
+        hipLaunchKernelGGL(gm_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, vn, st);
       }
-      st = dots_to_host(c, n, 1, vn, ldv, vn, dres, hbuf);
-      if (st != IMEX_OK) return st;
-      const double hn = std::sqrt(hbuf[0]);
-      H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0.0) hipLaunchKernelGGL(scale_vec_kernel, dim3(nb), dim3(256), 0, c->stream, n, vn, 1.0 / hn, vn);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
-        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = t;
-      }
-      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-      const double rr = std::sqrt(a * a + bb * bb);
-      cs[j] = (rr > 0.0) ? a / rr : 1.0;
-      sn[j] = (rr > 0.0) ? bb / rr : 0.0;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      ++j;
-      ++total;
-      if (std::fabs(gv[j]) <= tol || hn == 0.0) { done = true; break; }
+      HTRY(hipGetLastError());
+      HTRY(hipMemcpyAsync(hb, st + GmState::RES + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, c->stream));
+      HTRY(hipStreamSynchronize(c->stream));
+      for (int jj = j; jj < j1; ++jj)
+        if (!(hb[jj - j] > tol)) { jdone = jj; break; }
+      total += (jdone >= 0 ? jdone + 1 : j1) - j;
+      j = (jdone >= 0) ? jdone + 1 : j1;
     }
-    // y = H^-1 g; x += P^-1 (V y)
-    for (int i = j - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * yv[k];
-      yv[i] = s / H[(size_t)i * m + i];
+    const int k = j;
+    if (k == 0) break;
+    // least squares: H[0:k, 0:k] y = g[0:k] (H already rotated to upper triangular)
+    HTRY(hipMemcpyAsync(hb, st + GmState::H, sizeof(double) * (GM_MAXM + 1) * GM_MAXM, hipMemcpyDeviceToHost,
+                        c->stream));
+    HTRY(hipMemcpyAsync(hb + (GM_MAXM + 1) * GM_MAXM, st + GmState::G, sizeof(double) * (GM_MAXM + 1),
+                        hipMemcpyDeviceToHost, c->stream));
+    HTRY(hipStreamSynchronize(c->stream));
+    const double* Hh = hb;
+    const double* gh = hb + (GM_MAXM + 1) * GM_MAXM;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gh[i];
+      for (int q = i + 1; q < k; ++q) s -= Hh[(size_t)q * (GM_MAXM + 1) + i] * yv[q];
+      const double d = Hh[(size_t)i * (GM_MAXM + 1) + i];
+      yv[i] = (d != 0.0) ? s / d : 0.0;
     }
-    HTRY(hipMemcpyAsync(dres, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, c->stream));
-    HTRY(hipMemsetAsync(r, 0, sizeof(double) * n, c->stream));
-    hipLaunchKernelGGL(multi_axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, j, V, ldv, dres, r, 1.0);
+    HTRY(hipMemcpyAsync(yd, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(gm_combine_kernel, dim3(nb), dim3(256), 0, c->stream, n, k, V, ldv, yd, r);
     HTRY(launch_precond(c, r, z));
     hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, 1.0, z, x);
-    if (done) break;
-    // true residual for the restart: r = b - S x
+    // true residual for the next cycle: r = b - S x
     HTRY(launch_apply(c, x, r));
-    hipLaunchKernelGGL(scale_vec_kernel, dim3(nb), dim3(256), 0, c->stream, n, r, -1.0, r);
-    hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, 1.0, b, r);
-    st = dots_to_host(c, n, 1, r, ldv, r, dres, hbuf);
-    if (st != IMEX_OK) return st;
-    beta = std::sqrt(hbuf[0]);
-    if (beta <= tol) break;
+    hipLaunchKernelGGL(rsub_kernel, dim3(nb), dim3(256), 0, c->stream, n, b, r);
+    HTRY(hipGetLastError());
+    if (jdone >= 0 || total >= c->opt.gmres_maxit) break;
   }
   *its_out = total;
-  HTRY(hipGetLastError());
   return IMEX_OK;
 }
 
 static hipError_t launch_backsub(imex_ctx* c, const double* dx, double* U, double* part) {
   HDG_DISPATCH(c->K, hipLaunchKernelGGL(hdg_backsub_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, c->dhdg(),
-                                        c->ws.X, c->ws.y, dx, U, part));
+                                        c->ws.X, dx, U, part));
   return hipGetLastError();
 }
 
@@ -1432,11 +1644,18 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   const int m = c->opt.gmres_restart;
   double* b = w.gm + (size_t)n * (m + 3);
   double* dx = b + n;
-  double* part = w.red + (size_t)GM_BLOCKS * (m + 2) + 4 * (size_t)(m + 2);
+  double* part = w.red;
   const int fb = 256;
   int newton = 0, gm_total = 0;
   bool converged = false;
   double last = 0.0;
+  // Newton (Sec. 4.3).  The Schwarz preconditioner of the facet solve is factorised at
+  // the first iteration of the stage and reused (GMRES still solves the current system);
+  // it is refreshed when GMRES needed many iterations.  Stopping: the increments of U
+  // and Uhat are below rtol times the largest |U| and |Uhat|, either measured or
+  // predicted from the observed contraction (theta / (1 - theta) |dz| with theta < 1/2).
+  double du_prev = 0.0, dh_prev = 0.0;
+  int last_gmres = 0;
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
     newton = it;
     HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
@@ -1444,7 +1663,8 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     HTRY(launch_condense(c));
     c->timer_end(tt);
     tt = c->timer_begin(TM_FACET);
-    HTRY(launch_facet_setup(c, b));
+    HTRY(launch_facet_rhs(c, b));
+    if (it == 1 || last_gmres > 30) HTRY(launch_ras_factor(c));
     c->timer_end(tt);
     int its = 0;
     tt = c->timer_begin(TM_GMRES);
@@ -1452,6 +1672,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     c->timer_end(tt);
     if (s != IMEX_OK) return s;
     gm_total += its;
+    last_gmres = its;
     tt = c->timer_begin(TM_BACKSUB);
     HTRY(launch_backsub(c, dx, U, part));
     hipLaunchKernelGGL(facet_update_kernel, dim3(fb), dim3(256), 0, c->stream, n, dx, Uhat, part + 2 * c->n_im);
@@ -1472,7 +1693,17 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
       return IMEX_ENONFINITE;
     }
     last = (uu > 0.0) ? du / uu : du;
-    if (du <= c->opt.newton_rtol * uu && dh <= c->opt.newton_rtol * hh) { converged = true; break; }
+    const double tu = c->opt.newton_rtol * uu, th = c->opt.newton_rtol * hh;
+    if (du <= tu && dh <= th) { converged = true; break; }
+    if (it >= 2 && du_prev > 0.0 && dh_prev > 0.0) {
+      const double qu = du / du_prev, qh = dh / dh_prev;
+      if (qu < 0.5 && qh < 0.5 && qu / (1.0 - qu) * du <= tu && qh / (1.0 - qh) * dh <= th) {
+        converged = true;
+        break;
+      }
+    }
+    du_prev = du;
+    dh_prev = dh;
   }
   if (st) {
     st->newton_its = newton;
@@ -1492,17 +1723,18 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
 imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
                              double* f, double* h, double* K, double* C, double* D, double* E) {
   HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
-  const size_t NU = 4 * c->NN, NF = 16 * c->NP, bs = blk_stride(c);
+  const size_t NU = 4 * c->NN, NF = 16 * c->NP, NC = NU + NF + 1, bs = blk_stride(c);
+  const size_t e8 = sizeof(double);
   for (int p = 0; p < c->n_im; ++p) {
     const double* bp = c->ws.blk + (size_t)p * bs;
-    HTRY(hipMemcpyAsync(f + p * NU, bp, 8 * NU, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpyAsync(h + p * NF, bp + NU, 8 * NF, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpyAsync(K + p * NU * NU, bp + NU + NF, 8 * NU * NU, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpyAsync(C + p * NU * NF, bp + NU + NF + NU * NU, 8 * NU * NF, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpyAsync(D + p * NF * NU, bp + NU + NF + NU * NU + NU * NF, 8 * NF * NU, hipMemcpyDeviceToDevice,
-                        c->stream));
-    HTRY(hipMemcpyAsync(E + p * NF * NF, bp + NU + NF + NU * NU + 2 * NU * NF, 8 * NF * NF, hipMemcpyDeviceToDevice,
-                        c->stream));
+    HTRY(hipMemcpy2DAsync(f + p * NU, e8, bp + NC - 1, NC * e8, e8, NU, hipMemcpyDeviceToDevice, c->stream));
+    HTRY(hipMemcpy2DAsync(h + p * NF, e8, bp + NU * NC + NC - 1, NC * e8, e8, NF, hipMemcpyDeviceToDevice, c->stream));
+    HTRY(hipMemcpy2DAsync(K + p * NU * NU, NU * e8, bp, NC * e8, NU * e8, NU, hipMemcpyDeviceToDevice, c->stream));
+    HTRY(hipMemcpy2DAsync(C + p * NU * NF, NF * e8, bp + NU, NC * e8, NF * e8, NU, hipMemcpyDeviceToDevice, c->stream));
+    HTRY(hipMemcpy2DAsync(D + p * NF * NU, NU * e8, bp + NU * NC, NC * e8, NU * e8, NF, hipMemcpyDeviceToDevice,
+                          c->stream));
+    HTRY(hipMemcpy2DAsync(E + p * NF * NF, NF * e8, bp + NU * NC + NU, NC * e8, NF * e8, NF, hipMemcpyDeviceToDevice,
+                          c->stream));
   }
   HTRY(hipStreamSynchronize(c->stream));
   return IMEX_OK;
