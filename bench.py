@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", default="boundary_layer")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (calibrates HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -92,6 +94,13 @@ def main():
     if not os.path.exists(binding.LIB_PATH):
         from paper_2607_16044_amd import build
         build.build()
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = workloads.get(args.workload)
     prec = 0 if args.precision == "fp64" else 1
     eng = binding.Engine(wl, precision=prec)
