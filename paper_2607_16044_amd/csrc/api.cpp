@@ -117,7 +117,7 @@ void free_regions(imex_ctx* c) {
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.blk, &w.scr, &w.Kinv, &w.X, &w.Wd, &w.Wg, &w.Wc, &w.Wy, &w.gH, &w.gm, &w.red}) {
+  for (double** p : {&w.blk, &w.scr, &w.rec, &w.Kinv, &w.X, &w.Wd, &w.Wg, &w.Wc, &w.Wy, &w.gH, &w.gm, &w.red}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

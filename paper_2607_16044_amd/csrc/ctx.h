@@ -49,6 +49,7 @@ struct Workspace {
   // implicit Newton
   double* blk = nullptr;        // per implicit element: augmented system [[K C f],[D E h]] (becomes [[. . .],[D S h-DK^-1f]])
   double* scr = nullptr;        // per implicit element: HDG-MX mixed blocks [A12; A32] and M_Q^-1 [A21 A23]
+  double* rec = nullptr;        // per implicit element: HDG-MX point-wise Jacobians (assembly -> contraction)
   double* Kinv = nullptr;       // per implicit element: K^-1 [NU][NU]
   double* X = nullptr;          // per implicit element: K^-1 [C f]  [NU][NF+1]
   float* X32 = nullptr;         // mixed-precision copies

@@ -227,13 +227,30 @@ template <int K, bool MX> struct AsmShared {
   double Qf[MX ? 4 : 1][S::NQ][5];
 };
 
-template <int K, bool MX>
+// Point-wise record of one HDG-MX element written by the assembly kernel in
+// point mode and read by the block contraction: d(volume flux)/d(U, Q) at the
+// volume points, d(s, t)/d(U, Uhat, Q) at the face points and the derivatives
+// of the lifted primitives (u, v, theta) with respect to U (volume points) and
+// Uhat (face points).
+template <int K> struct MxRec {
+  static constexpr int NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
+  static constexpr int JV = 0;                        // [NQV][8][9]
+  static constexpr int JF = JV + NQV * 8 * 9;         // [4][NQ][8][13]
+  static constexpr int JL = JF + 4 * NQ * 8 * 13;     // [NQV][3][4]
+  static constexpr int JLF = JL + NQV * 12;           // [4][NQ][3][4]
+  static constexpr int SIZE = JLF + 4 * NQ * 12;
+};
+
+// DUMP = false: residual rows and every Jacobian block contracted here.
+// DUMP = true (HDG-MX): residual rows here, the point-wise Jacobians go to rec
+// for hdg_mx_contract_kernel.
+template <int K, bool MX, bool DUMP = false>
 __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ Uhat,
                                                            const double* __restrict__ rhs, double* __restrict__ blk,
                                                            double* __restrict__ scr, double* __restrict__ Qout,
-                                                           double* __restrict__ Rh) {
+                                                           double* __restrict__ Rh, double* __restrict__ rec) {
   using S = HS<K, MX>;
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
@@ -592,6 +609,20 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
     }
   }
   if (!prm.jacobian) return;
+  if constexpr (DUMP) {
+    static_assert(MX, "point records are HDG-MX only");
+    using R = MxRec<K>;
+    double* rp = rec + (size_t)p * R::SIZE;
+    const double* jv = &sh.JV[0][0][0];
+    const double* jf = &sh.JF[0][0][0][0];
+    const double* jl = &sh.JL[0][0][0];
+    const double* jlf = &sh.JLF[0][0][0][0];
+    for (int i = tid; i < R::JF - R::JV; i += nt) rp[R::JV + i] = jv[i];
+    for (int i = tid; i < R::JL - R::JF; i += nt) rp[R::JF + i] = jf[i];
+    for (int i = tid; i < R::JLF - R::JL; i += nt) rp[R::JL + i] = jl[i];
+    for (int i = tid; i < R::SIZE - R::JLF; i += nt) rp[R::JLF + i] = jlf[i];
+    return;
+  } else {
   // ---- Jacobian blocks ---------------------------------------------------------
   constexpr int TO = MX ? 4 : 12;         // offset of t rows among face outputs
   constexpr int UHI = 4;                  // offset of Uhat among face inputs
@@ -775,6 +806,281 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         }
         Rm[(size_t)row * (NU + NF) + NU + cc] = minv * acc;
       }
+    }
+  }
+  }  // DUMP
+}
+
+// ---------------------------------------------------------------------------
+// HDG-MX block contraction from the point records (sum factorisation).
+//
+// Volume contributions to K = M + dt_a dR/dU, A12 = dt_a dR/dQ and the lifting
+// block A21 = M_Q^-1 dl/dU all have the form
+//   sum_{qi,qj} w_i w_j |J| [ s_x D(qi,a) L(qj,b) Jx(qi,qj) + s_y L(qi,a) D(qj,b) Jy(qi,qj) ] L(qi,a2) L(qj,b2)
+// for row node (a, b) and column node (a2, b2).  One thread owns the row/column
+// pair and the node pair (a, a2) and keeps all (b, b2) in registers: the qi sum
+// is done once per qj, the qj sum as a rank-2 update of the 25 accumulators
+// with the 1D tables TLL[q][b][b2] = w_q L(q,b) L(q,b2), TDL = w_q D(q,b) L(q,b2).
+// Faces x-/x+ add LE(a) LE(a2) sum_q TLL[q][b][b2] J_f(q), faces y-/y+ add
+// LE(b) LE(b2) sum_q TLL[q][a][a2] J_f(q).  The face-only blocks C, D, E, A32,
+// A23 are single 1D sums per entry.
+//
+// Work split: five workgroups per element (K | A12 | A21 | C D E | A32 A23),
+// numbered so that the five of one element run on the same XCD and share its
+// L2 copy of the point record.
+// ---------------------------------------------------------------------------
+template <int K> struct CtShared {
+  static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
+  double TLL[NQ][NP][NP];
+  double TDL[NQ][NP][NP];
+  double LE[2][NP];
+  double NW[NP];
+  union {
+    struct {                     // groups 0-2: up to 20 (row variable, column variable) pairs
+      double JX[20][NQV];
+      double JY[20][NQV];
+      double JS[20][4][NQ];
+    } v;
+    struct {                     // groups 3-4: the face records
+      double JF[4][NQ][8][13];
+      double JLF[4][NQ][3][4];
+    } f;
+  } u;
+};
+
+// coefficients of the lifted primitives in the mixed equations: component c of
+// l(U, Uhat) = sum_p (cx[c][p] d/dx + cy[c][p] d/dy) of P_p, P = (u, v, theta)
+__device__ __forceinline__ void lift_coef(int c, double cx[3], double cy[3]) {
+  cx[0] = cx[1] = cx[2] = cy[0] = cy[1] = cy[2] = 0.0;
+  switch (c) {
+    case 0: cx[0] = 2.0 / 3.0; cy[1] = -1.0 / 3.0; break;    // eps_11 - tr/3
+    case 1: cx[1] = 1.0; cy[0] = 1.0; break;                 // 2 eps_12 (weighted by 2 in M_Q)
+    case 2: cx[0] = -1.0 / 3.0; cy[1] = 2.0 / 3.0; break;    // eps_22 - tr/3
+    case 3: cx[2] = 1.0; break;                              // grad theta, x
+    default: cy[2] = 1.0; break;                             // grad theta, y
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
+                                                              const double* __restrict__ rec,
+                                                              double* __restrict__ blk, double* __restrict__ scr) {
+  using S = HS<K, true>;
+  using R = MxRec<K>;
+  constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
+  constexpr int NQM = S::NQM, NR = S::NR, NC = S::NC;
+  __shared__ CtShared<K> sh;
+  // XCD-aware numbering: consecutive workgroups go to consecutive XCDs, so the
+  // five groups of element p are spread over blocks 8 apart
+  const int L = blockIdx.x;
+  const int xcd = L & 7, rr = L >> 3;
+  const int grp = rr % 5;
+  const int p = 8 * (rr / 5) + xcd;
+  if (p >= h.n_im) return;
+  const int e = h.im_list[p];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const BasisTable& tb = *m.tab;
+  const double hx = m.hx[e], hy = m.hy[e];
+  const double sx = 2.0 / hx, sy = 2.0 / hy, jac = 0.25 * hx * hy;
+  const double wlx = 0.5 * hy, wly = 0.5 * hx;       // line measure factor of x-faces / y-faces
+  for (int i = tid; i < NQ * NN; i += nt) {
+    const int q = i / NN, a = (i / NP) % NP, a2 = i % NP;
+    sh.TLL[q][a][a2] = tb.W[q] * tb.L[q][a] * tb.L[q][a2];
+    sh.TDL[q][a][a2] = tb.W[q] * tb.D[q][a] * tb.L[q][a2];
+  }
+  if (tid < 2 * NP) sh.LE[tid / NP][tid % NP] = tb.LE[tid / NP][tid % NP];
+  if (tid < NP) sh.NW[tid] = tb.NW[tid];
+  const double* rp = rec + (size_t)p * R::SIZE;
+  double* bp = blk + (size_t)p * S::BLK;
+  double* Lm = scr + (size_t)p * S::SCR;             // [A12; A32]      NR x NQM
+  double* Rm = Lm + (size_t)NR * NQM;                // M_Q^-1 [A21 A23] NQM x NR
+  if (grp <= 2) {
+    // gather the pair slices: grp 0 K (v, v2), grp 1 A12 (v, c), grp 2 A21 (c, v2)
+    const int npair = (grp == 0) ? 16 : 20;
+    for (int i = tid; i < npair * NQV; i += nt) {
+      const int pr = i / NQV, qv = i % NQV;
+      double jx, jy;
+      if (grp == 0) {
+        const int v = pr >> 2, v2 = pr & 3;
+        jx = rp[R::JV + (qv * 8 + 2 * v) * 9 + v2];
+        jy = rp[R::JV + (qv * 8 + 2 * v + 1) * 9 + v2];
+      } else if (grp == 1) {
+        const int v = pr / 5, c = pr % 5;
+        jx = rp[R::JV + (qv * 8 + 2 * v) * 9 + 4 + c];
+        jy = rp[R::JV + (qv * 8 + 2 * v + 1) * 9 + 4 + c];
+      } else {
+        const int c = pr >> 2, v2 = pr & 3;
+        double cx[3], cy[3];
+        lift_coef(c, cx, cy);
+        jx = jy = 0.0;
+        for (int pp = 0; pp < 3; ++pp) {
+          const double d = rp[R::JL + (qv * 3 + pp) * 4 + v2];
+          jx += cx[pp] * d;
+          jy += cy[pp] * d;
+        }
+      }
+      sh.u.v.JX[pr][qv] = jx;
+      sh.u.v.JY[pr][qv] = jy;
+    }
+    if (grp < 2)
+      for (int i = tid; i < npair * 4 * NQ; i += nt) {
+        const int pr = i / (4 * NQ), f = (i / NQ) % 4, q = i % NQ;
+        const int v = (grp == 0) ? pr >> 2 : pr / 5;
+        const int col = (grp == 0) ? (pr & 3) : 8 + pr % 5;
+        sh.u.v.JS[pr][f][q] = rp[R::JF + ((f * NQ + q) * 8 + v) * 13 + col];
+      }
+    __syncthreads();
+    const double cx = jac * sx, cy = jac * sy;
+    for (int t = tid; t < npair * NN; t += nt) {
+      const int pr = t / NN, a = (t / NP) % NP, a2 = t % NP;
+      double acc[NP][NP];
+#pragma unroll
+      for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] = 0.0;
+      const double* jxp = sh.u.v.JX[pr];
+      const double* jyp = sh.u.v.JY[pr];
+#pragma unroll 1
+      for (int qj = 0; qj < NQ; ++qj) {
+        double px = 0.0, py = 0.0;
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+          px += sh.TDL[qi][a][a2] * jxp[qi + NQ * qj];
+          py += sh.TLL[qi][a][a2] * jyp[qi + NQ * qj];
+        }
+        px *= cx;
+        py *= cy;
+#pragma unroll
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.TLL[qj][b][b2] * px + sh.TDL[qj][b][b2] * py;
+      }
+      if (grp < 2) {
+        const double(*js)[NQ] = sh.u.v.JS[pr];
+#pragma unroll 1
+        for (int s = 0; s < 2; ++s) {       // x-faces: f = s
+          const double c0 = wlx * sh.LE[s][a] * sh.LE[s][a2];
+#pragma unroll 1
+          for (int q = 0; q < NQ; ++q) {
+            const double cq = c0 * js[s][q];
+#pragma unroll
+            for (int b = 0; b < NP; ++b)
+#pragma unroll
+              for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.TLL[q][b][b2] * cq;
+          }
+        }
+#pragma unroll 1
+        for (int s = 0; s < 2; ++s) {       // y-faces: f = 2 + s
+          double sg = 0.0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) sg += sh.TLL[q][a][a2] * js[2 + s][q];
+          sg *= wly;
+#pragma unroll
+          for (int b = 0; b < NP; ++b)
+#pragma unroll
+            for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.LE[s][b] * sh.LE[s][b2] * sg;
+        }
+      }
+      if (grp == 0) {
+        const int v = pr >> 2, v2 = pr & 3;
+#pragma unroll
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2) {
+            const int row = v * NN + a + NP * b, col = v2 * NN + a2 + NP * b2;
+            const double mass = (row == col) ? sh.NW[a] * sh.NW[b] * jac : 0.0;
+            bp[(size_t)row * NC + col] = dt_a * acc[b][b2] + mass;
+          }
+      } else if (grp == 1) {
+        const int v = pr / 5, c = pr % 5;
+#pragma unroll
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2)
+            Lm[(size_t)(v * NN + a + NP * b) * NQM + c * NN + a2 + NP * b2] = dt_a * acc[b][b2];
+      } else {
+        const int c = pr >> 2, v2 = pr & 3;
+        const double fc = (c == 1) ? 2.0 : 1.0;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+          const double minv = 1.0 / (fc * sh.NW[a] * sh.NW[b] * jac);
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2) Rm[(size_t)(c * NN + a + NP * b) * NR + v2 * NN + a2 + NP * b2] = minv * acc[b][b2];
+        }
+      }
+    }
+    return;
+  }
+  // face-only blocks
+  for (int i = tid; i < 4 * NQ * 8 * 13; i += nt) (&sh.u.f.JF[0][0][0][0])[i] = rp[R::JF + i];
+  for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
+  __syncthreads();
+  // 1D face sum: sum_q TLL[q][x][y] J(q) for face f
+  auto fsum = [&](int f, int x, int y, int jr, int jc) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc += sh.TLL[q][x][y] * sh.u.f.JF[f][q][jr][jc];
+    return acc;
+  };
+  if (grp == 3) {
+    // C = dt_a dR/dUhat (NU x NF), D = dh/dU (NF x NU), E = dh/dUhat (NF x NF, block diagonal)
+    constexpr int NCC = NU * NF, NDD = NF * NU, NEE = NF * NF;
+    for (int i = tid; i < NCC + NDD + NEE; i += nt) {
+      if (i < NCC) {
+        const int row = i / NF, col = i % NF;
+        const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
+        const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
+        const double val = (f < 2) ? wlx * sh.LE[s][a] * fsum(f, b, m2, v, 4 + v2)
+                                   : wly * sh.LE[s][b] * fsum(f, a, m2, v, 4 + v2);
+        bp[(size_t)row * NC + NU + col] = dt_a * val;
+      } else if (i < NCC + NDD) {
+        const int j = i - NCC, row = j / NU, col = j % NU;
+        const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
+        const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
+        const double val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, v2)
+                                   : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, v2);
+        bp[(size_t)(NU + row) * NC + col] = val;
+      } else {
+        const int j = i - NCC - NDD, row = j / NF, col = j % NF;
+        const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
+        const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
+        const double val = (f == f2) ? ((f < 2) ? wlx : wly) * fsum(f, mm, m2, 4 + v, 4 + v2) : 0.0;
+        bp[(size_t)(NU + row) * NC + NU + col] = val;
+      }
+    }
+    return;
+  }
+  // grp 4: A32 = dh/dQ (NF x NQM, rows NU.. of Lm), A23 = M_Q^-1 dl/dUhat (NQM x NF, columns NU.. of Rm)
+  constexpr int N32 = NF * NQM, N23 = NQM * NF;
+  for (int i = tid; i < N32 + N23; i += nt) {
+    if (i < N32) {
+      const int row = i / NQM, col = i % NQM;
+      const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
+      const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
+      const double val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, 8 + c)
+                                 : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, 8 + c);
+      Lm[(size_t)(NU + row) * NQM + col] = val;
+    } else {
+      const int j = i - N32, row = j / NF, col = j % NF;
+      const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
+      const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
+      double nx, ny;
+      fnormal(f, nx, ny);
+      double cx[3], cy[3];
+      lift_coef(c, cx, cy);
+      double cn[3];
+      for (int pp = 0; pp < 3; ++pp) cn[pp] = cx[pp] * nx + cy[pp] * ny;
+      const int x = (f < 2) ? b : a;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double gq = cn[0] * sh.u.f.JLF[f][q][0][v2] + cn[1] * sh.u.f.JLF[f][q][1][v2] +
+                          cn[2] * sh.u.f.JLF[f][q][2][v2];
+        acc += sh.TLL[q][x][m2] * gq;
+      }
+      const double edge = (f < 2) ? wlx * sh.LE[s][a] : wly * sh.LE[s][b];
+      const double minv = 1.0 / (((c == 1) ? 2.0 : 1.0) * sh.NW[a] * sh.NW[b] * jac);
+      Rm[(size_t)row * NR + NU + col] = -minv * edge * acc;
     }
   }
 }
@@ -1406,6 +1712,11 @@ static size_t scr_stride(const imex_ctx* c) {
   const size_t NU = 4 * c->NN, NF = 16 * c->NP, NQM = 5 * c->NN;
   return 2 * (NU + NF) * NQM;
 }
+static size_t rec_stride(const imex_ctx* c) {
+  if (!use_mx(c)) return 0;
+  const size_t NQ = (3 * c->K + 2) / 2, NQV = NQ * NQ;
+  return NQV * 8 * 9 + 4 * NQ * 8 * 13 + NQV * 12 + 4 * NQ * 12;
+}
 
 // GMRES vectors: V (m+1), z, r, b, dx, work
 static size_t gm_vectors(const imex_ctx* c) { return (size_t)c->opt.gmres_restart + 7; }
@@ -1413,7 +1724,8 @@ static size_t gm_vectors(const imex_ctx* c) { return (size_t)c->opt.gmres_restar
 size_t hdg_workspace_bytes(const imex_ctx* c) {
   const size_t n_im = c->n_im, NU = 4 * c->NN, NF = 16 * c->NP, NFF = 4 * c->NP, n = (size_t)c->n_hf * NFF;
   const size_t NB = 5 * NFF, NH = 2 * NFF, nsr = (size_t)std::max(c->n_superrows, 1);
-  return 8 * (n_im * (blk_stride(c) + scr_stride(c) + NU * NU + NU * (NF + 1)) + nsr * (NB * NB + 2 * NH * NB + NB) +
+  return 8 * (n_im * (blk_stride(c) + scr_stride(c) + rec_stride(c) + NU * NU + NU * (NF + 1)) +
+              nsr * (NB * NB + 2 * NH * NB + NB) +
               n * gm_vectors(c) + GmState::SIZE + 2 * (n_im + 1024));
 }
 
@@ -1424,6 +1736,7 @@ imex_status hdg_alloc(imex_ctx* c) {
   const size_t n = (size_t)c->n_hf * NFF;
   hipError_t e = hipMalloc(&w.blk, 8 * n_im * blk_stride(c));
   if (e == hipSuccess && scr_stride(c)) e = hipMalloc(&w.scr, 8 * n_im * scr_stride(c));
+  if (e == hipSuccess && rec_stride(c)) e = hipMalloc(&w.rec, 8 * n_im * rec_stride(c));
   if (e == hipSuccess) e = hipMalloc(&w.Kinv, 8 * n_im * NU * NU);
   if (e == hipSuccess) e = hipMalloc(&w.X, 8 * n_im * NU * (NF + 1));
   const size_t nsr = (size_t)std::max(c->n_superrows, 1), NB = 5 * NFF, NH = 2 * NFF;
@@ -1451,11 +1764,18 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
   HDG_DISPATCH(c->K, {
     const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
     if (mx) {
+      // point values, residual rows and point-wise Jacobians; then the block contraction
+      static_assert(MxRec<KK>::SIZE > 0, "");
       const size_t shm = sizeof(AsmShared<KK, true>);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true>), dim3(c->n_im), dim3(256), shm, c->stream, c->dmesh(),
-                         c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, w.Q, Rh);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true>), dim3(c->n_im), dim3(256), shm, c->stream,
+                         c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, w.Q, Rh, w.rec);
+      if (jacobian) {
+        const int nblk = 40 * ((c->n_im + 7) / 8);
+        hipLaunchKernelGGL(hdg_mx_contract_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
+                           dt_a, w.rec, w.blk, w.scr);
+      }
       c->timer_end(ta);
       if (jacobian) {
         // eliminate the mixed block: [[K C],[D E]] -= [A12; A32] M_Q^-1 [A21 A23]
@@ -1472,7 +1792,7 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
       hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       hipLaunchKernelGGL((hdg_assemble_kernel<KK, false>), dim3(c->n_im), dim3(256), shm, c->stream, c->dmesh(),
-                         c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, nullptr, Rh);
+                         c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, nullptr, Rh, nullptr);
       c->timer_end(ta);
     }
   });
