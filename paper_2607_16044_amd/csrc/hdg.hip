@@ -1165,16 +1165,63 @@ static hipError_t gemm_f64(hipStream_t st, int batch, int M, int N, int K, doubl
 // ---------------------------------------------------------------------------
 // condensation step 1: K^-1 by in-place Gauss-Jordan with partial pivoting in LDS
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inversion held in registers.  The N x N matrix is spread over
+// the workgroup in RT x CT tiles: thread t < (N/RT)(N/CT) owns rows
+// (t / (N/CT)) RT .. +RT-1 and columns (t % (N/CT)) CT .. +CT-1.  Partial
+// pivoting without row exchanges: step k takes the unused row with the largest
+// |A[r][k]| (lowest index on ties), found by every wave on its own from the
+// pivot column in LDS; only that column and the pivot row pass through LDS
+// (double-buffered, two barriers per step).  On return the tiles hold B with
+// A^-1[pos[i]][rp[c]] = B[i][c], where rp[k] is the pivot row of step k and
+// pos its inverse (both in LDS).  N <= 128.
+// ---------------------------------------------------------------------------
+template <int N> struct GJTile;
+template <> struct GJTile<16> { static constexpr int RT = 2, CT = 2; };
+template <> struct GJTile<36> { static constexpr int RT = 3, CT = 3; };
+template <> struct GJTile<40> { static constexpr int RT = 5, CT = 2; };
+template <> struct GJTile<60> { static constexpr int RT = 6, CT = 3; };
+template <> struct GJTile<64> { static constexpr int RT = 8, CT = 2; };
+template <> struct GJTile<80> { static constexpr int RT = 10, CT = 4; };
+template <> struct GJTile<100> { static constexpr int RT = 10, CT = 4; };
+
+template <int N> struct GJShared {
+  double col[2][N];
+  double row[2][N];
+  int rp[N];
+  int pos[N];
+};
+
 template <int N>
-__device__ void lds_invert(double* A, int* piv, double* fcol, int tid, int nt) {
-  __shared__ int pr;
-  for (int k = 0; k < N; ++k) {
-    if (tid < 64) {                 // pivot search by the first wave
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + tid; i < N; i += 64) {
-        const double v = fabs(A[i * N + k]);
-        if (v > best) { best = v; bi = i; }
+struct GJ {
+  static constexpr int RT = GJTile<N>::RT, CT = GJTile<N>::CT, NCG = N / CT, NTH = (N / RT) * NCG;
+  static_assert(N % RT == 0 && N % CT == 0 && NTH <= 256 && N <= 128, "tile shape");
+  __device__ static bool owns(int tid) { return tid < NTH; }
+  __device__ static int row0(int tid) { return (tid / NCG) * RT; }
+  __device__ static int col0(int tid) { return (tid % NCG) * CT; }
+
+  __device__ static void invert(double (&A)[RT][CT], GJShared<N>& sh, int tid) {
+    const bool own = owns(tid);
+    const int r0 = row0(tid), c0 = col0(tid);
+    const int lane = tid & 63;
+    bool used0 = lane >= N, used1 = lane + 64 >= N;
+    for (int k = 0; k < N; ++k) {
+      double* ck = sh.col[k & 1];
+      double* rk = sh.row[k & 1];
+      if (own) {
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          if (c0 + j == k) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) ck[r0 + i] = A[i][j];
+          }
+      }
+      __syncthreads();
+      double best = used0 ? -1.0 : fabs(ck[lane]);
+      int bi = lane;
+      if (!used1) {
+        const double v1 = fabs(ck[lane + 64]);
+        if (v1 > best) { best = v1; bi = lane + 64; }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -1182,56 +1229,66 @@ __device__ void lds_invert(double* A, int* piv, double* fcol, int tid, int nt) {
         const int oi = __shfl_xor(bi, off);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (tid == 0) { pr = bi; piv[k] = bi; }
-    }
-    __syncthreads();
-    const int p = pr;
-    if (p != k)
-      for (int c = tid; c < N; c += nt) {
-        const double t = A[k * N + c];
-        A[k * N + c] = A[p * N + c];
-        A[p * N + c] = t;
+      const int r = bi;
+      if (r == lane) used0 = true;
+      if (r == lane + 64) used1 = true;
+      if (tid == 0) { sh.rp[k] = r; sh.pos[r] = k; }
+      if (own && r >= r0 && r < r0 + RT) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+          if (r0 + i == r) {
+#pragma unroll
+            for (int j = 0; j < CT; ++j) rk[c0 + j] = A[i][j];
+          }
       }
-    __syncthreads();
-    const double inv = 1.0 / A[k * N + k];
-    for (int i = tid; i < N; i += nt) fcol[i] = A[i * N + k];
-    __syncthreads();
-    for (int c = tid; c < N; c += nt) A[k * N + c] = (c == k) ? inv : A[k * N + c] * inv;
-    __syncthreads();
-    for (int idx = tid; idx < N * N; idx += nt) {
-      const int i = idx / N, c = idx - i * N;
-      if (i == k) continue;
-      const double base = (c == k) ? 0.0 : A[idx];
-      A[idx] = base - fcol[i] * A[k * N + c];
+      __syncthreads();
+      const double inv = 1.0 / ck[r];
+      if (own) {
+        double rn[CT];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) rn[j] = rk[c0 + j] * inv;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const bool pr = (r0 + i == r);
+          const double f = ck[r0 + i];
+#pragma unroll
+          for (int j = 0; j < CT; ++j) {
+            const bool pc = (c0 + j == k);
+            const double upd = pc ? -f * inv : A[i][j] - f * rn[j];
+            const double pv = pc ? inv : rn[j];
+            A[i][j] = pr ? pv : upd;
+          }
+        }
+      }
     }
     __syncthreads();
   }
-  for (int k = N - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k)
-      for (int i = tid; i < N; i += nt) {
-        const double t = A[i * N + k];
-        A[i * N + k] = A[i * N + p];
-        A[i * N + p] = t;
-      }
-    __syncthreads();
-  }
-}
+};
 
 template <int K>
 __global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, const double* __restrict__ blk,
                                                          double* __restrict__ Kinv) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NC = NU + NF + 1;
-  extern __shared__ double sm[];
-  __shared__ int piv[NU];
-  __shared__ double fcol[NU];
-  const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  using G = GJ<NU>;
+  __shared__ GJShared<NU> sh;
+  const int p = blockIdx.x, tid = threadIdx.x;
   const double* bp = blk + (size_t)p * blk_stride;
-  for (int i = tid; i < NU * NU; i += nt) sm[i] = bp[(size_t)(i / NU) * NC + i % NU];
-  __syncthreads();
-  lds_invert<NU>(sm, piv, fcol, tid, nt);
+  const int r0 = G::row0(tid), c0 = G::col0(tid);
+  const bool own = G::owns(tid);
+  double A[G::RT][G::CT];
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+    for (int j = 0; j < G::CT; ++j) A[i][j] = own ? bp[(size_t)(r0 + i) * NC + c0 + j] : 0.0;
+  G::invert(A, sh, tid);
+  if (!own) return;
   double* Kp = Kinv + (size_t)p * NU * NU;
-  for (int i = tid; i < NU * NU; i += nt) Kp[i] = sm[i];
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i) {
+    const int row = sh.pos[r0 + i];
+#pragma unroll
+    for (int j = 0; j < G::CT; ++j) Kp[(size_t)row * NU + sh.rp[c0 + j]] = A[i][j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1283,72 +1340,124 @@ __device__ __forceinline__ double s_entry(const DeviceHDG& h, const double* __re
   return acc;
 }
 
+// Factorisation of the restricted additive Schwarz windows: each window is a
+// chain of super-rows (5 facet slots, NB unknowns) coupled block-tridiagonally
+// through the horizontal slots (first NH unknowns).  Forward block elimination
+// with explicit inverses: D_r = A_r - B_r D_{r-1}^-1 C_{r-1} on the NH x NH
+// corner, G_r = B_r D_{r-1}^-1.  The diagonal block lives in register tiles
+// (GJ<NB>), the previous inverse, B_r / G_r and C_{r-1} in LDS.  Stored for the
+// apply: D_r^-1, G_r and C_r, each transposed for coalesced matrix-vector products.
 template <int K>
 __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const double* __restrict__ S, size_t bs,
                                                          double* __restrict__ Wd, double* __restrict__ Wg,
                                                          double* __restrict__ Wc) {
   constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
+  using G = GJ<NB>;
   extern __shared__ double smem[];
-  double* A = smem;                    // NB x NB
-  double* Bm = A + NB * NB;            // NH x NB
-  __shared__ int piv[NB];
-  __shared__ double fcol[NB];
+  double* Ds = smem;                   // NB x NB: D_{r-1}^-1 (row-major)
+  double* Bs = Ds + NB * NB;           // NH x NB: B_r, then G_r
+  double* Cs = Bs + NH * NB;           // NB x NH: C_{r-1}
+  __shared__ GJShared<NB> gsh;
   __shared__ int fs[5], fp[5];
   const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  const bool own = G::owns(tid);
+  const int r0 = G::row0(tid), c0 = G::col0(tid);
+  // G_r = B_r D^-1 is NH x NB: 4 x 4 register tiles over (NH/4) x (NB/4) threads
+  constexpr int GR = 4, GC = 4, NGC = NB / GC, NGT = (NH / GR) * NGC;
+  static_assert(NH % GR == 0 && NB % GC == 0 && NGT <= 256, "G tile shape");
   for (int g = g0; g < g1; ++g) {
     if (tid < 5) {
       fs[tid] = h.win_slot[5 * g + tid];
       fp[tid] = (g > g0) ? h.win_slot[5 * (g - 1) + tid] : -1;
     }
     __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += nt) {
-      const int r = idx / NB, c = idx % NB;
-      const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
-      double v;
-      if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? 1.0 : 0.0;
-      else v = s_entry<K>(h, S, bs, fs[a], fs[b], i, j);
-      A[idx] = v;
-    }
+    double A[G::RT][G::CT];
+#pragma unroll
+    for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+      for (int j = 0; j < G::CT; ++j) {
+        const int r = r0 + i, c = c0 + j;
+        const int a = r / NFF, b = c / NFF;
+        double v = 0.0;
+        if (own) {
+          if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? 1.0 : 0.0;
+          else v = s_entry<K>(h, S, bs, fs[a], fs[b], r % NFF, c % NFF);
+        }
+        A[i][j] = v;
+      }
     if (g > g0) {
-      // B_r: facet rows of the horizontal slots of r, columns of all slots of r-1
       for (int idx = tid; idx < NH * NB; idx += nt) {
         const int r = idx / NB, c = idx % NB;
         const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
-        Bm[idx] = (fs[a] >= 0 && fp[b] >= 0) ? s_entry<K>(h, S, bs, fs[a], fp[b], i, j) : 0.0;
+        Bs[idx] = (fs[a] >= 0 && fp[b] >= 0) ? s_entry<K>(h, S, bs, fs[a], fp[b], i, j) : 0.0;
       }
-      // C_{r-1}: rows of all slots of r-1, columns of the horizontal slots of r (stored transposed)
       double* Cg = Wc + (size_t)(g - 1) * NB * NH;
       for (int idx = tid; idx < NB * NH; idx += nt) {
         const int r = idx / NH, c = idx % NH;
         const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
-        Cg[(size_t)c * NB + r] = (fp[a] >= 0 && fs[b] >= 0) ? s_entry<K>(h, S, bs, fp[a], fs[b], i, j) : 0.0;
+        const double v = (fp[a] >= 0 && fs[b] >= 0) ? s_entry<K>(h, S, bs, fp[a], fs[b], i, j) : 0.0;
+        Cs[idx] = v;
+        Cg[(size_t)c * NB + r] = v;
       }
       __syncthreads();
-      // G_r = B_r Dinv_{r-1}  (Dinv stored transposed: Dt[c*NB + k] = Dinv[k][c])
-      const double* Dt = Wd + (size_t)(g - 1) * NB * NB;
-      double* Gg = Wg + (size_t)g * NH * NB;
-      for (int idx = tid; idx < NH * NB; idx += nt) {
-        const int r = idx / NB, c = idx % NB;
-        double acc = 0.0;
-        for (int k = 0; k < NB; ++k) acc += Bm[r * NB + k] * Dt[(size_t)c * NB + k];
-        Gg[(size_t)c * NH + r] = acc;                   // transposed
+      // G_r = B_r D_{r-1}^-1
+      double gt[GR][GC];
+#pragma unroll
+      for (int i = 0; i < GR; ++i)
+#pragma unroll
+        for (int j = 0; j < GC; ++j) gt[i][j] = 0.0;
+      const int gr0 = (tid / NGC) * GR, gc0 = (tid % NGC) * GC;
+      if (tid < NGT) {
+        for (int k = 0; k < NB; ++k) {
+          double bv[GR], dv[GC];
+#pragma unroll
+          for (int i = 0; i < GR; ++i) bv[i] = Bs[(gr0 + i) * NB + k];
+#pragma unroll
+          for (int j = 0; j < GC; ++j) dv[j] = Ds[k * NB + gc0 + j];
+#pragma unroll
+          for (int i = 0; i < GR; ++i)
+#pragma unroll
+            for (int j = 0; j < GC; ++j) gt[i][j] += bv[i] * dv[j];
+        }
+      }
+      __syncthreads();
+      if (tid < NGT) {
+        double* Gg = Wg + (size_t)g * NH * NB;
+#pragma unroll
+        for (int i = 0; i < GR; ++i)
+#pragma unroll
+          for (int j = 0; j < GC; ++j) {
+            Bs[(gr0 + i) * NB + gc0 + j] = gt[i][j];
+            Gg[(size_t)(gc0 + j) * NH + gr0 + i] = gt[i][j];
+          }
       }
       __syncthreads();
       // A[H, H] -= G_r C_{r-1}
-      for (int idx = tid; idx < NH * NH; idx += nt) {
-        const int r = idx / NH, c = idx % NH;
-        double acc = 0.0;
-        for (int k = 0; k < NB; ++k) acc += Gg[(size_t)k * NH + r] * Cg[(size_t)c * NB + k];
-        A[r * NB + c] -= acc;
+      if (own && r0 < NH && c0 < NH) {
+        for (int k = 0; k < NB; ++k) {
+#pragma unroll
+          for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+            for (int j = 0; j < G::CT; ++j)
+              if (r0 + i < NH && c0 + j < NH) A[i][j] -= Bs[(r0 + i) * NB + k] * Cs[k * NH + c0 + j];
+        }
       }
     }
-    __syncthreads();
-    lds_invert<NB>(A, piv, fcol, tid, nt);
+    G::invert(A, gsh, tid);
+    // D_r^-1: transposed to global, row-major (un-permuted) to LDS for the next super-row
     double* Dg = Wd + (size_t)g * NB * NB;
-    for (int idx = tid; idx < NB * NB; idx += nt) {
-      const int r = idx / NB, c = idx % NB;
-      Dg[(size_t)c * NB + r] = A[idx];
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < G::RT; ++i) {
+        const int row = gsh.pos[r0 + i];
+#pragma unroll
+        for (int j = 0; j < G::CT; ++j) {
+          const int col = gsh.rp[c0 + j];
+          Dg[(size_t)col * NB + row] = A[i][j];
+          Ds[row * NB + col] = A[i][j];
+        }
+      }
     }
     __syncthreads();
   }
@@ -1806,10 +1915,7 @@ static hipError_t launch_condense(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
     constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NC = NU + NF + 1;
-    const size_t shm = sizeof(double) * (size_t)NU * NU;
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_invert_kernel<KK>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(hdg_invert_kernel<KK>, dim3(c->n_im), dim3(256), shm, c->stream, blk_stride(c), w.blk, w.Kinv);
+    hipLaunchKernelGGL(hdg_invert_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), w.blk, w.Kinv);
     const long long bs = (long long)blk_stride(c);
     hipError_t e = gemm_f64(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, w.Kinv, NU, (long long)NU * NU,
                             w.blk + NU, NC, bs, w.X, NF + 1, (long long)NU * (NF + 1));
@@ -1833,7 +1939,7 @@ static hipError_t launch_ras_factor(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
     constexpr int NFF = 4 * (KK + 1), NB = 5 * NFF, NH = 2 * NFF;
-    const size_t shm = sizeof(double) * ((size_t)NB * NB + (size_t)NH * NB);
+    const size_t shm = sizeof(double) * ((size_t)NB * NB + 2 * (size_t)NH * NB);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(ras_factor_kernel<KK>, dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(), w.blk,
