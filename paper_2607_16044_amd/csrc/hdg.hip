@@ -1093,15 +1093,21 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
 // ---------------------------------------------------------------------------
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, double alpha, int beta_one,
+__global__ void __launch_bounds__(256) gemm_f64_kernel(int batch, int M, int N, int Kd, double alpha, int beta_one,
                                                        const double* __restrict__ A, int lda, long long sA,
                                                        const double* __restrict__ B, int ldb, long long sB,
                                                        double* __restrict__ C, int ldc, long long sC) {
-  __shared__ double sa[64][17];
-  __shared__ double sb[16][65];
+  constexpr int KB = 32;                      // k-block staged in LDS
+  __shared__ double sa[64][KB + 1];
+  __shared__ double sb[KB][65];
+  // XCD-aware numbering: the output tiles of one batch entry share an XCD (and its L2)
+  const int tn = (N + 63) / 64, T = ((M + 63) / 64) * tn;
+  const int L = blockIdx.x, xcd = L & 7, rr = L >> 3;
+  const int t = rr % T;
+  const long long bz = 8LL * (rr / T) + xcd;
+  if (bz >= batch) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const long long bz = blockIdx.z;
+  const int m0 = (t / tn) * 64, n0 = (t % tn) * 64;
   const double* Ab = A + bz * sA;
   const double* Bb = B + bz * sB;
   double* Cb = C + bz * sC;
@@ -1112,20 +1118,32 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, dou
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = mf_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < Kd; k0 += 16) {
-    for (int idx = tid; idx < 64 * 16; idx += 256) {
-      const int r = idx >> 4, kk = idx & 15;
+  constexpr int NL = 64 * KB / 256;           // elements of each operand block per thread
+  double ra[NL], rb[NL];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int idx = tid + 256 * u;
+      const int r = idx / KB, kk = idx % KB;
       const int gm = m0 + r, gk = k0 + kk;
-      sa[r][kk] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : 0.0;
+      ra[u] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : 0.0;
+      const int kb = idx / 64, cc = idx % 64;
+      const int gk2 = k0 + kb, gn = n0 + cc;
+      rb[u] = (gk2 < Kd && gn < N) ? Bb[(size_t)gk2 * ldb + gn] : 0.0;
     }
-    for (int idx = tid; idx < 16 * 64; idx += 256) {
-      const int kk = idx >> 6, cc = idx & 63;
-      const int gk = k0 + kk, gn = n0 + cc;
-      sb[kk][cc] = (gk < Kd && gn < N) ? Bb[(size_t)gk * ldb + gn] : 0.0;
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < Kd; k0 += KB) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int idx = tid + 256 * u;
+      sa[idx / KB][idx % KB] = ra[u];
+      sb[idx / 64][idx % 64] = rb[u];
     }
     __syncthreads();
+    if (k0 + KB < Kd) fetch(k0 + KB);
 #pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) {
+    for (int k4 = 0; k4 < KB / 4; ++k4) {
       const int kk = 4 * k4 + lk;
       const double a0 = sa[32 * wr + li][kk], a1 = sa[32 * wr + 16 + li][kk];
       const double b0 = sb[kk][32 * wc + li], b1 = sb[kk][32 * wc + 16 + li];
@@ -1156,9 +1174,10 @@ static hipError_t gemm_f64(hipStream_t st, int batch, int M, int N, int K, doubl
                            const double* A, int lda, long long sA, const double* B, int ldb, long long sB, double* C,
                            int ldc, long long sC) {
   if (batch == 0 || M == 0 || N == 0) return hipSuccess;
-  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, ldb,
-                     sB, C, ldc, sC);
+  const long long T = (long long)((M + 63) / 64) * ((N + 63) / 64);
+  const long long nblk = 8LL * ((batch + 7) / 8) * T;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0,
+                     A, lda, sA, B, ldb, sB, C, ldc, sC);
   return hipGetLastError();
 }
 
@@ -1244,20 +1263,32 @@ struct GJ {
       __syncthreads();
       const double inv = 1.0 / ck[r];
       if (own) {
-        double rn[CT];
+        double rn[CT], f[RT];
 #pragma unroll
         for (int j = 0; j < CT; ++j) rn[j] = rk[c0 + j] * inv;
 #pragma unroll
-        for (int i = 0; i < RT; ++i) {
-          const bool pr = (r0 + i == r);
-          const double f = ck[r0 + i];
+        for (int i = 0; i < RT; ++i) f[i] = ck[r0 + i];
+        // rank-1 update everywhere, then the pivot column (-f_i / p) and the
+        // normalised pivot row (with 1 / p in the pivot column) overwritten
 #pragma unroll
-          for (int j = 0; j < CT; ++j) {
-            const bool pc = (c0 + j == k);
-            const double upd = pc ? -f * inv : A[i][j] - f * rn[j];
-            const double pv = pc ? inv : rn[j];
-            A[i][j] = pr ? pv : upd;
-          }
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j) A[i][j] = fma(-f[i], rn[j], A[i][j]);
+        if (k >= c0 && k < c0 + CT) {
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+            if (c0 + j == k) {
+#pragma unroll
+              for (int i = 0; i < RT; ++i) A[i][j] = -f[i] * inv;
+            }
+        }
+        if (r >= r0 && r < r0 + RT) {
+#pragma unroll
+          for (int i = 0; i < RT; ++i)
+            if (r0 + i == r) {
+#pragma unroll
+              for (int j = 0; j < CT; ++j) A[i][j] = (c0 + j == k) ? inv : rn[j];
+            }
         }
       }
     }
@@ -1322,22 +1353,31 @@ __global__ void facet_rhs_kernel(DeviceHDG h, size_t blk_stride, const double* _
 // ---------------------------------------------------------------------------
 // S[F, G] for HDG facets F, G (NFF x NFF block entry (i, j)): sum over the
 // implicit elements having both as faces of their condensed blocks S_T.
+// Offsets (into the condensed element systems) of the S_T blocks that couple
+// facet F (rows) to facet G (columns): for each side of F the element's facet
+// block of face G (up to two faces, for one-element periodic strips); -1 if none.
 template <int K>
-__device__ __forceinline__ double s_entry(const DeviceHDG& h, const double* __restrict__ blk, size_t bs, int F,
-                                          int G, int i, int j) {
+__device__ void s_block_offsets(const DeviceHDG& h, size_t bs, int F, int G, long long off[4]) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
-  double acc = 0.0;
-#pragma unroll
+  off[0] = off[1] = off[2] = off[3] = -1;
+  if (F < 0 || G < 0) return;
   for (int s = 0; s < 2; ++s) {
     const int pe = h.hf_side[2 * F + s];
     if (pe < 0) continue;
     const int lf = h.hf_face[2 * F + s];
-#pragma unroll
-    for (int lg = 0; lg < 4; ++lg)
+    int nm = 0;
+    for (int lg = 0; lg < 4 && nm < 2; ++lg)
       if (h.efacet[4 * pe + lg] == G)
-        acc += blk[(size_t)pe * bs + (size_t)(NU + lf * NFF + i) * NC + NU + lg * NFF + j];
+        off[2 * s + nm++] = (long long)pe * (long long)bs + (long long)(NU + lf * NFF) * NC + NU + lg * NFF;
   }
-  return acc;
+}
+
+__device__ __forceinline__ double s_gather(const double* __restrict__ S, const long long* off, int i, int j, int ld) {
+  double v = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (off[t] >= 0) v += S[off[t] + (long long)i * ld + j];
+  return v;
 }
 
 // Factorisation of the restricted additive Schwarz windows: each window is a
@@ -1351,14 +1391,17 @@ template <int K>
 __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const double* __restrict__ S, size_t bs,
                                                          double* __restrict__ Wd, double* __restrict__ Wg,
                                                          double* __restrict__ Wc) {
-  constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
+  constexpr int NC = NU + NF + 1;
   using G = GJ<NB>;
   extern __shared__ double smem[];
   double* Ds = smem;                   // NB x NB: D_{r-1}^-1 (row-major)
   double* Bs = Ds + NB * NB;           // NH x NB: B_r, then G_r
   double* Cs = Bs + NH * NB;           // NB x NH: C_{r-1}
+  double* Us = Cs + NB * NH;           // NH x NH: G_r C_{r-1}
   __shared__ GJShared<NB> gsh;
   __shared__ int fs[5], fp[5];
+  __shared__ long long oA[5][5][4], oB[2][5][4], oC[5][2][4];
   const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
   const bool own = G::owns(tid);
@@ -1366,11 +1409,18 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
   // G_r = B_r D^-1 is NH x NB: 4 x 4 register tiles over (NH/4) x (NB/4) threads
   constexpr int GR = 4, GC = 4, NGC = NB / GC, NGT = (NH / GR) * NGC;
   static_assert(NH % GR == 0 && NB % GC == 0 && NGT <= 256, "G tile shape");
+  // G_r C_{r-1} is NH x NH: 2 x 4 tiles
+  constexpr int UR = 2, UC = 4, NUC = NH / UC, NUT = (NH / UR) * NUC;
+  static_assert(NH % UR == 0 && NH % UC == 0 && NUT <= 256, "corner tile shape");
   for (int g = g0; g < g1; ++g) {
     if (tid < 5) {
       fs[tid] = h.win_slot[5 * g + tid];
       fp[tid] = (g > g0) ? h.win_slot[5 * (g - 1) + tid] : -1;
     }
+    __syncthreads();
+    if (tid < 25) s_block_offsets<K>(h, bs, fs[tid / 5], fs[tid % 5], oA[tid / 5][tid % 5]);
+    else if (tid < 35) s_block_offsets<K>(h, bs, fs[(tid - 25) / 5], fp[(tid - 25) % 5], oB[(tid - 25) / 5][(tid - 25) % 5]);
+    else if (tid < 45) s_block_offsets<K>(h, bs, fp[(tid - 35) / 2], fs[(tid - 35) % 2], oC[(tid - 35) / 2][(tid - 35) % 2]);
     __syncthreads();
     double A[G::RT][G::CT];
 #pragma unroll
@@ -1382,23 +1432,21 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
         double v = 0.0;
         if (own) {
           if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? 1.0 : 0.0;
-          else v = s_entry<K>(h, S, bs, fs[a], fs[b], r % NFF, c % NFF);
+          else v = s_gather(S, oA[a][b], r % NFF, c % NFF, NC);
         }
         A[i][j] = v;
       }
     if (g > g0) {
       for (int idx = tid; idx < NH * NB; idx += nt) {
         const int r = idx / NB, c = idx % NB;
-        const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
-        Bs[idx] = (fs[a] >= 0 && fp[b] >= 0) ? s_entry<K>(h, S, bs, fs[a], fp[b], i, j) : 0.0;
+        Bs[idx] = s_gather(S, oB[r / NFF][c / NFF], r % NFF, c % NFF, NC);
       }
       double* Cg = Wc + (size_t)(g - 1) * NB * NH;
       for (int idx = tid; idx < NB * NH; idx += nt) {
-        const int r = idx / NH, c = idx % NH;
-        const int a = r / NFF, i = r % NFF, b = c / NFF, j = c % NFF;
-        const double v = (fp[a] >= 0 && fs[b] >= 0) ? s_entry<K>(h, S, bs, fp[a], fs[b], i, j) : 0.0;
-        Cs[idx] = v;
-        Cg[(size_t)c * NB + r] = v;
+        const int c = idx / NB, r = idx % NB;          // coalesced transposed store
+        const double v = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+        Cs[r * NH + c] = v;
+        Cg[idx] = v;
       }
       __syncthreads();
       // G_r = B_r D_{r-1}^-1
@@ -1433,15 +1481,37 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
           }
       }
       __syncthreads();
-      // A[H, H] -= G_r C_{r-1}
-      if (own && r0 < NH && c0 < NH) {
+      // U = G_r C_{r-1} (NH x NH), then A[H, H] -= U by the tile owners
+      if (tid < NUT) {
+        const int ur0 = (tid / NUC) * UR, uc0 = (tid % NUC) * UC;
+        double ut[UR][UC];
+#pragma unroll
+        for (int i = 0; i < UR; ++i)
+#pragma unroll
+          for (int j = 0; j < UC; ++j) ut[i][j] = 0.0;
         for (int k = 0; k < NB; ++k) {
+          double gv[UR], cv[UC];
 #pragma unroll
-          for (int i = 0; i < G::RT; ++i)
+          for (int i = 0; i < UR; ++i) gv[i] = Bs[(ur0 + i) * NB + k];
 #pragma unroll
-            for (int j = 0; j < G::CT; ++j)
-              if (r0 + i < NH && c0 + j < NH) A[i][j] -= Bs[(r0 + i) * NB + k] * Cs[k * NH + c0 + j];
+          for (int j = 0; j < UC; ++j) cv[j] = Cs[k * NH + uc0 + j];
+#pragma unroll
+          for (int i = 0; i < UR; ++i)
+#pragma unroll
+            for (int j = 0; j < UC; ++j) ut[i][j] += gv[i] * cv[j];
         }
+#pragma unroll
+        for (int i = 0; i < UR; ++i)
+#pragma unroll
+          for (int j = 0; j < UC; ++j) Us[(ur0 + i) * NH + uc0 + j] = ut[i][j];
+      }
+      __syncthreads();
+      if (own && r0 < NH && c0 < NH) {
+#pragma unroll
+        for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+          for (int j = 0; j < G::CT; ++j)
+            if (r0 + i < NH && c0 + j < NH) A[i][j] -= Us[(r0 + i) * NH + c0 + j];
       }
     }
     G::invert(A, gsh, tid);
@@ -1939,7 +2009,7 @@ static hipError_t launch_ras_factor(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, {
     constexpr int NFF = 4 * (KK + 1), NB = 5 * NFF, NH = 2 * NFF;
-    const size_t shm = sizeof(double) * ((size_t)NB * NB + 2 * (size_t)NH * NB);
+    const size_t shm = sizeof(double) * ((size_t)NB * NB + 2 * (size_t)NH * NB + (size_t)NH * NH);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(ras_factor_kernel<KK>, dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(), w.blk,
