@@ -117,11 +117,11 @@ void free_regions(imex_ctx* c) {
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.blk, &w.scr, &w.rec, &w.Kinv, &w.X, &w.Wd, &w.Wg, &w.Wc, &w.Wy, &w.gH, &w.gm, &w.red}) {
+  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.gH, &w.gm, &w.red}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
-  for (float** p : {&w.X32, &w.S32}) {
+  for (void** p : {&w.blk, &w.scr, &w.Kinv, &w.X, &w.Wd, &w.Wg, &w.Wc}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

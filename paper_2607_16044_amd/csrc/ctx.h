@@ -46,17 +46,18 @@ struct Workspace {
   double* Un = nullptr;         // copy of U at t_n
   double* Y = nullptr;          // stage state
   double* rhs = nullptr;        // implicit stage right-hand side
-  // implicit Newton
-  double* blk = nullptr;        // per implicit element: augmented system [[K C f],[D E h]] (becomes [[. . .],[D S h-DK^-1f]])
-  double* scr = nullptr;        // per implicit element: HDG-MX mixed blocks [A12; A32] and M_Q^-1 [A21 A23]
+  // implicit Newton.  The linear-algebra buffers hold doubles (IMEX_FP64) or
+  // floats (IMEX_FP32_REFINE); the Newton residual column of blk is stored in
+  // the same type, the state, residual evaluation and Krylov vectors stay FP64.
+  void* blk = nullptr;          // per implicit element: augmented system [[K C f],[D E h]] (becomes [[. . .],[D S h-DK^-1f]])
+  void* scr = nullptr;          // per implicit element: HDG-MX mixed blocks [A12; A32] and M_Q^-1 [A21 A23]
   double* rec = nullptr;        // per implicit element: HDG-MX point-wise Jacobians (assembly -> contraction)
-  double* Kinv = nullptr;       // per implicit element: K^-1 [NU][NU]
-  double* X = nullptr;          // per implicit element: K^-1 [C f]  [NU][NF+1]
-  float* X32 = nullptr;         // mixed-precision copies
-  float* S32 = nullptr;
-  double* Wd = nullptr;         // per window super-row: inverse of the eliminated diagonal block
-  double* Wg = nullptr;         // per window super-row: B_r D_{r-1}^-1 (facet rows x previous super-row)
-  double* Wc = nullptr;         // per window super-row: coupling to the next super-row
+  double* hres = nullptr;       // per implicit element: its share of the facet residuals h (FP64) [NF]
+  void* Kinv = nullptr;         // per implicit element: K^-1 [NU][NU]
+  void* X = nullptr;            // per implicit element: K^-1 [C f]  [NU][NF+1]
+  void* Wd = nullptr;           // per window super-row: inverse of the eliminated diagonal block
+  void* Wg = nullptr;           // per window super-row: B_r D_{r-1}^-1 (facet rows x previous super-row)
+  void* Wc = nullptr;           // per window super-row: coupling to the next super-row
   double* Wy = nullptr;         // per window super-row: forward-sweep vector
   double* gH = nullptr;         // GMRES Hessenberg, rotations, g, residual history, scalars (device)
   double* gm = nullptr;         // GMRES basis and vectors

@@ -244,13 +244,14 @@ template <int K> struct MxRec {
 // DUMP = false: residual rows and every Jacobian block contracted here.
 // DUMP = true (HDG-MX): residual rows here, the point-wise Jacobians go to rec
 // for hdg_mx_contract_kernel.
-template <int K, bool MX, bool DUMP = false>
+template <int K, bool MX, bool DUMP, class T>
 __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ Uhat,
-                                                           const double* __restrict__ rhs, double* __restrict__ blk,
-                                                           double* __restrict__ scr, double* __restrict__ Qout,
-                                                           double* __restrict__ Rh, double* __restrict__ rec) {
+                                                           const double* __restrict__ rhs, T* __restrict__ blk,
+                                                           T* __restrict__ scr, double* __restrict__ Qout,
+                                                           double* __restrict__ Rh, double* __restrict__ rec,
+                                                           double* __restrict__ hres) {
   using S = HS<K, MX>;
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
@@ -573,7 +574,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   __syncthreads();
   // ---- residual rows ---------------------------------------------------------
   constexpr int NC = S::NC;
-  double* bp = blk + (size_t)p * S::BLK;       // row-major NR x NC: [[K C f],[D E h]]
+  T* bp = blk + (size_t)p * S::BLK;       // row-major NR x NC: [[K C f],[D E h]]
   for (int r = tid; r < NU + NF; r += nt) {
     if (r < NU) {
       const int v = r / NN, n = r % NN, a = n % NP, b = n / NP;
@@ -598,14 +599,17 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       const double mass = tb.NW[a] * tb.NW[b] * jac;
       const size_t gi = (size_t)e * NU + r;
       if (Rh) Rh[gi] = acc;
-      bp[(size_t)r * NC + NC - 1] = mass * sh.U[r] + prm.dt_a * acc - (rhs ? rhs[gi] : 0.0);
+      bp[(size_t)r * NC + NC - 1] = static_cast<T>(mass * sh.U[r] + prm.dt_a * acc - (rhs ? rhs[gi] : 0.0));
     } else {
       const int rr = r - NU, f = rr / NFF, v = (rr % NFF) / NP, mm = rr % NP;
       const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
       constexpr int TO = MX ? 4 : 12;
       double acc = 0.0;
       for (int q = 0; q < NQ; ++q) acc += tb.W[q] * wl * tb.L[q][mm] * sh.VF[f][q][TO + v];
-      bp[(size_t)(NU + rr) * NC + NC - 1] = acc;
+      // the element's share of its facet residuals: large where the two sides cancel,
+      // so it is kept in FP64 (hres) and the augmented column starts from 0
+      bp[(size_t)(NU + rr) * NC + NC - 1] = T(0);
+      hres[(size_t)p * NF + rr] = acc;
     }
   }
   if (!prm.jacobian) return;
@@ -669,7 +673,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         acc += w * ph * d;
       }
     }
-    bp[(size_t)row * NC + col] = prm.dt_a * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0);
+    bp[(size_t)row * NC + col] = static_cast<T>(prm.dt_a * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0));
   }
   // C = dt_a dR/dUhat (each column lives on one face)
   for (int idx = tid; idx < NU * NF; idx += nt) {
@@ -685,7 +689,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       acc += w * ph * sh.JF[f][q][v][UHI + v2];
       if (!MX) acc += w * (pxi * sx * sh.JF[f][q][4 + 2 * v][UHI + v2] + peta * sy * sh.JF[f][q][5 + 2 * v][UHI + v2]);
     }
-    bp[(size_t)row * NC + NU + col] = prm.dt_a * acc;
+    bp[(size_t)row * NC + NU + col] = static_cast<T>(prm.dt_a * acc);
   }
   // D = dh/dU, E = dh/dUhat (E block-diagonal over faces before the mixed elimination)
   for (int idx = tid; idx < NF * NU; idx += nt) {
@@ -702,7 +706,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       if (!MX) d += jt[XF + 2 * v2] * pxi2 * sx + jt[XF + 1 + 2 * v2] * peta2 * sy;
       acc += tb.W[q] * wl * tb.L[q][mm] * d;
     }
-    bp[(size_t)(NU + row) * NC + col] = acc;
+    bp[(size_t)(NU + row) * NC + col] = static_cast<T>(acc);
   }
   for (int idx = tid; idx < NF * NF; idx += nt) {
     const int row = idx / NF, col = idx % NF;
@@ -714,13 +718,13 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       for (int q = 0; q < NQ; ++q)
         acc += tb.W[q] * wl * tb.L[q][mm] * tb.L[q][m2] * sh.JF[f][q][TO + v][UHI + v2];
     }
-    bp[(size_t)(NU + row) * NC + NU + col] = acc;
+    bp[(size_t)(NU + row) * NC + NU + col] = static_cast<T>(acc);
   }
   if (MX) {
     // mixed blocks: A12 = dt_a dR/dQ, A32 = dh/dQ (rows of L), A21 = dg/dU, A23 = dg/dUhat (rows of R,
     // scaled by the inverse of the diagonal mixed mass matrix; g = M_Q Q + l)
-    double* Lm = scr + (size_t)p * S::SCR;          // NR x NQM
-    double* Rm = Lm + (size_t)(NU + NF) * NQM;      // NQM x NR
+    T* Lm = scr + (size_t)p * S::SCR;          // NR x NQM
+    T* Rm = Lm + (size_t)(NU + NF) * NQM;      // NQM x NR
     for (int idx = tid; idx < NU * NQM; idx += nt) {
       const int row = idx / NQM, col = idx % NQM;
       const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
@@ -743,7 +747,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
           acc += tb.W[q] * wl * ph * ph2 * sh.JF[f][q][v][XF + c];
         }
       }
-      Lm[(size_t)row * NQM + col] = prm.dt_a * acc;
+      Lm[(size_t)row * NQM + col] = static_cast<T>(prm.dt_a * acc);
     }
     for (int idx = tid; idx < NF * NQM; idx += nt) {
       const int row = idx / NQM, col = idx % NQM;
@@ -756,7 +760,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
         acc += tb.W[q] * wl * tb.L[q][mm] * ph2 * sh.JF[f][q][TO + v][XF + c];
       }
-      Lm[(size_t)(NU + row) * NQM + col] = acc;
+      Lm[(size_t)(NU + row) * NQM + col] = static_cast<T>(acc);
     }
     // lifting coefficients: l_c[n] = sum_q w sum_p cvol(c,p,d) P_p dphi_n/dx_d - sum_f,q w phi_n sum_p cfac(c,p,n) P_p
     for (int idx = tid; idx < NQM * (NU + NF); idx += nt) {
@@ -782,7 +786,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
             }
             acc += w * d;
           }
-        Rm[(size_t)row * (NU + NF) + col] = minv * acc;
+        Rm[(size_t)row * (NU + NF) + col] = static_cast<T>(minv * acc);
       } else {
         const int cc = col - NU;
         const int f = cc / NFF, v2 = (cc % NFF) / NP, m2 = cc % NP;
@@ -804,7 +808,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
           }
           acc -= w * d;
         }
-        Rm[(size_t)row * (NU + NF) + NU + cc] = minv * acc;
+        Rm[(size_t)row * (NU + NF) + NU + cc] = static_cast<T>(minv * acc);
       }
     }
   }
@@ -829,47 +833,48 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
 // numbered so that the five of one element run on the same XCD and share its
 // L2 copy of the point record.
 // ---------------------------------------------------------------------------
-template <int K> struct CtShared {
+template <int K, class T> struct CtShared {
   static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
-  double TLL[NQ][NP][NP];
-  double TDL[NQ][NP][NP];
-  double LE[2][NP];
-  double NW[NP];
+  T TLL[NQ][NP][NP];
+  T TDL[NQ][NP][NP];
+  T LE[2][NP];
+  T NW[NP];
   union {
     struct {                     // groups 0-2: up to 20 (row variable, column variable) pairs
-      double JX[20][NQV];
-      double JY[20][NQV];
-      double JS[20][4][NQ];
+      T JX[20][NQV];
+      T JY[20][NQV];
+      T JS[20][4][NQ];
     } v;
     struct {                     // groups 3-4: the face records
-      double JF[4][NQ][8][13];
-      double JLF[4][NQ][3][4];
+      T JF[4][NQ][8][13];
+      T JLF[4][NQ][3][4];
     } f;
   } u;
 };
 
 // coefficients of the lifted primitives in the mixed equations: component c of
 // l(U, Uhat) = sum_p (cx[c][p] d/dx + cy[c][p] d/dy) of P_p, P = (u, v, theta)
-__device__ __forceinline__ void lift_coef(int c, double cx[3], double cy[3]) {
-  cx[0] = cx[1] = cx[2] = cy[0] = cy[1] = cy[2] = 0.0;
+template <class T>
+__device__ __forceinline__ void lift_coef(int c, T cx[3], T cy[3]) {
+  cx[0] = cx[1] = cx[2] = cy[0] = cy[1] = cy[2] = T(0);
   switch (c) {
-    case 0: cx[0] = 2.0 / 3.0; cy[1] = -1.0 / 3.0; break;    // eps_11 - tr/3
-    case 1: cx[1] = 1.0; cy[0] = 1.0; break;                 // 2 eps_12 (weighted by 2 in M_Q)
-    case 2: cx[0] = -1.0 / 3.0; cy[1] = 2.0 / 3.0; break;    // eps_22 - tr/3
-    case 3: cx[2] = 1.0; break;                              // grad theta, x
-    default: cy[2] = 1.0; break;                             // grad theta, y
+    case 0: cx[0] = T(2.0 / 3.0); cy[1] = T(-1.0 / 3.0); break;    // eps_11 - tr/3
+    case 1: cx[1] = T(1); cy[0] = T(1); break;                 // 2 eps_12 (weighted by 2 in M_Q)
+    case 2: cx[0] = T(-1.0 / 3.0); cy[1] = T(2.0 / 3.0); break;    // eps_22 - tr/3
+    case 3: cx[2] = T(1); break;                              // grad theta, x
+    default: cy[2] = T(1); break;                             // grad theta, y
   }
 }
 
-template <int K>
+template <int K, class T>
 __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
                                                               const double* __restrict__ rec,
-                                                              double* __restrict__ blk, double* __restrict__ scr) {
+                                                              T* __restrict__ blk, T* __restrict__ scr) {
   using S = HS<K, true>;
   using R = MxRec<K>;
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NR = S::NR, NC = S::NC;
-  __shared__ CtShared<K> sh;
+  __shared__ CtShared<K, T> sh;
   // XCD-aware numbering: consecutive workgroups go to consecutive XCDs, so the
   // five groups of element p are spread over blocks 8 apart
   const int L = blockIdx.x;
@@ -881,8 +886,9 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
   const int tid = threadIdx.x, nt = blockDim.x;
   const BasisTable& tb = *m.tab;
   const double hx = m.hx[e], hy = m.hy[e];
-  const double sx = 2.0 / hx, sy = 2.0 / hy, jac = 0.25 * hx * hy;
-  const double wlx = 0.5 * hy, wly = 0.5 * hx;       // line measure factor of x-faces / y-faces
+  const T sx = T(2.0 / hx), sy = T(2.0 / hy), jac = T(0.25 * hx * hy);
+  const T wlx = T(0.5 * hy), wly = T(0.5 * hx);     // line measure factor of x-faces / y-faces
+  const T dta = T(dt_a);
   for (int i = tid; i < NQ * NN; i += nt) {
     const int q = i / NN, a = (i / NP) % NP, a2 = i % NP;
     sh.TLL[q][a][a2] = tb.W[q] * tb.L[q][a] * tb.L[q][a2];
@@ -891,15 +897,15 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
   if (tid < 2 * NP) sh.LE[tid / NP][tid % NP] = tb.LE[tid / NP][tid % NP];
   if (tid < NP) sh.NW[tid] = tb.NW[tid];
   const double* rp = rec + (size_t)p * R::SIZE;
-  double* bp = blk + (size_t)p * S::BLK;
-  double* Lm = scr + (size_t)p * S::SCR;             // [A12; A32]      NR x NQM
-  double* Rm = Lm + (size_t)NR * NQM;                // M_Q^-1 [A21 A23] NQM x NR
+  T* bp = blk + (size_t)p * S::BLK;
+  T* Lm = scr + (size_t)p * S::SCR;             // [A12; A32]      NR x NQM
+  T* Rm = Lm + (size_t)NR * NQM;                // M_Q^-1 [A21 A23] NQM x NR
   if (grp <= 2) {
     // gather the pair slices: grp 0 K (v, v2), grp 1 A12 (v, c), grp 2 A21 (c, v2)
     const int npair = (grp == 0) ? 16 : 20;
     for (int i = tid; i < npair * NQV; i += nt) {
       const int pr = i / NQV, qv = i % NQV;
-      double jx, jy;
+      T jx, jy;
       if (grp == 0) {
         const int v = pr >> 2, v2 = pr & 3;
         jx = rp[R::JV + (qv * 8 + 2 * v) * 9 + v2];
@@ -910,11 +916,11 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         jy = rp[R::JV + (qv * 8 + 2 * v + 1) * 9 + 4 + c];
       } else {
         const int c = pr >> 2, v2 = pr & 3;
-        double cx[3], cy[3];
+        T cx[3], cy[3];
         lift_coef(c, cx, cy);
         jx = jy = 0.0;
         for (int pp = 0; pp < 3; ++pp) {
-          const double d = rp[R::JL + (qv * 3 + pp) * 4 + v2];
+          const T d = rp[R::JL + (qv * 3 + pp) * 4 + v2];
           jx += cx[pp] * d;
           jy += cy[pp] * d;
         }
@@ -930,19 +936,19 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         sh.u.v.JS[pr][f][q] = rp[R::JF + ((f * NQ + q) * 8 + v) * 13 + col];
       }
     __syncthreads();
-    const double cx = jac * sx, cy = jac * sy;
+    const T cx = jac * sx, cy = jac * sy;
     for (int t = tid; t < npair * NN; t += nt) {
       const int pr = t / NN, a = (t / NP) % NP, a2 = t % NP;
-      double acc[NP][NP];
+      T acc[NP][NP];
 #pragma unroll
       for (int b = 0; b < NP; ++b)
 #pragma unroll
         for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] = 0.0;
-      const double* jxp = sh.u.v.JX[pr];
-      const double* jyp = sh.u.v.JY[pr];
+      const T* jxp = sh.u.v.JX[pr];
+      const T* jyp = sh.u.v.JY[pr];
 #pragma unroll 1
       for (int qj = 0; qj < NQ; ++qj) {
-        double px = 0.0, py = 0.0;
+        T px = 0.0, py = 0.0;
 #pragma unroll
         for (int qi = 0; qi < NQ; ++qi) {
           px += sh.TDL[qi][a][a2] * jxp[qi + NQ * qj];
@@ -956,13 +962,13 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
           for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.TLL[qj][b][b2] * px + sh.TDL[qj][b][b2] * py;
       }
       if (grp < 2) {
-        const double(*js)[NQ] = sh.u.v.JS[pr];
+        const T(*js)[NQ] = sh.u.v.JS[pr];
 #pragma unroll 1
         for (int s = 0; s < 2; ++s) {       // x-faces: f = s
-          const double c0 = wlx * sh.LE[s][a] * sh.LE[s][a2];
+          const T c0 = wlx * sh.LE[s][a] * sh.LE[s][a2];
 #pragma unroll 1
           for (int q = 0; q < NQ; ++q) {
-            const double cq = c0 * js[s][q];
+            const T cq = c0 * js[s][q];
 #pragma unroll
             for (int b = 0; b < NP; ++b)
 #pragma unroll
@@ -971,7 +977,7 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         }
 #pragma unroll 1
         for (int s = 0; s < 2; ++s) {       // y-faces: f = 2 + s
-          double sg = 0.0;
+          T sg = 0.0;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) sg += sh.TLL[q][a][a2] * js[2 + s][q];
           sg *= wly;
@@ -988,8 +994,8 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
 #pragma unroll
           for (int b2 = 0; b2 < NP; ++b2) {
             const int row = v * NN + a + NP * b, col = v2 * NN + a2 + NP * b2;
-            const double mass = (row == col) ? sh.NW[a] * sh.NW[b] * jac : 0.0;
-            bp[(size_t)row * NC + col] = dt_a * acc[b][b2] + mass;
+            const T mass = (row == col) ? sh.NW[a] * sh.NW[b] * jac : T(0);
+            bp[(size_t)row * NC + col] = dta * acc[b][b2] + mass;
           }
       } else if (grp == 1) {
         const int v = pr / 5, c = pr % 5;
@@ -997,13 +1003,13 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         for (int b = 0; b < NP; ++b)
 #pragma unroll
           for (int b2 = 0; b2 < NP; ++b2)
-            Lm[(size_t)(v * NN + a + NP * b) * NQM + c * NN + a2 + NP * b2] = dt_a * acc[b][b2];
+            Lm[(size_t)(v * NN + a + NP * b) * NQM + c * NN + a2 + NP * b2] = dta * acc[b][b2];
       } else {
         const int c = pr >> 2, v2 = pr & 3;
-        const double fc = (c == 1) ? 2.0 : 1.0;
+        const T fc = (c == 1) ? T(2) : T(1);
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
-          const double minv = 1.0 / (fc * sh.NW[a] * sh.NW[b] * jac);
+          const T minv = T(1) / (fc * sh.NW[a] * sh.NW[b] * jac);
 #pragma unroll
           for (int b2 = 0; b2 < NP; ++b2) Rm[(size_t)(c * NN + a + NP * b) * NR + v2 * NN + a2 + NP * b2] = minv * acc[b][b2];
         }
@@ -1017,7 +1023,7 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
   __syncthreads();
   // 1D face sum: sum_q TLL[q][x][y] J(q) for face f
   auto fsum = [&](int f, int x, int y, int jr, int jc) {
-    double acc = 0.0;
+    T acc = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc += sh.TLL[q][x][y] * sh.u.f.JF[f][q][jr][jc];
     return acc;
@@ -1030,21 +1036,21 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         const int row = i / NF, col = i % NF;
         const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
         const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
-        const double val = (f < 2) ? wlx * sh.LE[s][a] * fsum(f, b, m2, v, 4 + v2)
+        const T val = (f < 2) ? wlx * sh.LE[s][a] * fsum(f, b, m2, v, 4 + v2)
                                    : wly * sh.LE[s][b] * fsum(f, a, m2, v, 4 + v2);
-        bp[(size_t)row * NC + NU + col] = dt_a * val;
+        bp[(size_t)row * NC + NU + col] = dta * val;
       } else if (i < NCC + NDD) {
         const int j = i - NCC, row = j / NU, col = j % NU;
         const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
         const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-        const double val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, v2)
+        const T val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, v2)
                                    : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, v2);
         bp[(size_t)(NU + row) * NC + col] = val;
       } else {
         const int j = i - NCC - NDD, row = j / NF, col = j % NF;
         const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
         const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
-        const double val = (f == f2) ? ((f < 2) ? wlx : wly) * fsum(f, mm, m2, 4 + v, 4 + v2) : 0.0;
+        const T val = (f == f2) ? ((f < 2) ? wlx : wly) * fsum(f, mm, m2, 4 + v, 4 + v2) : T(0);
         bp[(size_t)(NU + row) * NC + NU + col] = val;
       }
     }
@@ -1057,79 +1063,98 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
       const int row = i / NQM, col = i % NQM;
       const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
       const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-      const double val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, 8 + c)
+      const T val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, 8 + c)
                                  : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, 8 + c);
       Lm[(size_t)(NU + row) * NQM + col] = val;
     } else {
       const int j = i - N32, row = j / NF, col = j % NF;
       const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
       const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
-      double nx, ny;
-      fnormal(f, nx, ny);
-      double cx[3], cy[3];
+      double nxd, nyd;
+      fnormal(f, nxd, nyd);
+      const T nx = T(nxd), ny = T(nyd);
+      T cx[3], cy[3];
       lift_coef(c, cx, cy);
-      double cn[3];
+      T cn[3];
       for (int pp = 0; pp < 3; ++pp) cn[pp] = cx[pp] * nx + cy[pp] * ny;
       const int x = (f < 2) ? b : a;
-      double acc = 0.0;
+      T acc = 0.0;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const double gq = cn[0] * sh.u.f.JLF[f][q][0][v2] + cn[1] * sh.u.f.JLF[f][q][1][v2] +
+        const T gq = cn[0] * sh.u.f.JLF[f][q][0][v2] + cn[1] * sh.u.f.JLF[f][q][1][v2] +
                           cn[2] * sh.u.f.JLF[f][q][2][v2];
         acc += sh.TLL[q][x][m2] * gq;
       }
-      const double edge = (f < 2) ? wlx * sh.LE[s][a] : wly * sh.LE[s][b];
-      const double minv = 1.0 / (((c == 1) ? 2.0 : 1.0) * sh.NW[a] * sh.NW[b] * jac);
+      const T edge = (f < 2) ? wlx * sh.LE[s][a] : wly * sh.LE[s][b];
+      const T minv = T(1) / (((c == 1) ? T(2) : T(1)) * sh.NW[a] * sh.NW[b] * jac);
       Rm[(size_t)row * NR + NU + col] = -minv * edge * acc;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// batched FP64 GEMM on the matrix cores: C[b] (+)= alpha A[b] B[b], row-major with
-// leading dimensions; 64x64 output tile per workgroup (4 waves x 2x2 tiles of the
-// 16x16x4 f64 MFMA).  Lane l holds A[l%16][l/16], B[l/16][l%16] and accumulates
-// D[l/16 + 4r][l%16], r = 0..3.
+// batched GEMM on the matrix cores (FP64 or FP32): C[b] (+)= alpha A[b] B[b],
+// row-major with leading dimensions; 64x64 output tile per workgroup (4 waves x
+// 2x2 tiles of the 16x16x4 MFMA), 32-deep k-blocks staged in LDS with the next
+// block prefetched into registers.
 // ---------------------------------------------------------------------------
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) gemm_f64_kernel(int batch, int M, int N, int Kd, double alpha, int beta_one,
-                                                       const double* __restrict__ A, int lda, long long sA,
-                                                       const double* __restrict__ B, int ldb, long long sB,
-                                                       double* __restrict__ C, int ldc, long long sC) {
+// 16x16x4 MFMA per element type: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element r of lane l is D[row(l/16, r)][l%16] (the FP64 and FP32
+// instructions order the rows differently).
+template <class T> struct Mfma16;
+template <> struct Mfma16<double> {
+  using V = mf_d4;
+  __device__ static V op(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma16<float> {
+  using V = mf_f4;
+  __device__ static V op(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int Kd, double alpha, int beta_one,
+                                                   const T* __restrict__ A, int lda, long long sA,
+                                                   const T* __restrict__ B, int ldb, long long sB,
+                                                   T* __restrict__ C, int ldc, long long sC) {
+  using MF = Mfma16<T>;
   constexpr int KB = 32;                      // k-block staged in LDS
-  __shared__ double sa[64][KB + 1];
-  __shared__ double sb[KB][65];
+  __shared__ T sa[64][KB + 1];
+  __shared__ T sb[KB][65];
   // XCD-aware numbering: the output tiles of one batch entry share an XCD (and its L2)
-  const int tn = (N + 63) / 64, T = ((M + 63) / 64) * tn;
+  const int tn = (N + 63) / 64, ntile = ((M + 63) / 64) * tn;
   const int L = blockIdx.x, xcd = L & 7, rr = L >> 3;
-  const int t = rr % T;
-  const long long bz = 8LL * (rr / T) + xcd;
+  const int t = rr % ntile;
+  const long long bz = 8LL * (rr / ntile) + xcd;
   if (bz >= batch) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = (t / tn) * 64, n0 = (t % tn) * 64;
-  const double* Ab = A + bz * sA;
-  const double* Bb = B + bz * sB;
-  double* Cb = C + bz * sC;
+  const T* Ab = A + bz * sA;
+  const T* Bb = B + bz * sB;
+  T* Cb = C + bz * sC;
   const int wr = wv >> 1, wc = wv & 1;
   const int li = lane & 15, lk = lane >> 4;
-  mf_d4 acc[2][2];
+  typename MF::V acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = typename MF::V{T(0), T(0), T(0), T(0)};
   constexpr int NL = 64 * KB / 256;           // elements of each operand block per thread
-  double ra[NL], rb[NL];
+  T ra[NL], rb[NL];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
       const int idx = tid + 256 * u;
       const int r = idx / KB, kk = idx % KB;
       const int gm = m0 + r, gk = k0 + kk;
-      ra[u] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : 0.0;
+      ra[u] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : T(0);
       const int kb = idx / 64, cc = idx % 64;
       const int gk2 = k0 + kb, gn = n0 + cc;
-      rb[u] = (gk2 < Kd && gn < N) ? Bb[(size_t)gk2 * ldb + gn] : 0.0;
+      rb[u] = (gk2 < Kd && gn < N) ? Bb[(size_t)gk2 * ldb + gn] : T(0);
     }
   };
   fetch(0);
@@ -1145,12 +1170,12 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int batch, int M, int N, 
 #pragma unroll
     for (int k4 = 0; k4 < KB / 4; ++k4) {
       const int kk = 4 * k4 + lk;
-      const double a0 = sa[32 * wr + li][kk], a1 = sa[32 * wr + 16 + li][kk];
-      const double b0 = sb[kk][32 * wc + li], b1 = sb[kk][32 * wc + 16 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = sa[32 * wr + li][kk], a1 = sa[32 * wr + 16 + li][kk];
+      const T b0 = sb[kk][32 * wc + li], b1 = sb[kk][32 * wc + 16 + li];
+      acc[0][0] = MF::op(a0, b0, acc[0][0]);
+      acc[0][1] = MF::op(a0, b1, acc[0][1]);
+      acc[1][0] = MF::op(a1, b0, acc[1][0]);
+      acc[1][1] = MF::op(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
@@ -1160,23 +1185,26 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int batch, int M, int N, 
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + 32 * wr + 16 * ti + lk + 4 * r;
+        const int gm = m0 + 32 * wr + 16 * ti + MF::row(lk, r);
         const int gn = n0 + 32 * wc + 16 * tj + li;
         if (gm < M && gn < N) {
-          double* cp = Cb + (size_t)gm * ldc + gn;
-          const double v = alpha * acc[ti][tj][r];
+          T* cp = Cb + (size_t)gm * ldc + gn;
+          const T v = T(alpha) * acc[ti][tj][r];
           *cp = beta_one ? (*cp + v) : v;
         }
       }
 }
 
-static hipError_t gemm_f64(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
-                           const double* A, int lda, long long sA, const double* B, int ldb, long long sB, double* C,
-                           int ldc, long long sC) {
+// C[b] (+)= alpha A[b] B[b] for b < batch (row-major, leading dimensions lda/ldb/ldc,
+// batch strides sA/sB/sC in elements); beta_one selects accumulation into C.
+template <class T>
+static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
+                               const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
+                               long long sC) {
   if (batch == 0 || M == 0 || N == 0) return hipSuccess;
-  const long long T = (long long)((M + 63) / 64) * ((N + 63) / 64);
-  const long long nblk = 8LL * ((batch + 7) / 8) * T;
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0,
+  const long long T_ = (long long)((M + 63) / 64) * ((N + 63) / 64);
+  const long long nblk = 8LL * ((batch + 7) / 8) * T_;
+  hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0,
                      A, lda, sA, B, ldb, sB, C, ldc, sC);
   return hipGetLastError();
 }
@@ -1204,14 +1232,18 @@ template <> struct GJTile<64> { static constexpr int RT = 8, CT = 2; };
 template <> struct GJTile<80> { static constexpr int RT = 10, CT = 4; };
 template <> struct GJTile<100> { static constexpr int RT = 10, CT = 4; };
 
-template <int N> struct GJShared {
-  double col[2][N];
-  double row[2][N];
+template <class T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <int N, class T> struct GJShared {
+  T col[2][N];
+  T row[2][N];
   int rp[N];
   int pos[N];
 };
 
-template <int N>
+template <int N, class T>
 struct GJ {
   static constexpr int RT = GJTile<N>::RT, CT = GJTile<N>::CT, NCG = N / CT, NTH = (N / RT) * NCG;
   static_assert(N % RT == 0 && N % CT == 0 && NTH <= 256 && N <= 128, "tile shape");
@@ -1219,14 +1251,14 @@ struct GJ {
   __device__ static int row0(int tid) { return (tid / NCG) * RT; }
   __device__ static int col0(int tid) { return (tid % NCG) * CT; }
 
-  __device__ static void invert(double (&A)[RT][CT], GJShared<N>& sh, int tid) {
+  __device__ static void invert(T (&A)[RT][CT], GJShared<N, T>& sh, int tid) {
     const bool own = owns(tid);
     const int r0 = row0(tid), c0 = col0(tid);
     const int lane = tid & 63;
     bool used0 = lane >= N, used1 = lane + 64 >= N;
     for (int k = 0; k < N; ++k) {
-      double* ck = sh.col[k & 1];
-      double* rk = sh.row[k & 1];
+      T* ck = sh.col[k & 1];
+      T* rk = sh.row[k & 1];
       if (own) {
 #pragma unroll
         for (int j = 0; j < CT; ++j)
@@ -1236,15 +1268,15 @@ struct GJ {
           }
       }
       __syncthreads();
-      double best = used0 ? -1.0 : fabs(ck[lane]);
+      T best = used0 ? T(-1) : tabs(ck[lane]);
       int bi = lane;
       if (!used1) {
-        const double v1 = fabs(ck[lane + 64]);
+        const T v1 = tabs(ck[lane + 64]);
         if (v1 > best) { best = v1; bi = lane + 64; }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
+        const T ob = __shfl_xor(best, off);
         const int oi = __shfl_xor(bi, off);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
@@ -1261,9 +1293,9 @@ struct GJ {
           }
       }
       __syncthreads();
-      const double inv = 1.0 / ck[r];
+      const T inv = T(1) / ck[r];
       if (own) {
-        double rn[CT], f[RT];
+        T rn[CT], f[RT];
 #pragma unroll
         for (int j = 0; j < CT; ++j) rn[j] = rk[c0 + j] * inv;
 #pragma unroll
@@ -1273,7 +1305,7 @@ struct GJ {
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
-          for (int j = 0; j < CT; ++j) A[i][j] = fma(-f[i], rn[j], A[i][j]);
+          for (int j = 0; j < CT; ++j) A[i][j] = tfma(-f[i], rn[j], A[i][j]);
         if (k >= c0 && k < c0 + CT) {
 #pragma unroll
           for (int j = 0; j < CT; ++j)
@@ -1296,24 +1328,24 @@ struct GJ {
   }
 };
 
-template <int K>
-__global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, const double* __restrict__ blk,
-                                                         double* __restrict__ Kinv) {
+template <int K, class T>
+__global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, const T* __restrict__ blk,
+                                                         T* __restrict__ Kinv) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NC = NU + NF + 1;
-  using G = GJ<NU>;
-  __shared__ GJShared<NU> sh;
+  using G = GJ<NU, T>;
+  __shared__ GJShared<NU, T> sh;
   const int p = blockIdx.x, tid = threadIdx.x;
-  const double* bp = blk + (size_t)p * blk_stride;
+  const T* bp = blk + (size_t)p * blk_stride;
   const int r0 = G::row0(tid), c0 = G::col0(tid);
   const bool own = G::owns(tid);
-  double A[G::RT][G::CT];
+  T A[G::RT][G::CT];
 #pragma unroll
   for (int i = 0; i < G::RT; ++i)
 #pragma unroll
-    for (int j = 0; j < G::CT; ++j) A[i][j] = own ? bp[(size_t)(r0 + i) * NC + c0 + j] : 0.0;
+    for (int j = 0; j < G::CT; ++j) A[i][j] = own ? bp[(size_t)(r0 + i) * NC + c0 + j] : T(0);
   G::invert(A, sh, tid);
   if (!own) return;
-  double* Kp = Kinv + (size_t)p * NU * NU;
+  T* Kp = Kinv + (size_t)p * NU * NU;
 #pragma unroll
   for (int i = 0; i < G::RT; ++i) {
     const int row = sh.pos[r0 + i];
@@ -1325,10 +1357,11 @@ __global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, cons
 // ---------------------------------------------------------------------------
 // facet system
 // ---------------------------------------------------------------------------
-// b_F = sum_T -(h_T - D_T K_T^-1 f_T)|_F  (the last column of the condensed augmented system)
-template <int K>
-__global__ void facet_rhs_kernel(DeviceHDG h, size_t blk_stride, const double* __restrict__ blk,
-                                 double* __restrict__ b) {
+// b_F = sum_T -(h_T - D_T K_T^-1 f_T)|_F: h_T (FP64) plus the last column of the condensed
+// augmented system, which holds -D_T K_T^-1 f_T
+template <int K, class T>
+__global__ void facet_rhs_kernel(DeviceHDG h, size_t blk_stride, const T* __restrict__ blk,
+                                 const double* __restrict__ hres, double* __restrict__ b) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h.n_hf * NFF) return;
@@ -1339,7 +1372,7 @@ __global__ void facet_rhs_kernel(DeviceHDG h, size_t blk_stride, const double* _
     if (pe < 0) continue;
     const int f = h.hf_face[2 * hf + s];
     const int lr = f * NFF + row;
-    acc -= blk[(size_t)pe * blk_stride + (size_t)(NU + lr) * NC + NC - 1];     // -(h - D K^-1 f)
+    acc -= hres[(size_t)pe * NF + lr] + (double)blk[(size_t)pe * blk_stride + (size_t)(NU + lr) * NC + NC - 1];
   }
   b[t] = acc;
 }
@@ -1372,8 +1405,9 @@ __device__ void s_block_offsets(const DeviceHDG& h, size_t bs, int F, int G, lon
   }
 }
 
-__device__ __forceinline__ double s_gather(const double* __restrict__ S, const long long* off, int i, int j, int ld) {
-  double v = 0.0;
+template <class T>
+__device__ __forceinline__ T s_gather(const T* __restrict__ S, const long long* off, int i, int j, int ld) {
+  T v = T(0);
 #pragma unroll
   for (int t = 0; t < 4; ++t)
     if (off[t] >= 0) v += S[off[t] + (long long)i * ld + j];
@@ -1387,19 +1421,19 @@ __device__ __forceinline__ double s_gather(const double* __restrict__ S, const l
 // corner, G_r = B_r D_{r-1}^-1.  The diagonal block lives in register tiles
 // (GJ<NB>), the previous inverse, B_r / G_r and C_{r-1} in LDS.  Stored for the
 // apply: D_r^-1, G_r and C_r, each transposed for coalesced matrix-vector products.
-template <int K>
-__global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const double* __restrict__ S, size_t bs,
-                                                         double* __restrict__ Wd, double* __restrict__ Wg,
-                                                         double* __restrict__ Wc) {
+template <int K, class T>
+__global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* __restrict__ S, size_t bs,
+                                                         T* __restrict__ Wd, T* __restrict__ Wg,
+                                                         T* __restrict__ Wc) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
   constexpr int NC = NU + NF + 1;
-  using G = GJ<NB>;
-  extern __shared__ double smem[];
-  double* Ds = smem;                   // NB x NB: D_{r-1}^-1 (row-major)
-  double* Bs = Ds + NB * NB;           // NH x NB: B_r, then G_r
-  double* Cs = Bs + NH * NB;           // NB x NH: C_{r-1}
-  double* Us = Cs + NB * NH;           // NH x NH: G_r C_{r-1}
-  __shared__ GJShared<NB> gsh;
+  using G = GJ<NB, T>;
+  extern __shared__ __align__(16) unsigned char smem_bytes[];
+  T* Ds = reinterpret_cast<T*>(smem_bytes);   // NB x NB: D_{r-1}^-1 (row-major)
+  T* Bs = Ds + NB * NB;                       // NH x NB: B_r, then G_r
+  T* Cs = Bs + NH * NB;                       // NB x NH: C_{r-1}
+  T* Us = Cs + NB * NH;                       // NH x NH: G_r C_{r-1}
+  __shared__ GJShared<NB, T> gsh;
   __shared__ int fs[5], fp[5];
   __shared__ long long oA[5][5][4], oB[2][5][4], oC[5][2][4];
   const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -1422,16 +1456,16 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
     else if (tid < 35) s_block_offsets<K>(h, bs, fs[(tid - 25) / 5], fp[(tid - 25) % 5], oB[(tid - 25) / 5][(tid - 25) % 5]);
     else if (tid < 45) s_block_offsets<K>(h, bs, fp[(tid - 35) / 2], fs[(tid - 35) % 2], oC[(tid - 35) / 2][(tid - 35) % 2]);
     __syncthreads();
-    double A[G::RT][G::CT];
+    T A[G::RT][G::CT];
 #pragma unroll
     for (int i = 0; i < G::RT; ++i)
 #pragma unroll
       for (int j = 0; j < G::CT; ++j) {
         const int r = r0 + i, c = c0 + j;
         const int a = r / NFF, b = c / NFF;
-        double v = 0.0;
+        T v = T(0);
         if (own) {
-          if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? 1.0 : 0.0;
+          if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? T(1) : T(0);
           else v = s_gather(S, oA[a][b], r % NFF, c % NFF, NC);
         }
         A[i][j] = v;
@@ -1441,24 +1475,24 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
         const int r = idx / NB, c = idx % NB;
         Bs[idx] = s_gather(S, oB[r / NFF][c / NFF], r % NFF, c % NFF, NC);
       }
-      double* Cg = Wc + (size_t)(g - 1) * NB * NH;
+      T* Cg = Wc + (size_t)(g - 1) * NB * NH;
       for (int idx = tid; idx < NB * NH; idx += nt) {
         const int c = idx / NB, r = idx % NB;          // coalesced transposed store
-        const double v = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+        const T v = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
         Cs[r * NH + c] = v;
         Cg[idx] = v;
       }
       __syncthreads();
       // G_r = B_r D_{r-1}^-1
-      double gt[GR][GC];
+      T gt[GR][GC];
 #pragma unroll
       for (int i = 0; i < GR; ++i)
 #pragma unroll
-        for (int j = 0; j < GC; ++j) gt[i][j] = 0.0;
+        for (int j = 0; j < GC; ++j) gt[i][j] = T(0);
       const int gr0 = (tid / NGC) * GR, gc0 = (tid % NGC) * GC;
       if (tid < NGT) {
         for (int k = 0; k < NB; ++k) {
-          double bv[GR], dv[GC];
+          T bv[GR], dv[GC];
 #pragma unroll
           for (int i = 0; i < GR; ++i) bv[i] = Bs[(gr0 + i) * NB + k];
 #pragma unroll
@@ -1471,7 +1505,7 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
       }
       __syncthreads();
       if (tid < NGT) {
-        double* Gg = Wg + (size_t)g * NH * NB;
+        T* Gg = Wg + (size_t)g * NH * NB;
 #pragma unroll
         for (int i = 0; i < GR; ++i)
 #pragma unroll
@@ -1484,13 +1518,13 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
       // U = G_r C_{r-1} (NH x NH), then A[H, H] -= U by the tile owners
       if (tid < NUT) {
         const int ur0 = (tid / NUC) * UR, uc0 = (tid % NUC) * UC;
-        double ut[UR][UC];
+        T ut[UR][UC];
 #pragma unroll
         for (int i = 0; i < UR; ++i)
 #pragma unroll
-          for (int j = 0; j < UC; ++j) ut[i][j] = 0.0;
+          for (int j = 0; j < UC; ++j) ut[i][j] = T(0);
         for (int k = 0; k < NB; ++k) {
-          double gv[UR], cv[UC];
+          T gv[UR], cv[UC];
 #pragma unroll
           for (int i = 0; i < UR; ++i) gv[i] = Bs[(ur0 + i) * NB + k];
 #pragma unroll
@@ -1516,7 +1550,7 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
     }
     G::invert(A, gsh, tid);
     // D_r^-1: transposed to global, row-major (un-permuted) to LDS for the next super-row
-    double* Dg = Wd + (size_t)g * NB * NB;
+    T* Dg = Wd + (size_t)g * NB * NB;
     if (own) {
 #pragma unroll
       for (int i = 0; i < G::RT; ++i) {
@@ -1534,9 +1568,9 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const doub
 }
 
 // z = M^-1 x: per window, block-Thomas sweeps; owned facets written
-template <int K>
-__global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const double* __restrict__ Wd,
-                                                        const double* __restrict__ Wg, const double* __restrict__ Wc,
+template <int K, class T>
+__global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wd,
+                                                        const T* __restrict__ Wg, const T* __restrict__ Wc,
                                                         double* __restrict__ Wy, const double* __restrict__ x,
                                                         double* __restrict__ z) {
   constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
@@ -1552,9 +1586,9 @@ __global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const doubl
       const int a = r / NFF;
       double v = (fs[a] >= 0) ? x[(size_t)fs[a] * NFF + r % NFF] : 0.0;
       if (g > g0 && r < NH) {
-        const double* Gg = Wg + (size_t)g * NH * NB;
+        const T* Gg = Wg + (size_t)g * NH * NB;
         double acc = 0.0;
-        for (int k = 0; k < NB; ++k) acc += Gg[(size_t)k * NH + r] * yv[k];
+        for (int k = 0; k < NB; ++k) acc += (double)Gg[(size_t)k * NH + r] * yv[k];
         v -= acc;
       }
       tv[r] = v;
@@ -1573,18 +1607,18 @@ __global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const doubl
     for (int r = tid; r < NB; r += nt) {
       double v = Wy[(size_t)g * NB + r];
       if (g < g1 - 1) {
-        const double* Cg = Wc + (size_t)g * NB * NH;
+        const T* Cg = Wc + (size_t)g * NB * NH;
         double acc = 0.0;
-        for (int k = 0; k < NH; ++k) acc += Cg[(size_t)k * NB + r] * yv[k];
+        for (int k = 0; k < NH; ++k) acc += (double)Cg[(size_t)k * NB + r] * yv[k];
         v -= acc;
       }
       tv[r] = v;
     }
     __syncthreads();
-    const double* Dg = Wd + (size_t)g * NB * NB;
+    const T* Dg = Wd + (size_t)g * NB * NB;
     for (int r = tid; r < NB; r += nt) {
       double acc = 0.0;
-      for (int k = 0; k < NB; ++k) acc += Dg[(size_t)k * NB + r] * tv[k];
+      for (int k = 0; k < NB; ++k) acc += (double)Dg[(size_t)k * NB + r] * tv[k];
       yv[r] = acc;                                        // z_r (its first NH entries feed the next step)
     }
     __syncthreads();
@@ -1597,8 +1631,8 @@ __global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const doubl
 }
 
 // y = S x: one 64-lane workgroup per facet, coalesced reads of the two S_T row blocks
-template <int K>
-__global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const double* __restrict__ blk, size_t bs,
+template <int K, class T>
+__global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* __restrict__ blk, size_t bs,
                                                          const double* __restrict__ x, double* __restrict__ y) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
   __shared__ double xs[2][NF];
@@ -1618,11 +1652,11 @@ __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const doub
   for (int r = 0; r < NFF; ++r) acc[r] = 0.0;
   for (int s = 0; s < 2; ++s) {
     if (pe[s] < 0) continue;
-    const double* Sb = blk + (size_t)pe[s] * bs + (size_t)(NU + fc[s] * NFF) * NC + NU;   // NFF rows of S_T
+    const T* Sb = blk + (size_t)pe[s] * bs + (size_t)(NU + fc[s] * NFF) * NC + NU;   // NFF rows of S_T
     for (int c = tid; c < NF; c += 64) {
       const double xc = xs[s][c];
 #pragma unroll
-      for (int r = 0; r < NFF; ++r) acc[r] += Sb[(size_t)r * NC + c] * xc;
+      for (int r = 0; r < NFF; ++r) acc[r] += (double)Sb[(size_t)r * NC + c] * xc;
     }
   }
 #pragma unroll
@@ -1813,8 +1847,8 @@ __global__ void zero_kernel(int n, double* __restrict__ x) {
 }
 
 // back-substitution: dU = -K^-1 f - K^-1 C dUhat; U += dU on implicit elements; max |dU|, max |U| per block
-template <int K>
-__global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const double* __restrict__ X,
+template <int K, class T>
+__global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const T* __restrict__ X,
                                                           const double* __restrict__ dUh, double* __restrict__ U,
                                                           double* __restrict__ part) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP;
@@ -1827,9 +1861,9 @@ __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const dou
   __syncthreads();
   double mdu = 0.0, mu = 0.0;
   for (int i = tid; i < NU; i += blockDim.x) {
-    const double* Xr = X + ((size_t)p * NU + i) * (NF + 1);      // [K^-1 C | K^-1 f]
-    double acc = Xr[NF];
-    for (int c = 0; c < NF; ++c) acc += Xr[c] * xs[c];
+    const T* Xr = X + ((size_t)p * NU + i) * (NF + 1);      // [K^-1 C | K^-1 f]
+    double acc = (double)Xr[NF];
+    for (int c = 0; c < NF; ++c) acc += (double)Xr[c] * xs[c];
     const double du = -acc;
     const double un = U[(size_t)e * NU + i] + du;
     U[(size_t)e * NU + i] = un;
@@ -1881,6 +1915,15 @@ __global__ void __launch_bounds__(256) facet_update_kernel(int n, const double* 
   }
 
 static bool use_mx(const imex_ctx* c) { return c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous; }
+static bool use_f32(const imex_ctx* c) { return c->opt.precision == IMEX_FP32_REFINE; }
+static size_t la_bytes(const imex_ctx* c) { return use_f32(c) ? sizeof(float) : sizeof(double); }
+
+// element type of the implicit linear algebra: LT = double (IMEX_FP64) or float (IMEX_FP32_REFINE)
+#define LA_DISPATCH(CTX, ...)                                       \
+  if (use_f32(CTX)) { using LT = float; __VA_ARGS__; }              \
+  else { using LT = double; __VA_ARGS__; }
+
+template <class T> static T* la(void* p) { return static_cast<T*>(p); }
 
 static size_t blk_stride(const imex_ctx* c) {      // augmented local system (NU+NF) x (NU+NF+1)
   const size_t NU = 4 * c->NN, NF = 16 * c->NP;
@@ -1903,9 +1946,9 @@ static size_t gm_vectors(const imex_ctx* c) { return (size_t)c->opt.gmres_restar
 size_t hdg_workspace_bytes(const imex_ctx* c) {
   const size_t n_im = c->n_im, NU = 4 * c->NN, NF = 16 * c->NP, NFF = 4 * c->NP, n = (size_t)c->n_hf * NFF;
   const size_t NB = 5 * NFF, NH = 2 * NFF, nsr = (size_t)std::max(c->n_superrows, 1);
-  return 8 * (n_im * (blk_stride(c) + scr_stride(c) + rec_stride(c) + NU * NU + NU * (NF + 1)) +
-              nsr * (NB * NB + 2 * NH * NB + NB) +
-              n * gm_vectors(c) + GmState::SIZE + 2 * (n_im + 1024));
+  const size_t lb = la_bytes(c);
+  return lb * (n_im * (blk_stride(c) + scr_stride(c) + NU * NU + NU * (NF + 1)) + nsr * (NB * NB + 2 * NH * NB)) +
+         8 * (n_im * (rec_stride(c) + NF) + nsr * NB + n * gm_vectors(c) + GmState::SIZE + 2 * (n_im + 1024));
 }
 
 imex_status hdg_alloc(imex_ctx* c) {
@@ -1913,15 +1956,17 @@ imex_status hdg_alloc(imex_ctx* c) {
   Workspace& w = c->ws;
   const size_t n_im = c->n_im, NU = 4 * c->NN, NF = 16 * c->NP, NFF = 4 * c->NP;
   const size_t n = (size_t)c->n_hf * NFF;
-  hipError_t e = hipMalloc(&w.blk, 8 * n_im * blk_stride(c));
-  if (e == hipSuccess && scr_stride(c)) e = hipMalloc(&w.scr, 8 * n_im * scr_stride(c));
+  const size_t lb = la_bytes(c);
+  hipError_t e = hipMalloc(&w.blk, lb * n_im * blk_stride(c));
+  if (e == hipSuccess && scr_stride(c)) e = hipMalloc(&w.scr, lb * n_im * scr_stride(c));
   if (e == hipSuccess && rec_stride(c)) e = hipMalloc(&w.rec, 8 * n_im * rec_stride(c));
-  if (e == hipSuccess) e = hipMalloc(&w.Kinv, 8 * n_im * NU * NU);
-  if (e == hipSuccess) e = hipMalloc(&w.X, 8 * n_im * NU * (NF + 1));
+  if (e == hipSuccess) e = hipMalloc(&w.hres, 8 * n_im * NF);
+  if (e == hipSuccess) e = hipMalloc(&w.Kinv, lb * n_im * NU * NU);
+  if (e == hipSuccess) e = hipMalloc(&w.X, lb * n_im * NU * (NF + 1));
   const size_t nsr = (size_t)std::max(c->n_superrows, 1), NB = 5 * NFF, NH = 2 * NFF;
-  if (e == hipSuccess) e = hipMalloc(&w.Wd, 8 * nsr * NB * NB);
-  if (e == hipSuccess) e = hipMalloc(&w.Wg, 8 * nsr * NH * NB);
-  if (e == hipSuccess) e = hipMalloc(&w.Wc, 8 * nsr * NB * NH);
+  if (e == hipSuccess) e = hipMalloc(&w.Wd, lb * nsr * NB * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.Wg, lb * nsr * NH * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.Wc, lb * nsr * NB * NH);
   if (e == hipSuccess) e = hipMalloc(&w.Wy, 8 * nsr * NB);
   if (e == hipSuccess) e = hipMalloc(&w.gm, 8 * n * gm_vectors(c));
   if (e == hipSuccess) e = hipMalloc(&w.gH, 8 * (size_t)GmState::SIZE);
@@ -1935,98 +1980,110 @@ imex_status hdg_alloc(imex_ctx* c) {
   return IMEX_OK;
 }
 
-static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, const double* Uhat, const double* rhs,
-                                  int jacobian, double* Rh) {
+template <int KK, class LT>
+static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, const double* Uhat, const double* rhs,
+                                    int jacobian, double* Rh) {
   AsmParams prm{dt_a, c->opt.alpha_hdg, c->opt.hdg_flux == IMEX_HDG_FLUX_LF, jacobian};
-  const bool mx = use_mx(c);
   Workspace& w = c->ws;
-  HDG_DISPATCH(c->K, {
-    const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
-    if (mx) {
-      // point values, residual rows and point-wise Jacobians; then the block contraction
-      static_assert(MxRec<KK>::SIZE > 0, "");
-      const size_t shm = sizeof(AsmShared<KK, true>);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true>), dim3(c->n_im), dim3(256), shm, c->stream,
-                         c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, w.Q, Rh, w.rec);
-      if (jacobian) {
-        const int nblk = 40 * ((c->n_im + 7) / 8);
-        hipLaunchKernelGGL(hdg_mx_contract_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
-                           dt_a, w.rec, w.blk, w.scr);
-      }
-      c->timer_end(ta);
-      if (jacobian) {
-        // eliminate the mixed block: [[K C],[D E]] -= [A12; A32] M_Q^-1 [A21 A23]
-        constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NR = NU + NF, NQM = 5 * (KK + 1) * (KK + 1);
-        const int te = c->timer_begin(TM_ELIMINATE);
-        const hipError_t ge = gemm_f64(c->stream, c->n_im, NR, NR, NQM, -1.0, true, w.scr, NQM, (long long)scr_stride(c),
-                                       w.scr + (size_t)NR * NQM, NR, (long long)scr_stride(c), w.blk, NR + 1,
-                                       (long long)blk_stride(c));
-        c->timer_end(te);
-        if (ge != hipSuccess) return ge;
-      }
-    } else {
-      const size_t shm = sizeof(AsmShared<KK, false>);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false>), dim3(c->n_im), dim3(256), shm, c->stream, c->dmesh(),
-                         c->dhdg(), c->gas, prm, U, Uhat, rhs, w.blk, w.scr, nullptr, Rh, nullptr);
-      c->timer_end(ta);
+  LT* blk = la<LT>(w.blk);
+  LT* scr = la<LT>(w.scr);
+  const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
+  if (use_mx(c)) {
+    // point values, residual rows and point-wise Jacobians; then the block contraction
+    const size_t shm = sizeof(AsmShared<KK, true>);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
+                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec, w.hres);
+    if (jacobian) {
+      const int nblk = 40 * ((c->n_im + 7) / 8);
+      hipLaunchKernelGGL((hdg_mx_contract_kernel<KK, LT>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
+                         dt_a, w.rec, blk, scr);
     }
-  });
+    c->timer_end(ta);
+    if (jacobian) {
+      // eliminate the mixed block: [[K C],[D E]] -= [A12; A32] M_Q^-1 [A21 A23]
+      constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NR = NU + NF, NQM = 5 * (KK + 1) * (KK + 1);
+      const int te = c->timer_begin(TM_ELIMINATE);
+      const long long ss = (long long)scr_stride(c);
+      const hipError_t ge = gemm_batched<LT>(c->stream, c->n_im, NR, NR, NQM, -1.0, true, scr, NQM, ss,
+                                             scr + (size_t)NR * NQM, NR, ss, blk, NR + 1, (long long)blk_stride(c));
+      c->timer_end(te);
+      if (ge != hipSuccess) return ge;
+    }
+  } else {
+    const size_t shm = sizeof(AsmShared<KK, false>);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
+                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr, w.hres);
+    c->timer_end(ta);
+  }
   return hipGetLastError();
 }
 
+static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, const double* Uhat, const double* rhs,
+                                  int jacobian, double* Rh) {
+  HDG_DISPATCH(c->K, { LA_DISPATCH(c, return launch_assemble_t<KK, LT>(c, dt_a, U, Uhat, rhs, jacobian, Rh)); });
+  return hipErrorInvalidValue;
+}
+
 // condensation (eqs. statically_condensed_system, SchurCompliment):
-//   K^-1 (LDS Gauss-Jordan);  X = K^-1 [C f];  [E h] -= D X  (so that the augmented system's
-//   facet block holds S_T = E - D K^-1 C and h - D K^-1 f)
+//   K^-1 (register Gauss-Jordan);  X = K^-1 [C f];  [E h] -= D X  (so that the augmented
+//   system's facet block holds S_T = E - D K^-1 C and h - D K^-1 f)
 static hipError_t launch_condense(imex_ctx* c) {
   Workspace& w = c->ws;
-  HDG_DISPATCH(c->K, {
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, {
     constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NC = NU + NF + 1;
-    hipLaunchKernelGGL(hdg_invert_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), w.blk, w.Kinv);
+    LT* blk = la<LT>(w.blk);
+    LT* Kinv = la<LT>(w.Kinv);
+    LT* X = la<LT>(w.X);
+    hipLaunchKernelGGL((hdg_invert_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv);
     const long long bs = (long long)blk_stride(c);
-    hipError_t e = gemm_f64(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, w.Kinv, NU, (long long)NU * NU,
-                            w.blk + NU, NC, bs, w.X, NF + 1, (long long)NU * (NF + 1));
+    hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
+                                    blk + NU, NC, bs, X, NF + 1, (long long)NU * (NF + 1));
     if (e != hipSuccess) return e;
-    e = gemm_f64(c->stream, c->n_im, NF, NF + 1, NU, -1.0, true, w.blk + (size_t)NU * NC, NC, bs, w.X, NF + 1,
-                 (long long)NU * (NF + 1), w.blk + (size_t)NU * NC + NU, NC, bs);
+    e = gemm_batched<LT>(c->stream, c->n_im, NF, NF + 1, NU, -1.0, true, blk + (size_t)NU * NC, NC, bs, X, NF + 1,
+                         (long long)NU * (NF + 1), blk + (size_t)NU * NC + NU, NC, bs);
     if (e != hipSuccess) return e;
-  });
+  }));
   return hipGetLastError();
 }
 
 static hipError_t launch_facet_rhs(imex_ctx* c, double* b) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_rhs_kernel<KK>, dim3((n + 127) / 128), dim3(128), 0, c->stream,
-                                        c->dhdg(), blk_stride(c), w.blk, b));
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((facet_rhs_kernel<KK, LT>), dim3((n + 127) / 128), dim3(128),
+                                                        0, c->stream, c->dhdg(), blk_stride(c), la<LT>(w.blk), w.hres,
+                                                        b)));
   return hipGetLastError();
 }
 
 static hipError_t launch_ras_factor(imex_ctx* c) {
   Workspace& w = c->ws;
-  HDG_DISPATCH(c->K, {
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, {
     constexpr int NFF = 4 * (KK + 1), NB = 5 * NFF, NH = 2 * NFF;
-    const size_t shm = sizeof(double) * ((size_t)NB * NB + 2 * (size_t)NH * NB + (size_t)NH * NH);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK>),
+    const size_t shm = sizeof(LT) * ((size_t)NB * NB + 2 * (size_t)NH * NB + (size_t)NH * NH);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK, LT>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(ras_factor_kernel<KK>, dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(), w.blk,
-                       blk_stride(c), w.Wd, w.Wg, w.Wc);
-  });
+    hipLaunchKernelGGL((ras_factor_kernel<KK, LT>), dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(),
+                       la<LT>(w.blk), blk_stride(c), la<LT>(w.Wd), la<LT>(w.Wg), la<LT>(w.Wc));
+  }));
   return hipGetLastError();
 }
 
 static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(ras_apply_kernel<KK>, dim3(c->n_win), dim3(128), 0, c->stream, c->dhdg(),
-                                        c->ws.Wd, c->ws.Wg, c->ws.Wc, c->ws.Wy, x, y));
+  Workspace& w = c->ws;
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((ras_apply_kernel<KK, LT>), dim3(c->n_win), dim3(128), 0,
+                                                        c->stream, c->dhdg(), la<LT>(w.Wd), la<LT>(w.Wg),
+                                                        la<LT>(w.Wc), w.Wy, x, y)));
   return hipGetLastError();
 }
 
 static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(facet_apply_kernel<KK>, dim3(c->n_hf), dim3(64), 0, c->stream, c->dhdg(),
-                                        c->ws.blk, blk_stride(c), x, y));
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((facet_apply_kernel<KK, LT>), dim3(c->n_hf), dim3(64), 0,
+                                                        c->stream, c->dhdg(), la<LT>(c->ws.blk), blk_stride(c), x,
+                                                        y)));
   return hipGetLastError();
 }
 
@@ -2128,8 +2185,8 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
 }
 
 static hipError_t launch_backsub(imex_ctx* c, const double* dx, double* U, double* part) {
-  HDG_DISPATCH(c->K, hipLaunchKernelGGL(hdg_backsub_kernel<KK>, dim3(c->n_im), dim3(256), 0, c->stream, c->dhdg(),
-                                        c->ws.X, dx, U, part));
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((hdg_backsub_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0,
+                                                        c->stream, c->dhdg(), la<LT>(c->ws.X), dx, U, part)));
   return hipGetLastError();
 }
 
@@ -2216,21 +2273,34 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   return IMEX_OK;
 }
 
+// dst[b][i][j] = src[b * sstride + i * sld + j] for b < batch, i < rows, j < cols (dst dense, FP64)
+template <class T>
+__global__ void copy_blocks_kernel(int batch, int rows, int cols, const T* __restrict__ src, int sld,
+                                   long long sstride, double* __restrict__ dst) {
+  const long long n = (long long)batch * rows * cols;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const long long b = t / ((long long)rows * cols);
+    const int r = (int)((t / cols) % rows), j = (int)(t % cols);
+    dst[t] = (double)src[b * sstride + (long long)r * sld + j];
+  }
+}
+
 imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
                              double* f, double* h, double* K, double* C, double* D, double* E) {
   HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
-  const size_t NU = 4 * c->NN, NF = 16 * c->NP, NC = NU + NF + 1, bs = blk_stride(c);
-  const size_t e8 = sizeof(double);
-  for (int p = 0; p < c->n_im; ++p) {
-    const double* bp = c->ws.blk + (size_t)p * bs;
-    HTRY(hipMemcpy2DAsync(f + p * NU, e8, bp + NC - 1, NC * e8, e8, NU, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpy2DAsync(h + p * NF, e8, bp + NU * NC + NC - 1, NC * e8, e8, NF, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpy2DAsync(K + p * NU * NU, NU * e8, bp, NC * e8, NU * e8, NU, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpy2DAsync(C + p * NU * NF, NF * e8, bp + NU, NC * e8, NF * e8, NU, hipMemcpyDeviceToDevice, c->stream));
-    HTRY(hipMemcpy2DAsync(D + p * NF * NU, NU * e8, bp + NU * NC, NC * e8, NU * e8, NF, hipMemcpyDeviceToDevice,
-                          c->stream));
-    HTRY(hipMemcpy2DAsync(E + p * NF * NF, NF * e8, bp + NU * NC + NU, NC * e8, NF * e8, NF, hipMemcpyDeviceToDevice,
-                          c->stream));
+  const int NU = 4 * c->NN, NF = 16 * c->NP, NC = NU + NF + 1;
+  const long long bs = (long long)blk_stride(c);
+  struct Part { int r0, c0, rows, cols; double* dst; };
+  const Part parts[5] = {{0, NC - 1, NU, 1, f}, {0, 0, NU, NU, K}, {0, NU, NU, NF, C}, {NU, 0, NF, NU, D},
+                         {NU, NU, NF, NF, E}};
+  HTRY(hipMemcpyAsync(h, c->ws.hres, sizeof(double) * (size_t)c->n_im * NF, hipMemcpyDeviceToDevice, c->stream));
+  for (const Part& pt : parts) {
+    LA_DISPATCH(c, {
+      const LT* src = la<LT>(c->ws.blk) + (size_t)pt.r0 * NC + pt.c0;
+      hipLaunchKernelGGL(copy_blocks_kernel<LT>, dim3(1024), dim3(256), 0, c->stream, c->n_im, pt.rows, pt.cols, src,
+                         NC, bs, pt.dst);
+    });
+    HTRY(hipGetLastError());
   }
   HTRY(hipStreamSynchronize(c->stream));
   return IMEX_OK;
