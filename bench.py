@@ -4,14 +4,18 @@ Workload (default): 256x128 quads on [0,2]x[0,0.5], wall-normal stretching to
 aspect ratio 1000, the 16 wall rows implicit HDG-MX, the rest explicit DG-IP,
 degree 4, ARS(3,4,3); Re 1e4, Ma 0.3, Pr 0.72.  One step = one full pass of the
 hot path: every explicit stage residual and ERK combination, every implicit
-Newton stage (assembly, mixed elimination, LU + condensation, GMRES facet
+Newton stage (assembly, mixed elimination, K^-1 + condensation, GMRES facet
 solve, back-substitution) and the interface coupling.
 
-value = N_DOF * s * steps / time, N_DOF = n_elem (k+1)^2 4, s = 3 stages.
-Inputs are resident in device memory before the timed region starts.
+value = N_DOF * s * steps / time (N_DOF = n_elem (k+1)^2 4, s = 3 stages) of the
+mixed-precision path (FP32 element linear algebra, FP64 residuals and Newton
+refinement).  The plain FP64 path is timed beside it on the same input and
+reported with the ratio and the largest relative difference between the two
+final states.  Inputs are resident in device memory before the timed region.
 
 Prints one JSON line.  Also reports:
-  roofline      the dominant kernel's achieved rate against the MI355X peak
+  roofline      the dominant kernel (the batched MFMA GEMM at its largest use,
+                the mixed-block elimination), HIP-event timed over the timed region
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -26,9 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}      # dense MFMA, FP32 / FP64
+LA_BYTES = {"mixed": 4, "fp64": 8}
 
 
 def parse():
@@ -37,14 +41,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="boundary_layer")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"],
+                    help="both: value from the mixed path, FP64 path timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (calibrates HBM traffic counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(seconds_budget: float = 25.0):
+def cpu_baseline():
     """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
     same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
     full mesh), one step, single thread."""
@@ -63,31 +68,57 @@ def cpu_baseline(seconds_budget: float = 25.0):
         s.step()
         dt = time.perf_counter() - t0
     finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
+        if ctx is not None and hasattr(ctx, "unregister"):
+            ctx.unregister()
     dof_stage = wl.n_dof * wl.stages
     return {"value": dof_stage / dt, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
             "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
 
 
-def assembly_flops(wl):
-    """Dense element-Jacobian contraction flops per implicit element."""
-    k = wl.degree
-    nq = (3 * k + 2) // 2
-    nn, nqv = (k + 1) ** 2, nq * nq
-    nu, nf = 4 * nn, 16 * (k + 1)
-    nqm = 5 * nn
-    # volume and face sandwich products B^T J B for the blocks K, A12, A21 (+ C, D, E, A23, A32 on faces)
-    vol = 2 * nqv * (nu * nu * 2 + nu * nqm * 2 + nqm * nu * 2)
-    face = 2 * 4 * nq * (nu * nu + nu * nqm) + 2 * nq * (nu * nf + nf * nu + nf * nf + nqm * nf + nf * nqm)
-    return vol + face
+def elimination_work(wl, n_im, la_bytes):
+    """Algorithmic flops and HBM bytes of one mixed-block elimination launch:
+    [[K C],[D E]] -= [A12; A32] (M_Q^-1 [A21 A23]) per implicit element, NR = NU + NF
+    rows and columns, inner dimension NQM = 5 (k+1)^2; reads both factors, reads and
+    writes the NR x NR block."""
+    k1 = wl.degree + 1
+    nu, nf, nqm = 4 * k1 * k1, 16 * k1, 5 * k1 * k1
+    nr = nu + nf
+    flops = 2.0 * n_im * nr * nr * nqm
+    nbytes = float(n_im) * la_bytes * (2 * nr * nqm + 2 * nr * nr)
+    return flops, nbytes
+
+
+def run(wl, precision, steps, warmup):
+    import torch
+    from paper_2607_16044_amd import binding
+    eng = binding.Engine(wl, precision=0 if precision == "fp64" else 1)
+    U = eng.initial_state()
+    Uhat = eng.init_facets(U)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        eng.ark_step(wl.dt, U, Uhat)
+    eng.reset_timers()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = gmres = 0
+    for _ in range(steps):
+        st = eng.ark_step(wl.dt, U, Uhat)
+        newton += st["newton_its"]
+        gmres += st["gmres_its"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = eng.timers()
+    n_im = eng.sizes["n_implicit"]
+    eng.close()
+    return {"elapsed": elapsed, "timers": timers, "newton": newton / steps, "gmres": gmres / steps, "U": U,
+            "Uhat": Uhat, "n_im": n_im}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this engine runs on one GPU; how the path would shard over several GPUs is "
+                                   "described in DESIGN.md and not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2607_16044_amd import binding, workloads
@@ -102,37 +133,24 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     wl = workloads.get(args.workload)
-    prec = 0 if args.precision == "fp64" else 1
-    eng = binding.Engine(wl, precision=prec)
-    U = eng.initial_state()
-    Uhat = eng.init_facets(U)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        eng.ark_step(wl.dt, U, Uhat)
-    eng.reset_timers()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    newton = gmres = 0
-    for _ in range(args.steps):
-        st = eng.ark_step(wl.dt, U, Uhat)
-        newton += st["newton_its"]
-        gmres += st["gmres_its"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timers = eng.timers()
+    main_prec = "fp64" if args.precision == "fp64" else "mixed"
+    res = run(wl, main_prec, args.steps, args.warmup)
+    other = run(wl, "fp64", args.steps, args.warmup) if args.precision == "both" else None
+    n_dof, s = wl.n_dof, wl.stages
+    value = n_dof * s * args.steps / res["elapsed"]
+    timers = res["timers"]
     phases = {k[:-3]: round(v / args.steps, 3) for k, v in timers.items() if k.endswith("_ms") and v > 0}
-    n_dof = wl.n_dof
-    s = wl.stages
-    value = n_dof * s * args.steps / elapsed
-    # dominant kernel: the element assembly (see the design doc for the algorithmic flop count)
     roof = None
-    if timers["assemble_launches"] > 0:
-        avg_ms = timers["assemble_ms"] / timers["assemble_launches"]
-        flops = assembly_flops(wl) * eng.sizes["n_implicit"]
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma" if False else "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "hdg_assemble_kernel<4,true>", "avg_ms": avg_ms}
+    if timers["eliminate_launches"] > 0:
+        avg_ms = timers["eliminate_ms"] / timers["eliminate_launches"]
+        flops, nbytes = elimination_work(wl, res["n_im"], LA_BYTES[main_prec])
+        gbs = nbytes / (avg_ms * 1e-3) / 1e9
+        tfl = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                "traffic": None,
+                "kernel": f"gemm_kernel<{'float' if main_prec == 'mixed' else 'double'}> (mixed-block elimination)",
+                "avg_ms": avg_ms, "launch_bytes": nbytes, "launch_flops": flops, "mfma_tflops": tfl,
+                "mfma_frac": tfl / PEAK_TFLOPS[main_prec]}
     out = {
         "metric": "DOF-stage updates/s, FP32+refine/batched vs plain FP64 GPU at <=1e-9 rel err",
         "value": value,
@@ -140,19 +158,27 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * res["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == 0 else "f32+f64",
+        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "mesh": f"{wl.nx}x{wl.ny}", "degree": wl.degree, "n_dof": n_dof,
-                   "implicit_elements": eng.sizes["n_implicit"], "tableau": wl.tableau, "stages": s,
-                   "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": args.precision,
-                   "newton_its_per_step": newton / args.steps, "gmres_its_per_step": gmres / args.steps},
+                   "implicit_elements": res["n_im"], "tableau": wl.tableau, "stages": s,
+                   "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": main_prec,
+                   "newton_its_per_step": res["newton"], "gmres_its_per_step": res["gmres"]},
         "roofline": roof,
         "phases_ms_per_step": phases,
     }
+    if other is not None:
+        fp64_value = n_dof * s * args.steps / other["elapsed"]
+        du = float((res["U"] - other["U"]).abs().max() / other["U"].abs().max())
+        dh = float((res["Uhat"] - other["Uhat"]).abs().max() / other["Uhat"].abs().max())
+        out["fp64"] = {"value": fp64_value, "ms_per_step": 1e3 * other["elapsed"] / args.steps,
+                       "newton_its_per_step": other["newton"], "gmres_its_per_step": other["gmres"]}
+        out["mixed_over_fp64"] = value / fp64_value
+        out["mixed_vs_fp64_max_rel_diff"] = max(du, dh)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -175,9 +175,11 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
 /* Accumulated device time per phase, measured with hipEvents on the context's
  * stream: out[2t] = milliseconds, out[2t+1] = number of timed launches for
  * t = 0 explicit DG residual (trace + residual kernels), 1 element assembly
- * kernel, 2 mixed-block elimination, 3 LU + condensation, 4 facet right-hand
- * side and block-Jacobi set-up, 5 GMRES, 6 back-substitution and update,
- * 7 reserved.  host out[16]; reset != 0 clears the counters after reading. */
+ * (point-wise Jacobians + block contraction), 2 mixed-block elimination (one
+ * batched GEMM launch), 3 K^-1 + condensation, 4 facet right-hand side and
+ * preconditioner factorisation, 5 GMRES (including 7), 6 back-substitution and
+ * update, 7 facet preconditioner applications.  host out[16]; reset != 0 clears
+ * the counters after reading. */
 imex_status imex_kernel_times(imex_ctx* ctx, double out[16], int reset);
 
 const char* imex_status_str(imex_status s);

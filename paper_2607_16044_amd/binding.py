@@ -221,7 +221,7 @@ class Engine:
         self._check(self.lib.imex_conservation_sums(self.ctx, _ptr(U), out))
         return np.array(list(out))
 
-    TIMER_NAMES = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "reserved"]
+    TIMER_NAMES = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "precond"]
 
     def timers(self, reset: bool = False):
         out = (ctypes.c_double * 16)()

@@ -112,12 +112,12 @@ hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 void free_regions(imex_ctx* c) {
   for (int** p : {&c->d_im_list, &c->d_ex_list, &c->d_face_kind, &c->d_efacet, &c->d_hf_side, &c->d_hf_face,
-                  &c->d_hf_elem, &c->d_win_off, &c->d_win_slot, &c->d_win_own}) {
+                  &c->d_hf_elem, &c->d_win_off, &c->d_win_slot, &c->d_win_own, &c->d_sr_flags}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.gH, &w.gm, &w.red}) {
+  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.Hp, &w.gH, &w.gm, &w.red}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
@@ -282,6 +282,7 @@ imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, co
   if (he == hipSuccess) he = hipMalloc(&w.Un, es * sizeof(double));
   if (he == hipSuccess) he = hipMalloc(&w.Y, es * sizeof(double));
   if (he == hipSuccess) he = hipMalloc(&w.rhs, es * sizeof(double));
+  if (he == hipSuccess) he = hipMalloc(&w.Yp, es * sizeof(double));
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) {
     imex_destroy(c);
@@ -417,6 +418,11 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
     }
     for (int f = 0; f < c->n_hf; ++f)
       if (!owned[f]) return fail(c, IMEX_EINVAL, "facet preconditioner windows do not cover every facet");
+    // per super-row: bit 0 = has a predecessor, bit 1 = has a successor in its window
+    c->sr_flags.assign(c->n_superrows, 0);
+    for (int w = 0; w < c->n_win; ++w)
+      for (int g = c->win_off[w]; g < c->win_off[w + 1]; ++g)
+        c->sr_flags[g] = (g > c->win_off[w] ? 1 : 0) | (g + 1 < c->win_off[w + 1] ? 2 : 0);
   }
   c->face_kind.assign(4 * c->n_im, 0);
   for (int p = 0; p < c->n_im; ++p) {
@@ -442,6 +448,7 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   if (he == hipSuccess) he = upload(&c->d_win_off, c->win_off, s);
   if (he == hipSuccess) he = upload(&c->d_win_slot, c->win_slot, s);
   if (he == hipSuccess) he = upload(&c->d_win_own, c->win_own, s);
+  if (he == hipSuccess) he = upload(&c->d_sr_flags, c->sr_flags, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return fail(c, IMEX_ENOMEM, std::string("region tables: ") + hipGetErrorString(he));
   imex_status st = hdg_alloc(c);
@@ -537,6 +544,14 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   double* Rhdg[3] = {w.Rstage[4], w.Rstage[5], w.Rstage[6]};
   HIP_TRY(c, hipMemcpyAsync(w.Un, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   HIP_TRY(c, hipMemcpyAsync(w.Y, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  if (c->n_im > 0) {
+    HIP_TRY(c, hipMemcpyAsync(w.Yp, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    HIP_TRY(c, hipMemcpyAsync(w.Hp, Uhat, (size_t)c->n_hf * 4 * c->NP * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  }
+  // implicit stage times c_i = sum_j a_ij (c_0 = 0)
+  double ci[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 1; i <= s; ++i)
+    for (int j = 0; j < i; ++j) ci[i] += tab->Ai[3 * (i - 1) + j];
   if (mx) HIP_TRY(c, launch_lift_mixed(c, w.Y, Uhat, w.Q));   // Q^im_0 = Q(U_n, Uhat_n)
   for (int i = 1; i <= s; ++i) {
     // R^DG(y^ex_i, y^im_{i-1}); the mixed variables in w.Q belong to y^im_{i-1}
@@ -557,6 +572,10 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
       HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
       for (int j = 0; j < i - 1; ++j)
         HIP_TRY(c, launch_scale_copy(c, w.rhs, w.rhs, 1.0, Rh[j], -ch[j], n));
+      // Newton initial guess (the converged root does not depend on it): linear
+      // extrapolation in stage time from the two previous implicit stage values
+      if (i >= 2 && ci[i - 1] - ci[i - 2] > 1e-12 * dt)
+        HIP_TRY(c, launch_extrapolate(c, (ci[i] - ci[i - 1]) / (ci[i - 1] - ci[i - 2]), w.Y, w.Yp, Uhat, w.Hp));
       imex_stats sst{};
       imex_status r = hdg_stage_solve(c, dt * tab->Ai[3 * (i - 1) + (i - 1)], w.rhs, w.Y, Uhat, Rhdg[i - 1], &sst);
       if (st) {
@@ -623,7 +642,7 @@ void imex_destroy(imex_ctx* c) {
   c->ev_free.clear();
   free_regions(c);
   Workspace& w = c->ws;
-  for (double** p : {&w.trace, &w.Q, &w.Un, &w.Y, &w.rhs}) {
+  for (double** p : {&w.trace, &w.Q, &w.Un, &w.Y, &w.rhs, &w.Yp}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

@@ -37,6 +37,8 @@ struct DeviceHDG {
   const int* win_off;       // [n_win+1] offsets (in super-rows) of each window
   const int* win_slot;      // [n_superrows][5] HDG facet of each slot or -1
   const int* win_own;       // [n_superrows][5] 1 if the window writes that facet's result
+  int n_sr;
+  const int* sr_flags;      // [n_superrows] bit 0: has a predecessor, bit 1: has a successor
 };
 
 struct Workspace {
@@ -46,6 +48,8 @@ struct Workspace {
   double* Un = nullptr;         // copy of U at t_n
   double* Y = nullptr;          // stage state
   double* rhs = nullptr;        // implicit stage right-hand side
+  double* Yp = nullptr;         // previous implicit stage value (stage predictor)
+  double* Hp = nullptr;         // previous facet stage value (stage predictor)
   // implicit Newton.  The linear-algebra buffers hold doubles (IMEX_FP64) or
   // floats (IMEX_FP32_REFINE); the Newton residual column of blk is stored in
   // the same type, the state, residual evaluation and Krylov vectors stay FP64.
@@ -57,8 +61,8 @@ struct Workspace {
   void* X = nullptr;            // per implicit element: K^-1 [C f]  [NU][NF+1]
   void* Wd = nullptr;           // per window super-row: inverse of the eliminated diagonal block
   void* Wg = nullptr;           // per window super-row: B_r D_{r-1}^-1 (facet rows x previous super-row)
-  void* Wc = nullptr;           // per window super-row: coupling to the next super-row
-  double* Wy = nullptr;         // per window super-row: forward-sweep vector
+  void* Wc = nullptr;           // per window super-row: D_r^-1 C_r, coupling to the next super-row
+  double* Wy = nullptr;         // per window super-row: sweep vectors y_r, w_r (NB each) and z_r on H (NH)
   double* gH = nullptr;         // GMRES Hessenberg, rotations, g, residual history, scalars (device)
   double* gm = nullptr;         // GMRES basis and vectors
   double* red = nullptr;        // reduction scratch
@@ -81,10 +85,16 @@ struct imex_ctx {
   std::vector<int> nbr, bcf;
   std::vector<unsigned char> imp;
   std::vector<int> im_list, ex_list, face_kind, efacet, hf_side, hf_face, hf_elem;
-  std::vector<int> win_off, win_slot, win_own;
+  std::vector<int> win_off, win_slot, win_own, sr_flags;
   int n_win = 0, n_superrows = 0;
   int n_im = 0, n_ex = 0, n_hf = 0;
   bool regions_set = false;
+  // facet preconditioner reuse across Newton iterations, stages and steps
+  bool prec_valid = false;      // factors match a recent system
+  bool prec_fresh = false;      // the next GMRES solve is the first after a refactorisation
+  int prec_base = 0;            // GMRES iterations of that first solve
+  int prec_extra = 0;           // GMRES iterations above prec_base since then
+  double prec_dt_a = 0.0;       // dt a_ii of the factorised system
   // device copies
   double *d_hx = nullptr, *d_hy = nullptr;
   int *d_nbr = nullptr, *d_bcf = nullptr;
@@ -92,7 +102,7 @@ struct imex_ctx {
   imex::BasisTable* d_tab = nullptr;
   int *d_im_list = nullptr, *d_ex_list = nullptr, *d_face_kind = nullptr, *d_efacet = nullptr;
   int *d_hf_side = nullptr, *d_hf_face = nullptr, *d_hf_elem = nullptr;
-  int *d_win_off = nullptr, *d_win_slot = nullptr, *d_win_own = nullptr;
+  int *d_win_off = nullptr, *d_win_slot = nullptr, *d_win_own = nullptr, *d_sr_flags = nullptr;
   imex::Workspace ws;
   std::string err;
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
@@ -109,15 +119,15 @@ struct imex_ctx {
     return imex::DeviceMesh{E, nx, ny, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab};
   }
   imex::DeviceHDG dhdg() const {
-    return imex::DeviceHDG{n_im,     n_hf,          d_im_list,  d_face_kind,  d_efacet,  d_hf_side, d_hf_face,
-                           d_hf_elem, n_win, d_win_off, d_win_slot, d_win_own};
+    return imex::DeviceHDG{n_im,      n_hf,  d_im_list, d_face_kind, d_efacet,    d_hf_side, d_hf_face,
+                           d_hf_elem, n_win, d_win_off, d_win_slot, d_win_own, n_superrows, d_sr_flags};
   }
 };
 
 // timer tags
 namespace imex {
 enum TimerTag { TM_DG = 0, TM_ASSEMBLE = 1, TM_ELIMINATE = 2, TM_CONDENSE = 3, TM_FACET = 4, TM_GMRES = 5,
-                TM_BACKSUB = 6, TM_ERK = 7 };
+                TM_BACKSUB = 6, TM_PRECOND = 7 };
 }
 
 // kernel launchers (dg.hip)
@@ -133,6 +143,7 @@ hipError_t launch_scale_copy(const imex_ctx* c, const double* src, double* dst, 
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);
+hipError_t launch_extrapolate(const imex_ctx* c, double coef, double* Y, double* Yp, double* Uhat, double* Hp);
 imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double* U, double* Uhat, double* R_out,
                             imex_stats* st);
 imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,

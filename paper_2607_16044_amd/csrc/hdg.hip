@@ -1420,7 +1420,8 @@ __device__ __forceinline__ T s_gather(const T* __restrict__ S, const long long* 
 // with explicit inverses: D_r = A_r - B_r D_{r-1}^-1 C_{r-1} on the NH x NH
 // corner, G_r = B_r D_{r-1}^-1.  The diagonal block lives in register tiles
 // (GJ<NB>), the previous inverse, B_r / G_r and C_{r-1} in LDS.  Stored for the
-// apply: D_r^-1, G_r and C_r, each transposed for coalesced matrix-vector products.
+// apply: D_r^-1, G_r and E_r = D_r^-1 C_r, each transposed for coalesced
+// matrix-vector products.
 template <int K, class T>
 __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* __restrict__ S, size_t bs,
                                                          T* __restrict__ Wd, T* __restrict__ Wg,
@@ -1443,6 +1444,9 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
   // G_r = B_r D^-1 is NH x NB: 4 x 4 register tiles over (NH/4) x (NB/4) threads
   constexpr int GR = 4, GC = 4, NGC = NB / GC, NGT = (NH / GR) * NGC;
   static_assert(NH % GR == 0 && NB % GC == 0 && NGT <= 256, "G tile shape");
+  // E_{r-1} = D_{r-1}^-1 C_{r-1} is NB x NH: 4 x 4 tiles
+  constexpr int ER = 4, EC = 4, NEC = NH / EC, NET = (NB / ER) * NEC;
+  static_assert(NB % ER == 0 && NH % EC == 0 && NET <= 256, "E tile shape");
   // G_r C_{r-1} is NH x NH: 2 x 4 tiles
   constexpr int UR = 2, UC = 4, NUC = NH / UC, NUT = (NH / UR) * NUC;
   static_assert(NH % UR == 0 && NH % UC == 0 && NUT <= 256, "corner tile shape");
@@ -1475,12 +1479,9 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
         const int r = idx / NB, c = idx % NB;
         Bs[idx] = s_gather(S, oB[r / NFF][c / NFF], r % NFF, c % NFF, NC);
       }
-      T* Cg = Wc + (size_t)(g - 1) * NB * NH;
       for (int idx = tid; idx < NB * NH; idx += nt) {
-        const int c = idx / NB, r = idx % NB;          // coalesced transposed store
-        const T v = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
-        Cs[r * NH + c] = v;
-        Cg[idx] = v;
+        const int r = idx / NH, c = idx % NH;
+        Cs[idx] = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
       }
       __syncthreads();
       // G_r = B_r D_{r-1}^-1
@@ -1504,6 +1505,31 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
         }
       }
       __syncthreads();
+      // E_{r-1} = D_{r-1}^-1 C_{r-1} (NB x NH), stored transposed: E[k * NB + i] = E_{r-1}[i][k]
+      if (tid < NET) {
+        const int er0 = (tid / NEC) * ER, ec0 = (tid % NEC) * EC;
+        T et[ER][EC];
+#pragma unroll
+        for (int i = 0; i < ER; ++i)
+#pragma unroll
+          for (int j = 0; j < EC; ++j) et[i][j] = T(0);
+        for (int k = 0; k < NB; ++k) {
+          T dv[ER], cv[EC];
+#pragma unroll
+          for (int i = 0; i < ER; ++i) dv[i] = Ds[(er0 + i) * NB + k];
+#pragma unroll
+          for (int j = 0; j < EC; ++j) cv[j] = Cs[k * NH + ec0 + j];
+#pragma unroll
+          for (int i = 0; i < ER; ++i)
+#pragma unroll
+            for (int j = 0; j < EC; ++j) et[i][j] += dv[i] * cv[j];
+        }
+        T* Eg = Wc + (size_t)(g - 1) * NB * NH;
+#pragma unroll
+        for (int i = 0; i < ER; ++i)
+#pragma unroll
+          for (int j = 0; j < EC; ++j) Eg[(size_t)(ec0 + j) * NB + er0 + i] = et[i][j];
+      }
       if (tid < NGT) {
         T* Gg = Wg + (size_t)g * NH * NB;
 #pragma unroll
@@ -1567,66 +1593,203 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
   }
 }
 
-// z = M^-1 x: per window, block-Thomas sweeps; owned facets written
+// Preconditioner apply z = M^-1 x in five launches.  Per window, with y, w, z
+// restricted to super-row r (NB unknowns, H = its first NH):
+//   forward   y_r = x_r - G_r y_{r-1}        (only the H rows change)
+//   diagonal  w_r = D_r^-1 y_r
+//   backward  z_r = w_r - E_r z_{r+1}[H]
+// Splitting G_r y_{r-1} = G_r[:, H] y_{r-1}[H] + G_r[:, ~H] x_{r-1}[~H], and the
+// backward update into its H rows and the rest, leaves two serial chains of
+// NH x NH products per window (one wave each); the D_r^-1 products and the
+// other pieces run over all super-rows at once.  Sweep vectors per super-row
+// in Wy: y_r (NB) | w_r (NB) | z_r[H] (NH).
+template <int K> struct RasDims {
+  static constexpr int NFF = 4 * (K + 1), NB = 5 * NFF, NH = 2 * NFF, NSV = 2 * NB + NH;
+};
+
+// y_r = x_r, then y_r[H] -= G_r[:, ~H] x_{r-1}[~H]
 template <int K, class T>
-__global__ void __launch_bounds__(128) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wd,
-                                                        const T* __restrict__ Wg, const T* __restrict__ Wc,
-                                                        double* __restrict__ Wy, const double* __restrict__ x,
-                                                        double* __restrict__ z) {
-  constexpr int NP = K + 1, NFF = 4 * NP, NB = 5 * NFF, NH = 2 * NFF;
-  __shared__ double yv[NB], tv[NB];
-  __shared__ int fs[5];
-  const int w = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
-  // forward: y_r = x_r - G_r y_{r-1}
-  for (int g = g0; g < g1; ++g) {
-    if (tid < 5) fs[tid] = h.win_slot[5 * g + tid];
-    __syncthreads();
-    for (int r = tid; r < NB; r += nt) {
-      const int a = r / NFF;
-      double v = (fs[a] >= 0) ? x[(size_t)fs[a] * NFF + r % NFF] : 0.0;
-      if (g > g0 && r < NH) {
-        const T* Gg = Wg + (size_t)g * NH * NB;
-        double acc = 0.0;
-        for (int k = 0; k < NB; ++k) acc += (double)Gg[(size_t)k * NH + r] * yv[k];
-        v -= acc;
-      }
-      tv[r] = v;
-    }
-    __syncthreads();
-    for (int r = tid; r < NB; r += nt) {
-      yv[r] = tv[r];
-      Wy[(size_t)g * NB + r] = tv[r];
-    }
-    __syncthreads();
+__global__ void __launch_bounds__(128) ras_pre_kernel(DeviceHDG h, const T* __restrict__ Wg,
+                                                      const double* __restrict__ x, double* __restrict__ Wy) {
+  using D = RasDims<K>;
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
+  __shared__ double xp[NB], yr[NB];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int fl = h.sr_flags[g];
+  for (int i = tid; i < NB; i += blockDim.x) {
+    const int a = i / NFF;
+    const int f = h.win_slot[5 * g + a];
+    yr[i] = (f >= 0) ? x[(size_t)f * NFF + i % NFF] : 0.0;
+    int fp = -1;
+    if (fl & 1) fp = h.win_slot[5 * (g - 1) + a];
+    xp[i] = (fp >= 0) ? x[(size_t)fp * NFF + i % NFF] : 0.0;
   }
-  // backward: z_r = Dinv_r (y_r - C_r z_{r+1})
-  for (int g = g1 - 1; g >= g0; --g) {
-    if (tid < 5) fs[tid] = h.win_slot[5 * g + tid];
-    __syncthreads();
-    for (int r = tid; r < NB; r += nt) {
-      double v = Wy[(size_t)g * NB + r];
-      if (g < g1 - 1) {
-        const T* Cg = Wc + (size_t)g * NB * NH;
-        double acc = 0.0;
-        for (int k = 0; k < NH; ++k) acc += (double)Cg[(size_t)k * NB + r] * yv[k];
-        v -= acc;
+  __syncthreads();
+  const T* Gg = Wg + (size_t)g * NH * NB;        // Gg[k * NH + i] = G_r[i][k]
+  double* Y = Wy + (size_t)g * D::NSV;
+  for (int i = tid; i < NB; i += blockDim.x) {
+    double v = yr[i];
+    if ((fl & 1) && i < NH) {
+      double a0 = 0.0, a1 = 0.0;
+      int k = NH;
+      for (; k + 1 < NB; k += 2) {
+        a0 += (double)Gg[(size_t)k * NH + i] * xp[k];
+        a1 += (double)Gg[(size_t)(k + 1) * NH + i] * xp[k + 1];
       }
-      tv[r] = v;
+      for (; k < NB; ++k) a0 += (double)Gg[(size_t)k * NH + i] * xp[k];
+      v -= a0 + a1;
+    }
+    Y[i] = v;
+  }
+}
+
+// forward chain: y_r[H] -= G_r[:, H] y_{r-1}[H], one wave per window
+template <int K, class T>
+__global__ void __launch_bounds__(64) ras_fwd_kernel(DeviceHDG h, const T* __restrict__ Wg, double* __restrict__ Wy) {
+  using D = RasDims<K>;
+  constexpr int NB = D::NB, NH = D::NH;
+  static_assert(NH <= 64, "one lane per H row");
+  __shared__ double yh[NH];
+  const int w = blockIdx.x, lane = threadIdx.x;
+  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  if (g1 <= g0) return;
+  if (lane < NH) yh[lane] = Wy[(size_t)g0 * D::NSV + lane];
+  T gc[NH];
+  if (g0 + 1 < g1 && lane < NH) {
+    const T* Gg = Wg + (size_t)(g0 + 1) * NH * NB;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) gc[k] = Gg[(size_t)k * NH + lane];
+  }
+  __syncthreads();
+  for (int g = g0 + 1; g < g1; ++g) {
+    T gn[NH];
+    if (g + 1 < g1 && lane < NH) {
+      const T* Gn = Wg + (size_t)(g + 1) * NH * NB;
+#pragma unroll
+      for (int k = 0; k < NH; ++k) gn[k] = Gn[(size_t)k * NH + lane];
+    }
+    double v = 0.0;
+    if (lane < NH) {
+      v = Wy[(size_t)g * D::NSV + lane];
+#pragma unroll
+      for (int k = 0; k < NH; ++k) v -= (double)gc[k] * yh[k];
     }
     __syncthreads();
-    const T* Dg = Wd + (size_t)g * NB * NB;
-    for (int r = tid; r < NB; r += nt) {
-      double acc = 0.0;
-      for (int k = 0; k < NB; ++k) acc += (double)Dg[(size_t)k * NB + r] * tv[k];
-      yv[r] = acc;                                        // z_r (its first NH entries feed the next step)
+    if (lane < NH) {
+      yh[lane] = v;
+      Wy[(size_t)g * D::NSV + lane] = v;
     }
     __syncthreads();
-    for (int r = tid; r < NB; r += nt) {
-      const int a = r / NFF;
-      if (fs[a] >= 0 && h.win_own[5 * g + a]) z[(size_t)fs[a] * NFF + r % NFF] = yv[r];
+    if (g + 1 < g1) {
+#pragma unroll
+      for (int k = 0; k < NH; ++k) gc[k] = gn[k];
+    }
+  }
+}
+
+// w_r = D_r^-1 y_r, one workgroup per super-row
+template <int K, class T>
+__global__ void __launch_bounds__(128) ras_diag_kernel(DeviceHDG h, const T* __restrict__ Wd, double* __restrict__ Wy) {
+  using D = RasDims<K>;
+  constexpr int NB = D::NB;
+  __shared__ double yv[NB];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  double* Y = Wy + (size_t)g * D::NSV;
+  for (int i = tid; i < NB; i += blockDim.x) yv[i] = Y[i];
+  __syncthreads();
+  const T* Dg = Wd + (size_t)g * NB * NB;        // Dg[k * NB + i] = D_r^-1[i][k]
+  for (int i = tid; i < NB; i += blockDim.x) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
+    for (; k + 3 < NB; k += 4) {
+      a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
+      a1 += (double)Dg[(size_t)(k + 1) * NB + i] * yv[k + 1];
+      a2 += (double)Dg[(size_t)(k + 2) * NB + i] * yv[k + 2];
+      a3 += (double)Dg[(size_t)(k + 3) * NB + i] * yv[k + 3];
+    }
+    for (; k < NB; ++k) a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
+    Y[NB + i] = (a0 + a1) + (a2 + a3);
+  }
+}
+
+// backward chain: z_r[H] = w_r[H] - E_r[H, :] z_{r+1}[H], one wave per window
+template <int K, class T>
+__global__ void __launch_bounds__(64) ras_bwd_kernel(DeviceHDG h, const T* __restrict__ Wc, double* __restrict__ Wy) {
+  using D = RasDims<K>;
+  constexpr int NB = D::NB, NH = D::NH;
+  __shared__ double zh[NH];
+  const int w = blockIdx.x, lane = threadIdx.x;
+  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  if (g1 <= g0) return;
+  if (lane < NH) {
+    const double v = Wy[(size_t)(g1 - 1) * D::NSV + NB + lane];
+    zh[lane] = v;
+    Wy[(size_t)(g1 - 1) * D::NSV + 2 * NB + lane] = v;
+  }
+  T ec[NH];
+  if (g1 - 2 >= g0 && lane < NH) {
+    const T* Eg = Wc + (size_t)(g1 - 2) * NB * NH;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) ec[k] = Eg[(size_t)k * NB + lane];
+  }
+  __syncthreads();
+  for (int g = g1 - 2; g >= g0; --g) {
+    T en[NH];
+    if (g - 1 >= g0 && lane < NH) {
+      const T* En = Wc + (size_t)(g - 1) * NB * NH;
+#pragma unroll
+      for (int k = 0; k < NH; ++k) en[k] = En[(size_t)k * NB + lane];
+    }
+    double v = 0.0;
+    if (lane < NH) {
+      v = Wy[(size_t)g * D::NSV + NB + lane];
+#pragma unroll
+      for (int k = 0; k < NH; ++k) v -= (double)ec[k] * zh[k];
     }
     __syncthreads();
+    if (lane < NH) {
+      zh[lane] = v;
+      Wy[(size_t)g * D::NSV + 2 * NB + lane] = v;
+    }
+    __syncthreads();
+    if (g - 1 >= g0) {
+#pragma unroll
+      for (int k = 0; k < NH; ++k) ec[k] = en[k];
+    }
+  }
+}
+
+// z_r[~H] = w_r[~H] - E_r[~H, :] z_{r+1}[H]; owned facets of z written
+template <int K, class T>
+__global__ void __launch_bounds__(128) ras_out_kernel(DeviceHDG h, const T* __restrict__ Wc,
+                                                      const double* __restrict__ Wy, double* __restrict__ z) {
+  using D = RasDims<K>;
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
+  __shared__ double zn[NH];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int fl = h.sr_flags[g];
+  const double* Y = Wy + (size_t)g * D::NSV;
+  if ((fl & 2) && tid < NH) zn[tid] = Wy[(size_t)(g + 1) * D::NSV + 2 * NB + tid];
+  __syncthreads();
+  const T* Eg = Wc + (size_t)g * NB * NH;         // Eg[k * NB + i] = E_r[i][k]
+  for (int i = tid; i < NB; i += blockDim.x) {
+    double v;
+    if (i < NH) {
+      v = Y[2 * NB + i];
+    } else {
+      v = Y[NB + i];
+      if (fl & 2) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int k = 0; k < NH; k += 2) {
+          a0 += (double)Eg[(size_t)k * NB + i] * zn[k];
+          a1 += (double)Eg[(size_t)(k + 1) * NB + i] * zn[k + 1];
+        }
+        v -= a0 + a1;
+      }
+    }
+    const int a = i / NFF;
+    const int f = h.win_slot[5 * g + a];
+    if (f >= 0 && h.win_own[5 * g + a]) z[(size_t)f * NFF + i % NFF] = v;
   }
 }
 
@@ -1948,7 +2111,8 @@ size_t hdg_workspace_bytes(const imex_ctx* c) {
   const size_t NB = 5 * NFF, NH = 2 * NFF, nsr = (size_t)std::max(c->n_superrows, 1);
   const size_t lb = la_bytes(c);
   return lb * (n_im * (blk_stride(c) + scr_stride(c) + NU * NU + NU * (NF + 1)) + nsr * (NB * NB + 2 * NH * NB)) +
-         8 * (n_im * (rec_stride(c) + NF) + nsr * NB + n * gm_vectors(c) + GmState::SIZE + 2 * (n_im + 1024));
+         8 * (n_im * (rec_stride(c) + NF) + nsr * (2 * NB + NH) + n * (gm_vectors(c) + 1) + GmState::SIZE +
+              2 * (n_im + 1024));
 }
 
 imex_status hdg_alloc(imex_ctx* c) {
@@ -1967,8 +2131,9 @@ imex_status hdg_alloc(imex_ctx* c) {
   if (e == hipSuccess) e = hipMalloc(&w.Wd, lb * nsr * NB * NB);
   if (e == hipSuccess) e = hipMalloc(&w.Wg, lb * nsr * NH * NB);
   if (e == hipSuccess) e = hipMalloc(&w.Wc, lb * nsr * NB * NH);
-  if (e == hipSuccess) e = hipMalloc(&w.Wy, 8 * nsr * NB);
+  if (e == hipSuccess) e = hipMalloc(&w.Wy, 8 * nsr * (2 * NB + NH));
   if (e == hipSuccess) e = hipMalloc(&w.gm, 8 * n * gm_vectors(c));
+  if (e == hipSuccess) e = hipMalloc(&w.Hp, 8 * n);
   if (e == hipSuccess) e = hipMalloc(&w.gH, 8 * (size_t)GmState::SIZE);
   if (e == hipSuccess) e = hipMalloc(&w.red, 8 * 2 * (n_im + 1024));
   if (e == hipSuccess) e = hipHostMalloc(&w.hred, 8 * ((size_t)GmState::SIZE + 2 * (n_im + 1024)), 0);
@@ -1977,6 +2142,7 @@ imex_status hdg_alloc(imex_ctx* c) {
     return IMEX_ENOMEM;
   }
   w.bytes += hdg_workspace_bytes(c);
+  c->prec_valid = false;
   return IMEX_OK;
 }
 
@@ -2074,9 +2240,16 @@ static hipError_t launch_ras_factor(imex_ctx* c) {
 
 static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
   Workspace& w = c->ws;
-  HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((ras_apply_kernel<KK, LT>), dim3(c->n_win), dim3(128), 0,
-                                                        c->stream, c->dhdg(), la<LT>(w.Wd), la<LT>(w.Wg),
-                                                        la<LT>(w.Wc), w.Wy, x, y)));
+  const int nsr = c->n_superrows;
+  const int tp = c->timer_begin(TM_PRECOND);
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, {
+    hipLaunchKernelGGL((ras_pre_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wg), x, w.Wy);
+    hipLaunchKernelGGL((ras_fwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wg), w.Wy);
+    hipLaunchKernelGGL((ras_diag_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wd), w.Wy);
+    hipLaunchKernelGGL((ras_bwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy);
+    hipLaunchKernelGGL((ras_out_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy, y);
+  }));
+  c->timer_end(tp);
   return hipGetLastError();
 }
 
@@ -2101,6 +2274,7 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
 // rotations) runs entirely on the device; the host reads the residual history
 // every GM_CHECK iterations and solves the small least-squares problem.
 constexpr int GM_CHECK = 8;
+constexpr int PREC_REFRESH_ITS = 8;
 
 static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) {
   Workspace& w = c->ws;
@@ -2202,13 +2376,14 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   int newton = 0, gm_total = 0;
   bool converged = false;
   double last = 0.0;
-  // Newton (Sec. 4.3).  The Schwarz preconditioner of the facet solve is factorised at
-  // the first iteration of the stage and reused (GMRES still solves the current system);
-  // it is refreshed when GMRES needed many iterations.  Stopping: the increments of U
+  // Newton (Sec. 4.3).  The Schwarz preconditioner of the facet solve is kept across
+  // Newton iterations, stages and steps (GMRES always solves the current system); it is
+  // refactorised when dt a_ii changes by more than 25 % or when the extra GMRES work
+  // since the last refactorisation outweighs a new one.  Stopping: the increments of U
   // and Uhat are below rtol times the largest |U| and |Uhat|, either measured or
   // predicted from the observed contraction (theta / (1 - theta) |dz| with theta < 1/2).
   double du_prev = 0.0, dh_prev = 0.0;
-  int last_gmres = 0;
+  if (c->prec_valid && std::fabs(dt_a / c->prec_dt_a - 1.0) > 0.25) c->prec_valid = false;
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
     newton = it;
     HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
@@ -2217,7 +2392,12 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     c->timer_end(tt);
     tt = c->timer_begin(TM_FACET);
     HTRY(launch_facet_rhs(c, b));
-    if (it == 1 || last_gmres > 30) HTRY(launch_ras_factor(c));
+    if (!c->prec_valid) {
+      HTRY(launch_ras_factor(c));
+      c->prec_valid = true;
+      c->prec_fresh = true;
+      c->prec_dt_a = dt_a;
+    }
     c->timer_end(tt);
     int its = 0;
     tt = c->timer_begin(TM_GMRES);
@@ -2225,7 +2405,16 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     c->timer_end(tt);
     if (s != IMEX_OK) return s;
     gm_total += its;
-    last_gmres = its;
+    // refactorise once the GMRES iterations spent above the post-refactorisation count
+    // exceed the cost of a refactorisation (about PREC_REFRESH_ITS iterations)
+    if (c->prec_fresh) {
+      c->prec_base = its;
+      c->prec_extra = 0;
+      c->prec_fresh = false;
+    } else {
+      c->prec_extra += std::max(0, its - c->prec_base);
+      if (c->prec_extra > PREC_REFRESH_ITS) c->prec_valid = false;
+    }
     tt = c->timer_begin(TM_BACKSUB);
     HTRY(launch_backsub(c, dx, U, part));
     hipLaunchKernelGGL(facet_update_kernel, dim3(fb), dim3(256), 0, c->stream, n, dx, Uhat, part + 2 * c->n_im);

@@ -152,6 +152,26 @@ __global__ void mass_rhs_kernel(DeviceMesh m, DeviceHDG h, const double* __restr
   rhs[idx] = mass * Un[idx];
 }
 
+// Stage predictor on the implicit rows: a <- Y, Y <- a + c (a - P), P <- a
+template <int K>
+__global__ void extrapolate_implicit_kernel(DeviceHDG h, double c, double* __restrict__ Y, double* __restrict__ P) {
+  constexpr int NN = (K + 1) * (K + 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_im * 4 * NN) return;
+  const size_t idx = (size_t)h.im_list[t / (4 * NN)] * 4 * NN + t % (4 * NN);
+  const double a = Y[idx];
+  Y[idx] = a + c * (a - P[idx]);
+  P[idx] = a;
+}
+
+__global__ void extrapolate_kernel(int n, double c, double* __restrict__ Y, double* __restrict__ P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double a = Y[t];
+  Y[t] = a + c * (a - P[t]);
+  P[t] = a;
+}
+
 #define IMEX_DISPATCH_K(KV, ...)                                \
   switch (KV) {                                                 \
     case 1: { constexpr int KK = 1; __VA_ARGS__; } break;       \
@@ -173,6 +193,16 @@ hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* U
   if (c->n_im == 0) return hipSuccess;
   IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(lift_mixed_kernel<KK>, dim3(c->n_im), dim3(64), 0, c->stream, c->dmesh(),
                                            c->dhdg(), c->gas, U, Uhat, Q));
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(const imex_ctx* c, double coef, double* Y, double* Yp, double* Uhat, double* Hp) {
+  const int n = c->n_im * 4 * c->NN;
+  if (n == 0) return hipSuccess;
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(extrapolate_implicit_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
+                                           c->stream, c->dhdg(), coef, Y, Yp));
+  const int nh = c->n_hf * 4 * c->NP;
+  hipLaunchKernelGGL(extrapolate_kernel, dim3((nh + 255) / 256), dim3(256), 0, c->stream, nh, coef, Uhat, Hp);
   return hipGetLastError();
 }
 
