@@ -182,6 +182,22 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
  * the counters after reading. */
 imex_status imex_kernel_times(imex_ctx* ctx, double out[16], int reset);
 
+/* Vector-Jacobian product of the explicit residual (reverse mode of Sec. 3.3):
+ * Ubar = (dR^DG/dU)^T Rbar, with R^DG as in imex_dg_residual.  U dev (all
+ * elements); Rbar dev [e][v][n], rows of implicit elements ignored; Ubar dev out,
+ * all elements (implicit elements receive the adjoint of their interface traces).
+ * Point-wise flux Jacobians by forward-mode dual numbers, contracted with the
+ * transposed basis; deterministic (no atomics).  Errors: ENOTIMPL when explicit
+ * faces read HDG-MX mixed variables (viscous HDG-MX with an implicit region). */
+imex_status imex_vjp_dg_residual(imex_ctx* ctx, const double* U, const double* Rbar, double* Ubar);
+
+/* Reverse mode of one explicit ARK step (Sec. 4.2.2, explicit tableau of tab):
+ * given the state U_n (dev, unchanged) and the adjoint Ubar_next of U_{n+1} (dev),
+ * writes Ubar = (dU_{n+1}/dU_n)^T Ubar_next (dev out).  The stage states are
+ * recomputed from U_n.  Errors: ENOTIMPL with an implicit region. */
+imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
+                              const double* Ubar_next, double* Ubar);
+
 const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);
 void imex_destroy(imex_ctx* ctx);

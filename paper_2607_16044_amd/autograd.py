@@ -1,0 +1,84 @@
+"""torch.autograd wrappers of the engine's residual and time stepping.
+
+* DGResidual: R^DG(U) with the hand-written vector-Jacobian product as backward.
+* ARKRollout: nsteps ARK steps from U_0 returning the states at the steps listed
+  in ``record``; the backward pass keeps only every ``checkpoint``-th state from
+  the forward pass and recomputes each segment from its checkpoint, then runs
+  the step adjoints in reverse, adding the adjoints of the recorded states on
+  the way (so time-averaged functionals of the trajectory are differentiable).
+Both run entirely on the GPU through the C-ABI; the tensors are FP64 device
+tensors in the engine's [element][variable][node] layout.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+
+class DGResidual(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, engine):
+        ctx.engine = engine
+        ctx.save_for_backward(U)
+        return engine.dg_residual(U.contiguous())
+
+    @staticmethod
+    def backward(ctx, Rbar):
+        (U,) = ctx.saved_tensors
+        return ctx.engine.vjp_dg_residual(U.contiguous(), Rbar.contiguous()), None
+
+
+def dg_residual(engine, U):
+    return DGResidual.apply(U, engine)
+
+
+class ARKRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, engine, dt: float, nsteps: int, record: Sequence[int], checkpoint: int):
+        if checkpoint < 1:
+            raise ValueError("checkpoint must be >= 1")
+        record = sorted(set(int(r) for r in record))
+        if record and (record[0] < 0 or record[-1] > nsteps):
+            raise ValueError("recorded steps must lie in [0, nsteps]")
+        U = U0.detach().clone().contiguous()
+        checkpoints = {0: U.clone()}
+        out = []
+        if 0 in record:
+            out.append(U.clone())
+        for n in range(1, nsteps + 1):
+            engine.ark_step(dt, U, None)
+            if n % checkpoint == 0 and n < nsteps:
+                checkpoints[n] = U.clone()
+            if n in record:
+                out.append(U.clone())
+        ctx.engine, ctx.dt, ctx.nsteps, ctx.record, ctx.every = engine, dt, nsteps, record, checkpoint
+        ctx.checkpoints = checkpoints
+        return torch.stack(out) if out else U.new_zeros((0,) + tuple(U.shape))
+
+    @staticmethod
+    def backward(ctx, gout):
+        eng, dt, nsteps, every = ctx.engine, ctx.dt, ctx.nsteps, ctx.every
+        seed = {r: gout[i] for i, r in enumerate(ctx.record)}
+        Ubar = torch.zeros_like(ctx.checkpoints[0])
+        if nsteps in seed:
+            Ubar += seed[nsteps]
+        starts = sorted(ctx.checkpoints)
+        for c0 in reversed(starts):
+            c1 = min(c0 + every, nsteps)
+            # recompute the states U_{c0} .. U_{c1-1} of this segment
+            states = [ctx.checkpoints[c0].clone()]
+            for _ in range(c0, c1 - 1):
+                U = states[-1].clone()
+                eng.ark_step(dt, U, None)
+                states.append(U)
+            for n in range(c1 - 1, c0 - 1, -1):
+                Ubar = eng.vjp_ark_step(dt, states[n - c0], Ubar.contiguous())
+                if n in seed:
+                    Ubar += seed[n]
+        return Ubar, None, None, None, None, None
+
+
+def ark_rollout(engine, U0, dt: float, nsteps: int, record: Sequence[int], checkpoint: int = 20):
+    """States at the steps in ``record`` of an explicit ARK run from U0, differentiable in U0."""
+    return ARKRollout.apply(U0, engine, dt, nsteps, list(record), checkpoint)

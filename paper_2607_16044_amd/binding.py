@@ -24,7 +24,8 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
-           "imex_local_system", "imex_kernel_times", "imex_status_str", "imex_last_error", "imex_destroy"]
+           "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
+           "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
+    lib.imex_vjp_dg_residual.argtypes = [P, P, P, P]
+    lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
     lib.imex_status_str.argtypes = [ctypes.c_int]
     lib.imex_status_str.restype = ctypes.c_char_p
     lib.imex_last_error.argtypes = [P]
@@ -215,6 +218,20 @@ class Engine:
         tab = self.tableau.to_ctypes(Tableau)
         self._check(self.lib.imex_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat), ctypes.byref(st)))
         return st.as_dict()
+
+    def vjp_dg_residual(self, U: torch.Tensor, Rbar: torch.Tensor) -> torch.Tensor:
+        """(dR^DG/dU)^T Rbar over all elements."""
+        Ubar = torch.empty_like(U)
+        self._check(self.lib.imex_vjp_dg_residual(self.ctx, _ptr(U), _ptr(Rbar), _ptr(Ubar)))
+        return Ubar
+
+    def vjp_ark_step(self, dt: float, U: torch.Tensor, Ubar_next: torch.Tensor) -> torch.Tensor:
+        """(dU_{n+1}/dU_n)^T Ubar_next of one explicit ARK step from U_n = U (U unchanged)."""
+        Ubar = torch.empty_like(U)
+        tab = self.tableau.to_ctypes(Tableau)
+        self._check(self.lib.imex_vjp_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Ubar_next),
+                                               _ptr(Ubar)))
+        return Ubar
 
     def conservation_sums(self, U: torch.Tensor):
         out = (ctypes.c_double * 4)()

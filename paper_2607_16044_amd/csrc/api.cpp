@@ -606,6 +606,71 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   return IMEX_OK;
 }
 
+static bool mx_coupled(const imex_ctx* c) {
+  return c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
+}
+
+imex_status imex_vjp_dg_residual(imex_ctx* c, const double* U, const double* Rbar, double* Ubar) {
+  if (!c || !U || !Rbar || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (mx_coupled(c)) return fail(c, IMEX_ENOTIMPL, "residual adjoint through HDG-MX interface data");
+  HIP_TRY(c, vjp_alloc(c));
+  HIP_TRY(c, launch_dg_vjp(c, U, Rbar, Ubar));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
+// Reverse mode of the explicit ARK step (all elements explicit).  Forward:
+// Y_1 = U_n, R_j = R(Y_j), Y_{i+1} = U_n - dt M^-1 sum_{j<=i} Ae[i][j] R_j, and
+// U_{n+1} = Y_{s+1} (FSAL) or U_n - dt M^-1 sum_j be_j R_j.  Reverse, stages in
+// decreasing order: Rbar_j = -dt M^-1 (be_j Ubar_{n+1} + sum_{i>j} Ae[i-1][j-1] Ybar_i),
+// Ybar_j = (dR/dU)^T(Y_j) Rbar_j; Ubar_n = sum_i Ybar_i (+ Ubar_{n+1} if not FSAL).
+imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, const double* U,
+                              const double* Ubar_next, double* Ubar) {
+  if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  if (c->n_im > 0) return fail(c, IMEX_ENOTIMPL, "step adjoint with an implicit region");
+  HIP_TRY(c, vjp_alloc(c));
+  Workspace& w = c->ws;
+  const int s = tab->s;
+  const size_t n = (size_t)c->E * 4 * c->NN;
+  hipStream_t hs = c->stream;
+  const int nres = tab->fsal ? s : s + 1;           // stages whose residual enters the step
+  double** Y = w.vjp_y;                             // Y[0..s]: stage states Y_1..Y_{s+1}
+  double** Yb = w.vjp_y + 4;                        // adjoints of Y_1..Y_4 (Y_{s+1} at most)
+  double* Rb = w.vjp_y[8];
+  double* zero = w.vjp_y[9];
+  double* Rs[4] = {w.Rstage[0], w.Rstage[1], w.Rstage[2], w.Rstage[3]};
+  HIP_TRY(c, hipMemsetAsync(zero, 0, n * sizeof(double), hs));
+  // forward stages
+  HIP_TRY(c, hipMemcpyAsync(Y[0], U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  for (int i = 1; i <= s; ++i) {
+    imex_status st = dg_residual_async(c, Y[i - 1], nullptr, Rs[i - 1]);
+    if (st != IMEX_OK) return st;
+    double coef[4];
+    const double* R[4];
+    for (int j = 0; j < i; ++j) { coef[j] = tab->Ae[4 * i + j]; R[j] = Rs[j]; }
+    HIP_TRY(c, launch_erk_combine(c, U, i, R, coef, dt, Y[i]));
+  }
+  // reverse
+  for (int i = 0; i <= s; ++i) HIP_TRY(c, hipMemsetAsync(Yb[i], 0, n * sizeof(double), hs));
+  if (tab->fsal) HIP_TRY(c, hipMemcpyAsync(Yb[s], Ubar_next, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  for (int j = nres; j >= 1; --j) {
+    double coef[5];
+    const double* T[5];
+    int nt = 0;
+    if (!tab->fsal) { coef[nt] = tab->be[j - 1]; T[nt++] = Ubar_next; }
+    for (int i = j + 1; i <= s + 1; ++i) { coef[nt] = tab->Ae[4 * (i - 1) + (j - 1)]; T[nt++] = Yb[i - 1]; }
+    HIP_TRY(c, launch_erk_combine(c, zero, nt, T, coef, dt, Rb));     // Rb = -dt M^-1 sum coef T
+    HIP_TRY(c, launch_dg_vjp(c, Y[j - 1], Rb, Yb[j - 1]));
+  }
+  HIP_TRY(c, hipMemcpyAsync(Ubar, tab->fsal ? zero : Ubar_next, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  for (int i = 0; i <= s; ++i) HIP_TRY(c, launch_scale_copy(c, Ubar, Ubar, 1.0, Yb[i], 1.0, n));
+  HIP_TRY(c, hipStreamSynchronize(hs));
+  return IMEX_OK;
+}
+
 imex_status imex_kernel_times(imex_ctx* c, double out[16], int reset) {
   if (!c || !out) return fail(c, IMEX_EINVAL, "null argument");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -649,6 +714,14 @@ void imex_destroy(imex_ctx* c) {
   for (int r = 0; r < 8; ++r) {
     if (w.Rstage[r]) hipFree(w.Rstage[r]);
     w.Rstage[r] = nullptr;
+  }
+  for (double** p : {&w.vjp_tu, &w.vjp_tr, &w.vjp_pf, &w.vjp_pv}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  for (int r = 0; r < 10; ++r) {
+    if (w.vjp_y[r]) hipFree(w.vjp_y[r]);
+    w.vjp_y[r] = nullptr;
   }
   for (double** p : {&c->d_hx, &c->d_hy}) {
     if (*p) hipFree(*p);

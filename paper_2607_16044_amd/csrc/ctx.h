@@ -65,6 +65,12 @@ struct Workspace {
   double* Wy = nullptr;         // per window super-row: sweep vectors y_r, w_r (NB each) and z_r on H (NH)
   double* gH = nullptr;         // GMRES Hessenberg, rotations, g, residual history, scalars (device)
   double* gm = nullptr;         // GMRES basis and vectors
+  // vector-Jacobian products (allocated on first use)
+  double* vjp_tu = nullptr;     // [E][4][NQ][12] face traces of U (value, d/dxi, d/deta)
+  double* vjp_tr = nullptr;     // [E][4][NQ][12] face traces of the residual adjoint
+  double* vjp_pf = nullptr;     // [E][4][NQ][12] face-point adjoints (trace, physical gradient)
+  double* vjp_pv = nullptr;     // [E][NQV][12] volume-point adjoints
+  double* vjp_y[10] = {};       // stage states, their adjoints and scratch ([E][4][NN] each)
   double* red = nullptr;        // reduction scratch
   double* hred = nullptr;       // pinned host reduction buffer
   size_t bytes = 0;
@@ -149,5 +155,8 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
 imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
                              double* f, double* h, double* K, double* C, double* D, double* E);
 size_t hdg_workspace_bytes(const imex_ctx* c);
+// vjp.hip
+hipError_t vjp_alloc(imex_ctx* c);
+hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub);
 imex_status hdg_alloc(imex_ctx* c);
 }  // namespace imex

@@ -13,13 +13,9 @@
 //     numerical / interior-penalty face fluxes at the face points, then each
 //     thread contracts them with the test functions of one node.
 #include "ctx.h"
+#include "dg_face.h"
 
 namespace imex {
-
-__device__ __forceinline__ void face_normal(int f, double& nx, double& ny) {
-  nx = (f == 0) ? -1.0 : (f == 1 ? 1.0 : 0.0);
-  ny = (f == 2) ? -1.0 : (f == 3 ? 1.0 : 0.0);
-}
 
 // Trace of a nodal field (nv components, stride NN) and of its reference
 // derivatives at Gauss point q of local face f.
@@ -190,7 +186,6 @@ __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, D
     }
   }
   // face points
-  const double kk = (double)((K + 1) * (K + 1));
   for (int i = tid; i < ET * 4 * NQ; i += blockDim.x) {
     const int el = i / (4 * NQ), f = (i / NQ) % 4, q = i % NQ;
     const int e = sE[el];
@@ -203,69 +198,24 @@ __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, D
     face_trace<K, 4>(tb, f, q, sU[el], Uo, dxi, deta);
     const int nb = m.nbr[e * 4 + f];
     const double le = hx * hy / (2.0 * (hx + hy));
-    double s[4], gc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    double G[4][2], UN[4] = {0, 0, 0, 0}, fnn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { G[v][0] = dxi[v] * sx; G[v][1] = deta[v] * sy; }
+    int kind = DGF_FARFIELD;
+    double ln = le;
     if (nb >= 0) {
+      kind = m.imp[nb] ? DGF_INTERFACE : DGF_INTERIOR;
       const double* tn = T + (((size_t)nb * 4 + (f ^ 1)) * NQ + q) * 8;
-      double UN[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) UN[v] = tn[v];
-      dg_num_flux(Uo, UN, nx, ny, prm.lf, g, s);
-      if (g.viscous) {
-        const bool itf = m.imp[nb] != 0;
-        const double hxn = m.hx[nb], hyn = m.hy[nb];
-        const double ln = hxn * hyn / (2.0 * (hxn + hyn));
-        const double tau = prm.alpha * kk / (itf ? le : fmin(le, ln));
-        double G[4][2], Fv[4][2];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { G[v][0] = dxi[v] * sx; G[v][1] = deta[v] * sy; }
-        visc_flux(Uo, G, g, Fv);
-        double Gj[4][2], KU[4][2], KN[4][2];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { const double d = Uo[v] - UN[v]; Gj[v][0] = d * nx; Gj[v][1] = d * ny; }
-        visc_flux(Uo, Gj, g, KU);
-        visc_flux(UN, Gj, g, KN);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double fo = Fv[v][0] * nx + Fv[v][1] * ny;
-          const double fn = -tn[4 + v];                       // neighbour's F^nu . n_e
-          const double pen = 0.5 * ((KU[v][0] + KN[v][0]) * nx + (KU[v][1] + KN[v][1]) * ny);
-          s[v] += -0.5 * (fo + fn) + tau * pen;
-          if (itf) {
-            gc[v][0] = -0.5 * (KU[v][0] + KN[v][0]);
-            gc[v][1] = -0.5 * (KU[v][1] + KN[v][1]);
-          } else {
-            gc[v][0] = -0.5 * KU[v][0];
-            gc[v][1] = -0.5 * KU[v][1];
-          }
-        }
+      for (int v = 0; v < 4; ++v) {
+        UN[v] = tn[v];
+        fnn[v] = -tn[4 + v];                 // neighbour's F^nu . n_e
       }
-    } else {
-      // far field (App. B.1.1): A^+(U) U + A^-(U) U_inf, viscous terms with K(U_inf)
-      double ap[4], am[4];
-      char_apply(Uo, Uo, nx, ny, +1, g, ap);
-      double Ui[4] = {g.uinf[0], g.uinf[1], g.uinf[2], g.uinf[3]};
-      char_apply(Uo, Ui, nx, ny, -1, g, am);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) s[v] = ap[v] + am[v];
-      if (g.viscous) {
-        const double tau = prm.alpha * kk / le;
-        double G[4][2], Fv[4][2], Gj[4][2], Kf[4][2];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          G[v][0] = dxi[v] * sx; G[v][1] = deta[v] * sy;
-          const double d = Uo[v] - Ui[v];
-          Gj[v][0] = d * nx; Gj[v][1] = d * ny;
-        }
-        visc_flux(Ui, G, g, Fv);
-        visc_flux(Ui, Gj, g, Kf);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          s[v] += -(Fv[v][0] * nx + Fv[v][1] * ny) + tau * (Kf[v][0] * nx + Kf[v][1] * ny);
-          gc[v][0] = -Kf[v][0];
-          gc[v][1] = -Kf[v][1];
-        }
-      }
+      ln = m.hx[nb] * m.hy[nb] / (2.0 * (m.hx[nb] + m.hy[nb]));
     }
+    const double tau = dg_tau(prm.alpha, K, kind, le, ln);
+    double s[4], gc[4][2];
+    dg_face_point(kind, Uo, G, UN, fnn, nx, ny, tau, prm.lf, g, s, gc);
     const double w = tb.W[q] * ((f < 2) ? 0.5 * hy : 0.5 * hx);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
