@@ -112,6 +112,18 @@ typedef struct {
 imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, const imex_options* opt,
                         void* stream, imex_ctx** out);
 
+/* A batch of n_inst independent meshes of the same degree advanced together
+ * (one context over their disjoint union: every kernel runs over all instances
+ * in one launch, Newton and GMRES treat the block-diagonal union system).
+ * meshes host [n_inst]; dt_scale host [n_inst] or NULL: instance k steps with
+ * dt * dt_scale[k] wherever a call takes dt or dt_aii.  Elements are numbered
+ * instance by instance (instance k starts after the elements of instances
+ * 0..k-1), each instance lexicographically as in imex_create; HDG facets and
+ * the flags of imex_set_regions follow the same instance order.  Physics and
+ * options are shared.  Errors as imex_create, EINVAL for mixed degrees. */
+imex_status imex_create_batch(int n_inst, const imex_mesh_desc* meshes, const double* dt_scale,
+                              const imex_physics* phys, const imex_options* opt, void* stream, imex_ctx** out);
+
 /* Geometry split T = T^im U T^ex (Sec. 4, eq. union_mesh): implicit_flag[e] != 0
  * marks element e implicit.  host, n_elem bytes.  Builds the HDG facet set and
  * allocates the implicit workspaces.  Errors: EINVAL (explicit element on a wall

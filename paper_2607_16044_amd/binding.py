@@ -25,6 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
+           "imex_create_batch",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     D = ctypes.c_double
     lib.imex_create.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(Physics), ctypes.POINTER(Options), P,
                                 ctypes.POINTER(P)]
+    lib.imex_create_batch.argtypes = [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(D),
+                                      ctypes.POINTER(Physics), ctypes.POINTER(Options), P, ctypes.POINTER(P)]
     lib.imex_set_regions.argtypes = [P, ctypes.POINTER(ctypes.c_ubyte)]
     lib.imex_query_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
     lib.imex_node_coords.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
@@ -266,3 +269,98 @@ class Engine:
         self._check(self.lib.imex_local_system(self.ctx, dt_a, _ptr(rhs), _ptr(U), _ptr(Uhat), _ptr(f), _ptr(h),
                                                _ptr(K), _ptr(C), _ptr(D), _ptr(E)))
         return f, h, K, C, D, E
+
+
+class BatchEngine(Engine):
+    """Several independent meshes of one degree in one context (their disjoint union).
+
+    Instance k steps with dt * dt_scale[k], dt_scale[k] = wl_k.dt / max_j wl_j.dt, so one
+    ark_step(self.dt, ...) advances every instance with its own time step.  Physics,
+    fluxes and tableau are shared (taken from the first workload)."""
+
+    def __init__(self, wls, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
+                 gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
+                 device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the engine runs only on the GPU")
+        if not wls or len({w.degree for w in wls}) != 1:
+            raise ValueError("a batch needs workloads of one degree")
+        self.lib = load_library()
+        self.wls = list(wls)
+        self.wl = wl = self.wls[0]
+        self.device = torch.device("cuda") if device is None else device
+        self._grids = [(np.ascontiguousarray(w.xgrid, dtype=np.float64), np.ascontiguousarray(w.ygrid, dtype=np.float64))
+                       for w in self.wls]
+        meshes = (MeshDesc * len(self.wls))()
+        for i, (w, (xg, yg)) in enumerate(zip(self.wls, self._grids)):
+            meshes[i] = MeshDesc(w.nx, w.ny, xg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 yg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), (ctypes.c_int * 4)(*w.bc),
+                                 w.degree)
+        self.dt = max(w.dt for w in self.wls)
+        scale = np.array([w.dt / self.dt for w in self.wls], dtype=np.float64)
+        phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
+        opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.imex_create_batch(len(self.wls), meshes, scale.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.byref(phys), ctypes.byref(opt),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != 0:
+            raise IMEXError(st, self.lib.imex_last_error(None).decode())
+        self.ctx = ctx
+        self.offsets = np.cumsum([0] + [w.nx * w.ny for w in self.wls])
+        self.set_regions(np.concatenate([w.implicit_flags() for w in self.wls]))
+        self.tableau = tableaux.get(wl.tableau)
+
+    def initial_state(self) -> torch.Tensor:
+        X, Y = self.node_coords()
+        nn = X.shape[1]
+        U = np.zeros((X.shape[0], 4, nn))
+        for k, w in enumerate(self.wls):
+            a, b = self.offsets[k], self.offsets[k + 1]
+            elem = np.repeat(np.arange(b - a)[:, None], nn, axis=1)
+            node = np.repeat(np.arange(nn)[None, :], b - a, axis=0)
+            U[a:b] = np.moveaxis(w.ic(X[a:b], Y[a:b], elem, node), 0, 1)
+        return torch.tensor(U, dtype=torch.float64, device=self.device)
+
+    def split(self, U: torch.Tensor):
+        """Per-instance views of a batch state."""
+        return [U[self.offsets[k]:self.offsets[k + 1]] for k in range(len(self.wls))]
+
+
+class Ensemble:
+    """Many independent workloads of mixed degrees: one BatchEngine per degree."""
+
+    def __init__(self, wls, precision: int = 0, **kw):
+        self.wls = list(wls)
+        self.groups = []
+        for k in sorted({w.degree for w in self.wls}):
+            idx = [i for i, w in enumerate(self.wls) if w.degree == k]
+            self.groups.append((idx, BatchEngine([self.wls[i] for i in idx], precision=precision, **kw)))
+        self.n_dof = sum(w.n_dof for w in self.wls)
+
+    def initial_state(self):
+        U = [eng.initial_state() for _, eng in self.groups]
+        H = [eng.init_facets(u) for u, (_, eng) in zip(U, self.groups)]
+        return U, H
+
+    def step(self, U, H):
+        """One ARK step of every instance (each with its own dt); returns summed solver counts."""
+        newton = gmres = 0
+        for u, h, (_, eng) in zip(U, H, self.groups):
+            st = eng.ark_step(eng.dt, u, h)
+            newton += st["newton_its"]
+            gmres += st["gmres_its"]
+        return newton, gmres
+
+    def instance_states(self, U):
+        out = [None] * len(self.wls)
+        for u, (idx, eng) in zip(U, self.groups):
+            for i, ui in zip(idx, eng.split(u)):
+                out[i] = ui
+        return out
+
+    def close(self):
+        for _, eng in self.groups:
+            eng.close()

@@ -181,10 +181,7 @@ const char* imex_status_str(imex_status s) {
 
 const char* imex_last_error(const imex_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, const imex_options* opt, void* stream,
-                        imex_ctx** out) {
-  if (!mesh || !phys || !opt || !out) return fail(nullptr, IMEX_EINVAL, "null argument");
-  *out = nullptr;
+static imex_status check_mesh(const imex_mesh_desc* mesh) {
   if (mesh->nx < 1 || mesh->ny < 1 || !mesh->xgrid || !mesh->ygrid)
     return fail(nullptr, IMEX_EINVAL, "mesh needs nx, ny >= 1 and both grids");
   if (mesh->degree < 1 || mesh->degree > 4) return fail(nullptr, IMEX_EINVAL, "degree must be in 1..4");
@@ -198,30 +195,42 @@ imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, co
     if (!(mesh->xgrid[i + 1] > mesh->xgrid[i])) return fail(nullptr, IMEX_EINVAL, "xgrid not increasing");
   for (int j = 0; j < mesh->ny; ++j)
     if (!(mesh->ygrid[j + 1] > mesh->ygrid[j])) return fail(nullptr, IMEX_EINVAL, "ygrid not increasing");
+  return IMEX_OK;
+}
+
+// One context over n structured meshes of the same degree (their disjoint union).
+static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double* dt_scale,
+                              const imex_physics* phys, const imex_options* opt, void* stream, imex_ctx** out) {
+  if (!meshes || !phys || !opt || !out || n < 1) return fail(nullptr, IMEX_EINVAL, "null argument or no mesh");
+  *out = nullptr;
+  long long Etot = 0;
+  for (int k = 0; k < n; ++k) {
+    imex_status st = check_mesh(&meshes[k]);
+    if (st != IMEX_OK) return st;
+    if (meshes[k].degree != meshes[0].degree) return fail(nullptr, IMEX_EINVAL, "all meshes need the same degree");
+    if (dt_scale && !(dt_scale[k] > 0.0)) return fail(nullptr, IMEX_EINVAL, "time-step scales must be positive");
+    Etot += (long long)meshes[k].nx * meshes[k].ny;
+  }
+  if (Etot > (1LL << 28)) return fail(nullptr, IMEX_EINVAL, "too many elements");
   if (!(phys->gamma > 1.0) || !(phys->R > 0.0) || phys->mu < 0.0 || !(phys->Pr > 0.0))
     return fail(nullptr, IMEX_EINVAL, "bad gas constants");
   if (opt->hdg_variant != IMEX_HDG_IP && opt->hdg_variant != IMEX_HDG_MX)
     return fail(nullptr, IMEX_EINVAL, "hdg_variant");
   if (opt->precision != IMEX_FP64 && opt->precision != IMEX_FP32_REFINE)
     return fail(nullptr, IMEX_EINVAL, "precision");
-  if (opt->newton_maxit < 1 || opt->gmres_restart < 1 || opt->gmres_restart > 64 || opt->gmres_maxit < 1 || !(opt->newton_rtol > 0.0) ||
-      !(opt->gmres_rtol > 0.0))
+  if (opt->newton_maxit < 1 || opt->gmres_restart < 1 || opt->gmres_restart > 64 || opt->gmres_maxit < 1 ||
+      !(opt->newton_rtol > 0.0) || !(opt->gmres_rtol > 0.0))
     return fail(nullptr, IMEX_EINVAL, "solver options");
 
   imex_ctx* c = new (std::nothrow) imex_ctx();
   if (!c) return fail(nullptr, IMEX_ENOMEM, "host allocation");
   hipGetDevice(&c->device);
   c->stream = static_cast<hipStream_t>(stream);
-  c->nx = mesh->nx;
-  c->ny = mesh->ny;
-  c->E = c->nx * c->ny;
-  c->K = mesh->degree;
+  c->E = (int)Etot;
+  c->K = meshes[0].degree;
   c->NP = c->K + 1;
   c->NQ = (3 * c->K + 2) / 2;
   c->NN = c->NP * c->NP;
-  std::memcpy(c->bc, mesh->bc, sizeof(c->bc));
-  c->xg.assign(mesh->xgrid, mesh->xgrid + c->nx + 1);
-  c->yg.assign(mesh->ygrid, mesh->ygrid + c->ny + 1);
   c->opt = *opt;
   Gas& g = c->gas;
   g.gamma = phys->gamma;
@@ -236,37 +245,53 @@ imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, co
   for (int v = 0; v < 4; ++v) g.uinf[v] = phys->u_inf[v];
   build_table(c->K, c->tab);
 
-  // geometry and neighbours
-  const int nx = c->nx, ny = c->ny, E = c->E;
-  std::vector<double> hx(E), hy(E);
+  // geometry and neighbours, instance by instance
+  const int E = c->E;
+  std::vector<double> hx(E), hy(E), dts(E, 1.0);
   c->nbr.assign(4 * E, -1);
   c->bcf.assign(4 * E, -1);
-  const bool px = mesh->bc[0] == IMEX_BC_PERIODIC, py = mesh->bc[2] == IMEX_BC_PERIODIC;
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) {
-      const int e = i + nx * j;
-      hx[e] = c->xg[i + 1] - c->xg[i];
-      hy[e] = c->yg[j + 1] - c->yg[j];
-      const int ci[4] = {i - 1, i + 1, i, i};
-      const int cj[4] = {j, j, j - 1, j + 1};
-      for (int f = 0; f < 4; ++f) {
-        int a = ci[f], b = cj[f];
-        const bool in = a >= 0 && a < nx && b >= 0 && b < ny;
-        if (!in) {
-          if (f < 2 && px) a = (a + nx) % nx;
-          else if (f >= 2 && py) b = (b + ny) % ny;
-          else { c->bcf[4 * e + f] = mesh->bc[f]; continue; }
+  int off = 0;
+  for (int k = 0; k < n; ++k) {
+    const imex_mesh_desc* mesh = &meshes[k];
+    Inst in;
+    in.nx = mesh->nx;
+    in.ny = mesh->ny;
+    in.e_off = off;
+    in.dt_scale = dt_scale ? dt_scale[k] : 1.0;
+    std::memcpy(in.bc, mesh->bc, sizeof(in.bc));
+    in.xg.assign(mesh->xgrid, mesh->xgrid + in.nx + 1);
+    in.yg.assign(mesh->ygrid, mesh->ygrid + in.ny + 1);
+    const int nx = in.nx, ny = in.ny;
+    const bool px = mesh->bc[0] == IMEX_BC_PERIODIC, py = mesh->bc[2] == IMEX_BC_PERIODIC;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int e = off + i + nx * j;
+        hx[e] = in.xg[i + 1] - in.xg[i];
+        hy[e] = in.yg[j + 1] - in.yg[j];
+        dts[e] = in.dt_scale;
+        const int ci[4] = {i - 1, i + 1, i, i};
+        const int cj[4] = {j, j, j - 1, j + 1};
+        for (int f = 0; f < 4; ++f) {
+          int a = ci[f], b = cj[f];
+          const bool inside = a >= 0 && a < nx && b >= 0 && b < ny;
+          if (!inside) {
+            if (f < 2 && px) a = (a + nx) % nx;
+            else if (f >= 2 && py) b = (b + ny) % ny;
+            else { c->bcf[4 * e + f] = mesh->bc[f]; continue; }
+          }
+          c->nbr[4 * e + f] = off + a + nx * b;
         }
-        c->nbr[4 * e + f] = a + nx * b;
       }
-    }
+    off += nx * ny;
+    c->inst.push_back(std::move(in));
+  }
   c->imp.assign(E, 0);
   c->err.clear();
   hipStream_t s = c->stream;
   hipError_t he = hipSuccess;
   if ((he = upload(&c->d_hx, hx, s)) != hipSuccess || (he = upload(&c->d_hy, hy, s)) != hipSuccess ||
       (he = upload(&c->d_nbr, c->nbr, s)) != hipSuccess || (he = upload(&c->d_bcf, c->bcf, s)) != hipSuccess ||
-      (he = upload(&c->d_imp, c->imp, s)) != hipSuccess) {
+      (he = upload(&c->d_imp, c->imp, s)) != hipSuccess || (dt_scale && (he = upload(&c->d_dts, dts, s)) != hipSuccess)) {
     imex_destroy(c);
     return fail(nullptr, IMEX_ENOMEM, std::string("device tables: ") + hipGetErrorString(he));
   }
@@ -288,14 +313,24 @@ imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, co
     imex_destroy(c);
     return fail(nullptr, IMEX_ENOMEM, std::string("workspace: ") + hipGetErrorString(he));
   }
-  w.bytes = (size_t)E * 4 * c->NQ * 8 * 8 + (size_t)E * 5 * c->NN * 8 + 11 * es * 8;
+  w.bytes = (size_t)E * 4 * c->NQ * 8 * 8 + (size_t)E * 5 * c->NN * 8 + 12 * es * 8;
   *out = c;
   return IMEX_OK;
 }
 
+imex_status imex_create(const imex_mesh_desc* mesh, const imex_physics* phys, const imex_options* opt, void* stream,
+                        imex_ctx** out) {
+  return create_ctx(1, mesh, nullptr, phys, opt, stream, out);
+}
+
+imex_status imex_create_batch(int n_inst, const imex_mesh_desc* meshes, const double* dt_scale,
+                              const imex_physics* phys, const imex_options* opt, void* stream, imex_ctx** out) {
+  return create_ctx(n_inst, meshes, dt_scale, phys, opt, stream, out);
+}
+
 imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   if (!c || !flag) return fail(c, IMEX_EINVAL, "null argument");
-  const int E = c->E, nx = c->nx, ny = c->ny;
+  const int E = c->E;
   c->imp.assign(flag, flag + E);
   for (int e = 0; e < E; ++e) c->imp[e] = c->imp[e] ? 1 : 0;
   c->im_list.clear();
@@ -309,8 +344,8 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   c->n_ex = (int)c->ex_list.size();
   std::vector<int> im_pos(E, -1);
   for (int p = 0; p < c->n_im; ++p) im_pos[c->im_list[p]] = p;
-  // global facets: vertical (x = x_i) then horizontal (y = y_j); keep those touching an implicit element
-  const bool px = c->bc[0] == IMEX_BC_PERIODIC, py = c->bc[2] == IMEX_BC_PERIODIC;
+  // HDG facets of each instance: vertical (x = x_i) then horizontal (y = y_j), keeping those
+  // touching an implicit element; ids continue over the instances
   c->hf_side.clear();
   c->hf_face.clear();
   c->hf_elem.clear();
@@ -328,40 +363,55 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       if (e >= 0 && im_pos[e] >= 0) c->efacet[4 * im_pos[e] + ff[s]] = id;
     }
   };
-  const int nvx = px ? nx : nx + 1, nhy = py ? ny : ny + 1;
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nvx; ++i) {
-      const int eR = i < nx ? i + nx * j : -1;
-      const int eL = i > 0 ? (i - 1) + nx * j : (px ? (nx - 1) + nx * j : -1);
-      add(eL, 1, eR, 0);
-    }
-  for (int j = 0; j < nhy; ++j)
-    for (int i = 0; i < nx; ++i) {
-      const int eR = j < ny ? i + nx * j : -1;
-      const int eL = j > 0 ? i + nx * (j - 1) : (py ? i + nx * (ny - 1) : -1);
-      add(eL, 3, eR, 2);
-    }
+  std::vector<int> hf_base;
+  for (const Inst& in : c->inst) {
+    hf_base.push_back((int)(c->hf_side.size() / 2));
+    const int nx = in.nx, ny = in.ny, o = in.e_off;
+    const bool px = in.bc[0] == IMEX_BC_PERIODIC, py = in.bc[2] == IMEX_BC_PERIODIC;
+    const int nvx = px ? nx : nx + 1, nhy = py ? ny : ny + 1;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nvx; ++i) {
+        const int eR = i < nx ? o + i + nx * j : -1;
+        const int eL = i > 0 ? o + (i - 1) + nx * j : (px ? o + (nx - 1) + nx * j : -1);
+        add(eL, 1, eR, 0);
+      }
+    for (int j = 0; j < nhy; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int eR = j < ny ? o + i + nx * j : -1;
+        const int eL = j > 0 ? o + i + nx * (j - 1) : (py ? o + i + nx * (ny - 1) : -1);
+        add(eL, 3, eR, 2);
+      }
+  }
   c->n_hf = (int)(c->hf_side.size() / 2);
-  // Two-column Schwarz windows for the facet preconditioner.  Window w covers element
-  // columns c0 = w and c1 = w + 1 (wrapping when periodic in x); its unknowns are the
+  // Two-column Schwarz windows for the facet preconditioner, per instance.  Window w covers
+  // element columns c0 = w and c1 = w + 1 (wrapping when periodic in x); its unknowns are the
   // HDG facets of those columns, grouped in super-rows r (element rows) with slots
   // [H(c0, r), H(c1, r), V(x_c0, r), V(x_c0+1, r), V(x_c1+1, r)], plus a last super-row
   // holding the top horizontal facets.  A window writes only the facets it owns (column
   // c0's horizontal facets and left vertical facets; the last window of a non-periodic
   // mesh also owns its second column), so every facet is written exactly once.
-  {
+  c->win_off.assign(1, 0);
+  c->win_slot.clear();
+  c->win_own.clear();
+  c->n_win = 0;
+  std::vector<int> owned(c->n_hf, 0);
+  for (size_t k = 0; k < c->inst.size(); ++k) {
+    const Inst& in = c->inst[k];
+    const int nx = in.nx, ny = in.ny, o = in.e_off;
+    const bool px = in.bc[0] == IMEX_BC_PERIODIC, py = in.bc[2] == IMEX_BC_PERIODIC;
+    const int nvx = px ? nx : nx + 1, nhy = py ? ny : ny + 1;
     std::vector<int> vid((nx + 1) * ny, -1), hid(nx * (ny + 1), -1);
-    int id = 0;
+    int id = hf_base[k];
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nvx; ++i) {
-        const int eR = i < nx ? i + nx * j : -1;
-        const int eL = i > 0 ? (i - 1) + nx * j : (px ? (nx - 1) + nx * j : -1);
+        const int eR = i < nx ? o + i + nx * j : -1;
+        const int eL = i > 0 ? o + (i - 1) + nx * j : (px ? o + (nx - 1) + nx * j : -1);
         if ((eL >= 0 && c->imp[eL]) || (eR >= 0 && c->imp[eR])) vid[i + (nx + 1) * j] = id++;
       }
     for (int j = 0; j < nhy; ++j)
       for (int i = 0; i < nx; ++i) {
-        const int eR = j < ny ? i + nx * j : -1;
-        const int eL = j > 0 ? i + nx * (j - 1) : (py ? i + nx * (ny - 1) : -1);
+        const int eR = j < ny ? o + i + nx * j : -1;
+        const int eL = j > 0 ? o + i + nx * (j - 1) : (py ? o + i + nx * (ny - 1) : -1);
         if ((eL >= 0 && c->imp[eL]) || (eR >= 0 && c->imp[eR])) hid[i + nx * j] = id++;
       }
     auto V = [&](int xi, int j) -> int {          // vertical facet at x_xi, row j
@@ -375,10 +425,6 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       if (j > (py ? ny - 1 : ny)) return -1;
       return hid[i + nx * j];
     };
-    c->win_off.assign(1, 0);
-    c->win_slot.clear();
-    c->win_own.clear();
-    std::vector<int> owned(c->n_hf, 0);
     const int nwin = (nx == 1) ? 1 : (px ? nx : nx - 1);
     for (int w = 0; w < nwin; ++w) {
       const int c0 = w;
@@ -387,7 +433,7 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       int rlo = ny, rhi = -1;
       for (int j = 0; j < ny; ++j)
         for (int col : {c0, c1})
-          if (col >= 0 && c->imp[col + nx * j]) { rlo = std::min(rlo, j); rhi = std::max(rhi, j); }
+          if (col >= 0 && c->imp[o + col + nx * j]) { rlo = std::min(rlo, j); rhi = std::max(rhi, j); }
       if (rhi < 0) { c->win_off.push_back((int)(c->win_slot.size() / 5)); continue; }
       for (int r = rlo; r <= rhi + 1; ++r) {
         int f[5] = {H(c0, r), c1 >= 0 ? H(c1, r) : -1, -1, -1, -1};
@@ -409,21 +455,21 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       }
       c->win_off.push_back((int)(c->win_slot.size() / 5));
     }
-    c->n_win = nwin;
-    c->n_superrows = (int)(c->win_slot.size() / 5);
-    // facets of implicit regions with ragged column extents: first occurrence owns them
-    for (size_t q = 0; q < c->win_slot.size(); ++q) {
-      const int f = c->win_slot[q];
-      if (f >= 0 && !owned[f]) { owned[f] = 1; c->win_own[q] = 1; }
-    }
-    for (int f = 0; f < c->n_hf; ++f)
-      if (!owned[f]) return fail(c, IMEX_EINVAL, "facet preconditioner windows do not cover every facet");
-    // per super-row: bit 0 = has a predecessor, bit 1 = has a successor in its window
-    c->sr_flags.assign(c->n_superrows, 0);
-    for (int w = 0; w < c->n_win; ++w)
-      for (int g = c->win_off[w]; g < c->win_off[w + 1]; ++g)
-        c->sr_flags[g] = (g > c->win_off[w] ? 1 : 0) | (g + 1 < c->win_off[w + 1] ? 2 : 0);
+    c->n_win += nwin;
   }
+  c->n_superrows = (int)(c->win_slot.size() / 5);
+  // facets of implicit regions with ragged column extents: first occurrence owns them
+  for (size_t q = 0; q < c->win_slot.size(); ++q) {
+    const int f = c->win_slot[q];
+    if (f >= 0 && !owned[f]) { owned[f] = 1; c->win_own[q] = 1; }
+  }
+  for (int f = 0; f < c->n_hf; ++f)
+    if (!owned[f]) return fail(c, IMEX_EINVAL, "facet preconditioner windows do not cover every facet");
+  // per super-row: bit 0 = has a predecessor, bit 1 = has a successor in its window
+  c->sr_flags.assign(c->n_superrows, 0);
+  for (int w = 0; w < c->n_win; ++w)
+    for (int g = c->win_off[w]; g < c->win_off[w + 1]; ++g)
+      c->sr_flags[g] = (g > c->win_off[w] ? 1 : 0) | (g + 1 < c->win_off[w + 1] ? 2 : 0);
   c->face_kind.assign(4 * c->n_im, 0);
   for (int p = 0; p < c->n_im; ++p) {
     const int e = c->im_list[p];
@@ -474,15 +520,16 @@ imex_status imex_node_coords(const imex_ctx* c, double* x, double* y) {
   if (!c || !x || !y) return IMEX_EINVAL;
   double nodes[MAXNP], nw[MAXNP];
   gauss_legendre(c->NP, nodes, nw);
-  for (int j = 0; j < c->ny; ++j)
-    for (int i = 0; i < c->nx; ++i) {
-      const int e = i + c->nx * j;
-      const double hx = c->xg[i + 1] - c->xg[i], hy = c->yg[j + 1] - c->yg[j];
-      for (int n = 0; n < c->NN; ++n) {
-        x[(size_t)e * c->NN + n] = c->xg[i] + 0.5 * (nodes[n % c->NP] + 1.0) * hx;
-        y[(size_t)e * c->NN + n] = c->yg[j] + 0.5 * (nodes[n / c->NP] + 1.0) * hy;
+  for (const Inst& in : c->inst)
+    for (int j = 0; j < in.ny; ++j)
+      for (int i = 0; i < in.nx; ++i) {
+        const int e = in.e_off + i + in.nx * j;
+        const double hx = in.xg[i + 1] - in.xg[i], hy = in.yg[j + 1] - in.yg[j];
+        for (int n = 0; n < c->NN; ++n) {
+          x[(size_t)e * c->NN + n] = in.xg[i] + 0.5 * (nodes[n % c->NP] + 1.0) * hx;
+          y[(size_t)e * c->NN + n] = in.yg[j] + 0.5 * (nodes[n / c->NP] + 1.0) * hy;
+        }
       }
-    }
   return IMEX_OK;
 }
 
@@ -570,8 +617,7 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
       for (int j = 0; j < i - 1; ++j) { ch[j] = dt * tab->Ai[3 * (i - 1) + j]; Rh[j] = Rhdg[j]; }
       // rhs = M U_n - dt sum_{j<i} a_ij R^HDG_j
       HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
-      for (int j = 0; j < i - 1; ++j)
-        HIP_TRY(c, launch_scale_copy(c, w.rhs, w.rhs, 1.0, Rh[j], -ch[j], n));
+      for (int j = 0; j < i - 1; ++j) HIP_TRY(c, launch_rhs_accumulate(c, -ch[j], Rh[j], w.rhs));
       // Newton initial guess (the converged root does not depend on it): linear
       // extrapolation in stage time from the two previous implicit stage values
       if (i >= 2 && ci[i - 1] - ci[i - 2] > 1e-12 * dt)
@@ -723,7 +769,7 @@ void imex_destroy(imex_ctx* c) {
     if (w.vjp_y[r]) hipFree(w.vjp_y[r]);
     w.vjp_y[r] = nullptr;
   }
-  for (double** p : {&c->d_hx, &c->d_hy}) {
+  for (double** p : {&c->d_hx, &c->d_hy, &c->d_dts}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

@@ -14,14 +14,27 @@ namespace imex {
 enum FaceKind { FK_INTERIOR = 0, FK_INTERFACE = 1, FK_FARFIELD = 2, FK_WALL = 3 };
 
 struct DeviceMesh {
-  int E, nx, ny, K;
+  int E, K;
   const double* hx;         // [E]
   const double* hy;         // [E]
   const int* nbr;           // [E][4] neighbour element or -1
   const int* bcf;           // [E][4] boundary type where nbr == -1
   const unsigned char* imp; // [E]
   const BasisTable* tab;
+  const double* dts;        // [E] time-step scale of each element's instance, or null (all 1)
 };
+
+// one structured mesh of a (possibly multi-instance) context; elements e_off ..
+// e_off + nx ny - 1, element e_off + i + nx j covers [xg_i, xg_i+1] x [yg_j, yg_j+1]
+struct Inst {
+  int nx = 0, ny = 0, e_off = 0;
+  int bc[4] = {0, 0, 0, 0};
+  double dt_scale = 1.0;
+  std::vector<double> xg, yg;
+};
+
+// per-element time-step factor (1 without a scale table)
+__device__ __forceinline__ double elem_dt(const DeviceMesh& m, int e) { return m.dts ? m.dts[e] : 1.0; }
 
 // Implicit-region tables (device)
 struct DeviceHDG {
@@ -81,9 +94,8 @@ struct Workspace {
 struct imex_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int nx = 0, ny = 0, E = 0, K = 0, NP = 0, NQ = 0, NN = 0;
-  int bc[4] = {0, 0, 0, 0};
-  std::vector<double> xg, yg;
+  int E = 0, K = 0, NP = 0, NQ = 0, NN = 0;
+  std::vector<imex::Inst> inst;     // the structured meshes (one, or a batch of disjoint ones)
   imex::Gas gas{};
   imex_options opt{};
   imex::BasisTable tab{};
@@ -102,7 +114,7 @@ struct imex_ctx {
   int prec_extra = 0;           // GMRES iterations above prec_base since then
   double prec_dt_a = 0.0;       // dt a_ii of the factorised system
   // device copies
-  double *d_hx = nullptr, *d_hy = nullptr;
+  double *d_hx = nullptr, *d_hy = nullptr, *d_dts = nullptr;
   int *d_nbr = nullptr, *d_bcf = nullptr;
   unsigned char* d_imp = nullptr;
   imex::BasisTable* d_tab = nullptr;
@@ -122,7 +134,7 @@ struct imex_ctx {
   void timer_end(int idx);
   void timers_resolve();
   imex::DeviceMesh dmesh() const {
-    return imex::DeviceMesh{E, nx, ny, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab};
+    return imex::DeviceMesh{E, K, d_hx, d_hy, d_nbr, d_bcf, d_imp, d_tab, d_dts};
   }
   imex::DeviceHDG dhdg() const {
     return imex::DeviceHDG{n_im,      n_hf,  d_im_list, d_face_kind, d_efacet,    d_hf_side, d_hf_face,
@@ -149,6 +161,7 @@ hipError_t launch_scale_copy(const imex_ctx* c, const double* src, double* dst, 
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);
+hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, double* rhs);
 hipError_t launch_extrapolate(const imex_ctx* c, double coef, double* Y, double* Yp, double* Uhat, double* Hp);
 imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double* U, double* Uhat, double* R_out,
                             imex_stats* st);

@@ -289,7 +289,7 @@ __global__ void erk_combine_kernel(DeviceMesh m, const int* __restrict__ ex_list
   const size_t idx = (size_t)e * 4 * NN + r;
   double acc = 0.0;
   for (int j = 0; j < terms.n; ++j) acc += terms.c[j] * terms.R[j][idx];
-  Y[idx] = Un[idx] - dt * acc / mass;
+  Y[idx] = Un[idx] - dt * elem_dt(m, e) * acc / mass;
 }
 
 // per-block partial sums of int_T U_v over all elements

@@ -227,23 +227,27 @@ template <int K, bool MX> struct AsmShared {
   double Qf[MX ? 4 : 1][S::NQ][5];
 };
 
-// Point-wise record of one HDG-MX element written by the assembly kernel in
-// point mode and read by the block contraction: d(volume flux)/d(U, Q) at the
-// volume points, d(s, t)/d(U, Uhat, Q) at the face points and the derivatives
-// of the lifted primitives (u, v, theta) with respect to U (volume points) and
-// Uhat (face points).
-template <int K> struct MxRec {
+// Point-wise record of one element written by the assembly kernel in point mode
+// and read by the block contraction: d(volume flux)/d(U, Q | grad U) at the
+// volume points, d(face outputs)/d(U, Uhat, Q | grad U) at the face points and,
+// for HDG-MX, the derivatives of the lifted primitives (u, v, theta) with
+// respect to U (volume points) and Uhat (face points).  Face outputs: HDG-MX
+// (s, t); HDG-IP (s, coefficient of grad V, t).
+template <int K, bool MX> struct PointRec {
   static constexpr int NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
-  static constexpr int JV = 0;                        // [NQV][8][9]
-  static constexpr int JF = JV + NQV * 8 * 9;         // [4][NQ][8][13]
-  static constexpr int JL = JF + 4 * NQ * 8 * 13;     // [NQV][3][4]
-  static constexpr int JLF = JL + NQV * 12;           // [4][NQ][3][4]
-  static constexpr int SIZE = JLF + 4 * NQ * 12;
+  static constexpr int NIV = MX ? 9 : 12, NOF = MX ? 8 : 16, NIF = MX ? 13 : 16;
+  static constexpr int TO = MX ? 4 : 12;              // t rows among the face outputs
+  static constexpr int JV = 0;                        // [NQV][8][NIV]
+  static constexpr int JF = JV + NQV * 8 * NIV;       // [4][NQ][NOF][NIF]
+  static constexpr int JL = JF + 4 * NQ * NOF * NIF;  // [NQV][3][4]      (HDG-MX)
+  static constexpr int JLF = JL + (MX ? NQV * 12 : 0);// [4][NQ][3][4]    (HDG-MX)
+  static constexpr int SIZE = JLF + (MX ? 4 * NQ * 12 : 0);
 };
+template <int K> using MxRec = PointRec<K, true>;
 
 // DUMP = false: residual rows and every Jacobian block contracted here.
-// DUMP = true (HDG-MX): residual rows here, the point-wise Jacobians go to rec
-// for hdg_mx_contract_kernel.
+// DUMP = true (HDG-MX, inviscid HDG-IP): residual rows here, the point-wise
+// Jacobians go to rec for hdg_contract_kernel.
 template <int K, bool MX, bool DUMP, class T>
 __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
@@ -271,6 +275,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   const BasisTable& tb = sh.tb;
   const double hx = m.hx[e], hy = m.hy[e];
   const double sx = 2.0 / hx, sy = 2.0 / hy, jac = 0.25 * hx * hy;
+  const double dta = prm.dt_a * elem_dt(m, e);      // dt a_ii of this element's instance
   const double le = hx * hy / (2.0 * (hx + hy));
   const double tau = prm.alpha * (double)((K + 1) * (K + 1)) / le;
   // ---- point values -----------------------------------------------------
@@ -418,7 +423,10 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
     __syncthreads();
   }
   // ---- point-wise outputs and Jacobians (dual numbers, 4 seeds per pass) ----
-  constexpr int CV = (NIV + 3) / 4, CF = (NIF + 3) / 4, CL = 1;
+  constexpr int CV0 = (NIV + 3) / 4, CF0 = (NIF + 3) / 4, CL = 1;
+  // inviscid HDG-IP: the outputs do not depend on grad U, only the chunks of U (and Uhat)
+  const bool full = MX || g.viscous || !DUMP;
+  const int CV = full ? CV0 : 1, CF = full ? CF0 : 2;
   const int ntask = NQV * CV + 4 * NQ * CF + (MX ? (NQV + 4 * NQ) * CL : 0);
   for (int task = tid; task < (prm.jacobian ? ntask : NQV + 4 * NQ); task += nt) {
     if (!prm.jacobian) {
@@ -599,7 +607,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       const double mass = tb.NW[a] * tb.NW[b] * jac;
       const size_t gi = (size_t)e * NU + r;
       if (Rh) Rh[gi] = acc;
-      bp[(size_t)r * NC + NC - 1] = static_cast<T>(mass * sh.U[r] + prm.dt_a * acc - (rhs ? rhs[gi] : 0.0));
+      bp[(size_t)r * NC + NC - 1] = static_cast<T>(mass * sh.U[r] + dta * acc - (rhs ? rhs[gi] : 0.0));
     } else {
       const int rr = r - NU, f = rr / NFF, v = (rr % NFF) / NP, mm = rr % NP;
       const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
@@ -614,17 +622,18 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   }
   if (!prm.jacobian) return;
   if constexpr (DUMP) {
-    static_assert(MX, "point records are HDG-MX only");
-    using R = MxRec<K>;
+    using R = PointRec<K, MX>;
     double* rp = rec + (size_t)p * R::SIZE;
     const double* jv = &sh.JV[0][0][0];
     const double* jf = &sh.JF[0][0][0][0];
-    const double* jl = &sh.JL[0][0][0];
-    const double* jlf = &sh.JLF[0][0][0][0];
     for (int i = tid; i < R::JF - R::JV; i += nt) rp[R::JV + i] = jv[i];
     for (int i = tid; i < R::JL - R::JF; i += nt) rp[R::JF + i] = jf[i];
-    for (int i = tid; i < R::JLF - R::JL; i += nt) rp[R::JL + i] = jl[i];
-    for (int i = tid; i < R::SIZE - R::JLF; i += nt) rp[R::JLF + i] = jlf[i];
+    if constexpr (MX) {
+      const double* jl = &sh.JL[0][0][0];
+      const double* jlf = &sh.JLF[0][0][0][0];
+      for (int i = tid; i < R::JLF - R::JL; i += nt) rp[R::JL + i] = jl[i];
+      for (int i = tid; i < R::SIZE - R::JLF; i += nt) rp[R::JLF + i] = jlf[i];
+    }
     return;
   } else {
   // ---- Jacobian blocks ---------------------------------------------------------
@@ -673,7 +682,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         acc += w * ph * d;
       }
     }
-    bp[(size_t)row * NC + col] = static_cast<T>(prm.dt_a * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0));
+    bp[(size_t)row * NC + col] = static_cast<T>(dta * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0));
   }
   // C = dt_a dR/dUhat (each column lives on one face)
   for (int idx = tid; idx < NU * NF; idx += nt) {
@@ -689,7 +698,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       acc += w * ph * sh.JF[f][q][v][UHI + v2];
       if (!MX) acc += w * (pxi * sx * sh.JF[f][q][4 + 2 * v][UHI + v2] + peta * sy * sh.JF[f][q][5 + 2 * v][UHI + v2]);
     }
-    bp[(size_t)row * NC + NU + col] = static_cast<T>(prm.dt_a * acc);
+    bp[(size_t)row * NC + NU + col] = static_cast<T>(dta * acc);
   }
   // D = dh/dU, E = dh/dUhat (E block-diagonal over faces before the mixed elimination)
   for (int idx = tid; idx < NF * NU; idx += nt) {
@@ -747,7 +756,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
           acc += tb.W[q] * wl * ph * ph2 * sh.JF[f][q][v][XF + c];
         }
       }
-      Lm[(size_t)row * NQM + col] = static_cast<T>(prm.dt_a * acc);
+      Lm[(size_t)row * NQM + col] = static_cast<T>(dta * acc);
     }
     for (int idx = tid; idx < NF * NQM; idx += nt) {
       const int row = idx / NQM, col = idx % NQM;
@@ -816,7 +825,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
 }
 
 // ---------------------------------------------------------------------------
-// HDG-MX block contraction from the point records (sum factorisation).
+// Element block contraction from the point records (sum factorisation).
 //
 // Volume contributions to K = M + dt_a dR/dU, A12 = dt_a dR/dQ and the lifting
 // block A21 = M_Q^-1 dl/dU all have the form
@@ -829,9 +838,10 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
 // LE(b) LE(b2) sum_q TLL[q][a][a2] J_f(q).  The face-only blocks C, D, E, A32,
 // A23 are single 1D sums per entry.
 //
-// Work split: five workgroups per element (K | A12 | A21 | C D E | A32 A23),
-// numbered so that the five of one element run on the same XCD and share its
-// L2 copy of the point record.
+// Work split: five workgroups per HDG-MX element (K | A12 | A21 | C D E |
+// A32 A23), two per inviscid HDG-IP element (K | C D E), numbered so that the
+// workgroups of one element run on the same XCD and share its L2 copy of the
+// point record.
 // ---------------------------------------------------------------------------
 template <int K, class T> struct CtShared {
   static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
@@ -866,12 +876,13 @@ __device__ __forceinline__ void lift_coef(int c, T cx[3], T cy[3]) {
   }
 }
 
-template <int K, class T>
-__global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
-                                                              const double* __restrict__ rec,
-                                                              T* __restrict__ blk, T* __restrict__ scr) {
+template <int K, class T, bool MX>
+__global__ void __launch_bounds__(256) hdg_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
+                                                           const double* __restrict__ rec,
+                                                           T* __restrict__ blk, T* __restrict__ scr) {
   using S = HS<K, true>;
-  using R = MxRec<K>;
+  using R = PointRec<K, MX>;
+  constexpr int NGRP = MX ? 5 : 2;              // HDG-IP: K and the face-only blocks C D E
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NR = S::NR, NC = S::NC;
   __shared__ CtShared<K, T> sh;
@@ -879,8 +890,8 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
   // five groups of element p are spread over blocks 8 apart
   const int L = blockIdx.x;
   const int xcd = L & 7, rr = L >> 3;
-  const int grp = rr % 5;
-  const int p = 8 * (rr / 5) + xcd;
+  const int grp = MX ? rr % NGRP : (rr % NGRP == 0 ? 0 : 3);
+  const int p = 8 * (rr / NGRP) + xcd;
   if (p >= h.n_im) return;
   const int e = h.im_list[p];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -888,7 +899,7 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
   const double hx = m.hx[e], hy = m.hy[e];
   const T sx = T(2.0 / hx), sy = T(2.0 / hy), jac = T(0.25 * hx * hy);
   const T wlx = T(0.5 * hy), wly = T(0.5 * hx);     // line measure factor of x-faces / y-faces
-  const T dta = T(dt_a);
+  const T dta = T(dt_a * elem_dt(m, e));
   for (int i = tid; i < NQ * NN; i += nt) {
     const int q = i / NN, a = (i / NP) % NP, a2 = i % NP;
     sh.TLL[q][a][a2] = tb.W[q] * tb.L[q][a] * tb.L[q][a2];
@@ -908,8 +919,8 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
       T jx, jy;
       if (grp == 0) {
         const int v = pr >> 2, v2 = pr & 3;
-        jx = rp[R::JV + (qv * 8 + 2 * v) * 9 + v2];
-        jy = rp[R::JV + (qv * 8 + 2 * v + 1) * 9 + v2];
+        jx = rp[R::JV + (qv * 8 + 2 * v) * R::NIV + v2];
+        jy = rp[R::JV + (qv * 8 + 2 * v + 1) * R::NIV + v2];
       } else if (grp == 1) {
         const int v = pr / 5, c = pr % 5;
         jx = rp[R::JV + (qv * 8 + 2 * v) * 9 + 4 + c];
@@ -933,7 +944,7 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
         const int pr = i / (4 * NQ), f = (i / NQ) % 4, q = i % NQ;
         const int v = (grp == 0) ? pr >> 2 : pr / 5;
         const int col = (grp == 0) ? (pr & 3) : 8 + pr % 5;
-        sh.u.v.JS[pr][f][q] = rp[R::JF + ((f * NQ + q) * 8 + v) * 13 + col];
+        sh.u.v.JS[pr][f][q] = rp[R::JF + ((f * NQ + q) * R::NOF + v) * R::NIF + col];
       }
     __syncthreads();
     const T cx = jac * sx, cy = jac * sy;
@@ -1017,9 +1028,18 @@ __global__ void __launch_bounds__(256) hdg_mx_contract_kernel(DeviceMesh m, Devi
     }
     return;
   }
-  // face-only blocks
-  for (int i = tid; i < 4 * NQ * 8 * 13; i += nt) (&sh.u.f.JF[0][0][0][0])[i] = rp[R::JF + i];
-  for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
+  // face-only blocks; LDS holds rows s (0..3) and t (4..7) of the face Jacobians,
+  // columns U (0..3), Uhat (4..7) and, for HDG-MX, Q (8..12)
+  if constexpr (MX) {
+    for (int i = tid; i < 4 * NQ * 8 * 13; i += nt) (&sh.u.f.JF[0][0][0][0])[i] = rp[R::JF + i];
+    for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
+  } else {
+    for (int i = tid; i < 4 * NQ * 8 * 8; i += nt) {
+      const int f = i / (NQ * 64), q = (i / 64) % NQ, r = (i / 8) % 8, col = i % 8;
+      const int src = r < 4 ? r : R::TO + (r - 4);
+      sh.u.f.JF[f][q][r][col] = rp[R::JF + ((f * NQ + q) * R::NOF + src) * R::NIF + col];
+    }
+  }
   __syncthreads();
   // 1D face sum: sum_q TLL[q][x][y] J(q) for face f
   auto fsum = [&](int f, int x, int y, int jr, int jc) {
@@ -2097,10 +2117,12 @@ static size_t scr_stride(const imex_ctx* c) {
   const size_t NU = 4 * c->NN, NF = 16 * c->NP, NQM = 5 * c->NN;
   return 2 * (NU + NF) * NQM;
 }
+static bool use_points(const imex_ctx* c) { return use_mx(c) || !c->gas.viscous; }
 static size_t rec_stride(const imex_ctx* c) {
-  if (!use_mx(c)) return 0;
+  if (!use_points(c)) return 0;
   const size_t NQ = (3 * c->K + 2) / 2, NQV = NQ * NQ;
-  return NQV * 8 * 9 + 4 * NQ * 8 * 13 + NQV * 12 + 4 * NQ * 12;
+  if (use_mx(c)) return NQV * 8 * 9 + 4 * NQ * 8 * 13 + NQV * 12 + 4 * NQ * 12;
+  return NQV * 8 * 12 + 4 * NQ * 16 * 16;
 }
 
 // GMRES vectors: V (m+1), z, r, b, dx, work
@@ -2163,8 +2185,8 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
                        c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec, w.hres);
     if (jacobian) {
       const int nblk = 40 * ((c->n_im + 7) / 8);
-      hipLaunchKernelGGL((hdg_mx_contract_kernel<KK, LT>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(), c->dhdg(),
-                         dt_a, w.rec, blk, scr);
+      hipLaunchKernelGGL((hdg_contract_kernel<KK, LT, true>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
+                         c->dhdg(), dt_a, w.rec, blk, scr);
     }
     c->timer_end(ta);
     if (jacobian) {
@@ -2177,6 +2199,19 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
       c->timer_end(te);
       if (ge != hipSuccess) return ge;
     }
+  } else if (!c->gas.viscous) {
+    // inviscid HDG-IP: the same split without mixed blocks (K and C D E)
+    const size_t shm = sizeof(AsmShared<KK, false>);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
+                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec, w.hres);
+    if (jacobian) {
+      const int nblk = 16 * ((c->n_im + 7) / 8);
+      hipLaunchKernelGGL((hdg_contract_kernel<KK, LT, false>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
+                         c->dhdg(), dt_a, w.rec, blk, scr);
+    }
+    c->timer_end(ta);
   } else {
     const size_t shm = sizeof(AsmShared<KK, false>);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT>),

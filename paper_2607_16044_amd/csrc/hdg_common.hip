@@ -172,6 +172,18 @@ __global__ void extrapolate_kernel(int n, double c, double* __restrict__ Y, doub
   P[t] = a;
 }
 
+// rhs += b dts_e R on the rows of implicit elements
+template <int K>
+__global__ void rhs_accumulate_kernel(DeviceMesh m, DeviceHDG h, double b, const double* __restrict__ R,
+                                      double* __restrict__ rhs) {
+  constexpr int NN = (K + 1) * (K + 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_im * 4 * NN) return;
+  const int e = h.im_list[t / (4 * NN)];
+  const size_t idx = (size_t)e * 4 * NN + t % (4 * NN);
+  rhs[idx] += b * elem_dt(m, e) * R[idx];
+}
+
 #define IMEX_DISPATCH_K(KV, ...)                                \
   switch (KV) {                                                 \
     case 1: { constexpr int KK = 1; __VA_ARGS__; } break;       \
@@ -203,6 +215,14 @@ hipError_t launch_extrapolate(const imex_ctx* c, double coef, double* Y, double*
                                            c->stream, c->dhdg(), coef, Y, Yp));
   const int nh = c->n_hf * 4 * c->NP;
   hipLaunchKernelGGL(extrapolate_kernel, dim3((nh + 255) / 256), dim3(256), 0, c->stream, nh, coef, Uhat, Hp);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, double* rhs) {
+  const int n = c->n_im * 4 * c->NN;
+  if (n == 0) return hipSuccess;
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(rhs_accumulate_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
+                                           c->stream, c->dmesh(), c->dhdg(), b, R, rhs));
   return hipGetLastError();
 }
 

@@ -132,25 +132,24 @@ def _strip_grid_y(ny: int, strip_rows: int, compression: float, L: float = 10.0)
 
 
 def _euler_dt(wl_grid_x, wl_grid_y, implicit, k, ic, gamma, cfl=0.5):
-    """Explicit-region time step: dt = cfl / max_T (k+1)^2 (|u|+c)/h_min."""
-    xs, ys = wl_grid_x, wl_grid_y
-    lam = 0.0
-    for j in range(len(ys) - 1):
-        for i in range(len(xs) - 1):
-            if implicit[j, i]:
-                continue
-            px = np.linspace(xs[i], xs[i + 1], 5)
-            py = np.linspace(ys[j], ys[j + 1], 5)
-            X, Y = np.meshgrid(px, py)
-            U = ic(X, Y)
-            rho = U[0]
-            u = U[1] / rho
-            v = U[2] / rho
-            p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
-            s = np.max(np.sqrt(u * u + v * v) + np.sqrt(gamma * p / rho))
-            h = min(xs[i + 1] - xs[i], ys[j + 1] - ys[j])
-            lam = max(lam, (k + 1) ** 2 * s / h)
-    return cfl / lam
+    """Explicit-region time step: dt = cfl / max_T (k+1)^2 (|u|+c)/h_min, the wave speed
+    sampled on a 5x5 grid of points of each explicit element."""
+    xs, ys = np.asarray(wl_grid_x), np.asarray(wl_grid_y)
+    jj, ii = np.nonzero(~np.asarray(implicit))
+    if len(ii) == 0:
+        return np.inf
+    t = np.linspace(0.0, 1.0, 5)
+    X = xs[ii, None, None] + (xs[ii + 1] - xs[ii])[:, None, None] * t[None, None, :]
+    Y = ys[jj, None, None] + (ys[jj + 1] - ys[jj])[:, None, None] * t[None, :, None]
+    X, Y = np.broadcast_arrays(X, Y)
+    U = ic(X, Y)
+    rho = U[0]
+    u = U[1] / rho
+    v = U[2] / rho
+    p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
+    s = (np.sqrt(u * u + v * v) + np.sqrt(gamma * p / rho)).reshape(len(ii), -1).max(axis=1)
+    h = np.minimum(xs[ii + 1] - xs[ii], ys[jj + 1] - ys[jj])
+    return cfl / np.max((k + 1) ** 2 * s / h)
 
 
 def vortex(nx: int = 16, ny: int = 16, k: int = 2, strip_rows: int = 4, compression: float = 20.0,
@@ -246,6 +245,23 @@ def boundary_layer(nx: int = 256, ny: int = 128, k: int = 4, implicit_rows: int 
                     implicit=implicit, degree=k, gamma=gamma, R=R, mu=mu, Pr=Pr, viscous=True, u_inf=u_inf,
                     dg_flux=FLUX_VIJAYASUNDARAM, hdg_flux=HDG_FLUX_FVS, hdg_variant=hdg_variant,
                     tableau=tableau, dt=dt, steps=steps, ic=ic)
+
+
+def vortex_ensemble(n: int = 512, seed: int = 4, steps: int = 5, nmin: int = 8, nmax: int = 48):
+    """Independent isentropic-vortex instances: square meshes N x N with N uniform in
+    [nmin, nmax], degree uniform in {1, 2, 3, 4}, vortex strength uniform in [1, 5], a centred
+    implicit strip of 1..6 rows (at most N - 2) compressed by a factor uniform in [5, 50]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        N = int(rng.integers(nmin, nmax + 1))
+        k = int(rng.integers(1, 5))
+        beta = float(rng.uniform(1.0, 5.0))
+        rows = min(int(rng.integers(1, 7)), N - 2)
+        comp = float(rng.uniform(5.0, 50.0))
+        out.append(vortex(nx=N, ny=N, k=k, strip_rows=rows, compression=comp, beta=beta, steps=steps,
+                          name=f"vortex_ensemble_{i}"))
+    return out
 
 
 def get(name: str) -> Workload:
