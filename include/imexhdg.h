@@ -194,6 +194,24 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
  * the counters after reading. */
 imex_status imex_kernel_times(imex_ctx* ctx, double out[16], int reset);
 
+/* Graph mode (on != 0): imex_ark_step replays the explicit sequence of every stage
+ * (explicit residual, stage combination and implicit right-hand side) from a
+ * hipGraph captured on first use on a private stream and captured again when dt
+ * or the tableau changes; the Newton solves, which decide on the host when they
+ * have converged, run eagerly between the replays.  on = 0 returns to eager
+ * launches.  Results are identical either way.  Errors: EDEVICE. */
+imex_status imex_set_graphs(imex_ctx* ctx, int on);
+
+/* Launch-shape autotuner: times the explicit residual kernel for each feasible
+ * number of elements per workgroup (at state U, all elements; Uhat needed for
+ * HDG-MX coupling, else nullable) and each batched GEMM of the implicit stage for
+ * both output tiles (64x64, 32x32), and keeps the fastest for this context.
+ * out (host [4]): elements per residual workgroup (0 = built-in default), then
+ * the tiles of the mixed-block elimination, K^-1 [C f] and Schur-update GEMMs
+ * (0 = not used).  Call after imex_set_regions and before stepping: it
+ * overwrites the implicit-stage workspaces and resets the kernel timers. */
+imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, int out[4]);
+
 /* Vector-Jacobian product of the explicit residual (reverse mode of Sec. 3.3):
  * Ubar = (dR^DG/dU)^T Rbar, with R^DG as in imex_dg_residual.  U dev (all
  * elements); Rbar dev [e][v][n], rows of implicit elements ignored; Ubar dev out,

@@ -25,7 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P]
+    lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
+    lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
     lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
     lib.imex_status_str.argtypes = [ctypes.c_int]
     lib.imex_status_str.restype = ctypes.c_char_p
@@ -222,6 +224,16 @@ class Engine:
         self._check(self.lib.imex_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat), ctypes.byref(st)))
         return st.as_dict()
 
+    def autotune(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None):
+        """Pick launch shapes by timing (see imex_autotune); returns the choices."""
+        out = (ctypes.c_int * 4)()
+        self._check(self.lib.imex_autotune(self.ctx, _ptr(U), _ptr(Uhat), out))
+        return {"dg_tile": out[0], "gemm_tile_eliminate": out[1], "gemm_tile_condense": out[2],
+                "gemm_tile_schur": out[3]}
+
+    def set_graphs(self, on: bool = True):
+        self._check(self.lib.imex_set_graphs(self.ctx, int(bool(on))))
+
     def vjp_dg_residual(self, U: torch.Tensor, Rbar: torch.Tensor) -> torch.Tensor:
         """(dR^DG/dU)^T Rbar over all elements."""
         Ubar = torch.empty_like(U)
@@ -344,6 +356,14 @@ class Ensemble:
         U = [eng.initial_state() for _, eng in self.groups]
         H = [eng.init_facets(u) for u, (_, eng) in zip(U, self.groups)]
         return U, H
+
+    def tune(self, U, H, graphs: bool = True):
+        """Autotune every degree group's launch shapes at state (U, H) and switch graph replay on."""
+        picks = []
+        for u, h, (_, eng) in zip(U, H, self.groups):
+            picks.append(eng.autotune(u, h if h.numel() else None))
+            eng.set_graphs(graphs)
+        return picks
 
     def step(self, U, H):
         """One ARK step of every instance (each with its own dt); returns summed solver counts."""

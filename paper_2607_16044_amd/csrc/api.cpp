@@ -131,7 +131,16 @@ void free_regions(imex_ctx* c) {
 
 }  // namespace
 
+void imex_ctx::drop_graphs() {
+  for (StageGraph& g : sg) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.key.clear();
+  }
+}
+
 int imex_ctx::timer_begin(int tag) {
+  if (capturing) return -1;
   hipEvent_t a, b;
   if (ev_free.size() >= 2) {
     a = ev_free.back(); ev_free.pop_back();
@@ -551,6 +560,44 @@ static imex_status dg_residual_async(imex_ctx* c, const double* U, const double*
   return IMEX_OK;
 }
 
+extern "C++" {
+// Run body() on the context's stream, or, with graphs enabled, replay the graph of
+// slot captured from it (captured again when key changes: dt, coefficients).
+template <class F>
+static imex_status run_captured(imex_ctx* c, int slot, const std::vector<double>& key, F&& body) {
+  if (!c->use_graphs) return body();
+  imex_ctx::StageGraph& g = c->sg[slot];
+  if (!g.exec || g.key != key) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipStream_t orig = c->stream;
+    HIP_TRY(c, hipStreamSynchronize(orig));
+    HIP_TRY(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+    c->stream = c->gstream;
+    c->capturing = true;
+    imex_status st = body();
+    c->capturing = false;
+    c->stream = orig;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->gstream, &graph);
+    if (st != IMEX_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(c, IMEX_EDEVICE, std::string("stream capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return fail(c, IMEX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    g.key = key;
+  }
+  HIP_TRY(c, hipGraphLaunch(g.exec, c->stream));
+  return IMEX_OK;
+}
+}  // extern "C++"
+
 imex_status imex_dg_residual(imex_ctx* c, const double* U, const double* Uhat, double* R) {
   if (!c || !U || !R) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
@@ -601,23 +648,32 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
     for (int j = 0; j < i; ++j) ci[i] += tab->Ai[3 * (i - 1) + j];
   if (mx) HIP_TRY(c, launch_lift_mixed(c, w.Y, Uhat, w.Q));   // Q^im_0 = Q(U_n, Uhat_n)
   for (int i = 1; i <= s; ++i) {
-    // R^DG(y^ex_i, y^im_{i-1}); the mixed variables in w.Q belong to y^im_{i-1}
-    // (rows of implicit elements in Rdg are never read)
-    const int tdg = c->timer_begin(TM_DG);
-    HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
-    HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[i - 1]));
-    c->timer_end(tdg);
+    // R^DG(y^ex_i, y^im_{i-1}) (the mixed variables in w.Q belong to y^im_{i-1}; rows of
+    // implicit elements in Rdg are never read), y^ex_{i+1}, and the implicit right-hand
+    // side rhs = M U_n - dt sum_{j<i} a_ij R^HDG_j: replayed from a graph when enabled
     double coef[4];
     const double* Rs[4];
     for (int j = 0; j < i; ++j) { coef[j] = tab->Ae[4 * i + j]; Rs[j] = Rdg[j]; }
-    HIP_TRY(c, launch_erk_combine(c, w.Un, i, Rs, coef, dt, w.Y));
+    const double* Rh[3];
+    double ch[3];
+    for (int j = 0; j < i - 1; ++j) { ch[j] = dt * tab->Ai[3 * (i - 1) + j]; Rh[j] = Rhdg[j]; }
+    std::vector<double> key = {dt, (double)i};
+    key.insert(key.end(), coef, coef + i);
+    key.insert(key.end(), ch, ch + i - 1);
+    const int tdg = c->timer_begin(TM_DG);
+    imex_status se = run_captured(c, i - 1, key, [&]() -> imex_status {
+      HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
+      HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[i - 1]));
+      HIP_TRY(c, launch_erk_combine(c, w.Un, i, Rs, coef, dt, w.Y));
+      if (c->n_im > 0) {
+        HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
+        for (int j = 0; j < i - 1; ++j) HIP_TRY(c, launch_rhs_accumulate(c, -ch[j], Rh[j], w.rhs));
+      }
+      return IMEX_OK;
+    });
+    c->timer_end(tdg);
+    if (se != IMEX_OK) return se;
     if (c->n_im > 0) {
-      const double* Rh[3];
-      double ch[3];
-      for (int j = 0; j < i - 1; ++j) { ch[j] = dt * tab->Ai[3 * (i - 1) + j]; Rh[j] = Rhdg[j]; }
-      // rhs = M U_n - dt sum_{j<i} a_ij R^HDG_j
-      HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
-      for (int j = 0; j < i - 1; ++j) HIP_TRY(c, launch_rhs_accumulate(c, -ch[j], Rh[j], w.rhs));
       // Newton initial guess (the converged root does not depend on it): linear
       // extrapolation in stage time from the two previous implicit stage values
       if (i >= 2 && ci[i - 1] - ci[i - 2] > 1e-12 * dt)
@@ -634,21 +690,75 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
       if (r != IMEX_OK) return r;
     }
   }
-  HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   if (!tab->fsal) {
-    const int tdg = c->timer_begin(TM_DG);
-    HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
-    HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[s]));
-    c->timer_end(tdg);
+    // U^ex_{n+1} = U^ex_n - dt M^-1 sum_j be_j R^DG_j, written over the explicit rows of Y
     double coef[4];
     const double* Rs[4];
     for (int j = 0; j <= s; ++j) { coef[j] = tab->be[j]; Rs[j] = Rdg[j]; }
-    HIP_TRY(c, launch_erk_combine(c, w.Un, s + 1, Rs, coef, dt, U));
+    std::vector<double> key = {dt, -1.0};
+    key.insert(key.end(), coef, coef + s + 1);
+    const int tdg = c->timer_begin(TM_DG);
+    imex_status se = run_captured(c, 4, key, [&]() -> imex_status {
+      HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
+      HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[s]));
+      HIP_TRY(c, launch_erk_combine(c, w.Un, s + 1, Rs, coef, dt, w.Y));
+      return IMEX_OK;
+    });
+    c->timer_end(tdg);
+    if (se != IMEX_OK) return se;
   }
+  HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   if (c->n_im > 0 && !tab->stiffly_accurate)
     return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
   HIP_TRY(c, hipStreamSynchronize(hs));
   c->timers_resolve();
+  return IMEX_OK;
+}
+
+imex_status imex_autotune(imex_ctx* c, const double* U, const double* Uhat, int out[4]) {
+  if (!c || !U || !out) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (c->n_im > 0 && (c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous) && !Uhat) return fail(c, IMEX_EINVAL, "Uhat required for HDG-MX");
+  // explicit residual: elements per workgroup
+  if (c->n_ex > 0) {
+    float best = 1e30f;
+    int pick = 0;
+    for (int et : {0, 2, 4, 8, 16, 32}) {
+      if (et && !dg_tile_valid(c->K, et)) continue;
+      c->dg_tile = et;
+      hipEvent_t a, b;
+      HIP_TRY(c, hipEventCreate(&a));
+      HIP_TRY(c, hipEventCreate(&b));
+      imex_status st = dg_residual_async(c, U, Uhat, c->ws.Rstage[7]);
+      HIP_TRY(c, hipEventRecord(a, c->stream));
+      for (int r = 0; r < 5 && st == IMEX_OK; ++r) st = dg_residual_async(c, U, Uhat, c->ws.Rstage[7]);
+      HIP_TRY(c, hipEventRecord(b, c->stream));
+      float ms = 1e30f;
+      HIP_TRY(c, hipEventSynchronize(b));
+      HIP_TRY(c, hipEventElapsedTime(&ms, a, b));
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      if (st != IMEX_OK) return st;
+      if (ms < best) { best = ms; pick = et; }
+    }
+    c->dg_tile = pick;
+  }
+  imex_status st = hdg_autotune_gemm(c);
+  if (st != IMEX_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timers_resolve();
+  for (int t = 0; t < imex_ctx::NTIMER; ++t) { c->tm_ms[t] = 0.0; c->tm_n[t] = 0; }
+  c->drop_graphs();
+  out[0] = c->dg_tile;
+  for (int g = 0; g < 3; ++g) out[1 + g] = c->gemm_tile[g];
+  return IMEX_OK;
+}
+
+imex_status imex_set_graphs(imex_ctx* c, int on) {
+  if (!c) return fail(c, IMEX_EINVAL, "null argument");
+  if (on && !c->gstream) HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  c->drop_graphs();
+  c->use_graphs = on != 0;
   return IMEX_OK;
 }
 
@@ -751,6 +861,9 @@ void imex_destroy(imex_ctx* c) {
   c->timers_resolve();
   for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
   c->ev_free.clear();
+  c->drop_graphs();
+  if (c->gstream) hipStreamDestroy(c->gstream);
+  c->gstream = nullptr;
   free_regions(c);
   Workspace& w = c->ws;
   for (double** p : {&w.trace, &w.Q, &w.Un, &w.Y, &w.rhs, &w.Yp}) {

@@ -107,6 +107,9 @@ struct imex_ctx {
   int n_win = 0, n_superrows = 0;
   int n_im = 0, n_ex = 0, n_hf = 0;
   bool regions_set = false;
+  // launch shapes (0 = built-in default), chosen by imex_autotune
+  int dg_tile = 0;              // explicit elements per workgroup of the residual kernel
+  int gemm_tile[3] = {0, 0, 0}; // output tile (64 or 32) of the elimination, K^-1 [C f] and Schur GEMMs
   // facet preconditioner reuse across Newton iterations, stages and steps
   bool prec_valid = false;      // factors match a recent system
   bool prec_fresh = false;      // the next GMRES solve is the first after a refactorisation
@@ -123,6 +126,16 @@ struct imex_ctx {
   int *d_win_off = nullptr, *d_win_slot = nullptr, *d_win_own = nullptr, *d_sr_flags = nullptr;
   imex::Workspace ws;
   std::string err;
+  // hipGraph replay of each stage's explicit sequence (imex_set_graphs)
+  struct StageGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> key;
+  };
+  bool use_graphs = false;
+  bool capturing = false;
+  hipStream_t gstream = nullptr;
+  StageGraph sg[5];
+  void drop_graphs();
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
   static constexpr int NTIMER = 8;
   double tm_ms[NTIMER] = {};
@@ -157,6 +170,7 @@ hipError_t launch_erk_combine(const imex_ctx* c, const double* Un, int nterms, c
 hipError_t launch_mass_sums(const imex_ctx* c, const double* U, double* partial, int* nblocks);
 hipError_t launch_scale_copy(const imex_ctx* c, const double* src, double* dst, double a, const double* add,
                              double b, size_t n);
+bool dg_tile_valid(int K, int et);
 // hdg.hip
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
@@ -168,6 +182,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
 imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const double* U, const double* Uhat,
                              double* f, double* h, double* K, double* C, double* D, double* E);
 size_t hdg_workspace_bytes(const imex_ctx* c);
+imex_status hdg_autotune_gemm(imex_ctx* c);
 // vjp.hip
 hipError_t vjp_alloc(imex_ctx* c);
 hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub);

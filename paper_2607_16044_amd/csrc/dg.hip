@@ -110,19 +110,22 @@ struct DGParams {
   double alpha;      // IP penalty factor
 };
 
+// Elements per workgroup: the default fills about 256 volume points; other tiles
+// are offered to the autotuner (imex_autotune) when their LDS fits in 64 KB.
 template <int K> struct DGTile {
-  static constexpr int NQV = ((3 * K + 2) / 2) * ((3 * K + 2) / 2);
+  static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NQV = NQ * NQ;
   static constexpr int ET0 = (256 / NQV) > 0 ? (256 / NQV) : 1;
   static constexpr int ET = ET0 > 32 ? 32 : ET0;
+  static constexpr size_t lds(int et) { return 8 * (size_t)et * (4 * NN + NQV * 8 + 4 * NQ * 12) + 2048; }
 };
+constexpr int DG_TILES[5] = {2, 4, 8, 16, 32};
 
-template <int K>
+template <int K, int ET>
 __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, DGParams prm,
                                                           const int* __restrict__ ex_list, int n_ex,
                                                           const double* __restrict__ U,
                                                           const double* __restrict__ T, double* __restrict__ R) {
   constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NQV = NQ * NQ;
-  constexpr int ET = DGTile<K>::ET;
   __shared__ double sU[ET][4 * NN];
   __shared__ double sF[ET][NQV][8];        // volume coefficients of d/dxi phi (0..3) and d/deta phi (4..7)
   __shared__ double sS[ET][4][NQ][4];      // face coefficients of phi
@@ -346,14 +349,41 @@ hipError_t launch_dg_trace(const imex_ctx* c, const double* U, const double* Q, 
   return hipGetLastError();
 }
 
+template <int KK, int ET>
+static bool launch_dg_tile(const imex_ctx* c, DGParams prm, const double* U, const double* trace, double* R) {
+  if constexpr (DGTile<KK>::lds(ET) <= 65536) {
+    const int nb = (c->n_ex + ET - 1) / ET;
+    hipLaunchKernelGGL((dg_residual_kernel<KK, ET>), dim3(nb), dim3(256), 0, c->stream, c->dmesh(), c->gas, prm,
+                       c->d_ex_list, c->n_ex, U, trace, R);
+    return true;
+  }
+  return false;
+}
+
+bool dg_tile_valid(int K, int et) {
+  switch (K) {
+    case 1: return DGTile<1>::lds(et) <= 65536;
+    case 2: return DGTile<2>::lds(et) <= 65536;
+    case 3: return DGTile<3>::lds(et) <= 65536;
+    case 4: return DGTile<4>::lds(et) <= 65536;
+  }
+  return false;
+}
+
 hipError_t launch_dg_residual(const imex_ctx* c, const double* U, const double* trace, double* R) {
   if (c->n_ex == 0) return hipSuccess;
   DGParams prm{c->opt.dg_flux == IMEX_FLUX_LAX_FRIEDRICHS, c->opt.alpha_dg};
   IMEX_DISPATCH_K(c->K, {
-    constexpr int ET = DGTile<KK>::ET;
-    const int nb = (c->n_ex + ET - 1) / ET;
-    hipLaunchKernelGGL(dg_residual_kernel<KK>, dim3(nb), dim3(256), 0, c->stream, c->dmesh(), c->gas, prm,
-                       c->d_ex_list, c->n_ex, U, trace, R);
+    bool ok = true;
+    switch (c->dg_tile) {
+      case 2: ok = launch_dg_tile<KK, 2>(c, prm, U, trace, R); break;
+      case 4: ok = launch_dg_tile<KK, 4>(c, prm, U, trace, R); break;
+      case 8: ok = launch_dg_tile<KK, 8>(c, prm, U, trace, R); break;
+      case 16: ok = launch_dg_tile<KK, 16>(c, prm, U, trace, R); break;
+      case 32: ok = launch_dg_tile<KK, 32>(c, prm, U, trace, R); break;
+      default: ok = launch_dg_tile<KK, DGTile<KK>::ET>(c, prm, U, trace, R); break;
+    }
+    if (!ok) return hipErrorInvalidValue;
   });
   return hipGetLastError();
 }

@@ -1136,34 +1136,36 @@ template <> struct Mfma16<float> {
   __device__ static int row(int lk, int r) { return 4 * lk + r; }
 };
 
-template <class T>
+template <class T, int TILE>
 __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int Kd, double alpha, int beta_one,
                                                    const T* __restrict__ A, int lda, long long sA,
                                                    const T* __restrict__ B, int ldb, long long sB,
                                                    T* __restrict__ C, int ldc, long long sC) {
   using MF = Mfma16<T>;
   constexpr int KB = 32;                      // k-block staged in LDS
-  __shared__ T sa[64][KB + 1];
-  __shared__ T sb[KB][65];
+  constexpr int SUB = TILE / 32;              // 16x16 MFMA tiles per wave and dimension
+  static_assert(TILE == 32 || TILE == 64, "tile");
+  __shared__ T sa[TILE][KB + 1];
+  __shared__ T sb[KB][TILE + 1];
   // XCD-aware numbering: the output tiles of one batch entry share an XCD (and its L2)
-  const int tn = (N + 63) / 64, ntile = ((M + 63) / 64) * tn;
+  const int tn = (N + TILE - 1) / TILE, ntile = ((M + TILE - 1) / TILE) * tn;
   const int L = blockIdx.x, xcd = L & 7, rr = L >> 3;
   const int t = rr % ntile;
   const long long bz = 8LL * (rr / ntile) + xcd;
   if (bz >= batch) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m0 = (t / tn) * 64, n0 = (t % tn) * 64;
+  const int m0 = (t / tn) * TILE, n0 = (t % tn) * TILE;
   const T* Ab = A + bz * sA;
   const T* Bb = B + bz * sB;
   T* Cb = C + bz * sC;
   const int wr = wv >> 1, wc = wv & 1;
   const int li = lane & 15, lk = lane >> 4;
-  typename MF::V acc[2][2];
+  typename MF::V acc[SUB][SUB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SUB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = typename MF::V{T(0), T(0), T(0), T(0)};
-  constexpr int NL = 64 * KB / 256;           // elements of each operand block per thread
+    for (int j = 0; j < SUB; ++j) acc[i][j] = typename MF::V{T(0), T(0), T(0), T(0)};
+  constexpr int NL = TILE * KB / 256;         // elements of each operand block per thread
   T ra[NL], rb[NL];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -1172,7 +1174,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
       const int r = idx / KB, kk = idx % KB;
       const int gm = m0 + r, gk = k0 + kk;
       ra[u] = (gm < M && gk < Kd) ? Ab[(size_t)gm * lda + gk] : T(0);
-      const int kb = idx / 64, cc = idx % 64;
+      const int kb = idx / TILE, cc = idx % TILE;
       const int gk2 = k0 + kb, gn = n0 + cc;
       rb[u] = (gk2 < Kd && gn < N) ? Bb[(size_t)gk2 * ldb + gn] : T(0);
     }
@@ -1183,30 +1185,34 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
     for (int u = 0; u < NL; ++u) {
       const int idx = tid + 256 * u;
       sa[idx / KB][idx % KB] = ra[u];
-      sb[idx / 64][idx % 64] = rb[u];
+      sb[idx / TILE][idx % TILE] = rb[u];
     }
     __syncthreads();
     if (k0 + KB < Kd) fetch(k0 + KB);
 #pragma unroll
     for (int k4 = 0; k4 < KB / 4; ++k4) {
       const int kk = 4 * k4 + lk;
-      const T a0 = sa[32 * wr + li][kk], a1 = sa[32 * wr + 16 + li][kk];
-      const T b0 = sb[kk][32 * wc + li], b1 = sb[kk][32 * wc + 16 + li];
-      acc[0][0] = MF::op(a0, b0, acc[0][0]);
-      acc[0][1] = MF::op(a0, b1, acc[0][1]);
-      acc[1][0] = MF::op(a1, b0, acc[1][0]);
-      acc[1][1] = MF::op(a1, b1, acc[1][1]);
+      T av[SUB], bv[SUB];
+#pragma unroll
+      for (int i = 0; i < SUB; ++i) {
+        av[i] = sa[16 * SUB * wr + 16 * i + li][kk];
+        bv[i] = sb[kk][16 * SUB * wc + 16 * i + li];
+      }
+#pragma unroll
+      for (int i = 0; i < SUB; ++i)
+#pragma unroll
+        for (int j = 0; j < SUB; ++j) acc[i][j] = MF::op(av[i], bv[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < SUB; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < SUB; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + 32 * wr + 16 * ti + MF::row(lk, r);
-        const int gn = n0 + 32 * wc + 16 * tj + li;
+        const int gm = m0 + 16 * SUB * wr + 16 * ti + MF::row(lk, r);
+        const int gn = n0 + 16 * SUB * wc + 16 * tj + li;
         if (gm < M && gn < N) {
           T* cp = Cb + (size_t)gm * ldc + gn;
           const T v = T(alpha) * acc[ti][tj][r];
@@ -1216,16 +1222,22 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
 }
 
 // C[b] (+)= alpha A[b] B[b] for b < batch (row-major, leading dimensions lda/ldb/ldc,
-// batch strides sA/sB/sC in elements); beta_one selects accumulation into C.
+// batch strides sA/sB/sC in elements); beta_one selects accumulation into C; tile is
+// the output tile edge (64, or 32 for small matrices; 0 = 64).
 template <class T>
 static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
                                const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
-                               long long sC) {
+                               long long sC, int tile = 64) {
   if (batch == 0 || M == 0 || N == 0) return hipSuccess;
-  const long long T_ = (long long)((M + 63) / 64) * ((N + 63) / 64);
-  const long long nblk = 8LL * ((batch + 7) / 8) * T_;
-  hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0,
-                     A, lda, sA, B, ldb, sB, C, ldc, sC);
+  const int tl = tile == 32 ? 32 : 64;
+  const long long nt = (long long)((M + tl - 1) / tl) * ((N + tl - 1) / tl);
+  const long long nblk = 8LL * ((batch + 7) / 8) * nt;
+  if (tl == 32)
+    hipLaunchKernelGGL((gemm_kernel<T, 32>), dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha,
+                       beta_one ? 1 : 0, A, lda, sA, B, ldb, sB, C, ldc, sC);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, 64>), dim3((unsigned)nblk), dim3(256), 0, st, batch, M, N, K, alpha,
+                       beta_one ? 1 : 0, A, lda, sA, B, ldb, sB, C, ldc, sC);
   return hipGetLastError();
 }
 
@@ -2098,6 +2110,16 @@ __global__ void __launch_bounds__(256) facet_update_kernel(int n, const double* 
   }
 
 static bool use_mx(const imex_ctx* c) { return c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous; }
+
+// HDG_DISPATCH for functions returning imex_status
+#define HDG_DISPATCH_ST(KV, ...)                                \
+  switch (KV) {                                                 \
+    case 1: { constexpr int KK = 1; __VA_ARGS__; } break;       \
+    case 2: { constexpr int KK = 2; __VA_ARGS__; } break;       \
+    case 3: { constexpr int KK = 3; __VA_ARGS__; } break;       \
+    case 4: { constexpr int KK = 4; __VA_ARGS__; } break;       \
+    default: return IMEX_EINVAL;                                \
+  }
 static bool use_f32(const imex_ctx* c) { return c->opt.precision == IMEX_FP32_REFINE; }
 static size_t la_bytes(const imex_ctx* c) { return use_f32(c) ? sizeof(float) : sizeof(double); }
 
@@ -2195,7 +2217,8 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
       const int te = c->timer_begin(TM_ELIMINATE);
       const long long ss = (long long)scr_stride(c);
       const hipError_t ge = gemm_batched<LT>(c->stream, c->n_im, NR, NR, NQM, -1.0, true, scr, NQM, ss,
-                                             scr + (size_t)NR * NQM, NR, ss, blk, NR + 1, (long long)blk_stride(c));
+                                             scr + (size_t)NR * NQM, NR, ss, blk, NR + 1, (long long)blk_stride(c),
+                                             c->gemm_tile[0]);
       c->timer_end(te);
       if (ge != hipSuccess) return ge;
     }
@@ -2242,13 +2265,71 @@ static hipError_t launch_condense(imex_ctx* c) {
     hipLaunchKernelGGL((hdg_invert_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv);
     const long long bs = (long long)blk_stride(c);
     hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
-                                    blk + NU, NC, bs, X, NF + 1, (long long)NU * (NF + 1));
+                                    blk + NU, NC, bs, X, NF + 1, (long long)NU * (NF + 1), c->gemm_tile[1]);
     if (e != hipSuccess) return e;
     e = gemm_batched<LT>(c->stream, c->n_im, NF, NF + 1, NU, -1.0, true, blk + (size_t)NU * NC, NC, bs, X, NF + 1,
-                         (long long)NU * (NF + 1), blk + (size_t)NU * NC + NU, NC, bs);
+                         (long long)NU * (NF + 1), blk + (size_t)NU * NC + NU, NC, bs, c->gemm_tile[2]);
     if (e != hipSuccess) return e;
   }));
   return hipGetLastError();
+}
+
+// average device time (ms) of reps runs of f on the context's stream
+template <class F>
+static float time_ms(imex_ctx* c, int reps, F&& f) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30f;
+  if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return 1e30f; }
+  f();                                              // warm-up
+  hipEventRecord(a, c->stream);
+  for (int r = 0; r < reps; ++r) f();
+  hipEventRecord(b, c->stream);
+  float ms = 1e30f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 1e30f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms / reps;
+}
+
+// Output tile of each batched GEMM (elimination, K^-1 [C f], Schur update) by timing
+// both tiles on the implicit workspaces (whose contents every assembly rewrites).
+imex_status hdg_autotune_gemm(imex_ctx* c) {
+  if (c->n_im == 0) return IMEX_OK;
+  Workspace& w = c->ws;
+  HDG_DISPATCH_ST(c->K, LA_DISPATCH(c, {
+    constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NR = NU + NF, NC = NU + NF + 1;
+    constexpr int NQM = 5 * (KK + 1) * (KK + 1);
+    LT* blk = la<LT>(w.blk);
+    LT* scr = la<LT>(w.scr);
+    LT* Kinv = la<LT>(w.Kinv);
+    LT* X = la<LT>(w.X);
+    const long long bs = (long long)blk_stride(c), ss = (long long)scr_stride(c);
+    for (int g = 0; g < 3; ++g) {
+      if (g == 0 && !use_mx(c)) continue;
+      float best = 1e30f;
+      for (int tile : {64, 32}) {
+        const float ms = time_ms(c, 3, [&]() {
+          if (g == 0)
+            gemm_batched<LT>(c->stream, c->n_im, NR, NR, NQM, -1.0, true, scr, NQM, ss, scr + (size_t)NR * NQM,
+                             NR, ss, blk, NR + 1, bs, tile);
+          else if (g == 1)
+            gemm_batched<LT>(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU, blk + NU,
+                             NC, bs, X, NF + 1, (long long)NU * (NF + 1), tile);
+          else
+            gemm_batched<LT>(c->stream, c->n_im, NF, NF + 1, NU, -1.0, true, blk + (size_t)NU * NC, NC, bs, X,
+                             NF + 1, (long long)NU * (NF + 1), blk + (size_t)NU * NC + NU, NC, bs, tile);
+        });
+        if (ms < best) { best = ms; c->gemm_tile[g] = tile; }
+      }
+    }
+  }));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("GEMM autotuning: ") + hipGetErrorString(e);
+    return IMEX_EDEVICE;
+  }
+  c->prec_valid = false;                            // the factors read the overwritten blocks
+  return IMEX_OK;
 }
 
 static hipError_t launch_facet_rhs(imex_ctx* c, double* b) {

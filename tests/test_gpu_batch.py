@@ -92,3 +92,44 @@ def test_full_ensemble_one_step():
         b = eng.conservation_sums(u)
         assert np.abs(b - a).max() < 1e-3 * np.abs(a).max()
     ens.close()
+
+
+@pytest.mark.parametrize("case", ["boundary_layer_small", "vortex_small", "explicit"])
+def test_graph_replay_equals_eager(case):
+    """Each step with graph replay of the explicit stage sequence equals the eager step."""
+    from _common import smooth_square
+    wl = smooth_square(4, 2, viscous=True) if case == "explicit" else W.get(case)
+    runs = []
+    for graphs in (False, True):
+        eng = gpu_engine(wl)
+        eng.set_graphs(graphs)
+        U = eng.initial_state()
+        H = eng.init_facets(U) if eng.sizes["n_implicit"] else None
+        states = []
+        for _ in range(4):
+            eng.ark_step(wl.dt, U, H)
+            states.append(U.cpu().numpy().copy())
+        runs.append(states)
+        eng.close()
+    for a, b in zip(*runs):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("case,precision", [("boundary_layer_small", 0), ("boundary_layer_small", 1),
+                                            ("vortex_small", 1)])
+def test_autotuned_shapes_give_same_result(case, precision):
+    wl = W.get(case)
+    res = []
+    for tune in (False, True):
+        eng = gpu_engine(wl, precision=precision)
+        U = eng.initial_state()
+        H = eng.init_facets(U)
+        if tune:
+            picks = eng.autotune(U, H)
+            print(case, picks)
+            assert picks["dg_tile"] in (0, 2, 4, 8, 16, 32)
+        for _ in range(2):
+            eng.ark_step(wl.dt, U, H)
+        res.append(U.cpu().numpy())
+        eng.close()
+    assert rel_err(res[1], res[0]) < 1e-12
