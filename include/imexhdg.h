@@ -228,6 +228,22 @@ imex_status imex_vjp_dg_residual(imex_ctx* ctx, const double* U, const double* R
 imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
                               const double* Ubar_next, double* Ubar);
 
+/* Reverse mode of one IMEX step (Alg. imex_scheme_update) with implicit region:
+ * given the state (U dev, Uhat dev; unchanged) at t_n and the adjoints Ubar_next
+ * (dev, all elements) and Uhatbar_next (dev, facets; nullable = 0) of the state
+ * after the step, writes Ubar = adjoint of U_n (dev out, all elements); the
+ * adjoint of Uhat_n is zero (it only seeds Newton).  The step is recomputed
+ * from (U, Uhat) recording the stage values; each implicit stage is reversed
+ * with the transposed condensed system at its converged state (K^-T, S^T by
+ * GMRES with a facet block-Jacobi preconditioner, tolerance min(gmres_rtol,
+ * 1e-12)), the explicit parts with imex_vjp_dg_residual.  Without an implicit
+ * region this is imex_vjp_ark_step.  st host (nullable): gmres_its of the
+ * transposed solves.  Errors: ENOTIMPL for HDG-MX coupling or implicit tableaux
+ * that are not stiffly accurate; as imex_ark_step. */
+imex_status imex_vjp_imex_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
+                               const double* Uhat, const double* Ubar_next, const double* Uhatbar_next,
+                               double* Ubar, imex_stats* st);
+
 const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);
 void imex_destroy(imex_ctx* ctx);

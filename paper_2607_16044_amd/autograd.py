@@ -1,11 +1,13 @@
 """torch.autograd wrappers of the engine's residual and time stepping.
 
 * DGResidual: R^DG(U) with the hand-written vector-Jacobian product as backward.
-* ARKRollout: nsteps ARK steps from U_0 returning the states at the steps listed
-  in ``record``; the backward pass keeps only every ``checkpoint``-th state from
-  the forward pass and recomputes each segment from its checkpoint, then runs
-  the step adjoints in reverse, adding the adjoints of the recorded states on
-  the way (so time-averaged functionals of the trajectory are differentiable).
+* ARKRollout: nsteps IMEX ARK steps from U_0 (explicit-only or with an HDG-IP
+  implicit region; the facet state starts from the element traces) returning the
+  states at the steps listed in ``record``; the backward pass keeps only every
+  ``checkpoint``-th (U, Uhat) from the forward pass and recomputes each segment
+  from its checkpoint, then runs the step adjoints in reverse, adding the
+  adjoints of the recorded states on the way (so time-averaged functionals of
+  the trajectory are differentiable).
 Both run entirely on the GPU through the C-ABI; the tensors are FP64 device
 tensors in the engine's [element][variable][node] layout.
 """
@@ -42,14 +44,15 @@ class ARKRollout(torch.autograd.Function):
         if record and (record[0] < 0 or record[-1] > nsteps):
             raise ValueError("recorded steps must lie in [0, nsteps]")
         U = U0.detach().clone().contiguous()
-        checkpoints = {0: U.clone()}
+        H = engine.init_facets(U) if engine.sizes["n_implicit"] else None
+        checkpoints = {0: (U.clone(), None if H is None else H.clone())}
         out = []
         if 0 in record:
             out.append(U.clone())
         for n in range(1, nsteps + 1):
-            engine.ark_step(dt, U, None)
+            engine.ark_step(dt, U, H)
             if n % checkpoint == 0 and n < nsteps:
-                checkpoints[n] = U.clone()
+                checkpoints[n] = (U.clone(), None if H is None else H.clone())
             if n in record:
                 out.append(U.clone())
         ctx.engine, ctx.dt, ctx.nsteps, ctx.record, ctx.every = engine, dt, nsteps, record, checkpoint
@@ -60,25 +63,29 @@ class ARKRollout(torch.autograd.Function):
     def backward(ctx, gout):
         eng, dt, nsteps, every = ctx.engine, ctx.dt, ctx.nsteps, ctx.every
         seed = {r: gout[i] for i, r in enumerate(ctx.record)}
-        Ubar = torch.zeros_like(ctx.checkpoints[0])
+        Ubar = torch.zeros_like(ctx.checkpoints[0][0])
         if nsteps in seed:
             Ubar += seed[nsteps]
         starts = sorted(ctx.checkpoints)
         for c0 in reversed(starts):
             c1 = min(c0 + every, nsteps)
-            # recompute the states U_{c0} .. U_{c1-1} of this segment
-            states = [ctx.checkpoints[c0].clone()]
+            # recompute the states (U, Uhat)_{c0} .. (U, Uhat)_{c1-1} of this segment
+            U0, H0 = ctx.checkpoints[c0]
+            states = [(U0.clone(), None if H0 is None else H0.clone())]
             for _ in range(c0, c1 - 1):
-                U = states[-1].clone()
-                eng.ark_step(dt, U, None)
-                states.append(U)
+                U, H = states[-1]
+                U, H = U.clone(), None if H is None else H.clone()
+                eng.ark_step(dt, U, H)
+                states.append((U, H))
             for n in range(c1 - 1, c0 - 1, -1):
-                Ubar = eng.vjp_ark_step(dt, states[n - c0], Ubar.contiguous())
+                U, H = states[n - c0]
+                # the facet state only seeds the Newton iterations: its adjoint is zero
+                Ubar = eng.vjp_imex_step(dt, U, H, Ubar.contiguous())
                 if n in seed:
                     Ubar += seed[n]
         return Ubar, None, None, None, None, None
 
 
 def ark_rollout(engine, U0, dt: float, nsteps: int, record: Sequence[int], checkpoint: int = 20):
-    """States at the steps in ``record`` of an explicit ARK run from U0, differentiable in U0."""
+    """States at the steps in ``record`` of an ARK run from U0, differentiable in U0."""
     return ARKRollout.apply(U0, engine, dt, nsteps, list(record), checkpoint)

@@ -25,7 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch", "imex_autotune", "imex_set_graphs",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P]
     lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
+    lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, ctypes.POINTER(Stats)]
     lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
     lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
     lib.imex_status_str.argtypes = [ctypes.c_int]
@@ -246,6 +247,17 @@ class Engine:
         tab = self.tableau.to_ctypes(Tableau)
         self._check(self.lib.imex_vjp_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Ubar_next),
                                                _ptr(Ubar)))
+        return Ubar
+
+    def vjp_imex_step(self, dt: float, U: torch.Tensor, Uhat: Optional[torch.Tensor], Ubar_next: torch.Tensor,
+                      Uhatbar_next: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Adjoint of U_n for one IMEX step from (U, Uhat) (both unchanged)."""
+        Ubar = torch.empty_like(U)
+        st = Stats()
+        tab = self.tableau.to_ctypes(Tableau)
+        self._check(self.lib.imex_vjp_imex_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat),
+                                                _ptr(Ubar_next), _ptr(Uhatbar_next), _ptr(Ubar), ctypes.byref(st)))
+        self.last_adjoint_stats = st.as_dict()
         return Ubar
 
     def conservation_sums(self, U: torch.Tensor):

@@ -112,12 +112,13 @@ hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 void free_regions(imex_ctx* c) {
   for (int** p : {&c->d_im_list, &c->d_ex_list, &c->d_face_kind, &c->d_efacet, &c->d_hf_side, &c->d_hf_face,
-                  &c->d_hf_elem, &c->d_win_off, &c->d_win_slot, &c->d_win_own, &c->d_sr_flags}) {
+                  &c->d_hf_elem, &c->d_win_off, &c->d_win_slot, &c->d_win_own, &c->d_sr_flags,
+                  &c->d_ex_ifacet}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.Hp, &w.gH, &w.gm, &w.red}) {
+  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.Hp, &w.gH, &w.gm, &w.red, &w.adj_P, &w.adj_w}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
@@ -127,6 +128,9 @@ void free_regions(imex_ctx* c) {
   }
   if (w.hred) hipHostFree(w.hred);
   w.hred = nullptr;
+  for (double* p : w.adj_buf)
+    if (p) hipFree(p);
+  w.adj_buf.clear();
 }
 
 }  // namespace
@@ -490,6 +494,13 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
       c->face_kind[4 * p + f] = k;
     }
   }
+  // interface facet across each face of an explicit element (adjoint of the interface rows)
+  c->ex_ifacet.assign(4 * (size_t)E, -1);
+  for (int e : c->ex_list)
+    for (int f = 0; f < 4; ++f) {
+      const int nb = c->nbr[4 * e + f];
+      if (nb >= 0 && c->imp[nb]) c->ex_ifacet[4 * e + f] = c->efacet[4 * im_pos[nb] + (f ^ 1)];
+    }
   free_regions(c);
   hipStream_t s = c->stream;
   hipError_t he = hipMemcpyAsync(c->d_imp, c->imp.data(), E, hipMemcpyHostToDevice, s);
@@ -504,6 +515,7 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   if (he == hipSuccess) he = upload(&c->d_win_slot, c->win_slot, s);
   if (he == hipSuccess) he = upload(&c->d_win_own, c->win_own, s);
   if (he == hipSuccess) he = upload(&c->d_sr_flags, c->sr_flags, s);
+  if (he == hipSuccess) he = upload(&c->d_ex_ifacet, c->ex_ifacet, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return fail(c, IMEX_ENOMEM, std::string("region tables: ") + hipGetErrorString(he));
   imex_status st = hdg_alloc(c);
@@ -623,7 +635,30 @@ imex_status imex_local_system(imex_ctx* c, double dt_a, const double* rhs, const
   return hdg_local_system(c, dt_a, rhs, U, Uhat, f, h, K, C, D, E);
 }
 
+}  // extern "C"
+
+// Stage data recorded by a step for its reverse mode: Ydg[i] = state entering the
+// explicit residual of stage i+1 (Ydg[s]: the final residual, not FSAL); Ysol[i],
+// Hsol[i] = stage state and facet state after the implicit solve of stage i+1.
+struct ArkTape {
+  double* Ydg[4] = {};
+  double* Ysol[3] = {};
+  double* Hsol[3] = {};
+};
+
+static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt, double* U, double* Uhat,
+                                 imex_stats* st, const ArkTape* tape);
+
+extern "C" {
+
 imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, double* U, double* Uhat, imex_stats* st) {
+  return ark_step_impl(c, tab, dt, U, Uhat, st, nullptr);
+}
+
+}  // extern "C"
+
+static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt, double* U, double* Uhat,
+                                 imex_stats* st, const ArkTape* tape) {
   if (!c || !tab || !U) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
@@ -660,6 +695,7 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
     std::vector<double> key = {dt, (double)i};
     key.insert(key.end(), coef, coef + i);
     key.insert(key.end(), ch, ch + i - 1);
+    if (tape) HIP_TRY(c, hipMemcpyAsync(tape->Ydg[i - 1], w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
     const int tdg = c->timer_begin(TM_DG);
     imex_status se = run_captured(c, i - 1, key, [&]() -> imex_status {
       HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
@@ -688,9 +724,15 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
         st->t_solve_ms += sst.t_solve_ms;
       }
       if (r != IMEX_OK) return r;
+      if (tape) {
+        HIP_TRY(c, hipMemcpyAsync(tape->Ysol[i - 1], w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+        HIP_TRY(c, hipMemcpyAsync(tape->Hsol[i - 1], Uhat, (size_t)c->n_hf * 4 * c->NP * sizeof(double),
+                                  hipMemcpyDeviceToDevice, hs));
+      }
     }
   }
   if (!tab->fsal) {
+    if (tape) HIP_TRY(c, hipMemcpyAsync(tape->Ydg[s], w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
     // U^ex_{n+1} = U^ex_n - dt M^-1 sum_j be_j R^DG_j, written over the explicit rows of Y
     double coef[4];
     const double* Rs[4];
@@ -714,6 +756,8 @@ imex_status imex_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, doubl
   c->timers_resolve();
   return IMEX_OK;
 }
+
+extern "C" {
 
 imex_status imex_autotune(imex_ctx* c, const double* U, const double* Uhat, int out[4]) {
   if (!c || !U || !out) return fail(c, IMEX_EINVAL, "null argument");
@@ -824,6 +868,104 @@ imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, c
   HIP_TRY(c, hipMemcpyAsync(Ubar, tab->fsal ? zero : Ubar_next, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   for (int i = 0; i <= s; ++i) HIP_TRY(c, launch_scale_copy(c, Ubar, Ubar, 1.0, Yb[i], 1.0, n));
   HIP_TRY(c, hipStreamSynchronize(hs));
+  return IMEX_OK;
+}
+
+// Reverse mode of one IMEX step (Alg. imex_scheme_update) with an implicit region.
+// The step is recomputed from (U_n, Uhat_n) recording the stage data; then, stages in
+// decreasing order, with y^ex_i / y^im_i the explicit / implicit stage values:
+//   (d) implicit stage i: transposed condensed solve at the converged stage state,
+//       also taking in the adjoint of R^HDG_i from later right-hand sides; gives the
+//       adjoint of rhs_i and adds that of the interface data y^ex_{i+1};
+//   (c) rhs_i = M U_n - dt sum_{j<i} a_ij R^HDG_j: adjoints of U_n and of R^HDG_j;
+//   (b) y^ex_{i+1} = U_n - dt M^-1 sum_{j<=i} ae_{i,j} R^DG_j: adjoints of U_n, R^DG_j;
+//   (a) R^DG_i = R^DG(y^ex_i, y^im_{i-1}): residual adjoint into both stage values.
+// Uhat_n enters only the Newton initial guess, so its adjoint is zero (HDG-IP).
+imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, const double* U, const double* Uhat,
+                               const double* Ubar_next, const double* Uhatbar_next, double* Ubar,
+                               imex_stats* st) {
+  if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  if (c->n_im == 0) return imex_vjp_ark_step(c, tab, dt, U, Ubar_next, Ubar);
+  if (!Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
+  if (mx_coupled(c)) return fail(c, IMEX_ENOTIMPL, "step adjoint through HDG-MX interface data");
+  if (!tab->stiffly_accurate) return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
+  if (st) std::memset(st, 0, sizeof(*st));
+  HIP_TRY(c, vjp_alloc(c));
+  Workspace& w = c->ws;
+  const int s = tab->s;
+  const size_t n = (size_t)c->E * 4 * c->NN, nh = (size_t)c->n_hf * 4 * c->NP;
+  hipStream_t hs = c->stream;
+  // buffers: tape Ydg[4] Ysol[3] | Uw | yexb[5] yimb[4] Rdgb[5] Rhb[4] rhsb Yb  (state-sized),
+  //          Hsol[3] Hw hb[4] (facet-sized)
+  constexpr int NSTATE = 4 + 3 + 1 + 5 + 4 + 5 + 4 + 1 + 1, NFAC = 3 + 1 + 4;
+  if (w.adj_buf.empty()) {
+    for (int i = 0; i < NSTATE + NFAC; ++i) {
+      double* p = nullptr;
+      HIP_TRY(c, hipMalloc(&p, 8 * (i < NSTATE ? n : std::max<size_t>(nh, 1))));
+      w.adj_buf.push_back(p);
+    }
+    w.bytes += 8 * (NSTATE * n + NFAC * nh);
+  }
+  double** B = w.adj_buf.data();
+  ArkTape tape;
+  for (int i = 0; i < 4; ++i) tape.Ydg[i] = B[i];
+  for (int i = 0; i < 3; ++i) tape.Ysol[i] = B[4 + i];
+  double* Uw = B[7];
+  double** yexb = B + 8;       // [i] adjoint of y^ex_i, i = 1..s+1
+  double** yimb = B + 13;      // [i] adjoint of y^im_i, i = 0..s
+  double** Rdgb = B + 17;      // [j] adjoint of R^DG_j, j = 1..s+1
+  double** Rhb = B + 22;       // [j] adjoint of R^HDG_j, j = 1..s
+  double* rhsb = B[26];
+  double* Yb = B[27];
+  for (int i = 0; i < 3; ++i) tape.Hsol[i] = B[NSTATE + i];
+  double* Hw = B[NSTATE + 3];
+  double** hb = B + NSTATE + 4; // [i] adjoint of Uhat_i, i = 1..s
+  // forward recompute with the tape
+  HIP_TRY(c, hipMemcpyAsync(Uw, U, n * 8, hipMemcpyDeviceToDevice, hs));
+  HIP_TRY(c, hipMemcpyAsync(Hw, Uhat, nh * 8, hipMemcpyDeviceToDevice, hs));
+  imex_status fs = ark_step_impl(c, tab, dt, Uw, Hw, nullptr, &tape);
+  if (fs != IMEX_OK) return fs;
+  for (int i = 8; i < NSTATE; ++i) HIP_TRY(c, hipMemsetAsync(B[i], 0, n * 8, hs));
+  for (int i = NSTATE + 4; i < NSTATE + NFAC; ++i) HIP_TRY(c, hipMemsetAsync(B[i], 0, nh * 8, hs));
+  HIP_TRY(c, hipMemsetAsync(Ubar, 0, n * 8, hs));
+  // the step's outputs: U_{n+1} = (y^ex_{s+1} | final update, y^im_s), Uhat_{n+1} = Uhat_s
+  HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Ubar_next, yimb[s]));
+  if (Uhatbar_next) HIP_TRY(c, launch_scale_copy(c, hb[s], hb[s], 1.0, Uhatbar_next, 1.0, nh));
+  if (tab->fsal) {
+    HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Ubar_next, yexb[s + 1]));
+  } else {
+    HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Ubar_next, Ubar));
+    for (int j = 1; j <= s + 1; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->be[j - 1], Ubar_next, Rdgb[j]));
+    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[s], Rdgb[s + 1], Yb));
+    HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, yexb[s + 1]));
+    HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[s]));
+  }
+  int gm_total = 0;
+  for (int i = s; i >= 1; --i) {
+    // (d) implicit stage i
+    HIP_TRY(c, hipMemsetAsync(rhsb, 0, n * 8, hs));
+    int its = 0;
+    imex_status r = hdg_stage_adjoint(c, dt * tab->Ai[3 * (i - 1) + (i - 1)], tape.Ysol[i - 1], tape.Hsol[i - 1],
+                                      Rhb[i], yimb[i], hb[i], rhsb, yexb[i + 1], &its);
+    if (r != IMEX_OK) return r;
+    gm_total += its;
+    // (c) right-hand side
+    HIP_TRY(c, launch_rows_axpy(c, 2, 1, 1.0, rhsb, Ubar));
+    for (int j = 1; j < i; ++j) HIP_TRY(c, launch_rows_axpy(c, 2, 3, -dt * tab->Ai[3 * (i - 1) + (j - 1)], rhsb, Rhb[j]));
+    // (b) explicit stage value y^ex_{i+1}
+    HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, yexb[i + 1], Ubar));
+    for (int j = 1; j <= i; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->Ae[4 * i + (j - 1)], yexb[i + 1], Rdgb[j]));
+    // (a) explicit residual of stage i at (y^ex_i, y^im_{i-1})
+    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[i - 1], Rdgb[i], Yb));
+    HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, i >= 2 ? yexb[i] : Ubar));
+    HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[i - 1]));
+  }
+  HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, yimb[0], Ubar));
+  HIP_TRY(c, hipStreamSynchronize(hs));
+  c->timers_resolve();
+  if (st) st->gmres_its = gm_total;
   return IMEX_OK;
 }
 

@@ -84,6 +84,9 @@ struct Workspace {
   double* vjp_pf = nullptr;     // [E][4][NQ][12] face-point adjoints (trace, physical gradient)
   double* vjp_pv = nullptr;     // [E][NQV][12] volume-point adjoints
   double* vjp_y[10] = {};       // stage states, their adjoints and scratch ([E][4][NN] each)
+  double* adj_P = nullptr;      // [n_hf][NFF][NFF] facet block-Jacobi factors of S^T
+  double* adj_w = nullptr;      // [E][4][NN] element scratch of the transposed solve
+  std::vector<double*> adj_buf; // step-adjoint tape and adjoints ([E][4][NN] or facet-sized)
   double* red = nullptr;        // reduction scratch
   double* hred = nullptr;       // pinned host reduction buffer
   size_t bytes = 0;
@@ -124,6 +127,9 @@ struct imex_ctx {
   int *d_im_list = nullptr, *d_ex_list = nullptr, *d_face_kind = nullptr, *d_efacet = nullptr;
   int *d_hf_side = nullptr, *d_hf_face = nullptr, *d_hf_elem = nullptr;
   int *d_win_off = nullptr, *d_win_slot = nullptr, *d_win_own = nullptr, *d_sr_flags = nullptr;
+  std::vector<int> ex_ifacet;           // [E][4] interface HDG facet across each face of explicit elements, or -1
+  int* d_ex_ifacet = nullptr;
+  bool adj_mode = false;                // GMRES solves S^T (reverse mode)
   imex::Workspace ws;
   std::string err;
   // hipGraph replay of each stage's explicit sequence (imex_set_graphs)
@@ -183,6 +189,9 @@ imex_status hdg_local_system(imex_ctx* c, double dt_a, const double* rhs, const 
                              double* f, double* h, double* K, double* C, double* D, double* E);
 size_t hdg_workspace_bytes(const imex_ctx* c);
 imex_status hdg_autotune_gemm(imex_ctx* c);
+imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const double* H, const double* Rhbar,
+                              double* ybar, double* hbar, double* rhsbar, double* yexbar, int* gmres_its);
+hipError_t launch_rows_axpy(const imex_ctx* c, int rows, int fac, double a, const double* in, double* out);
 // vjp.hip
 hipError_t vjp_alloc(imex_ctx* c);
 hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub);

@@ -1256,7 +1256,10 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
 // pos its inverse (both in LDS).  N <= 128.
 // ---------------------------------------------------------------------------
 template <int N> struct GJTile;
+template <> struct GJTile<8> { static constexpr int RT = 2, CT = 2; };
+template <> struct GJTile<12> { static constexpr int RT = 3, CT = 3; };
 template <> struct GJTile<16> { static constexpr int RT = 2, CT = 2; };
+template <> struct GJTile<20> { static constexpr int RT = 5, CT = 2; };
 template <> struct GJTile<36> { static constexpr int RT = 3, CT = 3; };
 template <> struct GJTile<40> { static constexpr int RT = 5, CT = 2; };
 template <> struct GJTile<60> { static constexpr int RT = 6, CT = 3; };
@@ -2098,6 +2101,224 @@ __global__ void __launch_bounds__(256) facet_update_kernel(int n, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Transposed stage system (reverse mode of the implicit stage, Sec. 4.3).  With
+// J = [[K C],[D E]] per element (HDG-MX: mixed block eliminated) and facet rows
+// assembled over the elements, J^T [lam; lamhat] = [a; ahat] is condensed as
+//   w = K^-T a,   S^T lamhat = ahat - sum_T C_T^T w_T,   lam = K^-T (a - D^T lamhat)
+// (S^T = E^T - C^T K^-T D^T), reusing K^-1 and the condensed blocks of the forward
+// path.  Element vectors use the full-state layout [e][v][n] (rows of implicit
+// elements), facet vectors the Uhat layout.
+// ---------------------------------------------------------------------------
+
+// out_e = K^-T in_e on implicit elements
+template <int K, class T>
+__global__ void __launch_bounds__(128) kinvT_kernel(DeviceHDG h, const T* __restrict__ Kinv,
+                                                    const double* __restrict__ in, double* __restrict__ out) {
+  constexpr int NU = 4 * (K + 1) * (K + 1);
+  __shared__ double a[NU];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const size_t e = h.im_list[p];
+  for (int i = tid; i < NU; i += blockDim.x) a[i] = in[e * NU + i];
+  __syncthreads();
+  const T* Kp = Kinv + (size_t)p * NU * NU;
+  for (int n = tid; n < NU; n += blockDim.x) {
+    double acc = 0.0;
+    for (int m = 0; m < NU; ++m) acc += (double)Kp[(size_t)m * NU + n] * a[m];
+    out[e * NU + n] = acc;
+  }
+}
+
+// out_F += coef sum_T (C_T^T v_T)|_F, v on implicit elements (full-state layout)
+template <int K, class T>
+__global__ void facet_CT_kernel(DeviceHDG h, size_t bs, const T* __restrict__ blk, const double* __restrict__ v,
+                                double coef, double* __restrict__ out) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_hf * NFF) return;
+  const int hf = t / NFF, j = t % NFF;
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int pe = h.hf_side[2 * hf + s];
+    if (pe < 0) continue;
+    const int lf = h.hf_face[2 * hf + s];
+    const T* B = blk + (size_t)pe * bs + NU + lf * NFF + j;
+    const double* vv = v + (size_t)h.im_list[pe] * NU;
+    for (int m = 0; m < NU; ++m) acc += (double)B[(size_t)m * NC] * vv[m];
+  }
+  out[t] += coef * acc;
+}
+
+// y = S^T x on the facets
+template <int K, class T>
+__global__ void facet_applyT_kernel(DeviceHDG h, size_t bs, const T* __restrict__ blk, const double* __restrict__ x,
+                                    double* __restrict__ y) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_hf * NFF) return;
+  const int hf = t / NFF, j = t % NFF;
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int pe = h.hf_side[2 * hf + s];
+    if (pe < 0) continue;
+    const int lf = h.hf_face[2 * hf + s];
+    const T* B = blk + (size_t)pe * bs + (size_t)NU * NC + NU + lf * NFF + j;      // column (lf, j) of S_T
+    for (int lg = 0; lg < 4; ++lg) {
+      const double* xg = x + (size_t)h.efacet[4 * pe + lg] * NFF;
+      for (int i = 0; i < NFF; ++i) acc += (double)B[(size_t)(lg * NFF + i) * NC] * xg[i];
+    }
+  }
+  y[t] = acc;
+}
+
+// lam_e = K^-T (a_e - D_T^T lamhat_T) on implicit elements
+template <int K, class T>
+__global__ void __launch_bounds__(128) backsubT_kernel(DeviceHDG h, size_t bs, const T* __restrict__ blk,
+                                                       const T* __restrict__ Kinv, const double* __restrict__ a,
+                                                       const double* __restrict__ lh, double* __restrict__ lam) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  __shared__ double xs[NF], tv[NU];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const size_t e = h.im_list[p];
+  for (int i = tid; i < NF; i += blockDim.x) xs[i] = lh[(size_t)h.efacet[4 * p + i / NFF] * NFF + i % NFF];
+  __syncthreads();
+  const T* B = blk + (size_t)p * bs;
+  for (int m = tid; m < NU; m += blockDim.x) {
+    double acc = a[e * NU + m];
+    for (int i = 0; i < NF; ++i) acc -= (double)B[(size_t)(NU + i) * NC + m] * xs[i];
+    tv[m] = acc;
+  }
+  __syncthreads();
+  const T* Kp = Kinv + (size_t)p * NU * NU;
+  for (int n = tid; n < NU; n += blockDim.x) {
+    double acc = 0.0;
+    for (int m = 0; m < NU; ++m) acc += (double)Kp[(size_t)m * NU + n] * tv[m];
+    lam[e * NU + n] = acc;
+  }
+}
+
+// Block-Jacobi preconditioner of S^T: P_F = ((sum_T S_T[F, F])^T)^-1 per facet (FP64)
+template <int K, class T>
+__global__ void __launch_bounds__(64) bjT_factor_kernel(DeviceHDG h, size_t bs, const T* __restrict__ blk,
+                                                        double* __restrict__ P) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  using G = GJ<NFF, double>;
+  __shared__ GJShared<NFF, double> sh;
+  const int hf = blockIdx.x, tid = threadIdx.x;
+  const bool own = G::owns(tid);
+  const int r0 = G::row0(tid), c0 = G::col0(tid);
+  double A[G::RT][G::CT];
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+    for (int j = 0; j < G::CT; ++j) {
+      double acc = 0.0;
+      if (own)
+        for (int s = 0; s < 2; ++s) {
+          const int pe = h.hf_side[2 * hf + s];
+          if (pe < 0) continue;
+          const int lf = h.hf_face[2 * hf + s];
+          // (S_FF)^T [r0+i][c0+j] = S_FF[c0+j][r0+i]
+          acc += (double)blk[(size_t)pe * bs + (size_t)(NU + lf * NFF + c0 + j) * NC + NU + lf * NFF + r0 + i];
+        }
+      A[i][j] = acc;
+    }
+  G::invert(A, sh, tid);
+  if (!own) return;
+  double* Pf = P + (size_t)hf * NFF * NFF;
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+    for (int j = 0; j < G::CT; ++j) Pf[(size_t)sh.pos[r0 + i] * NFF + sh.rp[c0 + j]] = A[i][j];
+}
+
+template <int K>
+__global__ void bjT_apply_kernel(int n_hf, const double* __restrict__ P, const double* __restrict__ x,
+                                 double* __restrict__ y) {
+  constexpr int NFF = 4 * (K + 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_hf * NFF) return;
+  const int hf = t / NFF, i = t % NFF;
+  const double* Pr = P + ((size_t)hf * NFF + i) * NFF;
+  const double* xf = x + (size_t)hf * NFF;
+  double acc = 0.0;
+  for (int j = 0; j < NFF; ++j) acc += Pr[j] * xf[j];
+  y[t] = acc;
+}
+
+// out_e += (K_T - M_T)^T v_e / (dt_a dts_e): adjoint of R^HDG's element rows through U
+template <int K, class T>
+__global__ void __launch_bounds__(128) elem_KT_kernel(DeviceMesh m, DeviceHDG h, size_t bs, const T* __restrict__ blk,
+                                                      double dt_a, const double* __restrict__ v,
+                                                      double* __restrict__ out) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NC = NU + NF + 1;
+  __shared__ double a[NU];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int e = h.im_list[p];
+  for (int i = tid; i < NU; i += blockDim.x) a[i] = v[(size_t)e * NU + i];
+  __syncthreads();
+  const T* B = blk + (size_t)p * bs;
+  const BasisTable& tb = *m.tab;
+  const double jac = 0.25 * m.hx[e] * m.hy[e];
+  const double sc = 1.0 / (dt_a * elem_dt(m, e));
+  for (int n = tid; n < NU; n += blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < NU; ++r) acc += (double)B[(size_t)r * NC + n] * a[r];
+    const int nn = n % NN;
+    acc -= tb.NW[nn % NP] * tb.NW[nn / NP] * jac * a[n];
+    out[(size_t)e * NU + n] += sc * acc;
+  }
+}
+
+// Adjoint of the interface Dirichlet rows int_F (Uhat - u^ex) . muhat: the explicit
+// element on the other side of each interface facet receives the transposed trace
+//   ybar_e[v][n] += sum_q w_q phi_n(x_q) sum_m L_m(x_q) lamhat[F][v][m]
+template <int K>
+__global__ void interfaceT_kernel(DeviceMesh m, const int* __restrict__ ex_ifacet, const double* __restrict__ lh,
+                                  double* __restrict__ ybar) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NFF = 4 * NP;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.E * NN) return;
+  const int e = t / NN, n = t % NN, a = n % NP, b = n / NP;
+  if (m.imp[e]) return;
+  const BasisTable& tb = *m.tab;
+  double acc[4] = {0, 0, 0, 0};
+  bool any = false;
+  for (int f = 0; f < 4; ++f) {
+    const int F = ex_ifacet[4 * e + f];
+    if (F < 0) continue;
+    any = true;
+    const int s = f & 1;
+    const double wl = (f < 2) ? 0.5 * m.hy[e] : 0.5 * m.hx[e];
+    const double* lf = lh + (size_t)F * NFF;
+    for (int q = 0; q < NQ; ++q) {
+      const double ph = (f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b];
+      const double w = tb.W[q] * wl * ph;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double lq = 0.0;
+        for (int mm = 0; mm < NP; ++mm) lq += tb.L[q][mm] * lf[v * NP + mm];
+        acc[v] += w * lq;
+      }
+    }
+  }
+  if (!any) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ybar[(size_t)e * 4 * NN + v * NN + n] += acc[v];
+}
+
+// out_e = in_e / (dt_a dts_e) on implicit elements
+template <int K>
+__global__ void rows_scale_kernel(DeviceMesh m, DeviceHDG h, double dt_a, const double* __restrict__ in,
+                                  double* __restrict__ out) {
+  constexpr int NU = 4 * (K + 1) * (K + 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_im * NU) return;
+  const int e = h.im_list[t / NU];
+  const size_t idx = (size_t)e * NU + t % NU;
+  out[idx] = in[idx] / (dt_a * elem_dt(m, e));
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 #define HDG_DISPATCH(KV, ...)                                   \
@@ -2356,6 +2577,12 @@ static hipError_t launch_ras_factor(imex_ctx* c) {
 
 static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
   Workspace& w = c->ws;
+  if (c->adj_mode) {
+    const int n = c->n_hf * 4 * c->NP;
+    HDG_DISPATCH(c->K, hipLaunchKernelGGL(bjT_apply_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                                          c->n_hf, w.adj_P, x, y));
+    return hipGetLastError();
+  }
   const int nsr = c->n_superrows;
   const int tp = c->timer_begin(TM_PRECOND);
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
@@ -2370,6 +2597,13 @@ static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
 }
 
 static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
+  if (c->adj_mode) {
+    const int n = c->n_hf * 4 * c->NP;
+    HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((facet_applyT_kernel<KK, LT>), dim3((n + 127) / 128),
+                                                          dim3(128), 0, c->stream, c->dhdg(), blk_stride(c),
+                                                          la<LT>(c->ws.blk), x, y)));
+    return hipGetLastError();
+  }
   HDG_DISPATCH(c->K, LA_DISPATCH(c, hipLaunchKernelGGL((facet_apply_kernel<KK, LT>), dim3(c->n_hf), dim3(64), 0,
                                                         c->stream, c->dhdg(), la<LT>(c->ws.blk), blk_stride(c), x,
                                                         y)));
@@ -2575,6 +2809,72 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     c->err = "Newton did not converge within newton_maxit";
     return IMEX_ENOCONV;
   }
+  return IMEX_OK;
+}
+
+// Reverse mode of one implicit stage at its converged state (Y: stage state, explicit rows
+// holding the interface data y^ex_{i+1}; H: facet state).  Given the adjoint Rhbar of
+// R^HDG_i (element rows) and the adjoints ybar (implicit rows of y^im_i, in/out) and hbar
+// (Uhat_i, in/out) it
+//   1. adds the transposed Jacobian of R^HDG: ybar += (K - M)^T Rhbar / dt_a,
+//      hbar += C^T Rhbar / dt_a;
+//   2. solves J^T [lam; lamhat] = [ybar; hbar] (condensed, GMRES on S^T with a facet
+//      block-Jacobi preconditioner);
+//   3. returns rhsbar = lam (the stage equation is M y + dt_a R - rhs = 0) and adds the
+//      adjoint of the interface data to yexbar (explicit rows).
+imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const double* H, const double* Rhbar,
+                              double* ybar, double* hbar, double* rhsbar, double* yexbar, int* gmres_its) {
+  Workspace& w = c->ws;
+  const int nh = c->n_hf * 4 * c->NP;
+  if (!w.adj_P) {
+    const size_t NFF = 4 * c->NP;
+    HTRY(hipMalloc(&w.adj_P, 8 * (size_t)c->n_hf * NFF * NFF));
+    HTRY(hipMalloc(&w.adj_w, 8 * (size_t)c->E * 4 * c->NN));
+    w.bytes += 8 * ((size_t)c->n_hf * NFF * NFF + (size_t)c->E * 4 * c->NN);
+  }
+  HTRY(launch_assemble(c, dt_a, Y, H, nullptr, 1, nullptr));
+  HTRY(launch_condense(c));
+  const int m = c->opt.gmres_restart;
+  double* b = w.gm + (size_t)nh * (m + 3);
+  double* lh = b + nh;
+  HDG_DISPATCH_ST(c->K, LA_DISPATCH(c, {
+    const LT* blk = la<LT>(w.blk);
+    const LT* Kinv = la<LT>(w.Kinv);
+    const size_t bs = blk_stride(c);
+    const int nfb = (nh + 127) / 128;
+    if (Rhbar) {
+      hipLaunchKernelGGL((elem_KT_kernel<KK, LT>), dim3(c->n_im), dim3(128), 0, c->stream, c->dmesh(), c->dhdg(), bs,
+                         blk, dt_a, Rhbar, ybar);
+      // hbar += C^T Rhbar / (dt_a dts_e): the element scale is folded into a scaled copy
+      hipLaunchKernelGGL(rows_scale_kernel<KK>, dim3((c->n_im * 4 * c->NN + 255) / 256), dim3(256), 0, c->stream,
+                         c->dmesh(), c->dhdg(), dt_a, Rhbar, w.adj_w);
+      hipLaunchKernelGGL((facet_CT_kernel<KK, LT>), dim3(nfb), dim3(128), 0, c->stream, c->dhdg(), bs, blk, w.adj_w,
+                         1.0, hbar);
+    }
+    // b = hbar - C^T K^-T ybar
+    hipLaunchKernelGGL((kinvT_kernel<KK, LT>), dim3(c->n_im), dim3(128), 0, c->stream, c->dhdg(), Kinv, ybar, w.adj_w);
+    HTRY(hipMemcpyAsync(b, hbar, sizeof(double) * nh, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL((facet_CT_kernel<KK, LT>), dim3(nfb), dim3(128), 0, c->stream, c->dhdg(), bs, blk, w.adj_w,
+                       -1.0, b);
+    hipLaunchKernelGGL((bjT_factor_kernel<KK, LT>), dim3(c->n_hf), dim3(64), 0, c->stream, c->dhdg(), bs, blk, w.adj_P);
+  }));
+  HTRY(hipGetLastError());
+  c->adj_mode = true;
+  const double rtol = c->opt.gmres_rtol;
+  c->opt.gmres_rtol = std::min(rtol, 1e-12);
+  int its = 0;
+  imex_status st = gmres(c, b, lh, &its);
+  c->opt.gmres_rtol = rtol;
+  c->adj_mode = false;
+  if (st != IMEX_OK) return st;
+  if (gmres_its) *gmres_its = its;
+  HDG_DISPATCH_ST(c->K, LA_DISPATCH(c, {
+    hipLaunchKernelGGL((backsubT_kernel<KK, LT>), dim3(c->n_im), dim3(128), 0, c->stream, c->dhdg(), blk_stride(c),
+                       la<LT>(w.blk), la<LT>(w.Kinv), ybar, lh, rhsbar);
+    hipLaunchKernelGGL(interfaceT_kernel<KK>, dim3((c->E * c->NN + 255) / 256), dim3(256), 0, c->stream, c->dmesh(),
+                       c->d_ex_ifacet, lh, yexbar);
+  }));
+  HTRY(hipGetLastError());
   return IMEX_OK;
 }
 

@@ -184,6 +184,25 @@ __global__ void rhs_accumulate_kernel(DeviceMesh m, DeviceHDG h, double b, const
   rhs[idx] += b * elem_dt(m, e) * R[idx];
 }
 
+// out += a f_e(n) in over the selected rows: rows 0 all, 1 explicit, 2 implicit elements;
+// f = 1 (fac 0), the nodal mass (1), dts_e / mass (2) or dts_e (3)
+template <int K>
+__global__ void rows_axpy_kernel(DeviceMesh m, int rows, int fac, double a, const double* __restrict__ in,
+                                 double* __restrict__ out) {
+  constexpr int NP = K + 1, NN = NP * NP;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.E * 4 * NN) return;
+  const int e = t / (4 * NN), n = t % NN;
+  if ((rows == 1 && m.imp[e]) || (rows == 2 && !m.imp[e])) return;
+  double f = 1.0;
+  if (fac) {
+    const BasisTable& tb = *m.tab;
+    const double mass = tb.NW[n % NP] * tb.NW[n / NP] * m.hx[e] * m.hy[e] * 0.25;
+    f = fac == 1 ? mass : (fac == 2 ? elem_dt(m, e) / mass : elem_dt(m, e));
+  }
+  out[t] += a * f * in[t];
+}
+
 #define IMEX_DISPATCH_K(KV, ...)                                \
   switch (KV) {                                                 \
     case 1: { constexpr int KK = 1; __VA_ARGS__; } break;       \
@@ -223,6 +242,13 @@ hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, d
   if (n == 0) return hipSuccess;
   IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(rhs_accumulate_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
                                            c->stream, c->dmesh(), c->dhdg(), b, R, rhs));
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_axpy(const imex_ctx* c, int rows, int fac, double a, const double* in, double* out) {
+  const int n = c->E * 4 * c->NN;
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(rows_axpy_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                                           c->dmesh(), rows, fac, a, in, out));
   return hipGetLastError();
 }
 

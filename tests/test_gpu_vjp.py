@@ -8,9 +8,11 @@ product must satisfy <Ubar, d> = <Rbar, J d>.
 
 * DG residual: interior, far-field and interface faces, viscous and inviscid.
 * One explicit ARK step: the oracle's explicit stage recursion on complex input.
+* One IMEX step with an implicit HDG-IP region (transposed condensed solves):
+  central differences of the GPU forward map and of the oracle's own step.
 * Rollout with checkpointed recomputation (torch.autograd.Function): gradients with
   and without checkpointing agree, and match central finite differences of the GPU
-  forward map (h = 1e-6).
+  forward map (h = 1e-6), explicit-only and with an implicit region.
 """
 import numpy as np
 import pytest
@@ -140,4 +142,79 @@ def test_rollout_checkpointing_and_fd():
     got = float((grads[0] * d).sum())
     err = abs(got - float(fd)) / abs(float(fd))
     print("rollout", got, float(fd), err)
+    assert err < 1e-6
+
+
+IMEX_CASES = {
+    "vortex_small": lambda: W.get("vortex_small"),
+    "square_ip_viscous": lambda: smooth_square(4, 2, viscous=True, variant=W.HDG_IP, implicit_rows=(1, 2)),
+    "bl_small_ip": lambda: W.boundary_layer(nx=4, ny=5, k=2, implicit_rows=2, Lx=4 * 2.0 / 256, height=None,
+                                            steps=1, name="bl_ip", hdg_variant=W.HDG_IP),
+}
+
+
+@pytest.mark.parametrize("case", list(IMEX_CASES))
+def test_imex_step_vjp(case):
+    wl = IMEX_CASES[case]()
+    eng = gpu_engine(wl, newton_rtol=1e-14, gmres_rtol=1e-13)
+    rng = np.random.default_rng(5)
+    # a generic point: the Lax-Friedrichs bound has kinks where the wave speeds of both
+    # sides tie, as in an exactly uniform free stream
+    U0 = eng.initial_state()
+    U0 = U0 * (1.0 + 1e-3 * torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda"))
+    H0 = eng.init_facets(U0)
+    c = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda")
+    d = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * float(U0.abs().max())
+    Ub = eng.vjp_imex_step(wl.dt, U0, H0, c)
+    got = float((Ub * d).sum())
+
+    def J(U):
+        U = U.clone()
+        H = eng.init_facets(U)
+        eng.ark_step(wl.dt, U, H)
+        return float((c * U).sum())
+    h = 1e-6
+    fd = (J(U0 + h * d) - J(U0 - h * d)) / (2 * h)
+    err = abs(got - fd) / abs(fd)
+    # the oracle's step (its own Newton and sparse direct solves)
+    cn, U0n, dn = c.cpu().numpy(), U0.cpu().numpy(), d.cpu().numpy()
+
+    def Jo(U):
+        ora = IMEXSolver(wl, U0=U)
+        ora.step()
+        return float(np.sum(cn * ora.U))
+    fdo = (Jo(U0n + 1e-5 * dn) - Jo(U0n - 1e-5 * dn)) / 2e-5
+    erro = abs(got - fdo) / abs(fdo)
+    print(case, got, fd, err, fdo, erro, eng.last_adjoint_stats)
+    assert err < 1e-6
+    assert erro < 1e-4
+
+
+def test_rollout_imex_checkpointing():
+    from paper_2607_16044_amd.autograd import ark_rollout
+    wl = W.get("vortex_small")
+    eng = gpu_engine(wl, newton_rtol=1e-14, gmres_rtol=1e-13)
+    rng = np.random.default_rng(9)
+    U0 = eng.initial_state()
+    U0 = U0 * (1.0 + 1e-3 * torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda"))
+    nsteps, record = 4, [2, 4]
+    w = torch.tensor(rng.standard_normal((len(record),) + tuple(U0.shape)), device="cuda")
+
+    def J(U, every):
+        return (ark_rollout(eng, U, wl.dt, nsteps, record, checkpoint=every) * w).sum()
+
+    grads = []
+    for every in (1, 3, 10):
+        U = U0.clone().requires_grad_(True)
+        J(U, every).backward()
+        grads.append(U.grad.detach().clone())
+    for g in grads[1:]:
+        assert torch.allclose(g, grads[0], rtol=0, atol=1e-12 * float(grads[0].abs().max()))
+    d = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * float(U0.abs().max())
+    h = 1e-6
+    with torch.no_grad():
+        fd = (J(U0 + h * d, 10) - J(U0 - h * d, 10)) / (2 * h)
+    got = float((grads[0] * d).sum())
+    err = abs(got - float(fd)) / abs(float(fd))
+    print("rollout imex", got, float(fd), err)
     assert err < 1e-6
