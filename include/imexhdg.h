@@ -143,6 +143,12 @@ imex_status imex_node_coords(const imex_ctx* ctx, double* x_host, double* y_host
  * interface_bilinearform_implicit_facet).  U dev (all elements), Uhat dev (out). */
 imex_status imex_init_facets(imex_ctx* ctx, const double* U, double* Uhat);
 
+/* Transpose of imex_init_facets (a linear map): Ubar += (dUhat/dU)^T Uhatbar, for
+ * runs whose facet state starts from the element traces.  Uhatbar dev [n_hf][4][k+1]
+ * (read); Ubar dev [E][4][(k+1)^2] (accumulated).  Deterministic (no atomics).
+ * Errors: EINVAL (null argument), ESTATE (regions not set). */
+imex_status imex_vjp_init_facets(imex_ctx* ctx, const double* Uhatbar, double* Ubar);
+
 /* Explicit DG-IP residual R^DG (Sec. 3.3, eq. bilinear_form_interior_sdg with the
  * far-field form of App. B.1.1 and the interface form of eq.
  * interface_bilinearform_explicit), with M dU/dt = -R.  U dev, all elements
@@ -216,10 +222,13 @@ imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, in
  * Ubar = (dR^DG/dU)^T Rbar, with R^DG as in imex_dg_residual.  U dev (all
  * elements); Rbar dev [e][v][n], rows of implicit elements ignored; Ubar dev out,
  * all elements (implicit elements receive the adjoint of their interface traces).
+ * With viscous HDG-MX coupling the implicit side's mixed variables are lifted
+ * from (U, Uhat) (Uhat dev, required) and Uhatbar (dev out, facets) receives
+ * their adjoint through the lifting; otherwise Uhat, Uhatbar may be NULL.
  * Point-wise flux Jacobians by forward-mode dual numbers, contracted with the
- * transposed basis; deterministic (no atomics).  Errors: ENOTIMPL when explicit
- * faces read HDG-MX mixed variables (viscous HDG-MX with an implicit region). */
-imex_status imex_vjp_dg_residual(imex_ctx* ctx, const double* U, const double* Rbar, double* Ubar);
+ * transposed basis; deterministic (no atomics).  Errors: EINVAL. */
+imex_status imex_vjp_dg_residual(imex_ctx* ctx, const double* U, const double* Uhat, const double* Rbar,
+                                 double* Ubar, double* Uhatbar);
 
 /* Reverse mode of one explicit ARK step (Sec. 4.2.2, explicit tableau of tab):
  * given the state U_n (dev, unchanged) and the adjoint Ubar_next of U_{n+1} (dev),
@@ -231,18 +240,20 @@ imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt,
 /* Reverse mode of one IMEX step (Alg. imex_scheme_update) with implicit region:
  * given the state (U dev, Uhat dev; unchanged) at t_n and the adjoints Ubar_next
  * (dev, all elements) and Uhatbar_next (dev, facets; nullable = 0) of the state
- * after the step, writes Ubar = adjoint of U_n (dev out, all elements); the
- * adjoint of Uhat_n is zero (it only seeds Newton).  The step is recomputed
+ * after the step, writes Ubar = adjoint of U_n (dev out, all elements) and
+ * Uhatbar = adjoint of Uhat_n (dev out, facets, nullable; zero except for HDG-MX,
+ * whose first explicit residual reads the mixed variables lifted from
+ * (U_n, Uhat_n); Uhat_n otherwise only seeds Newton).  The step is recomputed
  * from (U, Uhat) recording the stage values; each implicit stage is reversed
  * with the transposed condensed system at its converged state (K^-T, S^T by
  * GMRES with a facet block-Jacobi preconditioner, tolerance min(gmres_rtol,
  * 1e-12)), the explicit parts with imex_vjp_dg_residual.  Without an implicit
  * region this is imex_vjp_ark_step.  st host (nullable): gmres_its of the
- * transposed solves.  Errors: ENOTIMPL for HDG-MX coupling or implicit tableaux
+ * transposed solves.  Errors: ENOTIMPL for implicit tableaux
  * that are not stiffly accurate; as imex_ark_step. */
 imex_status imex_vjp_imex_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
                                const double* Uhat, const double* Ubar_next, const double* Uhatbar_next,
-                               double* Ubar, imex_stats* st);
+                               double* Ubar, double* Uhatbar, imex_stats* st);
 
 const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);

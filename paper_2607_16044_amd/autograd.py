@@ -1,8 +1,8 @@
 """torch.autograd wrappers of the engine's residual and time stepping.
 
 * DGResidual: R^DG(U) with the hand-written vector-Jacobian product as backward.
-* ARKRollout: nsteps IMEX ARK steps from U_0 (explicit-only or with an HDG-IP
-  implicit region; the facet state starts from the element traces) returning the
+* ARKRollout: nsteps IMEX ARK steps from U_0 (explicit-only or with an implicit
+  HDG region; the facet state starts from the element traces) returning the
   states at the steps listed in ``record``; the backward pass keeps only every
   ``checkpoint``-th (U, Uhat) from the forward pass and recomputes each segment
   from its checkpoint, then runs the step adjoints in reverse, adding the
@@ -64,6 +64,7 @@ class ARKRollout(torch.autograd.Function):
         eng, dt, nsteps, every = ctx.engine, ctx.dt, ctx.nsteps, ctx.every
         seed = {r: gout[i] for i, r in enumerate(ctx.record)}
         Ubar = torch.zeros_like(ctx.checkpoints[0][0])
+        Hbar = None
         if nsteps in seed:
             Ubar += seed[nsteps]
         starts = sorted(ctx.checkpoints)
@@ -79,10 +80,14 @@ class ARKRollout(torch.autograd.Function):
                 states.append((U, H))
             for n in range(c1 - 1, c0 - 1, -1):
                 U, H = states[n - c0]
-                # the facet state only seeds the Newton iterations: its adjoint is zero
-                Ubar = eng.vjp_imex_step(dt, U, H, Ubar.contiguous())
+                # the facet state seeds the Newton iterations and, for HDG-MX, the mixed
+                # variables of the first explicit residual: its adjoint travels with Ubar
+                Ubar, Hbar = eng.vjp_imex_step(dt, U, H, Ubar.contiguous(), Hbar, return_facets=True)
                 if n in seed:
                     Ubar += seed[n]
+        if Hbar is not None:
+            # the run's first facet state is init_facets(U_0)
+            Ubar = eng.vjp_init_facets(Hbar, Ubar.contiguous())
         return Ubar, None, None, None, None, None
 
 

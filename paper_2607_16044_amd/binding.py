@@ -25,7 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -87,9 +87,10 @@ def load_library(path: str = LIB_PATH):
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
-    lib.imex_vjp_dg_residual.argtypes = [P, P, P, P]
+    lib.imex_vjp_dg_residual.argtypes = [P, P, P, P, P, P]
+    lib.imex_vjp_init_facets.argtypes = [P, P, P]
     lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
-    lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, ctypes.POINTER(Stats)]
+    lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, P, ctypes.POINTER(Stats)]
     lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
     lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
     lib.imex_status_str.argtypes = [ctypes.c_int]
@@ -207,6 +208,12 @@ class Engine:
             self._check(self.lib.imex_init_facets(self.ctx, _ptr(U), _ptr(Uhat)))
         return Uhat
 
+    def vjp_init_facets(self, Uhatbar: torch.Tensor, Ubar: torch.Tensor) -> torch.Tensor:
+        """Ubar += (d init_facets / dU)^T Uhatbar (in place); returns Ubar."""
+        if Uhatbar.numel():
+            self._check(self.lib.imex_vjp_init_facets(self.ctx, _ptr(Uhatbar), _ptr(Ubar)))
+        return Ubar
+
     def dg_residual(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None) -> torch.Tensor:
         R = torch.empty_like(U)
         self._check(self.lib.imex_dg_residual(self.ctx, _ptr(U), _ptr(Uhat), _ptr(R)))
@@ -235,11 +242,13 @@ class Engine:
     def set_graphs(self, on: bool = True):
         self._check(self.lib.imex_set_graphs(self.ctx, int(bool(on))))
 
-    def vjp_dg_residual(self, U: torch.Tensor, Rbar: torch.Tensor) -> torch.Tensor:
-        """(dR^DG/dU)^T Rbar over all elements."""
+    def vjp_dg_residual(self, U: torch.Tensor, Rbar: torch.Tensor, Uhat: Optional[torch.Tensor] = None):
+        """(dR^DG/dU)^T Rbar over all elements; with Uhat (needed for HDG-MX coupling) also
+        returns the adjoint of Uhat: (Ubar, Uhatbar)."""
         Ubar = torch.empty_like(U)
-        self._check(self.lib.imex_vjp_dg_residual(self.ctx, _ptr(U), _ptr(Rbar), _ptr(Ubar)))
-        return Ubar
+        Hb = torch.zeros(self.facet_shape(), dtype=torch.float64, device=self.device) if Uhat is not None else None
+        self._check(self.lib.imex_vjp_dg_residual(self.ctx, _ptr(U), _ptr(Uhat), _ptr(Rbar), _ptr(Ubar), _ptr(Hb)))
+        return Ubar if Uhat is None else (Ubar, Hb)
 
     def vjp_ark_step(self, dt: float, U: torch.Tensor, Ubar_next: torch.Tensor) -> torch.Tensor:
         """(dU_{n+1}/dU_n)^T Ubar_next of one explicit ARK step from U_n = U (U unchanged)."""
@@ -250,15 +259,20 @@ class Engine:
         return Ubar
 
     def vjp_imex_step(self, dt: float, U: torch.Tensor, Uhat: Optional[torch.Tensor], Ubar_next: torch.Tensor,
-                      Uhatbar_next: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """Adjoint of U_n for one IMEX step from (U, Uhat) (both unchanged)."""
+                      Uhatbar_next: Optional[torch.Tensor] = None, return_facets: bool = False):
+        """Adjoint of U_n (and, with return_facets, of Uhat_n) for one IMEX step from
+        (U, Uhat) (both unchanged)."""
         Ubar = torch.empty_like(U)
+        Hb = None
+        if Uhat is not None and Uhat.numel():
+            Hb = torch.zeros_like(Uhat)
         st = Stats()
         tab = self.tableau.to_ctypes(Tableau)
         self._check(self.lib.imex_vjp_imex_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat),
-                                                _ptr(Ubar_next), _ptr(Uhatbar_next), _ptr(Ubar), ctypes.byref(st)))
+                                                _ptr(Ubar_next), _ptr(Uhatbar_next), _ptr(Ubar), _ptr(Hb),
+                                                ctypes.byref(st)))
         self.last_adjoint_stats = st.as_dict()
-        return Ubar
+        return (Ubar, Hb) if return_facets else Ubar
 
     def conservation_sums(self, U: torch.Tensor):
         out = (ctypes.c_double * 4)()

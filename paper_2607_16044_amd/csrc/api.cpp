@@ -563,6 +563,15 @@ imex_status imex_init_facets(imex_ctx* c, const double* U, double* Uhat) {
   return IMEX_OK;
 }
 
+imex_status imex_vjp_init_facets(imex_ctx* c, const double* Uhatbar, double* Ubar) {
+  if (!c || !Uhatbar || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (c->n_hf == 0) return IMEX_OK;
+  HIP_TRY(c, launch_init_facets_vjp(c, Uhatbar, Ubar));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
 static imex_status dg_residual_async(imex_ctx* c, const double* U, const double* Uhat, double* R) {
   const bool mx = c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
   if (mx && Uhat) HIP_TRY(c, launch_lift_mixed(c, U, Uhat, c->ws.Q));
@@ -810,12 +819,15 @@ static bool mx_coupled(const imex_ctx* c) {
   return c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
 }
 
-imex_status imex_vjp_dg_residual(imex_ctx* c, const double* U, const double* Rbar, double* Ubar) {
+imex_status imex_vjp_dg_residual(imex_ctx* c, const double* U, const double* Uhat, const double* Rbar, double* Ubar,
+                                 double* Uhatbar) {
   if (!c || !U || !Rbar || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
-  if (mx_coupled(c)) return fail(c, IMEX_ENOTIMPL, "residual adjoint through HDG-MX interface data");
+  if (mx_coupled(c) && (!Uhat || !Uhatbar)) return fail(c, IMEX_EINVAL, "HDG-MX coupling needs Uhat and Uhatbar");
   HIP_TRY(c, vjp_alloc(c));
-  HIP_TRY(c, launch_dg_vjp(c, U, Rbar, Ubar));
+  if (mx_coupled(c))
+    HIP_TRY(c, hipMemsetAsync(Uhatbar, 0, sizeof(double) * (size_t)c->n_hf * 4 * c->NP, c->stream));
+  HIP_TRY(c, launch_dg_vjp(c, U, Rbar, Ubar, mx_coupled(c) ? Uhat : nullptr, Uhatbar));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return IMEX_OK;
 }
@@ -880,17 +892,18 @@ imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, c
 //   (c) rhs_i = M U_n - dt sum_{j<i} a_ij R^HDG_j: adjoints of U_n and of R^HDG_j;
 //   (b) y^ex_{i+1} = U_n - dt M^-1 sum_{j<=i} ae_{i,j} R^DG_j: adjoints of U_n, R^DG_j;
 //   (a) R^DG_i = R^DG(y^ex_i, y^im_{i-1}): residual adjoint into both stage values.
-// Uhat_n enters only the Newton initial guess, so its adjoint is zero (HDG-IP).
+// Uhat_n enters the Newton initial guess and, for HDG-MX, the mixed variables read by
+// the first explicit residual; only the latter has an adjoint.
 imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, const double* U, const double* Uhat,
-                               const double* Ubar_next, const double* Uhatbar_next, double* Ubar,
+                               const double* Ubar_next, const double* Uhatbar_next, double* Ubar, double* Uhatbar,
                                imex_stats* st) {
   if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
   if (c->n_im == 0) return imex_vjp_ark_step(c, tab, dt, U, Ubar_next, Ubar);
   if (!Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
-  if (mx_coupled(c)) return fail(c, IMEX_ENOTIMPL, "step adjoint through HDG-MX interface data");
   if (!tab->stiffly_accurate) return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
+  const bool mx = mx_coupled(c);
   if (st) std::memset(st, 0, sizeof(*st));
   HIP_TRY(c, vjp_alloc(c));
   Workspace& w = c->ws;
@@ -930,6 +943,11 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   for (int i = 8; i < NSTATE; ++i) HIP_TRY(c, hipMemsetAsync(B[i], 0, n * 8, hs));
   for (int i = NSTATE + 4; i < NSTATE + NFAC; ++i) HIP_TRY(c, hipMemsetAsync(B[i], 0, nh * 8, hs));
   HIP_TRY(c, hipMemsetAsync(Ubar, 0, n * 8, hs));
+  if (Uhatbar) HIP_TRY(c, hipMemsetAsync(Uhatbar, 0, nh * 8, hs));
+  // HDG-MX: the explicit residual of stage i reads the mixed variables lifted from
+  // (y^im_{i-1}, Uhat_{i-1}); their adjoint goes to that facet state as well
+  auto hin = [&](int i) -> const double* { return i >= 2 ? tape.Hsol[i - 2] : Uhat; };
+  auto hout = [&](int i) -> double* { return i >= 2 ? hb[i - 1] : (Uhatbar ? Uhatbar : Hw); };
   // the step's outputs: U_{n+1} = (y^ex_{s+1} | final update, y^im_s), Uhat_{n+1} = Uhat_s
   HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Ubar_next, yimb[s]));
   if (Uhatbar_next) HIP_TRY(c, launch_scale_copy(c, hb[s], hb[s], 1.0, Uhatbar_next, 1.0, nh));
@@ -938,7 +956,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   } else {
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Ubar_next, Ubar));
     for (int j = 1; j <= s + 1; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->be[j - 1], Ubar_next, Rdgb[j]));
-    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[s], Rdgb[s + 1], Yb));
+    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[s], Rdgb[s + 1], Yb, mx ? tape.Hsol[s - 1] : nullptr, hb[s]));
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, yexb[s + 1]));
     HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[s]));
   }
@@ -958,7 +976,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, yexb[i + 1], Ubar));
     for (int j = 1; j <= i; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->Ae[4 * i + (j - 1)], yexb[i + 1], Rdgb[j]));
     // (a) explicit residual of stage i at (y^ex_i, y^im_{i-1})
-    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[i - 1], Rdgb[i], Yb));
+    HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[i - 1], Rdgb[i], Yb, mx ? hin(i) : nullptr, hout(i)));
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, i >= 2 ? yexb[i] : Ubar));
     HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[i - 1]));
   }
@@ -1016,7 +1034,8 @@ void imex_destroy(imex_ctx* c) {
     if (w.Rstage[r]) hipFree(w.Rstage[r]);
     w.Rstage[r] = nullptr;
   }
-  for (double** p : {&w.vjp_tu, &w.vjp_tr, &w.vjp_pf, &w.vjp_pv}) {
+  for (double** p : {&w.vjp_tu, &w.vjp_tr, &w.vjp_pf, &w.vjp_pv, &w.vjp_tq, &w.vjp_pq, &w.vjp_qb, &w.vjp_q,
+                     &w.vjp_hb}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

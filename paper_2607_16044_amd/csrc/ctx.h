@@ -84,6 +84,11 @@ struct Workspace {
   double* vjp_pf = nullptr;     // [E][4][NQ][12] face-point adjoints (trace, physical gradient)
   double* vjp_pv = nullptr;     // [E][NQV][12] volume-point adjoints
   double* vjp_y[10] = {};       // stage states, their adjoints and scratch ([E][4][NN] each)
+  double* vjp_tq = nullptr;     // [E][4][NQ][5] face traces of the mixed variables (HDG-MX)
+  double* vjp_pq = nullptr;     // [E][4][NQ][5] their adjoints
+  double* vjp_qb = nullptr;     // [E][5][NN] adjoint of the mixed variables
+  double* vjp_q = nullptr;      // [E][5][NN] lifted mixed variables
+  double* vjp_hb = nullptr;     // [n_im][4][4][NP] element shares of the facet adjoint
   double* adj_P = nullptr;      // [n_hf][NFF][NFF] facet block-Jacobi factors of S^T
   double* adj_w = nullptr;      // [E][4][NN] element scratch of the transposed solve
   std::vector<double*> adj_buf; // step-adjoint tape and adjoints ([E][4][NN] or facet-sized)
@@ -179,6 +184,7 @@ hipError_t launch_scale_copy(const imex_ctx* c, const double* src, double* dst, 
 bool dg_tile_valid(int K, int et);
 // hdg.hip
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
+hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* Ub);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);
 hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, double* rhs);
@@ -192,8 +198,11 @@ imex_status hdg_autotune_gemm(imex_ctx* c);
 imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const double* H, const double* Rhbar,
                               double* ybar, double* hbar, double* rhsbar, double* yexbar, int* gmres_its);
 hipError_t launch_rows_axpy(const imex_ctx* c, int rows, int fac, double a, const double* in, double* out);
+hipError_t launch_lift_vjp(const imex_ctx* c, const double* U, const double* Uhat, const double* Qb, double* Ub,
+                           double* Hb, double* Uhatbar);
 // vjp.hip
 hipError_t vjp_alloc(imex_ctx* c);
-hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub);
+hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub, const double* Uhat = nullptr,
+                         double* Uhatbar = nullptr);
 imex_status hdg_alloc(imex_ctx* c);
 }  // namespace imex

@@ -54,6 +54,36 @@ __global__ void init_facets_kernel(DeviceMesh m, DeviceHDG h, const double* __re
   Uhat[t] = acc / cnt;
 }
 
+// Transpose of init_facets_kernel for the sides on local face fpass:
+// Ub[e] += (trace_f)^T Uhatbar[hf] / cnt.  An element has one face fpass, so within a
+// pass every element node has at most one writer; the four passes run in stream order.
+template <int K>
+__global__ void init_facets_vjp_kernel(DeviceMesh m, DeviceHDG h, int fpass, const double* __restrict__ Hb,
+                                       double* __restrict__ Ub) {
+  constexpr int NP = K + 1, NN = NP * NP;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_hf * 2 * 4 * NN) return;
+  const int n = t % NN, v = (t / NN) % 4, s = (t / (4 * NN)) % 2, hf = t / (8 * NN);
+  const int e = h.hf_elem[2 * hf + s];
+  if (e < 0 || h.hf_face[2 * hf + s] != fpass) return;
+  int nexp = 0;
+  for (int q = 0; q < 2; ++q) {
+    const int eq = h.hf_elem[2 * hf + q];
+    if (eq >= 0 && !m.imp[eq]) ++nexp;
+  }
+  if (nexp > 0 && m.imp[e]) return;                // interface facet: explicit trace only
+  int cnt = 0;
+  for (int q = 0; q < 2; ++q) {
+    const int eq = h.hf_elem[2 * hf + q];
+    if (eq >= 0 && !(nexp > 0 && m.imp[eq])) ++cnt;
+  }
+  const int a = n % NP, b = n / NP;
+  const double* hb = Hb + ((size_t)hf * 4 + v) * NP;
+  // x faces (0, 1) interpolate along a at face node b; y faces (2, 3) along b at node a
+  const double coef = fpass < 2 ? m.tab->LE[fpass & 1][a] * hb[b] : m.tab->LE[fpass & 1][b] * hb[a];
+  Ub[((size_t)e * 4 + v) * NN + n] += coef / cnt;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG h, Gas g,
                                                          const double* __restrict__ U,
@@ -135,6 +165,114 @@ __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) Q[(size_t)e * 5 * NN + cc * NN + n] = -l[cc] / (fac[cc] * mass);
   }
+}
+
+// Reverse mode of the lifting Q = Q(U, Uhat) above: given Qbar [e][5][NN] on implicit
+// elements, adds the adjoint of U to Ubar (implicit rows) and writes this element's
+// share of the facet adjoint, Hb[p][f][v][m] (summed over both sides by
+// facet_gather_kernel).  l_c[n] = -fac_c mass_n Q_c[n] is linear in the primitives
+// (u, v, theta) at the volume points (weights w dphi_n/dx_d) and at the face points
+// (weights -w phi_n n_d); the primitives' Jacobians come from dual numbers.
+template <int K>
+__global__ void __launch_bounds__(64) lift_vjp_kernel(DeviceMesh m, DeviceHDG h, Gas g, const double* __restrict__ U,
+                                                      const double* __restrict__ Uhat, const double* __restrict__ Qb,
+                                                      double* __restrict__ Ub, double* __restrict__ Hb) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NQV = NQ * NQ;
+  __shared__ double sU[4 * NN];
+  __shared__ double lb[5][NN];
+  __shared__ double sWb[NQV][4];
+  __shared__ double sHb[4][NQ][4];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int e = h.im_list[p];
+  const BasisTable& tb = *m.tab;
+  const double hx = m.hx[e], hy = m.hy[e], sx = 2.0 / hx, sy = 2.0 / hy, jac = 0.25 * hx * hy;
+  const double fac[5] = {1.0, 2.0, 1.0, 1.0, 1.0};
+  for (int i = tid; i < 4 * NN; i += blockDim.x) sU[i] = U[(size_t)e * 4 * NN + i];
+  for (int i = tid; i < 5 * NN; i += blockDim.x) {
+    const int c = i / NN, n = i % NN;
+    const double mass = tb.NW[n % NP] * tb.NW[n / NP] * jac;
+    lb[c][n] = -Qb[(size_t)e * 5 * NN + i] / (fac[c] * mass);
+  }
+  __syncthreads();
+  using D4 = Dual<4>;
+  for (int qv = tid; qv < NQV; qv += blockDim.x) {
+    const int qi = qv % NQ, qj = qv / NQ;
+    double W[4] = {0, 0, 0, 0}, pb[3] = {0, 0, 0};
+    const double w = tb.W[qi] * tb.W[qj] * jac;
+    for (int b = 0; b < NP; ++b)
+      for (int a = 0; a < NP; ++a) {
+        const int n = a + NP * b;
+        const double ph = tb.L[qi][a] * tb.L[qj][b];
+        const double px = w * tb.D[qi][a] * tb.L[qj][b] * sx, py = w * tb.L[qi][a] * tb.D[qj][b] * sy;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) W[v] += ph * sU[v * NN + n];
+        pb[0] += lb[0][n] * (2.0 / 3.0) * px + lb[1][n] * py - lb[2][n] * (1.0 / 3.0) * px;
+        pb[1] += -lb[0][n] * (1.0 / 3.0) * py + lb[1][n] * px + lb[2][n] * (2.0 / 3.0) * py;
+        pb[2] += lb[3][n] * px + lb[4][n] * py;
+      }
+    D4 Wd[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { Wd[v] = D4(W[v]); Wd[v].d[v] = 1.0; }
+    const Prim<D4> P = primitives(Wd, g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sWb[qv][v] = pb[0] * P.u.d[v] + pb[1] * P.v.d[v] + pb[2] * P.theta.d[v];
+  }
+  for (int i = tid; i < 4 * NQ; i += blockDim.x) {
+    const int f = i / NQ, q = i % NQ, s = f & 1;
+    const int hf = h.efacet[4 * p + f];
+    const double nx = (f == 0) ? -1.0 : (f == 1 ? 1.0 : 0.0);
+    const double ny = (f == 2) ? -1.0 : (f == 3 ? 1.0 : 0.0);
+    const double w = tb.W[q] * ((f < 2) ? 0.5 * hy : 0.5 * hx);
+    double W[4] = {0, 0, 0, 0};
+    for (int mm = 0; mm < NP; ++mm)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[v] += tb.L[q][mm] * Uhat[((size_t)hf * 4 + v) * NP + mm];
+    double pb[3] = {0, 0, 0};
+    for (int b = 0; b < NP; ++b)
+      for (int a = 0; a < NP; ++a) {
+        const int n = a + NP * b;
+        const double ph = -w * ((f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b]);
+        pb[0] += ph * (lb[0][n] * (2.0 / 3.0) * nx + lb[1][n] * ny - lb[2][n] * (1.0 / 3.0) * nx);
+        pb[1] += ph * (-lb[0][n] * (1.0 / 3.0) * ny + lb[1][n] * nx + lb[2][n] * (2.0 / 3.0) * ny);
+        pb[2] += ph * (lb[3][n] * nx + lb[4][n] * ny);
+      }
+    D4 Wd[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { Wd[v] = D4(W[v]); Wd[v].d[v] = 1.0; }
+    const Prim<D4> P = primitives(Wd, g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sHb[f][q][v] = pb[0] * P.u.d[v] + pb[1] * P.v.d[v] + pb[2] * P.theta.d[v];
+  }
+  __syncthreads();
+  for (int i = tid; i < 16 * NP; i += blockDim.x) {
+    const int f = i / (4 * NP), v = (i / NP) % 4, mm = i % NP;
+    double acc = 0.0;
+    for (int q = 0; q < NQ; ++q) acc += tb.L[q][mm] * sHb[f][q][v];
+    Hb[(size_t)p * 16 * NP + i] = acc;
+  }
+  for (int i = tid; i < 4 * NN; i += blockDim.x) {
+    const int v = i / NN, n = i % NN, a = n % NP, b = n / NP;
+    double acc = 0.0;
+    for (int qj = 0; qj < NQ; ++qj)
+      for (int qi = 0; qi < NQ; ++qi) acc += tb.L[qi][a] * tb.L[qj][b] * sWb[qi + NQ * qj][v];
+    Ub[(size_t)e * 4 * NN + i] += acc;
+  }
+}
+
+// out[F][v][m] += sum over the implicit sides T of F of Hb[T][face of F][v][m]
+template <int K>
+__global__ void facet_gather_kernel(DeviceHDG h, const double* __restrict__ Hb, double* __restrict__ out) {
+  constexpr int NFF = 4 * (K + 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_hf * NFF) return;
+  const int hf = t / NFF, j = t % NFF;
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int pe = h.hf_side[2 * hf + s];
+    if (pe < 0) continue;
+    acc += Hb[((size_t)pe * 4 + h.hf_face[2 * hf + s]) * NFF + j];
+  }
+  out[t] += acc;
 }
 
 // rhs = M U_n on implicit elements (the remaining terms are added by axpy)
@@ -220,6 +358,15 @@ hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat) 
   return hipGetLastError();
 }
 
+hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* Ub) {
+  const int n = c->n_hf * 2 * 4 * c->NN;
+  if (n == 0) return hipSuccess;
+  for (int f = 0; f < 4; ++f)
+    IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(init_facets_vjp_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
+                                             c->stream, c->dmesh(), c->dhdg(), f, Hb, Ub));
+  return hipGetLastError();
+}
+
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q) {
   if (c->n_im == 0) return hipSuccess;
   IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(lift_mixed_kernel<KK>, dim3(c->n_im), dim3(64), 0, c->stream, c->dmesh(),
@@ -242,6 +389,19 @@ hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, d
   if (n == 0) return hipSuccess;
   IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(rhs_accumulate_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
                                            c->stream, c->dmesh(), c->dhdg(), b, R, rhs));
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_vjp(const imex_ctx* c, const double* U, const double* Uhat, const double* Qb, double* Ub,
+                           double* Hb, double* Uhatbar) {
+  if (c->n_im == 0) return hipSuccess;
+  const int nh = c->n_hf * 4 * c->NP;
+  IMEX_DISPATCH_K(c->K, {
+    hipLaunchKernelGGL(lift_vjp_kernel<KK>, dim3(c->n_im), dim3(64), 0, c->stream, c->dmesh(), c->dhdg(), c->gas, U,
+                       Uhat, Qb, Ub, Hb);
+    hipLaunchKernelGGL(facet_gather_kernel<KK>, dim3((nh + 255) / 256), dim3(256), 0, c->stream, c->dhdg(), Hb,
+                       Uhatbar);
+  });
   return hipGetLastError();
 }
 

@@ -54,7 +54,8 @@ __device__ inline void vjp_face_interp(const BasisTable& T, int f, int q, const 
 template <int K>
 __global__ void __launch_bounds__(256) vjp_trace_kernel(DeviceMesh m, const double* __restrict__ U,
                                                         const double* __restrict__ Rb, double* __restrict__ TU,
-                                                        double* __restrict__ TR) {
+                                                        double* __restrict__ TR, const double* __restrict__ Q,
+                                                        double* __restrict__ TQ) {
   constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.E * 4 * NQ) return;
@@ -65,6 +66,17 @@ __global__ void __launch_bounds__(256) vjp_trace_kernel(DeviceMesh m, const doub
   for (int i = 0; i < 12; ++i) TU[(size_t)t * 12 + i] = o[i];
   if (m.imp[e]) {
     for (int i = 0; i < 12; ++i) TR[(size_t)t * 12 + i] = 0.0;
+    if (Q) {                         // HDG-MX: trace of the mixed variables
+      const int s = f & 1;
+      const double* qe = Q + (size_t)e * 5 * NN;
+      for (int c = 0; c < 5; ++c) {
+        double acc = 0.0;
+        for (int b = 0; b < NP; ++b)
+          for (int a = 0; a < NP; ++a)
+            acc += ((f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b]) * qe[c * NN + a + NP * b];
+        TQ[(size_t)t * 5 + c] = acc;
+      }
+    }
   } else {
     vjp_face_interp<K>(tb, f, q, Rb + (size_t)e * 4 * NN, o);
     for (int i = 0; i < 12; ++i) TR[(size_t)t * 12 + i] = o[i];
@@ -150,11 +162,56 @@ __device__ inline void face_point_adjoint(int side, int kind, const double Uo[4]
   }
 }
 
+// side 1 with an HDG-MX implicit element: its viscous flux is F^nu(U, eps, phi) with the
+// lifted mixed variables Q = (eps, phi); X = (trace U, trace Q), adjoints to xb[0..3], qb[0..4]
+__device__ inline void face_point_adjoint_mx(int kind, const double Uo[4], const double Go[4][2],
+                                             const double UN[4], const double QN[5], double nx, double ny,
+                                             double tau, int lf, const Gas& g, const double sb[4],
+                                             const double gb[4][2], double xb[12], double qb[5]) {
+  using D4 = Dual<4>;
+  for (int ch = 0; ch < 3; ++ch) {
+    D4 Xu[4], Xq[5], A[4], AG[4][2], fnn[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Xu[v] = D4(UN[v]);
+      const int idx = v - 4 * ch;
+      if (idx >= 0 && idx < 4) Xu[v].d[idx] = 1.0;
+      A[v] = D4(Uo[v]);
+      AG[v][0] = D4(Go[v][0]);
+      AG[v][1] = D4(Go[v][1]);
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Xq[c] = D4(QN[c]);
+      const int idx = 4 + c - 4 * ch;
+      if (idx >= 0 && idx < 4) Xq[c].d[idx] = 1.0;
+    }
+    D4 Fn[4][2];
+    visc_flux_mx(Xu, Xq, Xq + 3, g, Fn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fnn[v] = Fn[v][0] * nx + Fn[v][1] * ny;
+    D4 s[4], gc[4][2];
+    dg_face_point(kind, A, AG, Xu, fnn, nx, ny, tau, lf, g, s, gc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int col = 4 * ch + k;
+      if (col >= 9) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc += sb[v] * s[v].d[k] + gb[v][0] * gc[v][0].d[k] + gb[v][1] * gc[v][1].d[k];
+      if (col < 4) xb[col] += acc;
+      else qb[col - 4] += acc;
+    }
+  }
+}
+
 // 2. face-point adjoints PF[e][f][q][12]: (trace adjoint 4, physical-gradient adjoint [v][d] 8)
+//    and, for HDG-MX implicit elements, PQ[e][f][q][5] (adjoint of the trace of Q)
 template <int K>
 __global__ void __launch_bounds__(128) vjp_face_kernel(DeviceMesh m, Gas g, int lf, double alpha,
                                                        const double* __restrict__ TU, const double* __restrict__ TR,
-                                                       double* __restrict__ PF) {
+                                                       double* __restrict__ PF, const double* __restrict__ TQ,
+                                                       double* __restrict__ PQ) {
   constexpr int NQ = (3 * K + 2) / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.E * 4 * NQ) return;
@@ -192,8 +249,49 @@ __global__ void __launch_bounds__(128) vjp_face_kernel(DeviceMesh m, Gas g, int 
     double sb[4], gb[4][2];
 #pragma unroll
     for (int v = 0; v < 4; ++v) { sb[v] = w * tr[v]; gb[v][0] = w * sx * tr[4 + v]; gb[v][1] = w * sy * tr[8 + v]; }
-    face_point_adjoint(0, kind, Uo, Go, UN, GN, nx, ny, tau, lf, g, sb, gb, xb);
+    if (TQ && kind == DGF_INTERFACE) {
+      // the HDG-MX neighbour's viscous flux uses its mixed variables (fixed here)
+      const double* tq = TQ + (((size_t)nb * 4 + (f ^ 1)) * NQ + q) * 5;
+      double Fn[4][2], fnn[4];
+      visc_flux_mx(UN, tq, tq + 3, g, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fnn[v] = Fn[v][0] * nx + Fn[v][1] * ny;
+      using D4 = Dual<4>;
+      const int nchunk = g.viscous ? 3 : 1;
+      for (int ch = 0; ch < nchunk; ++ch) {
+        D4 A[4], AG[4][2], B[4], FN[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          A[v] = D4(Uo[v]);
+          int idx = v - 4 * ch;
+          if (idx >= 0 && idx < 4) A[v].d[idx] = 1.0;
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            AG[v][d] = D4(Go[v][d]);
+            idx = 4 + 2 * v + d - 4 * ch;
+            if (idx >= 0 && idx < 4) AG[v][d].d[idx] = 1.0;
+          }
+          B[v] = D4(UN[v]);
+          FN[v] = D4(fnn[v]);
+        }
+        D4 so[4], go[4][2];
+        dg_face_point(kind, A, AG, B, FN, nx, ny, tau, lf, g, so, go);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int col = 4 * ch + k;
+          if (col >= 12) break;
+          double acc = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc += sb[v] * so[v].d[k] + gb[v][0] * go[v][0].d[k] + gb[v][1] * go[v][1].d[k];
+          xb[col] += acc;
+        }
+      }
+    } else {
+      face_point_adjoint(0, kind, Uo, Go, UN, GN, nx, ny, tau, lf, g, sb, gb, xb);
+    }
   }
+  double qb[5] = {0, 0, 0, 0, 0};
   if (nb >= 0 && !m.imp[nb]) {
     // the explicit neighbour's integrand on the same face, seen from its side
     const int kind = m.imp[e] ? DGF_INTERFACE : DGF_INTERIOR;
@@ -206,11 +304,17 @@ __global__ void __launch_bounds__(128) vjp_face_kernel(DeviceMesh m, Gas g, int 
 #pragma unroll
     for (int v = 0; v < 4; ++v) { sb[v] = w * tr[v]; gb[v][0] = w * sxn * tr[4 + v]; gb[v][1] = w * syn * tr[8 + v]; }
     // for the neighbour, "own" is its trace, "neighbour" is this element's
-    face_point_adjoint(1, kind, UN, GN, Uo, Go, -nx, -ny, tau, lf, g, sb, gb, xb);
+    if (TQ && m.imp[e])
+      face_point_adjoint_mx(kind, UN, GN, Uo, TQ + (size_t)t * 5, -nx, -ny, tau, lf, g, sb, gb, xb, qb);
+    else
+      face_point_adjoint(1, kind, UN, GN, Uo, Go, -nx, -ny, tau, lf, g, sb, gb, xb);
   }
   double* out = PF + (size_t)t * 12;
 #pragma unroll
   for (int i = 0; i < 12; ++i) out[i] = xb[i];
+  if (PQ && m.imp[e])
+#pragma unroll
+    for (int c = 0; c < 5; ++c) PQ[(size_t)t * 5 + c] = qb[c];
 }
 
 // 3. volume-point adjoints PV[e][qv][12] of explicit elements: F = F^nu(U, G) - F^c(U)
@@ -338,6 +442,29 @@ __global__ void __launch_bounds__(256) vjp_contract_kernel(DeviceMesh m, const d
   for (int v = 0; v < 4; ++v) Ub[(size_t)e * 4 * NN + v * NN + n] = r[v];
 }
 
+// Qbar[e][c][n] = sum over face points of phi_n PQ[e][f][q][c] (HDG-MX implicit elements)
+template <int K>
+__global__ void vjp_qcontract_kernel(DeviceMesh m, const double* __restrict__ PQ, double* __restrict__ Qb) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.E * NN) return;
+  const int e = t / NN, n = t % NN, a = n % NP, b = n / NP;
+  if (!m.imp[e]) return;
+  const BasisTable& tb = *m.tab;
+  double r[5] = {0, 0, 0, 0, 0};
+  for (int f = 0; f < 4; ++f) {
+    const int s = f & 1;
+    for (int q = 0; q < NQ; ++q) {
+      const double ph = (f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b];
+      const double* pq = PQ + (((size_t)e * 4 + f) * NQ + q) * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) r[c] += ph * pq[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) Qb[(size_t)e * 5 * NN + c * NN + n] = r[c];
+}
+
 #define VJP_DISPATCH(KV, ...)                                   \
   switch (KV) {                                                 \
     case 1: { constexpr int KK = 1; __VA_ARGS__; } break;       \
@@ -357,24 +484,46 @@ hipError_t vjp_alloc(imex_ctx* c) {
   if (e == hipSuccess) e = hipMalloc(&w.vjp_pf, 8 * nf);
   if (e == hipSuccess) e = hipMalloc(&w.vjp_pv, 8 * nv);
   for (int i = 0; i < 10 && e == hipSuccess; ++i) e = hipMalloc(&w.vjp_y[i], 8 * es);
-  if (e == hipSuccess) w.bytes += 8 * (3 * nf + nv + 10 * es);
+  if (e == hipSuccess) e = hipMalloc(&w.vjp_tq, 8 * E * 4 * NQ * 5);
+  if (e == hipSuccess) e = hipMalloc(&w.vjp_pq, 8 * E * 4 * NQ * 5);
+  if (e == hipSuccess) e = hipMalloc(&w.vjp_qb, 8 * E * 5 * NN);
+  if (e == hipSuccess) e = hipMalloc(&w.vjp_q, 8 * E * 5 * NN);
+  if (e == hipSuccess) e = hipMalloc(&w.vjp_hb, 8 * std::max<size_t>((size_t)c->n_im * 16 * c->NP, 1));
+  if (e == hipSuccess) e = hipMemsetAsync(w.vjp_q, 0, 8 * E * 5 * NN, c->stream);
+  if (e == hipSuccess) w.bytes += 8 * (3 * nf + nv + 10 * es + 2 * E * 4 * NQ * 5 + 2 * E * 5 * NN);
   return e;
 }
 
-hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub) {
+// Ubar = (dR^DG/dU)^T Rbar; with HDG-MX coupling (Uhat given) the implicit side's mixed
+// variables are lifted from (U, Uhat) and their adjoint is taken back through the lifting:
+// Ubar (implicit rows) and Uhatbar (added) receive it.
+hipError_t launch_dg_vjp(imex_ctx* c, const double* U, const double* Rb, double* Ub, const double* Uhat,
+                         double* Uhatbar) {
   Workspace& w = c->ws;
   const int nfp = c->E * 4 * c->NQ, nvp = c->E * c->NQ * c->NQ, nn = c->E * c->NN;
   const int lf = c->opt.dg_flux == IMEX_FLUX_LAX_FRIEDRICHS;
+  const bool mx = Uhat && c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
+  if (mx) {
+    hipError_t e = launch_lift_mixed(c, U, Uhat, w.vjp_q);
+    if (e != hipSuccess) return e;
+  }
+  double* TQ = mx ? w.vjp_tq : nullptr;
+  double* PQ = mx ? w.vjp_pq : nullptr;
   VJP_DISPATCH(c->K, {
     hipLaunchKernelGGL(vjp_trace_kernel<KK>, dim3((nfp + 255) / 256), dim3(256), 0, c->stream, c->dmesh(), U, Rb,
-                       w.vjp_tu, w.vjp_tr);
+                       w.vjp_tu, w.vjp_tr, mx ? w.vjp_q : nullptr, TQ);
     hipLaunchKernelGGL(vjp_face_kernel<KK>, dim3((nfp + 127) / 128), dim3(128), 0, c->stream, c->dmesh(), c->gas, lf,
-                       c->opt.alpha_dg, w.vjp_tu, w.vjp_tr, w.vjp_pf);
+                       c->opt.alpha_dg, w.vjp_tu, w.vjp_tr, w.vjp_pf, TQ, PQ);
     hipLaunchKernelGGL(vjp_volume_kernel<KK>, dim3((nvp + 127) / 128), dim3(128), 0, c->stream, c->dmesh(), c->gas,
                        U, Rb, w.vjp_pv);
     hipLaunchKernelGGL(vjp_contract_kernel<KK>, dim3((nn + 255) / 256), dim3(256), 0, c->stream, c->dmesh(),
                        w.vjp_pv, w.vjp_pf, Ub);
+    if (mx) {
+      hipLaunchKernelGGL(vjp_qcontract_kernel<KK>, dim3((nn + 255) / 256), dim3(256), 0, c->stream, c->dmesh(), PQ,
+                         w.vjp_qb);
+    }
   });
+  if (mx) return launch_lift_vjp(c, U, Uhat, w.vjp_qb, Ub, w.vjp_hb, Uhatbar);
   return hipGetLastError();
 }
 

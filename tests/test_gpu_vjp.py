@@ -8,11 +8,14 @@ product must satisfy <Ubar, d> = <Rbar, J d>.
 
 * DG residual: interior, far-field and interface faces, viscous and inviscid.
 * One explicit ARK step: the oracle's explicit stage recursion on complex input.
-* One IMEX step with an implicit HDG-IP region (transposed condensed solves):
+* DG residual at an HDG-MX interface: adjoints of U and of the facet state through the
+  lifted mixed variables.
+* One IMEX step with an implicit HDG-IP or HDG-MX region (transposed condensed solves):
   central differences of the GPU forward map and of the oracle's own step.
+* Transpose of the facet initialisation (dot-product identity).
 * Rollout with checkpointed recomputation (torch.autograd.Function): gradients with
   and without checkpointing agree, and match central finite differences of the GPU
-  forward map (h = 1e-6), explicit-only and with an implicit region.
+  forward map (h = 1e-6), explicit-only and with HDG-IP and HDG-MX regions.
 """
 import numpy as np
 import pytest
@@ -145,7 +148,68 @@ def test_rollout_checkpointing_and_fd():
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("case,h,bar", [("square_mx", 1e-5, 1e-8), ("bl_small_mx", 1e-5, 2e-7)])
+def test_dg_residual_vjp_mx_coupling(case, h, bar):
+    """HDG-MX interface: the explicit residual reads the implicit side's lifted mixed
+    variables Q(U, Uhat); <(Ubar, Uhatbar), (dU, dUhat)> against central differences of the
+    oracle's R^DG with Q lifted by the oracle from the perturbed (U, Uhat) (real arithmetic:
+    the oracle's lifting stores real arrays).  On the aspect-1000 boundary-layer cells the
+    viscous terms are large against the residual and the differences lose digits to
+    rounding (the error falls as h grows: 3e-7 at h = 1e-6, 3e-8 at 1e-5), hence its bar."""
+    from oracle.hdg import init_mixed
+    wl = (smooth_square(4, 2, viscous=True, variant=W.HDG_MX, implicit_rows=(1, 2)) if case == "square_mx"
+          else W.get("boundary_layer_small"))
+    ora = IMEXSolver(wl)
+    rng = np.random.default_rng(13)
+    U = ora.U * (1.0 + 1e-3 * rng.standard_normal(ora.U.shape))
+    H = ora.Uhat * (1.0 + 1e-3 * rng.standard_normal(ora.Uhat.shape))
+    d = rng.standard_normal(U.shape) * 1e-2 * np.abs(U).max()
+    dh = rng.standard_normal(H.shape) * 1e-2 * np.abs(H).max()
+    Rbar = rng.standard_normal(U.shape)
+    Rbar[ora.mesh.im_elems] = 0.0
+
+    def f(X, Xh):
+        Q = init_mixed(X, Xh, ora.system)
+        return dg_residual(X, Q, wl, ora.mesh, ora.basis, ora.gas)
+    eng = gpu_engine(wl)
+    Ub, Hb = eng.vjp_dg_residual(torch.tensor(U, device="cuda"), torch.tensor(Rbar, device="cuda"),
+                                 torch.tensor(H, device="cuda"))
+    Ub, Hb = Ub.cpu().numpy(), Hb.cpu().numpy()
+    # the element and facet parts separately: the facet part enters only through Q
+    for a, b in ((1.0, 0.0), (0.0, 1.0)):
+        jd = (f(U + h * a * d, H + h * b * dh) - f(U - h * a * d, H - h * b * dh)) / (2 * h)
+        ref = float(np.sum(Rbar * jd))
+        got = a * float(np.sum(Ub * d)) + b * float(np.sum(Hb * dh))
+        err = abs(got - ref) / abs(ref)
+        print(case, a, b, got, ref, err)
+        assert err < bar
+
+
+@pytest.mark.parametrize("case", ["bl_small_mx", "vortex_small"])
+def test_init_facets_transpose(case):
+    """<Uhatbar, T d> = <T^T Uhatbar, d> for the linear facet initialisation T, and T
+    against the oracle's init_facets."""
+    from oracle.hdg import init_facets as oracle_init_facets
+    wl = W.get("boundary_layer_small" if case == "bl_small_mx" else case)
+    ora = IMEXSolver(wl)
+    eng = gpu_engine(wl)
+    rng = np.random.default_rng(21)
+    d = torch.tensor(rng.standard_normal(tuple(ora.U.shape)), device="cuda")
+    Td = eng.init_facets(d)
+    ref = oracle_init_facets(d.cpu().numpy(), ora.mesh, ora.basis)
+    assert np.abs(Td.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    hb = torch.tensor(rng.standard_normal(tuple(Td.shape)), device="cuda")
+    base = torch.tensor(rng.standard_normal(tuple(ora.U.shape)), device="cuda")
+    out = eng.vjp_init_facets(hb, base.clone())
+    lhs = float((hb * Td).sum())
+    rhs = float(((out - base) * d).sum())
+    print(case, lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-12 * float((hb.abs() * Td.abs()).sum())
+
+
 IMEX_CASES = {
+    "bl_small_mx": lambda: W.get("boundary_layer_small"),
+    "square_mx": lambda: smooth_square(4, 2, viscous=True, variant=W.HDG_MX, implicit_rows=(1, 2)),
     "vortex_small": lambda: W.get("vortex_small"),
     "square_ip_viscous": lambda: smooth_square(4, 2, viscous=True, variant=W.HDG_IP, implicit_rows=(1, 2)),
     "bl_small_ip": lambda: W.boundary_layer(nx=4, ny=5, k=2, implicit_rows=2, Lx=4 * 2.0 / 256, height=None,
@@ -165,8 +229,12 @@ def test_imex_step_vjp(case):
     H0 = eng.init_facets(U0)
     c = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda")
     d = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * float(U0.abs().max())
-    Ub = eng.vjp_imex_step(wl.dt, U0, H0, c)
+    Ub, Hb = eng.vjp_imex_step(wl.dt, U0, H0, c, return_facets=True)
     got = float((Ub * d).sum())
+    if Hb is not None:
+        # the step's facet input is init_facets(U) (linear in U); with HDG-MX it enters the
+        # first explicit residual through the lifted mixed variables
+        got += float((Hb * eng.init_facets(d)).sum())
 
     def J(U):
         U = U.clone()
@@ -217,4 +285,33 @@ def test_rollout_imex_checkpointing():
     got = float((grads[0] * d).sum())
     err = abs(got - float(fd)) / abs(float(fd))
     print("rollout imex", got, float(fd), err)
+    assert err < 1e-6
+
+
+def test_rollout_mx_boundary_layer():
+    """Checkpointed rollout over HDG-MX IMEX steps (small boundary layer, ARS(3,4,3))."""
+    from paper_2607_16044_amd.autograd import ark_rollout
+    wl = W.get("boundary_layer_small")
+    eng = gpu_engine(wl, newton_rtol=1e-14, gmres_rtol=1e-13)
+    rng = np.random.default_rng(17)
+    U0 = eng.initial_state()
+    nsteps, record = 3, [1, 3]
+    w = torch.tensor(rng.standard_normal((len(record),) + tuple(U0.shape)), device="cuda")
+
+    def J(U, every):
+        return (ark_rollout(eng, U, wl.dt, nsteps, record, checkpoint=every) * w).sum()
+
+    grads = []
+    for every in (1, 2):
+        U = U0.clone().requires_grad_(True)
+        J(U, every).backward()
+        grads.append(U.grad.detach().clone())
+    assert torch.allclose(grads[1], grads[0], rtol=0, atol=1e-12 * float(grads[0].abs().max()))
+    d = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * float(U0.abs().max())
+    h = 1e-6
+    with torch.no_grad():
+        fd = (J(U0 + h * d, 10) - J(U0 - h * d, 10)) / (2 * h)
+    got = float((grads[0] * d).sum())
+    err = abs(got - float(fd)) / abs(float(fd))
+    print("rollout mx", got, float(fd), err)
     assert err < 1e-6
