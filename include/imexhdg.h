@@ -83,6 +83,16 @@ typedef struct {
   double gmres_rtol;     /* relative residual of the condensed facet solve                  */
   int gmres_restart;     /* 1..64                                                           */
   int gmres_maxit;
+  /* Newton corrections that reuse the last Jacobian (simplified Newton steps: the
+   * condensed factors of the previous iterate with a fresh FP64 residual, one facet
+   * solve, no assembly or condensation).  Convergence is still certified by the
+   * increment test above, on the measured contraction of each correction.
+   *   0  every correction assembles and condenses the Jacobian at the current iterate
+   *   1  after two full iterations, while the last correction contracted by < 1/20
+   *   2  after the first full iteration, under the same contraction bound (the Jacobian
+   *      is frozen within a stage, a variant the paper leaves out)
+   * A simplified correction that contracts more slowly hands back to full iterations. */
+  int newton_simplified;
 } imex_options;
 
 /* ARK pair synchronised by padding (Sec. 4.2.2): explicit (s+1)x(s+1) tableau Ae
@@ -104,6 +114,10 @@ typedef struct {
   double newton_last_du; /* last max|dU| / max|U|                                         */
   double t_assemble_ms;  /* device time in assembly + condensation                        */
   double t_solve_ms;     /* device time in the facet solve                                */
+  int n_jacobians;       /* Newton corrections that assembled a Jacobian (the rest reused one) */
+  int n_hist;            /* entries of du_hist in use                                     */
+  double du_hist[24];    /* per Newton iteration, in order over the stages of a step:
+                            max(max|dU|/max|U|, max|dUhat|/max|Uhat|) of its increment   */
 } imex_stats;
 
 /* Create a context for one mesh on the current HIP device.  stream: hipStream_t
@@ -148,6 +162,19 @@ imex_status imex_init_facets(imex_ctx* ctx, const double* U, double* Uhat);
  * (read); Ubar dev [E][4][(k+1)^2] (accumulated).  Deterministic (no atomics).
  * Errors: EINVAL (null argument), ESTATE (regions not set). */
 imex_status imex_vjp_init_facets(imex_ctx* ctx, const double* Uhatbar, double* Ubar);
+
+/* Wall shear of the HDG-MX region: J = sum over adiabatic-wall faces of implicit
+ * elements of the integral of 2 mu eps_12 = mu (du/dy + dv/dx), with eps_12 the
+ * stored strain component of the mixed variables (Sec. 3.5) lifted from (U, Uhat).
+ * It is the integrand of a time-averaged wall-shear objective.  U, Uhat dev (read);
+ * J host out.  Errors: ENOTIMPL without an HDG-MX region (viscous), EINVAL, ESTATE. */
+imex_status imex_wall_shear(imex_ctx* ctx, const double* U, const double* Uhat, double* J);
+
+/* Adjoint of imex_wall_shear: Ubar += Jbar dJ/dU, Uhatbar += Jbar dJ/dUhat (through the
+ * lifting of the mixed variables).  Ubar dev [E][4][(k+1)^2], Uhatbar dev
+ * [n_hf][4][k+1], both accumulated.  Errors as imex_wall_shear. */
+imex_status imex_vjp_wall_shear(imex_ctx* ctx, const double* U, const double* Uhat, double Jbar, double* Ubar,
+                                double* Uhatbar);
 
 /* Explicit DG-IP residual R^DG (Sec. 3.3, eq. bilinear_form_interior_sdg with the
  * far-field form of App. B.1.1 and the interface form of eq.

@@ -368,3 +368,19 @@ def init_mixed(U_all, Uhat, system: HDGSystem):
     sol = np.linalg.solve(A, -g0.reshape(system.B, -1, 1))[..., 0]
     Q_all[system.elems] = sol.reshape(system.B, 5, nn)
     return Q_all
+
+
+def wall_shear(Q_all, mesh: Mesh, basis: Basis, gas: ph.Gas) -> float:
+    """Integral over the implicit region's adiabatic walls of the wall shear
+    mu (du/dy + dv/dx) = 2 mu eps_12, with eps_12 the stored off-diagonal strain of the
+    HDG-MX mixed variables (Sec. 3.5) evaluated at the face Gauss points (the integrand of
+    a time-averaged wall-shear objective)."""
+    J = 0.0
+    for e in mesh.im_elems:
+        for f in range(4):
+            if mesh.face_kind[e, f] != KIND_WALL:
+                continue
+            ds = 0.5 * (mesh.hy[e] if f < 2 else mesh.hx[e])
+            eps12 = basis.fphi[f] @ Q_all[e, 1]
+            J += 2.0 * gas.mu * float(np.sum(basis.qw * eps12)) * ds
+    return J

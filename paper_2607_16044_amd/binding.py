@@ -25,7 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets", "imex_wall_shear", "imex_vjp_wall_shear",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
     _fields_ = [("dg_flux", ctypes.c_int), ("hdg_flux", ctypes.c_int), ("hdg_variant", ctypes.c_int),
                 ("alpha_dg", ctypes.c_double), ("alpha_hdg", ctypes.c_double), ("precision", ctypes.c_int),
                 ("newton_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
-                ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int)]
+                ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int), ("newton_simplified", ctypes.c_int)]
 
 
 class Tableau(ctypes.Structure):
@@ -54,10 +54,14 @@ class Tableau(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("gmres_its", ctypes.c_int), ("newton_last_du", ctypes.c_double),
-                ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("n_jacobians", ctypes.c_int),
+                ("n_hist", ctypes.c_int),
+                ("du_hist", ctypes.c_double * 24)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "du_hist"}
+        d["du_hist"] = [self.du_hist[i] for i in range(self.n_hist)]
+        return d
 
 
 _lib = None
@@ -89,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P, P, P]
     lib.imex_vjp_init_facets.argtypes = [P, P, P]
+    lib.imex_wall_shear.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.imex_vjp_wall_shear.argtypes = [P, P, P, D, P, P]
     lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
     lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, P, ctypes.POINTER(Stats)]
     lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
@@ -125,7 +131,7 @@ class Engine:
 
     def __init__(self, wl, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         self.lib = load_library()
@@ -138,7 +144,7 @@ class Engine:
                         wl.degree)
         phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
         opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
-                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit)
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         st = self.lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt),
@@ -213,6 +219,19 @@ class Engine:
         if Uhatbar.numel():
             self._check(self.lib.imex_vjp_init_facets(self.ctx, _ptr(Uhatbar), _ptr(Ubar)))
         return Ubar
+
+    def wall_shear(self, U: torch.Tensor, Uhat: torch.Tensor) -> float:
+        """Integral of the wall shear mu (du/dy + dv/dx) over the HDG-MX region's walls."""
+        out = ctypes.c_double()
+        self._check(self.lib.imex_wall_shear(self.ctx, _ptr(U), _ptr(Uhat), ctypes.byref(out)))
+        return out.value
+
+    def vjp_wall_shear(self, U: torch.Tensor, Uhat: torch.Tensor, Jbar: float, Ubar: torch.Tensor,
+                       Uhatbar: torch.Tensor):
+        """Ubar += Jbar dJ/dU, Uhatbar += Jbar dJ/dUhat (in place)."""
+        self._check(self.lib.imex_vjp_wall_shear(self.ctx, _ptr(U), _ptr(Uhat), float(Jbar), _ptr(Ubar),
+                                                 _ptr(Uhatbar)))
+        return Ubar, Uhatbar
 
     def dg_residual(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None) -> torch.Tensor:
         R = torch.empty_like(U)
@@ -318,7 +337,7 @@ class BatchEngine(Engine):
 
     def __init__(self, wls, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         if not wls or len({w.degree for w in wls}) != 1:
@@ -338,7 +357,7 @@ class BatchEngine(Engine):
         scale = np.array([w.dt / self.dt for w in self.wls], dtype=np.float64)
         phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
         opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
-                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit)
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         st = self.lib.imex_create_batch(len(self.wls), meshes, scale.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

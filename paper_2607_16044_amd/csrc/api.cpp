@@ -232,7 +232,8 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
   if (opt->precision != IMEX_FP64 && opt->precision != IMEX_FP32_REFINE)
     return fail(nullptr, IMEX_EINVAL, "precision");
   if (opt->newton_maxit < 1 || opt->gmres_restart < 1 || opt->gmres_restart > 64 || opt->gmres_maxit < 1 ||
-      !(opt->newton_rtol > 0.0) || !(opt->gmres_rtol > 0.0))
+      !(opt->newton_rtol > 0.0) || !(opt->gmres_rtol > 0.0) || opt->newton_simplified < 0 ||
+      opt->newton_simplified > 2)
     return fail(nullptr, IMEX_EINVAL, "solver options");
 
   imex_ctx* c = new (std::nothrow) imex_ctx();
@@ -572,6 +573,43 @@ imex_status imex_vjp_init_facets(imex_ctx* c, const double* Uhatbar, double* Uba
   return IMEX_OK;
 }
 
+imex_status imex_wall_shear(imex_ctx* c, const double* U, const double* Uhat, double* J) {
+  if (!c || !U || !J) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  *J = 0.0;
+  if (c->n_im == 0) return IMEX_OK;
+  if (!Uhat) return fail(c, IMEX_EINVAL, "null argument");
+  if (c->opt.hdg_variant != IMEX_HDG_MX || !c->gas.viscous)
+    return fail(c, IMEX_ENOTIMPL, "the wall shear is taken from the HDG-MX mixed variables");
+  Workspace& w = c->ws;
+  HIP_TRY(c, vjp_alloc(c));
+  HIP_TRY(c, launch_lift_mixed(c, U, Uhat, w.vjp_q));
+  HIP_TRY(c, launch_wall_shear(c, w.vjp_q, w.red));
+  HIP_TRY(c, hipMemcpyAsync(w.hred, w.red, sizeof(double) * c->n_im, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (int p = 0; p < c->n_im; ++p) s += w.hred[p];
+  *J = s;
+  return IMEX_OK;
+}
+
+imex_status imex_vjp_wall_shear(imex_ctx* c, const double* U, const double* Uhat, double Jbar, double* Ubar,
+                                double* Uhatbar) {
+  if (!c || !U || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  if (c->n_im == 0) return IMEX_OK;
+  if (!Uhat || !Uhatbar) return fail(c, IMEX_EINVAL, "null argument");
+  if (c->opt.hdg_variant != IMEX_HDG_MX || !c->gas.viscous)
+    return fail(c, IMEX_ENOTIMPL, "the wall shear is taken from the HDG-MX mixed variables");
+  Workspace& w = c->ws;
+  HIP_TRY(c, vjp_alloc(c));
+  HIP_TRY(c, hipMemsetAsync(w.vjp_qb, 0, sizeof(double) * (size_t)c->E * 5 * c->NN, c->stream));
+  HIP_TRY(c, launch_wall_shear_qbar(c, 2.0 * c->gas.mu * Jbar, w.vjp_qb));
+  HIP_TRY(c, launch_lift_vjp(c, U, Uhat, w.vjp_qb, Ubar, w.vjp_hb, Uhatbar));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
 static imex_status dg_residual_async(imex_ctx* c, const double* U, const double* Uhat, double* R) {
   const bool mx = c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
   if (mx && Uhat) HIP_TRY(c, launch_lift_mixed(c, U, Uhat, c->ws.Q));
@@ -731,6 +769,9 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
         st->newton_last_du = sst.newton_last_du;
         st->t_assemble_ms += sst.t_assemble_ms;
         st->t_solve_ms += sst.t_solve_ms;
+        st->n_jacobians += sst.n_jacobians;
+        for (int q = 0; q < sst.n_hist && st->n_hist < (int)(sizeof(st->du_hist) / sizeof(double)); ++q)
+          st->du_hist[st->n_hist++] = sst.du_hist[q];
       }
       if (r != IMEX_OK) return r;
       if (tape) {

@@ -185,6 +185,8 @@ bool dg_tile_valid(int K, int et);
 // hdg.hip
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
 hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* Ub);
+hipError_t launch_wall_shear(const imex_ctx* c, const double* Q, double* part);
+hipError_t launch_wall_shear_qbar(const imex_ctx* c, double scale, double* Qb);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);
 hipError_t launch_rhs_accumulate(const imex_ctx* c, double b, const double* R, double* rhs);

@@ -1870,7 +1870,7 @@ __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* _
 // ---------------------------------------------------------------------------
 // device-resident GMRES pieces
 // ---------------------------------------------------------------------------
-constexpr int GM_NB = 128;        // blocks of the reduction kernels
+constexpr int GM_NB = 256;        // blocks of the reduction kernels
 constexpr int GM_MAXM = 64;       // maximum restart length
 
 struct GmState {                  // device layout of the small GMRES arrays (doubles)
@@ -1886,11 +1886,36 @@ struct GmState {                  // device layout of the small GMRES arrays (do
   static constexpr int SIZE = NPART + GM_NB;
 };
 
-// partial dots of w with V_0..V_{k-1}: part[b][c]
+// sum over the 64 lanes of a wave (lane 0 holds the result)
+__device__ inline double gm_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// sum of the GM_NB partial norms, by one wave (every lane returns it)
+__device__ inline double gm_norm_total(const double* __restrict__ st, int nblocks) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nblocks; b += 64) s += st[GmState::NPART + b];
+  s = gm_wave_sum(s);
+  return __shfl(s, 0, 64);
+}
+
+// block-wide sum of one value per thread (256 threads); thread 0 gets the result
+__device__ inline double gm_block_sum(double v, double* red4) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = gm_wave_sum(v);
+  if (lane == 0) red4[wv] = v;
+  __syncthreads();
+  return red4[0] + red4[1] + red4[2] + red4[3];
+}
+
+// partial dots of w with V_0..V_{k-1}: part[b][c] (block b covers one contiguous chunk)
 __global__ void __launch_bounds__(256) gm_dots_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
                                                       const double* __restrict__ w, double* __restrict__ st) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
+  __shared__ double red[4][8];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int chunk = (n + GM_NB - 1) / GM_NB;
   const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
   double* part = st + GmState::PART + (size_t)blockIdx.x * (GM_MAXM + 1);
@@ -1902,30 +1927,29 @@ __global__ void __launch_bounds__(256) gm_dots_kernel(int n, int k, const double
       for (int c = 0; c < 8; ++c)
         if (c0 + c < k) acc[c] += V[(size_t)(c0 + c) * ldv + r] * wr;
     }
-    for (int c = 0; c < 8 && c0 + c < k; ++c) {
-      red[tid] = acc[c];
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-      }
-      if (tid == 0) part[c0 + c] = red[0];
-      __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double t = gm_wave_sum(acc[c]);
+      if (lane == 0) red[wv][c] = t;
     }
+    __syncthreads();
+    if (tid < 8 && c0 + tid < k) part[c0 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
   }
 }
 
-// h = sum of the partial dots (added into column j of H when accumulate != 0); w -= V h;
-// with norm != 0 also the partial sums of |w|^2
+// h = sum of the partial dots (added into column j of H); w -= V h; with norm != 0 also
+// the partial sums of |w|^2
 __global__ void __launch_bounds__(256) gm_orth_kernel(int n, int k, int j, const double* __restrict__ V, size_t ldv,
                                                       double* __restrict__ w, double* __restrict__ st, int norm) {
   __shared__ double hc[GM_MAXM + 1];
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
-  if (tid < k) {
-    double acc = 0.0;
-    for (int b = 0; b < GM_NB; ++b) acc += st[GmState::PART + (size_t)b * (GM_MAXM + 1) + tid];
-    hc[tid] = acc;
+  __shared__ double red4[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = wv; c < k; c += 4) {
+    double a = 0.0;
+    for (int b = lane; b < GM_NB; b += 64) a += st[GmState::PART + (size_t)b * (GM_MAXM + 1) + c];
+    a = gm_wave_sum(a);
+    if (lane == 0) hc[c] = a;
   }
   __syncthreads();
   if (blockIdx.x == 0 && tid < k) st[GmState::H + (size_t)j * (GM_MAXM + 1) + tid] += hc[tid];
@@ -1938,41 +1962,30 @@ __global__ void __launch_bounds__(256) gm_orth_kernel(int n, int k, int j, const
     nrm += v * v;
   }
   if (!norm) return;
-  red[tid] = nrm;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  if (tid == 0) st[GmState::NPART + blockIdx.x] = red[0];
+  const double t = gm_block_sum(nrm, red4);
+  if (tid == 0) st[GmState::NPART + blockIdx.x] = t;
 }
 
 // |w|^2 partials only (for the initial residual)
 __global__ void __launch_bounds__(256) gm_norm_kernel(int n, const double* __restrict__ w, double* __restrict__ st) {
-  __shared__ double red[256];
+  __shared__ double red4[4];
   const int tid = threadIdx.x;
   double nrm = 0.0;
   for (int r = blockIdx.x * blockDim.x + tid; r < n; r += gridDim.x * blockDim.x) nrm += w[r] * w[r];
-  red[tid] = nrm;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  if (tid == 0) st[GmState::NPART + blockIdx.x] = red[0];
+  const double t = gm_block_sum(nrm, red4);
+  if (tid == 0) st[GmState::NPART + blockIdx.x] = t;
 }
 
 // start a cycle: beta = |r|, g = (beta, 0, ...), H = 0, invb = 1/beta
 __global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
   const int tid = threadIdx.x;
-  __shared__ double beta;
-  if (tid == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += st[GmState::NPART + b];
-    beta = sqrt(s);
-    st[GmState::G] = beta;
-    st[GmState::INVB] = beta > 0.0 ? 1.0 / beta : 0.0;
-    st[GmState::INVB + 1] = beta;
+  if (tid < 64) {
+    const double beta = sqrt(gm_norm_total(st, nblocks));
+    if (tid == 0) {
+      st[GmState::G] = beta;
+      st[GmState::INVB] = beta > 0.0 ? 1.0 / beta : 0.0;
+      st[GmState::INVB + 1] = beta;
+    }
   }
   for (int i = tid; i < (GM_MAXM + 1) * GM_MAXM; i += blockDim.x) st[GmState::H + i] = 0.0;
   for (int i = 1 + tid; i < GM_MAXM + 1; i += blockDim.x) st[GmState::G + i] = 0.0;
@@ -1980,10 +1993,9 @@ __global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
 
 // Givens update of column j: beta from the norm partials, rotations, g, residual estimate, 1/beta
 __global__ void gm_givens_kernel(int j, double* __restrict__ st, int nblocks) {
+  if (threadIdx.x >= 64) return;
+  const double beta = sqrt(gm_norm_total(st, nblocks));
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += st[GmState::NPART + b];
-  const double beta = sqrt(s);
   double* Hc = st + GmState::H + (size_t)j * (GM_MAXM + 1);
   Hc[j + 1] = beta;
   for (int i = 0; i < j; ++i) {
@@ -2495,6 +2507,28 @@ static hipError_t launch_condense(imex_ctx* c) {
   return hipGetLastError();
 }
 
+// Right-hand side of a simplified Newton correction.  The residual assembly has put the
+// new f in the augmented column of the element rows and zeroed the facet rows' column;
+// K^-1, X[:, :NF] = K^-1 C, D and S of the previous Jacobian are untouched:
+//   X[:, NF] = K^-1 f,  [h - D K^-1 f] column = -D X[:, NF]  (h is added from hres).
+static hipError_t launch_resolve(imex_ctx* c) {
+  Workspace& w = c->ws;
+  HDG_DISPATCH(c->K, LA_DISPATCH(c, {
+    constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NC = NU + NF + 1;
+    LT* blk = la<LT>(w.blk);
+    LT* Kinv = la<LT>(w.Kinv);
+    LT* X = la<LT>(w.X);
+    const long long bs = (long long)blk_stride(c), sx = (long long)NU * (NF + 1);
+    hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
+                                    blk + NU + NF, NC, bs, X + NF, NF + 1, sx, 32);
+    if (e != hipSuccess) return e;
+    e = gemm_batched<LT>(c->stream, c->n_im, NF, 1, NU, -1.0, true, blk + (size_t)NU * NC, NC, bs, X + NF, NF + 1,
+                         sx, blk + (size_t)NU * NC + NU + NF, NC, bs, 32);
+    if (e != hipSuccess) return e;
+  }));
+  return hipGetLastError();
+}
+
 // average device time (ms) of reps runs of f on the context's stream
 template <class F>
 static float time_ms(imex_ctx* c, int reps, F&& f) {
@@ -2625,6 +2659,8 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
 // every GM_CHECK iterations and solves the small least-squares problem.
 constexpr int GM_CHECK = 8;
 constexpr int PREC_REFRESH_ITS = 8;
+// a simplified Newton correction follows only a correction that contracted by at least this
+constexpr double SIMPLIFIED_QMAX = 0.05;
 
 static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) {
   Workspace& w = c->ws;
@@ -2732,14 +2768,31 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   // since the last refactorisation outweighs a new one.  Stopping: the increments of U
   // and Uhat are below rtol times the largest |U| and |Uhat|, either measured or
   // predicted from the observed contraction (theta / (1 - theta) |dz| with theta < 1/2).
+  //
+  // Simplified corrections (newton_simplified > 0) reuse the condensed factors of the last
+  // Jacobian with a fresh FP64 residual; the increment test below is applied to them in
+  // the same way, so a simplified correction that passes it certifies convergence.
   double du_prev = 0.0, dh_prev = 0.0;
+  int nfull = 0;
+  double q_last = 0.0;                      // contraction of the last correction
+  const int need_full = c->opt.newton_simplified == 2 ? 1 : 2;
   if (c->prec_valid && std::fabs(dt_a / c->prec_dt_a - 1.0) > 0.25) c->prec_valid = false;
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
     newton = it;
-    HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
-    int tt = c->timer_begin(TM_CONDENSE);
-    HTRY(launch_condense(c));
-    c->timer_end(tt);
+    const bool simplified = c->opt.newton_simplified > 0 && nfull >= need_full && q_last < SIMPLIFIED_QMAX;
+    int tt;
+    if (simplified) {
+      HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 0, nullptr));
+      tt = c->timer_begin(TM_CONDENSE);
+      HTRY(launch_resolve(c));
+      c->timer_end(tt);
+    } else {
+      HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 1, nullptr));
+      tt = c->timer_begin(TM_CONDENSE);
+      HTRY(launch_condense(c));
+      c->timer_end(tt);
+      ++nfull;
+    }
     tt = c->timer_begin(TM_FACET);
     HTRY(launch_facet_rhs(c, b));
     if (!c->prec_valid) {
@@ -2785,14 +2838,20 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
       return IMEX_ENONFINITE;
     }
     last = (uu > 0.0) ? du / uu : du;
+    if (st && st->n_hist < (int)(sizeof(st->du_hist) / sizeof(double)))
+      st->du_hist[st->n_hist++] = std::fmax(last, hh > 0.0 ? dh / hh : dh);
     const double tu = c->opt.newton_rtol * uu, th = c->opt.newton_rtol * hh;
     if (du <= tu && dh <= th) { converged = true; break; }
     if (it >= 2 && du_prev > 0.0 && dh_prev > 0.0) {
       const double qu = du / du_prev, qh = dh / dh_prev;
+      q_last = std::fmax(qu, qh);
       if (qu < 0.5 && qh < 0.5 && qu / (1.0 - qu) * du <= tu && qh / (1.0 - qh) * dh <= th) {
         converged = true;
         break;
       }
+    } else {
+      // no contraction measured yet: a chord step may follow the first Jacobian
+      q_last = 0.0;
     }
     du_prev = du;
     dh_prev = dh;
@@ -2801,8 +2860,11 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     st->newton_its = newton;
     st->gmres_its = gm_total;
     st->newton_last_du = last;
+    st->n_jacobians = nfull;
   }
-  // R^HDG and the mixed variables at the converged state
+  // R^HDG and the mixed variables at the converged state.  Also after a simplified
+  // correction: the contraction test accepts increments up to about rtol / theta, and
+  // R^HDG feeds the later stages' right-hand sides through the stiff (K - M) / dt_a.
   HTRY(launch_assemble(c, dt_a, U, Uhat, rhs, 0, R_out));
   HTRY(hipStreamSynchronize(c->stream));
   if (!converged) {

@@ -84,6 +84,55 @@ __global__ void init_facets_vjp_kernel(DeviceMesh m, DeviceHDG h, int fpass, con
   Ub[((size_t)e * 4 + v) * NN + n] += coef / cnt;
 }
 
+// Wall shear of the HDG-MX region: per implicit element, the integral over its adiabatic
+// wall faces of 2 mu eps_12 = mu (du/dy + dv/dx), with eps_12 the lifted mixed variable
+// Q_1 traced onto the face (Sec. 3.5: the stored strain components).
+template <int K>
+__global__ void wall_shear_kernel(DeviceMesh m, DeviceHDG h, double mu, const double* __restrict__ Q,
+                                  double* __restrict__ part) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= h.n_im) return;
+  const int e = h.im_list[p];
+  const BasisTable& tb = *m.tab;
+  const double* q1 = Q + ((size_t)e * 5 + 1) * NN;
+  double acc = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    if (h.face_kind[4 * p + f] != FK_WALL) continue;
+    const int s = f & 1;
+    const double wl = (f < 2) ? 0.5 * m.hy[e] : 0.5 * m.hx[e];
+    for (int q = 0; q < NQ; ++q) {
+      double val = 0.0;
+      for (int b = 0; b < NP; ++b)
+        for (int a = 0; a < NP; ++a)
+          val += ((f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b]) * q1[a + NP * b];
+      acc += tb.W[q] * wl * val;
+    }
+  }
+  part[p] = 2.0 * mu * acc;
+}
+
+// Qbar = scale * d(wall shear)/dQ: component 1 of implicit elements with wall faces (the
+// rest of Qb is left as it is)
+template <int K>
+__global__ void wall_shear_qbar_kernel(DeviceMesh m, DeviceHDG h, double scale, double* __restrict__ Qb) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h.n_im * NN) return;
+  const int p = t / NN, n = t % NN, a = n % NP, b = n / NP;
+  const int e = h.im_list[p];
+  const BasisTable& tb = *m.tab;
+  double acc = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    if (h.face_kind[4 * p + f] != FK_WALL) continue;
+    const int s = f & 1;
+    const double wl = (f < 2) ? 0.5 * m.hy[e] : 0.5 * m.hx[e];
+    for (int q = 0; q < NQ; ++q)
+      acc += tb.W[q] * wl * ((f < 2) ? tb.LE[s][a] * tb.L[q][b] : tb.L[q][a] * tb.LE[s][b]);
+  }
+  Qb[((size_t)e * 5 + 1) * NN + n] = scale * acc;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG h, Gas g,
                                                          const double* __restrict__ U,
@@ -364,6 +413,21 @@ hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* U
   for (int f = 0; f < 4; ++f)
     IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(init_facets_vjp_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
                                              c->stream, c->dmesh(), c->dhdg(), f, Hb, Ub));
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_shear(const imex_ctx* c, const double* Q, double* part) {
+  if (c->n_im == 0) return hipSuccess;
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(wall_shear_kernel<KK>, dim3((c->n_im + 63) / 64), dim3(64), 0, c->stream,
+                                           c->dmesh(), c->dhdg(), c->gas.mu, Q, part));
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_shear_qbar(const imex_ctx* c, double scale, double* Qb) {
+  const int n = c->n_im * c->NN;
+  if (n == 0) return hipSuccess;
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(wall_shear_qbar_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
+                                           c->stream, c->dmesh(), c->dhdg(), scale, Qb));
   return hipGetLastError();
 }
 

@@ -1,0 +1,64 @@
+"""Newton corrections that reuse the last Jacobian (simplified Newton steps).
+
+All three settings solve the same stage equations to the same increment test, so the
+states after a few steps agree to the Newton tolerance; the reuse settings assemble
+fewer Jacobians; and the default setting stays within the oracle bars.
+"""
+import numpy as np
+import pytest
+
+from _common import gpu_engine, rel_err, smooth_square
+from oracle.ark import IMEXSolver
+from paper_2607_16044_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "bl_small_mx": lambda: W.get("boundary_layer_small"),
+    "vortex_small": lambda: W.get("vortex_small"),
+    "square_ip_viscous": lambda: smooth_square(4, 2, viscous=True, variant=W.HDG_IP, implicit_rows=(1, 2)),
+}
+
+
+def _run(wl, precision, mode, steps):
+    eng = gpu_engine(wl, precision=precision, newton_simplified=mode)
+    U = eng.initial_state()
+    H = eng.init_facets(U)
+    jac = its = 0
+    for _ in range(steps):
+        st = eng.ark_step(wl.dt, U, H)
+        jac += st["n_jacobians"]
+        its += st["newton_its"]
+    out = U.cpu().numpy()
+    eng.close()
+    return out, jac, its
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", list(CASES))
+def test_simplified_corrections_same_root(case, precision):
+    wl = CASES[case]()
+    steps = 3
+    base, j0, i0 = _run(wl, precision, 0, steps)
+    assert j0 == i0
+    for mode in (1, 2):
+        u, j, i = _run(wl, precision, mode, steps)
+        e = rel_err(u, base)
+        print(case, precision, mode, "jacobians", j0, "->", j, "corrections", i0, "->", i, "diff", e)
+        assert e < 1e-11
+        assert j <= j0
+    ora = IMEXSolver(wl)
+    for _ in range(steps):
+        ora.step()
+    e = rel_err(base, ora.U)
+    print(case, precision, "oracle", e)
+    assert e < (1e-10 if precision == 0 else 1e-9)
+
+
+def test_simplified_corrections_fewer_jacobians_boundary_layer():
+    wl = W.get("boundary_layer_small")
+    _, j0, _ = _run(wl, 1, 0, 4)
+    _, j1, _ = _run(wl, 1, 1, 4)
+    _, j2, _ = _run(wl, 1, 2, 4)
+    print("jacobians", j0, j1, j2)
+    assert j2 < j1 < j0

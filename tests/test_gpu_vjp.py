@@ -315,3 +315,89 @@ def test_rollout_mx_boundary_layer():
     err = abs(got - float(fd)) / abs(float(fd))
     print("rollout mx", got, float(fd), err)
     assert err < 1e-6
+
+
+def _bl_generic_state(seed):
+    wl = W.get("boundary_layer_small")
+    ora = IMEXSolver(wl)
+    rng = np.random.default_rng(seed)
+    U = ora.U * (1.0 + 1e-3 * rng.standard_normal(ora.U.shape))
+    H = ora.Uhat * (1.0 + 1e-3 * rng.standard_normal(ora.Uhat.shape))
+    return wl, ora, rng, U, H
+
+
+def test_wall_shear_matches_oracle():
+    from oracle.hdg import init_mixed, wall_shear
+    wl, ora, rng, U, H = _bl_generic_state(31)
+    ref = wall_shear(init_mixed(U, H, ora.system), ora.mesh, ora.basis, ora.gas)
+    eng = gpu_engine(wl)
+    got = eng.wall_shear(torch.tensor(U, device="cuda"), torch.tensor(H, device="cuda"))
+    print("wall shear", got, ref)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+def test_wall_shear_vjp():
+    """<(Ubar, Uhatbar), (dU, dUhat)> of the wall shear against central differences of the
+    oracle's functional (Q lifted by the oracle)."""
+    from oracle.hdg import init_mixed, wall_shear
+    wl, ora, rng, U, H = _bl_generic_state(33)
+    d = rng.standard_normal(U.shape) * 1e-2 * np.abs(U).max()
+    dh = rng.standard_normal(H.shape) * 1e-2 * np.abs(H).max()
+    eng = gpu_engine(wl)
+    Ut, Ht = torch.tensor(U, device="cuda"), torch.tensor(H, device="cuda")
+    Ub, Hb = torch.zeros_like(Ut), torch.zeros_like(Ht)
+    eng.vjp_wall_shear(Ut, Ht, 2.5, Ub, Hb)
+    got = float((Ub.cpu().numpy() * d).sum() + (Hb.cpu().numpy() * dh).sum())
+
+    def f(X, Xh):
+        return 2.5 * wall_shear(init_mixed(X, Xh, ora.system), ora.mesh, ora.basis, ora.gas)
+    h = 1e-5
+    ref = (f(U + h * d, H + h * dh) - f(U - h * d, H - h * dh)) / (2 * h)
+    err = abs(got - ref) / abs(ref)
+    print("wall shear vjp", got, ref, err)
+    assert err < 1e-7
+
+
+def test_wall_shear_objective_gradient():
+    """Gradient in U_0 of the wall shear averaged over steps 2..4 (HDG-MX boundary layer):
+    checkpointed and plain recomputation agree; central differences of the GPU run and of
+    the oracle's run agree with it."""
+    from oracle.hdg import init_mixed, wall_shear
+    from paper_2607_16044_amd.autograd import wall_shear_objective
+    wl = W.get("boundary_layer_small")
+    eng = gpu_engine(wl, newton_rtol=1e-14, gmres_rtol=1e-13)
+    rng = np.random.default_rng(35)
+    U0 = eng.initial_state()
+    nsteps, window = 4, (2, 4)
+    grads, vals = [], []
+    for every in (1, 3, 10):
+        U = U0.clone().requires_grad_(True)
+        J = wall_shear_objective(eng, U, wl.dt, nsteps, window, checkpoint=every)
+        J.backward()
+        grads.append(U.grad.detach().clone())
+        vals.append(float(J))
+    for g in grads[1:]:
+        assert torch.allclose(g, grads[0], rtol=0, atol=1e-12 * float(grads[0].abs().max()))
+    assert max(vals) - min(vals) <= 1e-14 * abs(vals[0])
+    d = torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * float(U0.abs().max())
+    got = float((grads[0] * d).sum())
+    h = 1e-6
+    with torch.no_grad():
+        fd = (float(wall_shear_objective(eng, U0 + h * d, wl.dt, nsteps, window)) -
+              float(wall_shear_objective(eng, U0 - h * d, wl.dt, nsteps, window))) / (2 * h)
+    err = abs(got - fd) / abs(fd)
+
+    def Jo(Un):
+        ora = IMEXSolver(wl, U0=Un)
+        acc = 0.0
+        for n in range(1, nsteps + 1):
+            ora.step()
+            if window[0] <= n <= window[1]:
+                acc += wall_shear(init_mixed(ora.U, ora.Uhat, ora.system), ora.mesh, ora.basis, ora.gas)
+        return acc / (window[1] - window[0] + 1)
+    U0n, dn = U0.cpu().numpy(), d.cpu().numpy()
+    fdo = (Jo(U0n + 1e-5 * dn) - Jo(U0n - 1e-5 * dn)) / 2e-5
+    erro = abs(got - fdo) / abs(fdo)
+    print("objective", vals[0], got, fd, err, fdo, erro)
+    assert err < 1e-6
+    assert erro < 1e-4
