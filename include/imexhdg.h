@@ -275,12 +275,17 @@ imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt,
  * with the transposed condensed system at its converged state (K^-T, S^T by
  * GMRES with a facet block-Jacobi preconditioner, tolerance min(gmres_rtol,
  * 1e-12)), the explicit parts with imex_vjp_dg_residual.  Without an implicit
- * region this is imex_vjp_ark_step.  st host (nullable): gmres_its of the
- * transposed solves.  Errors: ENOTIMPL for implicit tableaux
- * that are not stiffly accurate; as imex_ark_step. */
+ * region this is imex_vjp_ark_step.  duinf host [4] and pbar host [1] (both
+ * nullable): the derivative of <Ubar_next, U_{n+1}> + <Uhatbar_next, Uhat_{n+1}>
+ * along a change u_inf + p duinf of the far-field state (App. B.1.1, B.2.1) at p = 0,
+ * with U_n, Uhat_n fixed: the sum over the step's residual evaluations of their
+ * adjoint times the residual's derivative in p (central differences in p at the
+ * recorded states).  st host (nullable): gmres_its of the transposed solves.
+ * Errors: ENOTIMPL for implicit tableaux that are not stiffly accurate, or for duinf
+ * without an implicit region; as imex_ark_step. */
 imex_status imex_vjp_imex_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
-                               const double* Uhat, const double* Ubar_next, const double* Uhatbar_next,
-                               double* Ubar, double* Uhatbar, imex_stats* st);
+                               const double* Uhat, const double* Ubar_next, const double* Uhatbar_next, double* Ubar,
+                               double* Uhatbar, const double* duinf, double* pbar, imex_stats* st);
 
 const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);

@@ -59,10 +59,12 @@ def _forward_run(engine, U0, dt: float, nsteps: int, checkpoint: int,
 
 
 def _reverse(engine, dt: float, nsteps: int, every: int, checkpoints: Dict[int, Tuple], final,
-             seed: Callable[[int, torch.Tensor, Optional[torch.Tensor], torch.Tensor, Optional[torch.Tensor]], None]):
+             seed: Callable[[int, torch.Tensor, Optional[torch.Tensor], torch.Tensor, Optional[torch.Tensor]], None],
+             duinf=None, pacc: Optional[list] = None):
     """Adjoint of U_0 for a run recorded by _forward_run.  seed(n, U_n, H_n, Ubar, Hbar)
     adds the adjoints of the state after step n into (Ubar, Hbar) in place (Hbar is None
-    without an implicit region)."""
+    without an implicit region).  With duinf, pacc[0] accumulates the derivative along
+    the far-field state u_inf + p duinf (U_0 fixed)."""
     U_N, H_N = final
     Ubar = torch.zeros_like(U_N)
     Hbar = None if H_N is None else torch.zeros_like(H_N)
@@ -80,7 +82,9 @@ def _reverse(engine, dt: float, nsteps: int, every: int, checkpoints: Dict[int, 
             U, H = states[n - c0]
             # the facet state seeds the Newton iterations and, for HDG-MX, the mixed
             # variables of the first explicit residual: its adjoint travels with Ubar
-            Ubar, Hb = engine.vjp_imex_step(dt, U, H, Ubar.contiguous(), Hbar, return_facets=True)
+            Ubar, Hb = engine.vjp_imex_step(dt, U, H, Ubar.contiguous(), Hbar, return_facets=True, duinf=duinf)
+            if duinf is not None:
+                pacc[0] += engine.last_param_adjoint
             Hbar = Hb if Hbar is None or Hb is None else Hb.contiguous()
             seed(n, U, H, Ubar, Hbar)
     if Hbar is not None:
@@ -122,7 +126,7 @@ def ark_rollout(engine, U0, dt: float, nsteps: int, record: Sequence[int], check
 
 class WallShearObjective(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, engine, dt: float, nsteps: int, window: Tuple[int, int], checkpoint: int):
+    def forward(ctx, U0, p, engine, dt: float, nsteps: int, window: Tuple[int, int], checkpoint: int, duinf):
         n0, n1 = int(window[0]), int(window[1])
         if not (0 <= n0 <= n1 <= nsteps):
             raise ValueError("window must satisfy 0 <= n0 <= n1 <= nsteps")
@@ -135,6 +139,7 @@ class WallShearObjective(torch.autograd.Function):
                 acc[0] += engine.wall_shear(U, H)
         ctx.checkpoints, ctx.final = _forward_run(engine, U0, dt, nsteps, checkpoint, visit)
         ctx.engine, ctx.dt, ctx.nsteps, ctx.window, ctx.every = engine, dt, nsteps, (n0, n1), checkpoint
+        ctx.duinf = duinf
         return U0.new_tensor(acc[0] / (n1 - n0 + 1))
 
     @staticmethod
@@ -142,15 +147,27 @@ class WallShearObjective(torch.autograd.Function):
         n0, n1 = ctx.window
         w = float(gJ) / (n1 - n0 + 1)
         eng = ctx.engine
+        want_p = ctx.duinf is not None and ctx.needs_input_grad[1]
 
         def seed(n, U, H, Ubar, Hbar):
             if n0 <= n <= n1:
                 eng.vjp_wall_shear(U, H, w, Ubar, Hbar)
-        Ubar = _reverse(eng, ctx.dt, ctx.nsteps, ctx.every, ctx.checkpoints, ctx.final, seed)
-        return Ubar, None, None, None, None, None
+        pacc = [0.0]
+        Ubar = _reverse(eng, ctx.dt, ctx.nsteps, ctx.every, ctx.checkpoints, ctx.final, seed,
+                        duinf=ctx.duinf if want_p else None, pacc=pacc)
+        pbar = gJ.new_tensor(pacc[0]) if want_p else None
+        return Ubar, pbar, None, None, None, None, None, None
 
 
-def wall_shear_objective(engine, U0, dt: float, nsteps: int, window: Tuple[int, int], checkpoint: int = 20):
+def wall_shear_objective(engine, U0, dt: float, nsteps: int, window: Tuple[int, int], checkpoint: int = 20,
+                         p: Optional[torch.Tensor] = None, duinf=None):
     """(1 / (n1 - n0 + 1)) sum_{n = n0}^{n1} J_wall(U_n, Uhat_n) of an ARK run from U0 (J_wall:
-    the integral of mu (du/dy + dv/dx) over the HDG-MX region's walls), differentiable in U0."""
-    return WallShearObjective.apply(U0, engine, dt, nsteps, tuple(window), checkpoint)
+    the integral of mu (du/dy + dv/dx) over the HDG-MX region's walls), differentiable in U0.
+
+    With a scalar tensor p and a direction duinf (4 floats) of the far-field state, the
+    objective is also differentiable in p: the run uses the engine's far-field state, and
+    the gradient of p is the derivative along u_inf + p duinf at that state (U_0 fixed).
+    For the free-stream Mach number, duinf = workloads.farfield_mach_direction(...)."""
+    if p is None:
+        p = U0.new_zeros(())
+    return WallShearObjective.apply(U0, p, engine, dt, nsteps, tuple(window), checkpoint, duinf)

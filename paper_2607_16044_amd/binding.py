@@ -96,7 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.imex_wall_shear.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
     lib.imex_vjp_wall_shear.argtypes = [P, P, P, D, P, P]
     lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
-    lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, P, ctypes.POINTER(Stats)]
+    lib.imex_vjp_imex_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P, P, P, P, P, P,
+                                       ctypes.POINTER(Stats)]
     lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
     lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
     lib.imex_status_str.argtypes = [ctypes.c_int]
@@ -278,19 +279,25 @@ class Engine:
         return Ubar
 
     def vjp_imex_step(self, dt: float, U: torch.Tensor, Uhat: Optional[torch.Tensor], Ubar_next: torch.Tensor,
-                      Uhatbar_next: Optional[torch.Tensor] = None, return_facets: bool = False):
+                      Uhatbar_next: Optional[torch.Tensor] = None, return_facets: bool = False, duinf=None):
         """Adjoint of U_n (and, with return_facets, of Uhat_n) for one IMEX step from
-        (U, Uhat) (both unchanged)."""
+        (U, Uhat) (both unchanged).  With duinf (4 floats) the derivative of the seeded
+        output along the far-field state u_inf + p duinf is left in last_param_adjoint."""
         Ubar = torch.empty_like(U)
         Hb = None
         if Uhat is not None and Uhat.numel():
             Hb = torch.zeros_like(Uhat)
         st = Stats()
         tab = self.tableau.to_ctypes(Tableau)
+        du = (ctypes.c_double * 4)(*[float(x) for x in duinf]) if duinf is not None else None
+        pb = (ctypes.c_double * 1)(0.0)
         self._check(self.lib.imex_vjp_imex_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat),
                                                 _ptr(Ubar_next), _ptr(Uhatbar_next), _ptr(Ubar), _ptr(Hb),
+                                                ctypes.cast(du, ctypes.c_void_p) if du is not None else None,
+                                                ctypes.cast(pb, ctypes.c_void_p) if du is not None else None,
                                                 ctypes.byref(st)))
         self.last_adjoint_stats = st.as_dict()
+        self.last_param_adjoint = pb[0] if du is not None else None
         return (Ubar, Hb) if return_facets else Ubar
 
     def conservation_sums(self, U: torch.Tensor):
@@ -387,37 +394,74 @@ class BatchEngine(Engine):
 
 
 class Ensemble:
-    """Many independent workloads of mixed degrees: one BatchEngine per degree."""
+    """Many independent workloads of mixed degrees: one BatchEngine per degree, each on a
+    stream of its own (default priority).  step() drives the groups from one host thread
+    each, so the small launches of different degrees overlap on the device; every call
+    leaves the current stream ordered after the groups' work."""
 
-    def __init__(self, wls, precision: int = 0, **kw):
+    def __init__(self, wls, precision: int = 0, concurrent: bool = True, **kw):
         self.wls = list(wls)
         self.groups = []
+        self.concurrent = concurrent
         for k in sorted({w.degree for w in self.wls}):
             idx = [i for i, w in enumerate(self.wls) if w.degree == k]
-            self.groups.append((idx, BatchEngine([self.wls[i] for i in idx], precision=precision, **kw)))
+            st = torch.cuda.Stream() if concurrent else torch.cuda.current_stream()
+            with torch.cuda.stream(st):
+                eng = BatchEngine([self.wls[i] for i in idx], precision=precision, **kw)
+            self.groups.append((idx, eng))
         self.n_dof = sum(w.n_dof for w in self.wls)
+        self._pool = None
+        if concurrent and len(self.groups) > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(max_workers=len(self.groups))
+
+    def _join(self):
+        cur = torch.cuda.current_stream()
+        for _, eng in self.groups:
+            if eng.stream != cur:
+                cur.wait_stream(eng.stream)
+
+    def _each(self, fn):
+        """fn(g, eng) for every group on the group's stream (in parallel host threads when
+        concurrent); returns the results in group order."""
+        def run(g):
+            eng = self.groups[g][1]
+            with torch.cuda.stream(eng.stream):
+                return fn(g, eng)
+        cur = torch.cuda.current_stream()
+        for _, eng in self.groups:
+            if eng.stream != cur:
+                eng.stream.wait_stream(cur)
+        if self._pool is None:
+            out = [run(g) for g in range(len(self.groups))]
+        else:
+            out = list(self._pool.map(run, range(len(self.groups))))
+        self._join()
+        return out
 
     def initial_state(self):
-        U = [eng.initial_state() for _, eng in self.groups]
-        H = [eng.init_facets(u) for u, (_, eng) in zip(U, self.groups)]
-        return U, H
+        pairs = self._each(lambda g, eng: (lambda u: (u, eng.init_facets(u)))(eng.initial_state()))
+        return [p[0] for p in pairs], [p[1] for p in pairs]
 
     def tune(self, U, H, graphs: bool = True):
         """Autotune every degree group's launch shapes at state (U, H) and switch graph replay on."""
-        picks = []
-        for u, h, (_, eng) in zip(U, H, self.groups):
-            picks.append(eng.autotune(u, h if h.numel() else None))
+        def one(g, eng):
+            pick = eng.autotune(U[g], H[g] if H[g].numel() else None)
             eng.set_graphs(graphs)
+            return pick
+        # timing runs one group at a time, so the groups do not disturb each other's picks
+        picks = []
+        for g, (_, eng) in enumerate(self.groups):
+            eng.stream.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(eng.stream):
+                picks.append(one(g, eng))
+        self._join()
         return picks
 
     def step(self, U, H):
         """One ARK step of every instance (each with its own dt); returns summed solver counts."""
-        newton = gmres = 0
-        for u, h, (_, eng) in zip(U, H, self.groups):
-            st = eng.ark_step(eng.dt, u, h)
-            newton += st["newton_its"]
-            gmres += st["gmres_its"]
-        return newton, gmres
+        sts = self._each(lambda g, eng: eng.ark_step(eng.dt, U[g], H[g]))
+        return sum(st["newton_its"] for st in sts), sum(st["gmres_its"] for st in sts)
 
     def instance_states(self, U):
         out = [None] * len(self.wls)
@@ -427,5 +471,8 @@ class Ensemble:
         return out
 
     def close(self):
+        if self._pool is not None:
+            self._pool.shutdown()
+            self._pool = None
         for _, eng in self.groups:
             eng.close()

@@ -118,7 +118,8 @@ void free_regions(imex_ctx* c) {
     *p = nullptr;
   }
   Workspace& w = c->ws;
-  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.Hp, &w.gH, &w.gm, &w.red, &w.adj_P, &w.adj_w}) {
+  for (double** p : {&w.rec, &w.hres, &w.Wy, &w.Hp, &w.gH, &w.gm, &w.red, &w.adj_P, &w.adj_w, &w.adj_rp, &w.adj_rm,
+                     &w.adj_hp, &w.adj_hm}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
@@ -937,11 +938,16 @@ imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, c
 // the first explicit residual; only the latter has an adjoint.
 imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, const double* U, const double* Uhat,
                                const double* Ubar_next, const double* Uhatbar_next, double* Ubar, double* Uhatbar,
-                               imex_stats* st) {
+                               const double* duinf, double* pbar, imex_stats* st) {
   if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
-  if (c->n_im == 0) return imex_vjp_ark_step(c, tab, dt, U, Ubar_next, Ubar);
+  const bool want_p = duinf && pbar;
+  if (want_p) *pbar = 0.0;
+  if (c->n_im == 0) {
+    if (want_p) return fail(c, IMEX_ENOTIMPL, "far-field parameter adjoint without an implicit region");
+    return imex_vjp_ark_step(c, tab, dt, U, Ubar_next, Ubar);
+  }
   if (!Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
   if (!tab->stiffly_accurate) return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
   const bool mx = mx_coupled(c);
@@ -985,6 +991,87 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   for (int i = NSTATE + 4; i < NSTATE + NFAC; ++i) HIP_TRY(c, hipMemsetAsync(B[i], 0, nh * 8, hs));
   HIP_TRY(c, hipMemsetAsync(Ubar, 0, n * 8, hs));
   if (Uhatbar) HIP_TRY(c, hipMemsetAsync(Uhatbar, 0, nh * 8, hs));
+  // Far-field parameter: u_inf enters the step only through the residuals' far-field
+  // terms, so d(out)/dp along du_inf is the sum over the step's residual evaluations of
+  // <their adjoint, dresidual/dp>; the residual derivatives are central differences in p
+  // at the taped states (the far-field forms are affine or smooth in u_inf).
+  double pacc = 0.0, peps = 0.0;
+  if (want_p) {
+    double dmax = 0.0, umax = 0.0;
+    for (int v = 0; v < 4; ++v) {
+      dmax = std::max(dmax, std::fabs(duinf[v]));
+      umax = std::max(umax, std::fabs(c->gas.uinf[v]));
+    }
+    peps = dmax > 0.0 ? 1e-4 * std::max(umax, 1e-300) / dmax : 0.0;
+    if (!w.adj_rp) {
+      const size_t ns = (size_t)c->n_im * 16 * c->NP;
+      HIP_TRY(c, hipMalloc(&w.adj_rp, 8 * n));
+      HIP_TRY(c, hipMalloc(&w.adj_rm, 8 * n));
+      HIP_TRY(c, hipMalloc(&w.adj_hp, 8 * std::max<size_t>(ns, 1)));
+      HIP_TRY(c, hipMalloc(&w.adj_hm, 8 * std::max<size_t>(ns, 1)));
+      w.bytes += 8 * (2 * n + 2 * ns);
+    }
+  }
+  auto with_uinf = [&](double sgn, auto&& body) -> imex_status {
+    const Gas save = c->gas;
+    for (int v = 0; v < 4; ++v) c->gas.uinf[v] = save.uinf[v] + sgn * peps * duinf[v];
+    const imex_status r = body();
+    c->gas = save;
+    return r;
+  };
+  auto pdot = [&](int kind, int scaled, const double* a, const double* b, double* out) -> imex_status {
+    constexpr int nblk = 256;
+    HIP_TRY(c, launch_param_dot(c, kind, scaled, a, b, w.red, nblk));
+    HIP_TRY(c, hipMemcpyAsync(w.hred, w.red, sizeof(double) * nblk, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(c, hipStreamSynchronize(hs));
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += w.hred[b];
+    *out = acc;
+    return IMEX_OK;
+  };
+  // <Rbar, dR^DG/dp> for the explicit residual at (Y, Hin)
+  auto p_dg = [&](const double* Y, const double* Hin, const double* Rb) -> imex_status {
+    if (!want_p || peps == 0.0) return IMEX_OK;
+    imex_status r = with_uinf(1.0, [&] { return dg_residual_async(c, Y, Hin, w.adj_rp); });
+    if (r != IMEX_OK) return r;
+    r = with_uinf(-1.0, [&] { return dg_residual_async(c, Y, Hin, w.adj_rm); });
+    if (r != IMEX_OK) return r;
+    HIP_TRY(c, launch_scale_copy(c, w.adj_rp, w.adj_rp, 0.5 / peps, w.adj_rm, -0.5 / peps, n));
+    double d = 0.0;
+    r = pdot(0, 0, Rb, w.adj_rp, &d);
+    pacc += d;
+    return r;
+  };
+  // implicit stage at (Y, H) with the solution (lam, lamhat) of its transposed system:
+  // <Rhbar, dR^HDG/dp> - <lam, dt_a dR^HDG/dp> - <lamhat, dh/dp>
+  auto p_hdg = [&](double dt_a, const double* Y, const double* H, const double* Rhbar,
+                   const double* lam) -> imex_status {
+    if (!want_p || peps == 0.0) return IMEX_OK;
+    const size_t ns = (size_t)c->n_im * 16 * c->NP;
+    const double* lamhat = adjoint_facet_solution(c);
+    HIP_TRY(c, hipMemsetAsync(w.adj_rp, 0, 8 * n, hs));
+    HIP_TRY(c, hipMemsetAsync(w.adj_rm, 0, 8 * n, hs));
+    imex_status r = with_uinf(1.0, [&]() -> imex_status {
+      HIP_TRY(c, launch_hdg_residual(c, dt_a, Y, H, w.adj_rp));
+      HIP_TRY(c, hipMemcpyAsync(w.adj_hp, w.hres, 8 * ns, hipMemcpyDeviceToDevice, hs));
+      return IMEX_OK;
+    });
+    if (r != IMEX_OK) return r;
+    r = with_uinf(-1.0, [&]() -> imex_status {
+      HIP_TRY(c, launch_hdg_residual(c, dt_a, Y, H, w.adj_rm));
+      HIP_TRY(c, hipMemcpyAsync(w.adj_hm, w.hres, 8 * ns, hipMemcpyDeviceToDevice, hs));
+      return IMEX_OK;
+    });
+    if (r != IMEX_OK) return r;
+    HIP_TRY(c, launch_scale_copy(c, w.adj_rp, w.adj_rp, 0.5 / peps, w.adj_rm, -0.5 / peps, n));
+    HIP_TRY(c, launch_scale_copy(c, w.adj_hp, w.adj_hp, 0.5 / peps, w.adj_hm, -0.5 / peps, ns));
+    double d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    if (Rhbar && (r = pdot(1, 0, Rhbar, w.adj_rp, &d1)) != IMEX_OK) return r;
+    if ((r = pdot(1, 1, lam, w.adj_rp, &d2)) != IMEX_OK) return r;
+    if ((r = pdot(2, 0, lamhat, w.adj_hp, &d3)) != IMEX_OK) return r;
+    pacc += d1 - dt_a * d2 - d3;
+    return IMEX_OK;
+  };
   // HDG-MX: the explicit residual of stage i reads the mixed variables lifted from
   // (y^im_{i-1}, Uhat_{i-1}); their adjoint goes to that facet state as well
   auto hin = [&](int i) -> const double* { return i >= 2 ? tape.Hsol[i - 2] : Uhat; };
@@ -998,6 +1085,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Ubar_next, Ubar));
     for (int j = 1; j <= s + 1; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->be[j - 1], Ubar_next, Rdgb[j]));
     HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[s], Rdgb[s + 1], Yb, mx ? tape.Hsol[s - 1] : nullptr, hb[s]));
+    if (imex_status r = p_dg(tape.Ydg[s], tape.Hsol[s - 1], Rdgb[s + 1]); r != IMEX_OK) return r;
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, yexb[s + 1]));
     HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[s]));
   }
@@ -1006,9 +1094,11 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
     // (d) implicit stage i
     HIP_TRY(c, hipMemsetAsync(rhsb, 0, n * 8, hs));
     int its = 0;
-    imex_status r = hdg_stage_adjoint(c, dt * tab->Ai[3 * (i - 1) + (i - 1)], tape.Ysol[i - 1], tape.Hsol[i - 1],
-                                      Rhb[i], yimb[i], hb[i], rhsb, yexb[i + 1], &its);
+    const double dta = dt * tab->Ai[3 * (i - 1) + (i - 1)];
+    imex_status r = hdg_stage_adjoint(c, dta, tape.Ysol[i - 1], tape.Hsol[i - 1], Rhb[i], yimb[i], hb[i], rhsb,
+                                      yexb[i + 1], &its);
     if (r != IMEX_OK) return r;
+    if ((r = p_hdg(dta, tape.Ysol[i - 1], tape.Hsol[i - 1], Rhb[i], rhsb)) != IMEX_OK) return r;
     gm_total += its;
     // (c) right-hand side
     HIP_TRY(c, launch_rows_axpy(c, 2, 1, 1.0, rhsb, Ubar));
@@ -1018,6 +1108,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
     for (int j = 1; j <= i; ++j) HIP_TRY(c, launch_rows_axpy(c, 1, 2, -dt * tab->Ae[4 * i + (j - 1)], yexb[i + 1], Rdgb[j]));
     // (a) explicit residual of stage i at (y^ex_i, y^im_{i-1})
     HIP_TRY(c, launch_dg_vjp(c, tape.Ydg[i - 1], Rdgb[i], Yb, mx ? hin(i) : nullptr, hout(i)));
+    if ((r = p_dg(tape.Ydg[i - 1], hin(i), Rdgb[i])) != IMEX_OK) return r;
     HIP_TRY(c, launch_rows_axpy(c, 1, 0, 1.0, Yb, i >= 2 ? yexb[i] : Ubar));
     HIP_TRY(c, launch_rows_axpy(c, 2, 0, 1.0, Yb, yimb[i - 1]));
   }
@@ -1025,6 +1116,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   HIP_TRY(c, hipStreamSynchronize(hs));
   c->timers_resolve();
   if (st) st->gmres_its = gm_total;
+  if (want_p) *pbar = pacc;
   return IMEX_OK;
 }
 

@@ -92,6 +92,10 @@ struct Workspace {
   double* adj_P = nullptr;      // [n_hf][NFF][NFF] facet block-Jacobi factors of S^T
   double* adj_w = nullptr;      // [E][4][NN] element scratch of the transposed solve
   std::vector<double*> adj_buf; // step-adjoint tape and adjoints ([E][4][NN] or facet-sized)
+  double* adj_rp = nullptr;     // [E][4][NN] residuals at u_inf +- eps du_inf (parameter adjoint)
+  double* adj_rm = nullptr;
+  double* adj_hp = nullptr;     // [n_im][NF] facet residual shares at u_inf +- eps du_inf
+  double* adj_hm = nullptr;
   double* red = nullptr;        // reduction scratch
   double* hred = nullptr;       // pinned host reduction buffer
   size_t bytes = 0;
@@ -186,6 +190,10 @@ bool dg_tile_valid(int K, int et);
 hipError_t launch_init_facets(const imex_ctx* c, const double* U, double* Uhat);
 hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* Ub);
 hipError_t launch_wall_shear(const imex_ctx* c, const double* Q, double* part);
+hipError_t launch_hdg_residual(imex_ctx* c, double dt_a, const double* Y, const double* H, double* Rh);
+const double* adjoint_facet_solution(const imex_ctx* c);
+hipError_t launch_param_dot(const imex_ctx* c, int kind, int scaled, const double* a, const double* b, double* part,
+                            int nblk);
 hipError_t launch_wall_shear_qbar(const imex_ctx* c, double scale, double* Qb);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);

@@ -1642,43 +1642,55 @@ template <int K> struct RasDims {
   static constexpr int NFF = 4 * (K + 1), NB = 5 * NFF, NH = 2 * NFF, NSV = 2 * NB + NH;
 };
 
-// y_r = x_r, then y_r[H] -= G_r[:, ~H] x_{r-1}[~H]
+// y_r = x_r, then y_r[H] -= G_r[:, ~H] x_{r-1}[~H].  The H-row products are split over
+// P = 128 / NH slices of the ~H columns so that every thread issues its loads at once.
 template <int K, class T>
 __global__ void __launch_bounds__(128) ras_pre_kernel(DeviceHDG h, const T* __restrict__ Wg,
                                                       const double* __restrict__ x, double* __restrict__ Wy) {
   using D = RasDims<K>;
-  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
-  __shared__ double xp[NB], yr[NB];
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH, NX = NB - NH;
+  constexpr int P = 128 / NH, CH = (NX + P - 1) / P;
+  __shared__ double xp[NX], yr[NB], part[P][NH];
   const int g = blockIdx.x, tid = threadIdx.x;
   const int fl = h.sr_flags[g];
   for (int i = tid; i < NB; i += blockDim.x) {
     const int a = i / NFF;
     const int f = h.win_slot[5 * g + a];
     yr[i] = (f >= 0) ? x[(size_t)f * NFF + i % NFF] : 0.0;
-    int fp = -1;
-    if (fl & 1) fp = h.win_slot[5 * (g - 1) + a];
-    xp[i] = (fp >= 0) ? x[(size_t)fp * NFF + i % NFF] : 0.0;
+    if (i >= NH) {
+      int fp = -1;
+      if (fl & 1) fp = h.win_slot[5 * (g - 1) + a];
+      xp[i - NH] = (fp >= 0) ? x[(size_t)fp * NFF + i % NFF] : 0.0;
+    }
   }
   __syncthreads();
   const T* Gg = Wg + (size_t)g * NH * NB;        // Gg[k * NH + i] = G_r[i][k]
+  if ((fl & 1) && tid < P * NH) {
+    const int i = tid % NH, q = tid / NH, k0 = q * CH;
+    double a = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < CH; ++kk) {
+      const int k = k0 + kk;
+      if (k < NX) a += (double)Gg[(size_t)(NH + k) * NH + i] * xp[k];
+    }
+    part[q][i] = a;
+  }
+  __syncthreads();
   double* Y = Wy + (size_t)g * D::NSV;
   for (int i = tid; i < NB; i += blockDim.x) {
     double v = yr[i];
     if ((fl & 1) && i < NH) {
-      double a0 = 0.0, a1 = 0.0;
-      int k = NH;
-      for (; k + 1 < NB; k += 2) {
-        a0 += (double)Gg[(size_t)k * NH + i] * xp[k];
-        a1 += (double)Gg[(size_t)(k + 1) * NH + i] * xp[k + 1];
-      }
-      for (; k < NB; ++k) a0 += (double)Gg[(size_t)k * NH + i] * xp[k];
-      v -= a0 + a1;
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) a += part[q][i];
+      v -= a;
     }
     Y[i] = v;
   }
 }
 
-// forward chain: y_r[H] -= G_r[:, H] y_{r-1}[H], one wave per window
+// forward chain: y_r[H] -= G_r[:, H] y_{r-1}[H], one wave per window; the next super-row's
+// block and vector are fetched while the current one is applied
 template <int K, class T>
 __global__ void __launch_bounds__(64) ras_fwd_kernel(DeviceHDG h, const T* __restrict__ Wg, double* __restrict__ Wy) {
   using D = RasDims<K>;
@@ -1690,22 +1702,25 @@ __global__ void __launch_bounds__(64) ras_fwd_kernel(DeviceHDG h, const T* __res
   if (g1 <= g0) return;
   if (lane < NH) yh[lane] = Wy[(size_t)g0 * D::NSV + lane];
   T gc[NH];
+  double ycur = 0.0;
   if (g0 + 1 < g1 && lane < NH) {
     const T* Gg = Wg + (size_t)(g0 + 1) * NH * NB;
 #pragma unroll
     for (int k = 0; k < NH; ++k) gc[k] = Gg[(size_t)k * NH + lane];
+    ycur = Wy[(size_t)(g0 + 1) * D::NSV + lane];
   }
   __syncthreads();
   for (int g = g0 + 1; g < g1; ++g) {
     T gn[NH];
+    double ynext = 0.0;
     if (g + 1 < g1 && lane < NH) {
       const T* Gn = Wg + (size_t)(g + 1) * NH * NB;
 #pragma unroll
       for (int k = 0; k < NH; ++k) gn[k] = Gn[(size_t)k * NH + lane];
+      ynext = Wy[(size_t)(g + 1) * D::NSV + lane];
     }
-    double v = 0.0;
+    double v = ycur;
     if (lane < NH) {
-      v = Wy[(size_t)g * D::NSV + lane];
 #pragma unroll
       for (int k = 0; k < NH; ++k) v -= (double)gc[k] * yh[k];
     }
@@ -1718,32 +1733,41 @@ __global__ void __launch_bounds__(64) ras_fwd_kernel(DeviceHDG h, const T* __res
     if (g + 1 < g1) {
 #pragma unroll
       for (int k = 0; k < NH; ++k) gc[k] = gn[k];
+      ycur = ynext;
     }
   }
 }
 
-// w_r = D_r^-1 y_r, one workgroup per super-row
+// w_r = D_r^-1 y_r, one workgroup of 256 per super-row, the columns split over
+// P = 256 / NB slices
 template <int K, class T>
-__global__ void __launch_bounds__(128) ras_diag_kernel(DeviceHDG h, const T* __restrict__ Wd, double* __restrict__ Wy) {
+__global__ void __launch_bounds__(256) ras_diag_kernel(DeviceHDG h, const T* __restrict__ Wd, double* __restrict__ Wy) {
   using D = RasDims<K>;
   constexpr int NB = D::NB;
-  __shared__ double yv[NB];
+  constexpr int P = 256 / NB, CH = (NB + P - 1) / P;
+  __shared__ double yv[NB], part[P][NB];
   const int g = blockIdx.x, tid = threadIdx.x;
   double* Y = Wy + (size_t)g * D::NSV;
   for (int i = tid; i < NB; i += blockDim.x) yv[i] = Y[i];
   __syncthreads();
   const T* Dg = Wd + (size_t)g * NB * NB;        // Dg[k * NB + i] = D_r^-1[i][k]
-  for (int i = tid; i < NB; i += blockDim.x) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = 0;
-    for (; k + 3 < NB; k += 4) {
-      a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
-      a1 += (double)Dg[(size_t)(k + 1) * NB + i] * yv[k + 1];
-      a2 += (double)Dg[(size_t)(k + 2) * NB + i] * yv[k + 2];
-      a3 += (double)Dg[(size_t)(k + 3) * NB + i] * yv[k + 3];
+  if (tid < P * NB) {
+    const int i = tid % NB, q = tid / NB, k0 = q * CH;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < CH; kk += 2) {
+      const int k = k0 + kk;
+      if (k < NB) a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
+      if (kk + 1 < CH && k + 1 < NB) a1 += (double)Dg[(size_t)(k + 1) * NB + i] * yv[k + 1];
     }
-    for (; k < NB; ++k) a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
-    Y[NB + i] = (a0 + a1) + (a2 + a3);
+    part[q][i] = a0 + a1;
+  }
+  __syncthreads();
+  for (int i = tid; i < NB; i += blockDim.x) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) a += part[q][i];
+    Y[NB + i] = a;
   }
 }
 
@@ -1762,22 +1786,25 @@ __global__ void __launch_bounds__(64) ras_bwd_kernel(DeviceHDG h, const T* __res
     Wy[(size_t)(g1 - 1) * D::NSV + 2 * NB + lane] = v;
   }
   T ec[NH];
+  double wcur = 0.0;
   if (g1 - 2 >= g0 && lane < NH) {
     const T* Eg = Wc + (size_t)(g1 - 2) * NB * NH;
 #pragma unroll
     for (int k = 0; k < NH; ++k) ec[k] = Eg[(size_t)k * NB + lane];
+    wcur = Wy[(size_t)(g1 - 2) * D::NSV + NB + lane];
   }
   __syncthreads();
   for (int g = g1 - 2; g >= g0; --g) {
     T en[NH];
+    double wnext = 0.0;
     if (g - 1 >= g0 && lane < NH) {
       const T* En = Wc + (size_t)(g - 1) * NB * NH;
 #pragma unroll
       for (int k = 0; k < NH; ++k) en[k] = En[(size_t)k * NB + lane];
+      wnext = Wy[(size_t)(g - 1) * D::NSV + NB + lane];
     }
-    double v = 0.0;
+    double v = wcur;
     if (lane < NH) {
-      v = Wy[(size_t)g * D::NSV + NB + lane];
 #pragma unroll
       for (int k = 0; k < NH; ++k) v -= (double)ec[k] * zh[k];
     }
@@ -1790,23 +1817,38 @@ __global__ void __launch_bounds__(64) ras_bwd_kernel(DeviceHDG h, const T* __res
     if (g - 1 >= g0) {
 #pragma unroll
       for (int k = 0; k < NH; ++k) ec[k] = en[k];
+      wcur = wnext;
     }
   }
 }
 
-// z_r[~H] = w_r[~H] - E_r[~H, :] z_{r+1}[H]; owned facets of z written
+// z_r[~H] = w_r[~H] - E_r[~H, :] z_{r+1}[H] (the H columns split over P = 128 / NX slices);
+// owned facets of z written
 template <int K, class T>
 __global__ void __launch_bounds__(128) ras_out_kernel(DeviceHDG h, const T* __restrict__ Wc,
                                                       const double* __restrict__ Wy, double* __restrict__ z) {
   using D = RasDims<K>;
-  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
-  __shared__ double zn[NH];
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH, NX = NB - NH;
+  constexpr int P = 128 / NX, CH = (NH + P - 1) / P;
+  static_assert(P >= 1, "slices");
+  __shared__ double zn[NH], part[P][NX];
   const int g = blockIdx.x, tid = threadIdx.x;
   const int fl = h.sr_flags[g];
   const double* Y = Wy + (size_t)g * D::NSV;
   if ((fl & 2) && tid < NH) zn[tid] = Wy[(size_t)(g + 1) * D::NSV + 2 * NB + tid];
   __syncthreads();
   const T* Eg = Wc + (size_t)g * NB * NH;         // Eg[k * NB + i] = E_r[i][k]
+  if ((fl & 2) && tid < P * NX) {
+    const int i = tid % NX, q = tid / NX, k0 = q * CH;
+    double a = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < CH; ++kk) {
+      const int k = k0 + kk;
+      if (k < NH) a += (double)Eg[(size_t)k * NB + NH + i] * zn[k];
+    }
+    part[q][i] = a;
+  }
+  __syncthreads();
   for (int i = tid; i < NB; i += blockDim.x) {
     double v;
     if (i < NH) {
@@ -1814,12 +1856,10 @@ __global__ void __launch_bounds__(128) ras_out_kernel(DeviceHDG h, const T* __re
     } else {
       v = Y[NB + i];
       if (fl & 2) {
-        double a0 = 0.0, a1 = 0.0;
-        for (int k = 0; k < NH; k += 2) {
-          a0 += (double)Eg[(size_t)k * NB + i] * zn[k];
-          a1 += (double)Eg[(size_t)(k + 1) * NB + i] * zn[k + 1];
-        }
-        v -= a0 + a1;
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) a += part[q][i - NH];
+        v -= a;
       }
     }
     const int a = i / NFF;
@@ -1834,7 +1874,6 @@ __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* _
                                                          const double* __restrict__ x, double* __restrict__ y) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
   __shared__ double xs[2][NF];
-  __shared__ double part[NFF][65];
   const int hf = blockIdx.x, tid = threadIdx.x;
   int pe[2], fc[2];
   for (int s = 0; s < 2; ++s) {
@@ -1857,14 +1896,16 @@ __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* _
       for (int r = 0; r < NFF; ++r) acc[r] += (double)Sb[(size_t)r * NC + c] * xc;
     }
   }
+  // butterfly sums over the wave; lane r keeps row r
+  double out = 0.0;
 #pragma unroll
-  for (int r = 0; r < NFF; ++r) part[r][tid] = acc[r];
-  __syncthreads();
-  if (tid < NFF) {
-    double sum = 0.0;
-    for (int i = 0; i < 64; ++i) sum += part[tid][i];
-    y[(size_t)hf * NFF + tid] = sum;
+  for (int r = 0; r < NFF; ++r) {
+    double v = acc[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (tid == r) out = v;
   }
+  if (tid < NFF) y[(size_t)hf * NFF + tid] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -2622,7 +2663,7 @@ static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
     hipLaunchKernelGGL((ras_pre_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wg), x, w.Wy);
     hipLaunchKernelGGL((ras_fwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wg), w.Wy);
-    hipLaunchKernelGGL((ras_diag_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wd), w.Wy);
+    hipLaunchKernelGGL((ras_diag_kernel<KK, LT>), dim3(nsr), dim3(256), 0, c->stream, c->dhdg(), la<LT>(w.Wd), w.Wy);
     hipLaunchKernelGGL((ras_bwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy);
     hipLaunchKernelGGL((ras_out_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy, y);
   }));
@@ -2938,6 +2979,17 @@ imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const d
   }));
   HTRY(hipGetLastError());
   return IMEX_OK;
+}
+
+// R^HDG (implicit rows of Rh) and the facet residual shares (ws.hres) at (Y, H), FP64
+hipError_t launch_hdg_residual(imex_ctx* c, double dt_a, const double* Y, const double* H, double* Rh) {
+  return launch_assemble(c, dt_a, Y, H, nullptr, 0, Rh);
+}
+
+// the facet part of the last hdg_stage_adjoint solution (valid until the next facet solve)
+const double* adjoint_facet_solution(const imex_ctx* c) {
+  const size_t nh = (size_t)c->n_hf * 4 * c->NP;
+  return c->ws.gm + nh * (c->opt.gmres_restart + 3) + nh;
 }
 
 // dst[b][i][j] = src[b * sstride + i * sld + j] for b < batch, i < rows, j < cols (dst dense, FP64)

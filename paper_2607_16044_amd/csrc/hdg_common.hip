@@ -133,6 +133,36 @@ __global__ void wall_shear_qbar_kernel(DeviceMesh m, DeviceHDG h, double scale, 
   Qb[((size_t)e * 5 + 1) * NN + n] = scale * acc;
 }
 
+// Partial sums (one per block of 256 threads) of a . b for the parameter adjoint:
+// kind 0 all element rows; kind 1 implicit rows, each element weighted by its instance
+// time-step scale when scaled != 0; kind 2 facet shares: a is a facet vector, b holds
+// per-implicit-element facet rows [p][face][v][m], summed as a[facet of face] . b[p][face].
+template <int K>
+__global__ void __launch_bounds__(256) param_dot_kernel(DeviceMesh m, DeviceHDG h, int E, int kind, int scaled,
+                                                        const double* __restrict__ a, const double* __restrict__ b,
+                                                        double* __restrict__ part) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NFF = 4 * NP, NF = 4 * NFF;
+  __shared__ double red4[4];
+  const long long n = kind == 0 ? (long long)E * NU : (long long)h.n_im * (kind == 1 ? NU : NF);
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    if (kind == 0) {
+      acc += a[t] * b[t];
+    } else if (kind == 1) {
+      const int p = (int)(t / NU), i = (int)(t % NU), e = h.im_list[p];
+      const size_t gi = (size_t)e * NU + i;
+      acc += a[gi] * b[gi] * (scaled ? elem_dt(m, e) : 1.0);
+    } else {
+      const int p = (int)(t / NF), r = (int)(t % NF), f = r / NFF, j = r % NFF;
+      acc += a[(size_t)h.efacet[4 * p + f] * NFF + j] * b[t];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red4[0] + red4[1] + red4[2] + red4[3];
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG h, Gas g,
                                                          const double* __restrict__ U,
@@ -413,6 +443,13 @@ hipError_t launch_init_facets_vjp(const imex_ctx* c, const double* Hb, double* U
   for (int f = 0; f < 4; ++f)
     IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(init_facets_vjp_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0,
                                              c->stream, c->dmesh(), c->dhdg(), f, Hb, Ub));
+  return hipGetLastError();
+}
+
+hipError_t launch_param_dot(const imex_ctx* c, int kind, int scaled, const double* a, const double* b, double* part,
+                            int nblk) {
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(param_dot_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
+                                           c->dhdg(), c->E, kind, scaled, a, b, part));
   return hipGetLastError();
 }
 

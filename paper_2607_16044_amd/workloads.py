@@ -247,6 +247,12 @@ def boundary_layer(nx: int = 256, ny: int = 128, k: int = 4, implicit_rows: int 
                     tableau=tableau, dt=dt, steps=steps, ic=ic)
 
 
+def farfield_mach_direction(gamma: float, Ma: float) -> np.ndarray:
+    """d u_inf / d Ma of the boundary-layer far-field state (rho = |u| = 1, p = 1 / (gamma Ma^2)):
+    only the energy changes, by dp/dMa / (gamma - 1)."""
+    return np.array([0.0, 0.0, 0.0, -2.0 / (gamma * (gamma - 1.0) * Ma ** 3)])
+
+
 def vortex_ensemble(n: int = 512, seed: int = 4, steps: int = 5, nmin: int = 8, nmax: int = 48):
     """Independent isentropic-vortex instances: square meshes N x N with N uniform in
     [nmin, nmax], degree uniform in {1, 2, 3, 4}, vortex strength uniform in [1, 5], a centred

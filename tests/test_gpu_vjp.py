@@ -401,3 +401,60 @@ def test_wall_shear_objective_gradient():
     print("objective", vals[0], got, fd, err, fdo, erro)
     assert err < 1e-6
     assert erro < 1e-4
+
+
+def test_wall_shear_objective_mach_derivative():
+    """dJ/dMa of the averaged wall shear (U_0 and dt fixed; Ma enters through the far-field
+    state) from the far-field parameter adjoint, against central differences of GPU runs
+    at Ma +- h and of the oracle's runs; and the total derivative through the initial state
+    (its energy carries p_inf = 1 / (gamma Ma^2)) against runs from the perturbed initial
+    state."""
+    from oracle.hdg import init_mixed, wall_shear
+    from paper_2607_16044_amd.autograd import wall_shear_objective
+    Ma = 0.3
+
+    def make(ma):
+        return W.boundary_layer(nx=6, ny=6, k=2, implicit_rows=2, Lx=6 * 2.0 / 256, height=None, steps=2,
+                                name="bl_mach", Ma=ma)
+    wl = make(Ma)
+    dt, nsteps, window = wl.dt, 4, (2, 4)
+    kw = dict(newton_rtol=1e-14, gmres_rtol=1e-13)
+    eng = gpu_engine(wl, **kw)
+    U0 = eng.initial_state()
+    duinf = W.farfield_mach_direction(wl.gamma, Ma)
+    U = U0.clone().requires_grad_(True)
+    p = torch.zeros((), dtype=torch.float64, device="cuda", requires_grad=True)
+    J = wall_shear_objective(eng, U, dt, nsteps, window, checkpoint=2, p=p, duinf=duinf)
+    J.backward()
+    partial = float(p.grad)
+    dU0 = torch.zeros_like(U0)
+    dU0[:, 3] = duinf[3]
+    total = partial + float((U.grad * dU0).sum())
+
+    def Jg(ma, from_ic):
+        e = gpu_engine(make(ma), **kw)
+        start = e.initial_state() if from_ic else U0
+        with torch.no_grad():
+            out = float(wall_shear_objective(e, start, dt, nsteps, window))
+        e.close()
+        return out
+    h = 1e-5
+    fd = (Jg(Ma + h, False) - Jg(Ma - h, False)) / (2 * h)
+    fdt = (Jg(Ma + h, True) - Jg(Ma - h, True)) / (2 * h)
+    err, errt = abs(partial - fd) / abs(fd), abs(total - fdt) / abs(fdt)
+
+    def Jo(ma):
+        ora = IMEXSolver(make(ma), U0=U0.cpu().numpy())
+        ora.wl.dt = dt
+        acc = 0.0
+        for n in range(1, nsteps + 1):
+            ora.step()
+            if window[0] <= n <= window[1]:
+                acc += wall_shear(init_mixed(ora.U, ora.Uhat, ora.system), ora.mesh, ora.basis, ora.gas)
+        return acc / (window[1] - window[0] + 1)
+    fdo = (Jo(Ma + 1e-4) - Jo(Ma - 1e-4)) / 2e-4
+    erro = abs(partial - fdo) / abs(fdo)
+    print("dJ/dMa", partial, fd, err, fdo, erro, "total", total, fdt, errt)
+    assert err < 1e-6
+    assert errt < 1e-6
+    assert erro < 1e-4
