@@ -89,6 +89,40 @@ def cpu_baseline():
             "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "gemm_elimination_boundary_layer_mixed_counters.md")
+
+
+def gemm_source_digest():
+    """sha256 of the batched MFMA GEMM's source (from its MFMA wrapper to the end of its
+    launcher): the HBM counters in profiles/ hold for this text only."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2607_16044_amd", "csrc", "hdg.hip")).read()
+    a = src.index("template <class T> struct Mfma16;")
+    b = src.index("static hipError_t gemm_batched(")
+    b = src.index("\n}\n", b) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per elimination launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when it is missing, for another precision, or taken on another kernel source."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    try:
+        if vals.get("precision") != precision or vals.get("kernel_source_sha256") != gemm_source_digest():
+            return None
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def elimination_work(wl, n_im, la_bytes):
     """Algorithmic flops and HBM bytes of one mixed-block elimination launch:
     [[K C],[D E]] -= [A12; A32] (M_Q^-1 [A21 A23]) per implicit element, NR = NU + NF
@@ -193,7 +227,7 @@ def main():
         gbs = nbytes / (avg_ms * 1e-3) / 1e9
         tfl = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                "traffic": None,
+                "traffic": measured_traffic(main_prec),
                 "kernel": f"gemm_kernel<{'float' if main_prec == 'mixed' else 'double'}> (mixed-block elimination)",
                 "avg_ms": avg_ms, "launch_bytes": nbytes, "launch_flops": flops, "mfma_tflops": tfl,
                 "mfma_frac": tfl / PEAK_TFLOPS[main_prec]}

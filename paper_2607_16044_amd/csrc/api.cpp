@@ -142,6 +142,9 @@ void imex_ctx::drop_graphs() {
     g.exec = nullptr;
     g.key.clear();
   }
+  for (auto& kv : gm_graphs)
+    if (kv.second) hipGraphExecDestroy(kv.second);
+  gm_graphs.clear();
 }
 
 int imex_ctx::timer_begin(int tag) {

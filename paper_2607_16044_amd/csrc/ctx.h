@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,7 @@ struct imex_ctx {
   bool capturing = false;
   hipStream_t gstream = nullptr;
   StageGraph sg[5];
+  std::map<int, hipGraphExec_t> gm_graphs;   // GMRES inner blocks by (first column, adjoint mode)
   void drop_graphs();
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
   static constexpr int NTIMER = 8;

@@ -196,6 +196,21 @@ template <class T> __device__ inline void lift_point(const T W[4], const Gas& g,
 // ---------------------------------------------------------------------------
 // assembly
 // ---------------------------------------------------------------------------
+// dual-number seeds per pass of the point-wise Jacobians (1, 2 or 4)
+#ifndef ASM_SEEDS
+#define ASM_SEEDS 1
+#endif
+static_assert(ASM_SEEDS == 1 || ASM_SEEDS == 2 || ASM_SEEDS == 4, "seeds per pass");
+// optional bound on the assembly kernel's waves per SIMD (0: the compiler's choice)
+#ifndef ASM_WAVES_PER_EU
+#define ASM_WAVES_PER_EU 0
+#endif
+#if ASM_WAVES_PER_EU > 0
+#define ASM_WAVES __attribute__((amdgpu_waves_per_eu(ASM_WAVES_PER_EU, ASM_WAVES_PER_EU)))
+#else
+#define ASM_WAVES
+#endif
+
 struct AsmParams {
   double dt_a;
   double alpha;
@@ -203,21 +218,26 @@ struct AsmParams {
   int jacobian;      // 0: residual only
 };
 
-template <int K, bool MX> struct AsmShared {
+// DUMP: the point-wise Jacobians go straight to the element's record in global memory
+// (same layout), so the workgroup's LDS holds only the values and several elements
+// share a CU.
+template <int K, bool MX, bool DUMP = false> struct AsmShared {
   using S = HS<K, MX>;
+  static constexpr int NJV = DUMP ? 1 : S::NQV, NJF = DUMP ? 1 : 4, NJL = (MX && !DUMP) ? S::NQV : 1,
+                       NJLF = (MX && !DUMP) ? 4 : 1;
   BasisTable tb;
   double U[S::NU];
   double Uh[S::NF];                   // [face][v][m]
   double Q[MX ? S::NQM : 1];          // [c][n]
   double uex[4][S::NQ][4];
   double VV[S::NQV][8];               // volume point outputs
-  double JV[S::NQV][8][S::NIV];       // d out / d in at volume points
+  double JV[NJV][8][S::NIV];          // d out / d in at volume points
   double VF[4][S::NQ][S::NOF];        // face point outputs
-  double JF[4][S::NQ][S::NOF][S::NIF];
+  double JF[NJF][S::NQ][S::NOF][S::NIF];
   double PL[S::NQV][3];               // lifting inputs at volume points (MX)
-  double JL[MX ? S::NQV : 1][3][4];
+  double JL[NJL][3][4];
   double PLF[4][S::NQ][3];
-  double JLF[MX ? 4 : 1][S::NQ][3][4];
+  double JLF[NJLF][S::NQ][3][4];
   double Gv[S::NQV][8];               // grad U at volume points (IP)
   double Gf[4][S::NQ][8];             // grad U at face points (IP)
   double Wv[S::NQV][4];
@@ -249,7 +269,7 @@ template <int K> using MxRec = PointRec<K, true>;
 // DUMP = true (HDG-MX, inviscid HDG-IP): residual rows here, the point-wise
 // Jacobians go to rec for hdg_contract_kernel.
 template <int K, bool MX, bool DUMP, class T>
-__global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
+__global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ Uhat,
                                                            const double* __restrict__ rhs, T* __restrict__ blk,
@@ -260,7 +280,26 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
   extern __shared__ double smem_raw[];
-  AsmShared<K, MX>& sh = *reinterpret_cast<AsmShared<K, MX>*>(smem_raw);
+  AsmShared<K, MX, DUMP>& sh = *reinterpret_cast<AsmShared<K, MX, DUMP>*>(smem_raw);
+  using Rec = PointRec<K, MX>;
+  double* const rp = DUMP ? rec + (size_t)blockIdx.x * Rec::SIZE : nullptr;
+  // point-wise Jacobian entries: LDS, or the record in global memory (DUMP)
+  auto jv = [&](int qv, int o, int col) -> double& {
+    if constexpr (DUMP) return rp[Rec::JV + ((size_t)qv * 8 + o) * NIV + col];
+    else return sh.JV[qv][o][col];
+  };
+  auto jf = [&](int f, int q, int o, int col) -> double& {
+    if constexpr (DUMP) return rp[Rec::JF + (((size_t)f * NQ + q) * NOF + o) * NIF + col];
+    else return sh.JF[f][q][o][col];
+  };
+  auto jl = [&](int qv, int c, int v) -> double& {
+    if constexpr (DUMP) return rp[Rec::JL + ((size_t)qv * 3 + c) * 4 + v];
+    else return sh.JL[MX ? qv : 0][c][v];
+  };
+  auto jlf = [&](int f, int q, int c, int v) -> double& {
+    if constexpr (DUMP) return rp[Rec::JLF + (((size_t)f * NQ + q) * 3 + c) * 4 + v];
+    else return sh.JLF[MX ? f : 0][q][c][v];
+  };
   const int p = blockIdx.x;
   const int e = h.im_list[p];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -422,11 +461,13 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
     }
     __syncthreads();
   }
-  // ---- point-wise outputs and Jacobians (dual numbers, 4 seeds per pass) ----
-  constexpr int CV0 = (NIV + 3) / 4, CF0 = (NIF + 3) / 4, CL = 1;
+  // ---- point-wise outputs and Jacobians (dual numbers, NSD seeds per pass) ----
+  // Fewer seeds per pass cost more passes but far fewer registers per task.
+  constexpr int NSD = ASM_SEEDS;
+  constexpr int CV0 = (NIV + NSD - 1) / NSD, CF0 = (NIF + NSD - 1) / NSD, CL = 4 / NSD;
   // inviscid HDG-IP: the outputs do not depend on grad U, only the chunks of U (and Uhat)
   const bool full = MX || g.viscous || !DUMP;
-  const int CV = full ? CV0 : 1, CF = full ? CF0 : 2;
+  const int CV = full ? CV0 : 4 / NSD, CF = full ? CF0 : 8 / NSD;
   const int ntask = NQV * CV + 4 * NQ * CF + (MX ? (NQV + 4 * NQ) * CL : 0);
   for (int task = tid; task < (prm.jacobian ? ntask : NQV + 4 * NQ); task += nt) {
     if (!prm.jacobian) {
@@ -467,23 +508,23 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       }
       continue;
     }
-    using D4 = Dual<4>;
+    using D4 = Dual<NSD>;
     if (task < NQV * CV) {
       const int qv = task / CV, ch = task % CV;
       // inputs: 0..3 U, then (MX) 4..8 Q, (IP) 4..11 grad U as [v][d]
       D4 W[4];
       for (int v = 0; v < 4; ++v) {
         W[v] = D4(sh.Wv[qv][v]);
-        const int idx = v - 4 * ch;
-        if (idx >= 0 && idx < 4) W[v].d[idx] = 1.0;
+        const int idx = v - NSD * ch;
+        if (idx >= 0 && idx < NSD) W[v].d[idx] = 1.0;
       }
       D4 out[4][2];
       if (MX) {
         D4 Qd[5];
         for (int c = 0; c < 5; ++c) {
           Qd[c] = D4(sh.Qv[qv][c]);
-          const int idx = 4 + c - 4 * ch;
-          if (idx >= 0 && idx < 4) Qd[c].d[idx] = 1.0;
+          const int idx = 4 + c - NSD * ch;
+          if (idx >= 0 && idx < NSD) Qd[c].d[idx] = 1.0;
         }
         vol_point_mx(W, Qd, g, out);
       } else {
@@ -491,17 +532,17 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         for (int v = 0; v < 4; ++v)
           for (int d = 0; d < 2; ++d) {
             G[v][d] = D4(sh.Gv[qv][2 * v + d]);
-            const int idx = 4 + 2 * v + d - 4 * ch;
-            if (idx >= 0 && idx < 4) G[v][d].d[idx] = 1.0;
+            const int idx = 4 + 2 * v + d - NSD * ch;
+            if (idx >= 0 && idx < NSD) G[v][d].d[idx] = 1.0;
           }
         vol_point_ip(W, G, g, out);
       }
       for (int v = 0; v < 4; ++v)
         for (int d = 0; d < 2; ++d) {
           if (ch == 0) sh.VV[qv][2 * v + d] = out[v][d].v;
-          for (int k = 0; k < 4; ++k) {
-            const int col = 4 * ch + k;
-            if (col < NIV) sh.JV[qv][2 * v + d][col] = out[v][d].d[k];
+          for (int k = 0; k < NSD; ++k) {
+            const int col = NSD * ch + k;
+            if (col < NIV) jv(qv, 2 * v + d, col) = out[v][d].d[k];
           }
         }
     } else if (task < NQV * CV + 4 * NQ * CF) {
@@ -519,24 +560,24 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
       for (int v = 0; v < 4; ++v) {
         W[v] = D4(sh.Wf[f][q][v]);
         Wh[v] = D4(sh.Wh[f][q][v]);
-        int idx = v - 4 * ch;
-        if (idx >= 0 && idx < 4) W[v].d[idx] = 1.0;
-        idx = 4 + v - 4 * ch;
-        if (idx >= 0 && idx < 4) Wh[v].d[idx] = 1.0;
+        int idx = v - NSD * ch;
+        if (idx >= 0 && idx < NSD) W[v].d[idx] = 1.0;
+        idx = 4 + v - NSD * ch;
+        if (idx >= 0 && idx < NSD) Wh[v].d[idx] = 1.0;
       }
       if (MX) {
         D4 Qd[5], s[4], t[4];
         for (int c = 0; c < 5; ++c) {
           Qd[c] = D4(sh.Qf[f][q][c]);
-          const int idx = 8 + c - 4 * ch;
-          if (idx >= 0 && idx < 4) Qd[c].d[idx] = 1.0;
+          const int idx = 8 + c - NSD * ch;
+          if (idx >= 0 && idx < NSD) Qd[c].d[idx] = 1.0;
         }
         face_point_mx(W, Wh, Qd, fd, g, s, t);
         for (int v = 0; v < 4; ++v) {
           if (ch == 0) { sh.VF[f][q][v] = s[v].v; sh.VF[f][q][4 + v] = t[v].v; }
-          for (int k = 0; k < 4; ++k) {
-            const int col = 4 * ch + k;
-            if (col < NIF) { sh.JF[f][q][v][col] = s[v].d[k]; sh.JF[f][q][4 + v][col] = t[v].d[k]; }
+          for (int k = 0; k < NSD; ++k) {
+            const int col = NSD * ch + k;
+            if (col < NIF) { jf(f, q, v, col) = s[v].d[k]; jf(f, q, 4 + v, col) = t[v].d[k]; }
           }
         }
       } else {
@@ -544,8 +585,8 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
         for (int v = 0; v < 4; ++v)
           for (int d = 0; d < 2; ++d) {
             G[v][d] = D4(sh.Gf[f][q][2 * v + d]);
-            const int idx = 8 + 2 * v + d - 4 * ch;
-            if (idx >= 0 && idx < 4) G[v][d].d[idx] = 1.0;
+            const int idx = 8 + 2 * v + d - NSD * ch;
+            if (idx >= 0 && idx < NSD) G[v][d].d[idx] = 1.0;
           }
         face_point_ip(W, G, Wh, fd, g, s, gc, t);
         for (int v = 0; v < 4; ++v) {
@@ -555,27 +596,33 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
             sh.VF[f][q][5 + 2 * v] = gc[v][1].v;
             sh.VF[f][q][12 + v] = t[v].v;
           }
-          for (int k = 0; k < 4; ++k) {
-            const int col = 4 * ch + k;
+          for (int k = 0; k < NSD; ++k) {
+            const int col = NSD * ch + k;
             if (col < NIF) {
-              sh.JF[f][q][v][col] = s[v].d[k];
-              sh.JF[f][q][4 + 2 * v][col] = gc[v][0].d[k];
-              sh.JF[f][q][5 + 2 * v][col] = gc[v][1].d[k];
-              sh.JF[f][q][12 + v][col] = t[v].d[k];
+              jf(f, q, v, col) = s[v].d[k];
+              jf(f, q, 4 + 2 * v, col) = gc[v][0].d[k];
+              jf(f, q, 5 + 2 * v, col) = gc[v][1].d[k];
+              jf(f, q, 12 + v, col) = t[v].d[k];
             }
           }
         }
       }
     } else if (MX) {
-      const int i = task - NQV * CV - 4 * NQ * CF;
+      const int il = task - NQV * CV - 4 * NQ * CF;
+      const int i = il / CL, lc = il % CL;
       D4 W[4], P[3];
       const double* src = (i < NQV) ? sh.Wv[i] : sh.Wh[(i - NQV) / NQ][(i - NQV) % NQ];
-      for (int v = 0; v < 4; ++v) { W[v] = D4(src[v]); W[v].d[v] = 1.0; }
+      for (int v = 0; v < 4; ++v) {
+        W[v] = D4(src[v]);
+        const int idx = v - NSD * lc;
+        if (idx >= 0 && idx < NSD) W[v].d[idx] = 1.0;
+      }
       lift_point(W, g, P);
       for (int c = 0; c < 3; ++c)
-        for (int v = 0; v < 4; ++v) {
-          if (i < NQV) sh.JL[i][c][v] = P[c].d[v];
-          else sh.JLF[(i - NQV) / NQ][(i - NQV) % NQ][c][v] = P[c].d[v];
+        for (int k = 0; k < NSD; ++k) {
+          const int v = NSD * lc + k;
+          if (i < NQV) jl(i, c, v) = P[c].d[k];
+          else jlf((i - NQV) / NQ, (i - NQV) % NQ, c, v) = P[c].d[k];
         }
     }
   }
@@ -622,19 +669,7 @@ __global__ void __launch_bounds__(256) hdg_assemble_kernel(DeviceMesh m, DeviceH
   }
   if (!prm.jacobian) return;
   if constexpr (DUMP) {
-    using R = PointRec<K, MX>;
-    double* rp = rec + (size_t)p * R::SIZE;
-    const double* jv = &sh.JV[0][0][0];
-    const double* jf = &sh.JF[0][0][0][0];
-    for (int i = tid; i < R::JF - R::JV; i += nt) rp[R::JV + i] = jv[i];
-    for (int i = tid; i < R::JL - R::JF; i += nt) rp[R::JF + i] = jf[i];
-    if constexpr (MX) {
-      const double* jl = &sh.JL[0][0][0];
-      const double* jlf = &sh.JLF[0][0][0][0];
-      for (int i = tid; i < R::JLF - R::JL; i += nt) rp[R::JL + i] = jl[i];
-      for (int i = tid; i < R::SIZE - R::JLF; i += nt) rp[R::JLF + i] = jlf[i];
-    }
-    return;
+    return;                                // the Jacobians are already in the record
   } else {
   // ---- Jacobian blocks ---------------------------------------------------------
   constexpr int TO = MX ? 4 : 12;         // offset of t rows among face outputs
@@ -1271,6 +1306,22 @@ template <class T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x
 __device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+}  // namespace imex
+// wave-wide maximum from the device library (not declared by every HIP header configuration)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+namespace imex {
+
+// Pivot keys: the high 32 bits of |a| (monotonic in |a|; sign cleared so -0 ranks as 0)
+// above the inverted row index, so one 64-bit wave maximum gives the largest |a| and,
+// on ties, the lowest row.
+__device__ __forceinline__ unsigned int pivot_bits(float a) { return __float_as_uint(a) & 0x7fffffffu; }
+__device__ __forceinline__ unsigned int pivot_bits(double a) {
+  return (unsigned int)((unsigned long long)__double_as_longlong(a) >> 32) & 0x7fffffffu;
+}
+template <class T> __device__ __forceinline__ unsigned long long pivot_key(T a, int row) {
+  return ((unsigned long long)pivot_bits(a) << 32) | (unsigned long long)(0xffffffffu - (unsigned int)row);
+}
+
 template <int N, class T> struct GJShared {
   T col[2][N];
   T row[2][N];
@@ -1303,19 +1354,13 @@ struct GJ {
           }
       }
       __syncthreads();
-      T best = used0 ? T(-1) : tabs(ck[lane]);
-      int bi = lane;
+      unsigned long long key = used0 ? 0ull : pivot_key(ck[lane], lane);
       if (!used1) {
-        const T v1 = tabs(ck[lane + 64]);
-        if (v1 > best) { best = v1; bi = lane + 64; }
+        const unsigned long long k1 = pivot_key(ck[lane + 64], lane + 64);
+        key = k1 > key ? k1 : key;
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int r = bi;
+      key = __ockl_wfred_max_u64(key);
+      const int r = (int)(0xffffffffu - (unsigned int)(key & 0xffffffffull));
       if (r == lane) used0 = true;
       if (r == lane + 64) used1 = true;
       if (tid == 0) { sh.rp[k] = r; sh.pos[r] = k; }
@@ -2474,7 +2519,7 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
   const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
   if (use_mx(c)) {
     // point values, residual rows and point-wise Jacobians; then the block contraction
-    const size_t shm = sizeof(AsmShared<KK, true>);
+    const size_t shm = sizeof(AsmShared<KK, true, true>);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
@@ -2498,7 +2543,7 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     }
   } else if (!c->gas.viscous) {
     // inviscid HDG-IP: the same split without mixed blocks (K and C D E)
-    const size_t shm = sizeof(AsmShared<KK, false>);
+    const size_t shm = sizeof(AsmShared<KK, false, true>);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
@@ -2703,6 +2748,39 @@ constexpr int PREC_REFRESH_ITS = 8;
 // a simplified Newton correction follows only a correction that contracted by at least this
 constexpr double SIMPLIFIED_QMAX = 0.05;
 
+// Run body() (kernel launches only) on the context's stream, or, with graphs enabled,
+// replay its capture for key (captured on first use; the launches of an inner GMRES
+// block depend only on the block's first column and on the workspaces).
+template <class F>
+static imex_status replay_block(imex_ctx* c, int key, F&& body) {
+  if (!c->use_graphs || c->capturing) return body();
+  auto it = c->gm_graphs.find(key);
+  if (it == c->gm_graphs.end()) {
+    hipStream_t orig = c->stream;
+    HTRY(hipStreamSynchronize(orig));
+    HTRY(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+    c->stream = c->gstream;
+    c->capturing = true;
+    const imex_status st = body();
+    c->capturing = false;
+    c->stream = orig;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->gstream, &graph);
+    if (st != IMEX_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    HTRY(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    HTRY(ei);
+    it = c->gm_graphs.emplace(key, exec).first;
+  }
+  HTRY(hipGraphLaunch(it->second, c->stream));
+  return IMEX_OK;
+}
+
 static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
@@ -2734,20 +2812,27 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
     int j = 0, jdone = -1;
     while (j < m && jdone < 0 && total < c->opt.gmres_maxit) {
       const int j1 = std::min(std::min(m, j + GM_CHECK), j + (c->opt.gmres_maxit - total));
-      for (int jj = j; jj < j1; ++jj) {
-        double* vj = V + ldv * jj;
-        double* vn = V + ldv * (jj + 1);
-        HTRY(launch_precond(c, vj, z));
-        HTRY(launch_apply(c, z, vn));
-        for (int pass = 0; pass < 2; ++pass) {
-          hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
-          hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st,
-                             pass);
+      auto block = [&]() -> imex_status {
+        for (int jj = j; jj < j1; ++jj) {
+          double* vj = V + ldv * jj;
+          double* vn = V + ldv * (jj + 1);
+          HTRY(launch_precond(c, vj, z));
+          HTRY(launch_apply(c, z, vn));
+          for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
+            hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st,
+                               pass);
+          }
+          hipLaunchKernelGGL(gm_givens_kernel, dim3(1), dim3(64), 0, c->stream, jj, st, GM_NB);
+          hipLaunchKernelGGL(gm_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, vn, st);
         }
-        hipLaunchKernelGGL(gm_givens_kernel, dim3(1), dim3(64), 0, c->stream, jj, st, GM_NB);
-        hipLaunchKernelGGL(gm_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, vn, st);
-      }
-      HTRY(hipGetLastError());
+        HTRY(hipGetLastError());
+        return IMEX_OK;
+      };
+      // full-length blocks are replayed from graphs (the block shape is then fixed by j)
+      const imex_status bs = (j1 - j == std::min(GM_CHECK, m - j)) ? replay_block(c, 2 * j + (c->adj_mode ? 1 : 0), block)
+                                                                   : block();
+      if (bs != IMEX_OK) return bs;
       HTRY(hipMemcpyAsync(hb, st + GmState::RES + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, c->stream));
       HTRY(hipStreamSynchronize(c->stream));
       for (int jj = j; jj < j1; ++jj)
