@@ -223,9 +223,12 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
  * (point-wise Jacobians + block contraction), 2 mixed-block elimination (one
  * batched GEMM launch), 3 K^-1 + condensation, 4 facet right-hand side and
  * preconditioner factorisation, 5 GMRES (including 7), 6 back-substitution and
- * update, 7 facet preconditioner applications.  host out[16]; reset != 0 clears
- * the counters after reading. */
-imex_status imex_kernel_times(imex_ctx* ctx, double out[16], int reset);
+ * update, 7 facet preconditioner applications, and single kernels inside these:
+ * 8 point-wise Jacobians (assembly launches that build a Jacobian), 9 block
+ * contraction, 10 Gauss-Jordan K^-1.  Launches inside replayed graphs are not
+ * timed.  host out[2 * IMEX_NTIMERS]; reset != 0 clears the counters after reading. */
+#define IMEX_NTIMERS 11
+imex_status imex_kernel_times(imex_ctx* ctx, double out[2 * IMEX_NTIMERS], int reset);
 
 /* Graph mode (on != 0): imex_ark_step replays the explicit sequence of every stage
  * (explicit residual, stage combination and implicit right-hand side) from a

@@ -305,10 +305,11 @@ class Engine:
         self._check(self.lib.imex_conservation_sums(self.ctx, _ptr(U), out))
         return np.array(list(out))
 
-    TIMER_NAMES = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "precond"]
+    TIMER_NAMES = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "precond",
+                   "points", "contract", "invert"]
 
     def timers(self, reset: bool = False):
-        out = (ctypes.c_double * 16)()
+        out = (ctypes.c_double * (2 * len(self.TIMER_NAMES)))()
         self._check(self.lib.imex_kernel_times(self.ctx, out, int(reset)))
         r = {}
         for i, name in enumerate(self.TIMER_NAMES):

@@ -1123,7 +1123,9 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   return IMEX_OK;
 }
 
-imex_status imex_kernel_times(imex_ctx* c, double out[16], int reset) {
+static_assert(imex_ctx::NTIMER == IMEX_NTIMERS, "timer count of the C ABI");
+
+imex_status imex_kernel_times(imex_ctx* c, double out[2 * IMEX_NTIMERS], int reset) {
   if (!c || !out) return fail(c, IMEX_EINVAL, "null argument");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->timers_resolve();

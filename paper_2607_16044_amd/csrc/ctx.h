@@ -154,7 +154,7 @@ struct imex_ctx {
   std::map<int, hipGraphExec_t> gm_graphs;   // GMRES inner blocks by (first column, adjoint mode)
   void drop_graphs();
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
-  static constexpr int NTIMER = 8;
+  static constexpr int NTIMER = 11;
   double tm_ms[NTIMER] = {};
   long long tm_n[NTIMER] = {};
   std::vector<hipEvent_t> ev_free;
@@ -175,7 +175,7 @@ struct imex_ctx {
 // timer tags
 namespace imex {
 enum TimerTag { TM_DG = 0, TM_ASSEMBLE = 1, TM_ELIMINATE = 2, TM_CONDENSE = 3, TM_FACET = 4, TM_GMRES = 5,
-                TM_BACKSUB = 6, TM_PRECOND = 7 };
+                TM_BACKSUB = 6, TM_PRECOND = 7, TM_POINTS = 8, TM_CONTRACT = 9, TM_INVERT = 10 };
 }
 
 // kernel launchers (dg.hip)

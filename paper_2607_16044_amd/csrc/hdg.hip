@@ -268,7 +268,9 @@ template <int K> using MxRec = PointRec<K, true>;
 // DUMP = false: residual rows and every Jacobian block contracted here.
 // DUMP = true (HDG-MX, inviscid HDG-IP): residual rows here, the point-wise
 // Jacobians go to rec for hdg_contract_kernel.
-template <int K, bool MX, bool DUMP, class T>
+// JAC = false: point values and residual rows only (a separate instantiation without the
+// dual-number passes).
+template <int K, bool MX, bool DUMP, class T, bool JAC = true>
 __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ Uhat,
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
   extern __shared__ double smem_raw[];
-  AsmShared<K, MX, DUMP>& sh = *reinterpret_cast<AsmShared<K, MX, DUMP>*>(smem_raw);
+  AsmShared<K, MX, DUMP || !JAC>& sh = *reinterpret_cast<AsmShared<K, MX, DUMP || !JAC>*>(smem_raw);
   using Rec = PointRec<K, MX>;
   double* const rp = DUMP ? rec + (size_t)blockIdx.x * Rec::SIZE : nullptr;
   // point-wise Jacobian entries: LDS, or the record in global memory (DUMP)
@@ -469,8 +471,8 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
   const bool full = MX || g.viscous || !DUMP;
   const int CV = full ? CV0 : 4 / NSD, CF = full ? CF0 : 8 / NSD;
   const int ntask = NQV * CV + 4 * NQ * CF + (MX ? (NQV + 4 * NQ) * CL : 0);
-  for (int task = tid; task < (prm.jacobian ? ntask : NQV + 4 * NQ); task += nt) {
-    if (!prm.jacobian) {
+  for (int task = tid; task < (JAC ? ntask : NQV + 4 * NQ); task += nt) {
+    if constexpr (!JAC) {
       // values only
       if (task < NQV) {
         const int qv = task;
@@ -667,7 +669,7 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
       hres[(size_t)p * NF + rr] = acc;
     }
   }
-  if (!prm.jacobian) return;
+  if constexpr (!JAC) return;
   if constexpr (DUMP) {
     return;                                // the Jacobians are already in the record
   } else {
@@ -911,8 +913,18 @@ __device__ __forceinline__ void lift_coef(int c, T cx[3], T cy[3]) {
   }
 }
 
+// waves per SIMD the contraction's registers are held to (it is latency-bound: 8 measured
+// faster than the unconstrained 4)
+#ifndef CT_WAVES_PER_EU
+#define CT_WAVES_PER_EU 8
+#endif
+#if CT_WAVES_PER_EU > 0
+#define CT_WAVES __attribute__((amdgpu_waves_per_eu(CT_WAVES_PER_EU, CT_WAVES_PER_EU)))
+#else
+#define CT_WAVES
+#endif
 template <int K, class T, bool MX>
-__global__ void __launch_bounds__(256) hdg_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
+__global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
                                                            const double* __restrict__ rec,
                                                            T* __restrict__ blk, T* __restrict__ scr) {
   using S = HS<K, true>;
@@ -2520,14 +2532,27 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
   if (use_mx(c)) {
     // point values, residual rows and point-wise Jacobians; then the block contraction
     const size_t shm = sizeof(AsmShared<KK, true, true>);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
-                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec, w.hres);
+    const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
+    if (jacobian) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
+                         w.hres);
+    } else {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
+                         w.hres);
+    }
+    c->timer_end(tpo);
     if (jacobian) {
       const int nblk = 40 * ((c->n_im + 7) / 8);
+      const int tc = c->timer_begin(TM_CONTRACT);
       hipLaunchKernelGGL((hdg_contract_kernel<KK, LT, true>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
                          c->dhdg(), dt_a, w.rec, blk, scr);
+      c->timer_end(tc);
     }
     c->timer_end(ta);
     if (jacobian) {
@@ -2544,22 +2569,45 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
   } else if (!c->gas.viscous) {
     // inviscid HDG-IP: the same split without mixed blocks (K and C D E)
     const size_t shm = sizeof(AsmShared<KK, false, true>);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
-                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec, w.hres);
+    const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
+    if (jacobian) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
+                         w.hres);
+    } else {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
+                         w.hres);
+    }
+    c->timer_end(tpo);
     if (jacobian) {
       const int nblk = 16 * ((c->n_im + 7) / 8);
+      const int tc = c->timer_begin(TM_CONTRACT);
       hipLaunchKernelGGL((hdg_contract_kernel<KK, LT, false>), dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
                          c->dhdg(), dt_a, w.rec, blk, scr);
+      c->timer_end(tc);
     }
     c->timer_end(ta);
   } else {
-    const size_t shm = sizeof(AsmShared<KK, false>);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT>), dim3(c->n_im), dim3(256), shm, c->stream,
-                       c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr, w.hres);
+    if (jacobian) {
+      const size_t shm = sizeof(AsmShared<KK, false>);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT, true>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr,
+                         w.hres);
+    } else {
+      const size_t shm = sizeof(AsmShared<KK, false, true>);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT, false>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr,
+                         w.hres);
+    }
     c->timer_end(ta);
   }
   return hipGetLastError();
@@ -2581,7 +2629,9 @@ static hipError_t launch_condense(imex_ctx* c) {
     LT* blk = la<LT>(w.blk);
     LT* Kinv = la<LT>(w.Kinv);
     LT* X = la<LT>(w.X);
+    const int ti = c->timer_begin(TM_INVERT);
     hipLaunchKernelGGL((hdg_invert_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv);
+    c->timer_end(ti);
     const long long bs = (long long)blk_stride(c);
     hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
                                     blk + NU, NC, bs, X, NF + 1, (long long)NU * (NF + 1), c->gemm_tile[1]);
