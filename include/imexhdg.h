@@ -93,6 +93,12 @@ typedef struct {
    *      is frozen within a stage, a variant the paper leaves out)
    * A simplified correction that contracts more slowly hands back to full iterations. */
   int newton_simplified;
+  /* Forcing term of the facet solves (inexact Newton): 0 solves every correction to
+   * gmres_rtol; 1 solves correction k to max(gmres_rtol, min(1e-4, dz_{k-1} / 100)), with
+   * dz_{k-1} the relative size of the previous correction of the stage (1e-4 for the
+   * first).  The linear-solve error then stays below the Newton error it is added to, and
+   * convergence is certified by the increment test as before. */
+  int gmres_forcing;
 } imex_options;
 
 /* ARK pair synchronised by padding (Sec. 4.2.2): explicit (s+1)x(s+1) tableau Ae

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("dg_flux", ctypes.c_int), ("hdg_flux", ctypes.c_int), ("hdg_variant", ctypes.c_int),
                 ("alpha_dg", ctypes.c_double), ("alpha_hdg", ctypes.c_double), ("precision", ctypes.c_int),
                 ("newton_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
-                ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int), ("newton_simplified", ctypes.c_int)]
+                ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int), ("newton_simplified", ctypes.c_int),
+                ("gmres_forcing", ctypes.c_int)]
 
 
 class Tableau(ctypes.Structure):
@@ -132,7 +133,7 @@ class Engine:
 
     def __init__(self, wl, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 newton_simplified: int = 1, device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, gmres_forcing: int = 0, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         self.lib = load_library()
@@ -145,7 +146,7 @@ class Engine:
                         wl.degree)
         phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
         opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
-                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified)
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified, gmres_forcing)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         st = self.lib.imex_create(ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opt),
@@ -345,7 +346,7 @@ class BatchEngine(Engine):
 
     def __init__(self, wls, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 newton_simplified: int = 1, device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, gmres_forcing: int = 0, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         if not wls or len({w.degree for w in wls}) != 1:
@@ -365,7 +366,7 @@ class BatchEngine(Engine):
         scale = np.array([w.dt / self.dt for w in self.wls], dtype=np.float64)
         phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(*wl.u_inf))
         opt = Options(wl.dg_flux, wl.hdg_flux, wl.hdg_variant, wl.alpha_dg, wl.alpha_hdg, precision, newton_rtol,
-                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified)
+                      newton_maxit, gmres_rtol, gmres_restart, gmres_maxit, newton_simplified, gmres_forcing)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         st = self.lib.imex_create_batch(len(self.wls), meshes, scale.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

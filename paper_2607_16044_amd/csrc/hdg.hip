@@ -2951,6 +2951,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   double du_prev = 0.0, dh_prev = 0.0;
   int nfull = 0;
   double q_last = 0.0;                      // contraction of the last correction
+  double dz_prev = 1.0;                     // relative size of the last correction
   const int need_full = c->opt.newton_simplified == 2 ? 1 : 2;
   if (c->prec_valid && std::fabs(dt_a / c->prec_dt_a - 1.0) > 0.25) c->prec_valid = false;
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
@@ -2979,9 +2980,14 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     }
     c->timer_end(tt);
     int its = 0;
+    // forcing term: loose facet solves while the Newton corrections are large
+    const double rtol = c->opt.gmres_rtol;
+    if (c->opt.gmres_forcing)
+      c->opt.gmres_rtol = std::max(rtol, std::min(1e-4, it == 1 ? 1e-4 : 1e-2 * dz_prev));
     tt = c->timer_begin(TM_GMRES);
     imex_status s = gmres(c, b, dx, &its);
     c->timer_end(tt);
+    c->opt.gmres_rtol = rtol;
     if (s != IMEX_OK) return s;
     gm_total += its;
     // refactorise once the GMRES iterations spent above the post-refactorisation count
@@ -3014,8 +3020,8 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
       return IMEX_ENONFINITE;
     }
     last = (uu > 0.0) ? du / uu : du;
-    if (st && st->n_hist < (int)(sizeof(st->du_hist) / sizeof(double)))
-      st->du_hist[st->n_hist++] = std::fmax(last, hh > 0.0 ? dh / hh : dh);
+    dz_prev = std::fmax(last, hh > 0.0 ? dh / hh : dh);
+    if (st && st->n_hist < (int)(sizeof(st->du_hist) / sizeof(double))) st->du_hist[st->n_hist++] = dz_prev;
     const double tu = c->opt.newton_rtol * uu, th = c->opt.newton_rtol * hh;
     if (du <= tu && dh <= th) { converged = true; break; }
     if (it >= 2 && du_prev > 0.0 && dh_prev > 0.0) {
