@@ -247,12 +247,22 @@ imex_status imex_set_graphs(imex_ctx* ctx, int on);
 /* Launch-shape autotuner: times the explicit residual kernel for each feasible
  * number of elements per workgroup (at state U, all elements; Uhat needed for
  * HDG-MX coupling, else nullable) and each batched GEMM of the implicit stage for
- * both output tiles (64x64, 32x32), and keeps the fastest for this context.
+ * its output tiles (64x64, 32x32, and in FP32 the full-inner-dimension variants
+ * 1064, 1032 of imex_set_launch_shapes), and keeps the fastest for this context.
  * out (host [4]): elements per residual workgroup (0 = built-in default), then
  * the tiles of the mixed-block elimination, K^-1 [C f] and Schur-update GEMMs
  * (0 = not used).  Call after imex_set_regions and before stepping: it
  * overwrites the implicit-stage workspaces and resets the kernel timers. */
 imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, int out[4]);
+
+/* Set the launch shapes that imex_autotune picks, e.g. a table kept from an earlier
+ * run: in (host [4]) = elements per residual workgroup (0 = default, else one the
+ * residual kernel supports for the degree), then the tiles of the elimination,
+ * K^-1 [C f] and Schur-update GEMMs: 0 (default), 32, 64 (output tile edge), or
+ * 1032, 1064 (the same edges with the whole inner dimension staged in LDS; FP32 and
+ * inner dimension <= 128, else the plain edge).  Results do not depend on the shapes
+ * beyond rounding.  Errors: EINVAL. */
+imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
 
 /* Vector-Jacobian product of the explicit residual (reverse mode of Sec. 3.3):
  * Ubar = (dR^DG/dU)^T Rbar, with R^DG as in imex_dg_residual.  U dev (all

@@ -25,7 +25,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets", "imex_wall_shear", "imex_vjp_wall_shear",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets", "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P, P, P]
     lib.imex_vjp_init_facets.argtypes = [P, P, P]
+    lib.imex_set_launch_shapes.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.imex_wall_shear.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
     lib.imex_vjp_wall_shear.argtypes = [P, P, P, D, P, P]
     lib.imex_autotune.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int)]
@@ -252,6 +253,12 @@ class Engine:
         tab = self.tableau.to_ctypes(Tableau)
         self._check(self.lib.imex_ark_step(self.ctx, ctypes.byref(tab), dt, _ptr(U), _ptr(Uhat), ctypes.byref(st)))
         return st.as_dict()
+
+    def set_launch_shapes(self, picks: dict):
+        """Apply launch shapes as returned by autotune() (e.g. kept from an earlier run)."""
+        arr = (ctypes.c_int * 4)(int(picks.get("dg_tile", 0)), int(picks.get("gemm_tile_eliminate", 0)),
+                                 int(picks.get("gemm_tile_condense", 0)), int(picks.get("gemm_tile_schur", 0)))
+        self._check(self.lib.imex_set_launch_shapes(self.ctx, arr))
 
     def autotune(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None):
         """Pick launch shapes by timing (see imex_autotune); returns the choices."""

@@ -852,6 +852,19 @@ imex_status imex_autotune(imex_ctx* c, const double* U, const double* Uhat, int 
   return IMEX_OK;
 }
 
+imex_status imex_set_launch_shapes(imex_ctx* c, const int in[4]) {
+  if (!c || !in) return fail(c, IMEX_EINVAL, "null argument");
+  if (in[0] != 0 && !dg_tile_valid(c->K, in[0])) return fail(c, IMEX_EINVAL, "elements per residual workgroup");
+  for (int g = 0; g < 3; ++g) {
+    const int t = in[1 + g];
+    if (t != 0 && t != 32 && t != 64 && t != 1032 && t != 1064) return fail(c, IMEX_EINVAL, "GEMM tile");
+  }
+  c->dg_tile = in[0];
+  for (int g = 0; g < 3; ++g) c->gemm_tile[g] = in[1 + g];
+  c->drop_graphs();
+  return IMEX_OK;
+}
+
 imex_status imex_set_graphs(imex_ctx* c, int on) {
   if (!c) return fail(c, IMEX_EINVAL, "null argument");
   if (on && !c->gstream) HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));

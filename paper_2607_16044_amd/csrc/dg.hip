@@ -361,6 +361,7 @@ static bool launch_dg_tile(const imex_ctx* c, DGParams prm, const double* U, con
 }
 
 bool dg_tile_valid(int K, int et) {
+  if (et != 2 && et != 4 && et != 8 && et != 16 && et != 32) return false;   // the instantiated tiles
   switch (K) {
     case 1: return DGTile<1>::lds(et) <= 65536;
     case 2: return DGTile<2>::lds(et) <= 65536;

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -1270,12 +1271,118 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
 
 // C[b] (+)= alpha A[b] B[b] for b < batch (row-major, leading dimensions lda/ldb/ldc,
 // batch strides sA/sB/sC in elements); beta_one selects accumulation into C; tile is
-// the output tile edge (64, or 32 for small matrices; 0 = 64).
+// Full-inner-dimension variant (Kd <= 128, FP32): both panels of an output tile are loaded
+// into LDS in one round of global loads, together with the C tile when accumulating, and
+// the MFMA sweep then runs without further waits on global memory.  The elimination
+// GEMMs (inner dimension 5 (k+1)^2 <= 125) are latency-bound in the k-blocked kernel: one
+// long wait per tile instead of one per k-block.
+template <int TILE>
+__global__ void __launch_bounds__(256) gemm_fk_kernel(int batch, int M, int N, int Kd, double alpha, int beta_one,
+                                                      const float* __restrict__ A, int lda, long long sA,
+                                                      const float* __restrict__ B, int ldb, long long sB,
+                                                      float* __restrict__ C, int ldc, long long sC) {
+  using MF = Mfma16<float>;
+  constexpr int KM = 128, PA = 4, PB = 16;    // pads: two-way LDS bank pattern (the minimum for 64 lanes)
+  constexpr int SUB = TILE / 32;
+  static_assert(TILE == 32 || TILE == 64, "tile");
+  __shared__ float sa[TILE][KM + PA];
+  __shared__ float sb[KM][TILE + PB];
+  const int tn = (N + TILE - 1) / TILE, ntile = ((M + TILE - 1) / TILE) * tn;
+  const int L = blockIdx.x, xcd = L & 7, rr = L >> 3;
+  const int t = rr % ntile;
+  const long long bz = 8LL * (rr / ntile) + xcd;
+  if (bz >= batch) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = (t / tn) * TILE, n0 = (t % tn) * TILE;
+  const float* Ab = A + bz * sA;
+  const float* Bb = B + bz * sB;
+  float* Cb = C + bz * sC;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  // C tile first (its loads overlap the panel loads)
+  float cin[SUB][SUB][4];
+#pragma unroll
+  for (int ti = 0; ti < SUB; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < SUB; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + 16 * SUB * wr + 16 * ti + MF::row(lk, r);
+        const int gn = n0 + 16 * SUB * wc + 16 * tj + li;
+        cin[ti][tj][r] = (beta_one && gm < M && gn < N) ? Cb[(size_t)gm * ldc + gn] : 0.0f;
+      }
+  constexpr int NL = TILE * KM / 256;
+  float ra[NL], rb[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = tid + 256 * u;
+    const int r = idx / KM, kk = idx % KM;
+    const int gm = m0 + r;
+    ra[u] = (gm < M && kk < Kd) ? Ab[(size_t)gm * lda + kk] : 0.0f;
+    const int kb = idx / TILE, cc = idx % TILE;
+    const int gn = n0 + cc;
+    rb[u] = (kb < Kd && gn < N) ? Bb[(size_t)kb * ldb + gn] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = tid + 256 * u;
+    sa[idx / KM][idx % KM] = ra[u];
+    sb[idx / TILE][idx % TILE] = rb[u];
+  }
+  __syncthreads();
+  typename MF::V acc[SUB][SUB];
+#pragma unroll
+  for (int i = 0; i < SUB; ++i)
+#pragma unroll
+    for (int j = 0; j < SUB; ++j) acc[i][j] = typename MF::V{0.0f, 0.0f, 0.0f, 0.0f};
+  const int nk4 = (Kd + 3) / 4;
+  for (int k4 = 0; k4 < nk4; ++k4) {
+    const int kk = 4 * k4 + lk;
+    float av[SUB], bv[SUB];
+#pragma unroll
+    for (int i = 0; i < SUB; ++i) {
+      av[i] = sa[16 * SUB * wr + 16 * i + li][kk];
+      bv[i] = sb[kk][16 * SUB * wc + 16 * i + li];
+    }
+#pragma unroll
+    for (int i = 0; i < SUB; ++i)
+#pragma unroll
+      for (int j = 0; j < SUB; ++j) acc[i][j] = MF::op(av[i], bv[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int ti = 0; ti < SUB; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < SUB; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + 16 * SUB * wr + 16 * ti + MF::row(lk, r);
+        const int gn = n0 + 16 * SUB * wc + 16 * tj + li;
+        if (gm < M && gn < N) Cb[(size_t)gm * ldc + gn] = cin[ti][tj][r] + float(alpha) * acc[ti][tj][r];
+      }
+}
+
+// the output tile edge (64, or 32 for small matrices; 0 = 64); 1000 + edge selects the
+// full-inner-dimension variant (FP32, inner dimension <= 128; otherwise the edge alone).
 template <class T>
 static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
                                const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
                                long long sC, int tile = 64) {
   if (batch == 0 || M == 0 || N == 0) return hipSuccess;
+  if constexpr (std::is_same<T, float>::value) {
+    if (tile > 1000 && K <= 128) {
+      const int tf = tile == 1032 ? 32 : 64;
+      const long long ntf = (long long)((M + tf - 1) / tf) * ((N + tf - 1) / tf);
+      const long long nbf = 8LL * ((batch + 7) / 8) * ntf;
+      if (tf == 32)
+        hipLaunchKernelGGL((gemm_fk_kernel<32>), dim3((unsigned)nbf), dim3(256), 0, st, batch, M, N, K, alpha,
+                           beta_one ? 1 : 0, A, lda, sA, B, ldb, sB, C, ldc, sC);
+      else
+        hipLaunchKernelGGL((gemm_fk_kernel<64>), dim3((unsigned)nbf), dim3(256), 0, st, batch, M, N, K, alpha,
+                           beta_one ? 1 : 0, A, lda, sA, B, ldb, sB, C, ldc, sC);
+      return hipGetLastError();
+    }
+  }
+  if (tile > 1000) tile -= 1000;
   const int tl = tile == 32 ? 32 : 64;
   const long long nt = (long long)((M + tl - 1) / tl) * ((N + tl - 1) / tl);
   const long long nblk = 8LL * ((batch + 7) / 8) * nt;
@@ -2698,7 +2805,8 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32}) {
+      for (int tile : {64, 32, 1064, 1032}) {
+        if (tile > 1000 && sizeof(LT) != 4) continue;
         const float ms = time_ms(c, 3, [&]() {
           if (g == 0)
             gemm_batched<LT>(c->stream, c->n_im, NR, NR, NQM, -1.0, true, scr, NQM, ss, scr + (size_t)NR * NQM,

@@ -133,3 +133,39 @@ def test_autotuned_shapes_give_same_result(case, precision):
         res.append(U.cpu().numpy())
         eng.close()
     assert rel_err(res[1], res[0]) < 1e-12
+
+
+@pytest.mark.parametrize("case,precision", [("boundary_layer_small", 1), ("boundary_layer_small", 0),
+                                            ("vortex_small", 1)])
+def test_every_gemm_variant_gives_same_result(case, precision):
+    """Each GEMM launch shape (64, 32 and, in FP32, the full-inner-dimension 1064 / 1032)
+    set through imex_set_launch_shapes gives the default's states to rounding."""
+    wl = W.get(case)
+
+    def run(shapes):
+        eng = gpu_engine(wl, precision=precision)
+        if shapes is not None:
+            eng.set_launch_shapes(shapes)
+        U = eng.initial_state()
+        H = eng.init_facets(U)
+        for _ in range(2):
+            eng.ark_step(wl.dt, U, H)
+        out = U.cpu().numpy()
+        eng.close()
+        return out
+    ref = run(None)
+    tiles = [64, 32] + ([1064, 1032] if precision == 1 else [])
+    for t in tiles:
+        e = rel_err(run({"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}), ref)
+        print(case, precision, t, e)
+        assert e < 1e-12
+
+
+def test_invalid_launch_shapes_rejected():
+    from paper_2607_16044_amd.binding import IMEXError
+    eng = gpu_engine(W.get("vortex_small"))
+    with pytest.raises(IMEXError):
+        eng.set_launch_shapes({"gemm_tile_eliminate": 48})
+    with pytest.raises(IMEXError):
+        eng.set_launch_shapes({"dg_tile": 7})
+    eng.close()
