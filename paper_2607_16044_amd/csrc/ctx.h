@@ -151,7 +151,8 @@ struct imex_ctx {
   bool capturing = false;
   hipStream_t gstream = nullptr;
   StageGraph sg[5];
-  std::map<int, hipGraphExec_t> gm_graphs;   // GMRES inner blocks by (first column, adjoint mode)
+  std::map<int, hipGraphExec_t> gm_graphs;   // GMRES inner blocks by (first column, length, adjoint mode)
+  int gm_hist[8] = {};                       // iterations of the last GMRES solve of each kind
   void drop_graphs();
   // device-time accounting per phase (hipEvents resolved at synchronisation points)
   static constexpr int NTIMER = 11;

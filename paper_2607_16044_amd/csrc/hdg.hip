@@ -2899,12 +2899,20 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
 
 // Right-preconditioned restarted GMRES(m) on S x = b, x from 0.  The Arnoldi
 // process (classical Gram-Schmidt with one re-orthogonalisation pass, Givens
-// rotations) runs entirely on the device; the host reads the residual history
-// every GM_CHECK iterations and solves the small least-squares problem.
+// rotations) runs entirely on the device in blocks of iterations; after each block the
+// host reads the block's residual estimates and, at the end, solves the small
+// least-squares problem.  Iterations past convergence inside a block are wasted and a
+// host check costs far less than an iteration, so the block lengths are predicted: the
+// first from the iteration count of the previous solve of the same kind (less one), the
+// following ones from the residual's recent contraction rate (at most GM_CHECK).
 constexpr int GM_CHECK = 8;
+constexpr int GM_FIRST = 4;           // first block without a history
+constexpr size_t GM_MAXGRAPHS = 512;  // captured block graphs kept per context
 constexpr int PREC_REFRESH_ITS = 8;
 // a simplified Newton correction follows only a correction that contracted by at least this
 constexpr double SIMPLIFIED_QMAX = 0.05;
+// relative residual of the facet solve of a simplified correction
+constexpr double SIMPLIFIED_GMRES_RTOL = 1e-4;
 
 // Run body() (kernel launches only) on the context's stream, or, with graphs enabled,
 // replay its capture for key (captured on first use; the launches of an inner GMRES
@@ -2939,7 +2947,20 @@ static imex_status replay_block(imex_ctx* c, int key, F&& body) {
   return IMEX_OK;
 }
 
-static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) {
+// Iterations still needed to bring the residual estimate res[n-1] below tol at the
+// geometric rate of the last (up to three) iterations; res[-1] is the cycle's |r_0|.
+static int gm_predict(const std::vector<double>& res, double tol) {
+  const int n = (int)res.size();
+  const int q = std::min(3, n - 1);
+  if (q < 1) return GM_FIRST;
+  const double last = res[n - 1];
+  const double rate = std::pow(last / res[n - 1 - q], 1.0 / q);
+  if (!(rate > 0.0 && rate < 0.999) || !(last > 0.0)) return GM_CHECK;
+  const double need = std::ceil(std::log(tol / last) / std::log(rate));
+  return (int)std::min<double>(GM_CHECK, std::max(1.0, need));
+}
+
+static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, int kind) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
   const int m = std::min(c->opt.gmres_restart, GM_MAXM);
@@ -2957,6 +2978,9 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
   double tol = -1.0;
   int total = 0;
   *its_out = 0;
+  const int hist = c->gm_hist[kind];
+  int want = hist > 1 ? hist - 1 : GM_FIRST;
+  std::vector<double> res;
   while (true) {
     // beta = |r|, V_0 = r / beta
     hipLaunchKernelGGL(gm_norm_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, r, st);
@@ -2967,9 +2991,10 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
     const double beta = hb[0];
     if (tol < 0.0) tol = c->opt.gmres_rtol * beta;
     if (!(beta > tol) || total >= c->opt.gmres_maxit) break;
+    res.assign(1, beta);
     int j = 0, jdone = -1;
     while (j < m && jdone < 0 && total < c->opt.gmres_maxit) {
-      const int j1 = std::min(std::min(m, j + GM_CHECK), j + (c->opt.gmres_maxit - total));
+      const int j1 = std::min(std::min(m, j + want), j + (c->opt.gmres_maxit - total));
       auto block = [&]() -> imex_status {
         for (int jj = j; jj < j1; ++jj) {
           double* vj = V + ldv * jj;
@@ -2987,16 +3012,20 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
         HTRY(hipGetLastError());
         return IMEX_OK;
       };
-      // full-length blocks are replayed from graphs (the block shape is then fixed by j)
-      const imex_status bs = (j1 - j == std::min(GM_CHECK, m - j)) ? replay_block(c, 2 * j + (c->adj_mode ? 1 : 0), block)
-                                                                   : block();
+      // the launches of a block are fixed by its first column, its length and the mode
+      const int key = ((j * (GM_CHECK + 1) + (j1 - j)) << 1) + (c->adj_mode ? 1 : 0);
+      const bool replay = c->gm_graphs.count(key) || c->gm_graphs.size() < GM_MAXGRAPHS;
+      const imex_status bs = replay ? replay_block(c, key, block) : block();
       if (bs != IMEX_OK) return bs;
       HTRY(hipMemcpyAsync(hb, st + GmState::RES + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, c->stream));
       HTRY(hipStreamSynchronize(c->stream));
-      for (int jj = j; jj < j1; ++jj)
+      for (int jj = j; jj < j1; ++jj) {
+        res.push_back(hb[jj - j]);
         if (!(hb[jj - j] > tol)) { jdone = jj; break; }
+      }
       total += (jdone >= 0 ? jdone + 1 : j1) - j;
       j = (jdone >= 0) ? jdone + 1 : j1;
+      want = gm_predict(res, tol);
     }
     const int k = j;
     if (k == 0) break;
@@ -3018,13 +3047,15 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out) 
     hipLaunchKernelGGL(gm_combine_kernel, dim3(nb), dim3(256), 0, c->stream, n, k, V, ldv, yd, r);
     HTRY(launch_precond(c, r, z));
     hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, 1.0, z, x);
+    HTRY(hipGetLastError());
+    if (jdone >= 0 || total >= c->opt.gmres_maxit) break;
     // true residual for the next cycle: r = b - S x
     HTRY(launch_apply(c, x, r));
     hipLaunchKernelGGL(rsub_kernel, dim3(nb), dim3(256), 0, c->stream, n, b, r);
     HTRY(hipGetLastError());
-    if (jdone >= 0 || total >= c->opt.gmres_maxit) break;
   }
   *its_out = total;
+  c->gm_hist[kind] = total;
   return IMEX_OK;
 }
 
@@ -3088,12 +3119,16 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     }
     c->timer_end(tt);
     int its = 0;
-    // forcing term: loose facet solves while the Newton corrections are large
+    // forcing term: loose facet solves while the Newton corrections are large.  A
+    // simplified correction needs only a few digits: it certifies convergence through its
+    // size relative to the previous correction, and its own error (1e-4 of an increment
+    // already near the tolerance) is far below the Newton tolerance.
     const double rtol = c->opt.gmres_rtol;
     if (c->opt.gmres_forcing)
       c->opt.gmres_rtol = std::max(rtol, std::min(1e-4, it == 1 ? 1e-4 : 1e-2 * dz_prev));
+    if (simplified) c->opt.gmres_rtol = std::max(c->opt.gmres_rtol, SIMPLIFIED_GMRES_RTOL);
     tt = c->timer_begin(TM_GMRES);
-    imex_status s = gmres(c, b, dx, &its);
+    imex_status s = gmres(c, b, dx, &its, simplified ? 0 : std::min(it, 4));
     c->timer_end(tt);
     c->opt.gmres_rtol = rtol;
     if (s != IMEX_OK) return s;
@@ -3215,7 +3250,7 @@ imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const d
   const double rtol = c->opt.gmres_rtol;
   c->opt.gmres_rtol = std::min(rtol, 1e-12);
   int its = 0;
-  imex_status st = gmres(c, b, lh, &its);
+  imex_status st = gmres(c, b, lh, &its, 5);
   c->opt.gmres_rtol = rtol;
   c->adj_mode = false;
   if (st != IMEX_OK) return st;
