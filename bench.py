@@ -105,9 +105,10 @@ def gemm_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, kernel):
     """HBM bytes per elimination launch from the committed FETCH_SIZE / WRITE_SIZE summary,
-    or None when it is missing, for another precision, or taken on another kernel source."""
+    or None when it is missing, for another precision or launch shape, or taken on another
+    kernel source."""
     try:
         text = open(COUNTERS_FILE).read()
     except OSError:
@@ -119,6 +120,8 @@ def measured_traffic(precision):
             vals[k.strip()] = v.strip().strip("`")
     try:
         if vals.get("precision") != precision or vals.get("kernel_source_sha256") != gemm_source_digest():
+            return None
+        if kernel not in vals.get("kernel", ""):
             return None
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -156,7 +159,7 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
     eng = binding.Engine(wl, precision=0 if precision == "fp64" else 1, newton_simplified=newton_simplified)
     U = eng.initial_state()
     Uhat = eng.init_facets(U)
-    eng.autotune(U, Uhat)
+    shapes = eng.autotune(U, Uhat)
     eng.set_graphs(True)
     torch.cuda.synchronize()
     for _ in range(warmup):
@@ -176,7 +179,19 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
     n_im = eng.sizes["n_implicit"]
     eng.close()
     return {"elapsed": elapsed, "timers": timers, "newton": newton / steps, "gmres": gmres / steps,
-            "jacobians": jac / steps, "U": U, "Uhat": Uhat, "n_im": n_im}
+            "jacobians": jac / steps, "U": U, "Uhat": Uhat, "n_im": n_im, "shapes": shapes}
+
+
+# the batched GEMM kernel run for a launch-shape code (imex_set_launch_shapes)
+WHOLE_SHAPES = {2001: "4, 4, 3, 3", 2002: "2, 4, 6, 3", 2003: "2, 2, 4, 3", 2004: "4, 2, 2, 3"}
+
+
+def gemm_kernel_name(code, ltype):
+    if ltype == "float" and code in WHOLE_SHAPES:
+        return f"gemm_whole_kernel<{WHOLE_SHAPES[code]}>"
+    if ltype == "float" and code in (1032, 1064):
+        return f"gemm_fk_kernel<{code - 1000}>"
+    return f"gemm_kernel<{ltype}, {32 if code in (32, 1032) else 64}>"
 
 
 def run_ensemble(precision, steps, warmup, n=512):
@@ -249,9 +264,10 @@ def main():
             flops, nbytes = elimination_work(wl, res["n_im"], la)
             gbs = nbytes / (avg_ms * 1e-3) / 1e9
             tfl = flops / (avg_ms * 1e-3) / 1e12
+            kname = gemm_kernel_name(res["shapes"]["gemm_tile_eliminate"], ltype)
             roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "traffic": measured_traffic(main_prec),
-                    "kernel": f"gemm_kernel<{ltype}, tile> (mixed-block elimination)",
+                    "traffic": measured_traffic(main_prec, kname),
+                    "kernel": kname + " (mixed-block elimination)",
                     "avg_ms": avg_ms, "launch_bytes": nbytes, "launch_flops": flops, "mfma_tflops": tfl,
                     "mfma_frac": tfl / PEAK_TFLOPS[main_prec]}
         else:

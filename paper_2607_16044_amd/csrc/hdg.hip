@@ -1269,6 +1269,129 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
       }
 }
 
+// Whole-matrix variant (FP32, M <= BM, N <= BN): one workgroup per batch entry, a WM x WN
+// grid of waves each holding a (16 SM) x (16 SN) block of the output in registers.  Each
+// operand panel is read once per entry (the tiled kernels read it once per output tile),
+// and every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  32-deep
+// k-blocks are staged in LDS with the next block prefetched into registers.
+template <int WM, int WN, int SM, int SN>
+__global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
+                                                                  int beta_one, const float* __restrict__ A, int lda,
+                                                                  long long sA, const float* __restrict__ B, int ldb,
+                                                                  long long sB, float* __restrict__ C, int ldc,
+                                                                  long long sC) {
+  using MF = Mfma16<float>;
+  constexpr int NT = 64 * WM * WN, BM = 16 * SM * WM, BN = 16 * SN * WN, KB = 32;
+  constexpr int PA = 4, PB = 16;              // pads: two-way LDS bank pattern for both operands
+  static_assert((BM * KB) % NT == 0 && (KB * BN) % NT == 0 && BN % 32 == 0, "block shape");
+  __shared__ float sa[BM][KB + PA];
+  __shared__ float sb[KB][BN + PB];
+  const long long bz = blockIdx.x;
+  if (bz >= batch) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv / WN, wc = wv % WN;
+  const int li = lane & 15, lk = lane >> 4;
+  const float* Ab = A + bz * sA;
+  const float* Bb = B + bz * sB;
+  float* Cb = C + bz * sC;
+  constexpr int NLA = BM * KB / NT, NLB = KB * BN / NT;
+  float ra[NLA], rb[NLB];
+  // branch-free loads: 32-bit offsets from the entry's base, lanes outside the matrix
+  // read its first element and take zero
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int idx = tid + NT * u;
+      const int r = idx / KB, gk = k0 + idx % KB;
+      const bool ok = r < M && gk < Kd;
+      const float v = Ab[ok ? r * lda + gk : 0];
+      ra[u] = ok ? v : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int idx = tid + NT * u;
+      const int gk = k0 + idx / BN, cc = idx % BN;
+      const bool ok = gk < Kd && cc < N;
+      const float v = Bb[ok ? gk * ldb + cc : 0];
+      rb[u] = ok ? v : 0.0f;
+    }
+  };
+  typename MF::V acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = typename MF::V{0.0f, 0.0f, 0.0f, 0.0f};
+  fetch(0);
+  for (int k0 = 0; k0 < Kd; k0 += KB) {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int idx = tid + NT * u;
+      sa[idx / KB][idx % KB] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int idx = tid + NT * u;
+      sb[idx / BN][idx % BN] = rb[u];
+    }
+    __syncthreads();
+    if (k0 + KB < Kd) fetch(k0 + KB);
+#pragma unroll
+    for (int k4 = 0; k4 < KB / 4; ++k4) {
+      const int kk = 4 * k4 + lk;
+      float av[SM], bv[SN];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) av[i] = sa[16 * SM * wr + 16 * i + li][kk];
+#pragma unroll
+      for (int j = 0; j < SN; ++j) bv[j] = sb[kk][16 * SN * wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) acc[i][j] = MF::op(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  // C by rows of tiles: all loads of a row before its stores (a store could alias a later
+  // load for all the compiler knows, which would serialise every element)
+#pragma unroll
+  for (int ti = 0; ti < SM; ++ti) {
+    float cv[SN][4];
+#pragma unroll
+    for (int tj = 0; tj < SN; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = 16 * SM * wr + 16 * ti + MF::row(lk, r);
+        const int gn = 16 * SN * wc + 16 * tj + li;
+        const bool ok = gm < M && gn < N;
+        const float v = Cb[ok ? gm * ldc + gn : 0];
+        cv[tj][r] = (beta_one && ok) ? v : 0.0f;
+      }
+#pragma unroll
+    for (int tj = 0; tj < SN; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = 16 * SM * wr + 16 * ti + MF::row(lk, r);
+        const int gn = 16 * SN * wc + 16 * tj + li;
+        if (gm < M && gn < N) Cb[gm * ldc + gn] = cv[tj][r] + float(alpha) * acc[ti][tj][r];
+      }
+  }
+}
+
+// Whole-matrix shapes: code 2001..2004 -> {WM, WN, SM, SN}.  Several waves per SIMD are
+// needed to keep the matrix cores fed (one wave holding a 96 x 96 block runs at half the
+// speed of sixteen waves holding 48 x 48 blocks), so the shapes trade block size for waves.
+struct WholeShape { int wm, wn, sm, sn; };
+__host__ __device__ constexpr WholeShape whole_shape(int code) {
+  return code == 2001 ? WholeShape{4, 4, 3, 3}     // 192 x 192, 1024 threads
+       : code == 2002 ? WholeShape{2, 4, 6, 3}     // 192 x 192, 512 threads
+       : code == 2003 ? WholeShape{2, 2, 4, 3}     // 128 x 96, 256 threads
+       : code == 2004 ? WholeShape{4, 2, 2, 3}     // 128 x 96, 512 threads
+                      : WholeShape{0, 0, 0, 0};
+}
+static bool gemm_whole_fits(int code, int M, int N) {
+  const WholeShape w = whole_shape(code);
+  return w.wm > 0 && M <= 16 * w.sm * w.wm && N <= 16 * w.sn * w.wn;
+}
+
 // C[b] (+)= alpha A[b] B[b] for b < batch (row-major, leading dimensions lda/ldb/ldc,
 // batch strides sA/sB/sC in elements); beta_one selects accumulation into C; tile is
 // Full-inner-dimension variant (Kd <= 128, FP32): both panels of an output tile are loaded
@@ -1362,14 +1485,30 @@ __global__ void __launch_bounds__(256) gemm_fk_kernel(int batch, int M, int N, i
 }
 
 // the output tile edge (64, or 32 for small matrices; 0 = 64); 1000 + edge selects the
-// full-inner-dimension variant (FP32, inner dimension <= 128; otherwise the edge alone).
+// full-inner-dimension variant (FP32, inner dimension <= 128; otherwise the edge alone);
+// 2001..2004 the whole-matrix shapes (FP32, when the matrix fits; otherwise edge 64).
 template <class T>
 static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
                                const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
                                long long sC, int tile = 64) {
   if (batch == 0 || M == 0 || N == 0) return hipSuccess;
   if constexpr (std::is_same<T, float>::value) {
-    if (tile > 1000 && K <= 128) {
+    if (tile > 2000 && gemm_whole_fits(tile, M, N)) {
+#define WHOLE_LAUNCH(CODE)                                                                                     \
+  if (tile == CODE) {                                                                                          \
+    constexpr WholeShape ws = whole_shape(CODE);                                                               \
+    hipLaunchKernelGGL((gemm_whole_kernel<ws.wm, ws.wn, ws.sm, ws.sn>), dim3((unsigned)batch),                 \
+                       dim3(64 * ws.wm * ws.wn), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, \
+                       ldb, sB, C, ldc, sC);                                                                   \
+    return hipGetLastError();                                                                                  \
+  }
+      WHOLE_LAUNCH(2001)
+      WHOLE_LAUNCH(2002)
+      WHOLE_LAUNCH(2003)
+      WHOLE_LAUNCH(2004)
+#undef WHOLE_LAUNCH
+    }
+    if (tile > 1000 && tile < 2000 && K <= 128) {
       const int tf = tile == 1032 ? 32 : 64;
       const long long ntf = (long long)((M + tf - 1) / tf) * ((N + tf - 1) / tf);
       const long long nbf = 8LL * ((batch + 7) / 8) * ntf;
@@ -1382,7 +1521,7 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
       return hipGetLastError();
     }
   }
-  if (tile > 1000) tile -= 1000;
+  if (tile > 1000 && tile < 2000) tile -= 1000;
   const int tl = tile == 32 ? 32 : 64;
   const long long nt = (long long)((M + tl - 1) / tl) * ((N + tl - 1) / tl);
   const long long nblk = 8LL * ((batch + 7) / 8) * nt;
@@ -2805,8 +2944,11 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32, 1064, 1032}) {
+      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004}) {
         if (tile > 1000 && sizeof(LT) != 4) continue;
+        if (tile > 2000 && !(g == 0 ? gemm_whole_fits(tile, NR, NR)
+                                    : gemm_whole_fits(tile, g == 1 ? NU : NF, NF + 1)))
+          continue;
         const float ms = time_ms(c, 3, [&]() {
           if (g == 0)
             gemm_batched<LT>(c->stream, c->n_im, NR, NR, NQM, -1.0, true, scr, NQM, ss, scr + (size_t)NR * NQM,

@@ -138,8 +138,9 @@ def test_autotuned_shapes_give_same_result(case, precision):
 @pytest.mark.parametrize("case,precision", [("boundary_layer_small", 1), ("boundary_layer_small", 0),
                                             ("vortex_small", 1)])
 def test_every_gemm_variant_gives_same_result(case, precision):
-    """Each GEMM launch shape (64, 32 and, in FP32, the full-inner-dimension 1064 / 1032)
-    set through imex_set_launch_shapes gives the default's states to rounding."""
+    """Each GEMM launch shape (64, 32 and, in FP32, the full-inner-dimension 1064 / 1032 and
+    the whole-matrix 2001..2004, which fall back to the 64 tile where the matrix does not
+    fit) set through imex_set_launch_shapes gives the default's states to rounding."""
     wl = W.get(case)
 
     def run(shapes):
@@ -154,7 +155,7 @@ def test_every_gemm_variant_gives_same_result(case, precision):
         eng.close()
         return out
     ref = run(None)
-    tiles = [64, 32] + ([1064, 1032] if precision == 1 else [])
+    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004] if precision == 1 else [])
     for t in tiles:
         e = rel_err(run({"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}), ref)
         print(case, precision, t, e)
@@ -166,6 +167,8 @@ def test_invalid_launch_shapes_rejected():
     eng = gpu_engine(W.get("vortex_small"))
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"gemm_tile_eliminate": 48})
+    with pytest.raises(IMEXError):
+        eng.set_launch_shapes({"gemm_tile_schur": 2005})
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"dg_tile": 7})
     eng.close()
