@@ -91,26 +91,33 @@ def cpu_baseline():
             "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "gemm_elimination_boundary_layer_mixed_counters.md")
+# committed FETCH_SIZE / WRITE_SIZE summaries of the two kernels that can dominate a step, and
+# the source region each was measured on (from the first marker to the end of the function
+# that starts at the second)
+COUNTERS = {
+    "eliminate": (os.path.join(ROOT, "profiles", "gemm_elimination_boundary_layer_mixed_counters.md"),
+                  "template <class T> struct Mfma16;", "static hipError_t gemm_batched("),
+    "contract": (os.path.join(ROOT, "profiles", "contraction_boundary_layer_mixed_counters.md"),
+                 "// waves per SIMD the contraction's registers", "CT_WAVES hdg_contract_kernel("),
+}
 
 
-def gemm_source_digest():
-    """sha256 of the batched MFMA GEMM's source (from its MFMA wrapper to the end of its
-    launcher): the HBM counters in profiles/ hold for this text only."""
+def source_digest(which):
+    """sha256 of a kernel's source region: the HBM counters in profiles/ hold for this text only."""
     import hashlib
+    _, start, fn = COUNTERS[which]
     src = open(os.path.join(ROOT, "paper_2607_16044_amd", "csrc", "hdg.hip")).read()
-    a = src.index("template <class T> struct Mfma16;")
-    b = src.index("static hipError_t gemm_batched(")
-    b = src.index("\n}\n", b) + 3
+    a = src.index(start)
+    b = src.index("\n}\n", src.index(fn)) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(precision, kernel):
-    """HBM bytes per elimination launch from the committed FETCH_SIZE / WRITE_SIZE summary,
-    or None when it is missing, for another precision or launch shape, or taken on another
-    kernel source."""
+def measured_traffic(which, precision, kernel):
+    """HBM bytes per launch of the elimination or the contraction from its committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when it is missing, for another precision or
+    launch shape, or taken on another kernel source."""
     try:
-        text = open(COUNTERS_FILE).read()
+        text = open(COUNTERS[which][0]).read()
     except OSError:
         return None
     vals = {}
@@ -119,7 +126,7 @@ def measured_traffic(precision, kernel):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     try:
-        if vals.get("precision") != precision or vals.get("kernel_source_sha256") != gemm_source_digest():
+        if vals.get("precision") != precision or vals.get("kernel_source_sha256") != source_digest(which):
             return None
         if kernel not in vals.get("kernel", ""):
             return None
@@ -266,16 +273,17 @@ def main():
             tfl = flops / (avg_ms * 1e-3) / 1e12
             kname = gemm_kernel_name(res["shapes"]["gemm_tile_eliminate"], ltype)
             roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "traffic": measured_traffic(main_prec, kname),
+                    "traffic": measured_traffic("eliminate", main_prec, kname),
                     "kernel": kname + " (mixed-block elimination)",
                     "avg_ms": avg_ms, "launch_bytes": nbytes, "launch_flops": flops, "mfma_tflops": tfl,
                     "mfma_frac": tfl / PEAK_TFLOPS[main_prec]}
         else:
             nbytes = contraction_work(wl, res["n_im"], la)
             gbs = nbytes / (avg_ms * 1e-3) / 1e9
+            kname = f"hdg_contract_kernel<{wl.degree}, {ltype}, true>"
             roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "traffic": None, "kernel": f"hdg_contract_kernel<k, {ltype}, MX> (element block contraction)",
-                    "avg_ms": avg_ms, "launch_bytes": nbytes}
+                    "traffic": measured_traffic("contract", main_prec, kname),
+                    "kernel": kname + " (element block contraction)", "avg_ms": avg_ms, "launch_bytes": nbytes}
     out = {
         "metric": "DOF-stage updates/s, FP32+refine/batched vs plain FP64 GPU at <=1e-9 rel err",
         "value": value,
