@@ -2227,7 +2227,8 @@ struct GmState {                  // device layout of the small GMRES arrays (do
   static constexpr int INVB = HC + GM_MAXM + 1;                 // 1 / beta of the newest vector
   static constexpr int PART = INVB + 2;                         // GM_NB x (MAXM+1) partial sums
   static constexpr int NPART = PART + GM_NB * (GM_MAXM + 1);    // GM_NB partial norms
-  static constexpr int SIZE = NPART + GM_NB;
+  static constexpr int PART2 = NPART + GM_NB;                   // GM_NB x (MAXM+1) partial dots, second pass
+  static constexpr int SIZE = PART2 + GM_NB * (GM_MAXM + 1);
 };
 
 // sum over the 64 lanes of a wave (lane 0 holds the result)
@@ -2282,32 +2283,59 @@ __global__ void __launch_bounds__(256) gm_dots_kernel(int n, int k, const double
   }
 }
 
-// h = sum of the partial dots (added into column j of H); w -= V h; with norm != 0 also
-// the partial sums of |w|^2
+// Classical Gram-Schmidt pass on w: h = sum of the block partials of V^T w (added into
+// column j of H), w -= V h.  The first pass (pass 0, partials in PART) also forms the
+// partials of the second pass's dots V^T w over the rows it has just updated (into
+// PART2, so that no block overwrites partials another block is still reading); the
+// second pass (pass 1, partials in PART2) forms the partials of |w|^2.
 __global__ void __launch_bounds__(256) gm_orth_kernel(int n, int k, int j, const double* __restrict__ V, size_t ldv,
-                                                      double* __restrict__ w, double* __restrict__ st, int norm) {
+                                                      double* __restrict__ w, double* __restrict__ st, int pass) {
   __shared__ double hc[GM_MAXM + 1];
+  __shared__ double red[4][8];
   __shared__ double red4[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int src = pass == 0 ? GmState::PART : GmState::PART2;
   for (int c = wv; c < k; c += 4) {
     double a = 0.0;
-    for (int b = lane; b < GM_NB; b += 64) a += st[GmState::PART + (size_t)b * (GM_MAXM + 1) + c];
+    for (int b = lane; b < GM_NB; b += 64) a += st[src + (size_t)b * (GM_MAXM + 1) + c];
     a = gm_wave_sum(a);
     if (lane == 0) hc[c] = a;
   }
   __syncthreads();
   if (blockIdx.x == 0 && tid < k) st[GmState::H + (size_t)j * (GM_MAXM + 1) + tid] += hc[tid];
+  const int stride = gridDim.x * blockDim.x;
   double nrm = 0.0;
-  for (int r = blockIdx.x * blockDim.x + tid; r < n; r += gridDim.x * blockDim.x) {
+  for (int r = blockIdx.x * blockDim.x + tid; r < n; r += stride) {
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += V[(size_t)c * ldv + r] * hc[c];
     const double v = w[r] - acc;
     w[r] = v;
     nrm += v * v;
   }
-  if (!norm) return;
-  const double t = gm_block_sum(nrm, red4);
-  if (tid == 0) st[GmState::NPART + blockIdx.x] = t;
+  if (pass == 1) {
+    const double t = gm_block_sum(nrm, red4);
+    if (tid == 0) st[GmState::NPART + blockIdx.x] = t;
+    return;
+  }
+  // second-pass dots over this thread's rows (each thread rereads only what it wrote)
+  double* part = st + GmState::PART2 + (size_t)blockIdx.x * (GM_MAXM + 1);
+  for (int c0 = 0; c0 < k; c0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = blockIdx.x * blockDim.x + tid; r < n; r += stride) {
+      const double wr = w[r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < k) acc[c] += V[(size_t)(c0 + c) * ldv + r] * wr;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double t = gm_wave_sum(acc[c]);
+      if (lane == 0) red[wv][c] = t;
+    }
+    __syncthreads();
+    if (tid < 8 && c0 + tid < k) part[c0 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
+  }
 }
 
 // |w|^2 partials only (for the initial residual)
@@ -2335,36 +2363,42 @@ __global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
   for (int i = 1 + tid; i < GM_MAXM + 1; i += blockDim.x) st[GmState::G + i] = 0.0;
 }
 
-// Givens update of column j: beta from the norm partials, rotations, g, residual estimate, 1/beta
-__global__ void gm_givens_kernel(int j, double* __restrict__ st, int nblocks) {
-  if (threadIdx.x >= 64) return;
-  const double beta = sqrt(gm_norm_total(st, nblocks));
-  if (threadIdx.x != 0) return;
-  double* Hc = st + GmState::H + (size_t)j * (GM_MAXM + 1);
-  Hc[j + 1] = beta;
-  for (int i = 0; i < j; ++i) {
-    const double c = st[GmState::CS + i], sn = st[GmState::SN + i];
-    const double t = c * Hc[i] + sn * Hc[i + 1];
-    Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
-    Hc[i] = t;
+// Givens update of column j and v /= beta in one launch: every block sums the norm
+// partials itself (beta is needed everywhere); block 0 also updates the rotations.
+__global__ void __launch_bounds__(256) gm_givens_scale_kernel(int n, int j, double* __restrict__ v,
+                                                              double* __restrict__ st, int nblocks) {
+  __shared__ double sb[1];
+  if (threadIdx.x < 64) {
+    const double beta = sqrt(gm_norm_total(st, nblocks));
+    if (threadIdx.x == 0) sb[0] = beta;
   }
-  const double a = Hc[j], b = Hc[j + 1];
-  const double rr = sqrt(a * a + b * b);
-  const double c = rr > 0.0 ? a / rr : 1.0, sn = rr > 0.0 ? b / rr : 0.0;
-  st[GmState::CS + j] = c;
-  st[GmState::SN + j] = sn;
-  Hc[j] = rr;
-  Hc[j + 1] = 0.0;
-  const double gj = st[GmState::G + j];
-  st[GmState::G + j + 1] = -sn * gj;
-  st[GmState::G + j] = c * gj;
-  st[GmState::RES + j] = fabs(sn * gj);
-  st[GmState::INVB] = (beta > 1e-300) ? 1.0 / beta : 0.0;
-}
-
-__global__ void gm_scale_kernel(int n, double* __restrict__ v, const double* __restrict__ st) {
+  __syncthreads();
+  const double beta = sb[0];
+  const double inv = (beta > 1e-300) ? 1.0 / beta : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* Hc = st + GmState::H + (size_t)j * (GM_MAXM + 1);
+    Hc[j + 1] = beta;
+    for (int i = 0; i < j; ++i) {
+      const double c = st[GmState::CS + i], sn = st[GmState::SN + i];
+      const double t = c * Hc[i] + sn * Hc[i + 1];
+      Hc[i + 1] = -sn * Hc[i] + c * Hc[i + 1];
+      Hc[i] = t;
+    }
+    const double a = Hc[j], b = Hc[j + 1];
+    const double rr = sqrt(a * a + b * b);
+    const double c = rr > 0.0 ? a / rr : 1.0, sn = rr > 0.0 ? b / rr : 0.0;
+    st[GmState::CS + j] = c;
+    st[GmState::SN + j] = sn;
+    Hc[j] = rr;
+    Hc[j + 1] = 0.0;
+    const double gj = st[GmState::G + j];
+    st[GmState::G + j + 1] = -sn * gj;
+    st[GmState::G + j] = c * gj;
+    st[GmState::RES + j] = fabs(sn * gj);
+    st[GmState::INVB] = inv;
+  }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] *= st[GmState::INVB];
+  if (i < n) v[i] *= inv;
 }
 
 __global__ void gm_scale_copy_kernel(int n, const double* __restrict__ x, double* __restrict__ v,
@@ -3143,13 +3177,11 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
           double* vn = V + ldv * (jj + 1);
           HTRY(launch_precond(c, vj, z));
           HTRY(launch_apply(c, z, vn));
-          for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
-            hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st,
-                               pass);
-          }
-          hipLaunchKernelGGL(gm_givens_kernel, dim3(1), dim3(64), 0, c->stream, jj, st, GM_NB);
-          hipLaunchKernelGGL(gm_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, vn, st);
+          // CGS2: dots, first pass (with the second pass's dots), second pass (with |w|^2)
+          hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
+          hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st, 0);
+          hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st, 1);
+          hipLaunchKernelGGL(gm_givens_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, jj, vn, st, GM_NB);
         }
         HTRY(hipGetLastError());
         return IMEX_OK;
