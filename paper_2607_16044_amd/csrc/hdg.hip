@@ -2407,6 +2407,20 @@ __global__ void gm_scale_copy_kernel(int n, const double* __restrict__ x, double
   if (i < n) v[i] = x[i] * st[GmState::INVB];
 }
 
+// least squares of the Arnoldi cycle on the device: H[0:k, 0:k] y = g[0:k], H already
+// rotated to upper triangular (one thread: k <= 64)
+__global__ void gm_lsq_kernel(int k, const double* __restrict__ st, double* __restrict__ y) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double* H = st + GmState::H;
+  const double* g = st + GmState::G;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int q = i + 1; q < k; ++q) s -= H[(size_t)q * (GM_MAXM + 1) + i] * y[q];
+    const double d = H[(size_t)i * (GM_MAXM + 1) + i];
+    y[i] = (d != 0.0) ? s / d : 0.0;
+  }
+}
+
 // r = V y (y on the device, length k)
 __global__ void gm_combine_kernel(int n, int k, const double* __restrict__ V, size_t ldv,
                                   const double* __restrict__ y, double* __restrict__ r) {
@@ -3150,24 +3164,20 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
   const int nb = (n + 255) / 256;
   hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, c->stream, n, x);
   HTRY(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  std::vector<double> H((size_t)(GM_MAXM + 1) * GM_MAXM), g(GM_MAXM + 1), yv(GM_MAXM);
   double tol = -1.0;
   int total = 0;
   *its_out = 0;
+  // block lengths never exceed GM_CHECK: the graph keys below rely on it
   const int hist = c->gm_hist[kind];
-  int want = hist > 1 ? hist - 1 : GM_FIRST;
+  int want = hist > 1 ? std::min(hist - 1, GM_CHECK) : GM_FIRST;
   std::vector<double> res;
-  while (true) {
-    // beta = |r|, V_0 = r / beta
+  while (total < c->opt.gmres_maxit) {
+    // beta = |r|, V_0 = r / beta; beta is read back with the first block's residual
+    // estimates (a cycle that starts below the tolerance discards that block)
     hipLaunchKernelGGL(gm_norm_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, r, st);
     hipLaunchKernelGGL(gm_start_kernel, dim3(1), dim3(256), 0, c->stream, st, GM_NB);
     hipLaunchKernelGGL(gm_scale_copy_kernel, dim3(nb), dim3(256), 0, c->stream, n, r, V, st);
-    HTRY(hipMemcpyAsync(hb, st + GmState::INVB + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HTRY(hipStreamSynchronize(c->stream));
-    const double beta = hb[0];
-    if (tol < 0.0) tol = c->opt.gmres_rtol * beta;
-    if (!(beta > tol) || total >= c->opt.gmres_maxit) break;
-    res.assign(1, beta);
+    bool small = false;
     int j = 0, jdone = -1;
     while (j < m && jdone < 0 && total < c->opt.gmres_maxit) {
       const int j1 = std::min(std::min(m, j + want), j + (c->opt.gmres_maxit - total));
@@ -3192,7 +3202,15 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
       const imex_status bs = replay ? replay_block(c, key, block) : block();
       if (bs != IMEX_OK) return bs;
       HTRY(hipMemcpyAsync(hb, st + GmState::RES + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, c->stream));
+      if (j == 0)
+        HTRY(hipMemcpyAsync(hb + GM_CHECK, st + GmState::INVB + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HTRY(hipStreamSynchronize(c->stream));
+      if (j == 0) {
+        const double beta = hb[GM_CHECK];
+        if (tol < 0.0) tol = c->opt.gmres_rtol * beta;
+        if (!(beta > tol)) { small = true; break; }
+        res.assign(1, beta);
+      }
       for (int jj = j; jj < j1; ++jj) {
         res.push_back(hb[jj - j]);
         if (!(hb[jj - j] > tol)) { jdone = jj; break; }
@@ -3201,23 +3219,10 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
       j = (jdone >= 0) ? jdone + 1 : j1;
       want = gm_predict(res, tol);
     }
+    if (small) break;
     const int k = j;
     if (k == 0) break;
-    // least squares: H[0:k, 0:k] y = g[0:k] (H already rotated to upper triangular)
-    HTRY(hipMemcpyAsync(hb, st + GmState::H, sizeof(double) * (GM_MAXM + 1) * GM_MAXM, hipMemcpyDeviceToHost,
-                        c->stream));
-    HTRY(hipMemcpyAsync(hb + (GM_MAXM + 1) * GM_MAXM, st + GmState::G, sizeof(double) * (GM_MAXM + 1),
-                        hipMemcpyDeviceToHost, c->stream));
-    HTRY(hipStreamSynchronize(c->stream));
-    const double* Hh = hb;
-    const double* gh = hb + (GM_MAXM + 1) * GM_MAXM;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = gh[i];
-      for (int q = i + 1; q < k; ++q) s -= Hh[(size_t)q * (GM_MAXM + 1) + i] * yv[q];
-      const double d = Hh[(size_t)i * (GM_MAXM + 1) + i];
-      yv[i] = (d != 0.0) ? s / d : 0.0;
-    }
-    HTRY(hipMemcpyAsync(yd, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(gm_lsq_kernel, dim3(1), dim3(64), 0, c->stream, k, st, yd);
     hipLaunchKernelGGL(gm_combine_kernel, dim3(nb), dim3(256), 0, c->stream, n, k, V, ldv, yd, r);
     HTRY(launch_precond(c, r, z));
     hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, 1.0, z, x);

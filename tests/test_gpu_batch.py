@@ -115,6 +115,32 @@ def test_graph_replay_equals_eager(case):
         assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_long_facet_solves(precision):
+    """Facet solves of many GMRES iterations (a tight tolerance) replayed from graphs give
+    the eager states: the replayed blocks are keyed by their first column and length, and
+    every block length, including the first one taken from the previous solve, stays
+    within the range the keys distinguish."""
+    wl = W.get("boundary_layer_small")
+    runs, its = [], []
+    for graphs in (False, True):
+        eng = gpu_engine(wl, precision=precision, gmres_rtol=1e-13)
+        eng.set_graphs(graphs)
+        U = eng.initial_state()
+        H = eng.init_facets(U)
+        states = []
+        for _ in range(3):
+            st = eng.ark_step(wl.dt, U, H)
+            states.append(U.cpu().numpy().copy())
+            its.append(st["gmres_its"] / max(st["newton_its"], 1))
+        runs.append(states)
+        eng.close()
+    print("GMRES iterations per facet solve", its)
+    assert max(its) > 10         # (the simplified corrections' solves stop at 1e-4 and pull the mean down)
+    for a, b in zip(*runs):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
 @pytest.mark.parametrize("case,precision", [("boundary_layer_small", 0), ("boundary_layer_small", 1),
                                             ("vortex_small", 1)])
 def test_autotuned_shapes_give_same_result(case, precision):
