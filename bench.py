@@ -301,7 +301,8 @@ def main():
                    "implicit_elements": res["n_im"], "tableau": wl.tableau, "stages": s,
                    "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": main_prec,
                    "newton_corrections_per_step": res["newton"], "jacobians_per_step": res["jacobians"],
-                   "gmres_its_per_step": res["gmres"], "newton_simplified": 1},
+                   "gmres_its_per_step": res["gmres"], "newton_simplified": 1,
+                   "gmres_forcing": 2},
         "roofline": roof,
         "phases_ms_per_step": phases,
         "kernels_ms_per_step": kernels,

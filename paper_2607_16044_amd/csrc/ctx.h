@@ -128,6 +128,7 @@ struct imex_ctx {
   bool prec_fresh = false;      // the next GMRES solve is the first after a refactorisation
   int prec_base = 0;            // GMRES iterations of that first solve
   int prec_extra = 0;           // GMRES iterations above prec_base since then
+  double newton_q2 = 0.0;       // contraction of the second Newton correction in the last stage (0: none yet)
   double prec_dt_a = 0.0;       // dt a_ii of the factorised system
   // device copies
   double *d_hx = nullptr, *d_hy = nullptr, *d_dts = nullptr;

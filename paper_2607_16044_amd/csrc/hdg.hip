@@ -3103,6 +3103,11 @@ constexpr int PREC_REFRESH_ITS = 8;
 constexpr double SIMPLIFIED_QMAX = 0.05;
 // relative residual of the facet solve of a simplified correction
 constexpr double SIMPLIFIED_GMRES_RTOL = 1e-4;
+// With gmres_forcing = 2 the first correction's facet solve stops at min(this, q / 100),
+// q the contraction of the second correction against the first in the previous stage: its
+// linear error (relative to the first correction) then stays a hundredth of the second
+// correction, so it does not change the Newton iterates beyond rounding.
+constexpr double FIRST_CORRECTION_RTOL = 1e-5;
 
 // Run body() (kernel launches only) on the context's stream, or, with graphs enabled,
 // replay its capture for key (captured on first use; the launches of an inner GMRES
@@ -3269,6 +3274,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   double du_prev = 0.0, dh_prev = 0.0;
   int nfull = 0;
   double q_last = 0.0;                      // contraction of the last correction
+  double q2 = 0.0;                          // contraction of the second correction
   double dz_prev = 1.0;                     // relative size of the last correction
   const int need_full = c->opt.newton_simplified == 2 ? 1 : 2;
   if (c->prec_valid && std::fabs(dt_a / c->prec_dt_a - 1.0) > 0.25) c->prec_valid = false;
@@ -3303,8 +3309,10 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     // size relative to the previous correction, and its own error (1e-4 of an increment
     // already near the tolerance) is far below the Newton tolerance.
     const double rtol = c->opt.gmres_rtol;
-    if (c->opt.gmres_forcing)
+    if (c->opt.gmres_forcing == 1)
       c->opt.gmres_rtol = std::max(rtol, std::min(1e-4, it == 1 ? 1e-4 : 1e-2 * dz_prev));
+    else if (c->opt.gmres_forcing == 2 && it == 1 && !simplified && c->newton_q2 > 0.0)
+      c->opt.gmres_rtol = std::max(rtol, std::min(FIRST_CORRECTION_RTOL, 1e-2 * c->newton_q2));
     if (simplified) c->opt.gmres_rtol = std::max(c->opt.gmres_rtol, SIMPLIFIED_GMRES_RTOL);
     tt = c->timer_begin(TM_GMRES);
     imex_status s = gmres(c, b, dx, &its, simplified ? 0 : std::min(it, 4));
@@ -3349,6 +3357,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     if (it >= 2 && du_prev > 0.0 && dh_prev > 0.0) {
       const double qu = du / du_prev, qh = dh / dh_prev;
       q_last = std::fmax(qu, qh);
+      if (it == 2) q2 = q_last;
       if (qu < 0.5 && qh < 0.5 && qu / (1.0 - qu) * du <= tu && qh / (1.0 - qh) * dh <= th) {
         converged = true;
         break;
@@ -3360,6 +3369,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     du_prev = du;
     dh_prev = dh;
   }
+  if (q2 > 0.0) c->newton_q2 = q2;
   if (st) {
     st->newton_its = newton;
     st->gmres_its = gm_total;

@@ -124,7 +124,7 @@ def test_graph_replay_long_facet_solves(precision):
     wl = W.get("boundary_layer_small")
     runs, its = [], []
     for graphs in (False, True):
-        eng = gpu_engine(wl, precision=precision, gmres_rtol=1e-13)
+        eng = gpu_engine(wl, precision=precision, gmres_rtol=1e-13, gmres_forcing=0)
         eng.set_graphs(graphs)
         U = eng.initial_state()
         H = eng.init_facets(U)
