@@ -302,7 +302,7 @@ def main():
                    "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": main_prec,
                    "newton_corrections_per_step": res["newton"], "jacobians_per_step": res["jacobians"],
                    "gmres_its_per_step": res["gmres"], "newton_simplified": 1,
-                   "gmres_forcing": 2},
+                   "gmres_forcing": 3},
         "roofline": roof,
         "phases_ms_per_step": phases,
         "kernels_ms_per_step": kernels,

@@ -96,12 +96,14 @@ typedef struct {
   /* Forcing term of the facet solves (inexact Newton): 0 solves every correction to
    * gmres_rtol; 1 solves correction k to max(gmres_rtol, min(1e-4, dz_{k-1} / 100)), with
    * dz_{k-1} the relative size of the previous correction of the stage (1e-4 for the
-   * first); 2 solves only the first correction of each stage loosely, to
+   * first); 2 solves the first full correction of each stage loosely, to
    * max(gmres_rtol, min(1e-5, q / 100)) with q the contraction of the second correction
    * against the first in the previous stage of this context (gmres_rtol until one has
-   * been measured), and the later full corrections to gmres_rtol.  With 2 the first
-   * correction's linear error stays a hundredth of the second correction, so the Newton
-   * iterates, and the corrections assembled, are those of 0.  Convergence is certified by the increment
+   * been measured), and the later full corrections to gmres_rtol; 3 (the recommended
+   * setting) solves the first two full corrections so.  The first correction's linear
+   * error stays a hundredth of the second correction; the second's is removed by the
+   * correction that follows it, or is below newton_rtol when the stage stops there.  The
+   * corrections and Jacobians are those of 0 on the workloads measured.  Convergence is certified by the increment
    * test either way.  (The facet solve of a simplified correction, which only certifies
    * convergence, always stops at 1e-4.) */
   int gmres_forcing;

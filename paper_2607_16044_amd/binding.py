@@ -134,7 +134,7 @@ class Engine:
 
     def __init__(self, wl, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 newton_simplified: int = 1, gmres_forcing: int = 2, device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, gmres_forcing: int = 3, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         self.lib = load_library()
@@ -353,7 +353,7 @@ class BatchEngine(Engine):
 
     def __init__(self, wls, precision: int = 0, newton_rtol: float = 1e-12, newton_maxit: int = 25,
                  gmres_rtol: float = 1e-9, gmres_restart: int = 60, gmres_maxit: int = 600,
-                 newton_simplified: int = 1, gmres_forcing: int = 2, device: Optional[torch.device] = None):
+                 newton_simplified: int = 1, gmres_forcing: int = 3, device: Optional[torch.device] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the engine runs only on the GPU")
         if not wls or len({w.degree for w in wls}) != 1:

@@ -237,7 +237,7 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
     return fail(nullptr, IMEX_EINVAL, "precision");
   if (opt->newton_maxit < 1 || opt->gmres_restart < 1 || opt->gmres_restart > 64 || opt->gmres_maxit < 1 ||
       !(opt->newton_rtol > 0.0) || !(opt->gmres_rtol > 0.0) || opt->newton_simplified < 0 ||
-      opt->newton_simplified > 2 || opt->gmres_forcing < 0 || opt->gmres_forcing > 2)
+      opt->newton_simplified > 2 || opt->gmres_forcing < 0 || opt->gmres_forcing > 3)
     return fail(nullptr, IMEX_EINVAL, "solver options");
 
   imex_ctx* c = new (std::nothrow) imex_ctx();

@@ -3103,10 +3103,11 @@ constexpr int PREC_REFRESH_ITS = 8;
 constexpr double SIMPLIFIED_QMAX = 0.05;
 // relative residual of the facet solve of a simplified correction
 constexpr double SIMPLIFIED_GMRES_RTOL = 1e-4;
-// With gmres_forcing = 2 the first correction's facet solve stops at min(this, q / 100),
-// q the contraction of the second correction against the first in the previous stage: its
-// linear error (relative to the first correction) then stays a hundredth of the second
-// correction, so it does not change the Newton iterates beyond rounding.
+// With gmres_forcing = 2 (3) the facet solve of the first (first two) full correction(s) of
+// a stage stops at min(this, q / 100), q the contraction of the second correction against
+// the first in the previous stage.  The first correction's linear error then stays a
+// hundredth of the second correction; the second's is removed by the correction that
+// follows it, or is below the Newton tolerance when the stage stops there.
 constexpr double FIRST_CORRECTION_RTOL = 1e-5;
 
 // Run body() (kernel launches only) on the context's stream, or, with graphs enabled,
@@ -3311,7 +3312,8 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     const double rtol = c->opt.gmres_rtol;
     if (c->opt.gmres_forcing == 1)
       c->opt.gmres_rtol = std::max(rtol, std::min(1e-4, it == 1 ? 1e-4 : 1e-2 * dz_prev));
-    else if (c->opt.gmres_forcing == 2 && it == 1 && !simplified && c->newton_q2 > 0.0)
+    else if (c->opt.gmres_forcing >= 2 && (it == 1 || (it == 2 && c->opt.gmres_forcing == 3)) && !simplified &&
+             c->newton_q2 > 0.0)
       c->opt.gmres_rtol = std::max(rtol, std::min(FIRST_CORRECTION_RTOL, 1e-2 * c->newton_q2));
     if (simplified) c->opt.gmres_rtol = std::max(c->opt.gmres_rtol, SIMPLIFIED_GMRES_RTOL);
     tt = c->timer_begin(TM_GMRES);

@@ -58,12 +58,12 @@ def test_simplified_corrections_same_root(case, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("case", list(CASES))
 def test_first_correction_forcing_same_root(case, precision):
-    """Solving only the first correction of each stage loosely (gmres_forcing = 2, the
-    default) keeps the Newton corrections and Jacobians of tight solves (gmres_forcing = 0)
-    and their root, with fewer GMRES iterations."""
+    """Solving the first (gmres_forcing = 2) or the first two (3, the default) full
+    corrections of each stage loosely keeps the Newton corrections and Jacobians of tight
+    solves (gmres_forcing = 0) and their root, with fewer GMRES iterations."""
     wl = CASES[case]()
     res = {}
-    for forcing in (0, 2):
+    for forcing in (0, 2, 3):
         eng = gpu_engine(wl, precision=precision, gmres_forcing=forcing)
         U = eng.initial_state()
         H = eng.init_facets(U)
@@ -75,12 +75,14 @@ def test_first_correction_forcing_same_root(case, precision):
             gm += st["gmres_its"]
         res[forcing] = (U.cpu().numpy(), jac, its, gm)
         eng.close()
-    (u0, j0, i0, g0), (u2, j2, i2, g2) = res[0], res[2]
-    e = rel_err(u2, u0)
-    print(case, precision, "jacobians", j0, j2, "corrections", i0, i2, "gmres", g0, g2, "diff", e)
-    assert e < 1e-11
-    assert j2 <= j0 and i2 <= i0
-    assert g2 <= g0
+    u0, j0, i0, g0 = res[0]
+    for forcing in (2, 3):
+        u2, j2, i2, g2 = res[forcing]
+        e = rel_err(u2, u0)
+        print(case, precision, forcing, "jacobians", j0, j2, "corrections", i0, i2, "gmres", g0, g2, "diff", e)
+        assert e < 1e-11
+        assert j2 <= j0 and i2 <= i0
+        assert g2 <= g0
 
 
 def test_simplified_corrections_fewer_jacobians_boundary_layer():
