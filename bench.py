@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--ensemble-only", action="store_true",
                     help="time only the batched ensemble (for profiling it on its own); prints its own JSON line")
+    ap.add_argument("--mx-ip-study", action="store_true",
+                    help="time HDG-MX against HDG-IP assembly and linear solve per Newton iteration for k = 1..4 on "
+                         "a 128x128 all-implicit boundary-layer mesh (FP64); prints its own JSON line")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (calibrates HBM traffic counters)")
     return ap.parse_args()
@@ -201,6 +204,47 @@ def gemm_kernel_name(code, ltype):
     return f"gemm_kernel<{ltype}, {32 if code in (32, 1032) else 64}>"
 
 
+def mx_ip_study(steps=3, warmup=1, n=128):
+    """Cost of the HDG-MX implicit region against HDG-IP (Sec. 5, timings over the degree):
+    device time per Newton iteration of the assembly (point Jacobians, contraction and, for
+    MX, the mixed-block elimination) and of the linear solve (K^-1, condensation, facet
+    solve, back-substitution), on an n x n mesh with every element implicit, FP64, a full
+    Jacobian at every Newton iteration."""
+    import torch
+    from paper_2607_16044_amd import binding, workloads
+    rows = []
+    for k in (1, 2, 3, 4):
+        row = {"degree": k}
+        for name, variant in (("ip", workloads.HDG_IP), ("mx", workloads.HDG_MX)):
+            wl = workloads.boundary_layer(nx=n, ny=n, k=k, implicit_rows=n, hdg_variant=variant,
+                                          name=f"boundary_layer_{n}x{n}_implicit")
+            eng = binding.Engine(wl, precision=0, newton_simplified=0, gmres_forcing=0)
+            U = eng.initial_state()
+            H = eng.init_facets(U)
+            eng.autotune(U, H)
+            for _ in range(warmup):
+                eng.ark_step(wl.dt, U, H)
+            eng.reset_timers()
+            its = jac = 0
+            for _ in range(steps):
+                st = eng.ark_step(wl.dt, U, H)
+                its += st["newton_its"]
+                jac += st["n_jacobians"]
+            torch.cuda.synchronize()
+            t = eng.timers()
+            eng.close()
+            asm = (t["assemble_ms"] + t["eliminate_ms"]) / jac
+            sol = (t["condense_ms"] + t["facet_setup_ms"] + t["gmres_ms"] + t["backsub_ms"]) / its
+            row[name] = {"assembly_ms_per_iteration": round(asm, 4), "solve_ms_per_iteration": round(sol, 4),
+                         "newton_its_per_step": its / steps}
+        row["assembly_mx_over_ip"] = row["mx"]["assembly_ms_per_iteration"] / row["ip"]["assembly_ms_per_iteration"]
+        row["solve_mx_over_ip"] = row["mx"]["solve_ms_per_iteration"] / row["ip"]["solve_ms_per_iteration"]
+        print(f"mx-ip study: degree {k} done", file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"study": "HDG-MX over HDG-IP, device time per Newton iteration", "mesh": f"{n}x{n}, all implicit",
+            "precision": "fp64", "steps": steps, "rows": rows}
+
+
 def run_ensemble(precision, steps, warmup, n=512):
     """The batched vortex ensemble (n instances, 8x8..48x48, p in 1..4), one context per
     degree, autotuned launch shapes and graph replay of the explicit stages."""
@@ -241,6 +285,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.mx_ip_study:
+        print(json.dumps(mx_ip_study()))
+        return
     if args.ensemble_only:
         precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
         out = {"ensemble_only": True, "steps": args.ensemble_steps}
