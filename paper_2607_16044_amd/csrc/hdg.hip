@@ -266,9 +266,10 @@ template <int K, bool MX> struct PointRec {
 };
 template <int K> using MxRec = PointRec<K, true>;
 
-// DUMP = false: residual rows and every Jacobian block contracted here.
-// DUMP = true (HDG-MX, inviscid HDG-IP): residual rows here, the point-wise
-// Jacobians go to rec for hdg_contract_kernel.
+// Residual rows here; the point-wise Jacobians go to rec, which hdg_contract_kernel
+// (HDG-MX, inviscid HDG-IP) or hdg_contract_ipv_kernel (viscous HDG-IP) contracts into
+// the element blocks.  (DUMP = true is the only mode: it selects the record as the
+// destination of the point Jacobians.)
 // JAC = false: point values and residual rows only (a separate instantiation without the
 // dual-number passes).
 template <int K, bool MX, bool DUMP, class T, bool JAC = true>
@@ -280,6 +281,7 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
                                                            double* __restrict__ Rh, double* __restrict__ rec,
                                                            double* __restrict__ hres) {
   using S = HS<K, MX>;
+  static_assert(DUMP, "the point Jacobians go to the record");
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
   extern __shared__ double smem_raw[];
@@ -671,195 +673,7 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
     }
   }
   if constexpr (!JAC) return;
-  if constexpr (DUMP) {
-    return;                                // the Jacobians are already in the record
-  } else {
-  // ---- Jacobian blocks ---------------------------------------------------------
-  constexpr int TO = MX ? 4 : 12;         // offset of t rows among face outputs
-  constexpr int UHI = 4;                  // offset of Uhat among face inputs
-  constexpr int XF = 8;                   // offset of (Q | grad U) among face inputs
-  // K = M + dt_a dR/dU
-  for (int idx = tid; idx < NU * NU; idx += nt) {
-    const int row = idx / NU, col = idx % NU;
-    const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
-    const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-    double acc = 0.0;
-    for (int qj = 0; qj < NQ; ++qj)
-      for (int qi = 0; qi < NQ; ++qi) {
-        const int qv = qi + NQ * qj;
-        const double w = tb.W[qi] * tb.W[qj] * jac;
-        const double tx = tb.D[qi][a] * tb.L[qj][b] * sx, ty = tb.L[qi][a] * tb.D[qj][b] * sy;
-        const double ph2 = tb.L[qi][a2] * tb.L[qj][b2];
-        const double* jx = sh.JV[qv][2 * v];
-        const double* jy = sh.JV[qv][2 * v + 1];
-        double dx = jx[v2] * ph2, dy = jy[v2] * ph2;
-        if (!MX) {
-          const double px2 = tb.D[qi][a2] * tb.L[qj][b2] * sx, py2 = tb.L[qi][a2] * tb.D[qj][b2] * sy;
-          dx += jx[4 + 2 * v2] * px2 + jx[5 + 2 * v2] * py2;
-          dy += jy[4 + 2 * v2] * px2 + jy[5 + 2 * v2] * py2;
-        }
-        acc += w * (tx * dx + ty * dy);
-      }
-    for (int f = 0; f < 4; ++f) {
-      const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-      for (int q = 0; q < NQ; ++q) {
-        double ph, pxi, peta, ph2, pxi2, peta2;
-        face_basis<K>(tb, f, q, a, b, ph, pxi, peta);
-        face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
-        const double w = tb.W[q] * wl;
-        const double* js = sh.JF[f][q][v];
-        double d = js[v2] * ph2;
-        if (!MX) {
-          d += js[XF + 2 * v2] * pxi2 * sx + js[XF + 1 + 2 * v2] * peta2 * sy;
-          const double* jgx = sh.JF[f][q][4 + 2 * v];
-          const double* jgy = sh.JF[f][q][5 + 2 * v];
-          const double dgx = jgx[v2] * ph2 + jgx[XF + 2 * v2] * pxi2 * sx + jgx[XF + 1 + 2 * v2] * peta2 * sy;
-          const double dgy = jgy[v2] * ph2 + jgy[XF + 2 * v2] * pxi2 * sx + jgy[XF + 1 + 2 * v2] * peta2 * sy;
-          acc += w * (pxi * sx * dgx + peta * sy * dgy);
-        }
-        acc += w * ph * d;
-      }
-    }
-    bp[(size_t)row * NC + col] = static_cast<T>(dta * acc + ((row == col) ? tb.NW[a] * tb.NW[b] * jac : 0.0));
-  }
-  // C = dt_a dR/dUhat (each column lives on one face)
-  for (int idx = tid; idx < NU * NF; idx += nt) {
-    const int row = idx / NF, col = idx % NF;
-    const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
-    const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
-    const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-    double acc = 0.0;
-    for (int q = 0; q < NQ; ++q) {
-      double ph, pxi, peta;
-      face_basis<K>(tb, f, q, a, b, ph, pxi, peta);
-      const double w = tb.W[q] * wl * tb.L[q][m2];
-      acc += w * ph * sh.JF[f][q][v][UHI + v2];
-      if (!MX) acc += w * (pxi * sx * sh.JF[f][q][4 + 2 * v][UHI + v2] + peta * sy * sh.JF[f][q][5 + 2 * v][UHI + v2]);
-    }
-    bp[(size_t)row * NC + NU + col] = static_cast<T>(dta * acc);
-  }
-  // D = dh/dU, E = dh/dUhat (E block-diagonal over faces before the mixed elimination)
-  for (int idx = tid; idx < NF * NU; idx += nt) {
-    const int row = idx / NU, col = idx % NU;
-    const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
-    const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-    const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-    double acc = 0.0;
-    for (int q = 0; q < NQ; ++q) {
-      double ph2, pxi2, peta2;
-      face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
-      const double* jt = sh.JF[f][q][TO + v];
-      double d = jt[v2] * ph2;
-      if (!MX) d += jt[XF + 2 * v2] * pxi2 * sx + jt[XF + 1 + 2 * v2] * peta2 * sy;
-      acc += tb.W[q] * wl * tb.L[q][mm] * d;
-    }
-    bp[(size_t)(NU + row) * NC + col] = static_cast<T>(acc);
-  }
-  for (int idx = tid; idx < NF * NF; idx += nt) {
-    const int row = idx / NF, col = idx % NF;
-    const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
-    const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
-    double acc = 0.0;
-    if (f == f2) {
-      const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-      for (int q = 0; q < NQ; ++q)
-        acc += tb.W[q] * wl * tb.L[q][mm] * tb.L[q][m2] * sh.JF[f][q][TO + v][UHI + v2];
-    }
-    bp[(size_t)(NU + row) * NC + NU + col] = static_cast<T>(acc);
-  }
-  if (MX) {
-    // mixed blocks: A12 = dt_a dR/dQ, A32 = dh/dQ (rows of L), A21 = dg/dU, A23 = dg/dUhat (rows of R,
-    // scaled by the inverse of the diagonal mixed mass matrix; g = M_Q Q + l)
-    T* Lm = scr + (size_t)p * S::SCR;          // NR x NQM
-    T* Rm = Lm + (size_t)(NU + NF) * NQM;      // NQM x NR
-    for (int idx = tid; idx < NU * NQM; idx += nt) {
-      const int row = idx / NQM, col = idx % NQM;
-      const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
-      const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-      double acc = 0.0;
-      for (int qj = 0; qj < NQ; ++qj)
-        for (int qi = 0; qi < NQ; ++qi) {
-          const int qv = qi + NQ * qj;
-          const double w = tb.W[qi] * tb.W[qj] * jac;
-          const double tx = tb.D[qi][a] * tb.L[qj][b] * sx, ty = tb.L[qi][a] * tb.D[qj][b] * sy;
-          const double ph2 = tb.L[qi][a2] * tb.L[qj][b2];
-          acc += w * ph2 * (tx * sh.JV[qv][2 * v][4 + c] + ty * sh.JV[qv][2 * v + 1][4 + c]);
-        }
-      for (int f = 0; f < 4; ++f) {
-        const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-        for (int q = 0; q < NQ; ++q) {
-          double ph, pxi, peta, ph2, pxi2, peta2;
-          face_basis<K>(tb, f, q, a, b, ph, pxi, peta);
-          face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
-          acc += tb.W[q] * wl * ph * ph2 * sh.JF[f][q][v][XF + c];
-        }
-      }
-      Lm[(size_t)row * NQM + col] = static_cast<T>(dta * acc);
-    }
-    for (int idx = tid; idx < NF * NQM; idx += nt) {
-      const int row = idx / NQM, col = idx % NQM;
-      const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
-      const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-      const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-      double acc = 0.0;
-      for (int q = 0; q < NQ; ++q) {
-        double ph2, pxi2, peta2;
-        face_basis<K>(tb, f, q, a2, b2, ph2, pxi2, peta2);
-        acc += tb.W[q] * wl * tb.L[q][mm] * ph2 * sh.JF[f][q][TO + v][XF + c];
-      }
-      Lm[(size_t)(NU + row) * NQM + col] = static_cast<T>(acc);
-    }
-    // lifting coefficients: l_c[n] = sum_q w sum_p cvol(c,p,d) P_p dphi_n/dx_d - sum_f,q w phi_n sum_p cfac(c,p,n) P_p
-    for (int idx = tid; idx < NQM * (NU + NF); idx += nt) {
-      const int row = idx / (NU + NF), col = idx % (NU + NF);
-      const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
-      const double minv = 1.0 / ((c == 1 ? 2.0 : 1.0) * tb.NW[a] * tb.NW[b] * jac);
-      double acc = 0.0;
-      if (col < NU) {
-        const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-        for (int qj = 0; qj < NQ; ++qj)
-          for (int qi = 0; qi < NQ; ++qi) {
-            const int qv = qi + NQ * qj;
-            const double w = tb.W[qi] * tb.W[qj] * jac * tb.L[qi][a2] * tb.L[qj][b2];
-            const double px = tb.D[qi][a] * tb.L[qj][b] * sx, py = tb.L[qi][a] * tb.D[qj][b] * sy;
-            const double du = sh.JL[qv][0][v2], dv = sh.JL[qv][1][v2], dth = sh.JL[qv][2][v2];
-            double d;
-            switch (c) {
-              case 0: d = (2.0 / 3.0) * du * px - (1.0 / 3.0) * dv * py; break;
-              case 1: d = du * py + dv * px; break;
-              case 2: d = -(1.0 / 3.0) * du * px + (2.0 / 3.0) * dv * py; break;
-              case 3: d = dth * px; break;
-              default: d = dth * py; break;
-            }
-            acc += w * d;
-          }
-        Rm[(size_t)row * (NU + NF) + col] = static_cast<T>(minv * acc);
-      } else {
-        const int cc = col - NU;
-        const int f = cc / NFF, v2 = (cc % NFF) / NP, m2 = cc % NP;
-        double nx, ny;
-        fnormal(f, nx, ny);
-        const double wl = (f < 2) ? 0.5 * hy : 0.5 * hx;
-        for (int q = 0; q < NQ; ++q) {
-          double ph, pxi, peta;
-          face_basis<K>(tb, f, q, a, b, ph, pxi, peta);
-          const double w = tb.W[q] * wl * ph * tb.L[q][m2];
-          const double du = sh.JLF[f][q][0][v2], dv = sh.JLF[f][q][1][v2], dth = sh.JLF[f][q][2][v2];
-          double d;
-          switch (c) {
-            case 0: d = (2.0 / 3.0) * du * nx - (1.0 / 3.0) * dv * ny; break;
-            case 1: d = du * ny + dv * nx; break;
-            case 2: d = -(1.0 / 3.0) * du * nx + (2.0 / 3.0) * dv * ny; break;
-            case 3: d = dth * nx; break;
-            default: d = dth * ny; break;
-          }
-          acc -= w * d;
-        }
-        Rm[(size_t)row * (NU + NF) + NU + cc] = static_cast<T>(minv * acc);
-      }
-    }
-  }
-  }  // DUMP
+  // the point-wise Jacobians are in the record; the block contraction kernels read them
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,6 +970,217 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
       const T edge = (f < 2) ? wlx * sh.LE[s][a] : wly * sh.LE[s][b];
       const T minv = T(1) / (((c == 1) ? T(2) : T(1)) * sh.NW[a] * sh.NW[b] * jac);
       Rm[(size_t)row * NR + NU + col] = -minv * edge * acc;
+    }
+  }
+}
+
+// Viscous HDG-IP: the same contraction of the point records into K, C, D, E, with the
+// gradient columns and rows the viscous flux brings (Sec. 3.4): volume terms pair a test
+// derivative with a trial value or derivative, face terms pair test value/derivatives
+// with trial value/derivatives.  Every term is a product of 1D factors, so each is a sum
+// over one quadrature direction of the tabulated products W L L, W D L, W L D, W D D.
+// Three workgroups per element: K rows of v in {0, 1}, K rows of v in {2, 3}, and C D E.
+template <int K, class T> struct CtIpShared {
+  static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NQV = NQ * NQ;
+  T TLL[NQ][NP][NP], TDL[NQ][NP][NP], TLD[NQ][NP][NP], TDD[NQ][NP][NP];
+  T LE[2][NP], DE[2][NP], NW[NP];
+  union {
+    struct {
+      T J[8][6][NQV];               // per (v, v2) pair: d(F_x, F_y)_v / d(U, U_x, U_y)_v2 at volume points
+      T JS[8][4][NQ][9];            // per pair and face point: rows (s, g_x, g_y) x columns (U, U_x, U_y)
+    } v;
+    struct {
+      T JF[4][NQ][16][16];          // face records: rows s, g, t; columns U, Uhat, grad U
+    } f;
+  } u;
+};
+
+template <int K, class T>
+__global__ void __launch_bounds__(256) hdg_contract_ipv_kernel(DeviceMesh m, DeviceHDG h, double dt_a,
+                                                               const double* __restrict__ rec, T* __restrict__ blk) {
+  using S = HS<K, false>;
+  using R = PointRec<K, false>;
+  constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
+  constexpr int NC = S::NC;
+  static_assert(R::NOF == 16 && R::NIF == 16 && R::NIV == 12 && R::TO == 12, "viscous HDG-IP record layout");
+  __shared__ CtIpShared<K, T> sh;
+  const int grp = blockIdx.x % 3, p = blockIdx.x / 3;
+  if (p >= h.n_im) return;
+  const int e = h.im_list[p];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const BasisTable& tb = *m.tab;
+  const double hx = m.hx[e], hy = m.hy[e];
+  const T sx = T(2.0 / hx), sy = T(2.0 / hy), jac = T(0.25 * hx * hy);
+  const T wlx = T(0.5 * hy), wly = T(0.5 * hx);
+  const T dta = T(dt_a * elem_dt(m, e));
+  for (int i = tid; i < NQ * NN; i += nt) {
+    const int q = i / NN, x = (i / NP) % NP, y = i % NP;
+    sh.TLL[q][x][y] = T(tb.W[q] * tb.L[q][x] * tb.L[q][y]);
+    sh.TDL[q][x][y] = T(tb.W[q] * tb.D[q][x] * tb.L[q][y]);
+    sh.TLD[q][x][y] = T(tb.W[q] * tb.L[q][x] * tb.D[q][y]);
+    sh.TDD[q][x][y] = T(tb.W[q] * tb.D[q][x] * tb.D[q][y]);
+  }
+  if (tid < 2 * NP) {
+    sh.LE[tid / NP][tid % NP] = T(tb.LE[tid / NP][tid % NP]);
+    sh.DE[tid / NP][tid % NP] = T(tb.DE[tid / NP][tid % NP]);
+  }
+  if (tid < NP) sh.NW[tid] = T(tb.NW[tid]);
+  const double* rp = rec + (size_t)p * R::SIZE;
+  T* bp = blk + (size_t)p * S::BLK;
+  if (grp < 2) {
+    // pairs pr = 4 vl + v2 with the row variable v = 2 grp + vl
+    for (int i = tid; i < 8 * NQV; i += nt) {
+      const int pr = i / NQV, qv = i % NQV, v = 2 * grp + pr / 4, v2 = pr % 4;
+      const double* jx = rp + R::JV + ((size_t)qv * 8 + 2 * v) * R::NIV;
+      const double* jy = jx + R::NIV;
+      sh.u.v.J[pr][0][qv] = T(jx[v2]);
+      sh.u.v.J[pr][1][qv] = T(jx[4 + 2 * v2]);
+      sh.u.v.J[pr][2][qv] = T(jx[5 + 2 * v2]);
+      sh.u.v.J[pr][3][qv] = T(jy[v2]);
+      sh.u.v.J[pr][4][qv] = T(jy[4 + 2 * v2]);
+      sh.u.v.J[pr][5][qv] = T(jy[5 + 2 * v2]);
+    }
+    for (int i = tid; i < 8 * 4 * NQ * 9; i += nt) {
+      const int pr = i / (4 * NQ * 9), f = (i / (NQ * 9)) % 4, q = (i / 9) % NQ, k = i % 9;
+      const int v = 2 * grp + pr / 4, v2 = pr % 4;
+      const int ri = k / 3, ci = k % 3;
+      const int row = ri == 0 ? v : (ri == 1 ? 4 + 2 * v : 5 + 2 * v);
+      const int col = ci == 0 ? v2 : (ci == 1 ? 8 + 2 * v2 : 9 + 2 * v2);
+      sh.u.v.JS[pr][f][q][k] = T(rp[R::JF + (((size_t)f * NQ + q) * R::NOF + row) * R::NIF + col]);
+    }
+    __syncthreads();
+    for (int t = tid; t < 8 * NN; t += nt) {
+      const int pr = t / NN, a = (t / NP) % NP, a2 = t % NP;
+      const int v = 2 * grp + pr / 4, v2 = pr % 4;
+      T acc[NP][NP];
+#pragma unroll
+      for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] = T(0);
+      // volume: (test d/dx, d/dy) x (trial value, d/dx, d/dy)
+      const T(*J)[NQV] = sh.u.v.J[pr];
+#pragma unroll 1
+      for (int qj = 0; qj < NQ; ++qj) {
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+          const int qv = qi + NQ * qj;
+          s0 += sh.TDL[qi][a][a2] * J[0][qv];
+          s1 += sh.TDD[qi][a][a2] * J[1][qv];
+          s2 += sh.TDL[qi][a][a2] * J[2][qv];
+          s3 += sh.TLL[qi][a][a2] * J[3][qv];
+          s4 += sh.TLD[qi][a][a2] * J[4][qv];
+          s5 += sh.TLL[qi][a][a2] * J[5][qv];
+        }
+        const T cLL = jac * sx * (s0 + sx * s1), cLD = jac * sx * sy * s2;
+        const T cDL = jac * sy * (s3 + sx * s4), cDD = jac * sy * sy * s5;
+#pragma unroll
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2)
+            acc[b][b2] += sh.TLL[qj][b][b2] * cLL + sh.TLD[qj][b][b2] * cLD + sh.TDL[qj][b][b2] * cDL +
+                          sh.TDD[qj][b][b2] * cDD;
+      }
+      // x-faces (f = s): test and trial factors along x are edge values LE / derivatives DE
+#pragma unroll 1
+      for (int s = 0; s < 2; ++s) {
+        const T La = sh.LE[s][a], Da = sh.DE[s][a], La2 = sh.LE[s][a2], Da2 = sh.DE[s][a2];
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+          const T* j = sh.u.v.JS[pr][s][q];
+          const T cLL = wlx * (La * La2 * j[0] + sx * (La * Da2 * j[1] + Da * La2 * j[3]) + sx * sx * Da * Da2 * j[4]);
+          const T cLD = wlx * sy * (La * La2 * j[2] + sx * Da * La2 * j[5]);
+          const T cDL = wlx * sy * (La * La2 * j[6] + sx * La * Da2 * j[7]);
+          const T cDD = wlx * sy * sy * La * La2 * j[8];
+#pragma unroll
+          for (int b = 0; b < NP; ++b)
+#pragma unroll
+            for (int b2 = 0; b2 < NP; ++b2)
+              acc[b][b2] += sh.TLL[q][b][b2] * cLL + sh.TLD[q][b][b2] * cLD + sh.TDL[q][b][b2] * cDL +
+                            sh.TDD[q][b][b2] * cDD;
+        }
+      }
+      // y-faces (f = 2 + s): the quadrature runs along x (a, a2), the edge factors along y
+#pragma unroll 1
+      for (int s = 0; s < 2; ++s) {
+        const T(*js)[9] = sh.u.v.JS[pr][2 + s];
+        T S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const T ll = sh.TLL[q][a][a2], ld = sh.TLD[q][a][a2], dl = sh.TDL[q][a][a2], dd = sh.TDD[q][a][a2];
+          S0 += ll * js[q][0];
+          S1 += ld * js[q][1];
+          S2 += ll * js[q][2];
+          S3 += dl * js[q][3];
+          S4 += dd * js[q][4];
+          S5 += dl * js[q][5];
+          S6 += ll * js[q][6];
+          S7 += ld * js[q][7];
+          S8 += ll * js[q][8];
+        }
+        const T cEE = wly * (S0 + sx * (S1 + S3) + sx * sx * S4);
+        const T cED = wly * sy * (S2 + sx * S5);
+        const T cDE = wly * sy * (S6 + sx * S7);
+        const T cDD = wly * sy * sy * S8;
+#pragma unroll
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2)
+            acc[b][b2] += sh.LE[s][b] * (sh.LE[s][b2] * cEE + sh.DE[s][b2] * cED) +
+                          sh.DE[s][b] * (sh.LE[s][b2] * cDE + sh.DE[s][b2] * cDD);
+      }
+#pragma unroll
+      for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int b2 = 0; b2 < NP; ++b2) {
+          const int row = v * NN + a + NP * b, col = v2 * NN + a2 + NP * b2;
+          const T mass = (row == col) ? sh.NW[a] * sh.NW[b] * jac : T(0);
+          bp[(size_t)row * NC + col] = dta * acc[b][b2] + mass;
+        }
+    }
+    return;
+  }
+  // C = dt_a dR/dUhat, D = dh/dU, E = dh/dUhat from the face records
+  for (int i = tid; i < 4 * NQ * 16 * 16; i += nt) (&sh.u.f.JF[0][0][0][0])[i] = T(rp[R::JF + i]);
+  __syncthreads();
+  auto fs = [&](const T(*tab)[NP][NP], int f, int x, int y, int r, int c) {
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc += tab[q][x][y] * sh.u.f.JF[f][q][r][c];
+    return acc;
+  };
+  constexpr int NCC = NU * NF, NDD = NF * NU, NEE = NF * NF;
+  for (int i = tid; i < NCC + NDD + NEE; i += nt) {
+    if (i < NCC) {
+      const int row = i / NF, col = i % NF;
+      const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
+      const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1, c = 4 + v2;
+      T val;
+      if (f < 2)
+        val = wlx * (sh.LE[s][a] * fs(sh.TLL, f, b, m2, v, c) + sx * sh.DE[s][a] * fs(sh.TLL, f, b, m2, 4 + 2 * v, c) +
+                     sy * sh.LE[s][a] * fs(sh.TDL, f, b, m2, 5 + 2 * v, c));
+      else
+        val = wly * (sh.LE[s][b] * fs(sh.TLL, f, a, m2, v, c) + sx * sh.LE[s][b] * fs(sh.TDL, f, a, m2, 4 + 2 * v, c) +
+                     sy * sh.DE[s][b] * fs(sh.TLL, f, a, m2, 5 + 2 * v, c));
+      bp[(size_t)row * NC + NU + col] = dta * val;
+    } else if (i < NCC + NDD) {
+      const int j = i - NCC, row = j / NU, col = j % NU;
+      const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1, r = 12 + v;
+      const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
+      T val;
+      if (f < 2)
+        val = wlx * (sh.LE[s][a2] * fs(sh.TLL, f, mm, b2, r, v2) + sx * sh.DE[s][a2] * fs(sh.TLL, f, mm, b2, r, 8 + 2 * v2) +
+                     sy * sh.LE[s][a2] * fs(sh.TLD, f, mm, b2, r, 9 + 2 * v2));
+      else
+        val = wly * (sh.LE[s][b2] * fs(sh.TLL, f, mm, a2, r, v2) + sx * sh.LE[s][b2] * fs(sh.TLD, f, mm, a2, r, 8 + 2 * v2) +
+                     sy * sh.DE[s][b2] * fs(sh.TLL, f, mm, a2, r, 9 + 2 * v2));
+      bp[(size_t)(NU + row) * NC + col] = val;
+    } else {
+      const int j = i - NCC - NDD, row = j / NF, col = j % NF;
+      const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
+      const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
+      const T val = (f == f2) ? ((f < 2) ? wlx : wly) * fs(sh.TLL, f, mm, m2, 12 + v, 4 + v2) : T(0);
+      bp[(size_t)(NU + row) * NC + NU + col] = val;
     }
   }
 }
@@ -2764,7 +2789,7 @@ static size_t scr_stride(const imex_ctx* c) {
   const size_t NU = 4 * c->NN, NF = 16 * c->NP, NQM = 5 * c->NN;
   return 2 * (NU + NF) * NQM;
 }
-static bool use_points(const imex_ctx* c) { return use_mx(c) || !c->gas.viscous; }
+static bool use_points(const imex_ctx* c) { (void)c; return true; }
 static size_t rec_stride(const imex_ctx* c) {
   if (!use_points(c)) return 0;
   const size_t NQ = (3 * c->K + 2) / 2, NQV = NQ * NQ;
@@ -2887,20 +2912,28 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     }
     c->timer_end(ta);
   } else {
+    // viscous HDG-IP: point records (with the gradient columns), then their contraction
+    const size_t shm = sizeof(AsmShared<KK, false, true>);
+    const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
-      const size_t shm = sizeof(AsmShared<KK, false>);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT, true>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT, true>), dim3(c->n_im), dim3(256), shm,
-                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr,
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     } else {
-      const size_t shm = sizeof(AsmShared<KK, false, true>);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, false, LT, false>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, false, LT, false>), dim3(c->n_im), dim3(256), shm,
-                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, nullptr,
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                         c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
+    }
+    c->timer_end(tpo);
+    if (jacobian) {
+      const int tc = c->timer_begin(TM_CONTRACT);
+      hipLaunchKernelGGL((hdg_contract_ipv_kernel<KK, LT>), dim3(3 * c->n_im), dim3(256), 0, c->stream, c->dmesh(),
+                         c->dhdg(), dt_a, w.rec, blk);
+      c->timer_end(tc);
     }
     c->timer_end(ta);
   }
