@@ -87,6 +87,7 @@ def cpu_baseline():
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         s = IMEXSolver(wl)
+        U0 = s.U.copy()
         t0 = time.perf_counter()
         s.step()
         dt = time.perf_counter() - t0
@@ -95,7 +96,28 @@ def cpu_baseline():
             ctx.unregister()
     dof_stage = wl.n_dof * wl.stages
     return {"value": dof_stage / dt, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s"}
+            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s",
+            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, s.U)}
+
+
+def gpu_vs_oracle(wl, U0, U_oracle):
+    """The same step of the sample on the GPU in FP64 and in mixed precision: the largest
+    relative error against the oracle over the four conservative fields (each relative to
+    that field's largest magnitude), with the gates 1e-10 (FP64) and 1e-9 (mixed)."""
+    import numpy as np
+    import torch
+    from paper_2607_16044_amd import binding
+    out = {}
+    for name, prec, gate in (("fp64", 0, 1e-10), ("mixed", 1, 1e-9)):
+        eng = binding.Engine(wl, precision=prec)
+        U = torch.tensor(U0, device="cuda")
+        H = eng.init_facets(U)
+        eng.ark_step(wl.dt, U, H)
+        u = U.cpu().numpy()
+        eng.close()
+        err = max(float(np.abs(u[:, v] - U_oracle[:, v]).max() / np.abs(U_oracle[:, v]).max()) for v in range(4))
+        out[name] = {"max_rel_err": err, "gate": gate, "pass": err <= gate}
+    return out
 
 
 # committed FETCH_SIZE / WRITE_SIZE summaries of the two kernels that can dominate a step, and
