@@ -97,7 +97,38 @@ def cpu_baseline():
     dof_stage = wl.n_dof * wl.stages
     return {"value": dof_stage / dt, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
             "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s",
-            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, s.U)}
+            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, s.U), "ensemble_vs_oracle": ensemble_vs_oracle()}
+
+
+def ensemble_vs_oracle(steps=1):
+    """The batched form against the oracle: the smallest instance of each degree 1..3 in the
+    seeded 512-instance vortex ensemble (the oracle needs about 30 s for one step of the
+    smallest k = 4 instance; tests/test_gpu_batch.py covers k = 4), batched by degree as in
+    the timed run, FP64 and mixed; the largest relative error over instances and fields,
+    with the gates."""
+    import numpy as np
+    from paper_2607_16044_amd import binding, workloads
+    from oracle.ark import IMEXSolver
+    members = workloads.vortex_ensemble(512)
+    wls = [min((w for w in members if w.degree == k), key=lambda w: w.n_dof) for k in (1, 2, 3)]
+    ref = []
+    for w in wls:
+        o = IMEXSolver(w)
+        for _ in range(steps):
+            o.step()
+        ref.append(o.U)
+    out = {"instances": [f"{w.name} ({w.nx}x{w.ny}, k={w.degree})" for w in wls], "steps": steps}
+    for name, prec, gate in (("fp64", 0, 1e-10), ("mixed", 1, 1e-9)):
+        ens = binding.Ensemble(wls, precision=prec)
+        U, H = ens.initial_state()
+        for _ in range(steps):
+            ens.step(U, H)
+        states = [u.cpu().numpy() for u in ens.instance_states(U)]
+        ens.close()
+        err = max(float(np.abs(u[:, v] - r[:, v]).max() / np.abs(r[:, v]).max())
+                  for u, r in zip(states, ref) for v in range(4))
+        out[name] = {"max_rel_err": err, "gate": gate, "pass": err <= gate}
+    return out
 
 
 def gpu_vs_oracle(wl, U0, U_oracle):
