@@ -250,7 +250,8 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
 
 
 # the batched GEMM kernel run for a launch-shape code (imex_set_launch_shapes)
-WHOLE_SHAPES = {2001: "4, 4, 3, 3", 2002: "2, 4, 6, 3", 2003: "2, 2, 4, 3", 2004: "4, 2, 2, 3"}
+WHOLE_SHAPES = {2001: "4, 4, 3, 3, 32", 2002: "2, 4, 6, 3, 32", 2003: "2, 2, 4, 3, 32", 2004: "4, 2, 2, 3, 32",
+                2005: "5, 2, 1, 3, 40", 2006: "1, 2, 7, 3, 8"}
 
 
 def gemm_kernel_name(code, ltype):

@@ -1297,18 +1297,18 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
 // Whole-matrix variant (FP32, M <= BM, N <= BN): one workgroup per batch entry, a WM x WN
 // grid of waves each holding a (16 SM) x (16 SN) block of the output in registers.  Each
 // operand panel is read once per entry (the tiled kernels read it once per output tile),
-// and every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  32-deep
+// and every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  KB-deep
 // k-blocks are staged in LDS with the next block prefetched into registers.
-template <int WM, int WN, int SM, int SN>
+template <int WM, int WN, int SM, int SN, int KB>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
                                                                   int beta_one, const float* __restrict__ A, int lda,
                                                                   long long sA, const float* __restrict__ B, int ldb,
                                                                   long long sB, float* __restrict__ C, int ldc,
                                                                   long long sC) {
   using MF = Mfma16<float>;
-  constexpr int NT = 64 * WM * WN, BM = 16 * SM * WM, BN = 16 * SN * WN, KB = 32;
+  constexpr int NT = 64 * WM * WN, BM = 16 * SM * WM, BN = 16 * SN * WN;
   constexpr int PA = 4, PB = 16;              // pads: two-way LDS bank pattern for both operands
-  static_assert((BM * KB) % NT == 0 && (KB * BN) % NT == 0 && BN % 32 == 0, "block shape");
+  static_assert((BM * KB) % NT == 0 && (KB * BN) % NT == 0 && BN % 32 == 0 && KB % 4 == 0, "block shape");
   __shared__ float sa[BM][KB + PA];
   __shared__ float sb[KB][BN + PB];
   const long long bz = blockIdx.x;
@@ -1401,16 +1401,18 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
   }
 }
 
-// Whole-matrix shapes: code 2001..2004 -> {WM, WN, SM, SN}.  Several waves per SIMD are
+// Whole-matrix shapes: code 2001..2006 -> {WM, WN, SM, SN, KB}.  Several waves per SIMD are
 // needed to keep the matrix cores fed (one wave holding a 96 x 96 block runs at half the
 // speed of sixteen waves holding 48 x 48 blocks), so the shapes trade block size for waves.
-struct WholeShape { int wm, wn, sm, sn; };
+struct WholeShape { int wm, wn, sm, sn, kb; };
 __host__ __device__ constexpr WholeShape whole_shape(int code) {
-  return code == 2001 ? WholeShape{4, 4, 3, 3}     // 192 x 192, 1024 threads
-       : code == 2002 ? WholeShape{2, 4, 6, 3}     // 192 x 192, 512 threads
-       : code == 2003 ? WholeShape{2, 2, 4, 3}     // 128 x 96, 256 threads
-       : code == 2004 ? WholeShape{4, 2, 2, 3}     // 128 x 96, 512 threads
-                      : WholeShape{0, 0, 0, 0};
+  return code == 2001 ? WholeShape{4, 4, 3, 3, 32}     // 192 x 192, 1024 threads
+       : code == 2002 ? WholeShape{2, 4, 6, 3, 32}     // 192 x 192, 512 threads
+       : code == 2003 ? WholeShape{2, 2, 4, 3, 32}     // 128 x 96, 256 threads
+       : code == 2004 ? WholeShape{4, 2, 2, 3, 32}     // 128 x 96, 512 threads
+       : code == 2005 ? WholeShape{5, 2, 1, 3, 40}     // 80 x 96, 640 threads
+       : code == 2006 ? WholeShape{1, 2, 7, 3, 8}      // 112 x 96, 128 threads
+                      : WholeShape{0, 0, 0, 0, 0};
 }
 static bool gemm_whole_fits(int code, int M, int N) {
   const WholeShape w = whole_shape(code);
@@ -1511,7 +1513,7 @@ __global__ void __launch_bounds__(256) gemm_fk_kernel(int batch, int M, int N, i
 
 // the output tile edge (64, or 32 for small matrices; 0 = 64); 1000 + edge selects the
 // full-inner-dimension variant (FP32, inner dimension <= 128; otherwise the edge alone);
-// 2001..2004 the whole-matrix shapes (FP32, when the matrix fits; otherwise edge 64).
+// 2001..2006 the whole-matrix shapes (FP32, when the matrix fits; otherwise edge 64).
 template <class T>
 static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
                                const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
@@ -1522,7 +1524,7 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
 #define WHOLE_LAUNCH(CODE)                                                                                     \
   if (tile == CODE) {                                                                                          \
     constexpr WholeShape ws = whole_shape(CODE);                                                               \
-    hipLaunchKernelGGL((gemm_whole_kernel<ws.wm, ws.wn, ws.sm, ws.sn>), dim3((unsigned)batch),                 \
+    hipLaunchKernelGGL((gemm_whole_kernel<ws.wm, ws.wn, ws.sm, ws.sn, ws.kb>), dim3((unsigned)batch),         \
                        dim3(64 * ws.wm * ws.wn), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, \
                        ldb, sB, C, ldc, sC);                                                                   \
     return hipGetLastError();                                                                                  \
@@ -1531,6 +1533,8 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
       WHOLE_LAUNCH(2002)
       WHOLE_LAUNCH(2003)
       WHOLE_LAUNCH(2004)
+      WHOLE_LAUNCH(2005)
+      WHOLE_LAUNCH(2006)
 #undef WHOLE_LAUNCH
     }
     if (tile > 1000 && tile < 2000 && K <= 128) {
@@ -3025,7 +3029,7 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004}) {
+      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006}) {
         if (tile > 1000 && sizeof(LT) != 4) continue;
         if (tile > 2000 && !(g == 0 ? gemm_whole_fits(tile, NR, NR)
                                     : gemm_whole_fits(tile, g == 1 ? NU : NF, NF + 1)))
