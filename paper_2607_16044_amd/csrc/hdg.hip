@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -688,7 +689,8 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
 // with the 1D tables TLL[q][b][b2] = w_q L(q,b) L(q,b2), TDL = w_q D(q,b) L(q,b2).
 // Faces x-/x+ add LE(a) LE(a2) sum_q TLL[q][b][b2] J_f(q), faces y-/y+ add
 // LE(b) LE(b2) sum_q TLL[q][a][a2] J_f(q).  The face-only blocks C, D, E, A32,
-// A23 are single 1D sums per entry.
+// A23 are an edge value times one 1D sum per entry; the distinct sums are
+// tabulated first.
 //
 // Work split: five workgroups per HDG-MX element (K | A12 | A21 | C D E |
 // A32 A23), two per inviscid HDG-IP element (K | C D E), numbered so that the
@@ -707,12 +709,74 @@ template <int K, class T> struct CtShared {
       T JY[20][NQV];
       T JS[20][4][NQ];
     } v;
-    struct {                     // groups 3-4: the face records
-      T JF[4][NQ][8][13];
+    struct {                     // groups 3-4: staged face records and their line sums
+      T JF[4][NQ][8][8];
       T JLF[4][NQ][3][4];
+      T G[80 * NP * NP];
     } f;
   } u;
 };
+
+// The same 1D tables W L L and W D L in constant memory.  In the rank-2 updates
+// every lane of a wave reads the same entry, so the contraction takes them
+// through scalar loads as instruction operands instead of LDS broadcasts (which
+// cost as much LDS bandwidth as a full-width read).  One copy per degree and
+// storage type, written once per device by ct_upload.
+template <int K, class T> struct CtTab {
+  static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2;
+  T TLL[NQ][NP][NP];
+  T TDL[NQ][NP][NP];
+};
+template <int K, class T> struct CtSym;
+#define CT_SYM(KK, TT, NAME)                                                                        \
+  __constant__ CtTab<KK, TT> NAME;                                                                  \
+  template <> struct CtSym<KK, TT> {                                                                \
+    static __device__ __forceinline__ const CtTab<KK, TT>& get() { return NAME; }                   \
+    static const void* symbol() { return reinterpret_cast<const void*>(&HIP_SYMBOL(NAME)); }        \
+  };
+CT_SYM(1, float, ct_tab_1f)
+CT_SYM(2, float, ct_tab_2f)
+CT_SYM(3, float, ct_tab_3f)
+CT_SYM(4, float, ct_tab_4f)
+CT_SYM(1, double, ct_tab_1d)
+CT_SYM(2, double, ct_tab_2d)
+CT_SYM(3, double, ct_tab_3d)
+CT_SYM(4, double, ct_tab_4d)
+#undef CT_SYM
+
+template <int K, class T> static hipError_t ct_upload_one(const BasisTable& tb) {
+  using C = CtTab<K, T>;
+  C h;
+  for (int q = 0; q < C::NQ; ++q)
+    for (int a = 0; a < C::NP; ++a)
+      for (int a2 = 0; a2 < C::NP; ++a2) {
+        h.TLL[q][a][a2] = static_cast<T>(tb.W[q] * tb.L[q][a] * tb.L[q][a2]);
+        h.TDL[q][a][a2] = static_cast<T>(tb.W[q] * tb.D[q][a] * tb.L[q][a2]);
+      }
+  return hipMemcpyToSymbol(CtSym<K, T>::symbol(), &h, sizeof(h), 0, hipMemcpyHostToDevice);
+}
+
+// fills the constant tables of degree K (both storage types) on the current device,
+// once per device and degree
+static hipError_t ct_upload(int K, const BasisTable& tb) {
+  static std::mutex mu;
+  static std::vector<unsigned> done;   // per device: bit K
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, 0u);
+  if (done[dev] & (1u << K)) return hipSuccess;
+  switch (K) {
+    case 1: e = ct_upload_one<1, float>(tb); if (e == hipSuccess) e = ct_upload_one<1, double>(tb); break;
+    case 2: e = ct_upload_one<2, float>(tb); if (e == hipSuccess) e = ct_upload_one<2, double>(tb); break;
+    case 3: e = ct_upload_one<3, float>(tb); if (e == hipSuccess) e = ct_upload_one<3, double>(tb); break;
+    case 4: e = ct_upload_one<4, float>(tb); if (e == hipSuccess) e = ct_upload_one<4, double>(tb); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e == hipSuccess) done[dev] |= 1u << K;
+  return e;
+}
 
 // coefficients of the lifted primitives in the mixed equations: component c of
 // l(U, Uhat) = sum_p (cx[c][p] d/dx + cy[c][p] d/dy) of P_p, P = (u, v, theta)
@@ -819,6 +883,7 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
         for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] = 0.0;
       const T* jxp = sh.u.v.JX[pr];
       const T* jyp = sh.u.v.JY[pr];
+      const CtTab<K, T>& ct = CtSym<K, T>::get();
 #pragma unroll 1
       for (int qj = 0; qj < NQ; ++qj) {
         T px = 0.0, py = 0.0;
@@ -832,7 +897,10 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
 #pragma unroll
         for (int b = 0; b < NP; ++b)
 #pragma unroll
-          for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.TLL[qj][b][b2] * px + sh.TDL[qj][b][b2] * py;
+          for (int b2 = 0; b2 < NP; ++b2) {
+            acc[b][b2] += ct.TLL[qj][b][b2] * px;
+            acc[b][b2] += ct.TDL[qj][b][b2] * py;
+          }
       }
       if (grp < 2) {
         const T(*js)[NQ] = sh.u.v.JS[pr];
@@ -845,7 +913,7 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
 #pragma unroll
             for (int b = 0; b < NP; ++b)
 #pragma unroll
-              for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += sh.TLL[q][b][b2] * cq;
+              for (int b2 = 0; b2 < NP; ++b2) acc[b][b2] += ct.TLL[q][b][b2] * cq;
           }
         }
 #pragma unroll 1
@@ -890,68 +958,117 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
     }
     return;
   }
-  // face-only blocks; LDS holds rows s (0..3) and t (4..7) of the face Jacobians,
-  // columns U (0..3), Uhat (4..7) and, for HDG-MX, Q (8..12)
-  if constexpr (MX) {
-    for (int i = tid; i < 4 * NQ * 8 * 13; i += nt) (&sh.u.f.JF[0][0][0][0])[i] = rp[R::JF + i];
-    for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
-  } else {
-    for (int i = tid; i < 4 * NQ * 8 * 8; i += nt) {
-      const int f = i / (NQ * 64), q = (i / 64) % NQ, r = (i / 8) % 8, col = i % 8;
+  // Face-only blocks.  Each entry is an edge value of a basis function times a line sum
+  //   G(x, y) = sum_q w_q L(q, x) L(q, y) J(q)
+  // over one face, and the sums depend on five of the entry's indices only, so each is
+  // formed once into LDS and the blocks are then written from those tables by threads
+  // that own one column each (consecutive lanes write consecutive addresses of a row).
+  // Staged face Jacobians JF[f][q][r][c]: group 3 takes rows s (0..3) and t (4..7) with
+  // columns U (0..3) and Uhat (4..7); group 4 takes the t rows (0..3) with the Q columns
+  // (0..4), and the lifting traces JLF.
+  if (grp == 3) {
+    for (int i = tid; i < 4 * NQ * 64; i += nt) {
+      const int fq = i / 64, r = (i / 8) % 8, col = i % 8;
       const int src = r < 4 ? r : R::TO + (r - 4);
-      sh.u.f.JF[f][q][r][col] = rp[R::JF + ((f * NQ + q) * R::NOF + src) * R::NIF + col];
+      (&sh.u.f.JF[0][0][0][0])[i] = rp[R::JF + (fq * R::NOF + src) * R::NIF + col];
     }
+  } else if constexpr (MX) {
+    for (int i = tid; i < 4 * NQ * 20; i += nt) {
+      const int fq = i / 20, v = (i % 20) / 5, c = i % 5;
+      (&sh.u.f.JF[0][0][0][0])[fq * 64 + v * 8 + c] = rp[R::JF + (fq * R::NOF + R::TO + v) * R::NIF + 8 + c];
+    }
+    for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
   }
-  __syncthreads();
-  // 1D face sum: sum_q TLL[q][x][y] J(q) for face f
-  auto fsum = [&](int f, int x, int y, int jr, int jc) {
-    T acc = 0.0;
+  T* G = sh.u.f.G;
+  // G[((f * 4 + v) * NV2 + v2) * NN + x * NP + y] = sum_q TLL[q][x][y] JF[f][q][r0 + v][c0 + v2]
+  auto line_sums = [&](int NV2, int r0, int c0) {
+    const int n = 4 * 4 * NV2 * NN;
+    for (int i = tid; i < n; i += nt) {
+      const int xy = i % NN, x = xy / NP, y = xy % NP, fvv = i / NN, v2 = fvv % NV2, fv = fvv / NV2;
+      const T* j = &sh.u.f.JF[fv >> 2][0][r0 + (fv & 3)][c0 + v2];
+      T acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc += sh.TLL[q][x][y] * sh.u.f.JF[f][q][jr][jc];
-    return acc;
+      for (int q = 0; q < NQ; ++q) acc += sh.TLL[q][x][y] * j[q * 64];
+      G[i] = acc;
+    }
   };
   if (grp == 3) {
-    // C = dt_a dR/dUhat (NU x NF), D = dh/dU (NF x NU), E = dh/dUhat (NF x NF, block diagonal)
-    constexpr int NCC = NU * NF, NDD = NF * NU, NEE = NF * NF;
-    for (int i = tid; i < NCC + NDD + NEE; i += nt) {
-      if (i < NCC) {
-        const int row = i / NF, col = i % NF;
-        const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
+    // C = dt_a dR/dUhat (NU x NF): row (v, a, b), column (f, v2, m2); the x-faces pair
+    // LE(a) with the line sum over (b, m2), the y-faces LE(b) with the sum over (a, m2)
+    __syncthreads();
+    line_sums(4, 0, 4);
+    __syncthreads();
+    {
+      const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
+      if (lane < lanes) {
         const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
-        const T val = (f < 2) ? wlx * sh.LE[s][a] * fsum(f, b, m2, v, 4 + v2)
-                                   : wly * sh.LE[s][b] * fsum(f, a, m2, v, 4 + v2);
-        bp[(size_t)row * NC + NU + col] = dta * val;
-      } else if (i < NCC + NDD) {
-        const int j = i - NCC, row = j / NU, col = j % NU;
-        const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
+        const T sc = dta * ((f < 2) ? wlx : wly);
+        const T* g = G + (f * 16 + v2) * NN + m2;
+        for (int row = lane; row < NU; row += lanes) {
+          const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
+          const T val = (f < 2) ? sh.LE[s][a] * g[v * 4 * NN + b * NP] : sh.LE[s][b] * g[v * 4 * NN + a * NP];
+          bp[(size_t)row * NC + NU + col] = sc * val;
+        }
+      }
+    }
+    // D = dh/dU (NF x NU): row (f, v, mm), column (v2, a2, b2)
+    __syncthreads();
+    line_sums(4, 4, 0);
+    __syncthreads();
+    {
+      const int lanes = nt / NU, lane = tid / NU, col = tid % NU;
+      if (lane < lanes) {
         const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-        const T val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, v2)
-                                   : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, v2);
-        bp[(size_t)(NU + row) * NC + col] = val;
-      } else {
-        const int j = i - NCC - NDD, row = j / NF, col = j % NF;
-        const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
+        for (int row = lane; row < NF; row += lanes) {
+          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
+          const T* g = G + ((f * 4 + v) * 4 + v2) * NN + mm * NP;
+          const T val = (f < 2) ? wlx * sh.LE[s][a2] * g[b2] : wly * sh.LE[s][b2] * g[a2];
+          bp[(size_t)(NU + row) * NC + col] = val;
+        }
+      }
+    }
+    // E = dh/dUhat (NF x NF, block diagonal over the faces): row (f, v, mm), column (f2, v2, m2)
+    __syncthreads();
+    line_sums(4, 4, 4);
+    __syncthreads();
+    {
+      const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
+      if (lane < lanes) {
         const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
-        const T val = (f == f2) ? ((f < 2) ? wlx : wly) * fsum(f, mm, m2, 4 + v, 4 + v2) : T(0);
-        bp[(size_t)(NU + row) * NC + NU + col] = val;
+        const T wl = (f2 < 2) ? wlx : wly;
+        for (int row = lane; row < NF; row += lanes) {
+          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
+          const T val = (f == f2) ? wl * G[((f * 4 + v) * 4 + v2) * NN + mm * NP + m2] : T(0);
+          bp[(size_t)(NU + row) * NC + NU + col] = val;
+        }
       }
     }
     return;
   }
-  // grp 4: A32 = dh/dQ (NF x NQM, rows NU.. of Lm), A23 = M_Q^-1 dl/dUhat (NQM x NF, columns NU.. of Rm)
-  constexpr int N32 = NF * NQM, N23 = NQM * NF;
-  for (int i = tid; i < N32 + N23; i += nt) {
-    if (i < N32) {
-      const int row = i / NQM, col = i % NQM;
-      const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
-      const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-      const T val = (f < 2) ? wlx * sh.LE[s][a2] * fsum(f, mm, b2, 4 + v, 8 + c)
-                                 : wly * sh.LE[s][b2] * fsum(f, mm, a2, 4 + v, 8 + c);
-      Lm[(size_t)(NU + row) * NQM + col] = val;
-    } else {
-      const int j = i - N32, row = j / NF, col = j % NF;
-      const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
-      const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
+  if constexpr (MX) {
+    // A32 = dh/dQ (NF x NQM, rows NU.. of Lm): row (f, v, mm), column (c, a2, b2)
+    __syncthreads();
+    line_sums(5, 0, 0);
+    __syncthreads();
+    {
+      const int lanes = nt / NQM, lane = tid / NQM, col = tid % NQM;
+      if (lane < lanes) {
+        const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
+        for (int row = lane; row < NF; row += lanes) {
+          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
+          const T* g = G + ((f * 4 + v) * 5 + c) * NN + mm * NP;
+          const T val = (f < 2) ? wlx * sh.LE[s][a2] * g[b2] : wly * sh.LE[s][b2] * g[a2];
+          Lm[(size_t)(NU + row) * NQM + col] = val;
+        }
+      }
+    }
+    // A23 = M_Q^-1 dl/dUhat (NQM x NF, columns NU.. of Rm): row (c, a, b), column (f, v2, m2).
+    // The line sums take the lifted normal traces g_q = sum_p cn_p JLF[f][q][p][v2] with
+    // cn_p = cx_p n_x + cy_p n_y of component c:
+    // G[((f * 5 + c) * 4 + v2) * NN + x * NP + y] = sum_q TLL[q][x][y] g_q
+    __syncthreads();
+    for (int i = tid; i < 4 * 5 * 4 * NN; i += nt) {
+      const int xy = i % NN, x = xy / NP, y = xy % NP, fcv = i / NN, v2 = fcv % 4, c = (fcv / 4) % 5, f = fcv / 20;
       double nxd, nyd;
       fnormal(f, nxd, nyd);
       const T nx = T(nxd), ny = T(nyd);
@@ -959,17 +1076,29 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
       lift_coef(c, cx, cy);
       T cn[3];
       for (int pp = 0; pp < 3; ++pp) cn[pp] = cx[pp] * nx + cy[pp] * ny;
-      const int x = (f < 2) ? b : a;
       T acc = 0.0;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T gq = cn[0] * sh.u.f.JLF[f][q][0][v2] + cn[1] * sh.u.f.JLF[f][q][1][v2] +
-                          cn[2] * sh.u.f.JLF[f][q][2][v2];
-        acc += sh.TLL[q][x][m2] * gq;
+                     cn[2] * sh.u.f.JLF[f][q][2][v2];
+        acc += sh.TLL[q][x][y] * gq;
       }
-      const T edge = (f < 2) ? wlx * sh.LE[s][a] : wly * sh.LE[s][b];
-      const T minv = T(1) / (((c == 1) ? T(2) : T(1)) * sh.NW[a] * sh.NW[b] * jac);
-      Rm[(size_t)row * NR + NU + col] = -minv * edge * acc;
+      G[i] = acc;
+    }
+    __syncthreads();
+    {
+      const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
+      if (lane < lanes) {
+        const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
+        const T wl = (f < 2) ? wlx : wly;
+        for (int row = lane; row < NQM; row += lanes) {
+          const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
+          const T* g = G + ((f * 5 + c) * 4 + v2) * NN + m2;
+          const T edge = (f < 2) ? wl * sh.LE[s][a] * g[b * NP] : wl * sh.LE[s][b] * g[a * NP];
+          const T minv = T(1) / (((c == 1) ? T(2) : T(1)) * sh.NW[a] * sh.NW[b] * jac);
+          Rm[(size_t)row * NR + NU + col] = -minv * edge;
+        }
+      }
     }
   }
 }
@@ -2838,6 +2967,11 @@ imex_status hdg_alloc(imex_ctx* c) {
   if (e != hipSuccess) {
     c->err = std::string("implicit workspace: ") + hipGetErrorString(e);
     return IMEX_ENOMEM;
+  }
+  e = ct_upload(c->K, c->tab);
+  if (e != hipSuccess) {
+    c->err = std::string("contraction tables: ") + hipGetErrorString(e);
+    return IMEX_EDEVICE;
   }
   w.bytes += hdg_workspace_bytes(c);
   c->prec_valid = false;
