@@ -250,8 +250,9 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
 
 
 # the batched GEMM kernel run for a launch-shape code (imex_set_launch_shapes)
-WHOLE_SHAPES = {2001: "4, 4, 3, 3, 32", 2002: "2, 4, 6, 3, 32", 2003: "2, 2, 4, 3, 32", 2004: "4, 2, 2, 3, 32",
-                2005: "5, 2, 1, 3, 40", 2006: "1, 2, 7, 3, 8"}
+WHOLE_SHAPES = {2001: "4, 4, 3, 3, 32, false", 2002: "2, 4, 6, 3, 32, false", 2003: "2, 2, 4, 3, 32, false",
+                2004: "4, 2, 2, 3, 32, false",
+                2005: "5, 2, 1, 3, 40, false", 2006: "1, 2, 7, 3, 8, false", 2007: "2, 4, 3, 3, 16, true", 2008: "2, 2, 3, 3, 16, true"}
 
 
 def gemm_kernel_name(code, ltype):
@@ -491,7 +492,7 @@ def main():
                    "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": main_prec,
                    "newton_corrections_per_step": res["newton"], "jacobians_per_step": res["jacobians"],
                    "gmres_its_per_step": res["gmres"], "newton_simplified": 1,
-                   "gmres_forcing": 3},
+                   "gmres_forcing": 3, "launch_shapes": res["shapes"]},
         "roofline": roof,
         "phases_ms_per_step": phases,
         "kernels_ms_per_step": kernels,

@@ -256,8 +256,8 @@ imex_status imex_set_graphs(imex_ctx* ctx, int on);
  * number of elements per workgroup (at state U, all elements; Uhat needed for
  * HDG-MX coupling, else nullable) and each batched GEMM of the implicit stage for
  * its output tiles (64x64, 32x32, and in FP32 the full-inner-dimension variants
- * 1064, 1032 and the whole-matrix shapes 2001..2006 of imex_set_launch_shapes that
- * fit the matrix), and keeps the fastest for this context.
+ * 1064, 1032 and the whole-matrix shapes 2001..2008 of imex_set_launch_shapes that
+ * apply to the matrix), and keeps the fastest for this context.
  * out (host [4]): elements per residual workgroup (0 = built-in default), then
  * the tiles of the mixed-block elimination, K^-1 [C f] and Schur-update GEMMs
  * (0 = not used).  Call after imex_set_regions and before stepping: it
@@ -272,7 +272,9 @@ imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, in
  * inner dimension <= 128, else the plain edge), or 2001..2006 (FP32, one workgroup
  * per element holding the whole output: up to 192 x 192 with 4 x 4 or 2 x 4 waves,
  * up to 128 x 96 with 2 x 2 or 4 x 2 waves, up to 80 x 96 with 5 x 2 waves, up to
- * 112 x 96 with 1 x 2 waves; else edge 64).  Results do
+ * 112 x 96 with 1 x 2 waves; else edge 64), or 2007, 2008 (FP32, the output split
+ * into parts of 96 x 192 with 2 x 4 waves or 96 x 96 with 2 x 2 waves, one
+ * workgroup per part; any size).  Results do
  * not depend on the shapes beyond rounding.  Errors: EINVAL. */
 imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
 

@@ -1423,12 +1423,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
       }
 }
 
-// Whole-matrix variant (FP32, M <= BM, N <= BN): one workgroup per batch entry, a WM x WN
-// grid of waves each holding a (16 SM) x (16 SN) block of the output in registers.  Each
-// operand panel is read once per entry (the tiled kernels read it once per output tile),
-// and every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  KB-deep
+// Whole-matrix variant (FP32): a WM x WN grid of waves each holding a (16 SM) x (16 SN)
+// block of the output in registers, so that a workgroup covers a BM x BN part of C.  When
+// C fits in one part each operand panel is read once per entry (the tiled kernels read it
+// once per output tile); larger C is split into parts, one workgroup each, numbered so
+// that the parts of one entry run on the same XCD and share its L2 copy of the panels.
+// Every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  KB-deep
 // k-blocks are staged in LDS with the next block prefetched into registers.
-template <int WM, int WN, int SM, int SN, int KB>
+template <int WM, int WN, int SM, int SN, int KB, bool SPLIT>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
                                                                   int beta_one, const float* __restrict__ A, int lda,
                                                                   long long sA, const float* __restrict__ B, int ldb,
@@ -1440,7 +1442,15 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
   static_assert((BM * KB) % NT == 0 && (KB * BN) % NT == 0 && BN % 32 == 0 && KB % 4 == 0, "block shape");
   __shared__ float sa[BM][KB + PA];
   __shared__ float sb[KB][BN + PB];
-  const long long bz = blockIdx.x;
+  int m0 = 0, n0 = 0;
+  long long bz = blockIdx.x;
+  if constexpr (SPLIT) {
+    const int pn = (N + BN - 1) / BN, np = ((M + BM - 1) / BM) * pn;
+    const int L = blockIdx.x, xcd = L & 7, rr = L >> 3, part = rr % np;
+    bz = 8LL * (rr / np) + xcd;
+    m0 = (part / pn) * BM;
+    n0 = (part % pn) * BN;
+  }
   if (bz >= batch) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = wv / WN, wc = wv % WN;
@@ -1456,7 +1466,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
 #pragma unroll
     for (int u = 0; u < NLA; ++u) {
       const int idx = tid + NT * u;
-      const int r = idx / KB, gk = k0 + idx % KB;
+      const int r = m0 + idx / KB, gk = k0 + idx % KB;
       const bool ok = r < M && gk < Kd;
       const float v = Ab[ok ? r * lda + gk : 0];
       ra[u] = ok ? v : 0.0f;
@@ -1464,7 +1474,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
       const int idx = tid + NT * u;
-      const int gk = k0 + idx / BN, cc = idx % BN;
+      const int gk = k0 + idx / BN, cc = n0 + idx % BN;
       const bool ok = gk < Kd && cc < N;
       const float v = Bb[ok ? gk * ldb + cc : 0];
       rb[u] = ok ? v : 0.0f;
@@ -1513,8 +1523,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
     for (int tj = 0; tj < SN; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = 16 * SM * wr + 16 * ti + MF::row(lk, r);
-        const int gn = 16 * SN * wc + 16 * tj + li;
+        const int gm = m0 + 16 * SM * wr + 16 * ti + MF::row(lk, r);
+        const int gn = n0 + 16 * SN * wc + 16 * tj + li;
         const bool ok = gm < M && gn < N;
         const float v = Cb[ok ? gm * ldc + gn : 0];
         cv[tj][r] = (beta_one && ok) ? v : 0.0f;
@@ -1523,29 +1533,38 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
     for (int tj = 0; tj < SN; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = 16 * SM * wr + 16 * ti + MF::row(lk, r);
-        const int gn = 16 * SN * wc + 16 * tj + li;
+        const int gm = m0 + 16 * SM * wr + 16 * ti + MF::row(lk, r);
+        const int gn = n0 + 16 * SN * wc + 16 * tj + li;
         if (gm < M && gn < N) Cb[gm * ldc + gn] = cv[tj][r] + float(alpha) * acc[ti][tj][r];
       }
   }
 }
 
-// Whole-matrix shapes: code 2001..2006 -> {WM, WN, SM, SN, KB}.  Several waves per SIMD are
+// Whole-matrix shapes: code 2001..2008 -> {WM, WN, SM, SN, KB}.  Several waves per SIMD are
 // needed to keep the matrix cores fed (one wave holding a 96 x 96 block runs at half the
-// speed of sixteen waves holding 48 x 48 blocks), so the shapes trade block size for waves.
-struct WholeShape { int wm, wn, sm, sn, kb; };
+// speed of sixteen waves holding 48 x 48 blocks), so the shapes trade block size for waves;
+// 2007 and 2008 cover 180 x 180 in two and four parts, with two and five workgroups per CU.
+struct WholeShape { int wm, wn, sm, sn, kb; bool split; };
 __host__ __device__ constexpr WholeShape whole_shape(int code) {
-  return code == 2001 ? WholeShape{4, 4, 3, 3, 32}     // 192 x 192, 1024 threads
-       : code == 2002 ? WholeShape{2, 4, 6, 3, 32}     // 192 x 192, 512 threads
-       : code == 2003 ? WholeShape{2, 2, 4, 3, 32}     // 128 x 96, 256 threads
-       : code == 2004 ? WholeShape{4, 2, 2, 3, 32}     // 128 x 96, 512 threads
-       : code == 2005 ? WholeShape{5, 2, 1, 3, 40}     // 80 x 96, 640 threads
-       : code == 2006 ? WholeShape{1, 2, 7, 3, 8}      // 112 x 96, 128 threads
-                      : WholeShape{0, 0, 0, 0, 0};
+  return code == 2001 ? WholeShape{4, 4, 3, 3, 32, false}     // 192 x 192, 1024 threads
+       : code == 2002 ? WholeShape{2, 4, 6, 3, 32, false}     // 192 x 192, 512 threads
+       : code == 2003 ? WholeShape{2, 2, 4, 3, 32, false}     // 128 x 96, 256 threads
+       : code == 2004 ? WholeShape{4, 2, 2, 3, 32, false}     // 128 x 96, 512 threads
+       : code == 2005 ? WholeShape{5, 2, 1, 3, 40, false}     // 80 x 96, 640 threads
+       : code == 2006 ? WholeShape{1, 2, 7, 3, 8, false}      // 112 x 96, 128 threads
+       : code == 2007 ? WholeShape{2, 4, 3, 3, 16, true}      // parts of 96 x 192, 512 threads
+       : code == 2008 ? WholeShape{2, 2, 3, 3, 16, true}      // parts of 96 x 96, 256 threads
+                      : WholeShape{0, 0, 0, 0, 0, false};
+}
+// workgroups per batch entry of a whole-matrix shape (the output split into parts)
+static int gemm_whole_parts(int code, int M, int N) {
+  const WholeShape w = whole_shape(code);
+  const int bm = 16 * w.sm * w.wm, bn = 16 * w.sn * w.wn;
+  return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
 }
 static bool gemm_whole_fits(int code, int M, int N) {
   const WholeShape w = whole_shape(code);
-  return w.wm > 0 && M <= 16 * w.sm * w.wm && N <= 16 * w.sn * w.wn;
+  return w.wm > 0 && (w.split || (M <= 16 * w.sm * w.wm && N <= 16 * w.sn * w.wn));
 }
 
 // C[b] (+)= alpha A[b] B[b] for b < batch (row-major, leading dimensions lda/ldb/ldc,
@@ -1642,7 +1661,8 @@ __global__ void __launch_bounds__(256) gemm_fk_kernel(int batch, int M, int N, i
 
 // the output tile edge (64, or 32 for small matrices; 0 = 64); 1000 + edge selects the
 // full-inner-dimension variant (FP32, inner dimension <= 128; otherwise the edge alone);
-// 2001..2006 the whole-matrix shapes (FP32, when the matrix fits; otherwise edge 64).
+// 2001..2008 the whole-matrix shapes (FP32; 2001..2006 when the matrix fits one part,
+// otherwise edge 64).
 template <class T>
 static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, double alpha, bool beta_one,
                                const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc,
@@ -1653,7 +1673,8 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
 #define WHOLE_LAUNCH(CODE)                                                                                     \
   if (tile == CODE) {                                                                                          \
     constexpr WholeShape ws = whole_shape(CODE);                                                               \
-    hipLaunchKernelGGL((gemm_whole_kernel<ws.wm, ws.wn, ws.sm, ws.sn, ws.kb>), dim3((unsigned)batch),         \
+    const long long nbw = 8LL * ((batch + 7) / 8) * gemm_whole_parts(CODE, M, N);                               \
+    hipLaunchKernelGGL((gemm_whole_kernel<ws.wm, ws.wn, ws.sm, ws.sn, ws.kb, ws.split>), dim3((unsigned)nbw), \
                        dim3(64 * ws.wm * ws.wn), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, \
                        ldb, sB, C, ldc, sC);                                                                   \
     return hipGetLastError();                                                                                  \
@@ -1664,6 +1685,8 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
       WHOLE_LAUNCH(2004)
       WHOLE_LAUNCH(2005)
       WHOLE_LAUNCH(2006)
+      WHOLE_LAUNCH(2007)
+      WHOLE_LAUNCH(2008)
 #undef WHOLE_LAUNCH
     }
     if (tile > 1000 && tile < 2000 && K <= 128) {
@@ -3163,7 +3186,7 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006}) {
+      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008}) {
         if (tile > 1000 && sizeof(LT) != 4) continue;
         if (tile > 2000 && !(g == 0 ? gemm_whole_fits(tile, NR, NR)
                                     : gemm_whole_fits(tile, g == 1 ? NU : NF, NF + 1)))

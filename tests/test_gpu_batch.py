@@ -165,8 +165,8 @@ def test_autotuned_shapes_give_same_result(case, precision):
                                             ("vortex_small", 1)])
 def test_every_gemm_variant_gives_same_result(case, precision):
     """Each GEMM launch shape (64, 32 and, in FP32, the full-inner-dimension 1064 / 1032 and
-    the whole-matrix 2001..2006, which fall back to the 64 tile where the matrix does not
-    fit) set through imex_set_launch_shapes gives the default's states to rounding."""
+    the whole-matrix 2001..2008, of which 2001..2006 fall back to the 64 tile where the matrix
+    does not fit and 2007 / 2008 split it into parts) set through imex_set_launch_shapes gives the default's states to rounding."""
     wl = W.get(case)
 
     def run(shapes):
@@ -181,7 +181,7 @@ def test_every_gemm_variant_gives_same_result(case, precision):
         eng.close()
         return out
     ref = run(None)
-    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006] if precision == 1 else [])
+    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008] if precision == 1 else [])
     for t in tiles:
         e = rel_err(run({"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}), ref)
         print(case, precision, t, e)
@@ -194,7 +194,7 @@ def test_invalid_launch_shapes_rejected():
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"gemm_tile_eliminate": 48})
     with pytest.raises(IMEXError):
-        eng.set_launch_shapes({"gemm_tile_schur": 2007})
+        eng.set_launch_shapes({"gemm_tile_schur": 2009})
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"dg_tile": 7})
     eng.close()
