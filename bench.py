@@ -69,7 +69,14 @@ def parse():
     ap.add_argument("--dt-study-n", type=int, default=48, help="mesh size n x n of --dt-study")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (calibrates HBM traffic counters)")
+    ap.add_argument("--eliminate-shape", type=int, default=0,
+                    help="launch-shape code of the mixed-block elimination GEMM in place of the autotuner's "
+                         "choice (FP32 path; for taking its HBM counters on a given shape)")
     return ap.parse_args()
+
+
+# launch-shape code that replaces the autotuner's choice for the elimination GEMM (0: keep it)
+ELIMINATE_SHAPE = 0
 
 
 def cpu_baseline():
@@ -175,22 +182,31 @@ def source_digest(which):
 def measured_traffic(which, precision, kernel):
     """HBM bytes per launch of the elimination or the contraction from its committed
     FETCH_SIZE / WRITE_SIZE summary, or None when it is missing, for another precision or
-    launch shape, or taken on another kernel source."""
+    launch shape, or taken on another kernel source.  The summary lists the precision and
+    the source digest, then one kernel line with its fetch and write figures per launch
+    shape measured."""
     try:
         text = open(COUNTERS[which][0]).read()
     except OSError:
         return None
-    vals = {}
+    common, entries = {}, []
     for line in text.splitlines():
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
+            k, v = k.strip(), v.strip().strip("`")
+            if k == "kernel":
+                entries.append({"kernel": v})
+            elif k in ("fetch_bytes_per_launch", "write_bytes_per_launch") and entries:
+                entries[-1][k] = v
+            else:
+                common[k] = v
     try:
-        if vals.get("precision") != precision or vals.get("kernel_source_sha256") != source_digest(which):
+        if common.get("precision") != precision or common.get("kernel_source_sha256") != source_digest(which):
             return None
-        if kernel not in vals.get("kernel", ""):
-            return None
-        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+        for e in entries:
+            if kernel in e["kernel"]:
+                return float(e["fetch_bytes_per_launch"]) + float(e["write_bytes_per_launch"])
+        return None
     except (KeyError, ValueError):
         return None
 
@@ -227,6 +243,9 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
     U = eng.initial_state()
     Uhat = eng.init_facets(U)
     shapes = eng.autotune(U, Uhat)
+    if ELIMINATE_SHAPE and precision != "fp64":
+        shapes = dict(shapes, gemm_tile_eliminate=ELIMINATE_SHAPE)
+        eng.set_launch_shapes(shapes)
     eng.set_graphs(True)
     torch.cuda.synchronize()
     for _ in range(warmup):
@@ -408,7 +427,9 @@ def run_ensemble(precision, steps, warmup, n=512):
 
 
 def main():
+    global ELIMINATE_SHAPE
     args = parse()
+    ELIMINATE_SHAPE = args.eliminate_shape
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; how the path would shard over several GPUs is "
                                    "described in DESIGN.md and not built", "n_gpus": args.gpus}))
