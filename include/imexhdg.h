@@ -208,12 +208,23 @@ imex_status imex_dg_residual(imex_ctx* ctx, const double* U, const double* Uhat,
  * interface data y^ex_{i+1} (read), implicit rows the initial guess on entry and
  * the stage solution on exit; Uhat dev inout; R_out dev (nullable): R^HDG at the
  * converged state in implicit rows.  st host (nullable).
- * Errors: ESTATE (no implicit region), ENOCONV, ENONFINITE. */
+ * Convergence is certified only by corrections whose facet solve reached gmres_rtol; a
+ * solve stopped by gmres_maxit is followed by another full correction.
+ * Errors: ESTATE (no implicit region), ENOCONV (newton_maxit corrections without a
+ * certified increment; U, Uhat hold the last iterate), ENONFINITE (a non-finite residual
+ * or increment: NaN or Inf in the inputs or a diverging iteration). */
 imex_status imex_implicit_stage_solve(imex_ctx* ctx, double dt_aii, const double* rhs, double* U,
                                       double* Uhat, double* R_out, imex_stats* st);
 
 /* One time step of Alg. imex_scheme_update (App. C) from t_n to t_n + dt:
- * U dev inout (all elements), Uhat dev inout.  st host (nullable). */
+ * U dev inout (all elements), Uhat dev inout.  st host (nullable).
+ * The tableau is checked before any work: s in 1..3, Ae strictly and Ai lower
+ * triangular, fsal and stiffly_accurate equal to what the coefficients say.
+ * Errors: EINVAL (bad tableau, flags that disagree with it, dt <= 0, Uhat NULL with
+ * an implicit region), ENOTIMPL (an implicit region with an implicit tableau that is
+ * not stiffly accurate), ESTATE (regions not set), and the errors of
+ * imex_implicit_stage_solve, after which U is unchanged and Uhat holds the failed
+ * stage's last iterate. */
 imex_status imex_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt, double* U, double* Uhat,
                           imex_stats* st);
 

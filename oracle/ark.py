@@ -23,7 +23,7 @@ from . import physics as ph
 from .basis import Basis
 from .dg import Geometry, apply_minv, dg_residual, mass_matrix
 from .hdg import HDGSystem, init_facets, init_mixed
-from .mesh import Mesh
+from .mesh import Mesh, BC_FARFIELD
 
 
 class Tableau:
@@ -79,6 +79,7 @@ class IMEXSolver:
         self.Uhat = init_facets(self.U, self.mesh, self.basis)
         self.Q = init_mixed(self.U, self.Uhat, self.system)
         self.newton_its = []
+        self.ledger = []
 
     def initial_state(self):
         X, Y = self.mesh.node_coords(self.basis)
@@ -91,31 +92,63 @@ class IMEXSolver:
     def mass_apply(self, U):
         return np.einsum("enm,evm->evn", self.M, U)
 
-    def dg(self, Y, Q):
-        return dg_residual(Y, Q, self.wl, self.mesh, self.basis, self.gas)
+    def dg(self, Y, Q, fluxes=None):
+        """R^DG; with a list fluxes, appends the flux of R^DG out of the explicit region
+        through the interface faces and through the far-field faces ((4,) each)."""
+        faces = {} if fluxes is not None else None
+        R = dg_residual(Y, Q, self.wl, self.mesh, self.basis, self.gas, faces=faces)
+        if fluxes is not None:
+            mesh = self.mesh
+            itf, bnd = np.zeros(4), np.zeros(4)
+            for f in range(4):
+                s, w = faces[f]
+                flux = np.einsum("veq,eq->ev", s, w)
+                nb = mesh.nbr[:, f]
+                explicit = ~mesh.implicit
+                itf += flux[explicit & (nb >= 0) & mesh.implicit[np.maximum(nb, 0)]].sum(axis=0)
+                bnd += flux[explicit & (nb < 0) & (mesh.bctype[:, f] == BC_FARFIELD)].sum(axis=0)
+            fluxes.append((itf, bnd))
+        return R
+
+    def totals(self, U=None):
+        """Conserved totals sum_T int_T U (4,)."""
+        return np.einsum("enm,evm->v", self.M, self.U if U is None else U)
 
     def step(self):
+        """One IMEX step (Alg. imex_scheme_update).  Also appends to self.ledger the
+        interface flux-defect ledger of the step: the change of the conserved totals that
+        the update formulas imply, split into (i) the interface term
+            -dt [ sum_j be_j Phi^DG_j + sum_j bi_j Phi^HDG_j ]  over the faces of Gamma_i,
+        Phi^DG_j the flux of R^DG_j out of the explicit elements and Phi^HDG_j that of
+        R^HDG_j out of the implicit elements through those faces (the two sides evaluate
+        the interface with different stage data, so they do not cancel), and (ii) the same
+        sums over the physical boundary faces.  Interior DG faces and (at the converged
+        stages) interior HDG facets cancel, so the totals change by (i) + (ii) up to
+        roundoff and the Newton tolerance."""
         tab, dt = self.tab, self.wl.dt
         ex, im = self.mesh.ex_elems, self.mesh.im_elems
         Un = self.U.copy()
         Y = self.U.copy()
         Rdg, Rhdg = [], []
+        fdg, fhdg = [], []
         its = []
         for i in range(1, tab.s + 1):
-            Rdg.append(self.dg(Y, self.Q))
+            Rdg.append(self.dg(Y, self.Q, fdg))
             acc = sum(tab.Ae[i, j] * Rdg[j] for j in range(i))
             Y[ex] = Un[ex] - dt * apply_minv(acc[ex], self.basis, _sub(self.geo, ex))
             if len(im):
                 rhs = self.mass_apply(Un)[im]
                 for j in range(i - 1):
                     rhs = rhs - dt * tab.Ai[i - 1, j] * Rhdg[j]
-                n_it, Rh = self.system.newton(Y, self.Q, self.Uhat, dt * tab.Ai[i - 1, i - 1], rhs)
+                dta = dt * tab.Ai[i - 1, i - 1]
+                n_it, Rh = self.system.newton(Y, self.Q, self.Uhat, dta, rhs)
                 its.append(n_it)
                 Rhdg.append(Rh)
+                fhdg.append(self.system.face_fluxes(Y, self.Q, self.Uhat, self.system.stage_data(Y, dta, rhs)))
         if tab.fsal:
             self.U[ex] = Y[ex]
         else:
-            Rdg.append(self.dg(Y, self.Q))
+            Rdg.append(self.dg(Y, self.Q, fdg))
             acc = sum(tab.be[j] * Rdg[j] for j in range(tab.s + 1))
             self.U[ex] = Un[ex] - dt * apply_minv(acc[ex], self.basis, _sub(self.geo, ex))
         if len(im):
@@ -125,6 +158,14 @@ class IMEXSolver:
                 acc = sum(tab.bi[j] * Rhdg[j] for j in range(tab.s))
                 self.U[im] = Un[im] - dt * apply_minv(acc, self.basis, _sub(self.geo, im))
         self.newton_its.append(its)
+        itf, bnd = np.zeros(4), np.zeros(4)
+        for j, (a, b) in enumerate(fdg):
+            itf -= dt * tab.be[j] * a
+            bnd -= dt * tab.be[j] * b
+        for j, (a, b) in enumerate(fhdg):
+            itf -= dt * tab.bi[j] * a
+            bnd -= dt * tab.bi[j] * b
+        self.ledger.append({"interface": itf, "boundary": bnd})
 
     def run(self, steps=None):
         for _ in range(self.wl.steps if steps is None else steps):

@@ -93,12 +93,17 @@ class _Subset:
         self.fjac = geo.fjac[idx]
 
 
-def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas, elems=None):
+def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas, elems=None, faces=None):
     """R^DG on explicit elements (zero rows on implicit elements).
 
     U:     (E, 4, nn) all elements; implicit entries are the implicit stage state y^im.
     Qmix:  (E, 5, nn) mixed variables of implicit elements (HDG-MX coupling) or None.
     elems: optional subset of element indices; the result then has one row per entry.
+    faces: optional dict; if given, faces[f] receives (s, w) for local face f: the part of
+           the face integrand tested against V itself (numerical flux, consistency and
+           penalty terms; (4, n_sel, Qf)) and the face quadrature weights (n_sel, Qf), so that
+           the face's flux through it is sum_q w s (the adjoint term, tested against grad V,
+           integrates to zero against a constant).
     """
     geo_all = Geometry(mesh, basis)
     sel = np.arange(mesh.E) if elems is None else np.asarray(elems)
@@ -161,6 +166,8 @@ def dg_residual(U, Qmix, wl, mesh: Mesh, basis: Basis, gas: ph.Gas, elems=None):
             adj_far = -Kf
             s = s + np.where(farfield[None, :, None], cons_far + pen_far, cons + pen)
             g = np.where(farfield[None, None, :, None], adj_far, adj)
+        if faces is not None:
+            faces[f] = (s, basis.qw[None, :] * geo.fjac[:, f][:, None])
         R += test_face(s, g, f, basis, geo)
     R[implicit_sel] = 0.0
     return R

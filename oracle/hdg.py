@@ -67,11 +67,13 @@ class StageData:
         self.rhs = rhs            # (B, 4, nn)
 
 
-def local_residual(U, Q, Uh, sd: StageData, wl, basis: Basis, bg: BatchGeometry, gas: ph.Gas):
+def local_residual(U, Q, Uh, sd: StageData, wl, basis: Basis, bg: BatchGeometry, gas: ph.Gas, faces=None):
     """Element-local stage residual.
 
     U (B, 4, nn), Q (B, 5, nn) or None, Uh (B, 4 faces, 4, k+1).
     Returns f (B, 4, nn), g (B, 5, nn) or None, h (B, 4 faces, 4, k+1), Rh (B, 4, nn).
+    faces: optional dict; faces[f] receives (s, w), the part of R^HDG's face-f integrand
+    tested against V itself ((4, B, Qf)) and the face quadrature weights ((B, Qf)).
     """
     k = basis.k
     mx = wl.hdg_variant == HDG_MX and wl.viscous
@@ -124,6 +126,8 @@ def local_residual(U, Q, Uh, sd: StageData, wl, basis: Basis, bg: BatchGeometry,
                 s = Fc + visc_s
                 g = -Kj
                 t_int = -Fc + ph.normal_flux(Kg, n) - tq * ph.normal_flux(Kj, n)
+        if faces is not None:
+            faces[f] = (s, basis.qw[None, :] * bg.fjac[:, f][:, None])
         Rh = Rh + test_face(s, g, f, basis, bg)
         # facet rows
         Uex = np.moveaxis(sd.uex_fq[:, f], 0, 1)                 # (4, B, Qf)
@@ -255,9 +259,9 @@ class HDGSystem:
         Uh = zl[:, o:].reshape(B, 4, 4, k1)
         return U, Q, Uh
 
-    def local_out(self, zl, sd):
+    def local_out(self, zl, sd, faces=None):
         U, Q, Uh = self.split_local(zl)
-        f, g, h, Rh = local_residual(U, Q, Uh, sd, self.wl, self.basis, self.bg, self.gas)
+        f, g, h, Rh = local_residual(U, Q, Uh, sd, self.wl, self.basis, self.bg, self.gas, faces=faces)
         parts = [f.reshape(self.B, -1)]
         if self.mx:
             parts.append(g.reshape(self.B, -1))
@@ -276,6 +280,24 @@ class HDGSystem:
                 vals, _ = face_eval(U_all, OPPOSITE[f], basis, self.geo)       # (4, E, Qf)
                 uex[itf, f] = np.moveaxis(vals[:, nb[itf]], 0, 1)
         return StageData(self.kind, uex, dt_a, rhs_im)
+
+    def face_fluxes(self, U_all, Q_all, Uhat, sd):
+        """Flux of R^HDG out of the implicit region through its interface faces and through
+        its physical boundary faces (far field and walls): two (4,) vectors, each the sum
+        over those faces of int_F s . 1 ds with s the face integrand tested against V (the
+        element rows tested with V = 1 sum to these face integrals: the volume term and the
+        adjoint term, tested against grad V, vanish)."""
+        z = self.pack(U_all, Q_all, Uhat)
+        faces = {}
+        self.local_out(z[self.locmap], sd, faces=faces)
+        itf = np.zeros(4)
+        bnd = np.zeros(4)
+        for f in range(4):
+            s, w = faces[f]
+            flux = np.einsum("vbq,bq->bv", s, w)
+            itf += flux[self.kind[:, f] == KIND_INTERFACE].sum(axis=0)
+            bnd += flux[(self.kind[:, f] == KIND_FARFIELD) | (self.kind[:, f] == KIND_WALL)].sum(axis=0)
+        return itf, bnd
 
     # -- residual and Jacobian ---------------------------------------------
     def residual(self, z, sd):
@@ -354,7 +376,7 @@ def init_mixed(U_all, Uhat, system: HDGSystem):
     Rtilde is affine in Q: Rtilde(Q) = Rtilde(0) + A Q, with A probed column by column."""
     nn = system.basis.nn
     Q_all = np.zeros((U_all.shape[0], 5, nn))
-    if not system.mx:
+    if not system.mx or system.B == 0:
         return Q_all
     z = system.pack(U_all, Q_all, Uhat)
     U, Q, Uh = system.split_local(z[system.locmap])

@@ -349,15 +349,27 @@ imex_status imex_create_batch(int n_inst, const imex_mesh_desc* meshes, const do
 imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   if (!c || !flag) return fail(c, IMEX_EINVAL, "null argument");
   const int E = c->E;
+  // validate before anything in the context changes
+  for (int e = 0; e < E; ++e)
+    if (!flag[e])
+      for (int f = 0; f < 4; ++f)
+        if (c->nbr[4 * e + f] < 0 && c->bcf[4 * e + f] == IMEX_BC_WALL)
+          return fail(c, IMEX_EINVAL, "adiabatic walls are supported on implicit elements only");
+  // the workspaces below are freed and reallocated: finish queued work and drop every
+  // captured graph (their kernel arguments point into the old workspaces).  The context
+  // counts as unconfigured until the new regions are complete.
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->drop_graphs();
+  c->regions_set = false;
+  c->prec_valid = false;
+  c->prec_fresh = false;
+  c->newton_q2 = 0.0;
+  for (int& g : c->gm_hist) g = 0;
   c->imp.assign(flag, flag + E);
   for (int e = 0; e < E; ++e) c->imp[e] = c->imp[e] ? 1 : 0;
   c->im_list.clear();
   c->ex_list.clear();
   for (int e = 0; e < E; ++e) (c->imp[e] ? c->im_list : c->ex_list).push_back(e);
-  for (int e : c->ex_list)
-    for (int f = 0; f < 4; ++f)
-      if (c->nbr[4 * e + f] < 0 && c->bcf[4 * e + f] == IMEX_BC_WALL)
-        return fail(c, IMEX_EINVAL, "adiabatic walls are supported on implicit elements only");
   c->n_im = (int)c->im_list.size();
   c->n_ex = (int)c->ex_list.size();
   std::vector<int> im_pos(E, -1);
@@ -688,6 +700,30 @@ imex_status imex_local_system(imex_ctx* c, double dt_a, const double* rhs, const
 
 }  // extern "C"
 
+// Checks an ARK pair before any work: s in 1..3, a strictly lower triangular explicit
+// tableau, and the fsal / stiffly_accurate flags equal to what the coefficients say
+// (fsal: be is the last row of Ae; stiffly accurate: bi is the last row of Ai; Sec. 4.2.2).
+// Implicit tableaux that are not stiffly accurate are not implemented with an implicit
+// region (the final implicit update would need R^HDG of every stage at U_{n+1}).
+static imex_status check_tableau(imex_ctx* c, const imex_tableau* tab, double dt) {
+  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  const int s = tab->s;
+  for (int i = 0; i <= s; ++i)
+    for (int j = i; j <= s; ++j)
+      if (tab->Ae[4 * i + j] != 0.0) return fail(c, IMEX_EINVAL, "explicit tableau not strictly lower triangular");
+  for (int i = 0; i < s; ++i)
+    for (int j = i + 1; j < s; ++j)
+      if (tab->Ai[3 * i + j] != 0.0) return fail(c, IMEX_EINVAL, "implicit tableau not lower triangular");
+  bool fsal = true, sa = true;
+  for (int j = 0; j <= s; ++j) fsal = fsal && tab->be[j] == tab->Ae[4 * s + j];
+  for (int j = 0; j < s; ++j) sa = sa && tab->bi[j] == tab->Ai[3 * (s - 1) + j];
+  if ((tab->fsal != 0) != fsal) return fail(c, IMEX_EINVAL, "fsal flag disagrees with be and the last row of Ae");
+  if ((tab->stiffly_accurate != 0) != sa)
+    return fail(c, IMEX_EINVAL, "stiffly_accurate flag disagrees with bi and the last row of Ai");
+  if (c->n_im > 0 && !sa) return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
+  return IMEX_OK;
+}
+
 // Stage data recorded by a step for its reverse mode: Ydg[i] = state entering the
 // explicit residual of stage i+1 (Ydg[s]: the final residual, not FSAL); Ysol[i],
 // Hsol[i] = stage state and facet state after the implicit solve of stage i+1.
@@ -712,8 +748,8 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
                                  imex_stats* st, const ArkTape* tape) {
   if (!c || !tab || !U) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
-  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
   if (c->n_im > 0 && !Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
+  if (imex_status ts = check_tableau(c, tab, dt); ts != IMEX_OK) return ts;
   if (st) std::memset(st, 0, sizeof(*st));
   Workspace& w = c->ws;
   const int s = tab->s;
@@ -804,8 +840,6 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
     if (se != IMEX_OK) return se;
   }
   HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
-  if (c->n_im > 0 && !tab->stiffly_accurate)
-    return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
   HIP_TRY(c, hipStreamSynchronize(hs));
   c->timers_resolve();
   return IMEX_OK;
@@ -900,7 +934,7 @@ imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, c
                               const double* Ubar_next, double* Ubar) {
   if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
-  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  if (imex_status ts = check_tableau(c, tab, dt); ts != IMEX_OK) return ts;
   if (c->n_im > 0) return fail(c, IMEX_ENOTIMPL, "step adjoint with an implicit region");
   HIP_TRY(c, vjp_alloc(c));
   Workspace& w = c->ws;
@@ -958,7 +992,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
                                const double* duinf, double* pbar, imex_stats* st) {
   if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
-  if (tab->s < 1 || tab->s > 3 || !(dt > 0.0)) return fail(c, IMEX_EINVAL, "tableau stages or dt");
+  if (imex_status ts = check_tableau(c, tab, dt); ts != IMEX_OK) return ts;
   const bool want_p = duinf && pbar;
   if (want_p) *pbar = 0.0;
   if (c->n_im == 0) {
@@ -966,7 +1000,6 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
     return imex_vjp_ark_step(c, tab, dt, U, Ubar_next, Ubar);
   }
   if (!Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an implicit region");
-  if (!tab->stiffly_accurate) return fail(c, IMEX_ENOTIMPL, "implicit tableaux that are not stiffly accurate");
   const bool mx = mx_coupled(c);
   if (st) std::memset(st, 0, sizeof(*st));
   HIP_TRY(c, vjp_alloc(c));

@@ -2650,8 +2650,9 @@ __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const T* 
     const double du = -acc;
     const double un = U[(size_t)e * NU + i] + du;
     U[(size_t)e * NU + i] = un;
-    mdu = fmax(mdu, fabs(du));
-    mu = fmax(mu, fabs(un));
+    // non-finite values count as infinite (fmax would drop a NaN): the host reports them
+    mdu = fmax(mdu, isfinite(du) ? fabs(du) : INFINITY);
+    mu = fmax(mu, isfinite(un) ? fabs(un) : INFINITY);
   }
   rd[0][tid] = mdu;
   rd[1][tid] = mu;
@@ -2672,8 +2673,8 @@ __global__ void __launch_bounds__(256) facet_update_kernel(int n, const double* 
   for (int i = blockIdx.x * blockDim.x + tid; i < n; i += gridDim.x * blockDim.x) {
     const double xn = x[i] + d[i];
     x[i] = xn;
-    md = fmax(md, fabs(d[i]));
-    mx = fmax(mx, fabs(xn));
+    md = fmax(md, isfinite(d[i]) ? fabs(d[i]) : INFINITY);
+    mx = fmax(mx, isfinite(xn) ? fabs(xn) : INFINITY);
   }
   rd[0][tid] = md;
   rd[1][tid] = mx;
@@ -3350,7 +3351,10 @@ static int gm_predict(const std::vector<double>& res, double tol) {
   return (int)std::min<double>(GM_CHECK, std::max(1.0, need));
 }
 
-static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, int kind) {
+// Right-preconditioned restarted GMRES on the condensed facet system.  *reached says
+// whether the relative residual estimate fell below gmres_rtol (false when gmres_maxit
+// iterations ran out first); a non-finite residual returns IMEX_ENONFINITE.
+static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, int kind, bool* reached) {
   Workspace& w = c->ws;
   const int n = c->n_hf * 4 * c->NP;
   const int m = std::min(c->opt.gmres_restart, GM_MAXM);
@@ -3367,6 +3371,7 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
   double tol = -1.0;
   int total = 0;
   *its_out = 0;
+  *reached = false;
   // block lengths never exceed GM_CHECK: the graph keys below rely on it
   const int hist = c->gm_hist[kind];
   int want = hist > 1 ? std::min(hist - 1, GM_CHECK) : GM_FIRST;
@@ -3407,11 +3412,19 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
       HTRY(hipStreamSynchronize(c->stream));
       if (j == 0) {
         const double beta = hb[GM_CHECK];
+        if (!std::isfinite(beta)) {
+          c->err = "non-finite facet residual";
+          return IMEX_ENONFINITE;
+        }
         if (tol < 0.0) tol = c->opt.gmres_rtol * beta;
         if (!(beta > tol)) { small = true; break; }
         res.assign(1, beta);
       }
       for (int jj = j; jj < j1; ++jj) {
+        if (!std::isfinite(hb[jj - j])) {
+          c->err = "non-finite GMRES residual estimate";
+          return IMEX_ENONFINITE;
+        }
         res.push_back(hb[jj - j]);
         if (!(hb[jj - j] > tol)) { jdone = jj; break; }
       }
@@ -3419,7 +3432,7 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
       j = (jdone >= 0) ? jdone + 1 : j1;
       want = gm_predict(res, tol);
     }
-    if (small) break;
+    if (small) { *reached = true; break; }
     const int k = j;
     if (k == 0) break;
     hipLaunchKernelGGL(gm_lsq_kernel, dim3(1), dim3(64), 0, c->stream, k, st, yd);
@@ -3427,7 +3440,8 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
     HTRY(launch_precond(c, r, z));
     hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, c->stream, n, 1.0, z, x);
     HTRY(hipGetLastError());
-    if (jdone >= 0 || total >= c->opt.gmres_maxit) break;
+    if (jdone >= 0) { *reached = true; break; }
+    if (total >= c->opt.gmres_maxit) break;
     // true residual for the next cycle: r = b - S x
     HTRY(launch_apply(c, x, r));
     hipLaunchKernelGGL(rsub_kernel, dim3(nb), dim3(256), 0, c->stream, n, b, r);
@@ -3472,6 +3486,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   double q2 = 0.0;                          // contraction of the second correction
   double dz_prev = 1.0;                     // relative size of the last correction
   const int need_full = c->opt.newton_simplified == 2 ? 1 : 2;
+  int gm_capped = 0;                        // corrections whose facet solve hit gmres_maxit
   if (c->prec_valid && std::fabs(dt_a / c->prec_dt_a - 1.0) > 0.25) c->prec_valid = false;
   for (int it = 1; it <= c->opt.newton_maxit; ++it) {
     newton = it;
@@ -3499,6 +3514,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     }
     c->timer_end(tt);
     int its = 0;
+    bool gm_reached = false;
     // forcing term: loose facet solves while the Newton corrections are large.  A
     // simplified correction needs only a few digits: it certifies convergence through its
     // size relative to the previous correction, and its own error (1e-4 of an increment
@@ -3511,7 +3527,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
       c->opt.gmres_rtol = std::max(rtol, std::min(FIRST_CORRECTION_RTOL, 1e-2 * c->newton_q2));
     if (simplified) c->opt.gmres_rtol = std::max(c->opt.gmres_rtol, SIMPLIFIED_GMRES_RTOL);
     tt = c->timer_begin(TM_GMRES);
-    imex_status s = gmres(c, b, dx, &its, simplified ? 0 : std::min(it, 4));
+    imex_status s = gmres(c, b, dx, &its, simplified ? 0 : std::min(it, 4), &gm_reached);
     c->timer_end(tt);
     c->opt.gmres_rtol = rtol;
     if (s != IMEX_OK) return s;
@@ -3549,6 +3565,15 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     dz_prev = std::fmax(last, hh > 0.0 ? dh / hh : dh);
     if (st && st->n_hist < (int)(sizeof(st->du_hist) / sizeof(double))) st->du_hist[st->n_hist++] = dz_prev;
     const double tu = c->opt.newton_rtol * uu, th = c->opt.newton_rtol * hh;
+    // a correction whose facet solve stopped at gmres_maxit short of its tolerance
+    // certifies nothing (a stalled solve gives a small increment): iterate on
+    if (!gm_reached) {
+      ++gm_capped;
+      q_last = SIMPLIFIED_QMAX;             // the next correction assembles a Jacobian
+      du_prev = 0.0;
+      dh_prev = 0.0;
+      continue;
+    }
     if (du <= tu && dh <= th) { converged = true; break; }
     if (it >= 2 && du_prev > 0.0 && dh_prev > 0.0) {
       const double qu = du / du_prev, qh = dh / dh_prev;
@@ -3579,6 +3604,7 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
   HTRY(hipStreamSynchronize(c->stream));
   if (!converged) {
     c->err = "Newton did not converge within newton_maxit";
+    if (gm_capped) c->err += " (" + std::to_string(gm_capped) + " facet solves stopped at gmres_maxit)";
     return IMEX_ENOCONV;
   }
   return IMEX_OK;
@@ -3635,10 +3661,15 @@ imex_status hdg_stage_adjoint(imex_ctx* c, double dt_a, const double* Y, const d
   const double rtol = c->opt.gmres_rtol;
   c->opt.gmres_rtol = std::min(rtol, 1e-12);
   int its = 0;
-  imex_status st = gmres(c, b, lh, &its, 5);
+  bool reached = false;
+  imex_status st = gmres(c, b, lh, &its, 5, &reached);
   c->opt.gmres_rtol = rtol;
   c->adj_mode = false;
   if (st != IMEX_OK) return st;
+  if (!reached) {
+    c->err = "transposed facet solve stopped at gmres_maxit short of its tolerance";
+    return IMEX_ENOCONV;
+  }
   if (gmres_its) *gmres_its = its;
   HDG_DISPATCH_ST(c->K, LA_DISPATCH(c, {
     hipLaunchKernelGGL((backsubT_kernel<KK, LT>), dim3(c->n_im), dim3(128), 0, c->stream, c->dhdg(), blk_stride(c),

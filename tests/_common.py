@@ -51,7 +51,16 @@ def smooth_square(n=4, k=2, viscous=True, mu=0.02, variant=W.HDG_IP, implicit_ro
 
 
 def rel_err(a, b):
+    """Largest relative error of a against b.  States laid out [element or facet][field][node]
+    (3D arrays with the four conservative fields on axis 1) are compared field by field, each
+    field relative to its own largest magnitude, and the worst field is returned, so a small
+    field (rho v near a wall) is held to the same relative bar as rho E.  Other arrays (element
+    blocks, flat vectors) are compared relative to their largest magnitude."""
     a = np.asarray(a)
     b = np.asarray(b)
+    if a.ndim == 3 and a.shape[1] == 4:
+        return max(rel_err(a[:, v], b[:, v]) for v in range(4))
+    if a.size == 0:
+        return 0.0
     scale = np.maximum(np.abs(b).max(), 1e-300)
     return float(np.abs(a - b).max() / scale)

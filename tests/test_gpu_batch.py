@@ -68,11 +68,16 @@ def test_mixed_degree_ensemble_equals_single_and_oracle():
         assert e < 1e-10
     for i in (0, 3):
         ora = IMEXSolver(wls[i])
+        m0 = ora.totals()
         for _ in range(steps):
             ora.step()
         e = rel_err(states[i].cpu().numpy(), ora.U)
         print("oracle", wls[i].name, e)
         assert e < 1e-10
+        # the instance's conserved totals move by the oracle's interface flux-defect ledger
+        drift = ora.totals(states[i].cpu().numpy()) - m0
+        ledger = sum(L["interface"] + L["boundary"] for L in ora.ledger)
+        assert np.all(np.abs(drift - ledger) < 1e-10 * np.abs(m0)), (drift, ledger)
     ens.close()
 
 
@@ -80,7 +85,9 @@ def test_full_ensemble_one_step():
     """The 512-instance ensemble (8x8..48x48, p in 1..4): one step stays finite and the
     conserved totals of every degree group move only by the interface coupling's defect
     (the stage-wise explicit and implicit interface data differ, so the split scheme is
-    not discretely conservative; the bound is the one of the vortex run)."""
+    not discretely conservative).  The defect is the oracle's ledger on the instances it
+    can run (test_mixed_degree_ensemble_equals_single_and_oracle); here its size is
+    bounded: measured at about 1.4e-6 of the group totals per step, bound 1e-5."""
     from paper_2607_16044_amd.binding import Ensemble
     wls = W.vortex_ensemble(512)
     ens = Ensemble(wls)
@@ -90,7 +97,8 @@ def test_full_ensemble_one_step():
     for u, (_, eng), a in zip(U, ens.groups, m0):
         assert torch.isfinite(u).all()
         b = eng.conservation_sums(u)
-        assert np.abs(b - a).max() < 1e-3 * np.abs(a).max()
+        print("group drift", (b - a) / np.abs(a))
+        assert np.all(np.abs(b - a) < 1e-5 * np.abs(a))
     ens.close()
 
 

@@ -85,7 +85,13 @@ def test_stage_solve_parity(case):
     im = ora.mesh.im_elems
     assert rel_err(U.cpu().numpy()[im], ora.U[im]) < 1e-10
     assert rel_err(Uhat.cpu().numpy(), ora.Uhat) < 1e-10
-    assert rel_err(R.cpu().numpy()[im], Rh) < 1e-9
+    # R^HDG at the root is (rhs - M y) / dt_a, a difference of two O(M y) terms: its error
+    # is the states' error times M / dt_a, so it is compared as dt_a R against M y, per
+    # field (the scale at which R enters the later stages' right-hand sides)
+    My = ora.mass_apply(ora.U)[im]
+    for v in range(4):
+        e = np.abs(dt_a * (R.cpu().numpy()[im][:, v] - Rh[:, v])).max() / np.abs(My[:, v]).max()
+        assert e < 1e-10, (v, e)
     assert st["newton_its"] <= its + 2
 
 
@@ -118,7 +124,16 @@ def test_vortex_full_run_parity():
     print("vortex 20 steps rel err", err)
     assert err < 1e-10
     m1 = eng.conservation_sums(U)
-    assert np.all(np.isfinite(m1)) and np.abs(m1 - m0).max() < 1e-3 * np.abs(m0).max()
+    # the split scheme is not discretely conservative: the totals move by the interface
+    # flux defect (the two sides see the interface with different stage data).  The GPU's
+    # drift must equal the oracle's ledger of that defect, which the oracle's own drift
+    # matches to roundoff (tests/test_oracle_ledger.py), per field to 1e-9 of the totals
+    # while the defect itself is about 1e-5 of them
+    ledger = sum(L["interface"] + L["boundary"] for L in ora.ledger)
+    print("drift", m1 - m0, "ledger", ledger)
+    for v in range(4):
+        assert abs((m1[v] - m0[v]) - ledger[v]) < 1e-9 * abs(m0[v]), (v, m1 - m0, ledger)
+    assert np.abs(ledger).max() > 1e-7 * np.abs(m0).max()      # the identity is not trivial
 
 
 @pytest.mark.parametrize("precision", [0, 1])
