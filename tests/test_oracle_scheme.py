@@ -50,13 +50,18 @@ def smooth_ic(X, Y, elem=None, node=None):
 
 def exact_divergence(X, Y, gas, viscous, h=1e-4):
     """div(F^c - F^nu) of the smooth field at (X, Y) by nested central differences."""
+    return exact_divergence_of(smooth_ic, X, Y, gas, viscous, h)
+
+
+def exact_divergence_of(field, X, Y, gas, viscous=True, h=1e-4):
+    """div(F^c - F^nu) of a smooth field(x, y) -> (4, ...) by nested central differences."""
     def grad_U(x, y):
-        gx = (smooth_ic(x + h, y) - smooth_ic(x - h, y)) / (2 * h)
-        gy = (smooth_ic(x, y + h) - smooth_ic(x, y - h)) / (2 * h)
+        gx = (field(x + h, y) - field(x - h, y)) / (2 * h)
+        gy = (field(x, y + h) - field(x, y - h)) / (2 * h)
         return np.stack([gx, gy], axis=1)
 
     def flux(x, y):
-        U = smooth_ic(x, y)
+        U = field(x, y)
         F = ph.convective_flux(U, gas)
         if viscous:
             F = F - ph.viscous_flux(U, grad_U(x, y), gas)
