@@ -199,6 +199,23 @@ imex_status imex_vjp_wall_shear(imex_ctx* ctx, const double* U, const double* Uh
  * implicit elements set to zero. */
 imex_status imex_dg_residual(imex_ctx* ctx, const double* U, const double* Uhat, double* R);
 
+/* imex_dg_residual for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same result from
+ * the same kernels, with its scratch (face traces, and the lifted mixed variables of an
+ * HDG-MX region) in a static device array of 96 MiB per device (12 582 912 doubles) that
+ * the library holds until the process ends, instead of the context's workspace.  It
+ * calls no hipMalloc / hipFree and no allocating library routine; R is cleared by a
+ * kernel, not a memset.  Limit: E * 4 * NQ * 8 doubles of face traces (NQ Gauss points
+ * per face) plus, with HDG-MX coupling, E * 5 * (k+1)^2 doubles of mixed variables must
+ * fit in the array (the 256 x 128, k = 4 boundary layer needs 11 436 032); larger meshes
+ * get EINVAL and nothing runs.  Every call on a device shares that device's array, which keeps the
+ * last call's contents: calls that overlap on one device (several contexts or streams)
+ * race and must be serialised by the caller.  U dev (all elements), Uhat dev (required
+ * with an HDG-MX region, else may be NULL), R dev out as imex_dg_residual.
+ * Errors: EINVAL (null argument, Uhat missing, mesh above the limit), ESTATE (regions
+ * not set), EDEVICE (the array's device address could not be resolved). */
+imex_status imex_dg_residual_noalloc(imex_ctx* ctx, const double* U, const double* Uhat, double* R);
+
 /* One SDIRK stage of the implicit region (eqs. dirk_stage_update_solution /
  * _facet / _mixed) solved by Newton (Sec. 4.3) with static condensation
  * (eqs. statically_condensed_system, SchurCompliment, local_solve_static_condensation)

@@ -25,7 +25,8 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
-           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets", "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes",
+           "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
+           "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes", "imex_dg_residual_noalloc",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_node_coords.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.imex_init_facets.argtypes = [P, P, P]
     lib.imex_dg_residual.argtypes = [P, P, P, P]
+    lib.imex_dg_residual_noalloc.argtypes = [P, P, P, P]
     lib.imex_implicit_stage_solve.argtypes = [P, D, P, P, P, P, ctypes.POINTER(Stats)]
     lib.imex_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, ctypes.POINTER(Stats)]
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
@@ -239,6 +241,11 @@ class Engine:
     def dg_residual(self, U: torch.Tensor, Uhat: Optional[torch.Tensor] = None) -> torch.Tensor:
         R = torch.empty_like(U)
         self._check(self.lib.imex_dg_residual(self.ctx, _ptr(U), _ptr(Uhat), _ptr(R)))
+        return R
+
+    def dg_residual_noalloc(self, U: torch.Tensor, Uhat: Optional[torch.Tensor], R: torch.Tensor) -> torch.Tensor:
+        """R^DG into the caller's R through the allocation-free entry point (static scratch)."""
+        self._check(self.lib.imex_dg_residual_noalloc(self.ctx, _ptr(U), _ptr(Uhat), _ptr(R)))
         return R
 
     def implicit_stage_solve(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):

@@ -243,6 +243,9 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
   imex_ctx* c = new (std::nothrow) imex_ctx();
   if (!c) return fail(nullptr, IMEX_ENOMEM, "host allocation");
   hipGetDevice(&c->device);
+  // the static scratch of imex_dg_residual_noalloc: its device address, once per device
+  // (a failure here is reported by that entry point, which cannot run without it)
+  static_scratch_init(c->device);
   c->stream = static_cast<hipStream_t>(stream);
   c->E = (int)Etot;
   c->K = meshes[0].degree;
@@ -678,6 +681,27 @@ imex_status imex_dg_residual(imex_ctx* c, const double* U, const double* Uhat, d
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   imex_status st = dg_residual_async(c, U, Uhat, R);
   if (st != IMEX_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
+imex_status imex_dg_residual_noalloc(imex_ctx* c, const double* U, const double* Uhat, double* R) {
+  if (!c || !U || !R) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
+  const bool mx = c->opt.hdg_variant == IMEX_HDG_MX && c->gas.viscous && c->n_im > 0;
+  if (mx && !Uhat) return fail(c, IMEX_EINVAL, "Uhat required with an HDG-MX region");
+  const size_t n_trace = (size_t)c->E * 4 * c->NQ * 8, n_q = mx ? (size_t)c->E * 5 * c->NN : 0;
+  if (n_trace + n_q > STATIC_SCRATCH_DOUBLES)
+    return fail(c, IMEX_EINVAL, "mesh too large for the static scratch (" + std::to_string(n_trace + n_q) +
+                                    " > " + std::to_string(STATIC_SCRATCH_DOUBLES) + " doubles)");
+  double* base = static_scratch(c->device);
+  if (!base) return fail(c, IMEX_EDEVICE, "static scratch address not resolved on this device");
+  double* trace = base;
+  double* Q = base + n_trace;
+  if (mx) HIP_TRY(c, launch_lift_mixed(c, U, Uhat, Q));
+  HIP_TRY(c, launch_dg_trace(c, U, mx ? Q : nullptr, trace));
+  HIP_TRY(c, launch_fill_zero(c, R, (size_t)c->E * 4 * c->NN));
+  HIP_TRY(c, launch_dg_residual(c, U, trace, R));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return IMEX_OK;
 }

@@ -182,6 +182,12 @@ enum TimerTag { TM_DG = 0, TM_ASSEMBLE = 1, TM_ELIMINATE = 2, TM_CONDENSE = 3, T
 
 // kernel launchers (dg.hip)
 namespace imex {
+// static device scratch of imex_dg_residual_noalloc: 96 MiB per device
+constexpr size_t STATIC_SCRATCH_DOUBLES = (size_t)96 << 17;
+constexpr int MAX_DEVICES = 64;
+hipError_t static_scratch_init(int device);   // resolve the device address (device current)
+double* static_scratch(int device);           // that address, or null before a successful init
+hipError_t launch_fill_zero(const imex_ctx* c, double* x, size_t n);
 hipError_t launch_dg_trace(const imex_ctx* c, const double* U, const double* Q, double* trace);
 hipError_t launch_dg_residual(const imex_ctx* c, const double* U, const double* trace, double* R);
 hipError_t launch_erk_combine(const imex_ctx* c, const double* Un, int nterms, const double* const* R,

@@ -12,10 +12,58 @@
 //     threads evaluate the volume fluxes at the volume Gauss points and the
 //     numerical / interior-penalty face fluxes at the face points, then each
 //     thread contracts them with the test functions of one node.
+#include <mutex>
+
 #include "ctx.h"
 #include "dg_face.h"
 
 namespace imex {
+
+// ---------------------------------------------------------------------------
+// Static device scratch of imex_dg_residual_noalloc (face traces and lifted mixed
+// variables), for callers that cannot allocate.  One copy per device, resolved to a
+// device address once per device with hipGetSymbolAddress; host code uses only that
+// address, never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;      // the device must be current
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* static_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+__global__ void fill_zero_kernel(size_t n, double* __restrict__ x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(const imex_ctx* c, double* x, size_t n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, x);
+  return hipGetLastError();
+}
 
 // Trace of a nodal field (nv components, stride NN) and of its reference
 // derivatives at Gauss point q of local face f.
