@@ -375,6 +375,10 @@ imex_status imex_set_regions(imex_ctx* c, const unsigned char* flag) {
   for (int e = 0; e < E; ++e) (c->imp[e] ? c->im_list : c->ex_list).push_back(e);
   c->n_im = (int)c->im_list.size();
   c->n_ex = (int)c->ex_list.size();
+  c->dg_farfield = false;
+  for (int e : c->ex_list)
+    for (int f = 0; f < 4; ++f)
+      if (c->nbr[4 * e + f] < 0 && c->bcf[4 * e + f] == IMEX_BC_FARFIELD) c->dg_farfield = true;
   std::vector<int> im_pos(E, -1);
   for (int p = 0; p < c->n_im; ++p) im_pos[c->im_list[p]] = p;
   // HDG facets of each instance: vertical (x = x_i) then horizontal (y = y_j), keeping those

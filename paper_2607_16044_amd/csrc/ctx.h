@@ -119,6 +119,7 @@ struct imex_ctx {
   std::vector<int> win_off, win_slot, win_own, sr_flags;
   int n_win = 0, n_superrows = 0;
   int n_im = 0, n_ex = 0, n_hf = 0;
+  bool dg_farfield = false;     // some explicit element has a far-field boundary face
   bool regions_set = false;
   // launch shapes (0 = built-in default), chosen by imex_autotune
   int dg_tile = 0;              // explicit elements per workgroup of the residual kernel

@@ -114,70 +114,177 @@ __device__ inline void face_trace(const BasisTable& T, int f, int q, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// 1. face traces: T[e][f][q][0..3] = U, [4..7] = F^nu(U, grad U) . n_e
+// 1. face traces: T[e][f][q][0..3] = U, and for viscous flows [4..7] = F^nu(U, grad U) . n_e
+//    (on far-field faces F^nu(U_inf, grad U) . n_e); records of 8 doubles, 4 when inviscid
+//    A workgroup stages a tile of TE consecutive elements (their U, and Q of HDG-MX
+//    elements) in LDS with coalesced loads; one thread per face point, and consecutive
+//    threads write consecutive 64-byte point records.
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K> struct TraceTile {
+  static constexpr int NQ = (3 * K + 2) / 2;
+  static constexpr int TE = 256 / (4 * NQ);       // elements per workgroup: about 256 face points
+};
+
+template <int K, bool VISC>
 __global__ void __launch_bounds__(256) dg_trace_kernel(DeviceMesh m, Gas g, int mx, const double* __restrict__ U,
                                                        const double* __restrict__ Q, double* __restrict__ T) {
-  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.E * 4 * NQ) return;
-  const int q = t % NQ;
-  const int f = (t / NQ) % 4;
-  const int e = t / (4 * NQ);
-  const BasisTable& tb = *m.tab;
-  double val[4], dxi[4], deta[4];
-  face_trace<K, 4>(tb, f, q, U + (size_t)e * 4 * NN, val, dxi, deta);
-  double* out = T + (size_t)t * 8;
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, TE = TraceTile<K>::TE;
+  constexpr int NEV = VISC ? 2 : 1;                 // end values, and end derivatives for gradients
+  constexpr int RS = VISC ? 8 : 4;                  // doubles per point record
+  __shared__ double sU[TE * 4 * NN];
+  __shared__ double sOut[TE * 4 * NQ * RS];         // records, staged for coalesced stores
+  __shared__ double sQ[VISC ? TE * 5 * NN : 1];
+  __shared__ double sE[TE][4][NEV][4][NP];          // U and dU across face f at its end, per line m
+  __shared__ double sEQ[VISC ? TE : 1][4][5][NP];   // mixed variables at the face end (HDG-MX)
+  __shared__ BasisTable tb;
+  const int tid = threadIdx.x;
+  const int base = blockIdx.x * TE;
+  const int ne = min(TE, m.E - base);
+  for (int i = tid; i < (int)(sizeof(BasisTable) / sizeof(double)); i += blockDim.x)
+    reinterpret_cast<double*>(&tb)[i] = reinterpret_cast<const double*>(m.tab)[i];
+  for (int i = tid; i < ne * 4 * NN; i += blockDim.x) sU[i] = U[(size_t)base * 4 * NN + i];
+  if (VISC && mx)
+    for (int i = tid; i < ne * 5 * NN; i += blockDim.x) {
+      const int e = base + i / (5 * NN);
+      sQ[i] = m.imp[e] ? Q[(size_t)base * 5 * NN + i] : 0.0;
+    }
+  __syncthreads();
+  // phase 1: contraction across each face to its end (x-faces: over a at fixed b = m;
+  // y-faces: over b at fixed a = m)
+  for (int i = tid; i < ne * 4 * 4 * NP; i += blockDim.x) {
+    const int mm = i % NP, v = (i / NP) % 4, f = (i / (4 * NP)) % 4, el = i / (16 * NP);
+    const int s = f & 1;
+    const double* u = sU + el * 4 * NN + v * NN;
+    double e0 = 0.0, e1 = 0.0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) out[v] = val[v];
-  if (!g.viscous) return;
-  double nx, ny;
-  face_normal(f, nx, ny);
-  double F[4][2];
-  if (mx && m.imp[e]) {
-    double qv[5], qx[5], qy[5];
-    face_trace<K, 5>(tb, f, q, Q + (size_t)e * 5 * NN, qv, qx, qy);
-    visc_flux_mx(val, qv, qv + 3, g, F);
-  } else {
-    const double sx = 2.0 / m.hx[e], sy = 2.0 / m.hy[e];
-    double G[4][2];
+    for (int j = 0; j < NP; ++j) {
+      const double x = (f < 2) ? u[j + NP * mm] : u[mm + NP * j];
+      e0 += tb.LE[s][j] * x;
+      if (VISC) e1 += tb.DE[s][j] * x;
+    }
+    sE[el][f][0][v][mm] = e0;
+    if (VISC) sE[el][f][NEV - 1][v][mm] = e1;
+  }
+  if (VISC && mx)
+    for (int i = tid; i < ne * 4 * 5 * NP; i += blockDim.x) {
+      const int mm = i % NP, c = (i / NP) % 5, f = (i / (5 * NP)) % 4, el = i / (20 * NP);
+      if (!m.imp[base + el]) continue;
+      const int s = f & 1;
+      const double* u = sQ + el * 5 * NN + c * NN;
+      double e0 = 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { G[v][0] = dxi[v] * sx; G[v][1] = deta[v] * sy; }
-    visc_flux(val, G, g, F);
+      for (int j = 0; j < NP; ++j) e0 += tb.LE[s][j] * ((f < 2) ? u[j + NP * mm] : u[mm + NP * j]);
+      sEQ[el][f][c][mm] = e0;
+    }
+  __syncthreads();
+  // phase 2: one thread per face point, along the face
+  if (tid < ne * 4 * NQ) {
+  const int q = tid % NQ;
+  const int f = (tid / NQ) % 4;
+  const int el = tid / (4 * NQ);
+  const int e = base + el;
+  double val[4], dn[4], dt[4];                      // value, derivative across and along the face
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < NP; ++mm) {
+      const double e0 = sE[el][f][0][v][mm];
+      a0 += tb.L[q][mm] * e0;
+      if (VISC) {
+        a1 += tb.L[q][mm] * sE[el][f][NEV - 1][v][mm];
+        a2 += tb.D[q][mm] * e0;
+      }
+    }
+    val[v] = a0;
+    dn[v] = a1;
+    dt[v] = a2;
+  }
+  double out[8];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { out[v] = val[v]; out[4 + v] = 0.0; }
+  if (VISC) {
+    double nx, ny;
+    face_normal(f, nx, ny);
+    if (mx && m.imp[e]) {
+      double qv[5], F[4][2];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double a0 = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < NP; ++mm) a0 += tb.L[q][mm] * sEQ[el][f][c][mm];
+        qv[c] = a0;
+      }
+      visc_flux_mx(val, qv, qv + 3, g, F);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[4 + v] = F[v][0] * nx + F[v][1] * ny;
+    } else {
+      const double sx = 2.0 / m.hx[e], sy = 2.0 / m.hy[e];
+      double G[4][2];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        G[v][0] = ((f < 2) ? dn[v] : dt[v]) * sx;
+        G[v][1] = ((f < 2) ? dt[v] : dn[v]) * sy;
+      }
+      // boundary faces carry the far-field consistency flux K(U_inf) grad U . n
+      const int far = m.nbr[e * 4 + f] < 0 && m.bcf[e * 4 + f] == IMEX_BC_FARFIELD;
+      dg_face_visc_n(far, val, G, nx, ny, g, out + 4);
+    }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) out[4 + v] = F[v][0] * nx + F[v][1] * ny;
+  for (int v = 0; v < RS; ++v) sOut[tid * RS + v] = out[v];
+  }
+  __syncthreads();
+  // the tile's records are contiguous in T: consecutive threads store consecutive doubles
+  double* o = T + (size_t)base * 4 * NQ * RS;
+  for (int i = tid; i < ne * 4 * NQ * RS; i += blockDim.x) o[i] = sOut[i];
 }
 
 // ---------------------------------------------------------------------------
-// 2. residual on a tile of ET explicit elements
+// 2. residual on a tile of ET explicit elements, sum-factorised
+//    (eq. bilinear_form_interior_sdg tested with phi_n = l_a(xi) l_b(eta)):
+//    P1  x-interpolation:  T0[v][b][i] = sum_a l_a(z_i) u[v][a,b],  T1 with l_a'
+//    P2  volume points (i, j): u, du/dxi, du/deta from T0, T1 along y; fluxes F^nu - F^c
+//        weighted by the rule; face points: traces, the neighbour's record, the face
+//        integrand (numerical flux, consistency, penalty; adjoint coefficient)
+//    P3  y-contraction of the volume coefficients, A[v][b][i] = sum_j l_b(z_j) Fx[j,i],
+//        B[v][b][i] = sum_j l_b'(z_j) Fy[j,i], and the face line sums (each face's
+//        points contracted with the 1D basis along the face)
+//    P4  x-contraction: r[v][a,b] = sum_i (l_a'(z_i) A[b][i] + l_a(z_i) B[b][i]) plus the
+//        face line sums times the end values l(+-1), l'(+-1) across the face
 // ---------------------------------------------------------------------------
 struct DGParams {
   int lf;            // Lax-Friedrichs instead of Vijayasundaram
   double alpha;      // IP penalty factor
 };
 
-// Elements per workgroup: the default fills about 256 volume points; other tiles
-// are offered to the autotuner (imex_autotune) when their LDS fits in 64 KB.
 template <int K> struct DGTile {
   static constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NQV = NQ * NQ;
-  static constexpr int ET0 = (256 / NQV) > 0 ? (256 / NQV) : 1;
-  static constexpr int ET = ET0 > 32 ? 32 : ET0;
-  static constexpr size_t lds(int et) { return 8 * (size_t)et * (4 * NN + NQV * 8 + 4 * NQ * 12) + 2048; }
+  // LDS doubles per element: U; x-interpolants (reused for the y-contraction); weighted
+  // volume fluxes (x, y); face coefficients (s, d/dxi, d/deta); face line sums (2 per face)
+  static constexpr int PER_EL = 4 * NN + 2 * 4 * NP * NQ + 2 * 4 * NQV + 4 * 3 * 4 * NQ + 4 * 2 * 4 * NP;
+  static constexpr size_t lds(int et) { return 8 * ((size_t)et * PER_EL + sizeof(BasisTable) / 8) + 256; }
+  // default: the largest power of two up to 32 whose tile stays within 48 KB
+  static constexpr int ET = lds(32) <= 49152 ? 32 : lds(16) <= 49152 ? 16 : lds(8) <= 49152 ? 8
+                            : lds(4) <= 49152 ? 4 : 2;
 };
 constexpr int DG_TILES[5] = {2, 4, 8, 16, 32};
 
-template <int K, int ET>
+// MODEL: DGM_GENERAL (runtime gas and flux flags) or DGM_EULER_LF (inviscid, Lax-Friedrichs,
+// no far-field faces: the vortex workloads), which compiles only what that case needs
+enum DGModel { DGM_GENERAL = 0, DGM_EULER_LF = 1 };
+
+template <int K, int ET, int MODEL>
 __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, DGParams prm,
                                                           const int* __restrict__ ex_list, int n_ex,
                                                           const double* __restrict__ U,
                                                           const double* __restrict__ T, double* __restrict__ R) {
   constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP, NQV = NQ * NQ;
-  __shared__ double sU[ET][4 * NN];
-  __shared__ double sF[ET][NQV][8];        // volume coefficients of d/dxi phi (0..3) and d/deta phi (4..7)
-  __shared__ double sS[ET][4][NQ][4];      // face coefficients of phi
-  __shared__ double sG[ET][4][NQ][8];      // face coefficients of d/dxi phi, d/deta phi
+  __shared__ double sU[ET][4][NN];
+  __shared__ double sT[ET][2][4][NP][NQ];       // P1: x-interpolants; P3: y-contractions A, B
+  __shared__ double sF[ET][2][4][NQV];          // weighted volume fluxes, x and y components
+  __shared__ double sS[ET][4][3][4][NQ];        // face coefficients of phi, dphi/dxi, dphi/deta
+  __shared__ double sL[ET][4][2][4][NP];        // face line sums
   __shared__ BasisTable tb;
   __shared__ int sE[ET];
   const int tid = threadIdx.x;
@@ -189,131 +296,167 @@ __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, D
   for (int i = tid; i < ET * 4 * NN; i += blockDim.x) {
     const int el = i / (4 * NN), r = i % (4 * NN);
     const int e = sE[el];
-    sU[el][r] = (e >= 0) ? U[(size_t)e * 4 * NN + r] : 0.0;
+    (&sU[el][0][0])[r] = (e >= 0) ? U[(size_t)e * 4 * NN + r] : 0.0;
   }
   __syncthreads();
-  // volume points
-  for (int i = tid; i < ET * NQV; i += blockDim.x) {
-    const int el = i / NQV, qv = i % NQV;
-    const int e = sE[el];
-    if (e < 0) continue;
-    const int qi = qv % NQ, qj = qv / NQ;
-    double val[4] = {0, 0, 0, 0}, dx[4] = {0, 0, 0, 0}, dy[4] = {0, 0, 0, 0};
+  // P1: interpolation along x at the Gauss abscissae
+  for (int i = tid; i < ET * 4 * NP * NQ; i += blockDim.x) {
+    const int qi = i % NQ, b = (i / NQ) % NP, v = (i / (NQ * NP)) % 4, el = i / (NQ * NP * 4);
+    double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const double lb = tb.L[qj][b], db = tb.D[qj][b];
+    for (int a = 0; a < NP; ++a) {
+      const double x = sU[el][v][a + NP * b];
+      t0 += tb.L[qi][a] * x;
+      t1 += tb.D[qi][a] * x;
+    }
+    sT[el][0][v][b][qi] = t0;
+    sT[el][1][v][b][qi] = t1;
+  }
+  __syncthreads();
+  // P2: volume points, then face points
+  for (int i = tid; i < ET * (NQV + 4 * NQ); i += blockDim.x) {
+    if (i < ET * NQV) {
+      const int el = i / NQV, qv = i % NQV;
+      const int e = sE[el];
+      if (e < 0) continue;
+      const int qi = qv % NQ, qj = qv / NQ;
+      double val[4] = {0, 0, 0, 0}, dx[4] = {0, 0, 0, 0}, dy[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int a = 0; a < NP; ++a) {
-        const double la = tb.L[qi][a], da = tb.D[qi][a];
+      for (int b = 0; b < NP; ++b) {
+        const double lb = tb.L[qj][b], db = tb.D[qj][b];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double x = sU[el][v * NN + a + NP * b];
-          val[v] += la * lb * x;
-          dx[v] += da * lb * x;
-          dy[v] += la * db * x;
+          const double t0 = sT[el][0][v][b][qi];
+          val[v] += lb * t0;
+          dy[v] += db * t0;
+          dx[v] += lb * sT[el][1][v][b][qi];
+        }
+      }
+      const double hx = m.hx[e], hy = m.hy[e];
+      double Fc[4][2];
+      conv_flux(val, g, Fc);
+      double F[4][2];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { F[v][0] = -Fc[v][0]; F[v][1] = -Fc[v][1]; }
+      if (MODEL == DGM_GENERAL && g.viscous) {
+        double G[4][2], Fv[4][2];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { G[v][0] = dx[v] * (2.0 / hx); G[v][1] = dy[v] * (2.0 / hy); }
+        visc_flux(val, G, g, Fv);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { F[v][0] += Fv[v][0]; F[v][1] += Fv[v][1]; }
+      }
+      // int F_x dphi/dx + F_y dphi/dy = sum_q w |J| (F_x (2/hx) dxi + F_y (2/hy) deta)
+      const double w = tb.W[qi] * tb.W[qj];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sF[el][0][v][qv] = w * F[v][0] * (0.5 * hy);
+        sF[el][1][v][qv] = w * F[v][1] * (0.5 * hx);
+      }
+    } else {
+      const int k = i - ET * NQV;
+      const int el = k / (4 * NQ), f = (k / NQ) % 4, q = k % NQ;
+      const int e = sE[el];
+      if (e < 0) continue;
+      const double hx = m.hx[e], hy = m.hy[e];
+      const double sx = 2.0 / hx, sy = 2.0 / hy;
+      double nx, ny;
+      face_normal(f, nx, ny);
+      // own trace and consistency flux from this element's record (written by dg_trace)
+      const int rs = (MODEL == DGM_GENERAL && g.viscous) ? 8 : 4;
+      double Uo[4], fo[4] = {0, 0, 0, 0};
+      const double* to = T + (((size_t)e * 4 + f) * NQ + q) * rs;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Uo[v] = to[v];
+      if (rs == 8) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fo[v] = to[4 + v];
+      }
+      const int nb = m.nbr[e * 4 + f];
+      const double le = hx * hy / (2.0 * (hx + hy));
+      double UN[4] = {0, 0, 0, 0}, fnn[4] = {0, 0, 0, 0};
+      int kind = DGF_FARFIELD;
+      double ln = le;
+      if (nb >= 0) {
+        kind = m.imp[nb] ? DGF_INTERFACE : DGF_INTERIOR;
+        const double* tn = T + (((size_t)nb * 4 + (f ^ 1)) * NQ + q) * rs;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) UN[v] = tn[v];
+        if (rs == 8) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) fnn[v] = -tn[4 + v];     // neighbour's F^nu . n_e
+        }
+        ln = m.hx[nb] * m.hy[nb] / (2.0 * (m.hx[nb] + m.hy[nb]));
+      }
+      const double tau = dg_tau(prm.alpha, K, kind, le, ln);
+      double s[4], gc[4][2];
+      dg_face_point_fo<MODEL == DGM_EULER_LF>(kind, Uo, fo, UN, fnn, nx, ny, tau, prm.lf, g, s, gc);
+      const double w = tb.W[q] * ((f < 2) ? 0.5 * hy : 0.5 * hx);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sS[el][f][0][v][q] = w * s[v];
+        if (MODEL != DGM_EULER_LF) {                 // inviscid: no test-gradient term
+          sS[el][f][1][v][q] = w * gc[v][0] * sx;
+          sS[el][f][2][v][q] = w * gc[v][1] * sy;
         }
       }
     }
-    const double hx = m.hx[e], hy = m.hy[e];
-    double Fc[4][2];
-    conv_flux(val, g, Fc);
-    double F[4][2];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) { F[v][0] = -Fc[v][0]; F[v][1] = -Fc[v][1]; }
-    if (g.viscous) {
-      double G[4][2], Fv[4][2];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { G[v][0] = dx[v] * (2.0 / hx); G[v][1] = dy[v] * (2.0 / hy); }
-      visc_flux(val, G, g, Fv);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { F[v][0] += Fv[v][0]; F[v][1] += Fv[v][1]; }
-    }
-    // int F_x dphi/dx + F_y dphi/dy = sum_q w |J| (F_x (2/hx) dxi + F_y (2/hy) deta)
-    const double w = tb.W[qi] * tb.W[qj];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      sF[el][qv][v] = w * F[v][0] * (0.5 * hy);
-      sF[el][qv][4 + v] = w * F[v][1] * (0.5 * hx);
-    }
   }
-  // face points
-  for (int i = tid; i < ET * 4 * NQ; i += blockDim.x) {
-    const int el = i / (4 * NQ), f = (i / NQ) % 4, q = i % NQ;
-    const int e = sE[el];
-    if (e < 0) continue;
-    const double hx = m.hx[e], hy = m.hy[e];
-    const double sx = 2.0 / hx, sy = 2.0 / hy;
-    double nx, ny;
-    face_normal(f, nx, ny);
-    double Uo[4], dxi[4], deta[4];
-    face_trace<K, 4>(tb, f, q, sU[el], Uo, dxi, deta);
-    const int nb = m.nbr[e * 4 + f];
-    const double le = hx * hy / (2.0 * (hx + hy));
-    double G[4][2], UN[4] = {0, 0, 0, 0}, fnn[4] = {0, 0, 0, 0};
+  __syncthreads();
+  // P3: y-contraction of the volume coefficients (into sT) and the face line sums
+  for (int i = tid; i < ET * 4 * NP * (NQ + 4); i += blockDim.x) {
+    if (i < ET * 4 * NP * NQ) {
+      const int qi = i % NQ, b = (i / NQ) % NP, v = (i / (NQ * NP)) % 4, el = i / (NQ * NP * 4);
+      double A = 0.0, B = 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { G[v][0] = dxi[v] * sx; G[v][1] = deta[v] * sy; }
-    int kind = DGF_FARFIELD;
-    double ln = le;
-    if (nb >= 0) {
-      kind = m.imp[nb] ? DGF_INTERFACE : DGF_INTERIOR;
-      const double* tn = T + (((size_t)nb * 4 + (f ^ 1)) * NQ + q) * 8;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        UN[v] = tn[v];
-        fnn[v] = -tn[4 + v];                 // neighbour's F^nu . n_e
+      for (int qj = 0; qj < NQ; ++qj) {
+        A += tb.L[qj][b] * sF[el][0][v][qi + NQ * qj];
+        B += tb.D[qj][b] * sF[el][1][v][qi + NQ * qj];
       }
-      ln = m.hx[nb] * m.hy[nb] / (2.0 * (m.hx[nb] + m.hy[nb]));
-    }
-    const double tau = dg_tau(prm.alpha, K, kind, le, ln);
-    double s[4], gc[4][2];
-    dg_face_point(kind, Uo, G, UN, fnn, nx, ny, tau, prm.lf, g, s, gc);
-    const double w = tb.W[q] * ((f < 2) ? 0.5 * hy : 0.5 * hx);
+      sT[el][0][v][b][qi] = A;
+      sT[el][1][v][b][qi] = B;
+    } else {
+      // face f, variable v, line index m (b for x-faces, a for y-faces)
+      const int k = i - ET * 4 * NP * NQ;
+      const int mm = k % NP, v = (k / NP) % 4, f = (k / (NP * 4)) % 4, el = k / (NP * 16);
+      double P = 0.0, Qs = 0.0;
+      if (MODEL == DGM_EULER_LF) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      sS[el][f][q][v] = w * s[v];
-      sG[el][f][q][v] = w * gc[v][0] * sx;
-      sG[el][f][q][4 + v] = w * gc[v][1] * sy;
+        for (int q = 0; q < NQ; ++q) P += sS[el][f][0][v][q] * tb.L[q][mm];
+      } else if (f < 2) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          P += sS[el][f][0][v][q] * tb.L[q][mm] + sS[el][f][2][v][q] * tb.D[q][mm];
+          Qs += sS[el][f][1][v][q] * tb.L[q][mm];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          P += sS[el][f][0][v][q] * tb.L[q][mm] + sS[el][f][1][v][q] * tb.D[q][mm];
+          Qs += sS[el][f][2][v][q] * tb.L[q][mm];
+        }
+      }
+      sL[el][f][0][v][mm] = P;
+      sL[el][f][1][v][mm] = Qs;
     }
   }
   __syncthreads();
-  // contraction with the test functions of node n = a + NP b
-  for (int i = tid; i < ET * NN; i += blockDim.x) {
-    const int el = i / NN, n = i % NN;
+  // P4: x-contraction and the face terms, one thread per (element, variable, node)
+  for (int i = tid; i < ET * 4 * NN; i += blockDim.x) {
+    const int n = i % NN, v = (i / NN) % 4, el = i / (4 * NN);
     const int e = sE[el];
     if (e < 0) continue;
     const int a = n % NP, b = n / NP;
-    double r[4] = {0, 0, 0, 0};
-    for (int qj = 0; qj < NQ; ++qj) {
+    double r = 0.0;
 #pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) {
-        const int qv = qi + NQ * qj;
-        const double px = tb.D[qi][a] * tb.L[qj][b];
-        const double py = tb.L[qi][a] * tb.D[qj][b];
+    for (int qi = 0; qi < NQ; ++qi) r += tb.D[qi][a] * sT[el][0][v][b][qi] + tb.L[qi][a] * sT[el][1][v][b][qi];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) r[v] += sF[el][qv][v] * px + sF[el][qv][4 + v] * py;
-      }
+    for (int s = 0; s < 2; ++s) {
+      r += tb.LE[s][a] * sL[el][s][0][v][b] + tb.LE[s][b] * sL[el][2 + s][0][v][a];       // x-, y-faces
+      if (MODEL != DGM_EULER_LF)
+        r += tb.DE[s][a] * sL[el][s][1][v][b] + tb.DE[s][b] * sL[el][2 + s][1][v][a];
     }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int s = f & 1;
-      for (int q = 0; q < NQ; ++q) {
-        double ph, pxi, peta;
-        if (f < 2) {
-          ph = tb.LE[s][a] * tb.L[q][b];
-          pxi = tb.DE[s][a] * tb.L[q][b];
-          peta = tb.LE[s][a] * tb.D[q][b];
-        } else {
-          ph = tb.L[q][a] * tb.LE[s][b];
-          pxi = tb.D[q][a] * tb.LE[s][b];
-          peta = tb.L[q][a] * tb.DE[s][b];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          r[v] += sS[el][f][q][v] * ph + sG[el][f][q][v] * pxi + sG[el][f][q][4 + v] * peta;
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) R[(size_t)e * 4 * NN + v * NN + n] = r[v];
+    R[(size_t)e * 4 * NN + v * NN + n] = r;
   }
 }
 
@@ -390,10 +533,16 @@ __global__ void scale_copy_kernel(const double* __restrict__ src, double* __rest
   }
 
 hipError_t launch_dg_trace(const imex_ctx* c, const double* U, const double* Q, double* trace) {
-  const int n = c->E * 4 * c->NQ;
   const int mx = (c->opt.hdg_variant == IMEX_HDG_MX) && c->gas.viscous && Q != nullptr;
-  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(dg_trace_kernel<KK>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
-                                           c->dmesh(), c->gas, mx, U, Q, trace));
+  IMEX_DISPATCH_K(c->K, {
+    constexpr int TE = TraceTile<KK>::TE;
+    if (c->gas.viscous)
+      hipLaunchKernelGGL((dg_trace_kernel<KK, true>), dim3((c->E + TE - 1) / TE), dim3(256), 0, c->stream,
+                         c->dmesh(), c->gas, mx, U, Q, trace);
+    else
+      hipLaunchKernelGGL((dg_trace_kernel<KK, false>), dim3((c->E + TE - 1) / TE), dim3(256), 0, c->stream,
+                         c->dmesh(), c->gas, mx, U, Q, trace);
+  });
   return hipGetLastError();
 }
 
@@ -401,8 +550,12 @@ template <int KK, int ET>
 static bool launch_dg_tile(const imex_ctx* c, DGParams prm, const double* U, const double* trace, double* R) {
   if constexpr (DGTile<KK>::lds(ET) <= 65536) {
     const int nb = (c->n_ex + ET - 1) / ET;
-    hipLaunchKernelGGL((dg_residual_kernel<KK, ET>), dim3(nb), dim3(256), 0, c->stream, c->dmesh(), c->gas, prm,
-                       c->d_ex_list, c->n_ex, U, trace, R);
+    if (!c->gas.viscous && prm.lf && !c->dg_farfield)
+      hipLaunchKernelGGL((dg_residual_kernel<KK, ET, DGM_EULER_LF>), dim3(nb), dim3(256), 0, c->stream, c->dmesh(),
+                         c->gas, prm, c->d_ex_list, c->n_ex, U, trace, R);
+    else
+      hipLaunchKernelGGL((dg_residual_kernel<KK, ET, DGM_GENERAL>), dim3(nb), dim3(256), 0, c->stream, c->dmesh(),
+                         c->gas, prm, c->d_ex_list, c->n_ex, U, trace, R);
     return true;
   }
   return false;
