@@ -340,8 +340,9 @@ imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt,
  * nullable): the derivative of <Ubar_next, U_{n+1}> + <Uhatbar_next, Uhat_{n+1}>
  * along a change u_inf + p duinf of the far-field state (App. B.1.1, B.2.1) at p = 0,
  * with U_n, Uhat_n fixed: the sum over the step's residual evaluations of their
- * adjoint times the residual's derivative in p (central differences in p at the
- * recorded states).  st host (nullable): gmres_its of the transposed solves.
+ * adjoint times the residual's exact derivative in p (the far-field face integrand of
+ * R^DG differentiated by a dual number seeded in u_inf, and A^-(Uhat) du_inf for the
+ * far-field facet rows).  st host (nullable): gmres_its of the transposed solves.
  * Errors: ENOTIMPL for implicit tableaux that are not stiffly accurate, or for duinf
  * without an implicit region; as imex_ark_step. */
 imex_status imex_vjp_imex_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,

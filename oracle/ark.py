@@ -181,3 +181,116 @@ class _sub:
         self.sx = geo.sx[elems]
         self.sy = geo.sy[elems]
         self.fjac = geo.fjac[elems]
+
+
+def step_jvp(solver: IMEXSolver, dU, dUhat, duinf=None, h=1e-30):
+    """Forward-mode derivative of one IMEX step from the solver's current (U_n, Uhat_n):
+    returns (U_{n+1}, Uhat_{n+1}, dU_{n+1}, dUhat_{n+1}) along the direction (dU, dUhat) of
+    the initial state and, optionally, duinf of the far-field state (u_inf + p duinf at
+    p = 0).  The solver itself is not advanced.
+
+    Each step of Alg. imex_scheme_update is differentiated in turn:
+    * the mixed variables of U_n lifted from (U_n, Uhat_n), the explicit residuals R^DG_i
+      and the final explicit update by the complex step (an exact derivative of the
+      real-analytic residuals, to rounding);
+    * each implicit stage through its converged root z_i = (y_i, q_i, yhat_i) of
+      F(z; rhs_i, y^ex_{i+1}, p) = 0 by the implicit-function theorem,
+      dz_i = -J(z_i)^-1 dF/d(rhs_i, y^ex_{i+1}, p), with the monolithic Jacobian J and
+      the right-hand side derivative by the complex step at fixed z_i;
+    * R^HDG_i at the root and the later right-hand sides rhs_j = M U_n - dt sum a_jk R^HDG_k
+      by the same rules.
+    Parity: the adjoint of the step satisfies <Ubar, dU> + <Uhatbar, dUhat> + pbar dp =
+    <Ubar_{n+1}, dU_{n+1}> + <Uhatbar_{n+1}, dUhat_{n+1}> for every direction."""
+    import dataclasses as _dc
+    import scipy.sparse.linalg as _spla
+
+    from .dg import dg_residual as _dgr
+    tab, dt = solver.tab, solver.wl.dt
+    wl0 = solver.wl
+    sysm = solver.system
+    ex, im = solver.mesh.ex_elems, solver.mesh.im_elems
+    du = np.zeros(4) if duinf is None else np.asarray(duinf, dtype=float)
+    wl_c = _dc.replace(wl0, u_inf=wl0.u_inf + 1j * h * du)    # complex far-field state
+    basis, mesh, gas = solver.basis, solver.mesh, solver.gas
+
+    def dgr(Y, Q, dY, dQ):
+        Yc = Y + 1j * h * dY
+        Qc = None if Q is None else Q + 1j * h * dQ
+        R = _dgr(Yc, Qc, wl_c, mesh, basis, gas)
+        return np.real(R), np.imag(R) / h
+
+    def minv(X, elems):
+        return apply_minv(X[elems], basis, _sub(solver.geo, elems))
+
+    Un = solver.U.copy()
+    Hn = solver.Uhat.copy()
+    dUn = np.array(dU, dtype=float)
+    dHn = np.array(dUhat, dtype=float)
+    Qc = init_mixed(Un + 1j * h * dUn, Hn + 1j * h * dHn, sysm)
+    Q, dQ = np.real(Qc), np.imag(Qc) / h
+    Y, dY = Un.copy(), dUn.copy()
+    H, dH = Hn.copy(), dHn.copy()
+    Rdg, dRdg, Rh, dRh = [], [], [], []
+    Mn, dMn = solver.mass_apply(Un), solver.mass_apply(dUn)
+    for i in range(1, tab.s + 1):
+        R, dR = dgr(Y, Q if sysm.mx else None, dY, dQ)
+        Rdg.append(R)
+        dRdg.append(dR)
+        acc = sum(tab.Ae[i, j] * Rdg[j] for j in range(i))
+        dacc = sum(tab.Ae[i, j] * dRdg[j] for j in range(i))
+        Y[ex] = Un[ex] - dt * minv(acc, ex)
+        dY[ex] = dUn[ex] - dt * minv(dacc, ex)
+        if not len(im):
+            continue
+        rhs = Mn[im] - sum(dt * tab.Ai[i - 1, j] * Rh[j] for j in range(i - 1)) if i > 1 else Mn[im].copy()
+        drhs = dMn[im] - sum(dt * tab.Ai[i - 1, j] * dRh[j] for j in range(i - 1)) if i > 1 else dMn[im].copy()
+        dta = dt * tab.Ai[i - 1, i - 1]
+        sysm.newton(Y, Q, H, dta, rhs)                      # the root (in place)
+        z = sysm.pack(Y, Q, H)
+        sd = sysm.stage_data(Y, dta, rhs)
+        J = sysm.jacobian(z, sd)
+        # dF/d(rhs, y^ex, p) along (drhs, dy^ex, dp) at fixed z
+        sd_c = sysm.stage_data(Y + 1j * h * dY, dta, rhs + 1j * h * drhs)
+        sysm.wl = wl_c
+        try:
+            Fc, _ = _residual_complex(sysm, z, sd_c)
+        finally:
+            sysm.wl = wl0
+        dz = _spla.spsolve(J.tocsc(), -np.imag(Fc) / h)
+        dYim = np.zeros_like(Y)
+        dQim = np.zeros_like(Q)
+        dHim = np.zeros_like(H)
+        sysm.unpack(dz, dYim, dQim, dHim)
+        dY[im] = dYim[im]
+        if sysm.mx:
+            dQ = dQim
+        dH = dHim
+        # R^HDG at the root and its derivative (z and the stage data move together)
+        sysm.wl = wl_c
+        try:
+            _, Rc = _residual_complex(sysm, z + 1j * h * dz, sd_c)
+        finally:
+            sysm.wl = wl0
+        Rh.append(np.real(Rc))
+        dRh.append(np.imag(Rc) / h)
+    U1, dU1 = Y.copy(), dY.copy()
+    if not tab.fsal:
+        R, dR = dgr(Y, Q if sysm.mx else None, dY, dQ)
+        Rdg.append(R)
+        dRdg.append(dR)
+        acc = sum(tab.be[j] * Rdg[j] for j in range(tab.s + 1))
+        dacc = sum(tab.be[j] * dRdg[j] for j in range(tab.s + 1))
+        U1[ex] = Un[ex] - dt * minv(acc, ex)
+        dU1[ex] = dUn[ex] - dt * minv(dacc, ex)
+    if len(im) and not tab.stiffly_accurate:
+        raise NotImplementedError("implicit tableaux that are not stiffly accurate")
+    return U1, H, dU1, dH
+
+
+def _residual_complex(sysm, z, sd):
+    """HDGSystem.residual for complex z or stage data (the global assembly in complex)."""
+    zl = z[sysm.locmap]
+    out, Rh = sysm.local_out(zl, sd)
+    F = np.zeros(sysm.N, dtype=complex)
+    np.add.at(F, sysm.locmap.reshape(-1), out.reshape(-1))
+    return F, Rh

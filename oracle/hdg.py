@@ -87,7 +87,7 @@ def local_residual(U, Q, Uh, sd: StageData, wl, basis: Basis, bg: BatchGeometry,
             vol = vol + ph.viscous_flux(Uq, Gq, gas)
     Rh = test_volume(vol, basis, bg)
     B = U.shape[0]
-    h = np.zeros((B, 4, 4, k + 1), dtype=np.result_type(U, Uh, float))
+    h = np.zeros((B, 4, 4, k + 1), dtype=np.result_type(U, Uh, sd.uex_fq, sd.rhs, wl.u_inf, float))
     tau = wl.alpha_hdg * (k + 1) ** 2 / bg.lchar
     uinf = wl.u_inf.reshape(4, 1, 1)
     wf_all = []
@@ -233,7 +233,8 @@ class HDGSystem:
 
     # -- packing ----------------------------------------------------------
     def pack(self, U_all, Q_all, Uhat):
-        z = np.zeros(self.N)
+        z = np.zeros(self.N, dtype=np.result_type(U_all, Uhat, float) if Q_all is None
+                     else np.result_type(U_all, Q_all, Uhat, float))
         z[:self.offQ] = U_all[self.elems].reshape(-1)
         if self.mx:
             z[self.offQ:self.offH] = Q_all[self.elems].reshape(-1)
@@ -272,7 +273,7 @@ class HDGSystem:
     def stage_data(self, U_all, dt_a, rhs_im):
         mesh, basis = self.mesh, self.basis
         B = self.B
-        uex = np.zeros((B, 4, 4, basis.nq))
+        uex = np.zeros((B, 4, 4, basis.nq), dtype=np.result_type(U_all, float))
         for f in range(4):
             nb = mesh.nbr[self.elems, f]
             itf = self.kind[:, f] == KIND_INTERFACE
@@ -375,7 +376,7 @@ def init_mixed(U_all, Uhat, system: HDGSystem):
 
     Rtilde is affine in Q: Rtilde(Q) = Rtilde(0) + A Q, with A probed column by column."""
     nn = system.basis.nn
-    Q_all = np.zeros((U_all.shape[0], 5, nn))
+    Q_all = np.zeros((U_all.shape[0], 5, nn), dtype=np.result_type(U_all, Uhat, float))
     if not system.mx or system.B == 0:
         return Q_all
     z = system.pack(U_all, Q_all, Uhat)
@@ -386,7 +387,9 @@ def init_mixed(U_all, Uhat, system: HDGSystem):
     for j in range(5 * nn):
         Qp = np.zeros_like(Q)
         Qp[:, j // nn, j % nn] = 1.0
-        A[:, :, j] = (mixed_residual(U, Qp, Uh, system.basis, system.bg, system.gas, wf_all) - g0).reshape(system.B, -1)
+        # the coefficients of Q are mass-matrix terms, real for complex (U, Uhat) as well
+        A[:, :, j] = np.real(mixed_residual(U, Qp, Uh, system.basis, system.bg, system.gas, wf_all)
+                             - g0).reshape(system.B, -1)
     sol = np.linalg.solve(A, -g0.reshape(system.B, -1, 1))[..., 0]
     Q_all[system.elems] = sol.reshape(system.B, 5, nn)
     return Q_all

@@ -1071,84 +1071,37 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   if (Uhatbar) HIP_TRY(c, hipMemsetAsync(Uhatbar, 0, nh * 8, hs));
   // Far-field parameter: u_inf enters the step only through the residuals' far-field
   // terms, so d(out)/dp along du_inf is the sum over the step's residual evaluations of
-  // <their adjoint, dresidual/dp>; the residual derivatives are central differences in p
-  // at the taped states (the far-field forms are affine or smooth in u_inf).
-  double pacc = 0.0, peps = 0.0;
-  if (want_p) {
-    double dmax = 0.0, umax = 0.0;
-    for (int v = 0; v < 4; ++v) {
-      dmax = std::max(dmax, std::fabs(duinf[v]));
-      umax = std::max(umax, std::fabs(c->gas.uinf[v]));
-    }
-    peps = dmax > 0.0 ? 1e-4 * std::max(umax, 1e-300) / dmax : 0.0;
-    if (!w.adj_rp) {
-      const size_t ns = (size_t)c->n_im * 16 * c->NP;
-      HIP_TRY(c, hipMalloc(&w.adj_rp, 8 * n));
-      HIP_TRY(c, hipMalloc(&w.adj_rm, 8 * n));
-      HIP_TRY(c, hipMalloc(&w.adj_hp, 8 * std::max<size_t>(ns, 1)));
-      HIP_TRY(c, hipMalloc(&w.adj_hm, 8 * std::max<size_t>(ns, 1)));
-      w.bytes += 8 * (2 * n + 2 * ns);
-    }
-  }
-  auto with_uinf = [&](double sgn, auto&& body) -> imex_status {
-    const Gas save = c->gas;
-    for (int v = 0; v < 4; ++v) c->gas.uinf[v] = save.uinf[v] + sgn * peps * duinf[v];
-    const imex_status r = body();
-    c->gas = save;
-    return r;
-  };
-  auto pdot = [&](int kind, int scaled, const double* a, const double* b, double* out) -> imex_status {
-    constexpr int nblk = 256;
-    HIP_TRY(c, launch_param_dot(c, kind, scaled, a, b, w.red, nblk));
-    HIP_TRY(c, hipMemcpyAsync(w.hred, w.red, sizeof(double) * nblk, hipMemcpyDeviceToHost, hs));
+  // <their adjoint, dresidual/dp>.  The residual derivatives are exact: the far-field face
+  // integrand of R^DG differentiated by a dual number seeded in u_inf, and the derivative
+  // A^-(Uhat) du_inf of the far-field facet rows (R^HDG's element rows do not depend on u_inf).
+  double pacc = 0.0;
+  auto psum = [&](hipError_t launched, double* out) -> imex_status {
+    HIP_TRY(c, launched);
+    HIP_TRY(c, hipMemcpyAsync(w.hred, w.red, sizeof(double) * 256, hipMemcpyDeviceToHost, hs));
     HIP_TRY(c, hipStreamSynchronize(hs));
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += w.hred[b];
+    for (int b = 0; b < 256; ++b) acc += w.hred[b];
     *out = acc;
     return IMEX_OK;
   };
-  // <Rbar, dR^DG/dp> for the explicit residual at (Y, Hin)
-  auto p_dg = [&](const double* Y, const double* Hin, const double* Rb) -> imex_status {
-    if (!want_p || peps == 0.0) return IMEX_OK;
-    imex_status r = with_uinf(1.0, [&] { return dg_residual_async(c, Y, Hin, w.adj_rp); });
-    if (r != IMEX_OK) return r;
-    r = with_uinf(-1.0, [&] { return dg_residual_async(c, Y, Hin, w.adj_rm); });
-    if (r != IMEX_OK) return r;
-    HIP_TRY(c, launch_scale_copy(c, w.adj_rp, w.adj_rp, 0.5 / peps, w.adj_rm, -0.5 / peps, n));
+  // <Rbar, dR^DG/dp> for the explicit residual at Y (the mixed variables of an HDG-MX
+  // neighbour do not depend on u_inf)
+  auto p_dg = [&](const double* Y, const double*, const double* Rb) -> imex_status {
+    if (!want_p) return IMEX_OK;
     double d = 0.0;
-    r = pdot(0, 0, Rb, w.adj_rp, &d);
+    const imex_status r = psum(launch_dg_param_dot(c, duinf, Y, Rb, w.red, 256), &d);
     pacc += d;
     return r;
   };
   // implicit stage at (Y, H) with the solution (lam, lamhat) of its transposed system:
-  // <Rhbar, dR^HDG/dp> - <lam, dt_a dR^HDG/dp> - <lamhat, dh/dp>
-  auto p_hdg = [&](double dt_a, const double* Y, const double* H, const double* Rhbar,
-                   const double* lam) -> imex_status {
-    if (!want_p || peps == 0.0) return IMEX_OK;
-    const size_t ns = (size_t)c->n_im * 16 * c->NP;
-    const double* lamhat = adjoint_facet_solution(c);
-    HIP_TRY(c, hipMemsetAsync(w.adj_rp, 0, 8 * n, hs));
-    HIP_TRY(c, hipMemsetAsync(w.adj_rm, 0, 8 * n, hs));
-    imex_status r = with_uinf(1.0, [&]() -> imex_status {
-      HIP_TRY(c, launch_hdg_residual(c, dt_a, Y, H, w.adj_rp));
-      HIP_TRY(c, hipMemcpyAsync(w.adj_hp, w.hres, 8 * ns, hipMemcpyDeviceToDevice, hs));
-      return IMEX_OK;
-    });
-    if (r != IMEX_OK) return r;
-    r = with_uinf(-1.0, [&]() -> imex_status {
-      HIP_TRY(c, launch_hdg_residual(c, dt_a, Y, H, w.adj_rm));
-      HIP_TRY(c, hipMemcpyAsync(w.adj_hm, w.hres, 8 * ns, hipMemcpyDeviceToDevice, hs));
-      return IMEX_OK;
-    });
-    if (r != IMEX_OK) return r;
-    HIP_TRY(c, launch_scale_copy(c, w.adj_rp, w.adj_rp, 0.5 / peps, w.adj_rm, -0.5 / peps, n));
-    HIP_TRY(c, launch_scale_copy(c, w.adj_hp, w.adj_hp, 0.5 / peps, w.adj_hm, -0.5 / peps, ns));
-    double d1 = 0.0, d2 = 0.0, d3 = 0.0;
-    if (Rhbar && (r = pdot(1, 0, Rhbar, w.adj_rp, &d1)) != IMEX_OK) return r;
-    if ((r = pdot(1, 1, lam, w.adj_rp, &d2)) != IMEX_OK) return r;
-    if ((r = pdot(2, 0, lamhat, w.adj_hp, &d3)) != IMEX_OK) return r;
-    pacc += d1 - dt_a * d2 - d3;
-    return IMEX_OK;
+  // -<lamhat, dh/dp> (the element rows' terms <Rhbar, dR^HDG/dp> and <lam, dt_a dR^HDG/dp>
+  // vanish)
+  auto p_hdg = [&](double, const double*, const double* H, const double*, const double*) -> imex_status {
+    if (!want_p) return IMEX_OK;
+    double d = 0.0;
+    const imex_status r = psum(launch_hdg_param_dot(c, duinf, H, adjoint_facet_solution(c), w.red, 256), &d);
+    pacc -= d;
+    return r;
   };
   // HDG-MX: the explicit residual of stage i reads the mixed variables lifted from
   // (y^im_{i-1}, Uhat_{i-1}); their adjoint goes to that facet state as well

@@ -205,6 +205,11 @@ hipError_t launch_hdg_residual(imex_ctx* c, double dt_a, const double* Y, const 
 const double* adjoint_facet_solution(const imex_ctx* c);
 hipError_t launch_param_dot(const imex_ctx* c, int kind, int scaled, const double* a, const double* b, double* part,
                             int nblk);
+// exact <Rbar, dR^DG/dp> and <lamhat, dh/dp> along u_inf + p du (per-block partial sums)
+hipError_t launch_dg_param_dot(const imex_ctx* c, const double* du, const double* U, const double* Rb, double* part,
+                               int nblk);
+hipError_t launch_hdg_param_dot(const imex_ctx* c, const double* du, const double* H, const double* lam, double* part,
+                                int nblk);
 hipError_t launch_wall_shear_qbar(const imex_ctx* c, double scale, double* Qb);
 hipError_t launch_lift_mixed(const imex_ctx* c, const double* U, const double* Uhat, double* Q);
 hipError_t launch_mass_rhs(const imex_ctx* c, const double* Un, double* rhs);

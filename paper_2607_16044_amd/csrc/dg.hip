@@ -461,6 +461,63 @@ __global__ void __launch_bounds__(256) dg_residual_kernel(DeviceMesh m, Gas g, D
 }
 
 // ---------------------------------------------------------------------------
+// <Rbar, dR^DG/dp> along a far-field direction u_inf + p du (reverse mode of the far-field
+// parameter): u_inf enters R^DG only at far-field faces of explicit elements (App. B.1.1),
+// so the derivative is the far-field face integrand differentiated exactly by a dual
+// number seeded in u_inf, tested against the trace and gradient of Rbar.  Per-block
+// partial sums in part[gridDim.x].
+// ---------------------------------------------------------------------------
+struct Dir4 { double v[4]; };
+
+template <int K>
+__global__ void __launch_bounds__(256) dg_param_dot_kernel(DeviceMesh m, Gas g, double alpha,
+                                                           const int* __restrict__ ex_list, int n_ex, Dir4 du,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ Rb, double* __restrict__ part) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NN = NP * NP;
+  using D1 = Dual<1>;
+  __shared__ double red[4];
+  const BasisTable& tb = *m.tab;
+  double acc = 0.0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_ex * 4 * NQ; t += gridDim.x * blockDim.x) {
+    const int q = t % NQ, f = (t / NQ) % 4, e = ex_list[t / (4 * NQ)];
+    if (m.nbr[e * 4 + f] >= 0 || m.bcf[e * 4 + f] != IMEX_BC_FARFIELD) continue;
+    const double hx = m.hx[e], hy = m.hy[e], sx = 2.0 / hx, sy = 2.0 / hy;
+    double nx, ny;
+    face_normal(f, nx, ny);
+    double Uo[4], dxi[4], deta[4], rv[4], rx[4], ry[4];
+    face_trace<K, 4>(tb, f, q, U + (size_t)e * 4 * NN, Uo, dxi, deta);
+    face_trace<K, 4>(tb, f, q, Rb + (size_t)e * 4 * NN, rv, rx, ry);
+    D1 Ui[4], fo[4], sd[4], gd[4][2];
+    double Go[4][2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ui[v] = D1(g.uinf[v]);
+      Ui[v].d[0] = du.v[v];
+      Go[v][0] = dxi[v] * sx;
+      Go[v][1] = deta[v] * sy;
+      fo[v] = D1(0.0);
+    }
+    if (g.viscous) {
+      D1 Fv[4][2];
+      visc_flux(Ui, Go, g, Fv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fo[v] = Fv[v][0] * nx + Fv[v][1] * ny;
+    }
+    const double le = hx * hy / (2.0 * (hx + hy));
+    dg_farfield_terms(Uo, fo, Ui, nx, ny, dg_tau(alpha, K, DGF_FARFIELD, le, le), g, sd, gd);
+    const double w = tb.W[q] * ((f < 2) ? 0.5 * hy : 0.5 * hx);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      acc += w * (sd[v].d[0] * rv[v] + gd[v][0].d[0] * rx[v] * sx + gd[v][1].d[0] * ry[v] * sy);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
 // ERK combination y = U_n - dt M^-1 sum_j c_j R_j on explicit elements
 // ---------------------------------------------------------------------------
 struct Terms {
@@ -587,6 +644,14 @@ hipError_t launch_dg_residual(const imex_ctx* c, const double* U, const double* 
     }
     if (!ok) return hipErrorInvalidValue;
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_param_dot(const imex_ctx* c, const double* du, const double* U, const double* Rb, double* part,
+                               int nblk) {
+  Dir4 d{{du[0], du[1], du[2], du[3]}};
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(dg_param_dot_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
+                                           c->gas, c->opt.alpha_dg, c->d_ex_list, c->n_ex, d, U, Rb, part));
   return hipGetLastError();
 }
 

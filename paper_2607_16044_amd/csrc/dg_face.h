@@ -38,6 +38,41 @@ __device__ inline void dg_face_visc_n(int farfield, const T Uo[4], const T Go[4]
   for (int v = 0; v < 4; ++v) fo[v] = Fv[v][0] * nx + Fv[v][1] * ny;
 }
 
+// Far-field face point (App. B.1.1) with the free-stream state Ui as an input, so that the
+// same code gives the residual and, with dual numbers in Ui, its derivative in u_inf:
+// s = A^+(U) U + A^-(U) Ui - fo + tau K(Ui)((U - Ui) x n) . n,  gc = -K(Ui)((U - Ui) x n),
+// fo = F^nu(Ui, grad U) . n (dg_face_visc_n on the far field).
+template <class T, class TI>
+__device__ inline void dg_farfield_terms(const T Uo[4], const TI fo[4], const TI Ui[4], double nx, double ny,
+                                         double tau, const Gas& g, TI s[4], TI gc[4][2]) {
+  TI ap[4], am[4], Uc[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Uc[v] = TI(Uo[v]);
+  char_apply(Uc, Uc, nx, ny, +1, g, ap);
+  char_apply(Uc, Ui, nx, ny, -1, g, am);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    s[v] = ap[v] + am[v];
+    gc[v][0] = TI(0.0);
+    gc[v][1] = TI(0.0);
+  }
+  if (!g.viscous) return;
+  TI Gj[4][2], Kf[4][2];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const TI d = Uc[v] - Ui[v];
+    Gj[v][0] = d * nx;
+    Gj[v][1] = d * ny;
+  }
+  visc_flux(Ui, Gj, g, Kf);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    s[v] = s[v] - fo[v] + tau * (Kf[v][0] * nx + Kf[v][1] * ny);
+    gc[v][0] = -Kf[v][0];
+    gc[v][1] = -Kf[v][1];
+  }
+}
+
 // The face integrand from the own trace Uo and its consistency flux fo (dg_face_visc_n):
 // everything a face point needs that is not a gradient.  EULER_LF: the caller guarantees
 // inviscid flow, the Lax-Friedrichs flux and no far-field face, so only that branch is
@@ -77,27 +112,8 @@ __device__ inline void dg_face_point_fo(int kind, const T Uo[4], const T fo[4], 
       }
     }
   } else {
-    T Ui[4] = {T(g.uinf[0]), T(g.uinf[1]), T(g.uinf[2]), T(g.uinf[3])};
-    T ap[4], am[4];
-    char_apply(Uo, Uo, nx, ny, +1, g, ap);
-    char_apply(Uo, Ui, nx, ny, -1, g, am);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) s[v] = ap[v] + am[v];
-    if (!g.viscous) return;
-    T Gj[4][2], Kf[4][2];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T d = Uo[v] - Ui[v];
-      Gj[v][0] = d * nx;
-      Gj[v][1] = d * ny;
-    }
-    visc_flux(Ui, Gj, g, Kf);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      s[v] = s[v] - fo[v] + tau * (Kf[v][0] * nx + Kf[v][1] * ny);
-      gc[v][0] = -Kf[v][0];
-      gc[v][1] = -Kf[v][1];
-    }
+    const T Ui[4] = {T(g.uinf[0]), T(g.uinf[1]), T(g.uinf[2]), T(g.uinf[3])};
+    dg_farfield_terms(Uo, fo, Ui, nx, ny, tau, g, s, gc);
   }
 }
 

@@ -163,6 +163,50 @@ __global__ void __launch_bounds__(256) param_dot_kernel(DeviceMesh m, DeviceHDG 
   if (threadIdx.x == 0) part[blockIdx.x] = red4[0] + red4[1] + red4[2] + red4[3];
 }
 
+// <lamhat, dh/dp> along a far-field direction u_inf + p du: u_inf enters the HDG facet
+// rows only on far-field facets, h = int (A^+(Uhat)(Uhat - U) - A^-(Uhat)(Uhat - u_inf)) psi
+// (App. B.2.1), whose derivative is int A^-(Uhat) du psi, exactly; the element rows do
+// not depend on u_inf.  lamhat is laid out as the facet unknowns.  Per-block partials.
+struct HDir4 { double v[4]; };
+
+template <int K>
+__global__ void __launch_bounds__(256) hdg_param_dot_kernel(DeviceMesh m, DeviceHDG h, Gas g, HDir4 du,
+                                                            const double* __restrict__ H,
+                                                            const double* __restrict__ lam, double* __restrict__ part) {
+  constexpr int NP = K + 1, NQ = (3 * K + 2) / 2, NFF = 4 * NP;
+  __shared__ double red[4];
+  const BasisTable& tb = *m.tab;
+  double acc = 0.0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < h.n_im * 4 * NQ; t += gridDim.x * blockDim.x) {
+    const int q = t % NQ, f = (t / NQ) % 4, pp = t / (4 * NQ);
+    if (h.face_kind[4 * pp + f] != FK_FARFIELD) continue;
+    const int e = h.im_list[pp];
+    const size_t fo = (size_t)h.efacet[4 * pp + f] * NFF;
+    double Wh[4], lq[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < NP; ++mm) {
+        a += tb.L[q][mm] * H[fo + v * NP + mm];
+        b += tb.L[q][mm] * lam[fo + v * NP + mm];
+      }
+      Wh[v] = a;
+      lq[v] = b;
+    }
+    const double nx = (f == 0) ? -1.0 : (f == 1 ? 1.0 : 0.0), ny = (f == 2) ? -1.0 : (f == 3 ? 1.0 : 0.0);
+    double am[4];
+    char_apply(Wh, du.v, nx, ny, -1, g, am);
+    const double w = tb.W[q] * ((f < 2) ? 0.5 * m.hy[e] : 0.5 * m.hx[e]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc += w * am[v] * lq[v];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG h, Gas g,
                                                          const double* __restrict__ U,
@@ -450,6 +494,14 @@ hipError_t launch_param_dot(const imex_ctx* c, int kind, int scaled, const doubl
                             int nblk) {
   IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(param_dot_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream, c->dmesh(),
                                            c->dhdg(), c->E, kind, scaled, a, b, part));
+  return hipGetLastError();
+}
+
+hipError_t launch_hdg_param_dot(const imex_ctx* c, const double* du, const double* H, const double* lam, double* part,
+                                int nblk) {
+  HDir4 d{{du[0], du[1], du[2], du[3]}};
+  IMEX_DISPATCH_K(c->K, hipLaunchKernelGGL(hdg_param_dot_kernel<KK>, dim3(nblk), dim3(256), 0, c->stream,
+                                           c->dmesh(), c->dhdg(), c->gas, d, H, lam, part));
   return hipGetLastError();
 }
 

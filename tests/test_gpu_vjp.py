@@ -458,3 +458,38 @@ def test_wall_shear_objective_mach_derivative():
     assert err < 1e-6
     assert errt < 1e-6
     assert erro < 1e-4
+
+
+@pytest.mark.parametrize("case", list(IMEX_CASES))
+def test_imex_step_vjp_against_oracle_jvp(case):
+    """Dot-product identity between the GPU's IMEX-step adjoint and the oracle's forward
+    derivative through the converged stages (oracle.ark.step_jvp): for seeded directions
+    of the initial state, the facet state and (with far-field faces) the far-field state,
+    <Ubar, dU> + <Uhatbar, dUhat> + pbar = <c, dU_{n+1}> + <ch, dUhat_{n+1}>."""
+    from oracle.ark import step_jvp
+    from oracle.hdg import init_facets
+    wl = IMEX_CASES[case]()
+    eng = gpu_engine(wl, newton_rtol=1e-14, gmres_rtol=1e-13)
+    rng = np.random.default_rng(23)
+    base = IMEXSolver(wl)
+    U0 = base.U * (1.0 + 1e-3 * rng.standard_normal(base.U.shape))
+    ora = IMEXSolver(wl, U0=U0)
+    dU = rng.standard_normal(U0.shape) * 1e-2 * np.abs(U0).max()
+    dH = init_facets(dU, ora.mesh, ora.basis) + 1e-3 * rng.standard_normal(ora.Uhat.shape)
+    far = any(b == W.BC_FARFIELD for b in wl.bc)
+    du = np.array([0.0, 0.01, -0.02, 1.0]) if far else None
+    _, _, dU1, dH1 = step_jvp(ora, dU, dH, du)
+    c = rng.standard_normal(U0.shape)
+    ch = rng.standard_normal(ora.Uhat.shape)
+    Ut = torch.tensor(U0, device="cuda")
+    Ht = torch.tensor(ora.Uhat, device="cuda")
+    Ub, Hb = eng.vjp_imex_step(wl.dt, Ut, Ht, torch.tensor(c, device="cuda"),
+                               Uhatbar_next=torch.tensor(ch, device="cuda"), return_facets=True, duinf=du)
+    got = float(np.sum(Ub.cpu().numpy() * dU)) + float(np.sum(Hb.cpu().numpy() * dH))
+    if far:
+        got += eng.last_param_adjoint
+    ref = float(np.sum(c * dU1) + np.sum(ch * dH1))
+    scale = float(np.sum(np.abs(c * dU1)) + np.sum(np.abs(ch * dH1)))
+    err = abs(got - ref) / scale
+    print(case, got, ref, err, eng.last_adjoint_stats)
+    assert err < 1e-9
