@@ -245,6 +245,23 @@ imex_status imex_implicit_stage_solve(imex_ctx* ctx, double dt_aii, const double
 imex_status imex_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt, double* U, double* Uhat,
                           imex_stats* st);
 
+/* Manufactured-solution source (Sec. 5.1.1, method of manufactured solutions): with on != 0
+ * every imex_ark_step adds S = dU_e/dt + div(F^c(U_e) - F^nu(U_e, grad U_e)) of the exact
+ * solution U_e = (s, s, s, s^2), s = sin(pi (kx x + ky y) - omega pi t) + 4, to the equations:
+ * the explicit residual of stage i takes R^DG - b(t_n + cbar_i dt), the implicit stage i solves
+ * M y + dt a_ii (R^HDG(y) - b(t_n + c_i dt)) = rhs and passes R^HDG - b to later stages, with
+ * b[e][v][n] = int_T S_v phi_n.  params host [3] = kx, ky, omega; t0 = the time of the state the
+ * next step starts from; each successful imex_ark_step advances that clock by dt.  on = 0
+ * removes the source (and sets the clock to t0).  The adjoint entry points return ENOTIMPL
+ * while a source is set.  Errors: EINVAL (null or non-finite parameters; a batch with
+ * per-instance time-step scales), ENOMEM. */
+imex_status imex_set_mms_source(imex_ctx* ctx, const double params[3], double t0, int on);
+
+/* The source's load vector at time t: b[e][v][n] = int_T S_v(x, t) phi_n dx over all
+ * elements (dev out [E][4][(k+1)^2]), with the volume Gauss rule.  Errors: ESTATE (no source
+ * set), EINVAL. */
+imex_status imex_mms_load(imex_ctx* ctx, double t, double* b);
+
 /* out[v] = sum over elements of int_T U_v (host, 4 doubles); U dev. */
 imex_status imex_conservation_sums(imex_ctx* ctx, const double* U, double out[4]);
 

@@ -27,6 +27,7 @@ EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coo
            "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
            "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
            "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes", "imex_dg_residual_noalloc",
+           "imex_set_mms_source", "imex_mms_load",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.imex_init_facets.argtypes = [P, P, P]
     lib.imex_dg_residual.argtypes = [P, P, P, P]
     lib.imex_dg_residual_noalloc.argtypes = [P, P, P, P]
+    lib.imex_set_mms_source.argtypes = [P, ctypes.POINTER(D), D, ctypes.c_int]
+    lib.imex_mms_load.argtypes = [P, D, P]
     lib.imex_implicit_stage_solve.argtypes = [P, D, P, P, P, P, ctypes.POINTER(Stats)]
     lib.imex_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, ctypes.POINTER(Stats)]
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
@@ -247,6 +250,17 @@ class Engine:
         """R^DG into the caller's R through the allocation-free entry point (static scratch)."""
         self._check(self.lib.imex_dg_residual_noalloc(self.ctx, _ptr(U), _ptr(Uhat), _ptr(R)))
         return R
+
+    def set_mms_source(self, kx: float, ky: float, omega: float, t0: float = 0.0, on: bool = True):
+        """Add the manufactured-solution source of wave numbers (kx, ky), frequency omega to
+        every following ARK step, starting at time t0 (see imex_set_mms_source)."""
+        prm = (ctypes.c_double * 3)(kx, ky, omega)
+        self._check(self.lib.imex_set_mms_source(self.ctx, prm, float(t0), int(bool(on))))
+
+    def mms_load(self, t: float) -> torch.Tensor:
+        b = torch.empty(self.state_shape(), dtype=torch.float64, device=self.device)
+        self._check(self.lib.imex_mms_load(self.ctx, float(t), _ptr(b)))
+        return b
 
     def implicit_stage_solve(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):
         R = torch.zeros_like(U)

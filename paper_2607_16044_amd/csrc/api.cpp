@@ -99,7 +99,10 @@ void build_table(int K, BasisTable& T) {
     T.DE[0][a] = dlag(nodes, np, a, -1.0);
     T.DE[1][a] = dlag(nodes, np, a, 1.0);
   }
-  for (int q = 0; q < nq; ++q) T.W[q] = w[q];
+  for (int q = 0; q < nq; ++q) {
+    T.W[q] = w[q];
+    T.Z[q] = z[q];
+  }
 }
 
 template <class T>
@@ -268,7 +271,7 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
 
   // geometry and neighbours, instance by instance
   const int E = c->E;
-  std::vector<double> hx(E), hy(E), dts(E, 1.0);
+  std::vector<double> hx(E), hy(E), dts(E, 1.0), xy0(2 * (size_t)E);
   c->nbr.assign(4 * E, -1);
   c->bcf.assign(4 * E, -1);
   int off = 0;
@@ -289,6 +292,8 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
         const int e = off + i + nx * j;
         hx[e] = in.xg[i + 1] - in.xg[i];
         hy[e] = in.yg[j + 1] - in.yg[j];
+        xy0[2 * e] = in.xg[i];
+        xy0[2 * e + 1] = in.yg[j];
         dts[e] = in.dt_scale;
         const int ci[4] = {i - 1, i + 1, i, i};
         const int cj[4] = {j, j, j - 1, j + 1};
@@ -311,6 +316,7 @@ static imex_status create_ctx(int n, const imex_mesh_desc* meshes, const double*
   hipStream_t s = c->stream;
   hipError_t he = hipSuccess;
   if ((he = upload(&c->d_hx, hx, s)) != hipSuccess || (he = upload(&c->d_hy, hy, s)) != hipSuccess ||
+      (he = upload(&c->d_xy0, xy0, s)) != hipSuccess ||
       (he = upload(&c->d_nbr, c->nbr, s)) != hipSuccess || (he = upload(&c->d_bcf, c->bcf, s)) != hipSuccess ||
       (he = upload(&c->d_imp, c->imp, s)) != hipSuccess || (dt_scale && (he = upload(&c->d_dts, dts, s)) != hipSuccess)) {
     imex_destroy(c);
@@ -689,6 +695,32 @@ imex_status imex_dg_residual(imex_ctx* c, const double* U, const double* Uhat, d
   return IMEX_OK;
 }
 
+imex_status imex_set_mms_source(imex_ctx* c, const double params[3], double t0, int on) {
+  if (!c || (on && !params)) return fail(c, IMEX_EINVAL, "null argument");
+  if (on && !(std::isfinite(params[0]) && std::isfinite(params[1]) && std::isfinite(params[2]) && std::isfinite(t0)))
+    return fail(c, IMEX_EINVAL, "non-finite source parameters");
+  if (on && c->d_dts) return fail(c, IMEX_EINVAL, "the source needs one time step for the whole context");
+  if (on && !c->d_src) {
+    HIP_TRY(c, hipMalloc(&c->d_src, sizeof(double) * (size_t)c->E * 4 * c->NN));
+    c->ws.bytes += sizeof(double) * (size_t)c->E * 4 * c->NN;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->drop_graphs();                          // the captured stage sequences change
+  c->mms_on = on != 0;
+  if (on)
+    for (int i = 0; i < 3; ++i) c->mms[i] = params[i];
+  c->t_now = t0;
+  return IMEX_OK;
+}
+
+imex_status imex_mms_load(imex_ctx* c, double t, double* b) {
+  if (!c || !b) return fail(c, IMEX_EINVAL, "null argument");
+  if (!c->mms_on) return fail(c, IMEX_ESTATE, "imex_set_mms_source first");
+  HIP_TRY(c, launch_mms_load(c, t, b));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return IMEX_OK;
+}
+
 imex_status imex_dg_residual_noalloc(imex_ctx* c, const double* U, const double* Uhat, double* R) {
   if (!c || !U || !R) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
@@ -792,10 +824,12 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
     HIP_TRY(c, hipMemcpyAsync(w.Yp, U, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
     HIP_TRY(c, hipMemcpyAsync(w.Hp, Uhat, (size_t)c->n_hf * 4 * c->NP * sizeof(double), hipMemcpyDeviceToDevice, hs));
   }
-  // implicit stage times c_i = sum_j a_ij (c_0 = 0)
-  double ci[4] = {0.0, 0.0, 0.0, 0.0};
+  // implicit stage times c_i = sum_j a_ij (c_0 = 0); explicit stage times cbar_i = row sums of Ae
+  double ci[4] = {0.0, 0.0, 0.0, 0.0}, ce[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = 1; i <= s; ++i)
     for (int j = 0; j < i; ++j) ci[i] += tab->Ai[3 * (i - 1) + j];
+  for (int i = 0; i <= s; ++i)
+    for (int j = 0; j < i; ++j) ce[i] += tab->Ae[4 * i + j];
   if (mx) HIP_TRY(c, launch_lift_mixed(c, w.Y, Uhat, w.Q));   // Q^im_0 = Q(U_n, Uhat_n)
   for (int i = 1; i <= s; ++i) {
     // R^DG(y^ex_i, y^im_{i-1}) (the mixed variables in w.Q belong to y^im_{i-1}; rows of
@@ -810,11 +844,17 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
     std::vector<double> key = {dt, (double)i};
     key.insert(key.end(), coef, coef + i);
     key.insert(key.end(), ch, ch + i - 1);
+    if (c->mms_on) key.push_back(c->t_now);          // the source depends on the time
     if (tape) HIP_TRY(c, hipMemcpyAsync(tape->Ydg[i - 1], w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
     const int tdg = c->timer_begin(TM_DG);
     imex_status se = run_captured(c, i - 1, key, [&]() -> imex_status {
       HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
       HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[i - 1]));
+      if (c->mms_on) {
+        // the source at the explicit stage time: R^DG_i - b(t_n + cbar_i dt)
+        HIP_TRY(c, launch_mms_load(c, c->t_now + ce[i - 1] * dt, c->d_src));
+        HIP_TRY(c, launch_rows_axpy(c, 1, 0, -1.0, c->d_src, Rdg[i - 1]));
+      }
       HIP_TRY(c, launch_erk_combine(c, w.Un, i, Rs, coef, dt, w.Y));
       if (c->n_im > 0) {
         HIP_TRY(c, launch_mass_rhs(c, w.Un, w.rhs));
@@ -829,8 +869,16 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
       // extrapolation in stage time from the two previous implicit stage values
       if (i >= 2 && ci[i - 1] - ci[i - 2] > 1e-12 * dt)
         HIP_TRY(c, launch_extrapolate(c, (ci[i] - ci[i - 1]) / (ci[i - 1] - ci[i - 2]), w.Y, w.Yp, Uhat, w.Hp));
+      const double dta = dt * tab->Ai[3 * (i - 1) + (i - 1)];
+      if (c->mms_on) {
+        // the source at the implicit stage time: M y + dt a_ii (R^HDG(y) - b) = rhs
+        HIP_TRY(c, launch_mms_load(c, c->t_now + ci[i] * dt, c->d_src));
+        HIP_TRY(c, launch_rhs_accumulate(c, dta, c->d_src, w.rhs));
+      }
       imex_stats sst{};
-      imex_status r = hdg_stage_solve(c, dt * tab->Ai[3 * (i - 1) + (i - 1)], w.rhs, w.Y, Uhat, Rhdg[i - 1], &sst);
+      imex_status r = hdg_stage_solve(c, dta, w.rhs, w.Y, Uhat, Rhdg[i - 1], &sst);
+      if (r == IMEX_OK && c->mms_on)        // later right-hand sides take R^HDG_i - b_i
+        HIP_TRY(c, launch_rows_axpy(c, 2, 0, -1.0, c->d_src, Rhdg[i - 1]));
       if (st) {
         st->newton_its += sst.newton_its;
         st->gmres_its += sst.gmres_its;
@@ -857,10 +905,15 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
     for (int j = 0; j <= s; ++j) { coef[j] = tab->be[j]; Rs[j] = Rdg[j]; }
     std::vector<double> key = {dt, -1.0};
     key.insert(key.end(), coef, coef + s + 1);
+    if (c->mms_on) key.push_back(c->t_now);
     const int tdg = c->timer_begin(TM_DG);
     imex_status se = run_captured(c, 4, key, [&]() -> imex_status {
       HIP_TRY(c, launch_dg_trace(c, w.Y, mx ? w.Q : nullptr, w.trace));
       HIP_TRY(c, launch_dg_residual(c, w.Y, w.trace, Rdg[s]));
+      if (c->mms_on) {
+        HIP_TRY(c, launch_mms_load(c, c->t_now + ce[s] * dt, c->d_src));
+        HIP_TRY(c, launch_rows_axpy(c, 1, 0, -1.0, c->d_src, Rdg[s]));
+      }
       HIP_TRY(c, launch_erk_combine(c, w.Un, s + 1, Rs, coef, dt, w.Y));
       return IMEX_OK;
     });
@@ -870,6 +923,7 @@ static imex_status ark_step_impl(imex_ctx* c, const imex_tableau* tab, double dt
   HIP_TRY(c, hipMemcpyAsync(U, w.Y, n * sizeof(double), hipMemcpyDeviceToDevice, hs));
   HIP_TRY(c, hipStreamSynchronize(hs));
   c->timers_resolve();
+  if (!tape) c->t_now += dt;                 // the clock of the manufactured-solution source
   return IMEX_OK;
 }
 
@@ -964,6 +1018,7 @@ imex_status imex_vjp_ark_step(imex_ctx* c, const imex_tableau* tab, double dt, c
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   if (imex_status ts = check_tableau(c, tab, dt); ts != IMEX_OK) return ts;
   if (c->n_im > 0) return fail(c, IMEX_ENOTIMPL, "step adjoint with an implicit region");
+  if (c->mms_on) return fail(c, IMEX_ENOTIMPL, "step adjoint with a manufactured-solution source");
   HIP_TRY(c, vjp_alloc(c));
   Workspace& w = c->ws;
   const int s = tab->s;
@@ -1021,6 +1076,7 @@ imex_status imex_vjp_imex_step(imex_ctx* c, const imex_tableau* tab, double dt, 
   if (!c || !tab || !U || !Ubar_next || !Ubar) return fail(c, IMEX_EINVAL, "null argument");
   if (!c->regions_set) return fail(c, IMEX_ESTATE, "imex_set_regions first");
   if (imex_status ts = check_tableau(c, tab, dt); ts != IMEX_OK) return ts;
+  if (c->mms_on) return fail(c, IMEX_ENOTIMPL, "step adjoint with a manufactured-solution source");
   const bool want_p = duinf && pbar;
   if (want_p) *pbar = 0.0;
   if (c->n_im == 0) {
@@ -1209,7 +1265,7 @@ void imex_destroy(imex_ctx* c) {
     if (w.vjp_y[r]) hipFree(w.vjp_y[r]);
     w.vjp_y[r] = nullptr;
   }
-  for (double** p : {&c->d_hx, &c->d_hy, &c->d_dts}) {
+  for (double** p : {&c->d_hx, &c->d_hy, &c->d_dts, &c->d_xy0, &c->d_src}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }

@@ -120,6 +120,12 @@ struct imex_ctx {
   int n_win = 0, n_superrows = 0;
   int n_im = 0, n_ex = 0, n_hf = 0;
   bool dg_farfield = false;     // some explicit element has a far-field boundary face
+  // manufactured-solution source (imex_set_mms_source): wave numbers, frequency, clock
+  bool mms_on = false;
+  double mms[3] = {0.0, 0.0, 0.0};
+  double t_now = 0.0;
+  double* d_xy0 = nullptr;      // [E][2] lower-left corner of each element
+  double* d_src = nullptr;      // [E][4][NN] source load of one stage time
   bool regions_set = false;
   // launch shapes (0 = built-in default), chosen by imex_autotune
   int dg_tile = 0;              // explicit elements per workgroup of the residual kernel
@@ -189,6 +195,8 @@ constexpr int MAX_DEVICES = 64;
 hipError_t static_scratch_init(int device);   // resolve the device address (device current)
 double* static_scratch(int device);           // that address, or null before a successful init
 hipError_t launch_fill_zero(const imex_ctx* c, double* x, size_t n);
+// b[e][v][n] = int_T S_v(x, t) phi_n of the manufactured-solution source at time t
+hipError_t launch_mms_load(const imex_ctx* c, double t, double* b);
 hipError_t launch_dg_trace(const imex_ctx* c, const double* U, const double* Q, double* trace);
 hipError_t launch_dg_residual(const imex_ctx* c, const double* U, const double* trace, double* R);
 hipError_t launch_erk_combine(const imex_ctx* c, const double* Un, int nterms, const double* const* R,

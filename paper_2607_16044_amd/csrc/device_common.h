@@ -37,6 +37,7 @@ struct BasisTable {
   double DE[2][MAXNP];       // l_a'(-1), l_a'(+1)
   double W[MAXNQ];           // Gauss weights (sum 2)
   double NW[MAXNP];          // node weights (mass matrix diagonal factors)
+  double Z[MAXNQ];           // Gauss abscissae z_q on [-1, 1]
 };
 
 // --------------------------------------------------------------------------

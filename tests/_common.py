@@ -64,3 +64,28 @@ def rel_err(a, b):
         return 0.0
     scale = np.maximum(np.abs(b).max(), 1e-300)
     return float(np.abs(a - b).max() / scale)
+
+
+MMS = (2.0, 2.0, 200.0)          # kx, ky, omega of the manufactured solution (Sec. 5.1.1)
+
+
+def mms_workload(n=8, k=2, implicit_cols=(), variant=W.HDG_MX, tableau="ARS222", dt=1e-4, mu=0.01, lf=False):
+    """Periodic unit square for the manufactured solution: U_e = (s, s, s, s^2),
+    s = sin(pi (kx x + ky y) - omega pi t) + 4 (u = v = 1), gamma 1.4, Pr 0.72, mu 0.01;
+    implicit_cols: the element columns of the implicit region (the paper takes the middle
+    half, x in [0.25, 0.75])."""
+    from oracle.mms import exact_state          # noqa: F401  (the same closed form, for the tests)
+    x = np.linspace(0.0, 1.0, n + 1)
+    implicit = np.zeros((n, n), dtype=bool)
+    for i in implicit_cols:
+        implicit[:, i] = True
+    kx, ky, om = MMS
+
+    def ic(X, Y, elem=None, node=None):
+        s = np.sin(np.pi * (kx * X + ky * Y)) + 4.0
+        return np.stack([s, s, s, s * s])
+    return W.Workload(name="mms", xgrid=x, ygrid=x.copy(), bc=(W.BC_PERIODIC,) * 4, implicit=implicit, degree=k,
+                      gamma=1.4, R=1.0, mu=mu, Pr=0.72, viscous=True, u_inf=np.array([4.0, 4.0, 4.0, 16.0]),
+                      dg_flux=W.FLUX_LAX_FRIEDRICHS if lf else W.FLUX_VIJAYASUNDARAM,
+                      hdg_flux=W.HDG_FLUX_LF if lf else W.HDG_FLUX_FVS, hdg_variant=variant, tableau=tableau,
+                      dt=dt, steps=1, ic=ic)
