@@ -67,6 +67,11 @@ def parse():
                     help="stable time step of fully explicit DG and of IMEX by bisection, and the speedup "
                          "S = r_t eta, on isentropic vortices with a compressed strip; prints its own JSON line")
     ap.add_argument("--dt-study-n", type=int, default=48, help="mesh size n x n of --dt-study")
+    ap.add_argument("--adjoint-study", action="store_true",
+                    help="gradient of the time-averaged wall shear on the full boundary layer (200 steps, window "
+                         "100..200, checkpoints every 20) in U_0 along 3 seeded directions and in Ma, against "
+                         "central differences of GPU runs; prints its own JSON line")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (calibrates HBM traffic counters)")
     ap.add_argument("--eliminate-shape", type=int, default=0,
@@ -79,18 +84,21 @@ def parse():
 ELIMINATE_SHAPE = 0
 
 
-def cpu_baseline():
-    """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
-    same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
-    full mesh), one step, single thread."""
+def _sample_workload(x0=0.0):
+    from paper_2607_16044_amd import workloads
+    return workloads.boundary_layer(nx=2, ny=16, k=4, implicit_rows=2, Lx=2 * 2.0 / 256, height=None, steps=1,
+                                    name="boundary_layer_sample", x0=x0)
+
+
+def _oracle_sample_step(x0=0.0):
+    """One oracle step of the sample strip starting at x0, on one thread; returns
+    (seconds, initial state, final state)."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:                       # pragma: no cover
         threadpool_limits = None
-    from paper_2607_16044_amd import workloads
     from oracle.ark import IMEXSolver
-    wl = workloads.boundary_layer(nx=2, ny=16, k=4, implicit_rows=2, Lx=2 * 2.0 / 256, height=None, steps=1,
-                                  name="boundary_layer_sample")
+    wl = _sample_workload(x0)
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         s = IMEXSolver(wl)
@@ -101,10 +109,48 @@ def cpu_baseline():
     finally:
         if ctx is not None and hasattr(ctx, "unregister"):
             ctx.unregister()
+    return dt, U0, s.U
+
+
+def _oracle_worker(x0):
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    return _oracle_sample_step(x0)[0]
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
+    same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
+    full mesh), one step.  Timed on one thread, and on all host cores as independent
+    single-thread strips (one per core, up to the 16-core share of a one-GPU machine): the
+    oracle is a serial numpy program, so the all-core rate is the aggregate throughput of
+    as many strips as cores, each a different stretch of the plate."""
+    import multiprocessing as mp
+    dt, U0, U1 = _oracle_sample_step()
+    wl = _sample_workload()
     dof_stage = wl.n_dof * wl.stages
-    return {"value": dof_stage / dt, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step, {dt:.1f} s",
-            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, s.U), "ensemble_vs_oracle": ensemble_vs_oracle()}
+    ncores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(ncores) as pool:
+        per = pool.map(_oracle_worker, [0.02 * i for i in range(ncores)])
+    wall = time.perf_counter() - t0
+    return {"value": ncores * dof_stage / wall, "unit": "DOF-stage updates/s", "cores": ncores, "kind": "oracle",
+            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step per core "
+                      f"on {ncores} cores at once ({wall:.1f} s wall, {min(per):.1f}-{max(per):.1f} s per strip); "
+                      f"one core alone: {dt:.1f} s",
+            "one_core": {"value": dof_stage / dt, "cores": 1, "seconds": dt},
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()},
+            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, U1), "ensemble_vs_oracle": ensemble_vs_oracle()}
 
 
 def ensemble_vs_oracle(steps=1):
@@ -323,14 +369,16 @@ def mx_ip_study(steps=3, warmup=1, n=128):
             "precision": "fp64", "steps": steps, "rows": rows}
 
 
-def dt_study(compressions=(5.0, 10.0, 20.0, 50.0), n=48, k=3, strip_rows=4, t_end=0.3, bisections=8):
+def dt_study(compressions=(5.0, 10.0, 20.0, 50.0), n=48, k=3, strip_rows=4, t_end=0.3, bisections=8, min_steps=60):
     """Stable time step and speedup of the IMEX split over fully explicit DG (Sec. 5: the
     speedup S = r_t eta, r_t the ratio of stable steps, eta the ratio of the costs per step),
     measured on the GPU.  Isentropic vortex on an n x n periodic mesh with a centred strip of
     strip_rows rows compressed by each factor; explicit DG everywhere against the strip
     implicit (HDG-IP).  A time step counts as stable when a run to t_end stays finite with
     the density in (0, 2 max rho_0] (an unstable mode grows from round-off to O(1) within
-    the run) and every Newton solve converges; bisection on log dt.  FP64."""
+    the run) and every Newton solve converges; the run takes at least min_steps steps, more
+    than the cost measurement takes at 0.9 of the step found, so a slowly growing mode at a
+    large step cannot pass in a few steps and fail in the timing; bisection on log dt.  FP64."""
     import dataclasses
     import math
     import numpy as np
@@ -343,7 +391,7 @@ def dt_study(compressions=(5.0, 10.0, 20.0, 50.0), n=48, k=3, strip_rows=4, t_en
             U = eng.initial_state()
             H = eng.init_facets(U) if eng.sizes["n_implicit"] else None
             rho_max = float(U.view(-1, 4, (k + 1) ** 2)[:, 0].max())
-            nsteps = min(steps_cap, int(math.ceil(t_end / dt)))
+            nsteps = min(steps_cap, max(min_steps, int(math.ceil(t_end / dt))))
             for i in range(nsteps):
                 eng.ark_step(dt, U, H)
                 if i % 10 == 9 or i == nsteps - 1:
@@ -370,7 +418,7 @@ def dt_study(compressions=(5.0, 10.0, 20.0, 50.0), n=48, k=3, strip_rows=4, t_en
                 hi = mid
         return lo
 
-    def cost_ms(wl, dt, steps=20):
+    def cost_ms(wl, dt, steps=min(20, min_steps - 5)):
         eng = binding.Engine(wl, precision=0)
         U = eng.initial_state()
         H = eng.init_facets(U) if eng.sizes["n_implicit"] else None
@@ -402,6 +450,69 @@ def dt_study(compressions=(5.0, 10.0, 20.0, 50.0), n=48, k=3, strip_rows=4, t_en
     return {"study": "stable time step and IMEX speedup over explicit DG", "workload":
             f"isentropic vortex {n}x{n}, k={k}, strip of {strip_rows} rows, ARS(2,2,2), FP64, stability to t={t_end}",
             "rows": rows}
+
+
+def adjoint_study(nsteps=200, window=(100, 200), checkpoint=20, h=1e-6, ndir=3, seed=5, Ma=0.3):
+    """The adjoint workload at size: the full boundary layer (256x128, k = 4, HDG-MX wall rows,
+    ARS(3,4,3)) in FP64, J = the wall shear of the HDG-MX walls averaged over the states
+    after steps window[0]..window[1] of an nsteps run (mu (du/dy + dv/dx) = 2 mu eps_12 of
+    the lifted mixed variables), with checkpoints every `checkpoint` steps and recomputation
+    in the backward pass.  Reports dJ/dU_0 . d for ndir seeded directions (seed 5: normal
+    draws scaled per field by 1e-2 of that field's largest magnitude) and the partial
+    dJ/dMa (U_0 and dt fixed; Ma enters through the far-field state), each against central
+    differences of GPU runs with relative step h."""
+    import numpy as np
+    import torch
+    from paper_2607_16044_amd import binding, workloads
+    from paper_2607_16044_amd.autograd import wall_shear_objective
+    kw = dict(precision=0, newton_rtol=1e-13, gmres_rtol=1e-12)
+
+    def make(ma):
+        return workloads.boundary_layer(Ma=ma, name="boundary_layer")
+    wl = make(Ma)
+    dt = wl.dt
+    eng = binding.Engine(wl, **kw)
+    U0 = eng.initial_state()
+    rng = np.random.default_rng(seed)
+    scale = U0.abs().amax(dim=(0, 2)).view(1, 4, 1)
+    dirs = [torch.tensor(rng.standard_normal(tuple(U0.shape)), device="cuda") * 1e-2 * scale for _ in range(ndir)]
+    duinf = workloads.farfield_mach_direction(wl.gamma, Ma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = U0.clone().requires_grad_(True)
+    p = torch.zeros((), dtype=torch.float64, device="cuda", requires_grad=True)
+    J = wall_shear_objective(eng, U, dt, nsteps, window, checkpoint=checkpoint, p=p, duinf=duinf)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    print("adjoint study: forward done", file=sys.stderr, flush=True)
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0 - t_fwd
+    print("adjoint study: backward done", file=sys.stderr, flush=True)
+    grad, dJdMa = U.grad.detach(), float(p.grad)
+
+    def run(e, start):
+        with torch.no_grad():
+            return float(wall_shear_objective(e, start, dt, nsteps, window))
+    out = {"study": "adjoint of the time-averaged wall shear", "workload": "boundary_layer 256x128, k=4, HDG-MX, "
+           f"ARS(3,4,3), FP64, {nsteps} steps, window {window[0]}..{window[1]}, checkpoint every {checkpoint}",
+           "J": float(J), "seconds_forward": t_fwd, "seconds_backward": t_bwd, "fd_step": h, "directions": []}
+    t1 = time.perf_counter()
+    for k, d in enumerate(dirs):
+        adj = float((grad * d).sum())
+        fd = (run(eng, U0 + h * d) - run(eng, U0 - h * d)) / (2 * h)
+        out["directions"].append({"adjoint": adj, "central_difference": fd, "rel_diff": abs(adj - fd) / abs(fd)})
+        print(f"adjoint study: direction {k} done", file=sys.stderr, flush=True)
+    eng.close()
+    vals = []
+    for sgn in (1.0, -1.0):
+        e = binding.Engine(make(Ma + sgn * h * Ma), **kw)
+        vals.append(run(e, U0))
+        e.close()
+    fdm = (vals[0] - vals[1]) / (2 * h * Ma)
+    out["dJ_dMa"] = {"adjoint": dJdMa, "central_difference": fdm, "rel_diff": abs(dJdMa - fdm) / abs(fdm)}
+    out["seconds_differences"] = time.perf_counter() - t1
+    return out
 
 
 def run_ensemble(precision, steps, warmup, n=512):
@@ -451,6 +562,10 @@ def main():
         return
     if args.mx_ip_study:
         print(json.dumps(mx_ip_study()))
+        return
+    if args.adjoint_study:
+        n = args.adjoint_steps
+        print(json.dumps(adjoint_study(nsteps=n, window=(n // 2, n), checkpoint=max(1, n // 10))))
         return
     if args.ensemble_only:
         precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
