@@ -128,7 +128,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline():
+def cpu_baseline(shapes=None):
     """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
     same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
     full mesh), one step.  Timed on one thread, and on all host cores as independent
@@ -150,7 +150,7 @@ def cpu_baseline():
                       f"one core alone: {dt:.1f} s",
             "one_core": {"value": dof_stage / dt, "cores": 1, "seconds": dt},
             "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()},
-            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, U1), "ensemble_vs_oracle": ensemble_vs_oracle()}
+            "gpu_vs_oracle": gpu_vs_oracle(wl, U0, U1, shapes), "ensemble_vs_oracle": ensemble_vs_oracle()}
 
 
 def ensemble_vs_oracle(steps=1):
@@ -184,16 +184,20 @@ def ensemble_vs_oracle(steps=1):
     return out
 
 
-def gpu_vs_oracle(wl, U0, U_oracle):
+def gpu_vs_oracle(wl, U0, U_oracle, shapes=None):
     """The same step of the sample on the GPU in FP64 and in mixed precision: the largest
     relative error against the oracle over the four conservative fields (each relative to
-    that field's largest magnitude), with the gates 1e-10 (FP64) and 1e-9 (mixed)."""
+    that field's largest magnitude), with the gates 1e-10 (FP64) and 1e-9 (mixed).  shapes:
+    the launch shapes the timed runs picked (applied to both legs; the mixed leg takes the
+    mixed run's)."""
     import numpy as np
     import torch
     from paper_2607_16044_amd import binding
     out = {}
     for name, prec, gate in (("fp64", 0, 1e-10), ("mixed", 1, 1e-9)):
         eng = binding.Engine(wl, precision=prec)
+        if shapes and shapes.get(name):
+            eng.set_launch_shapes(shapes[name])
         U = torch.tensor(U0, device="cuda")
         H = eng.init_facets(U)
         eng.ark_step(wl.dt, U, H)
@@ -282,6 +286,79 @@ def contraction_work(wl, n_im, la_bytes):
     return float(n_im) * (8 * rec + la_bytes * out)
 
 
+def schwarz_superrows(wl):
+    """Super-rows of the facet preconditioner's two-column windows (one per pair of
+    adjacent element columns that holds implicit elements: one super-row per element row
+    from the lowest to the highest implicit row of the pair, plus one)."""
+    import numpy as np
+    imp = np.asarray(wl.implicit, dtype=bool)          # [row][column]
+    ny, nx = imp.shape
+    from paper_2607_16044_amd import workloads
+    px = wl.bc[0] == workloads.BC_PERIODIC
+    nwin = 1 if nx == 1 else (nx if px else nx - 1)
+    total = 0
+    for w in range(nwin):
+        cols = [w] if nx == 1 else [w, (w + 1) % nx]
+        rows = np.nonzero(imp[:, cols].any(axis=1))[0]
+        if rows.size:
+            total += int(rows.max() - rows.min() + 2)
+    return total
+
+
+def step_roofline(wl, res, ms_per_step, prec):
+    """Roofline time of one step, phase by phase: count per step x max(bytes / 8 TB/s,
+    flops / dense peak of the phase's arithmetic type), with the algorithmic bytes and flops
+    of each phase (inputs read once, outputs written once; the condensation counted as an
+    LU of K with triangular solves, 2/3 NU^3 + 2 NU^2 (NF+1) + 2 NF NU (NF+1)).  Phases
+    whose work is pointwise flux arithmetic (explicit residual, FP64 implicit residual,
+    point Jacobians) are counted by bytes alone, so their roofline time is a lower bound.
+    frac = sum of the roofline times / measured ms per step."""
+    from paper_2607_16044_amd import tableaux, workloads
+    import numpy as np
+    k1 = wl.degree + 1
+    nn, nu, nf, nqm, nff = k1 * k1, 4 * k1 * k1, 16 * k1, 5 * k1 * k1, 4 * k1
+    nb_, nh_ = 5 * nff, 2 * nff
+    nq = (3 * wl.degree + 2) // 2
+    nqv = nq * nq
+    la = LA_BYTES[prec]
+    bw, peak = PEAK_HBM_GBS * 1e9, PEAK_TFLOPS[prec] * 1e12
+    sz = res["sizes"]
+    n_im, n_ex, n_hf = sz["n_implicit"], sz["n_explicit"], sz["n_hdg_facets"]
+    n = n_hf * nff
+    nsr = schwarz_superrows(wl)
+    J, C, G = res["jacobians"], res["newton"], res["gmres"]
+    tab = tableaux.get(wl.tableau)
+    n_dg = int(sum(1 for i in range(len(tab.be)) if np.any(tab.Ae[:, i] != 0.0) or tab.be[i] != 0.0))
+    mx = wl.hdg_variant == workloads.HDG_MX
+    out = {}
+
+    def add(name, count, nbytes, flops=0.0):
+        t = count * max(nbytes / bw, flops / peak)
+        out[name] = {"per_step": round(count, 3), "bytes": nbytes, "flops": flops, "roof_ms": 1e3 * t}
+    add("dg", n_dg, 2.0 * n_ex * 4 * nn * 8)
+    if mx:
+        rec = nqv * 8 * 9 + 4 * nq * 8 * 13 + nqv * 12 + 4 * nq * 12
+        blocks = nu * nu + 2 * nu * nqm + 2 * nu * nf + nf * nf + 2 * nf * nqm
+    else:
+        rec = nqv * 8 * 12 + 4 * nq * 16 * 16
+        blocks = nu * nu + 2 * nu * nf + nf * nf
+    add("assemble", J, n_im * (2.0 * 8 * rec + la * blocks))
+    add("residual", C + tab.s, n_im * 2.0 * 8 * (nu + nf))
+    if mx:
+        fl, by = elimination_work(wl, n_im, la)
+        add("eliminate", J, by, fl)
+    add("condense", J, n_im * la * (2.0 * (nu * nu + nu * (nf + 1) + nf * (nf + 1)) + nf * nu),
+        n_im * (2.0 / 3.0 * nu ** 3 + 2.0 * nu * nu * (nf + 1) + 2.0 * nf * nu * (nf + 1)))
+    add("facet_rhs", max(C - J, 0.0), n_im * la * (nu * nu + nf * nu), n_im * 2.0 * (nu * nu + nf * nu))
+    jbar = 0.5 * (G / max(C, 1.0) + 1.0)
+    add("gmres", G, n_im * la * nf * nf + nsr * la * (nb_ * nb_ + 2 * nh_ * nb_) + n * 8 * (3 * jbar + 6),
+        2.0 * (n_im * nf * nf + nsr * (nb_ * nb_ + 2 * nh_ * nb_)) + 4.0 * jbar * n)
+    add("backsub", C, n_im * (la * nu * (nf + 1) + 8.0 * (nf + 2 * nu)), n_im * 2.0 * nu * (nf + 1))
+    total = sum(v["roof_ms"] for v in out.values())
+    return {"roof_ms_per_step": total, "measured_ms_per_step": ms_per_step, "frac": total / ms_per_step,
+            "schwarz_superrows": nsr, "phases": {k: {**v, "roof_ms": round(v["roof_ms"], 4)} for k, v in out.items()}}
+
+
 def run(wl, precision, steps, warmup, newton_simplified=1):
     import torch
     from paper_2607_16044_amd import binding
@@ -309,9 +386,10 @@ def run(wl, precision, steps, warmup, newton_simplified=1):
     elapsed = time.perf_counter() - t0
     timers = eng.timers()
     n_im = eng.sizes["n_implicit"]
+    sizes = dict(eng.sizes)
     eng.close()
     return {"elapsed": elapsed, "timers": timers, "newton": newton / steps, "gmres": gmres / steps,
-            "jacobians": jac / steps, "U": U, "Uhat": Uhat, "n_im": n_im, "shapes": shapes}
+            "jacobians": jac / steps, "U": U, "Uhat": Uhat, "n_im": n_im, "shapes": shapes, "sizes": sizes}
 
 
 # the batched GEMM kernel run for a launch-shape code (imex_set_launch_shapes)
@@ -630,6 +708,7 @@ def main():
                    "gmres_its_per_step": res["gmres"], "newton_simplified": 1,
                    "gmres_forcing": 3, "launch_shapes": res["shapes"]},
         "roofline": roof,
+        "step_roofline": step_roofline(wl, res, 1e3 * res["elapsed"] / args.steps, main_prec),
         "phases_ms_per_step": phases,
         "kernels_ms_per_step": kernels,
     }
@@ -660,7 +739,10 @@ def main():
                            "unit": "DOF-stage updates/s", "steps": args.ensemble_steps,
                            "mixed": ens_m, "fp64": ens_d, "mixed_over_fp64": ens_m["value"] / ens_d["value"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        picked = {main_prec: res["shapes"]}
+        if other is not None:
+            picked["fp64"] = other["shapes"]
+        out["cpu_baseline"] = cpu_baseline(picked)
     print(json.dumps(out))
 
 
