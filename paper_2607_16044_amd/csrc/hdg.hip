@@ -2112,243 +2112,148 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
   }
 }
 
-// Preconditioner apply z = M^-1 x in five launches.  Per window, with y, w, z
-// restricted to super-row r (NB unknowns, H = its first NH):
-//   forward   y_r = x_r - G_r y_{r-1}        (only the H rows change)
-//   diagonal  w_r = D_r^-1 y_r
-//   backward  z_r = w_r - E_r z_{r+1}[H]
-// Splitting G_r y_{r-1} = G_r[:, H] y_{r-1}[H] + G_r[:, ~H] x_{r-1}[~H], and the
-// backward update into its H rows and the rest, leaves two serial chains of
-// NH x NH products per window (one wave each); the D_r^-1 products and the
-// other pieces run over all super-rows at once.  Sweep vectors per super-row
-// in Wy: y_r (NB) | w_r (NB) | z_r[H] (NH).
+// Sweep sizes of a super-row of the facet preconditioner's windows: NB unknowns (five
+// facet slots), the first NH of them (the two horizontal slots) coupling consecutive
+// super-rows; per super-row NSV doubles of Wy, of which the apply keeps w_r at offset NB.
 template <int K> struct RasDims {
   static constexpr int NFF = 4 * (K + 1), NB = 5 * NFF, NH = 2 * NFF, NSV = 2 * NB + NH;
 };
 
-// y_r = x_r, then y_r[H] -= G_r[:, ~H] x_{r-1}[~H].  The H-row products are split over
-// P = 128 / NH slices of the ~H columns so that every thread issues its loads at once.
+// Preconditioner apply z = M^-1 x in one launch: one workgroup per window sweeps its
+// super-rows forward, y_r = x_r - G_r [y_{r-1}[H]; x_{r-1}[~H]] (only the H rows change)
+// and w_r = D_r^-1 y_r (w_r kept in Wy), then backward, z_r = w_r - E_r z_{r+1}[H] with the
+// owned facets of z_r written.  Each product is split into column slices over the 256
+// threads (partial sums reduced through LDS, FP64 accumulation of the FP32 or FP64
+// factors), and the next super-row's factor entries and vector values are loaded into
+// registers while the current super-row is applied, so the factor stream, not the serial
+// chain, sets the pace.
 template <int K, class T>
-__global__ void __launch_bounds__(128) ras_pre_kernel(DeviceHDG h, const T* __restrict__ Wg,
-                                                      const double* __restrict__ x, double* __restrict__ Wy) {
+__global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wg, const T* __restrict__ Wd,
+                                                        const T* __restrict__ Wc, const double* __restrict__ x,
+                                                        double* __restrict__ Wy, double* __restrict__ z) {
   using D = RasDims<K>;
-  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH, NX = NB - NH;
-  constexpr int P = 128 / NH, CH = (NX + P - 1) / P;
-  __shared__ double xp[NX], yr[NB], part[P][NH];
-  const int g = blockIdx.x, tid = threadIdx.x;
-  const int fl = h.sr_flags[g];
-  for (int i = tid; i < NB; i += blockDim.x) {
-    const int a = i / NFF;
-    const int f = h.win_slot[5 * g + a];
-    yr[i] = (f >= 0) ? x[(size_t)f * NFF + i % NFF] : 0.0;
-    if (i >= NH) {
-      int fp = -1;
-      if (fl & 1) fp = h.win_slot[5 * (g - 1) + a];
-      xp[i - NH] = (fp >= 0) ? x[(size_t)fp * NFF + i % NFF] : 0.0;
-    }
-  }
-  __syncthreads();
-  const T* Gg = Wg + (size_t)g * NH * NB;        // Gg[k * NH + i] = G_r[i][k]
-  if ((fl & 1) && tid < P * NH) {
-    const int i = tid % NH, q = tid / NH, k0 = q * CH;
-    double a = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < CH; ++kk) {
-      const int k = k0 + kk;
-      if (k < NX) a += (double)Gg[(size_t)(NH + k) * NH + i] * xp[k];
-    }
-    part[q][i] = a;
-  }
-  __syncthreads();
-  double* Y = Wy + (size_t)g * D::NSV;
-  for (int i = tid; i < NB; i += blockDim.x) {
-    double v = yr[i];
-    if ((fl & 1) && i < NH) {
-      double a = 0.0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) a += part[q][i];
-      v -= a;
-    }
-    Y[i] = v;
-  }
-}
-
-// forward chain: y_r[H] -= G_r[:, H] y_{r-1}[H], one wave per window; the next super-row's
-// block and vector are fetched while the current one is applied
-template <int K, class T>
-__global__ void __launch_bounds__(64) ras_fwd_kernel(DeviceHDG h, const T* __restrict__ Wg, double* __restrict__ Wy) {
-  using D = RasDims<K>;
-  constexpr int NB = D::NB, NH = D::NH;
-  static_assert(NH <= 64, "one lane per H row");
-  __shared__ double yh[NH];
-  const int w = blockIdx.x, lane = threadIdx.x;
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
+  constexpr int PD = 256 / NB, CD = (NB + PD - 1) / PD;      // D^-1: NB rows, NB columns
+  constexpr int PG = 256 / NH, CG = (NB + PG - 1) / PG;      // G: NH rows, NB columns
+  constexpr int PE = 256 / NB, CE = (NH + PE - 1) / PE;      // E: NB rows, NH columns
+  __shared__ double yv[NB], prev[NB], zn[NH], pd[PD][NB], pg[PG][NH], pe[PE][NB];
+  const int w = blockIdx.x, t = threadIdx.x;
   const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
   if (g1 <= g0) return;
-  if (lane < NH) yh[lane] = Wy[(size_t)g0 * D::NSV + lane];
-  T gc[NH];
-  double ycur = 0.0;
-  if (g0 + 1 < g1 && lane < NH) {
-    const T* Gg = Wg + (size_t)(g0 + 1) * NH * NB;
+  const int di = t % NB, dq = t / NB;                        // D^-1 and E row / slice of this thread
+  const int gi = t % NH, gq = t / NH;                        // G row / slice
+  const bool dON = t < PD * NB, gON = t < PG * NH, eON = t < PE * NB;
+  auto xval = [&](int g, int i) -> double {
+    const int f = h.win_slot[5 * g + i / NFF];
+    return f >= 0 ? x[(size_t)f * NFF + i % NFF] : 0.0;
+  };
+  T gr[CG], dr[CD];
+  auto load_fwd = [&](int g) {
+    const T* Gg = Wg + (size_t)g * NH * NB;                  // Gg[k * NH + i] = G_r[i][k]
+    const T* Dg = Wd + (size_t)g * NB * NB;                  // Dg[k * NB + i] = D_r^-1[i][k]
 #pragma unroll
-    for (int k = 0; k < NH; ++k) gc[k] = Gg[(size_t)k * NH + lane];
-    ycur = Wy[(size_t)(g0 + 1) * D::NSV + lane];
-  }
-  __syncthreads();
-  for (int g = g0 + 1; g < g1; ++g) {
-    T gn[NH];
-    double ynext = 0.0;
-    if (g + 1 < g1 && lane < NH) {
-      const T* Gn = Wg + (size_t)(g + 1) * NH * NB;
-#pragma unroll
-      for (int k = 0; k < NH; ++k) gn[k] = Gn[(size_t)k * NH + lane];
-      ynext = Wy[(size_t)(g + 1) * D::NSV + lane];
+    for (int kk = 0; kk < CG; ++kk) {
+      const int k = gq * CG + kk;
+      gr[kk] = (gON && g > g0 && k < NB) ? Gg[(size_t)k * NH + gi] : T(0);
     }
-    double v = ycur;
-    if (lane < NH) {
 #pragma unroll
-      for (int k = 0; k < NH; ++k) v -= (double)gc[k] * yh[k];
+    for (int kk = 0; kk < CD; ++kk) {
+      const int k = dq * CD + kk;
+      dr[kk] = (dON && k < NB) ? Dg[(size_t)k * NB + di] : T(0);
     }
+  };
+  load_fwd(g0);
+  double xn = t < NB ? xval(g0, t) : 0.0;
+  for (int g = g0; g < g1; ++g) {
+    if (t < NB) yv[t] = xn;
     __syncthreads();
-    if (lane < NH) {
-      yh[lane] = v;
-      Wy[(size_t)g * D::NSV + lane] = v;
-    }
-    __syncthreads();
+    T gc[CG], dc[CD];
+#pragma unroll
+    for (int kk = 0; kk < CG; ++kk) gc[kk] = gr[kk];
+#pragma unroll
+    for (int kk = 0; kk < CD; ++kk) dc[kk] = dr[kk];
     if (g + 1 < g1) {
-#pragma unroll
-      for (int k = 0; k < NH; ++k) gc[k] = gn[k];
-      ycur = ynext;
+      load_fwd(g + 1);
+      xn = t < NB ? xval(g + 1, t) : 0.0;
     }
-  }
-}
-
-// w_r = D_r^-1 y_r, one workgroup of 256 per super-row, the columns split over
-// P = 256 / NB slices
-template <int K, class T>
-__global__ void __launch_bounds__(256) ras_diag_kernel(DeviceHDG h, const T* __restrict__ Wd, double* __restrict__ Wy) {
-  using D = RasDims<K>;
-  constexpr int NB = D::NB;
-  constexpr int P = 256 / NB, CH = (NB + P - 1) / P;
-  __shared__ double yv[NB], part[P][NB];
-  const int g = blockIdx.x, tid = threadIdx.x;
-  double* Y = Wy + (size_t)g * D::NSV;
-  for (int i = tid; i < NB; i += blockDim.x) yv[i] = Y[i];
-  __syncthreads();
-  const T* Dg = Wd + (size_t)g * NB * NB;        // Dg[k * NB + i] = D_r^-1[i][k]
-  if (tid < P * NB) {
-    const int i = tid % NB, q = tid / NB, k0 = q * CH;
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < CH; kk += 2) {
-      const int k = k0 + kk;
-      if (k < NB) a0 += (double)Dg[(size_t)k * NB + i] * yv[k];
-      if (kk + 1 < CH && k + 1 < NB) a1 += (double)Dg[(size_t)(k + 1) * NB + i] * yv[k + 1];
-    }
-    part[q][i] = a0 + a1;
-  }
-  __syncthreads();
-  for (int i = tid; i < NB; i += blockDim.x) {
-    double a = 0.0;
-#pragma unroll
-    for (int q = 0; q < P; ++q) a += part[q][i];
-    Y[NB + i] = a;
-  }
-}
-
-// backward chain: z_r[H] = w_r[H] - E_r[H, :] z_{r+1}[H], one wave per window
-template <int K, class T>
-__global__ void __launch_bounds__(64) ras_bwd_kernel(DeviceHDG h, const T* __restrict__ Wc, double* __restrict__ Wy) {
-  using D = RasDims<K>;
-  constexpr int NB = D::NB, NH = D::NH;
-  __shared__ double zh[NH];
-  const int w = blockIdx.x, lane = threadIdx.x;
-  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
-  if (g1 <= g0) return;
-  if (lane < NH) {
-    const double v = Wy[(size_t)(g1 - 1) * D::NSV + NB + lane];
-    zh[lane] = v;
-    Wy[(size_t)(g1 - 1) * D::NSV + 2 * NB + lane] = v;
-  }
-  T ec[NH];
-  double wcur = 0.0;
-  if (g1 - 2 >= g0 && lane < NH) {
-    const T* Eg = Wc + (size_t)(g1 - 2) * NB * NH;
-#pragma unroll
-    for (int k = 0; k < NH; ++k) ec[k] = Eg[(size_t)k * NB + lane];
-    wcur = Wy[(size_t)(g1 - 2) * D::NSV + NB + lane];
-  }
-  __syncthreads();
-  for (int g = g1 - 2; g >= g0; --g) {
-    T en[NH];
-    double wnext = 0.0;
-    if (g - 1 >= g0 && lane < NH) {
-      const T* En = Wc + (size_t)(g - 1) * NB * NH;
-#pragma unroll
-      for (int k = 0; k < NH; ++k) en[k] = En[(size_t)k * NB + lane];
-      wnext = Wy[(size_t)(g - 1) * D::NSV + NB + lane];
-    }
-    double v = wcur;
-    if (lane < NH) {
-#pragma unroll
-      for (int k = 0; k < NH; ++k) v -= (double)ec[k] * zh[k];
-    }
-    __syncthreads();
-    if (lane < NH) {
-      zh[lane] = v;
-      Wy[(size_t)g * D::NSV + 2 * NB + lane] = v;
-    }
-    __syncthreads();
-    if (g - 1 >= g0) {
-#pragma unroll
-      for (int k = 0; k < NH; ++k) ec[k] = en[k];
-      wcur = wnext;
-    }
-  }
-}
-
-// z_r[~H] = w_r[~H] - E_r[~H, :] z_{r+1}[H] (the H columns split over P = 128 / NX slices);
-// owned facets of z written
-template <int K, class T>
-__global__ void __launch_bounds__(128) ras_out_kernel(DeviceHDG h, const T* __restrict__ Wc,
-                                                      const double* __restrict__ Wy, double* __restrict__ z) {
-  using D = RasDims<K>;
-  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH, NX = NB - NH;
-  constexpr int P = 128 / NX, CH = (NH + P - 1) / P;
-  static_assert(P >= 1, "slices");
-  __shared__ double zn[NH], part[P][NX];
-  const int g = blockIdx.x, tid = threadIdx.x;
-  const int fl = h.sr_flags[g];
-  const double* Y = Wy + (size_t)g * D::NSV;
-  if ((fl & 2) && tid < NH) zn[tid] = Wy[(size_t)(g + 1) * D::NSV + 2 * NB + tid];
-  __syncthreads();
-  const T* Eg = Wc + (size_t)g * NB * NH;         // Eg[k * NB + i] = E_r[i][k]
-  if ((fl & 2) && tid < P * NX) {
-    const int i = tid % NX, q = tid / NX, k0 = q * CH;
-    double a = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < CH; ++kk) {
-      const int k = k0 + kk;
-      if (k < NH) a += (double)Eg[(size_t)k * NB + NH + i] * zn[k];
-    }
-    part[q][i] = a;
-  }
-  __syncthreads();
-  for (int i = tid; i < NB; i += blockDim.x) {
-    double v;
-    if (i < NH) {
-      v = Y[2 * NB + i];
-    } else {
-      v = Y[NB + i];
-      if (fl & 2) {
+    if (g > g0) {
+      if (gON) {
         double a = 0.0;
 #pragma unroll
-        for (int q = 0; q < P; ++q) a += part[q][i - NH];
-        v -= a;
+        for (int kk = 0; kk < CG; ++kk) {
+          const int k = gq * CG + kk;
+          if (k < NB) a += (double)gc[kk] * prev[k];
+        }
+        pg[gq][gi] = a;
+      }
+      __syncthreads();
+      if (t < NH) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < PG; ++q) a += pg[q][t];
+        yv[t] -= a;
+      }
+      __syncthreads();
+    }
+    if (dON) {
+      double a = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < CD; ++kk) {
+        const int k = dq * CD + kk;
+        if (k < NB) a += (double)dc[kk] * yv[k];
+      }
+      pd[dq][di] = a;
+    }
+    if (t < NB) prev[t] = yv[t];
+    __syncthreads();
+    if (t < NB) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < PD; ++q) a += pd[q][t];
+      Wy[(size_t)g * D::NSV + NB + t] = a;                   // w_r, read back by this thread
+    }
+  }
+  // backward sweep
+  T er[CE];
+  auto load_bwd = [&](int g) {
+    const T* Eg = Wc + (size_t)g * NB * NH;                  // Eg[k * NB + i] = E_r[i][k]
+#pragma unroll
+    for (int kk = 0; kk < CE; ++kk) {
+      const int k = dq * CE + kk;
+      er[kk] = (eON && k < NH) ? Eg[(size_t)k * NB + di] : T(0);
+    }
+  };
+  if (g1 - 2 >= g0) load_bwd(g1 - 2);
+  for (int g = g1 - 1; g >= g0; --g) {
+    double v = t < NB ? Wy[(size_t)g * D::NSV + NB + t] : 0.0;
+    if (g < g1 - 1) {
+      T ec[CE];
+#pragma unroll
+      for (int kk = 0; kk < CE; ++kk) ec[kk] = er[kk];
+      if (g - 1 >= g0) load_bwd(g - 1);
+      if (eON) {
+        double a = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < CE; ++kk) {
+          const int k = dq * CE + kk;
+          if (k < NH) a += (double)ec[kk] * zn[k];
+        }
+        pe[dq][di] = a;
+      }
+      __syncthreads();
+      if (t < NB) {
+#pragma unroll
+        for (int q = 0; q < PE; ++q) v -= pe[q][t];
       }
     }
-    const int a = i / NFF;
-    const int f = h.win_slot[5 * g + a];
-    if (f >= 0 && h.win_own[5 * g + a]) z[(size_t)f * NFF + i % NFF] = v;
+    __syncthreads();                                         // zn and pe free again
+    if (t < NB) {
+      if (t < NH) zn[t] = v;
+      const int a = t / NFF;
+      const int f = h.win_slot[5 * g + a];
+      if (f >= 0 && h.win_own[5 * g + a]) z[(size_t)f * NFF + t % NFF] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -3246,14 +3151,10 @@ static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
                                           c->n_hf, w.adj_P, x, y));
     return hipGetLastError();
   }
-  const int nsr = c->n_superrows;
   const int tp = c->timer_begin(TM_PRECOND);
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
-    hipLaunchKernelGGL((ras_pre_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wg), x, w.Wy);
-    hipLaunchKernelGGL((ras_fwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wg), w.Wy);
-    hipLaunchKernelGGL((ras_diag_kernel<KK, LT>), dim3(nsr), dim3(256), 0, c->stream, c->dhdg(), la<LT>(w.Wd), w.Wy);
-    hipLaunchKernelGGL((ras_bwd_kernel<KK, LT>), dim3(c->n_win), dim3(64), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy);
-    hipLaunchKernelGGL((ras_out_kernel<KK, LT>), dim3(nsr), dim3(128), 0, c->stream, c->dhdg(), la<LT>(w.Wc), w.Wy, y);
+    hipLaunchKernelGGL((ras_apply_kernel<KK, LT>), dim3(c->n_win), dim3(256), 0, c->stream, c->dhdg(), la<LT>(w.Wg),
+                       la<LT>(w.Wd), la<LT>(w.Wc), x, w.Wy, y);
   }));
   c->timer_end(tp);
   return hipGetLastError();
