@@ -2,7 +2,10 @@
 
 Workload (default): 256x128 quads on [0,2]x[0,0.5], wall-normal stretching to
 aspect ratio 1000, the 16 wall rows implicit HDG-MX, the rest explicit DG-IP,
-degree 4, ARS(3,4,3); Re 1e4, Ma 0.3, Pr 0.72.  One step = one full pass of the
+degree 4, ARS(3,4,3); Re 1e4, Ma 0.3, Pr 0.72; the initial profile perturbed by
+per-node uniform noise of amplitude 1 % (seed 2), the time step halved from the
+workload's until Newton converges (the run records the attempts; at the workload's
+step it converges).  One step = one full pass of the
 hot path: every explicit stage residual and ERK combination, every implicit
 Newton stage (assembly, mixed elimination, K^-1 + condensation, GMRES facet
 solve, back-substitution) and the interface coupling.
@@ -18,19 +21,23 @@ stage sequences from hipGraphs.  Newton: two full iterations, then simplified
 corrections (the last Jacobian's factors, a fresh FP64 residual) while they
 contract by < 1/20, stopped by the same increment test.  The variant with the
 Jacobian frozen after the first iteration of each stage is timed beside it
-("jacobian_frozen_per_stage", not the headline: the paper leaves it out).  The batched 512-instance vortex ensemble is timed
-the same way ("ensemble").
+("jacobian_frozen_per_stage", not the headline: the paper leaves it out), and so is
+the same plate with a smooth seeded perturbation field in place of the per-node noise
+("smooth_noise").  The batched 512-instance vortex ensemble is timed the same way
+("ensemble").
 
 Prints one JSON line.  Also reports:
   roofline      the dominant kernel: the larger, by device time per step, of the
                 mixed-block elimination (batched MFMA GEMM) and the element block
                 contraction, HIP-event timed over the timed region
+  step_roofline the step's roofline time phase by phase against the measured step
   kernels_ms_per_step  device time per step of the largest single kernels
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -55,6 +62,8 @@ def parse():
                     help="both: value from the mixed path, FP64 path timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-smooth", action="store_true",
+                    help="skip the boundary layer with the smooth perturbation field beside the per-node noise run")
     ap.add_argument("--no-jacobian-reuse", action="store_true",
                     help="skip the run with the Jacobian frozen within each stage")
     ap.add_argument("--ensemble-steps", type=int, default=3)
@@ -87,7 +96,7 @@ ELIMINATE_SHAPE = 0
 def _sample_workload(x0=0.0):
     from paper_2607_16044_amd import workloads
     return workloads.boundary_layer(nx=2, ny=16, k=4, implicit_rows=2, Lx=2 * 2.0 / 256, height=None, steps=1,
-                                    name="boundary_layer_sample", x0=x0)
+                                    name="boundary_layer_sample", x0=x0, noise_kind="node")
 
 
 def _oracle_sample_step(x0=0.0):
@@ -145,7 +154,7 @@ def cpu_baseline(shapes=None):
         per = pool.map(_oracle_worker, [0.02 * i for i in range(ncores)])
     wall = time.perf_counter() - t0
     return {"value": ncores * dof_stage / wall, "unit": "DOF-stage updates/s", "cores": ncores, "kind": "oracle",
-            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows), 1 ARS(3,4,3) step per core "
+            "sample": f"boundary layer 2x16 strip (k=4, 2 implicit HDG-MX rows, per-node noise), 1 ARS(3,4,3) step per core "
                       f"on {ncores} cores at once ({wall:.1f} s wall, {min(per):.1f}-{max(per):.1f} s per strip); "
                       f"one core alone: {dt:.1f} s",
             "one_core": {"value": dof_stage / dt, "cores": 1, "seconds": dt},
@@ -593,6 +602,26 @@ def adjoint_study(nsteps=200, window=(100, 200), checkpoint=20, h=1e-6, ndir=3, 
     return out
 
 
+def run_halving(make, precision, steps, warmup, max_halvings=5):
+    """run() on make(dt_scale) with the time step halved from the workload's until the
+    warm-up and timed steps all converge (a step that fails to converge or goes non-finite
+    restarts the attempt at half the step).  Returns (result, workload, attempts)."""
+    from paper_2607_16044_amd import binding
+    attempts = []
+    for h in range(max_halvings + 1):
+        scale = 0.5 ** h
+        wl = make(scale)
+        try:
+            res = run(wl, precision, steps, warmup)
+        except binding.IMEXError as e:
+            attempts.append({"dt_scale": scale, "error": str(e)[:120]})
+            print(f"{wl.name}: dt scale {scale:g} failed", file=sys.stderr, flush=True)
+            continue
+        attempts.append({"dt_scale": scale, "ok": True})
+        return res, wl, attempts
+    raise RuntimeError(f"no converging time step within {max_halvings} halvings: {attempts}")
+
+
 def run_ensemble(precision, steps, warmup, n=512):
     """The batched vortex ensemble (n instances, 8x8..48x48, p in 1..4), one context per
     degree, autotuned launch shapes and graph replay of the explicit stages."""
@@ -652,9 +681,12 @@ def main():
             out[p], _ = run_ensemble(p, args.ensemble_steps, 1)
         print(json.dumps(out))
         return
-    wl = workloads.get(args.workload)
     main_prec = "fp64" if args.precision == "fp64" else "mixed"
-    res = run(wl, main_prec, args.steps, args.warmup)
+
+    def make(scale):
+        w = workloads.get(args.workload)
+        return dataclasses.replace(w, dt=w.dt * scale) if scale != 1.0 else w
+    res, wl, attempts = run_halving(make, main_prec, args.steps, args.warmup)
     other = run(wl, "fp64", args.steps, args.warmup) if args.precision == "both" else None
     n_dof, s = wl.n_dof, wl.stages
     value = n_dof * s * args.steps / res["elapsed"]
@@ -706,7 +738,9 @@ def main():
                    "hdg": "MX" if wl.hdg_variant == workloads.HDG_MX else "IP", "precision": main_prec,
                    "newton_corrections_per_step": res["newton"], "jacobians_per_step": res["jacobians"],
                    "gmres_its_per_step": res["gmres"], "newton_simplified": 1,
-                   "gmres_forcing": 3, "launch_shapes": res["shapes"]},
+                   "gmres_forcing": 3, "launch_shapes": res["shapes"],
+                   "noise": "per-node uniform, 1 %, seed 2" if wl.name == "boundary_layer" else None,
+                   "dt": wl.dt, "dt_attempts": attempts},
         "roofline": roof,
         "step_roofline": step_roofline(wl, res, 1e3 * res["elapsed"] / args.steps, main_prec),
         "phases_ms_per_step": phases,
@@ -731,6 +765,14 @@ def main():
             "value": fv, "ms_per_step": 1e3 * fr["elapsed"] / args.steps, "precision": main_prec,
             "newton_corrections_per_step": fr["newton"], "jacobians_per_step": fr["jacobians"],
             "gmres_its_per_step": fr["gmres"], "over_value": fv / value, "max_rel_diff_vs_value_run": du}
+    if not args.no_smooth and args.workload == "boundary_layer":
+        # the same plate with the smooth seeded perturbation field in place of per-node noise
+        sm = run(workloads.get("boundary_layer_smooth"), main_prec, args.steps, args.warmup)
+        out["smooth_noise"] = {"workload": "boundary_layer_smooth", "precision": main_prec,
+                               "value": n_dof * s * args.steps / sm["elapsed"],
+                               "ms_per_step": 1e3 * sm["elapsed"] / args.steps,
+                               "newton_corrections_per_step": sm["newton"], "jacobians_per_step": sm["jacobians"],
+                               "gmres_its_per_step": sm["gmres"]}
     if not args.no_ensemble:
         ens_m, _ = run_ensemble("mixed", args.ensemble_steps, 1)
         ens_d, _ = run_ensemble("fp64", args.ensemble_steps, 1)

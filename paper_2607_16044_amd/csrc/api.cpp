@@ -1243,6 +1243,8 @@ void imex_destroy(imex_ctx* c) {
   c->timers_resolve();
   for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
   c->ev_free.clear();
+  for (hipEvent_t e : {c->pev_f[0], c->pev_f[1], c->pev_g[0][0], c->pev_g[0][1], c->pev_g[1][0], c->pev_g[1][1]})
+    if (e) hipEventDestroy(e);
   c->drop_graphs();
   if (c->gstream) hipStreamDestroy(c->gstream);
   c->gstream = nullptr;

@@ -137,6 +137,14 @@ struct imex_ctx {
   int prec_extra = 0;           // GMRES iterations above prec_base since then
   double newton_q2 = 0.0;       // contraction of the second Newton correction in the last stage (0: none yet)
   double prec_dt_a = 0.0;       // dt a_ii of the factorised system
+  // refactorisation cost in GMRES iterations, from the device time of the last
+  // factorisation over that of an iteration (events read once the stream has passed them)
+  double prec_cost_its = 8.0;
+  double prec_fac_ms = 0.0, prec_it_ms = 0.0;
+  hipEvent_t pev_f[2] = {nullptr, nullptr};                  // factorisation begin, end
+  hipEvent_t pev_g[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // GMRES begin, end (two slots)
+  bool pev_fset = false, pev_gset[2] = {false, false};
+  int pev_gits[2] = {0, 0}, pev_slot = 0;
   // device copies
   double *d_hx = nullptr, *d_hy = nullptr, *d_dts = nullptr;
   int *d_nbr = nullptr, *d_bcf = nullptr;

@@ -3194,7 +3194,41 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
 constexpr int GM_CHECK = 8;
 constexpr int GM_FIRST = 4;           // first block without a history
 constexpr size_t GM_MAXGRAPHS = 512;  // captured block graphs kept per context
-constexpr int PREC_REFRESH_ITS = 8;
+// Facet preconditioner reuse: refactorise once the GMRES iterations spent above the count
+// right after the last factorisation exceed what a factorisation costs, in iterations (the
+// online rule that pays at most twice the best choice in hindsight).  The cost ratio is
+// measured: the device time of the last factorisation over the device time per iteration
+// of an earlier facet solve (its events complete once a later solve has synchronised),
+// smoothed, within [PREC_COST_MIN, PREC_COST_MAX]; 8 iterations until measured.
+constexpr double PREC_COST_MIN = 2.0, PREC_COST_MAX = 200.0;
+
+static hipError_t prec_events(imex_ctx* c) {
+  for (hipEvent_t* e : {&c->pev_f[0], &c->pev_f[1], &c->pev_g[0][0], &c->pev_g[0][1], &c->pev_g[1][0],
+                        &c->pev_g[1][1]})
+    if (!*e) {
+      const hipError_t r = hipEventCreate(e);
+      if (r != hipSuccess) return r;
+    }
+  return hipSuccess;
+}
+
+// after a facet solve returned (it synchronised the stream after every earlier event):
+// read the last factorisation's time and the other slot's solve time
+static void prec_cost_update(imex_ctx* c) {
+  float ms = 0.0f;
+  if (c->pev_fset && hipEventElapsedTime(&ms, c->pev_f[0], c->pev_f[1]) == hipSuccess) {
+    c->prec_fac_ms = ms;
+    c->pev_fset = false;
+  }
+  const int o = c->pev_slot;                          // the slot not written by the last solve
+  if (c->pev_gset[o] && c->pev_gits[o] > 0 && hipEventElapsedTime(&ms, c->pev_g[o][0], c->pev_g[o][1]) == hipSuccess) {
+    const double it_ms = ms / c->pev_gits[o];
+    c->prec_it_ms = c->prec_it_ms > 0.0 ? 0.5 * (c->prec_it_ms + it_ms) : it_ms;
+    c->pev_gset[o] = false;
+  }
+  if (c->prec_fac_ms > 0.0 && c->prec_it_ms > 0.0)
+    c->prec_cost_its = std::min(PREC_COST_MAX, std::max(PREC_COST_MIN, c->prec_fac_ms / c->prec_it_ms));
+}
 // a simplified Newton correction follows only a correction that contracted by at least this
 constexpr double SIMPLIFIED_QMAX = 0.05;
 // relative residual of the facet solve of a simplified correction
@@ -3408,7 +3442,11 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     tt = c->timer_begin(TM_FACET);
     HTRY(launch_facet_rhs(c, b));
     if (!c->prec_valid) {
+      HTRY(prec_events(c));
+      HTRY(hipEventRecord(c->pev_f[0], c->stream));
       HTRY(launch_ras_factor(c));
+      HTRY(hipEventRecord(c->pev_f[1], c->stream));
+      c->pev_fset = true;
       c->prec_valid = true;
       c->prec_fresh = true;
       c->prec_dt_a = dt_a;
@@ -3428,20 +3466,29 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
       c->opt.gmres_rtol = std::max(rtol, std::min(FIRST_CORRECTION_RTOL, 1e-2 * c->newton_q2));
     if (simplified) c->opt.gmres_rtol = std::max(c->opt.gmres_rtol, SIMPLIFIED_GMRES_RTOL);
     tt = c->timer_begin(TM_GMRES);
+    const int slot = c->pev_slot;
+    if (c->pev_g[slot][0]) HTRY(hipEventRecord(c->pev_g[slot][0], c->stream));
     imex_status s = gmres(c, b, dx, &its, simplified ? 0 : std::min(it, 4), &gm_reached);
+    if (c->pev_g[slot][0]) {
+      HTRY(hipEventRecord(c->pev_g[slot][1], c->stream));
+      c->pev_gset[slot] = true;
+      c->pev_gits[slot] = its;
+      c->pev_slot = 1 - slot;
+    }
     c->timer_end(tt);
     c->opt.gmres_rtol = rtol;
     if (s != IMEX_OK) return s;
     gm_total += its;
+    prec_cost_update(c);
     // refactorise once the GMRES iterations spent above the post-refactorisation count
-    // exceed the cost of a refactorisation (about PREC_REFRESH_ITS iterations)
+    // exceed the measured cost of a refactorisation
     if (c->prec_fresh) {
       c->prec_base = its;
       c->prec_extra = 0;
       c->prec_fresh = false;
     } else {
       c->prec_extra += std::max(0, its - c->prec_base);
-      if (c->prec_extra > PREC_REFRESH_ITS) c->prec_valid = false;
+      if (c->prec_extra > c->prec_cost_its) c->prec_valid = false;
     }
     tt = c->timer_begin(TM_BACKSUB);
     HTRY(launch_backsub(c, dx, U, part));

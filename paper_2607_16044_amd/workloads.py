@@ -199,7 +199,13 @@ def boundary_layer(nx: int = 256, ny: int = 128, k: int = 4, implicit_rows: int 
                    height: Optional[float] = 0.5, Re: float = 1.0e4, Ma: float = 0.3, Pr: float = 0.72,
                    steps: int = 200, seed: int = 2, noise: float = 0.01, name: str = "boundary_layer",
                    hdg_variant: int = HDG_MX, tableau: str = "ARS343", dt_scale: float = 1.0,
-                   x0: float = 0.0) -> Workload:
+                   x0: float = 0.0, noise_kind: str = "smooth") -> Workload:
+    """Flat-plate boundary layer.  noise_kind "smooth": the perturbation is a seeded
+    random-phase Fourier field; "node": independent uniform draws in [-1, 1] at every
+    node (the same seed, one draw per velocity component and node in the order the nodes
+    are passed), both of amplitude `noise` and damped by the profile."""
+    if noise_kind not in ("smooth", "node"):
+        raise ValueError("noise_kind is 'smooth' or 'node'")
     gamma = 1.4
     hx = Lx / nx
     h0 = (2.0 / 256.0) / 1000.0          # first-cell aspect ratio 1000 at the reference spacing 2/256
@@ -226,9 +232,14 @@ def boundary_layer(nx: int = 256, ny: int = 128, k: int = 4, implicit_rows: int 
     def ic(X, Y, elem=None, node=None):
         delta = 1.85 * np.sqrt((X + 0.05) / Re)
         base = np.tanh(Y / delta)
+        if noise_kind == "node":
+            draws = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(2,) + np.shape(X))
+            n0, n1 = draws[0], draws[1]
+        else:
+            n0, n1 = xi(0, X, Y), xi(1, X, Y)
         # 1% perturbation of the free-stream speed, damped by the profile so the wall stays no-slip
-        u = base * (1.0 + noise * xi(0, X, Y))
-        v = noise * base * xi(1, X, Y)
+        u = base * (1.0 + noise * n0)
+        v = noise * base * n1
         rho = np.ones_like(u)
         p = np.full_like(u, p_inf)
         return _conservative(rho, u, v, p, gamma)
@@ -275,7 +286,8 @@ def get(name: str) -> Workload:
     table: Dict[str, Callable[[], Workload]] = {
         "vortex": lambda: vortex(),
         "vortex_small": lambda: vortex(nx=6, ny=6, k=2, strip_rows=2, steps=3, name="vortex_small"),
-        "boundary_layer": lambda: boundary_layer(),
+        "boundary_layer": lambda: boundary_layer(noise_kind="node"),
+        "boundary_layer_smooth": lambda: boundary_layer(name="boundary_layer_smooth"),
         "boundary_layer_small": lambda: boundary_layer(nx=6, ny=6, k=2, implicit_rows=2, Lx=6 * 2.0 / 256,
                                                        height=None, steps=2, name="boundary_layer_small"),
     }
