@@ -292,3 +292,131 @@ def get(name: str) -> Workload:
                                                        height=None, steps=2, name="boundary_layer_small"),
     }
     return table[name]()
+
+
+# ---------------------------------------------------------------------------
+# 3D (hexahedra): the explicit DG residual of the Navier-Stokes channel
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload3D:
+    """A Cartesian hexahedral mesh x(nx+1) x y(ny+1) x z(nz+1), element (i, j, l) at index
+    i + nx (j + ny l), five conservative variables (rho, rho u, rho v, rho w, rho E); the
+    boundary of each side is BC_PERIODIC or BC_FARFIELD (all elements explicit)."""
+    name: str
+    xgrid: np.ndarray
+    ygrid: np.ndarray
+    zgrid: np.ndarray
+    bc: tuple                    # (-x, +x, -y, +y, -z, +z)
+    degree: int
+    gamma: float
+    R: float
+    mu: float
+    Pr: float
+    viscous: bool
+    u_inf: np.ndarray            # (5,)
+    dg_flux: int
+    ic: Callable                 # ic(x, y, z) -> (5, ...) conservative
+    alpha_dg: float = 1.0
+
+    @property
+    def nx(self) -> int:
+        return len(self.xgrid) - 1
+
+    @property
+    def ny(self) -> int:
+        return len(self.ygrid) - 1
+
+    @property
+    def nz(self) -> int:
+        return len(self.zgrid) - 1
+
+    @property
+    def n_elem(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def nodes_per_elem(self) -> int:
+        return (self.degree + 1) ** 3
+
+    @property
+    def n_dof(self) -> int:
+        return self.n_elem * self.nodes_per_elem * 5
+
+
+def conservative3d(rho, u, v, w, p, gamma):
+    return np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def channel3d(nx: int = 64, ny: int = 32, nz: int = 32, k: int = 3, Re: float = 3000.0, Ma: float = 0.2,
+              Pr: float = 0.72, beta: float = 4.0610, seed: int = 3, amp: float = 0.05, viscous: bool = True,
+              flux: int = FLUX_VIJAYASUNDARAM, name: str = "channel3d") -> Workload3D:
+    """The 3D channel [0, 4 pi] x [-1, 1] x [0, 2 pi] with tanh-stretched rows
+    y_j = tanh(beta (2 j / ny - 1)) / tanh(beta) (first-cell aspect ratio about 500 at
+    ny = 32), periodic in x and z, Re 3000 on the half-height and bulk velocity, Ma 0.2.
+    Initial state: Poiseuille u = 1.5 (1 - y^2) plus sinusoidal perturbations of u, v, w
+    with random phases (seed 3), amplitude 5 %, damped by (1 - y^2); rho = 1, p = p_inf.
+    The explicit residual is exercised on all elements, the y = +-1 sides being far-field
+    boundaries at the wall-layer state (the wall layers themselves are the implicit
+    HDG-IP region of the channel, which this engine builds in 2D only)."""
+    gamma = 1.4
+    Lx, Lz = 4.0 * math.pi, 2.0 * math.pi
+    x = np.linspace(0.0, Lx, nx + 1)
+    j = np.arange(ny + 1)
+    y = np.tanh(beta * (2.0 * j / ny - 1.0)) / math.tanh(beta)
+    z = np.linspace(0.0, Lz, nz + 1)
+    R = 1.0 / (gamma * Ma * Ma)
+    p_inf = 1.0 / (gamma * Ma * Ma)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=(3, 3))
+    kx = [1, 2, 3]
+    kz = [2, 1, 3]
+
+    def pert(c, X, Y, Z):
+        s = np.zeros_like(X)
+        for m in range(3):
+            s = s + np.sin(kx[m] * 2.0 * math.pi * X / Lx + kz[m] * 2.0 * math.pi * Z / Lz + ph[c, m])
+        return s / 3.0
+
+    def ic(X, Y, Z):
+        damp = 1.0 - Y * Y
+        u = 1.5 * damp + amp * damp * pert(0, X, Y, Z)
+        v = amp * damp * pert(1, X, Y, Z)
+        w = amp * damp * pert(2, X, Y, Z)
+        return conservative3d(np.ones_like(X), u, v, w, np.full_like(X, p_inf), gamma)
+
+    u_inf = conservative3d(np.array(1.0), np.array(0.0), np.array(0.0), np.array(0.0), np.array(p_inf),
+                           gamma).astype(float)
+    return Workload3D(name=name, xgrid=x, ygrid=y, zgrid=z,
+                      bc=(BC_PERIODIC, BC_PERIODIC, BC_FARFIELD, BC_FARFIELD, BC_PERIODIC, BC_PERIODIC),
+                      degree=k, gamma=gamma, R=R, mu=(1.0 / Re) if viscous else 0.0, Pr=Pr, viscous=viscous,
+                      u_inf=u_inf, dg_flux=flux, ic=ic)
+
+
+def smooth_box3d(n=(3, 3, 3), k: int = 2, viscous: bool = True, mu: float = 0.02, flux: int = FLUX_VIJAYASUNDARAM,
+                 bc=(BC_PERIODIC,) * 6, stretch: float = 0.0, name: str = "box3d") -> Workload3D:
+    """Unit cube with a smooth state varying in all three directions (all velocity
+    components nonzero); `stretch` > 0 grades the y rows geometrically."""
+    gamma = 1.4
+    nx, ny, nz = n
+    x = np.linspace(0.0, 1.0, nx + 1)
+    if stretch > 0.0:
+        h = (1.0 + stretch) ** np.arange(ny)
+        y = np.concatenate([[0.0], np.cumsum(h)]) / h.sum()
+    else:
+        y = np.linspace(0.0, 1.0, ny + 1)
+    z = np.linspace(0.0, 1.0, nz + 1)
+    tp = 2.0 * math.pi
+
+    def ic(X, Y, Z):
+        rho = 1.0 + 0.2 * np.sin(tp * X) * np.cos(tp * Z) + 0.1 * np.cos(tp * Y)
+        u = 0.3 + 0.1 * np.cos(tp * (X + Y))
+        v = 0.2 - 0.1 * np.sin(tp * (X + Z))
+        w = -0.1 + 0.15 * np.sin(tp * (Y - Z))
+        p = 2.5 + 0.3 * np.cos(tp * Y) * np.sin(tp * Z)
+        return conservative3d(rho, u, v, w, p, gamma)
+
+    u_inf = conservative3d(np.array(1.0), np.array(0.3), np.array(0.2), np.array(-0.1), np.array(2.5), gamma)
+    return Workload3D(name=name, xgrid=x, ygrid=y, zgrid=z, bc=tuple(bc), degree=k, gamma=gamma, R=1.0,
+                      mu=mu if viscous else 0.0, Pr=0.72, viscous=viscous, u_inf=np.asarray(u_inf, float),
+                      dg_flux=flux, ic=ic)
