@@ -370,6 +370,52 @@ const char* imex_status_str(imex_status s);
 const char* imex_last_error(const imex_ctx* ctx);
 void imex_destroy(imex_ctx* ctx);
 
+/* ------------------------------------------------------------------------- *
+ * Three dimensions: the explicit DG residual on hexahedra (the explicit part of
+ * the 3D channel).  The paper's forms are two-dimensional; the 3D residual is
+ * eq. bilinear_form_interior_sdg with a third direction and five conservative
+ * variables (rho, rho u, rho v, rho w, rho E): convective and viscous fluxes of
+ * Sec. 2 (lambda = -2 mu / 3), Vijayasundaram or Lax-Friedrichs faces, the
+ * interior-penalty consistency, adjoint and penalty terms, far-field faces as in
+ * App. B.1.1.  All elements are explicit; the implicit wall layers are 2D only.
+ * ------------------------------------------------------------------------- */
+typedef struct imex3d_ctx imex3d_ctx;
+
+/* Cartesian hexahedral mesh: element (i, j, l) at index i + nx (j + ny l) covers
+ * [x_i, x_i+1] x [y_j, y_j+1] x [z_l, z_l+1]; bc[] for the sides -x, +x, -y, +y,
+ * -z, +z, each IMEX_BC_PERIODIC (paired) or IMEX_BC_FARFIELD; degree 1..3. */
+typedef struct {
+  int nx, ny, nz;
+  const double* xgrid;   /* host, nx+1 strictly increasing */
+  const double* ygrid;   /* host, ny+1 */
+  const double* zgrid;   /* host, nz+1 */
+  int bc[6];
+  int degree;
+} imex3d_mesh_desc;
+
+/* Create a 3D residual context.  phys: gamma, R, mu, Pr, viscous (its u_inf is not
+ * used); dg_flux: IMEX_FLUX_*; alpha_dg: penalty factor (tau = alpha (k+1)^2 / l,
+ * l = |T| / |dT|, the smaller l of the two sides on interior faces); u_inf: host,
+ * the five-variable far-field state.  Allocates the face-trace records
+ * (E x 6 x Q^2 x 10 doubles).  Errors: EINVAL, ENOMEM, EDEVICE. */
+imex_status imex3d_create(const imex3d_mesh_desc* mesh, const imex_physics* phys, int dg_flux, double alpha_dg,
+                          const double u_inf[5], void* stream, imex3d_ctx** out);
+
+/* out[0..3] = n_elem, nodes per element (k+1)^3, quadrature points per
+ * direction, workspace bytes.  host. */
+imex_status imex3d_query_sizes(const imex3d_ctx* ctx, long long out[4]);
+
+/* Node coordinates, host out [E][(k+1)^3] each (node a + N b + N^2 c at the
+ * Gauss-Legendre points of the element's three axes). */
+imex_status imex3d_node_coords(const imex3d_ctx* ctx, double* x, double* y, double* z);
+
+/* R^DG (eq. bilinear_form_interior_sdg in 3D) so that M dU/dt = -R: U and R dev
+ * [E][5][(k+1)^3], on the context's stream (asynchronous).  Errors: EINVAL, EDEVICE. */
+imex_status imex3d_residual(imex3d_ctx* ctx, const double* U, double* R);
+
+const char* imex3d_last_error(const imex3d_ctx* ctx);
+void imex3d_destroy(imex3d_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

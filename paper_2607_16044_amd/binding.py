@@ -28,12 +28,20 @@ EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coo
            "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
            "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes", "imex_dg_residual_noalloc",
            "imex_set_mms_source", "imex_mms_load",
+           "imex3d_create", "imex3d_query_sizes", "imex3d_node_coords", "imex3d_residual", "imex3d_last_error",
+           "imex3d_destroy",
            "imex_status_str", "imex_last_error", "imex_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("xgrid", ctypes.POINTER(ctypes.c_double)),
                 ("ygrid", ctypes.POINTER(ctypes.c_double)), ("bc", ctypes.c_int * 4), ("degree", ctypes.c_int)]
+
+
+class MeshDesc3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("xgrid", ctypes.POINTER(ctypes.c_double)), ("ygrid", ctypes.POINTER(ctypes.c_double)),
+                ("zgrid", ctypes.POINTER(ctypes.c_double)), ("bc", ctypes.c_int * 6), ("degree", ctypes.c_int)]
 
 
 class Physics(ctypes.Structure):
@@ -107,6 +115,15 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(Stats)]
     lib.imex_set_graphs.argtypes = [P, ctypes.c_int]
     lib.imex_vjp_ark_step.argtypes = [P, ctypes.POINTER(Tableau), D, P, P, P]
+    lib.imex3d_create.argtypes = [ctypes.POINTER(MeshDesc3), ctypes.POINTER(Physics), ctypes.c_int, D,
+                                  ctypes.POINTER(D), P, ctypes.POINTER(ctypes.c_void_p)]
+    lib.imex3d_query_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.imex3d_node_coords.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.imex3d_residual.argtypes = [P, P, P]
+    lib.imex3d_last_error.argtypes = [P]
+    lib.imex3d_last_error.restype = ctypes.c_char_p
+    lib.imex3d_destroy.argtypes = [P]
+    lib.imex3d_destroy.restype = None
     lib.imex_status_str.argtypes = [ctypes.c_int]
     lib.imex_status_str.restype = ctypes.c_char_p
     lib.imex_last_error.argtypes = [P]
@@ -114,7 +131,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_destroy.argtypes = [P]
     lib.imex_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("imex_status_str", "imex_last_error", "imex_destroy"):
+        if name not in ("imex_status_str", "imex_last_error", "imex_destroy", "imex3d_last_error", "imex3d_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -506,3 +523,65 @@ class Ensemble:
             self._pool = None
         for _, eng in self.groups:
             eng.close()
+
+
+class Engine3D:
+    """The explicit DG residual on a 3D hexahedral mesh (all elements explicit)."""
+
+    def __init__(self, wl, device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the engine runs only on the GPU")
+        self.lib = load_library()
+        self.wl = wl
+        self.device = torch.device("cuda") if device is None else device
+        self._g = [np.ascontiguousarray(a, dtype=np.float64) for a in (wl.xgrid, wl.ygrid, wl.zgrid)]
+        dp = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in self._g]
+        mesh = MeshDesc3(wl.nx, wl.ny, wl.nz, dp[0], dp[1], dp[2], (ctypes.c_int * 6)(*wl.bc), wl.degree)
+        phys = Physics(wl.gamma, wl.R, wl.mu, wl.Pr, int(wl.viscous), (ctypes.c_double * 4)(0, 0, 0, 0))
+        uinf = (ctypes.c_double * 5)(*[float(x) for x in wl.u_inf])
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.imex3d_create(ctypes.byref(mesh), ctypes.byref(phys), int(wl.dg_flux), float(wl.alpha_dg), uinf,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != 0:
+            raise IMEXError(st, "imex3d_create")
+        self.ctx = ctx
+        out = (ctypes.c_longlong * 4)()
+        self._check(self.lib.imex3d_query_sizes(self.ctx, out))
+        self.n_elem, self.nodes_per_elem = int(out[0]), int(out[1])
+
+    def _check(self, st: int):
+        if st != 0:
+            raise IMEXError(st, self.lib.imex3d_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.imex3d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state_shape(self):
+        return (self.n_elem, 5, self.nodes_per_elem)
+
+    def node_coords(self):
+        n = self.n_elem * self.nodes_per_elem
+        xyz = [np.zeros(n) for _ in range(3)]
+        self._check(self.lib.imex3d_node_coords(self.ctx, *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                             for a in xyz]))
+        return tuple(a.reshape(self.n_elem, self.nodes_per_elem) for a in xyz)
+
+    def initial_state(self) -> torch.Tensor:
+        X, Y, Z = self.node_coords()
+        U = np.moveaxis(self.wl.ic(X, Y, Z), 0, 1)
+        return torch.tensor(np.ascontiguousarray(U), dtype=torch.float64, device=self.device)
+
+    def residual(self, U: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if R is None:
+            R = torch.empty(self.state_shape(), dtype=torch.float64, device=self.device)
+        self._check(self.lib.imex3d_residual(self.ctx, _ptr(U), _ptr(R)))
+        return R

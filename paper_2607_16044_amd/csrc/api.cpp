@@ -139,6 +139,12 @@ void free_regions(imex_ctx* c) {
 
 }  // namespace
 
+// the 1D tables and Gauss rule for the other translation units (the 3D residual)
+namespace imex {
+void basis_table_1d(int K, BasisTable& T) { build_table(K, T); }
+void gauss_legendre_rule(int n, double* x, double* w) { gauss_legendre(n, x, w); }
+}  // namespace imex
+
 void imex_ctx::drop_graphs() {
   for (StageGraph& g : sg) {
     if (g.exec) hipGraphExecDestroy(g.exec);

@@ -11,7 +11,7 @@ from _common import ROOT, ensure_built
 
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "imexhdg.h")).read()
-    decl = r"^(?:imex_status|const char\*|void)\s+(imex_[a-z_0-9]+)\s*\("
+    decl = r"^(?:imex_status|const char\*|void)\s+(imex(?:3d)?_[a-z_0-9]+)\s*\("
     return sorted(set(re.findall(decl, text, flags=re.M)))
 
 
