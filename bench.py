@@ -62,6 +62,8 @@ def parse():
                     help="both: value from the mixed path, FP64 path timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--channel3d", action="store_true",
+                    help="time the explicit DG residual of the 3D channel and print its own JSON line")
     ap.add_argument("--no-smooth", action="store_true",
                     help="skip the boundary layer with the smooth perturbation field beside the per-node noise run")
     ap.add_argument("--no-jacobian-reuse", action="store_true",
@@ -602,6 +604,41 @@ def adjoint_study(nsteps=200, window=(100, 200), checkpoint=20, h=1e-6, ndir=3, 
     return out
 
 
+def channel3d_study(evals=20, warmup=3, k=3):
+    """The explicit DG residual of the 3D channel (64 x 32 x 32 hexahedra, k = 3, 21 M
+    unknowns, Navier-Stokes, Vijayasundaram faces): device time per residual evaluation
+    (torch events on the engine's stream, which is torch's current stream), unknowns per
+    second, and the HBM bytes of the design (state read, residual written, the face-trace
+    records written once and read by both sides of each face) against the 8 TB/s peak."""
+    import torch
+    from paper_2607_16044_amd import binding, workloads
+    wl = workloads.channel3d(k=k)
+    eng = binding.Engine3D(wl)
+    U = eng.initial_state()
+    R = torch.empty_like(U)
+    for _ in range(warmup):
+        eng.residual(U, R)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(evals):
+        eng.residual(U, R)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / evals
+    N, Q = k + 1, (3 * k + 2) // 2
+    E = eng.n_elem
+    state = 2.0 * E * 5 * N ** 3 * 8
+    records = 3.0 * E * 6 * Q * Q * 10 * 8
+    eng.close()
+    return {"study": "3D channel explicit DG residual", "workload": f"channel3d 64x32x32, k={k}, Navier-Stokes, "
+            "Vijayasundaram, far-field at y = +-1, periodic in x and z", "n_dof": wl.n_dof,
+            "ms_per_residual": ms, "dof_per_s": wl.n_dof / (ms * 1e-3),
+            "bytes_state": state, "bytes_records": records,
+            "hbm_frac_design": (state + records) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+            "hbm_frac_state_only": state / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9)}
+
+
 def run_halving(make, precision, steps, warmup, max_halvings=5):
     """run() on make(dt_scale) with the time step halved from the workload's until the
     warm-up and timed steps all converge (a step that fails to converge or goes non-finite
@@ -669,6 +706,9 @@ def main():
         return
     if args.mx_ip_study:
         print(json.dumps(mx_ip_study()))
+        return
+    if args.channel3d:
+        print(json.dumps(channel3d_study()))
         return
     if args.adjoint_study:
         n = args.adjoint_steps
