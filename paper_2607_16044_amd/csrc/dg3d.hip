@@ -166,15 +166,14 @@ __global__ void __launch_bounds__(NT3) dg3d_trace_kernel(Mesh3D m, Gas3D g, Basi
     const int f = i / (10 * NF2), r = i % (10 * NF2), kind = r / (5 * NF2), v = (r / NF2) % 5, tt = r % NF2;
     const int d = f >> 1, s = f & 1;
     const int j1 = tt % N, j2 = tt / N;     // tangential node indices (first, second tangential axis)
+    // node strides of the normal and the two tangential axes
+    const int sd = d == 0 ? 1 : (d == 1 ? N : N * N);
+    const int s1 = d == 0 ? N : 1, s2 = d == 2 ? N : N * N;
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      int idx[3];
-      idx[d] = a;
-      idx[d == 0 ? 1 : 0] = j1;
-      idx[d == 2 ? 1 : 2] = j2;
       const double wgt = kind == 0 ? tb.LE[s][a] : tb.DE[s][a];
-      acc += wgt * su[v][idx[0] + N * idx[1] + N * N * idx[2]];
+      acc += wgt * su[v][a * sd + j1 * s1 + j2 * s2];
     }
     ec[f][kind][v][tt] = acc;
   }
@@ -200,19 +199,21 @@ __global__ void __launch_bounds__(NT3) dg3d_trace_kernel(Mesh3D m, Gas3D g, Basi
           gn += L1 * L2 * x1;
         }
       Uf[v] = val;
-      G[v][d] = gn * 2.0 / h[d];
-      G[v][t1] = g1 * 2.0 / h[t1];
-      G[v][t2] = g2 * 2.0 / h[t2];
+      const double vn = gn * 2.0 / h[d], v1 = g1 * 2.0 / h[t1], v2 = g2 * 2.0 / h[t2];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) G[v][ax] = ax == d ? vn : (ax == t1 ? v1 : v2);
     }
     double* r = rec + (((size_t)e * 6 + f) * QQ + pnt) * RS;
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] = Uf[v];
     if (RS > 5) {
       const bool far = m.nbr[6 * (size_t)e + f] < 0 && m.bc[6 * (size_t)e + f] == IMEX_BC_FARFIELD;
-      double n[3] = {0.0, 0.0, 0.0};
-      n[d] = (f & 1) ? 1.0 : -1.0;
-      double F[5][3];
-      visc3(far ? g.uinf : Uf, G, g, F);
+      const double sg = (f & 1) ? 1.0 : -1.0;
+      const double n[3] = {d == 0 ? sg : 0.0, d == 1 ? sg : 0.0, d == 2 ? sg : 0.0};
+      double F[5][3], Ws[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ws[v] = far ? g.uinf[v] : Uf[v];
+      visc3(Ws, G, g, F);
 #pragma unroll
       for (int v = 0; v < 5; ++v) r[5 + v] = F[v][0] * n[0] + F[v][1] * n[1] + F[v][2] * n[2];
     }
@@ -232,9 +233,11 @@ __global__ void __launch_bounds__(NT3) dg3d_residual_kernel(Mesh3D m, Gas3D g, B
   constexpr int NX = 5 * 2 * Q * N * N, NY = 5 * 3 * Q * Q * N, NQ4 = 5 * 4 * QQQ;
   constexpr int NFB = 6 * 5 * QQ * 4;                    // face buffers: s and g per face point
   constexpr int BIG = NQ4 > NFB ? NQ4 : NFB;
+  constexpr int NHB = 6 * 5 * 2 * NF2;                   // per-face 2D contractions (after the volume passes)
+  constexpr int NTY = NY > NHB ? NY : NHB;
   __shared__ double su[5 * NN], rv[5 * NN];
-  __shared__ double tx[NX], ty[NY], big[BIG];
-  __shared__ double hb[6 * 5 * 2 * NF2];
+  __shared__ double tx[NX], ty[NTY], big[BIG];
+  double* hb = ty;                                       // ty is free once the transposed y pass has run
   const int e = blockIdx.x, t = threadIdx.x;
   const double* h = m.h + 3 * (size_t)e;
   const double hx = h[0], hy = h[1], hz = h[2];
