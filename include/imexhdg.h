@@ -331,7 +331,8 @@ imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
  * from (U, Uhat) (Uhat dev, required) and Uhatbar (dev out, facets) receives
  * their adjoint through the lifting; otherwise Uhat, Uhatbar may be NULL.
  * Point-wise flux Jacobians by forward-mode dual numbers, contracted with the
- * transposed basis; deterministic (no atomics).  Errors: EINVAL. */
+ * transposed basis; deterministic (no atomics).  The first call allocates the
+ * transposed-product buffers (kept by the context).  Errors: EINVAL, ENOMEM. */
 imex_status imex_vjp_dg_residual(imex_ctx* ctx, const double* U, const double* Uhat, const double* Rbar,
                                  double* Ubar, double* Uhatbar);
 
@@ -360,8 +361,11 @@ imex_status imex_vjp_ark_step(imex_ctx* ctx, const imex_tableau* tab, double dt,
  * adjoint times the residual's exact derivative in p (the far-field face integrand of
  * R^DG differentiated by a dual number seeded in u_inf, and A^-(Uhat) du_inf for the
  * far-field facet rows).  st host (nullable): gmres_its of the transposed solves.
- * Errors: ENOTIMPL for implicit tableaux that are not stiffly accurate, or for duinf
- * without an implicit region; as imex_ark_step. */
+ * The first reverse-mode call on a context allocates its adjoint workspaces (the
+ * step's stage tape, the facet block-Jacobi factors and the transposed-product
+ * buffers); later calls reuse them and allocate nothing.  Errors: ENOMEM (that first
+ * allocation), ENOTIMPL for implicit tableaux that are not stiffly accurate, or for
+ * duinf without an implicit region; as imex_ark_step. */
 imex_status imex_vjp_imex_step(imex_ctx* ctx, const imex_tableau* tab, double dt, const double* U,
                                const double* Uhat, const double* Ubar_next, const double* Uhatbar_next, double* Ubar,
                                double* Uhatbar, const double* duinf, double* pbar, imex_stats* st);
