@@ -273,6 +273,14 @@ template <int K> using MxRec = PointRec<K, true>;
 // destination of the point Jacobians.)
 // JAC = false: point values and residual rows only (a separate instantiation without the
 // dual-number passes).
+// EPB elements per workgroup (256 / EPB threads each, one LDS slot each): the low degrees
+// have too few points to occupy 256 threads per element.  A slot past the last element
+// repeats the last element (identical values to the same addresses).
+template <int K, bool MX> constexpr int asm_epb() { return K == 1 ? 4 : (K == 2 ? 2 : 1); }
+template <int K, bool MX, bool DUMP> constexpr size_t asm_slot_doubles() {
+  return (sizeof(AsmShared<K, MX, DUMP>) + 15) / 16 * 2;
+}
+
 template <int K, bool MX, bool DUMP, class T, bool JAC = true>
 __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh m, DeviceHDG h, Gas g, AsmParams prm,
                                                            const double* __restrict__ U,
@@ -285,10 +293,15 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
   static_assert(DUMP, "the point Jacobians go to the record");
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
+  constexpr int EPB = asm_epb<K, MX>(), TPE = 256 / EPB;
+  static_assert(sizeof(double) * asm_slot_doubles<K, MX, DUMP || !JAC>() * EPB <= 160 * 1024, "LDS per workgroup");
+  const int slot = threadIdx.x / TPE;
+  const int p = min((int)blockIdx.x * EPB + slot, h.n_im - 1);
   extern __shared__ double smem_raw[];
-  AsmShared<K, MX, DUMP || !JAC>& sh = *reinterpret_cast<AsmShared<K, MX, DUMP || !JAC>*>(smem_raw);
+  AsmShared<K, MX, DUMP || !JAC>& sh = *reinterpret_cast<AsmShared<K, MX, DUMP || !JAC>*>(
+      smem_raw + (size_t)slot * asm_slot_doubles<K, MX, DUMP || !JAC>());
   using Rec = PointRec<K, MX>;
-  double* const rp = DUMP ? rec + (size_t)blockIdx.x * Rec::SIZE : nullptr;
+  double* const rp = DUMP ? rec + (size_t)p * Rec::SIZE : nullptr;
   // point-wise Jacobian entries: LDS, or the record in global memory (DUMP)
   auto jv = [&](int qv, int o, int col) -> double& {
     if constexpr (DUMP) return rp[Rec::JV + ((size_t)qv * 8 + o) * NIV + col];
@@ -306,9 +319,8 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
     if constexpr (DUMP) return rp[Rec::JLF + (((size_t)f * NQ + q) * 3 + c) * 4 + v];
     else return sh.JLF[MX ? f : 0][q][c][v];
   };
-  const int p = blockIdx.x;
   const int e = h.im_list[p];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x % TPE, nt = TPE;
   for (int i = tid; i < (int)(sizeof(BasisTable) / sizeof(double)); i += nt)
     reinterpret_cast<double*>(&sh.tb)[i] = reinterpret_cast<const double*>(m.tab)[i];
   for (int i = tid; i < NU; i += nt) sh.U[i] = U[(size_t)e * NU + i];
@@ -2907,6 +2919,14 @@ imex_status hdg_alloc(imex_ctx* c) {
   return IMEX_OK;
 }
 
+template <int KK, bool MX> static int asm_blocks(int n_im) {
+  constexpr int EPB = asm_epb<KK, MX>();
+  return (n_im + EPB - 1) / EPB;
+}
+template <int KK, bool MX> static size_t asm_shm() {
+  return sizeof(double) * asm_slot_doubles<KK, MX, true>() * asm_epb<KK, MX>();
+}
+
 template <int KK, class LT>
 static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, const double* Uhat, const double* rhs,
                                     int jacobian, double* Rh) {
@@ -2917,18 +2937,17 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
   const int ta = jacobian ? c->timer_begin(TM_ASSEMBLE) : -1;
   if (use_mx(c)) {
     // point values, residual rows and point-wise Jacobians; then the block contraction
-    const size_t shm = sizeof(AsmShared<KK, true, true>);
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, true>), dim3((asm_blocks<KK, true>(c->n_im))), dim3(256), (asm_shm<KK, true>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, false>), dim3((asm_blocks<KK, true>(c->n_im))), dim3(256), (asm_shm<KK, true>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
                          w.hres);
     }
@@ -2954,18 +2973,17 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     }
   } else if (!c->gas.viscous) {
     // inviscid HDG-IP: the same split without mixed blocks (K and C D E)
-    const size_t shm = sizeof(AsmShared<KK, false, true>);
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     }
@@ -2980,18 +2998,17 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     c->timer_end(ta);
   } else {
     // viscous HDG-IP: point records (with the gradient columns), then their contraction
-    const size_t shm = sizeof(AsmShared<KK, false, true>);
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3(c->n_im), dim3(256), shm,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     }
