@@ -1443,7 +1443,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
 // Every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  KB-deep
 // k-blocks are staged in LDS with the next block prefetched into registers.
 template <int WM, int WN, int SM, int SN, int KB, bool SPLIT>
-__global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
+#ifndef GW_WAVES_PER_EU
+#define GW_WAVES_PER_EU 0
+#endif
+#if GW_WAVES_PER_EU > 0
+#define GW_WAVES __attribute__((amdgpu_waves_per_eu(GW_WAVES_PER_EU)))
+#else
+#define GW_WAVES
+#endif
+__global__ void __launch_bounds__(64 * WM * WN) GW_WAVES gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
                                                                   int beta_one, const float* __restrict__ A, int lda,
                                                                   long long sA, const float* __restrict__ B, int ldb,
                                                                   long long sB, float* __restrict__ C, int ldc,
@@ -2134,44 +2142,71 @@ template <int K> struct RasDims {
 // Preconditioner apply z = M^-1 x in one launch: one workgroup per window sweeps its
 // super-rows forward, y_r = x_r - G_r [y_{r-1}[H]; x_{r-1}[~H]] (only the H rows change)
 // and w_r = D_r^-1 y_r (w_r kept in Wy), then backward, z_r = w_r - E_r z_{r+1}[H] with the
-// owned facets of z_r written.  Each product is split into column slices over the 256
-// threads (partial sums reduced through LDS, FP64 accumulation of the FP32 or FP64
-// factors), and the next super-row's factor entries and vector values are loaded into
-// registers while the current super-row is applied, so the factor stream, not the serial
-// chain, sets the pace.
+// owned facets of z_r written.  Each product is split over the 256 threads into groups of
+// V consecutive rows (one 16-byte load per column: V = 4 in FP32, 2 in FP64) times slices
+// of columns, partial sums reduced through LDS with FP64 accumulation.  The next
+// super-row's factor entries and vector values are loaded into registers while the
+// current super-row is applied; the 16-byte loads keep a thread's prefetch at about a
+// dozen instructions, well inside the number of loads a wave can have in flight.
+template <class T> struct Ld16;
+template <> struct Ld16<float> {
+  static constexpr int V = 4;
+  __device__ static void get(const float* p, float (&o)[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+  }
+};
+template <> struct Ld16<double> {
+  static constexpr int V = 2;
+  __device__ static void get(const double* p, double (&o)[2]) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    o[0] = q.x; o[1] = q.y;
+  }
+};
+
 template <int K, class T>
 __global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wg, const T* __restrict__ Wd,
                                                         const T* __restrict__ Wc, const double* __restrict__ x,
                                                         double* __restrict__ Wy, double* __restrict__ z) {
   using D = RasDims<K>;
-  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
-  constexpr int PD = 256 / NB, CD = (NB + PD - 1) / PD;      // D^-1: NB rows, NB columns
-  constexpr int PG = 256 / NH, CG = (NB + PG - 1) / PG;      // G: NH rows, NB columns
-  constexpr int PE = 256 / NB, CE = (NH + PE - 1) / PE;      // E: NB rows, NH columns
-  __shared__ double yv[NB], prev[NB], zn[NH], pd[PD][NB], pg[PG][NH], pe[PE][NB];
+  using L = Ld16<T>;
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH, V = L::V;
+  static_assert(NB % V == 0 && NH % V == 0, "row groups");
+  constexpr int RD = NB / V, SD = 256 / RD, CD = (NB + SD - 1) / SD;   // D^-1: NB rows, NB columns
+  constexpr int RG = NH / V, SG = 256 / RG, CG = (NB + SG - 1) / SG;   // G: NH rows, NB columns
+  constexpr int RE = NB / V, SE = 256 / RE, CE = (NH + SE - 1) / SE;   // E: NB rows, NH columns
+  __shared__ double yv[NB], prev[NB], zn[NH], pd[SD][NB], pg[SG][NH], pe[SE][NB];
   const int w = blockIdx.x, t = threadIdx.x;
   const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
   if (g1 <= g0) return;
-  const int di = t % NB, dq = t / NB;                        // D^-1 and E row / slice of this thread
-  const int gi = t % NH, gq = t / NH;                        // G row / slice
-  const bool dON = t < PD * NB, gON = t < PG * NH, eON = t < PE * NB;
+  const int d0 = (t % RD) * V, dq = t / RD;                   // first row / column slice: D^-1
+  const int gr0 = (t % RG) * V, gq = t / RG;                  // G
+  const int e0 = (t % RE) * V, eq = t / RE;                   // E
+  const bool dON = t < SD * RD, gON = t < SG * RG, eON = t < SE * RE;
   auto xval = [&](int g, int i) -> double {
     const int f = h.win_slot[5 * g + i / NFF];
     return f >= 0 ? x[(size_t)f * NFF + i % NFF] : 0.0;
   };
-  T gr[CG], dr[CD];
+  T gr[CG][V], dr[CD][V];
+  // lanes without an entry read the block's first entry and take zero (branch-free loads)
   auto load_fwd = [&](int g) {
     const T* Gg = Wg + (size_t)g * NH * NB;                  // Gg[k * NH + i] = G_r[i][k]
     const T* Dg = Wd + (size_t)g * NB * NB;                  // Dg[k * NB + i] = D_r^-1[i][k]
 #pragma unroll
     for (int kk = 0; kk < CG; ++kk) {
       const int k = gq * CG + kk;
-      gr[kk] = (gON && g > g0 && k < NB) ? Gg[(size_t)k * NH + gi] : T(0);
+      const bool ok = gON && g > g0 && k < NB;
+      L::get(Gg + (ok ? (size_t)k * NH + gr0 : 0), gr[kk]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) gr[kk][v] = ok ? gr[kk][v] : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < CD; ++kk) {
       const int k = dq * CD + kk;
-      dr[kk] = (dON && k < NB) ? Dg[(size_t)k * NB + di] : T(0);
+      const bool ok = dON && k < NB;
+      L::get(Dg + (ok ? (size_t)k * NB + d0 : 0), dr[kk]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) dr[kk][v] = ok ? dr[kk][v] : T(0);
     }
   };
   load_fwd(g0);
@@ -2179,83 +2214,107 @@ __global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __
   for (int g = g0; g < g1; ++g) {
     if (t < NB) yv[t] = xn;
     __syncthreads();
-    T gc[CG], dc[CD];
+    T gc[CG][V], dc[CD][V];
 #pragma unroll
-    for (int kk = 0; kk < CG; ++kk) gc[kk] = gr[kk];
+    for (int kk = 0; kk < CG; ++kk)
 #pragma unroll
-    for (int kk = 0; kk < CD; ++kk) dc[kk] = dr[kk];
+      for (int v = 0; v < V; ++v) gc[kk][v] = gr[kk][v];
+#pragma unroll
+    for (int kk = 0; kk < CD; ++kk)
+#pragma unroll
+      for (int v = 0; v < V; ++v) dc[kk][v] = dr[kk][v];
     if (g + 1 < g1) {
       load_fwd(g + 1);
       xn = t < NB ? xval(g + 1, t) : 0.0;
     }
     if (g > g0) {
       if (gON) {
-        double a = 0.0;
+        double a[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) a[v] = 0.0;
 #pragma unroll
         for (int kk = 0; kk < CG; ++kk) {
           const int k = gq * CG + kk;
-          if (k < NB) a += (double)gc[kk] * prev[k];
+          const double pk = k < NB ? prev[k] : 0.0;
+#pragma unroll
+          for (int v = 0; v < V; ++v) a[v] += (double)gc[kk][v] * pk;
         }
-        pg[gq][gi] = a;
+#pragma unroll
+        for (int v = 0; v < V; ++v) pg[gq][gr0 + v] = a[v];
       }
       __syncthreads();
       if (t < NH) {
         double a = 0.0;
 #pragma unroll
-        for (int q = 0; q < PG; ++q) a += pg[q][t];
+        for (int q = 0; q < SG; ++q) a += pg[q][t];
         yv[t] -= a;
       }
       __syncthreads();
     }
     if (dON) {
-      double a = 0.0;
+      double a[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) a[v] = 0.0;
 #pragma unroll
       for (int kk = 0; kk < CD; ++kk) {
         const int k = dq * CD + kk;
-        if (k < NB) a += (double)dc[kk] * yv[k];
+        const double yk = k < NB ? yv[k] : 0.0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) a[v] += (double)dc[kk][v] * yk;
       }
-      pd[dq][di] = a;
+#pragma unroll
+      for (int v = 0; v < V; ++v) pd[dq][d0 + v] = a[v];
     }
     if (t < NB) prev[t] = yv[t];
     __syncthreads();
     if (t < NB) {
       double a = 0.0;
 #pragma unroll
-      for (int q = 0; q < PD; ++q) a += pd[q][t];
+      for (int q = 0; q < SD; ++q) a += pd[q][t];
       Wy[(size_t)g * D::NSV + NB + t] = a;                   // w_r, read back by this thread
     }
   }
   // backward sweep
-  T er[CE];
+  T er[CE][V];
   auto load_bwd = [&](int g) {
     const T* Eg = Wc + (size_t)g * NB * NH;                  // Eg[k * NB + i] = E_r[i][k]
 #pragma unroll
     for (int kk = 0; kk < CE; ++kk) {
-      const int k = dq * CE + kk;
-      er[kk] = (eON && k < NH) ? Eg[(size_t)k * NB + di] : T(0);
+      const int k = eq * CE + kk;
+      const bool ok = eON && k < NH;
+      L::get(Eg + (ok ? (size_t)k * NB + e0 : 0), er[kk]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) er[kk][v] = ok ? er[kk][v] : T(0);
     }
   };
   if (g1 - 2 >= g0) load_bwd(g1 - 2);
   for (int g = g1 - 1; g >= g0; --g) {
     double v = t < NB ? Wy[(size_t)g * D::NSV + NB + t] : 0.0;
     if (g < g1 - 1) {
-      T ec[CE];
+      T ec[CE][V];
 #pragma unroll
-      for (int kk = 0; kk < CE; ++kk) ec[kk] = er[kk];
+      for (int kk = 0; kk < CE; ++kk)
+#pragma unroll
+        for (int u = 0; u < V; ++u) ec[kk][u] = er[kk][u];
       if (g - 1 >= g0) load_bwd(g - 1);
       if (eON) {
-        double a = 0.0;
+        double a[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) a[u] = 0.0;
 #pragma unroll
         for (int kk = 0; kk < CE; ++kk) {
-          const int k = dq * CE + kk;
-          if (k < NH) a += (double)ec[kk] * zn[k];
+          const int k = eq * CE + kk;
+          const double zk = k < NH ? zn[k] : 0.0;
+#pragma unroll
+          for (int u = 0; u < V; ++u) a[u] += (double)ec[kk][u] * zk;
         }
-        pe[dq][di] = a;
+#pragma unroll
+        for (int u = 0; u < V; ++u) pe[eq][e0 + u] = a[u];
       }
       __syncthreads();
       if (t < NB) {
 #pragma unroll
-        for (int q = 0; q < PE; ++q) v -= pe[q][t];
+        for (int q = 0; q < SE; ++q) v -= pe[q][t];
       }
     }
     __syncthreads();                                         // zn and pe free again
