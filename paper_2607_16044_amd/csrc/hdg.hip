@@ -274,9 +274,12 @@ template <int K> using MxRec = PointRec<K, true>;
 // JAC = false: point values and residual rows only (a separate instantiation without the
 // dual-number passes).
 // EPB elements per workgroup (256 / EPB threads each, one LDS slot each): the low degrees
-// have too few points to occupy 256 threads per element.  A slot past the last element
+// have too few points to occupy 256 threads per element, and so has the residual-only
+// pass at any degree (one task per point: 77 at k = 4).  A slot past the last element
 // repeats the last element (identical values to the same addresses).
-template <int K, bool MX> constexpr int asm_epb() { return K == 1 ? 4 : (K == 2 ? 2 : 1); }
+template <int K, bool MX, bool JAC> constexpr int asm_epb() {
+  return !JAC ? 4 : (K == 1 ? 4 : (K == 2 ? 2 : 1));
+}
 template <int K, bool MX, bool DUMP> constexpr size_t asm_slot_doubles() {
   return (sizeof(AsmShared<K, MX, DUMP>) + 15) / 16 * 2;
 }
@@ -293,7 +296,7 @@ __global__ void __launch_bounds__(256) ASM_WAVES hdg_assemble_kernel(DeviceMesh 
   static_assert(DUMP, "the point Jacobians go to the record");
   constexpr int NP = S::NP, NQ = S::NQ, NN = S::NN, NQV = S::NQV, NU = S::NU, NF = S::NF, NFF = S::NFF;
   constexpr int NQM = S::NQM, NIV = S::NIV, NIF = S::NIF, NOF = S::NOF;
-  constexpr int EPB = asm_epb<K, MX>(), TPE = 256 / EPB;
+  constexpr int EPB = asm_epb<K, MX, JAC>(), TPE = 256 / EPB;
   static_assert(sizeof(double) * asm_slot_doubles<K, MX, DUMP || !JAC>() * EPB <= 160 * 1024, "LDS per workgroup");
   const int slot = threadIdx.x / TPE;
   const int p = min((int)blockIdx.x * EPB + slot, h.n_im - 1);
@@ -2978,12 +2981,12 @@ imex_status hdg_alloc(imex_ctx* c) {
   return IMEX_OK;
 }
 
-template <int KK, bool MX> static int asm_blocks(int n_im) {
-  constexpr int EPB = asm_epb<KK, MX>();
+template <int KK, bool MX, bool JAC> static int asm_blocks(int n_im) {
+  constexpr int EPB = asm_epb<KK, MX, JAC>();
   return (n_im + EPB - 1) / EPB;
 }
-template <int KK, bool MX> static size_t asm_shm() {
-  return sizeof(double) * asm_slot_doubles<KK, MX, true>() * asm_epb<KK, MX>();
+template <int KK, bool MX, bool JAC> static size_t asm_shm() {
+  return sizeof(double) * asm_slot_doubles<KK, MX, true>() * asm_epb<KK, MX, JAC>();
 }
 
 template <int KK, class LT>
@@ -2999,14 +3002,14 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, true>), dim3((asm_blocks<KK, true>(c->n_im))), dim3(256), (asm_shm<KK, true>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true, true>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, true>), dim3((asm_blocks<KK, true, true>(c->n_im))), dim3(256), (asm_shm<KK, true, true>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, true, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, false>), dim3((asm_blocks<KK, true>(c->n_im))), dim3(256), (asm_shm<KK, true>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, true, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, true, true, LT, false>), dim3((asm_blocks<KK, true, false>(c->n_im))), dim3(256), (asm_shm<KK, true, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, w.Q, Rh, w.rec,
                          w.hres);
     }
@@ -3035,14 +3038,14 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false, true>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false, true>(c->n_im))), dim3(256), (asm_shm<KK, false, true>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false, false>(c->n_im))), dim3(256), (asm_shm<KK, false, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     }
@@ -3060,14 +3063,14 @@ static hipError_t launch_assemble_t(imex_ctx* c, double dt_a, const double* U, c
     const int tpo = jacobian ? c->timer_begin(TM_POINTS) : -1;
     if (jacobian) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false, true>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, true>), dim3((asm_blocks<KK, false, true>(c->n_im))), dim3(256), (asm_shm<KK, false, true>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     } else {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_assemble_kernel<KK, false, true, LT, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false>());
-      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false>(c->n_im))), dim3(256), (asm_shm<KK, false>()),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asm_shm<KK, false, false>());
+      hipLaunchKernelGGL((hdg_assemble_kernel<KK, false, true, LT, false>), dim3((asm_blocks<KK, false, false>(c->n_im))), dim3(256), (asm_shm<KK, false, false>()),
                          c->stream, c->dmesh(), c->dhdg(), c->gas, prm, U, Uhat, rhs, blk, scr, nullptr, Rh, w.rec,
                          w.hres);
     }
