@@ -278,7 +278,7 @@ template <int K> using MxRec = PointRec<K, true>;
 // pass at any degree (one task per point: 77 at k = 4).  A slot past the last element
 // repeats the last element (identical values to the same addresses).
 template <int K, bool MX, bool JAC> constexpr int asm_epb() {
-  return !JAC ? 4 : (K == 1 ? 4 : (K == 2 ? 2 : 1));
+  return !JAC ? 4 : (K == 1 ? 4 : 2);
 }
 template <int K, bool MX, bool DUMP> constexpr size_t asm_slot_doubles() {
   return (sizeof(AsmShared<K, MX, DUMP>) + 15) / 16 * 2;
@@ -2331,13 +2331,19 @@ __global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __
   }
 }
 
-// y = S x: one 64-lane workgroup per facet, coalesced reads of the two S_T row blocks
+// y = S x: one 64-lane workgroup per facet over the NFF rows of S_T on both sides.  The wave
+// covers four rows at a time with 16 lanes per row on consecutive columns (four 64-byte
+// segments per load), so a row's sum is reduced over 16 lanes (4 shuffle steps) instead
+// of the whole wave.
 template <int K, class T>
 __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* __restrict__ blk, size_t bs,
                                                          const double* __restrict__ x, double* __restrict__ y) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP, NC = NU + NF + 1;
+  constexpr int RG = NFF / 4, CB = NF / 16;                 // row quads, 16-column blocks
+  static_assert(NFF % 4 == 0 && NF % 16 == 0, "facet block shape");
   __shared__ double xs[2][NF];
   const int hf = blockIdx.x, tid = threadIdx.x;
+  const int rq = tid >> 4, cl = tid & 15;
   int pe[2], fc[2];
   for (int s = 0; s < 2; ++s) {
     pe[s] = h.hf_side[2 * hf + s];
@@ -2347,28 +2353,27 @@ __global__ void __launch_bounds__(64) facet_apply_kernel(DeviceHDG h, const T* _
     for (int i = tid; i < NF; i += 64)
       xs[s][i] = (pe[s] >= 0) ? x[(size_t)h.efacet[4 * pe[s] + i / NFF] * NFF + i % NFF] : 0.0;
   __syncthreads();
-  double acc[NFF];
+  double acc[RG];
 #pragma unroll
-  for (int r = 0; r < NFF; ++r) acc[r] = 0.0;
+  for (int r = 0; r < RG; ++r) acc[r] = 0.0;
   for (int s = 0; s < 2; ++s) {
     if (pe[s] < 0) continue;
     const T* Sb = blk + (size_t)pe[s] * bs + (size_t)(NU + fc[s] * NFF) * NC + NU;   // NFF rows of S_T
-    for (int c = tid; c < NF; c += 64) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int c = 16 * cb + cl;
       const double xc = xs[s][c];
 #pragma unroll
-      for (int r = 0; r < NFF; ++r) acc[r] += (double)Sb[(size_t)r * NC + c] * xc;
+      for (int r = 0; r < RG; ++r) acc[r] += (double)Sb[(size_t)(4 * r + rq) * NC + c] * xc;
     }
   }
-  // butterfly sums over the wave; lane r keeps row r
-  double out = 0.0;
 #pragma unroll
-  for (int r = 0; r < NFF; ++r) {
+  for (int r = 0; r < RG; ++r) {
     double v = acc[r];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (tid == r) out = v;
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (cl == 0) y[(size_t)hf * NFF + 4 * r + rq] = v;
   }
-  if (tid < NFF) y[(size_t)hf * NFF + tid] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -2608,30 +2613,45 @@ __global__ void zero_kernel(int n, double* __restrict__ x) {
   if (i < n) x[i] = 0.0;
 }
 
-// back-substitution: dU = -K^-1 f - K^-1 C dUhat; U += dU on implicit elements; max |dU|, max |U| per block
+// back-substitution: dU = -K^-1 f - K^-1 C dUhat; U += dU on implicit elements; max |dU|, max |U| per block.
+// 16 lanes per row of X on consecutive columns, 16 rows at a time over the 256 threads, each
+// row's sum reduced over its 16 lanes.
 template <int K, class T>
 __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const T* __restrict__ X,
                                                           const double* __restrict__ dUh, double* __restrict__ U,
                                                           double* __restrict__ part) {
   constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NFF = 4 * NP;
+  constexpr int RP = (NU + 15) / 16, CB = NF / 16;          // row passes, 16-column blocks
+  static_assert(NF % 16 == 0, "facet columns");
   __shared__ double xs[NF];
   __shared__ double rd[2][256];
   const int p = blockIdx.x;
   const int e = h.im_list[p];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, rq = tid >> 4, cl = tid & 15;
   for (int i = tid; i < NF; i += blockDim.x) xs[i] = dUh[(size_t)h.efacet[4 * p + i / NFF] * NFF + i % NFF];
   __syncthreads();
+  double xv[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) xv[cb] = xs[16 * cb + cl];
   double mdu = 0.0, mu = 0.0;
-  for (int i = tid; i < NU; i += blockDim.x) {
-    const T* Xr = X + ((size_t)p * NU + i) * (NF + 1);      // [K^-1 C | K^-1 f]
-    double acc = (double)Xr[NF];
-    for (int c = 0; c < NF; ++c) acc += (double)Xr[c] * xs[c];
-    const double du = -acc;
-    const double un = U[(size_t)e * NU + i] + du;
-    U[(size_t)e * NU + i] = un;
-    // non-finite values count as infinite (fmax would drop a NaN): the host reports them
-    mdu = fmax(mdu, isfinite(du) ? fabs(du) : INFINITY);
-    mu = fmax(mu, isfinite(un) ? fabs(un) : INFINITY);
+#pragma unroll
+  for (int rp = 0; rp < RP; ++rp) {
+    const int i = 16 * rp + rq;
+    const bool ok = i < NU;
+    const T* Xr = X + ((size_t)p * NU + (ok ? i : 0)) * (NF + 1);   // [K^-1 C | K^-1 f]
+    double acc = cl == 0 ? (double)Xr[NF] : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc += (double)Xr[16 * cb + cl] * xv[cb];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (ok && cl == 0) {
+      const double du = -acc;
+      const double un = U[(size_t)e * NU + i] + du;
+      U[(size_t)e * NU + i] = un;
+      // non-finite values count as infinite (fmax would drop a NaN): the host reports them
+      mdu = fmax(mdu, isfinite(du) ? fabs(du) : INFINITY);
+      mu = fmax(mu, isfinite(un) ? fabs(un) : INFINITY);
+    }
   }
   rd[0][tid] = mdu;
   rd[1][tid] = mu;
