@@ -273,12 +273,13 @@ template <int K> using MxRec = PointRec<K, true>;
 // destination of the point Jacobians.)
 // JAC = false: point values and residual rows only (a separate instantiation without the
 // dual-number passes).
-// EPB elements per workgroup (256 / EPB threads each, one LDS slot each): the low degrees
-// have too few points to occupy 256 threads per element, and so has the residual-only
-// pass at any degree (one task per point: 77 at k = 4).  A slot past the last element
-// repeats the last element (identical values to the same addresses).
+// EPB elements per workgroup (256 / EPB threads each, one LDS slot each).  The kernel's
+// register budget allows one wave per SIMD, so a workgroup is all that a CU runs: with
+// one element per workgroup its waves would idle through the element's serial phases and
+// short task lists (77 point tasks at k = 4 in the residual-only pass).  A slot past the
+// last element repeats the last element (identical values to the same addresses).
 template <int K, bool MX, bool JAC> constexpr int asm_epb() {
-  return !JAC ? 4 : (K == 1 ? 4 : 2);
+  return 4;
 }
 template <int K, bool MX, bool DUMP> constexpr size_t asm_slot_doubles() {
   return (sizeof(AsmShared<K, MX, DUMP>) + 15) / 16 * 2;
