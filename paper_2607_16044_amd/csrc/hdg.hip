@@ -2146,12 +2146,147 @@ template <int K> struct RasDims {
 // Preconditioner apply z = M^-1 x in one launch: one workgroup per window sweeps its
 // super-rows forward, y_r = x_r - G_r [y_{r-1}[H]; x_{r-1}[~H]] (only the H rows change)
 // and w_r = D_r^-1 y_r (w_r kept in Wy), then backward, z_r = w_r - E_r z_{r+1}[H] with the
-// owned facets of z_r written.  Each product is split over the 256 threads into groups of
-// V consecutive rows (one 16-byte load per column: V = 4 in FP32, 2 in FP64) times slices
-// of columns, partial sums reduced through LDS with FP64 accumulation.  The next
-// super-row's factor entries and vector values are loaded into registers while the
-// current super-row is applied; the 16-byte loads keep a thread's prefetch at about a
-// dozen instructions, well inside the number of loads a wave can have in flight.
+// owned facets of z_r written.  Each product is split into column slices over the 256
+// threads (partial sums reduced through LDS, FP64 accumulation of the FP32 or FP64
+// factors), and the next super-row's factor entries and vector values are loaded into
+// registers while the current super-row is applied, so the factor stream, not the serial
+// chain, sets the pace.
+template <int K, class T>
+__global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wg, const T* __restrict__ Wd,
+                                                        const T* __restrict__ Wc, const double* __restrict__ x,
+                                                        double* __restrict__ Wy, double* __restrict__ z) {
+  using D = RasDims<K>;
+  constexpr int NFF = D::NFF, NB = D::NB, NH = D::NH;
+  constexpr int PD = 256 / NB, CD = (NB + PD - 1) / PD;      // D^-1: NB rows, NB columns
+  constexpr int PG = 256 / NH, CG = (NB + PG - 1) / PG;      // G: NH rows, NB columns
+  constexpr int PE = 256 / NB, CE = (NH + PE - 1) / PE;      // E: NB rows, NH columns
+  __shared__ double yv[NB], prev[NB], zn[NH], pd[PD][NB], pg[PG][NH], pe[PE][NB];
+  const int w = blockIdx.x, t = threadIdx.x;
+  const int g0 = h.win_off[w], g1 = h.win_off[w + 1];
+  if (g1 <= g0) return;
+  const int di = t % NB, dq = t / NB;                        // D^-1 and E row / slice of this thread
+  const int gi = t % NH, gq = t / NH;                        // G row / slice
+  const bool dON = t < PD * NB, gON = t < PG * NH, eON = t < PE * NB;
+  auto xval = [&](int g, int i) -> double {
+    const int f = h.win_slot[5 * g + i / NFF];
+    return f >= 0 ? x[(size_t)f * NFF + i % NFF] : 0.0;
+  };
+  T gr[CG], dr[CD];
+  auto load_fwd = [&](int g) {
+    const T* Gg = Wg + (size_t)g * NH * NB;                  // Gg[k * NH + i] = G_r[i][k]
+    const T* Dg = Wd + (size_t)g * NB * NB;                  // Dg[k * NB + i] = D_r^-1[i][k]
+#pragma unroll
+    for (int kk = 0; kk < CG; ++kk) {
+      const int k = gq * CG + kk;
+      gr[kk] = (gON && g > g0 && k < NB) ? Gg[(size_t)k * NH + gi] : T(0);
+    }
+#pragma unroll
+    for (int kk = 0; kk < CD; ++kk) {
+      const int k = dq * CD + kk;
+      dr[kk] = (dON && k < NB) ? Dg[(size_t)k * NB + di] : T(0);
+    }
+  };
+  load_fwd(g0);
+  double xn = t < NB ? xval(g0, t) : 0.0;
+  for (int g = g0; g < g1; ++g) {
+    if (t < NB) yv[t] = xn;
+    __syncthreads();
+    T gc[CG], dc[CD];
+#pragma unroll
+    for (int kk = 0; kk < CG; ++kk) gc[kk] = gr[kk];
+#pragma unroll
+    for (int kk = 0; kk < CD; ++kk) dc[kk] = dr[kk];
+    if (g + 1 < g1) {
+      load_fwd(g + 1);
+      xn = t < NB ? xval(g + 1, t) : 0.0;
+    }
+    if (g > g0) {
+      if (gON) {
+        double a = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < CG; ++kk) {
+          const int k = gq * CG + kk;
+          if (k < NB) a += (double)gc[kk] * prev[k];
+        }
+        pg[gq][gi] = a;
+      }
+      __syncthreads();
+      if (t < NH) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < PG; ++q) a += pg[q][t];
+        yv[t] -= a;
+      }
+      __syncthreads();
+    }
+    if (dON) {
+      double a = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < CD; ++kk) {
+        const int k = dq * CD + kk;
+        if (k < NB) a += (double)dc[kk] * yv[k];
+      }
+      pd[dq][di] = a;
+    }
+    if (t < NB) prev[t] = yv[t];
+    __syncthreads();
+    if (t < NB) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < PD; ++q) a += pd[q][t];
+      Wy[(size_t)g * D::NSV + NB + t] = a;                   // w_r, read back by this thread
+    }
+  }
+  // backward sweep
+  T er[CE];
+  auto load_bwd = [&](int g) {
+    const T* Eg = Wc + (size_t)g * NB * NH;                  // Eg[k * NB + i] = E_r[i][k]
+#pragma unroll
+    for (int kk = 0; kk < CE; ++kk) {
+      const int k = dq * CE + kk;
+      er[kk] = (eON && k < NH) ? Eg[(size_t)k * NB + di] : T(0);
+    }
+  };
+  if (g1 - 2 >= g0) load_bwd(g1 - 2);
+  for (int g = g1 - 1; g >= g0; --g) {
+    double v = t < NB ? Wy[(size_t)g * D::NSV + NB + t] : 0.0;
+    if (g < g1 - 1) {
+      T ec[CE];
+#pragma unroll
+      for (int kk = 0; kk < CE; ++kk) ec[kk] = er[kk];
+      if (g - 1 >= g0) load_bwd(g - 1);
+      if (eON) {
+        double a = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < CE; ++kk) {
+          const int k = dq * CE + kk;
+          if (k < NH) a += (double)ec[kk] * zn[k];
+        }
+        pe[dq][di] = a;
+      }
+      __syncthreads();
+      if (t < NB) {
+#pragma unroll
+        for (int q = 0; q < PE; ++q) v -= pe[q][t];
+      }
+    }
+    __syncthreads();                                         // zn and pe free again
+    if (t < NB) {
+      if (t < NH) zn[t] = v;
+      const int a = t / NFF;
+      const int f = h.win_slot[5 * g + a];
+      if (f >= 0 && h.win_own[5 * g + a]) z[(size_t)f * NFF + t % NFF] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// The same apply for k = 4 with 16-byte factor loads: each product is split over the 256
+// threads into groups of V consecutive rows (one 16-byte load per column: V = 4 in FP32,
+// 2 in FP64) times slices of columns.  A thread's prefetch of the next super-row is then
+// about a dozen loads instead of the 67 of one row per thread, which is more than a wave
+// can have in flight.  (At lower degrees one row per thread is faster: it needs fewer
+// registers and less LDS, so more of an ensemble's many short windows share a CU.)
 template <class T> struct Ld16;
 template <> struct Ld16<float> {
   static constexpr int V = 4;
@@ -2169,7 +2304,7 @@ template <> struct Ld16<double> {
 };
 
 template <int K, class T>
-__global__ void __launch_bounds__(256) ras_apply_kernel(DeviceHDG h, const T* __restrict__ Wg, const T* __restrict__ Wd,
+__global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* __restrict__ Wg, const T* __restrict__ Wd,
                                                         const T* __restrict__ Wc, const double* __restrict__ x,
                                                         double* __restrict__ Wy, double* __restrict__ z) {
   using D = RasDims<K>;
@@ -3253,8 +3388,12 @@ static hipError_t launch_precond(imex_ctx* c, const double* x, double* y) {
   }
   const int tp = c->timer_begin(TM_PRECOND);
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
-    hipLaunchKernelGGL((ras_apply_kernel<KK, LT>), dim3(c->n_win), dim3(256), 0, c->stream, c->dhdg(), la<LT>(w.Wg),
-                       la<LT>(w.Wd), la<LT>(w.Wc), x, w.Wy, y);
+    if constexpr (KK >= 4)
+      hipLaunchKernelGGL((ras_apply16_kernel<KK, LT>), dim3(c->n_win), dim3(256), 0, c->stream, c->dhdg(),
+                         la<LT>(w.Wg), la<LT>(w.Wd), la<LT>(w.Wc), x, w.Wy, y);
+    else
+      hipLaunchKernelGGL((ras_apply_kernel<KK, LT>), dim3(c->n_win), dim3(256), 0, c->stream, c->dhdg(),
+                         la<LT>(w.Wg), la<LT>(w.Wd), la<LT>(w.Wc), x, w.Wy, y);
   }));
   c->timer_end(tp);
   return hipGetLastError();
