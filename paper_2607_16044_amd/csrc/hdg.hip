@@ -277,9 +277,11 @@ template <int K> using MxRec = PointRec<K, true>;
 // register budget allows one wave per SIMD, so a workgroup is all that a CU runs: with
 // one element per workgroup its waves would idle through the element's serial phases and
 // short task lists (77 point tasks at k = 4 in the residual-only pass).  A slot past the
-// last element repeats the last element (identical values to the same addresses).
+// last element repeats the last element (identical values to the same addresses).  Eight
+// elements at k = 1 and for the k = 2 Jacobian pass; four otherwise (the k = 2 residual-only
+// pass was slower with eight).
 template <int K, bool MX, bool JAC> constexpr int asm_epb() {
-  return 4;
+  return (K == 1 || (JAC && K == 2)) ? 8 : 4;
 }
 template <int K, bool MX, bool DUMP> constexpr size_t asm_slot_doubles() {
   return (sizeof(AsmShared<K, MX, DUMP>) + 15) / 16 * 2;
