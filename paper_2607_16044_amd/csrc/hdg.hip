@@ -1449,15 +1449,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(int batch, int M, int N, int 
 // Every 4-deep k-step of a wave issues SM x SN MFMAs from SM + SN LDS reads.  KB-deep
 // k-blocks are staged in LDS with the next block prefetched into registers.
 template <int WM, int WN, int SM, int SN, int KB, bool SPLIT>
-#ifndef GW_WAVES_PER_EU
-#define GW_WAVES_PER_EU 0
-#endif
-#if GW_WAVES_PER_EU > 0
-#define GW_WAVES __attribute__((amdgpu_waves_per_eu(GW_WAVES_PER_EU)))
-#else
-#define GW_WAVES
-#endif
-__global__ void __launch_bounds__(64 * WM * WN) GW_WAVES gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
+__global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int M, int N, int Kd, double alpha,
                                                                   int beta_one, const float* __restrict__ A, int lda,
                                                                   long long sA, const float* __restrict__ B, int ldb,
                                                                   long long sB, float* __restrict__ C, int ldc,
