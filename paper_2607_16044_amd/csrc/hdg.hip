@@ -1942,12 +1942,17 @@ __device__ void s_block_offsets(const DeviceHDG& h, size_t bs, int F, int G, lon
   }
 }
 
+// Branch-free: a missing share (offset -1) reads S[0] and takes zero, so that a thread's
+// gathers are issued together instead of one conditional load (and its wait) at a time.
 template <class T>
 __device__ __forceinline__ T s_gather(const T* __restrict__ S, const long long* off, int i, int j, int ld) {
   T v = T(0);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-    if (off[t] >= 0) v += S[off[t] + (long long)i * ld + j];
+  for (int t = 0; t < 4; ++t) {
+    const bool ok = off[t] >= 0;
+    const T x = S[ok ? off[t] + (long long)i * ld + j : 0];
+    v += ok ? x : T(0);
+  }
   return v;
 }
 
@@ -1997,28 +2002,43 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
     else if (tid < 35) s_block_offsets<K>(h, bs, fs[(tid - 25) / 5], fp[(tid - 25) % 5], oB[(tid - 25) / 5][(tid - 25) % 5]);
     else if (tid < 45) s_block_offsets<K>(h, bs, fp[(tid - 35) / 2], fs[(tid - 35) % 2], oC[(tid - 35) / 2][(tid - 35) % 2]);
     __syncthreads();
+    // the diagonal block (identity rows and columns for empty slots); lanes without a
+    // tile gather entry (0, 0) and discard it
     T A[G::RT][G::CT];
 #pragma unroll
     for (int i = 0; i < G::RT; ++i)
 #pragma unroll
       for (int j = 0; j < G::CT; ++j) {
-        const int r = r0 + i, c = c0 + j;
+        const int r = own ? r0 + i : 0, c = own ? c0 + j : 0;
         const int a = r / NFF, b = c / NFF;
-        T v = T(0);
-        if (own) {
-          if (fs[a] < 0 || fs[b] < 0) v = (r == c) ? T(1) : T(0);
-          else v = s_gather(S, oA[a][b], r % NFF, c % NFF, NC);
-        }
-        A[i][j] = v;
+        const T v = s_gather(S, oA[a][b], r % NFF, c % NFF, NC);
+        A[i][j] = !own ? T(0) : (fs[a] < 0 || fs[b] < 0) ? ((r == c) ? T(1) : T(0)) : v;
       }
     if (g > g0) {
-      for (int idx = tid; idx < NH * NB; idx += nt) {
-        const int r = idx / NB, c = idx % NB;
-        Bs[idx] = s_gather(S, oB[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+      constexpr int NBC = (NH * NB + 255) / 256;   // entries of B_r (and of C_{r-1}) per thread
+      {
+        T bv[NBC];
+#pragma unroll
+        for (int u = 0; u < NBC; ++u) {
+          const int idx = tid + 256 * u, q = idx < NH * NB ? idx : 0;
+          const int r = q / NB, c = q % NB;
+          bv[u] = s_gather(S, oB[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+        }
+#pragma unroll
+        for (int u = 0; u < NBC; ++u)
+          if (tid + 256 * u < NH * NB) Bs[tid + 256 * u] = bv[u];
       }
-      for (int idx = tid; idx < NB * NH; idx += nt) {
-        const int r = idx / NH, c = idx % NH;
-        Cs[idx] = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+      {
+        T cv[NBC];
+#pragma unroll
+        for (int u = 0; u < NBC; ++u) {
+          const int idx = tid + 256 * u, q = idx < NB * NH ? idx : 0;
+          const int r = q / NH, c = q % NH;
+          cv[u] = s_gather(S, oC[r / NFF][c / NFF], r % NFF, c % NFF, NC);
+        }
+#pragma unroll
+        for (int u = 0; u < NBC; ++u)
+          if (tid + 256 * u < NB * NH) Cs[tid + 256 * u] = cv[u];
       }
       __syncthreads();
       // G_r = B_r D_{r-1}^-1
