@@ -289,6 +289,13 @@ imex_status imex_local_system(imex_ctx* ctx, double dt_aii, const double* rhs, c
 #define IMEX_NTIMERS 11
 imex_status imex_kernel_times(imex_ctx* ctx, double out[2 * IMEX_NTIMERS], int reset);
 
+/* Which of the phases above record their hipEvents: bit t of mask for phase t (all by
+ * default, mask = 2^IMEX_NTIMERS - 1).  Each timed launch adds two event records to the
+ * stream, a few microseconds of idle device time each, so a run measured by its wall
+ * clock keeps only the phases it reads.  The counters of masked phases stay unchanged.
+ * IMEX_EINVAL for bits at or above IMEX_NTIMERS. */
+imex_status imex_set_timer_mask(imex_ctx* ctx, unsigned mask);
+
 /* Graph mode (on != 0): imex_ark_step replays the explicit sequence of every stage
  * (explicit residual, stage combination and implicit right-hand side) from a
  * hipGraph captured on first use on a private stream and captured again when dt

@@ -24,7 +24,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
-           "imex_local_system", "imex_kernel_times", "imex_vjp_dg_residual", "imex_vjp_ark_step",
+           "imex_local_system", "imex_kernel_times", "imex_set_timer_mask", "imex_vjp_dg_residual", "imex_vjp_ark_step",
            "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
            "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes", "imex_dg_residual_noalloc",
            "imex_set_mms_source", "imex_mms_load",
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_conservation_sums.argtypes = [P, P, ctypes.POINTER(D)]
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
+    lib.imex_set_timer_mask.argtypes = [P, ctypes.c_uint]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P, P, P]
     lib.imex_vjp_init_facets.argtypes = [P, P, P]
     lib.imex_set_launch_shapes.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
@@ -366,6 +367,14 @@ class Engine:
     def reset_timers(self):
         self.timers(reset=True)
 
+    def set_timer_mask(self, names=None):
+        """Phases that record hipEvents: a list of TIMER_NAMES entries (None: all)."""
+        names = self.TIMER_NAMES if names is None else names
+        mask = 0
+        for n in names:
+            mask |= 1 << self.TIMER_NAMES.index(n)
+        self._check(self.lib.imex_set_timer_mask(self.ctx, mask))
+
     def local_system(self, dt_a: float, rhs: torch.Tensor, U: torch.Tensor, Uhat: torch.Tensor):
         n_im = self.sizes["n_implicit"]
         k1 = self.wl.degree + 1
@@ -504,6 +513,11 @@ class Ensemble:
                 picks.append(one(g, eng))
         self._join()
         return picks
+
+    def set_timer_mask(self, names=None):
+        """Phases that record hipEvents in every degree group (None: all)."""
+        for _, eng in self.groups:
+            eng.set_timer_mask(names)
 
     def step(self, U, H):
         """One ARK step of every instance (each with its own dt); returns summed solver counts."""

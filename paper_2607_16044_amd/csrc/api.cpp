@@ -157,7 +157,7 @@ void imex_ctx::drop_graphs() {
 }
 
 int imex_ctx::timer_begin(int tag) {
-  if (capturing) return -1;
+  if (capturing || !((timer_mask >> tag) & 1u)) return -1;
   hipEvent_t a, b;
   if (ev_free.size() >= 2) {
     a = ev_free.back(); ev_free.pop_back();
@@ -1224,6 +1224,13 @@ imex_status imex_kernel_times(imex_ctx* c, double out[2 * IMEX_NTIMERS], int res
     out[2 * t + 1] = (double)c->tm_n[t];
     if (reset) { c->tm_ms[t] = 0.0; c->tm_n[t] = 0; }
   }
+  return IMEX_OK;
+}
+
+imex_status imex_set_timer_mask(imex_ctx* c, unsigned mask) {
+  if (!c) return fail(c, IMEX_EINVAL, "null argument");
+  if (mask >> IMEX_NTIMERS) return fail(c, IMEX_EINVAL, "timer mask has bits beyond the phases");
+  c->timer_mask = mask;
   return IMEX_OK;
 }
 

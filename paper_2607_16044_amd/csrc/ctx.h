@@ -177,6 +177,7 @@ struct imex_ctx {
   std::vector<hipEvent_t> ev_free;
   struct Pending { int tag; hipEvent_t a, b; };
   std::vector<Pending> ev_pending;
+  unsigned timer_mask = ~0u;          // bit t: phase t records its hipEvents
   int timer_begin(int tag);
   void timer_end(int idx);
   void timers_resolve();

@@ -139,3 +139,30 @@ def test_wall_flag_on_explicit_element_leaves_context_usable():
     eng.ark_step(wl.dt, U, H)
     assert torch.isfinite(U).all()
     eng.close()
+
+
+def test_timer_mask_selects_the_timed_phases():
+    """imex_set_timer_mask: masked phases record no events and their counters stay put;
+    the step matches a context with every phase timed (to the parity gate: the solver's
+    refresh decisions follow measured times); bits beyond the phases are EINVAL."""
+    wl = W.get("boundary_layer_small")
+    ref, U_ref, H_ref = _setup(wl)
+    ref.ark_step(wl.dt, U_ref, H_ref)
+    ref.close()
+    eng, U, H = _setup(wl)
+    eng.set_timer_mask(["eliminate"])
+    eng.ark_step(wl.dt, U, H)
+    t = eng.timers(reset=True)
+    assert t["eliminate_launches"] > 0
+    assert all(t[n + "_launches"] == 0 for n in eng.TIMER_NAMES if n != "eliminate")
+    assert rel_err(U.cpu(), U_ref.cpu()) < 1e-10 and rel_err(H.cpu(), H_ref.cpu()) < 1e-10
+    eng.set_timer_mask([])
+    eng.ark_step(wl.dt, U, H)
+    assert all(v == 0 for v in eng.timers(reset=True).values())
+    eng.set_timer_mask(None)
+    eng.ark_step(wl.dt, U, H)
+    assert eng.timers()["assemble_launches"] > 0
+    with pytest.raises(IMEXError) as e:
+        eng._check(eng.lib.imex_set_timer_mask(eng.ctx, 1 << 11))
+    assert e.value.status == EINVAL
+    eng.close()
