@@ -132,6 +132,8 @@ void free_regions(imex_ctx* c) {
   }
   if (w.hred) hipHostFree(w.hred);
   w.hred = nullptr;
+  if (w.hgm) hipHostFree(w.hgm);
+  w.hgm = w.hgm_dev = nullptr;
   for (double* p : w.adj_buf)
     if (p) hipFree(p);
   w.adj_buf.clear();

@@ -99,6 +99,9 @@ struct Workspace {
   double* adj_hm = nullptr;
   double* red = nullptr;        // reduction scratch
   double* hred = nullptr;       // pinned host reduction buffer
+  double* hgm = nullptr;        // coherent pinned host buffer the GMRES kernels write their residual
+                                // estimates into ([0, GM_MAXM] and beta at GM_MAXM + 1), host address
+  double* hgm_dev = nullptr;    // the same buffer's device address
   size_t bytes = 0;
 };
 

@@ -19,6 +19,7 @@
 //  5. hdg_backsub    dU_T = -y_T - X_T dUhat_T (eq. local_solve_static_condensation),
 //                    update and increment norms.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -2664,7 +2665,9 @@ __global__ void __launch_bounds__(256) gm_norm_kernel(int n, const double* __res
 }
 
 // start a cycle: beta = |r|, g = (beta, 0, ...), H = 0, invb = 1/beta
-__global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
+// hbeta: host-visible copy of beta (coherent pinned memory), read by the host after the
+// block that follows
+__global__ void gm_start_kernel(double* __restrict__ st, int nblocks, double* __restrict__ hbeta) {
   const int tid = threadIdx.x;
   if (tid < 64) {
     const double beta = sqrt(gm_norm_total(st, nblocks));
@@ -2672,6 +2675,7 @@ __global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
       st[GmState::G] = beta;
       st[GmState::INVB] = beta > 0.0 ? 1.0 / beta : 0.0;
       st[GmState::INVB + 1] = beta;
+      *hbeta = beta;
     }
   }
   for (int i = tid; i < (GM_MAXM + 1) * GM_MAXM; i += blockDim.x) st[GmState::H + i] = 0.0;
@@ -2680,8 +2684,10 @@ __global__ void gm_start_kernel(double* __restrict__ st, int nblocks) {
 
 // Givens update of column j and v /= beta in one launch: every block sums the norm
 // partials itself (beta is needed everywhere); block 0 also updates the rotations.
+// hres: host-visible residual estimates (coherent pinned memory), hres[j] written with RES[j]
 __global__ void __launch_bounds__(256) gm_givens_scale_kernel(int n, int j, double* __restrict__ v,
-                                                              double* __restrict__ st, int nblocks) {
+                                                              double* __restrict__ st, int nblocks,
+                                                              double* __restrict__ hres) {
   __shared__ double sb[1];
   if (threadIdx.x < 64) {
     const double beta = sqrt(gm_norm_total(st, nblocks));
@@ -2710,6 +2716,7 @@ __global__ void __launch_bounds__(256) gm_givens_scale_kernel(int n, int j, doub
     st[GmState::G + j + 1] = -sn * gj;
     st[GmState::G + j] = c * gj;
     st[GmState::RES + j] = fabs(sn * gj);
+    hres[j] = fabs(sn * gj);
     st[GmState::INVB] = inv;
   }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2811,6 +2818,39 @@ __global__ void __launch_bounds__(256) hdg_backsub_kernel(DeviceHDG h, const T* 
     __syncthreads();
   }
   if (tid == 0) { part[2 * p] = rd[0][0]; part[2 * p + 1] = rd[1][0]; }
+}
+
+// Newton increment norms: the maxima of the per-block partials of the back-substitution
+// (n_im pairs: max |dU|, max |U|) and of the facet update (nf pairs: max |dUhat|, max |Uhat|),
+// written to host-visible memory, the last one after a system-scope fence (the host waits
+// for it).  The partials are >= 0 or infinite (non-finite values are counted as infinite).
+__global__ void __launch_bounds__(256) newton_norms_kernel(int n_im, int nf, const double* __restrict__ part,
+                                                           double* __restrict__ hout) {
+  __shared__ double r[4][256];
+  const int t = threadIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = t; i < n_im; i += 256) {
+    a[0] = fmax(a[0], part[2 * i]);
+    a[1] = fmax(a[1], part[2 * i + 1]);
+  }
+  for (int i = t; i < nf; i += 256) {
+    a[2] = fmax(a[2], part[2 * (n_im + i)]);
+    a[3] = fmax(a[3], part[2 * (n_im + i) + 1]);
+  }
+  for (int k = 0; k < 4; ++k) r[k][t] = a[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int k = 0; k < 4; ++k) r[k][t] = fmax(r[k][t], r[k][t + st]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    hout[0] = r[0][0];
+    hout[1] = r[1][0];
+    hout[2] = r[2][0];
+    __threadfence_system();
+    hout[3] = r[3][0];
+  }
 }
 
 // Uhat += dUhat; per-block max |dUhat|, max |Uhat|
@@ -3137,6 +3177,10 @@ imex_status hdg_alloc(imex_ctx* c) {
   if (e == hipSuccess) e = hipMalloc(&w.gH, 8 * (size_t)GmState::SIZE);
   if (e == hipSuccess) e = hipMalloc(&w.red, 8 * 2 * (n_im + 1024));
   if (e == hipSuccess) e = hipHostMalloc(&w.hred, 8 * ((size_t)GmState::SIZE + 2 * (n_im + 1024)), 0);
+  if (e == hipSuccess && !w.hgm) {
+    e = hipHostMalloc(&w.hgm, 8 * (size_t)(GM_MAXM + 6), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&w.hgm_dev), w.hgm, 0);
+  }
   if (e != hipSuccess) {
     c->err = std::string("implicit workspace: ") + hipGetErrorString(e);
     return IMEX_ENOMEM;
@@ -3447,6 +3491,14 @@ static hipError_t launch_apply(imex_ctx* c, const double* x, double* y) {
 constexpr int GM_CHECK = 8;
 constexpr int GM_FIRST = 4;           // first block without a history
 constexpr size_t GM_MAXGRAPHS = 512;  // captured block graphs kept per context
+// Replay of the inner GMRES blocks from captured graphs (1) or direct launches (0).  With
+// the host waiting on the residual estimates in coherent memory, direct launches start a
+// block sooner (about 20 us after the wait against 30 - 90 us for a graph launch, and new
+// block keys cost a capture); the boundary layer and the ensemble measured the same or
+// slightly faster without the graphs.
+#ifndef GM_BLOCK_GRAPHS
+#define GM_BLOCK_GRAPHS 0
+#endif
 // Facet preconditioner reuse: refactorise once the GMRES iterations spent above the count
 // right after the last factorisation exceed what a factorisation costs, in iterations (the
 // online rule that pays at most twice the best choice in hindsight).  The cost ratio is
@@ -3526,6 +3578,21 @@ static imex_status replay_block(imex_ctx* c, int key, F&& body) {
   return IMEX_OK;
 }
 
+// Wait until the device has overwritten *slot (coherent host memory, holding sentinel):
+// spin for up to SPIN_US microseconds, then wait for the stream.  Everything the device
+// wrote before that value (earlier kernels on the stream) is visible once it is.
+constexpr double SPIN_US = 10000.0;
+static hipError_t wait_host_value(imex_ctx* c, const double* slot, double sentinel) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    double v;
+    __atomic_load(slot, &v, __ATOMIC_ACQUIRE);
+    if (!(v == sentinel)) return hipSuccess;
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    if (us > SPIN_US) return hipStreamSynchronize(c->stream);
+  }
+}
+
 // Iterations still needed to bring the residual estimate res[n-1] below tol at the
 // geometric rate of the last (up to three) iterations; res[-1] is the cycle's |r_0|.
 static int gm_predict(const std::vector<double>& res, double tol) {
@@ -3568,7 +3635,7 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
     // beta = |r|, V_0 = r / beta; beta is read back with the first block's residual
     // estimates (a cycle that starts below the tolerance discards that block)
     hipLaunchKernelGGL(gm_norm_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, r, st);
-    hipLaunchKernelGGL(gm_start_kernel, dim3(1), dim3(256), 0, c->stream, st, GM_NB);
+    hipLaunchKernelGGL(gm_start_kernel, dim3(1), dim3(256), 0, c->stream, st, GM_NB, w.hgm_dev + GM_MAXM + 1);
     hipLaunchKernelGGL(gm_scale_copy_kernel, dim3(nb), dim3(256), 0, c->stream, n, r, V, st);
     bool small = false;
     int j = 0, jdone = -1;
@@ -3584,22 +3651,27 @@ static imex_status gmres(imex_ctx* c, const double* b, double* x, int* its_out, 
           hipLaunchKernelGGL(gm_dots_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, V, ldv, vn, st);
           hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st, 0);
           hipLaunchKernelGGL(gm_orth_kernel, dim3(GM_NB), dim3(256), 0, c->stream, n, jj + 1, jj, V, ldv, vn, st, 1);
-          hipLaunchKernelGGL(gm_givens_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, jj, vn, st, GM_NB);
+          hipLaunchKernelGGL(gm_givens_scale_kernel, dim3(nb), dim3(256), 0, c->stream, n, jj, vn, st, GM_NB,
+                             w.hgm_dev);
         }
         HTRY(hipGetLastError());
         return IMEX_OK;
       };
       // the launches of a block are fixed by its first column, its length and the mode
       const int key = ((j * (GM_CHECK + 1) + (j1 - j)) << 1) + (c->adj_mode ? 1 : 0);
-      const bool replay = c->gm_graphs.count(key) || c->gm_graphs.size() < GM_MAXGRAPHS;
+      const bool replay = GM_BLOCK_GRAPHS && (c->gm_graphs.count(key) || c->gm_graphs.size() < GM_MAXGRAPHS);
+      // the block's kernels write the residual estimates (and gm_start_kernel beta) into
+      // coherent host memory.  The host spins until the block's last estimate replaces a
+      // sentinel (estimates are |.| or NaN, never -1), which it sees a few microseconds
+      // after the write instead of after the runtime's stream wait; past SPIN_US it waits
+      // for the stream instead, which also reports any device error.
+      w.hgm[j1 - 1] = -1.0;
       const imex_status bs = replay ? replay_block(c, key, block) : block();
       if (bs != IMEX_OK) return bs;
-      HTRY(hipMemcpyAsync(hb, st + GmState::RES + j, sizeof(double) * (j1 - j), hipMemcpyDeviceToHost, c->stream));
-      if (j == 0)
-        HTRY(hipMemcpyAsync(hb + GM_CHECK, st + GmState::INVB + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HTRY(hipStreamSynchronize(c->stream));
+      HTRY(wait_host_value(c, &w.hgm[j1 - 1], -1.0));
+      for (int jj = j; jj < j1; ++jj) hb[jj - j] = w.hgm[jj];
       if (j == 0) {
-        const double beta = hb[GM_CHECK];
+        const double beta = w.hgm[GM_MAXM + 1];
         if (!std::isfinite(beta)) {
           c->err = "non-finite facet residual";
           return IMEX_ENONFINITE;
@@ -3748,16 +3820,16 @@ imex_status hdg_stage_solve(imex_ctx* c, double dt_a, const double* rhs, double*
     hipLaunchKernelGGL(facet_update_kernel, dim3(fb), dim3(256), 0, c->stream, n, dx, Uhat, part + 2 * c->n_im);
     c->timer_end(tt);
     HTRY(hipGetLastError());
-    const size_t np = 2 * ((size_t)c->n_im + fb);
-    HTRY(hipMemcpyAsync(w.hred, part, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
-    HTRY(hipStreamSynchronize(c->stream));
+    // the four norms into coherent host memory; the host spins on the last one (>= 0 or
+    // infinite, never the sentinel -1)
+    double* hn = w.hgm + GM_MAXM + 2;
+    hn[3] = -1.0;
+    hipLaunchKernelGGL(newton_norms_kernel, dim3(1), dim3(256), 0, c->stream, c->n_im, fb, part,
+                       w.hgm_dev + GM_MAXM + 2);
+    HTRY(hipGetLastError());
+    HTRY(wait_host_value(c, &hn[3], -1.0));
     c->timers_resolve();
-    double du = 0.0, uu = 0.0, dh = 0.0, hh = 0.0;
-    for (int i = 0; i < c->n_im; ++i) { du = std::fmax(du, w.hred[2 * i]); uu = std::fmax(uu, w.hred[2 * i + 1]); }
-    for (int i = 0; i < fb; ++i) {
-      dh = std::fmax(dh, w.hred[2 * (c->n_im + i)]);
-      hh = std::fmax(hh, w.hred[2 * (c->n_im + i) + 1]);
-    }
+    const double du = hn[0], uu = hn[1], dh = hn[2], hh = hn[3];
     if (!std::isfinite(du) || !std::isfinite(dh) || !std::isfinite(uu) || !std::isfinite(hh)) {
       c->err = "non-finite Newton increment";
       return IMEX_ENONFINITE;
