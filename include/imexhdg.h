@@ -330,6 +330,14 @@ imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, in
  * not depend on the shapes beyond rounding.  Errors: EINVAL. */
 imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
 
+/* The element inverse K^-1 of the static condensation (eq. local_solve_static_condensation):
+ * *method 0 is the register-tiled Gauss-Jordan with partial pivoting (FP64 and FP32), 1 the
+ * blocked Gauss-Jordan with partial pivoting whose rank-16 updates run on the matrix cores
+ * (FP32 only: IMEX_FP32_REFINE).  set != 0 selects *method (EINVAL for other values, or for
+ * 1 in FP64); on return *method holds the method in use.  imex_autotune times both in FP32
+ * and keeps the faster.  host method. */
+imex_status imex_element_inverse(imex_ctx* ctx, int set, int* method);
+
 /* Vector-Jacobian product of the explicit residual (reverse mode of Sec. 3.3):
  * Ubar = (dR^DG/dU)^T Rbar, with R^DG as in imex_dg_residual.  U dev (all
  * elements); Rbar dev [e][v][n], rows of implicit elements ignored; Ubar dev out,

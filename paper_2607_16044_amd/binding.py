@@ -24,7 +24,7 @@ IMEX_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV"
 
 EXPORTS = ["imex_create", "imex_set_regions", "imex_query_sizes", "imex_node_coords", "imex_init_facets",
            "imex_dg_residual", "imex_implicit_stage_solve", "imex_ark_step", "imex_conservation_sums",
-           "imex_local_system", "imex_kernel_times", "imex_set_timer_mask", "imex_vjp_dg_residual", "imex_vjp_ark_step",
+           "imex_local_system", "imex_kernel_times", "imex_set_timer_mask", "imex_element_inverse", "imex_vjp_dg_residual", "imex_vjp_ark_step",
            "imex_create_batch", "imex_autotune", "imex_set_graphs", "imex_vjp_imex_step", "imex_vjp_init_facets",
            "imex_wall_shear", "imex_vjp_wall_shear", "imex_set_launch_shapes", "imex_dg_residual_noalloc",
            "imex_set_mms_source", "imex_mms_load",
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     lib.imex_local_system.argtypes = [P, D, P, P, P, P, P, P, P, P, P]
     lib.imex_kernel_times.argtypes = [P, ctypes.POINTER(D), ctypes.c_int]
     lib.imex_set_timer_mask.argtypes = [P, ctypes.c_uint]
+    lib.imex_element_inverse.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.imex_vjp_dg_residual.argtypes = [P, P, P, P, P, P]
     lib.imex_vjp_init_facets.argtypes = [P, P, P]
     lib.imex_set_launch_shapes.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
@@ -366,6 +367,13 @@ class Engine:
 
     def reset_timers(self):
         self.timers(reset=True)
+
+    def element_inverse(self, method: Optional[int] = None) -> int:
+        """The element inverse in use (0 register Gauss-Jordan, 1 blocked Gauss-Jordan on the
+        matrix cores, FP32 only); selects it first when method is given."""
+        m = ctypes.c_int(0 if method is None else int(method))
+        self._check(self.lib.imex_element_inverse(self.ctx, 0 if method is None else 1, ctypes.byref(m)))
+        return m.value
 
     def set_timer_mask(self, names=None):
         """Phases that record hipEvents: a list of TIMER_NAMES entries (None: all)."""

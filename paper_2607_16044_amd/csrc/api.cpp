@@ -990,6 +990,18 @@ imex_status imex_set_launch_shapes(imex_ctx* c, const int in[4]) {
   return IMEX_OK;
 }
 
+imex_status imex_element_inverse(imex_ctx* c, int set, int* method) {
+  if (!c || !method) return fail(c, IMEX_EINVAL, "null argument");
+  if (set) {
+    if (*method != 0 && *method != 1) return fail(c, IMEX_EINVAL, "element inverse method");
+    if (*method == 1 && c->opt.precision != IMEX_FP32_REFINE)
+      return fail(c, IMEX_EINVAL, "the matrix-core inverse is the FP32 one");
+    c->inv_method = *method;
+  }
+  *method = c->inv_method;
+  return IMEX_OK;
+}
+
 imex_status imex_set_graphs(imex_ctx* c, int on) {
   if (!c) return fail(c, IMEX_EINVAL, "null argument");
   if (on && !c->gstream) HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));

@@ -133,6 +133,7 @@ struct imex_ctx {
   // launch shapes (0 = built-in default), chosen by imex_autotune
   int dg_tile = 0;              // explicit elements per workgroup of the residual kernel
   int gemm_tile[3] = {0, 0, 0}; // output tile (64 or 32) of the elimination, K^-1 [C f] and Schur GEMMs
+  int inv_method = 0;           // K^-1: 0 register Gauss-Jordan, 1 blocked Gauss-Jordan on MFMA (FP32)
   // facet preconditioner reuse across Newton iterations, stages and steps
   bool prec_valid = false;      // factors match a recent system
   bool prec_fresh = false;      // the next GMRES solve is the first after a refactorisation

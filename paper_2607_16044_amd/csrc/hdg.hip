@@ -1893,6 +1893,176 @@ __global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, cons
 }
 
 // ---------------------------------------------------------------------------
+// K^-1 in FP32 by blocked in-place Gauss-Jordan on the matrix cores.  The NU x NU block
+// sits column-major in LDS (columns padded to whole 16 x 16 tiles with zeros).  Pivots go
+// in panels of 16: the wave that owns a panel's tile column factorises the panel in
+// registers (each lane holds rows lane, lane + 64 of the 16 columns; partial pivoting
+// among the rows not yet used, by a wave-wide maximum of |a|, lowest row on ties), which
+// gives the panel transformation's columns T[:, r_t] for its pivot rows r_t.  Every other
+// column then takes the rank-16 update A[:, j] += (T[:, r] - I[:, r]) A[r, j] on
+// v_mfma_f32_16x16x4f32 tiles (accumulators loaded from and stored back to LDS), and the
+// panel's own columns become T[:, r].  In-place Gauss-Jordan keeps the accumulated
+// transformation in the pivoted columns, so after NU pivots the block holds K^-1 with
+// rows and columns permuted by the pivot order: K^-1[q][c] = A[rp[q]][pos[c]].
+// Column tiles are dealt round robin to the four waves; each wave updates all row tiles
+// of its columns, so a panel's pivot-row values are read and written by the same wave.
+// ---------------------------------------------------------------------------
+template <int K> struct GjiDims {
+  static constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN;
+  static constexpr int TT = (NU + 15) / 16, TN = 16 * TT;            // tiles per side, padded size
+  static constexpr int PB = 16, RPL = (NU + 63) / 64;                // pivots per panel, rows per lane
+  static_assert(NU % 4 == 0, "float4 column segments");
+  static constexpr size_t LDS = sizeof(float) * ((size_t)TN * NU + (size_t)PB * TN) + sizeof(int) * 2 * NU;
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const float* __restrict__ blk,
+                                                              float* __restrict__ Kinv) {
+  using D = GjiDims<K>;
+  constexpr int NU = D::NU, TT = D::TT, TN = D::TN, PB = D::PB, RPL = D::RPL;
+  constexpr int NC = NU + 16 * (K + 1) + 1;              // row stride of the element block
+  constexpr int TPW = (TT + 3) / 4;                      // tile columns per wave
+  extern __shared__ __align__(16) float gji_lds[];
+  float* Am = gji_lds;                                   // column j at Am + j * NU
+  float* Tb = Am + (size_t)TN * NU;                      // [PB][TN]: T[:, r_t] - e_{r_t}
+  int* rp = reinterpret_cast<int*>(Tb + PB * TN);        // [NU] pivot row of pivot k
+  int* pos = rp + NU;                                    // [NU] pivot index of row r (-1: not yet)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const float* bp = blk + (size_t)blockIdx.x * bs;
+  for (int idx = tid; idx < NU * NU; idx += 256) {
+    const int r = idx / NU, cc = idx - r * NU;
+    Am[cc * NU + r] = bp[(size_t)r * NC + cc];
+  }
+  for (int idx = tid; idx < (TN - NU) * NU; idx += 256) Am[NU * NU + idx] = 0.0f;
+  for (int idx = tid; idx < PB * TN; idx += 256) Tb[idx] = 0.0f;
+  for (int idx = tid; idx < NU; idx += 256) pos[idx] = -1;
+  __syncthreads();
+  for (int p0 = 0; p0 < NU; p0 += PB) {
+    const int nb = NU - p0 < PB ? NU - p0 : PB;
+    const int owner = (p0 / 16) & 3;                     // the wave holding the panel's tile column
+    float P[RPL][PB];
+    int rpan[PB];
+    if (wv == owner) {
+      bool avail[RPL];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int row = lane + 64 * s;
+        avail[s] = row < NU && pos[row < NU ? row : 0] < 0;
+#pragma unroll
+        for (int cc = 0; cc < PB; ++cc) P[s][cc] = (row < NU && cc < nb) ? Am[(p0 + cc) * NU + row] : 0.0f;
+      }
+#pragma unroll
+      for (int t = 0; t < PB; ++t) {
+        rpan[t] = 0;
+        if (t < nb) {
+          unsigned long long key = 0ull;
+#pragma unroll
+          for (int s = 0; s < RPL; ++s)
+            if (avail[s]) {
+              const unsigned long long kk = pivot_key(P[s][t], lane + 64 * s);
+              key = kk > key ? kk : key;
+            }
+          key = __ockl_wfred_max_u64(key);
+          const int r = (int)(0xffffffffu - (unsigned int)(key & 0xffffffffull));
+          rpan[t] = r;
+          const int sr = r >> 6, lr = r & 63;
+          float prow[PB];
+#pragma unroll
+          for (int cc = 0; cc < PB; ++cc) {
+            float v = P[0][cc];
+#pragma unroll
+            for (int s = 1; s < RPL; ++s) v = (sr == s) ? P[s][cc] : v;
+            prow[cc] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lr));
+          }
+          const float inv = 1.0f / prow[t];
+#pragma unroll
+          for (int cc = 0; cc < PB; ++cc) prow[cc] *= inv;
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) {
+            const bool me = (lane + 64 * s) == r;
+            const float m = P[s][t];
+#pragma unroll
+            for (int cc = 0; cc < PB; ++cc) {
+              const float up = me ? prow[cc] : __builtin_fmaf(-m, prow[cc], P[s][cc]);
+              P[s][cc] = (cc == t) ? (me ? inv : -m * inv) : up;
+            }
+            if (me) avail[s] = false;
+          }
+        }
+      }
+    }
+    __syncthreads();                                     // every wave is done with the last panel's T
+    if (wv == owner) {
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int row = lane + 64 * s;
+        if (row < NU) {
+#pragma unroll
+          for (int cc = 0; cc < PB; ++cc)
+            Tb[cc * TN + row] = (cc < nb) ? P[s][cc] - (row == rpan[cc] ? 1.0f : 0.0f) : 0.0f;
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < PB; ++t)
+          if (t < nb) { rp[p0 + t] = rpan[t]; pos[rpan[t]] = p0 + t; }
+      }
+    }
+    __syncthreads();
+    // rank-nb update of this wave's tile columns; the pivot-row values of its columns are
+    // read before any of its tiles is written
+    float bvs[TPW][PB / 4];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int col = 16 * (wv + 4 * q) + li;
+#pragma unroll
+      for (int ks = 0; ks < PB / 4; ++ks) {
+        const int t = 4 * ks + lk;
+        bvs[q][ks] = (t < nb && wv + 4 * q < TT) ? Am[col * NU + rp[p0 + (t < nb ? t : 0)]] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int qc = 0; qc < TPW; ++qc) {
+      const int tj = wv + 4 * qc;
+      if (tj >= TT) break;
+      const int col = 16 * tj + li;
+      const bool pcol = col >= p0 && col < p0 + nb;
+      const int tp = pcol ? col - p0 : 0;
+      const int prow_t = rp[p0 + tp];
+#pragma unroll
+      for (int ti = 0; ti < TT; ++ti) {
+        const int r0 = 16 * ti + 4 * lk;
+        const bool rows_ok = r0 < NU;
+        mf_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (rows_ok) {
+          const float4 cv = *reinterpret_cast<const float4*>(Am + col * NU + r0);
+          acc = mf_f4{cv.x, cv.y, cv.z, cv.w};
+        }
+#pragma unroll
+        for (int ks = 0; ks < PB / 4; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Tb[(4 * ks + lk) * TN + 16 * ti + li], bvs[qc][ks], acc, 0, 0, 0);
+        if (rows_ok) {
+          float4 o = make_float4(acc[0], acc[1], acc[2], acc[3]);
+          if (pcol) {
+            const float* tc = Tb + tp * TN + r0;
+            o = make_float4(tc[0] + (r0 == prow_t ? 1.0f : 0.0f), tc[1] + (r0 + 1 == prow_t ? 1.0f : 0.0f),
+                            tc[2] + (r0 + 2 == prow_t ? 1.0f : 0.0f), tc[3] + (r0 + 3 == prow_t ? 1.0f : 0.0f));
+          }
+          *reinterpret_cast<float4*>(Am + col * NU + r0) = o;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  float* Kp = Kinv + (size_t)blockIdx.x * NU * NU;
+  for (int idx = tid; idx < NU * NU; idx += 256) {
+    const int q = idx / NU, cc = idx - q * NU;
+    Kp[idx] = Am[pos[cc] * NU + rp[q]];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // facet system
 // ---------------------------------------------------------------------------
 // b_F = sum_T -(h_T - D_T K_T^-1 f_T)|_F: h_T (FP64) plus the last column of the condensed
@@ -3306,8 +3476,25 @@ static hipError_t launch_assemble(imex_ctx* c, double dt_a, const double* U, con
   return hipErrorInvalidValue;
 }
 
+// K^-1 of every implicit element: the register Gauss-Jordan, or in FP32 with inv_method = 1
+// the blocked Gauss-Jordan on the matrix cores
+template <int KK, class LT>
+static void launch_invert(imex_ctx* c, const LT* blk, LT* Kinv) {
+  if constexpr (std::is_same<LT, float>::value) {
+    if (c->inv_method == 1) {
+      const size_t shm = GjiDims<KK>::LDS;
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hdg_invert_mfma_kernel<KK>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL((hdg_invert_mfma_kernel<KK>), dim3(c->n_im), dim3(256), shm, c->stream, blk_stride(c), blk,
+                         Kinv);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((hdg_invert_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv);
+}
+
 // condensation (eqs. statically_condensed_system, SchurCompliment):
-//   K^-1 (register Gauss-Jordan);  X = K^-1 [C f];  [E h] -= D X  (so that the augmented
+//   K^-1 (Gauss-Jordan);  X = K^-1 [C f];  [E h] -= D X  (so that the augmented
 //   system's facet block holds S_T = E - D K^-1 C and h - D K^-1 f)
 static hipError_t launch_condense(imex_ctx* c) {
   Workspace& w = c->ws;
@@ -3317,7 +3504,7 @@ static hipError_t launch_condense(imex_ctx* c) {
     LT* Kinv = la<LT>(w.Kinv);
     LT* X = la<LT>(w.X);
     const int ti = c->timer_begin(TM_INVERT);
-    hipLaunchKernelGGL((hdg_invert_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv);
+    launch_invert<KK, LT>(c, blk, Kinv);
     c->timer_end(ti);
     const long long bs = (long long)blk_stride(c);
     hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, NF + 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
@@ -3403,6 +3590,17 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
         });
         if (ms < best) { best = ms; c->gemm_tile[g] = tile; }
       }
+    }
+    if constexpr (sizeof(LT) == 4) {
+      // the element inverse: register Gauss-Jordan against the blocked one on the matrix cores
+      float best = 1e30f;
+      int pick = 0;
+      for (int m : {0, 1}) {
+        c->inv_method = m;
+        const float ms = time_ms(c, 3, [&]() { launch_invert<KK, LT>(c, blk, Kinv); });
+        if (ms < best) { best = ms; pick = m; }
+      }
+      c->inv_method = pick;
     }
   }));
   const hipError_t e = hipGetLastError();
