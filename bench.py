@@ -50,7 +50,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}      # dense MFMA, FP32 / FP64
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6, "bf16": 2500.0}      # dense MFMA: FP32, FP64, bf16
 LA_BYTES = {"mixed": 4, "fp64": 8}
 
 
@@ -423,11 +423,15 @@ PHASE_STEPS = 2                    # steps with every phase timed, after the tim
 # the batched GEMM kernel run for a launch-shape code (imex_set_launch_shapes)
 WHOLE_SHAPES = {2001: "4, 4, 3, 3, 32, false", 2002: "2, 4, 6, 3, 32, false", 2003: "2, 2, 4, 3, 32, false",
                 2004: "4, 2, 2, 3, 32, false",
-                2005: "5, 2, 1, 3, 40, false", 2006: "1, 2, 7, 3, 8, false", 2007: "2, 4, 3, 3, 16, true", 2008: "2, 2, 3, 3, 16, true"}
+                2005: "5, 2, 1, 3, 40, false", 2006: "1, 2, 7, 3, 8, false", 2007: "2, 4, 3, 3, 16, true", 2008: "2, 2, 3, 3, 16, true",
+                2009: "2, 2, 3, 3, 16, true, true", 2010: "2, 4, 3, 3, 16, true, true"}
 
 
 def gemm_kernel_name(code, ltype):
     if ltype == "float" and code in WHOLE_SHAPES:
+        f = [a.strip() for a in WHOLE_SHAPES[code].split(",")]
+        if len(f) == 7 and f[6] == "true":                     # split-bf16 products
+            return f"gemm_bf3_kernel<{', '.join(f[:5])}>"
         return f"gemm_whole_kernel<{WHOLE_SHAPES[code]}>"
     if ltype == "float" and code in (1032, 1064):
         return f"gemm_fk_kernel<{code - 1000}>"
@@ -776,32 +780,38 @@ def main():
     phase_names = ["dg", "assemble", "eliminate", "condense", "facet_setup", "gmres", "backsub", "precond"]
     phases = {k: round(pt[k + "_ms"] / PHASE_STEPS, 3) for k in phase_names if pt[k + "_ms"] > 0}
     kernels = {k: round(pt[k + "_ms"] / PHASE_STEPS, 3) for k in ("points", "contract", "eliminate", "invert")}
-    roof = None
     # the dominant kernel: the larger per-step device time of the elimination GEMM and the
-    # block contraction (the two largest single kernels of the step; hipEvent timed)
+    # block contraction (the two largest single kernels of the step; hipEvent timed); the
+    # other one's roofline is reported beside it
     la = LA_BYTES[main_prec]
-    cands = [k for k in ("eliminate", "contract") if timers[k + "_launches"] > 0]
-    if cands:
-        top = max(cands, key=lambda k: timers[k + "_ms"])
-        avg_ms = timers[top + "_ms"] / timers[top + "_launches"]
-        ltype = "float" if main_prec == "mixed" else "double"
-        if top == "eliminate":
+    ltype = "float" if main_prec == "mixed" else "double"
+
+    def kernel_roofline(which):
+        avg_ms = timers[which + "_ms"] / timers[which + "_launches"]
+        if which == "eliminate":
             flops, nbytes = elimination_work(wl, res["n_im"], la)
             gbs = nbytes / (avg_ms * 1e-3) / 1e9
             tfl = flops / (avg_ms * 1e-3) / 1e12
             kname = gemm_kernel_name(res["shapes"]["gemm_tile_eliminate"], ltype)
-            roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            # split-bf16 products: six bf16 MFMA products per FP32 product
+            peak = PEAK_TFLOPS["bf16"] / 6.0 if kname.startswith("gemm_bf3_kernel") else PEAK_TFLOPS[main_prec]
+            return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
                     "traffic": measured_traffic("eliminate", main_prec, kname),
                     "kernel": kname + " (mixed-block elimination)",
                     "avg_ms": avg_ms, "launch_bytes": nbytes, "launch_flops": flops, "mfma_tflops": tfl,
-                    "mfma_frac": tfl / PEAK_TFLOPS[main_prec]}
-        else:
-            nbytes = contraction_work(wl, res["n_im"], la)
-            gbs = nbytes / (avg_ms * 1e-3) / 1e9
-            kname = f"hdg_contract_kernel<{wl.degree}, {ltype}, true>"
-            roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "traffic": measured_traffic("contract", main_prec, kname),
-                    "kernel": kname + " (element block contraction)", "avg_ms": avg_ms, "launch_bytes": nbytes}
+                    "mfma_peak_tflops": peak, "mfma_frac": tfl / peak}
+        nbytes = contraction_work(wl, res["n_im"], la)
+        gbs = nbytes / (avg_ms * 1e-3) / 1e9
+        kname = f"hdg_contract_kernel<{wl.degree}, {ltype}, true>"
+        return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                "traffic": measured_traffic("contract", main_prec, kname),
+                "kernel": kname + " (element block contraction)", "avg_ms": avg_ms, "launch_bytes": nbytes}
+    roof = roof_other = None
+    cands = sorted((k for k in ("eliminate", "contract") if timers[k + "_launches"] > 0),
+                   key=lambda k: -timers[k + "_ms"])
+    if cands:
+        roof = kernel_roofline(cands[0])
+        roof_other = kernel_roofline(cands[1]) if len(cands) > 1 else None
     out = {
         "metric": "DOF-stage updates/s, FP32+refine/batched vs plain FP64 GPU at <=1e-9 rel err",
         "value": value,
@@ -825,6 +835,7 @@ def main():
                    "noise": "per-node uniform, 1 %, seed 2" if wl.name == "boundary_layer" else None,
                    "dt": wl.dt, "dt_attempts": attempts},
         "roofline": roof,
+        "roofline_second_kernel": roof_other,
         "step_roofline": step_roofline(wl, res, 1e3 * res["elapsed"] / args.steps, main_prec),
         "phases_ms_per_step": phases,
         "kernels_ms_per_step": kernels,

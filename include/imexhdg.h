@@ -308,7 +308,7 @@ imex_status imex_set_graphs(imex_ctx* ctx, int on);
  * number of elements per workgroup (at state U, all elements; Uhat needed for
  * HDG-MX coupling, else nullable) and each batched GEMM of the implicit stage for
  * its output tiles (64x64, 32x32, and in FP32 the full-inner-dimension variants
- * 1064, 1032 and the whole-matrix shapes 2001..2008 of imex_set_launch_shapes that
+ * 1064, 1032 and the whole-matrix shapes 2001..2010 of imex_set_launch_shapes that
  * apply to the matrix), and keeps the fastest for this context.
  * out (host [4]): elements per residual workgroup (0 = built-in default), then
  * the tiles of the mixed-block elimination, K^-1 [C f] and Schur-update GEMMs
@@ -326,7 +326,9 @@ imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, in
  * up to 128 x 96 with 2 x 2 or 4 x 2 waves, up to 80 x 96 with 5 x 2 waves, up to
  * 112 x 96 with 1 x 2 waves; else edge 64), or 2007, 2008 (FP32, the output split
  * into parts of 96 x 192 with 2 x 4 waves or 96 x 96 with 2 x 2 waves, one
- * workgroup per part; any size).  Results do
+ * workgroup per part; any size), or 2010, 2009 (the parts of 2007, 2008 with each FP32
+ * product formed from three-way bf16 splits of both factors on the bf16 matrix cores,
+ * six partial products accumulated in FP32: FP32 accuracy).  Results do
  * not depend on the shapes beyond rounding.  Errors: EINVAL. */
 imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
 

@@ -1559,11 +1559,174 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
   }
 }
 
+// Whole-matrix GEMM in FP32 with the products on the bf16 matrix cores: every operand
+// entry is split into three bf16 parts, a = a0 + a1 + a2 (a0 = bf16(a), a1 = bf16(a - a0),
+// a2 = bf16(a - a0 - a1): 24 significant bits, those of FP32), and a b is accumulated in
+// FP32 from the six partial products a_i b_j with i + j <= 2 (the dropped ones are below
+// FP32 rounding).  A v_mfma_f32_16x16x16bf16_1k does the work of four FP32 16x16x4 MFMAs
+// in a quarter of the time of one, so the six take 1.5 FP32-MFMA times per 16-deep
+// k-step instead of 4.  Split parts (workgroup numbering, wave tiles, register prefetch of
+// the next k-block, C update) as gemm_whole_kernel; the LDS holds the three bf16 planes
+// of the A block with k contiguous and of the B block transposed (k contiguous as well),
+// so that each lane reads its four k values of a plane with one 8-byte load.  The splits
+// are formed two values at a time with the packed FP32 -> bf16 conversion (round to nearest
+// even) and stored as one 32-bit word per plane.
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+
+template <int WM, int WN, int SM, int SN, int KB>
+__global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M, int N, int Kd, double alpha,
+                                                                int beta_one, const float* __restrict__ A, int lda,
+                                                                long long sA, const float* __restrict__ B, int ldb,
+                                                                long long sB, float* __restrict__ C, int ldc,
+                                                                long long sC) {
+  constexpr int NT = 64 * WM * WN, BM = 16 * SM * WM, BN = 16 * SN * WN;
+  constexpr int KP = KB + 4;                  // bf16 row pitch (8-byte aligned rows, staggered banks)
+  static_assert(KB % 16 == 0, "block shape");
+  __shared__ __align__(16) unsigned short sa[3][BM][KP];
+  __shared__ __align__(16) unsigned short sb[3][BN][KP];
+  const int pn = (N + BN - 1) / BN, np = ((M + BM - 1) / BM) * pn;
+  const int L = blockIdx.x, xcd = L & 7, rr = L >> 3, part = rr % np;
+  const long long bz = 8LL * (rr / np) + xcd;
+  const int m0 = (part / pn) * BM, n0 = (part % pn) * BN;
+  if (bz >= batch) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv / WN, wc = wv % WN;
+  const int li = lane & 15, lk = lane >> 4;
+  const float* Ab = A + bz * sA;
+  const float* Bb = B + bz * sB;
+  float* Cb = C + bz * sC;
+  // each thread stages pairs of consecutive k values (one packed conversion, one 32-bit
+  // LDS store per bf16 plane)
+  constexpr int PA = BM * KB / 2, PBN = BN * KB / 2;
+  constexpr int NLA = (PA + NT - 1) / NT, NLB = (PBN + NT - 1) / NT;
+  float ra[NLA][2], rb[NLB][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int idx = tid + NT * u;
+      const int r = m0 + idx / (KB / 2), gk = k0 + 2 * (idx % (KB / 2));
+      const bool in = idx < PA && r < M;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool ok = in && gk + e < Kd;
+        const float v = Ab[ok ? r * lda + gk + e : 0];
+        ra[u][e] = ok ? v : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int idx = tid + NT * u;
+      const int gk = k0 + 2 * (idx / BN), cc = n0 + idx % BN;
+      const bool in = idx < PBN && cc < N;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool ok = in && gk + e < Kd;
+        const float v = Bb[ok ? (gk + e) * ldb + cc : 0];
+        rb[u][e] = ok ? v : 0.0f;
+      }
+    }
+  };
+  // x = h0 + h1 + h2 for a pair of values, each part a packed pair of bf16 (round to nearest)
+  auto split_pair = [](float x0, float x1, unsigned int (&w)[3]) {
+    typedef float vf2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 vb2 __attribute__((ext_vector_type(2)));
+    float y0 = x0, y1 = x1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const unsigned int h = __builtin_bit_cast(unsigned int, __builtin_convertvector(vf2{y0, y1}, vb2));
+      w[q] = h;
+      y0 -= __uint_as_float(h << 16);
+      y1 -= __uint_as_float(h & 0xffff0000u);
+    }
+  };
+  mf_f4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
+  fetch(0);
+  for (int k0 = 0; k0 < Kd; k0 += KB) {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int idx = tid + NT * u;
+      if (idx < PA) {
+        const int r = idx / (KB / 2), kk = 2 * (idx % (KB / 2));
+        unsigned int w[3];
+        split_pair(ra[u][0], ra[u][1], w);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) *reinterpret_cast<unsigned int*>(&sa[q][r][kk]) = w[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int idx = tid + NT * u;
+      if (idx < PBN) {
+        const int kk = 2 * (idx / BN), cc = idx % BN;
+        unsigned int w[3];
+        split_pair(rb[u][0], rb[u][1], w);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) *reinterpret_cast<unsigned int*>(&sb[q][cc][kk]) = w[q];
+      }
+    }
+    __syncthreads();
+    if (k0 + KB < Kd) fetch(k0 + KB);
+#pragma unroll
+    for (int k16 = 0; k16 < KB / 16; ++k16) {
+      const int kk = 16 * k16 + 4 * lk;
+      mf_s4 av[SM][3], bv[SN][3];
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) av[i][q] = *reinterpret_cast<const mf_s4*>(&sa[q][16 * SM * wr + 16 * i + li][kk]);
+#pragma unroll
+      for (int j = 0; j < SN; ++j)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) bv[j][q] = *reinterpret_cast<const mf_s4*>(&sb[q][16 * SN * wc + 16 * j + li][kk]);
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          mf_f4 c = acc[i][j];
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][2], bv[j][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][1], bv[j][1], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][0], bv[j][2], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][1], bv[j][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][0], bv[j][1], c, 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i][0], bv[j][0], c, 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // C by rows of tiles: all loads of a row before its stores
+#pragma unroll
+  for (int ti = 0; ti < SM; ++ti) {
+    float cv[SN][4];
+#pragma unroll
+    for (int tj = 0; tj < SN; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + 16 * SM * wr + 16 * ti + 4 * lk + r;
+        const int gn = n0 + 16 * SN * wc + 16 * tj + li;
+        const bool ok = gm < M && gn < N;
+        const float v = Cb[ok ? gm * ldc + gn : 0];
+        cv[tj][r] = (beta_one && ok) ? v : 0.0f;
+      }
+#pragma unroll
+    for (int tj = 0; tj < SN; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + 16 * SM * wr + 16 * ti + 4 * lk + r;
+        const int gn = n0 + 16 * SN * wc + 16 * tj + li;
+        if (gm < M && gn < N) Cb[gm * ldc + gn] = cv[tj][r] + float(alpha) * acc[ti][tj][r];
+      }
+  }
+}
+
 // Whole-matrix shapes: code 2001..2008 -> {WM, WN, SM, SN, KB}.  Several waves per SIMD are
 // needed to keep the matrix cores fed (one wave holding a 96 x 96 block runs at half the
 // speed of sixteen waves holding 48 x 48 blocks), so the shapes trade block size for waves;
 // 2007 and 2008 cover 180 x 180 in two and four parts, with two and five workgroups per CU.
-struct WholeShape { int wm, wn, sm, sn, kb; bool split; };
+struct WholeShape { int wm, wn, sm, sn, kb; bool split; bool bf3 = false; };
 __host__ __device__ constexpr WholeShape whole_shape(int code) {
   return code == 2001 ? WholeShape{4, 4, 3, 3, 32, false}     // 192 x 192, 1024 threads
        : code == 2002 ? WholeShape{2, 4, 6, 3, 32, false}     // 192 x 192, 512 threads
@@ -1573,6 +1736,8 @@ __host__ __device__ constexpr WholeShape whole_shape(int code) {
        : code == 2006 ? WholeShape{1, 2, 7, 3, 8, false}      // 112 x 96, 128 threads
        : code == 2007 ? WholeShape{2, 4, 3, 3, 16, true}      // parts of 96 x 192, 512 threads
        : code == 2008 ? WholeShape{2, 2, 3, 3, 16, true}      // parts of 96 x 96, 256 threads
+       : code == 2009 ? WholeShape{2, 2, 3, 3, 16, true, true}    // 2008 with split-bf16 products
+       : code == 2010 ? WholeShape{2, 4, 3, 3, 16, true, true}    // 2007 with split-bf16 products
                       : WholeShape{0, 0, 0, 0, 0, false};
 }
 // workgroups per batch entry of a whole-matrix shape (the output split into parts)
@@ -1707,6 +1872,18 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
       WHOLE_LAUNCH(2007)
       WHOLE_LAUNCH(2008)
 #undef WHOLE_LAUNCH
+#define BF3_LAUNCH(CODE)                                                                                       \
+  if (tile == CODE) {                                                                                          \
+    constexpr WholeShape ws = whole_shape(CODE);                                                               \
+    const long long nbw = 8LL * ((batch + 7) / 8) * gemm_whole_parts(CODE, M, N);                               \
+    hipLaunchKernelGGL((gemm_bf3_kernel<ws.wm, ws.wn, ws.sm, ws.sn, ws.kb>), dim3((unsigned)nbw),              \
+                       dim3(64 * ws.wm * ws.wn), 0, st, batch, M, N, K, alpha, beta_one ? 1 : 0, A, lda, sA, B, \
+                       ldb, sB, C, ldc, sC);                                                                   \
+    return hipGetLastError();                                                                                  \
+  }
+      BF3_LAUNCH(2009)
+      BF3_LAUNCH(2010)
+#undef BF3_LAUNCH
     }
     if (tile > 1000 && tile < 2000 && K <= 128) {
       const int tf = tile == 1032 ? 32 : 64;
@@ -3572,7 +3749,7 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008}) {
+      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010}) {
         if (tile > 1000 && sizeof(LT) != 4) continue;
         if (tile > 2000 && !(g == 0 ? gemm_whole_fits(tile, NR, NR)
                                     : gemm_whole_fits(tile, g == 1 ? NU : NF, NF + 1)))

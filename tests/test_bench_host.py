@@ -54,4 +54,7 @@ def test_whole_shape_names_match_the_kernel_table():
         want = [a.strip() for a in args.split(",")]
         got = [a.strip() for a in bench.WHOLE_SHAPES[int(code)].split(",")]
         assert got == want, (code, got, want)
-        assert bench.gemm_kernel_name(int(code), "float") == f"gemm_whole_kernel<{', '.join(want)}>"
+        if len(want) == 7 and want[6] == "true":
+            assert bench.gemm_kernel_name(int(code), "float") == f"gemm_bf3_kernel<{', '.join(want[:5])}>"
+        else:
+            assert bench.gemm_kernel_name(int(code), "float") == f"gemm_whole_kernel<{', '.join(want)}>"

@@ -173,8 +173,10 @@ def test_autotuned_shapes_give_same_result(case, precision):
                                             ("vortex_small", 1)])
 def test_every_gemm_variant_gives_same_result(case, precision):
     """Each GEMM launch shape (64, 32 and, in FP32, the full-inner-dimension 1064 / 1032 and
-    the whole-matrix 2001..2008, of which 2001..2006 fall back to the 64 tile where the matrix
-    does not fit and 2007 / 2008 split it into parts) set through imex_set_launch_shapes gives the default's states to rounding."""
+    the whole-matrix 2001..2010, of which 2001..2006 fall back to the 64 tile where the matrix
+    does not fit, 2007 / 2008 split it into parts and 2009 / 2010 split it so with FP32
+    products emulated on the bf16 matrix cores) set through imex_set_launch_shapes gives the
+    default's states to rounding."""
     wl = W.get(case)
 
     def run(shapes):
@@ -189,7 +191,7 @@ def test_every_gemm_variant_gives_same_result(case, precision):
         eng.close()
         return out
     ref = run(None)
-    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008] if precision == 1 else [])
+    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010] if precision == 1 else [])
     for t in tiles:
         e = rel_err(run({"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}), ref)
         print(case, precision, t, e)

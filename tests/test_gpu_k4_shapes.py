@@ -2,7 +2,8 @@
 
 The boundary-layer benchmark runs at k = 4, where the augmented element system is
 180 x 180 (NU = 100, NF = 80) and the whole-matrix FP32 GEMM shapes split it into parts
-(codes 2007 / 2008: 96 x 192 or 96 x 96 parts; 2001..2006 hold it whole or fall back to
+(codes 2007 / 2008: 96 x 192 or 96 x 96 parts, 2009 / 2010 the same parts with FP32 products
+emulated on the bf16 matrix cores; 2001..2006 hold it whole or fall back to
 the 64 tile).  Each shape set through imex_set_launch_shapes must reach the oracle's
 root: one implicit stage (eqs. dirk_stage_update_*, solved through
 eqs. statically_condensed_system / SchurCompliment / local_solve_static_condensation)
@@ -25,8 +26,10 @@ pytestmark = pytest.mark.gpu
 BAR = {0: 1e-10, 1: 1e-9}
 # default shapes, every single code, and the combinations the autotuner picks on the full mesh
 SHAPES = [None] + [{"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}
-                   for t in (64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008)] + [
+                   for t in (64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010)] + [
     {"gemm_tile_eliminate": 2008, "gemm_tile_condense": 2004, "gemm_tile_schur": 2008},
+    {"gemm_tile_eliminate": 2009, "gemm_tile_condense": 2004, "gemm_tile_schur": 2009},
+    {"gemm_tile_eliminate": 2010, "gemm_tile_condense": 2004, "gemm_tile_schur": 2009},
     {"gemm_tile_eliminate": 2001, "gemm_tile_condense": 2004, "gemm_tile_schur": 2008},
     {"gemm_tile_eliminate": 2007, "gemm_tile_condense": 2005, "gemm_tile_schur": 2007},
 ]
