@@ -424,7 +424,7 @@ PHASE_STEPS = 2                    # steps with every phase timed, after the tim
 WHOLE_SHAPES = {2001: "4, 4, 3, 3, 32, false", 2002: "2, 4, 6, 3, 32, false", 2003: "2, 2, 4, 3, 32, false",
                 2004: "4, 2, 2, 3, 32, false",
                 2005: "5, 2, 1, 3, 40, false", 2006: "1, 2, 7, 3, 8, false", 2007: "2, 4, 3, 3, 16, true", 2008: "2, 2, 3, 3, 16, true",
-                2009: "2, 2, 3, 3, 16, true, true", 2010: "2, 4, 3, 3, 16, true, true"}
+                2009: "2, 2, 3, 3, 16, true, true", 2010: "2, 4, 3, 3, 16, true, true", 2011: "4, 2, 2, 3, 16, true, true"}
 
 
 def gemm_kernel_name(code, ltype):

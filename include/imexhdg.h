@@ -326,9 +326,9 @@ imex_status imex_autotune(imex_ctx* ctx, const double* U, const double* Uhat, in
  * up to 128 x 96 with 2 x 2 or 4 x 2 waves, up to 80 x 96 with 5 x 2 waves, up to
  * 112 x 96 with 1 x 2 waves; else edge 64), or 2007, 2008 (FP32, the output split
  * into parts of 96 x 192 with 2 x 4 waves or 96 x 96 with 2 x 2 waves, one
- * workgroup per part; any size), or 2010, 2009 (the parts of 2007, 2008 with each FP32
- * product formed from three-way bf16 splits of both factors on the bf16 matrix cores,
- * six partial products accumulated in FP32: FP32 accuracy).  Results do
+ * workgroup per part; any size), or 2010, 2009, 2011 (parts of 96 x 192, 96 x 96 and
+ * 128 x 96 with each FP32 product formed from three-way bf16 splits of both factors on the
+ * bf16 matrix cores, six partial products accumulated in FP32: FP32 accuracy).  Results do
  * not depend on the shapes beyond rounding.  Errors: EINVAL. */
 imex_status imex_set_launch_shapes(imex_ctx* ctx, const int in[4]);
 

@@ -981,7 +981,7 @@ imex_status imex_set_launch_shapes(imex_ctx* c, const int in[4]) {
   if (in[0] != 0 && !dg_tile_valid(c->K, in[0])) return fail(c, IMEX_EINVAL, "elements per residual workgroup");
   for (int g = 0; g < 3; ++g) {
     const int t = in[1 + g];
-    if (t != 0 && t != 32 && t != 64 && t != 1032 && t != 1064 && !(t >= 2001 && t <= 2010))
+    if (t != 0 && t != 32 && t != 64 && t != 1032 && t != 1064 && !(t >= 2001 && t <= 2011))
       return fail(c, IMEX_EINVAL, "GEMM tile");
   }
   c->dg_tile = in[0];

@@ -1738,6 +1738,7 @@ __host__ __device__ constexpr WholeShape whole_shape(int code) {
        : code == 2008 ? WholeShape{2, 2, 3, 3, 16, true}      // parts of 96 x 96, 256 threads
        : code == 2009 ? WholeShape{2, 2, 3, 3, 16, true, true}    // 2008 with split-bf16 products
        : code == 2010 ? WholeShape{2, 4, 3, 3, 16, true, true}    // 2007 with split-bf16 products
+       : code == 2011 ? WholeShape{4, 2, 2, 3, 16, true, true}    // parts of 128 x 96 (2004's layout), split bf16
                       : WholeShape{0, 0, 0, 0, 0, false};
 }
 // workgroups per batch entry of a whole-matrix shape (the output split into parts)
@@ -1883,6 +1884,7 @@ static hipError_t gemm_batched(hipStream_t st, int batch, int M, int N, int K, d
   }
       BF3_LAUNCH(2009)
       BF3_LAUNCH(2010)
+      BF3_LAUNCH(2011)
 #undef BF3_LAUNCH
     }
     if (tile > 1000 && tile < 2000 && K <= 128) {
@@ -3749,7 +3751,7 @@ imex_status hdg_autotune_gemm(imex_ctx* c) {
     for (int g = 0; g < 3; ++g) {
       if (g == 0 && !use_mx(c)) continue;
       float best = 1e30f;
-      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010}) {
+      for (int tile : {64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010, 2011}) {
         if (tile > 1000 && sizeof(LT) != 4) continue;
         if (tile > 2000 && !(g == 0 ? gemm_whole_fits(tile, NR, NR)
                                     : gemm_whole_fits(tile, g == 1 ? NU : NF, NF + 1)))

@@ -191,7 +191,7 @@ def test_every_gemm_variant_gives_same_result(case, precision):
         eng.close()
         return out
     ref = run(None)
-    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010] if precision == 1 else [])
+    tiles = [64, 32] + ([1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010, 2011] if precision == 1 else [])
     for t in tiles:
         e = rel_err(run({"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}), ref)
         print(case, precision, t, e)

@@ -26,10 +26,11 @@ pytestmark = pytest.mark.gpu
 BAR = {0: 1e-10, 1: 1e-9}
 # default shapes, every single code, and the combinations the autotuner picks on the full mesh
 SHAPES = [None] + [{"gemm_tile_eliminate": t, "gemm_tile_condense": t, "gemm_tile_schur": t}
-                   for t in (64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010)] + [
+                   for t in (64, 32, 1064, 1032, 2001, 2002, 2003, 2004, 2005, 2006, 2007, 2008, 2009, 2010, 2011)] + [
     {"gemm_tile_eliminate": 2008, "gemm_tile_condense": 2004, "gemm_tile_schur": 2008},
     {"gemm_tile_eliminate": 2009, "gemm_tile_condense": 2004, "gemm_tile_schur": 2009},
     {"gemm_tile_eliminate": 2010, "gemm_tile_condense": 2004, "gemm_tile_schur": 2009},
+    {"gemm_tile_eliminate": 2009, "gemm_tile_condense": 2011, "gemm_tile_schur": 2009},
     {"gemm_tile_eliminate": 2001, "gemm_tile_condense": 2004, "gemm_tile_schur": 2008},
     {"gemm_tile_eliminate": 2007, "gemm_tile_condense": 2005, "gemm_tile_schur": 2007},
 ]
