@@ -204,7 +204,7 @@ def test_invalid_launch_shapes_rejected():
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"gemm_tile_eliminate": 48})
     with pytest.raises(IMEXError):
-        eng.set_launch_shapes({"gemm_tile_schur": 2009})
+        eng.set_launch_shapes({"gemm_tile_schur": 2012})           # past the whole-matrix codes 2001..2011
     with pytest.raises(IMEXError):
         eng.set_launch_shapes({"dg_tile": 7})
     eng.close()
