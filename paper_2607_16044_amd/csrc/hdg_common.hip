@@ -257,6 +257,9 @@ __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG
     const int a = n % NP, b = n / NP;
     double l[5] = {0, 0, 0, 0, 0};
     const double sx = 2.0 / hx, sy = 2.0 / hy;
+    // the quadrature loops stay rolled: unrolled, the table reads of all 49 points are
+    // hoisted into registers and spill
+#pragma unroll 1
     for (int qj = 0; qj < NQ; ++qj)
       for (int qi = 0; qi < NQ; ++qi) {
         const int qv = qi + NQ * qj;
@@ -269,6 +272,7 @@ __global__ void __launch_bounds__(256) lift_mixed_kernel(DeviceMesh m, DeviceHDG
         l[3] += th * px;
         l[4] += th * py;
       }
+#pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       const int s = f & 1;
       const double nx = (f == 0) ? -1.0 : (f == 1 ? 1.0 : 0.0);
