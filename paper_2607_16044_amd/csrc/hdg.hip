@@ -3698,22 +3698,69 @@ static hipError_t launch_condense(imex_ctx* c) {
 
 // Right-hand side of a simplified Newton correction.  The residual assembly has put the
 // new f in the augmented column of the element rows and zeroed the facet rows' column;
+// The two products of a simplified correction for one element per workgroup:
+// X[:, NF] = K^-1 f (f the last column of the element rows), then the facet rows' last
+// column -= D X[:, NF].  16 lanes per matrix row on consecutive columns, 16 rows at a time,
+// each row's sum reduced over its 16 lanes; x and K^-1 f staged in LDS (K^-1 f rounded to
+// the storage type, as it is stored in X).
+template <int K, class T>
+__global__ void __launch_bounds__(256) resolve_kernel(size_t bs, T* __restrict__ blk, const T* __restrict__ Kinv,
+                                                      T* __restrict__ X) {
+  constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN, NF = 16 * NP, NC = NU + NF + 1;
+  constexpr int CB = (NU + 15) / 16;                         // 16-column blocks of a row
+  __shared__ double xs[NU], ys[NU];
+  const int p = blockIdx.x, tid = threadIdx.x, rq = tid >> 4, cl = tid & 15;
+  T* bp = blk + (size_t)p * bs;
+  for (int i = tid; i < NU; i += 256) xs[i] = (double)bp[(size_t)i * NC + NU + NF];
+  __syncthreads();
+  const T* Kp = Kinv + (size_t)p * NU * NU;
+  for (int r0 = 0; r0 < NU; r0 += 16) {
+    const int i = r0 + rq;
+    double acc = 0.0;
+    if (i < NU) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int c = 16 * cb + cl;
+        if (c < NU) acc += (double)Kp[(size_t)i * NU + c] * xs[c];
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (cl == 0 && i < NU) {
+      const T y = (T)acc;
+      ys[i] = (double)y;
+      X[((size_t)p * NU + i) * (NF + 1) + NF] = y;
+    }
+  }
+  __syncthreads();
+  for (int r0 = 0; r0 < NF; r0 += 16) {
+    const int r = r0 + rq;
+    double acc = 0.0;
+    if (r < NF) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int c = 16 * cb + cl;
+        if (c < NU) acc += (double)bp[(size_t)(NU + r) * NC + c] * ys[c];
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (cl == 0 && r < NF) {
+      T* hp = bp + (size_t)(NU + r) * NC + NU + NF;
+      *hp = (T)((double)*hp - acc);
+    }
+  }
+}
+
 // K^-1, X[:, :NF] = K^-1 C, D and S of the previous Jacobian are untouched:
 //   X[:, NF] = K^-1 f,  [h - D K^-1 f] column = -D X[:, NF]  (h is added from hres).
 static hipError_t launch_resolve(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
-    constexpr int NU = 4 * (KK + 1) * (KK + 1), NF = 16 * (KK + 1), NC = NU + NF + 1;
     LT* blk = la<LT>(w.blk);
     LT* Kinv = la<LT>(w.Kinv);
     LT* X = la<LT>(w.X);
-    const long long bs = (long long)blk_stride(c), sx = (long long)NU * (NF + 1);
-    hipError_t e = gemm_batched<LT>(c->stream, c->n_im, NU, 1, NU, 1.0, false, Kinv, NU, (long long)NU * NU,
-                                    blk + NU + NF, NC, bs, X + NF, NF + 1, sx, 32);
-    if (e != hipSuccess) return e;
-    e = gemm_batched<LT>(c->stream, c->n_im, NF, 1, NU, -1.0, true, blk + (size_t)NU * NC, NC, bs, X + NF, NF + 1,
-                         sx, blk + (size_t)NU * NC + NU + NF, NC, bs, 32);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((resolve_kernel<KK, LT>), dim3(c->n_im), dim3(256), 0, c->stream, blk_stride(c), blk, Kinv, X);
   }));
   return hipGetLastError();
 }

@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(64) lift_vjp_kernel(DeviceMesh m, DeviceHDG h,
     const int qi = qv % NQ, qj = qv / NQ;
     double W[4] = {0, 0, 0, 0}, pb[3] = {0, 0, 0};
     const double w = tb.W[qi] * tb.W[qj] * jac;
+#pragma unroll 1
     for (int b = 0; b < NP; ++b)
       for (int a = 0; a < NP; ++a) {
         const int n = a + NP * b;
@@ -355,6 +356,7 @@ __global__ void __launch_bounds__(64) lift_vjp_kernel(DeviceMesh m, DeviceHDG h,
 #pragma unroll
       for (int v = 0; v < 4; ++v) W[v] += tb.L[q][mm] * Uhat[((size_t)hf * 4 + v) * NP + mm];
     double pb[3] = {0, 0, 0};
+#pragma unroll 1
     for (int b = 0; b < NP; ++b)
       for (int a = 0; a < NP; ++a) {
         const int n = a + NP * b;
