@@ -145,7 +145,7 @@ def cpu_baseline(shapes=None):
     """The oracle on a bounded sample of the boundary-layer workload: a 2x16 strip of the
     same mesh family (k=4, ARS(3,4,3), HDG-MX on the 2 wall rows = 1/8 implicit like the
     full mesh), one step.  Timed on one thread, and on all host cores as independent
-    single-thread strips (one per core, up to the 16-core share of a one-GPU machine): the
+    single-thread strips (one per core, up to 16 cores, a one-GPU node's host share): the
     oracle is a serial numpy program, so the all-core rate is the aggregate throughput of
     as many strips as cores, each a different stretch of the plate."""
     import multiprocessing as mp
