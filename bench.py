@@ -664,7 +664,7 @@ FORCINGS = (3, 1)
 
 
 def pick_forcing(wl, precision, steps=3, warmup=1, newton_simplified=1):
-    """The facet-solve forcing rule (R31) with the shorter device time over a few untimed
+    """The facet-solve forcing rule (imex_options.gmres_forcing) with the shorter device time over a few untimed
     steps from the initial state: 3 (loose first corrections of each stage, tuned on the
     smooth field) or 1 (each correction's tolerance from the previous increment), which
     spends fewer GMRES iterations on rougher inputs.  Returns (rule, {rule: ms per step}).
@@ -730,8 +730,8 @@ def main():
     args = parse()
     ELIMINATE_SHAPE = args.eliminate_shape
     if args.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; how the path would shard over several GPUs is "
-                                   "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this engine runs on one GPU; the sharding over several GPUs is a design "
+                                   "only and not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2607_16044_amd import binding, workloads

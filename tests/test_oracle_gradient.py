@@ -30,7 +30,7 @@ def test_step_jvp_matches_central_differences(case):
     wl = CASES[case]()
     rng = np.random.default_rng(3)
     base = IMEXSolver(wl)
-    U0 = base.U * (1.0 + 1e-3 * rng.standard_normal(base.U.shape))     # a generic point (R27)
+    U0 = base.U * (1.0 + 1e-3 * rng.standard_normal(base.U.shape))     # a generic point, off any symmetry
     s = IMEXSolver(wl, U0=U0)
     dU = rng.standard_normal(U0.shape) * 1e-2 * np.abs(U0).max()
     dH = init_facets(dU, s.mesh, s.basis)
