@@ -2086,39 +2086,30 @@ __global__ void __launch_bounds__(256) hdg_invert_kernel(size_t blk_stride, cons
 // Column tiles are dealt round robin to the four waves; each wave updates all row tiles
 // of its columns, so a panel's pivot-row values are read and written by the same wave.
 // ---------------------------------------------------------------------------
-template <int K> struct GjiDims {
-  static constexpr int NP = K + 1, NN = NP * NP, NU = 4 * NN;
-  static constexpr int TT = (NU + 15) / 16, TN = 16 * TT;            // tiles per side, padded size
-  static constexpr int PB = 16, RPL = (NU + 63) / 64;                // pivots per panel, rows per lane
-  static_assert(NU % 4 == 0, "float4 column segments");
-  static constexpr size_t LDS = sizeof(float) * ((size_t)TN * NU + (size_t)PB * TN) + sizeof(int) * 2 * NU;
+// LDS of the blocked Gauss-Jordan on an N x N matrix: the matrix column-major with its
+// columns padded to whole 16 x 16 tiles (TN floats per column, zeros beyond N), the
+// transformation buffer [PB][TN], and the pivot tables rp, pos (N ints each).
+template <int N> struct GjbDims {
+  static constexpr int TT = (N + 15) / 16, TN = 16 * TT;             // tiles per side, padded size
+  static constexpr int PB = 16, RPL = (N + 63) / 64;                 // pivots per panel, rows per lane
+  static_assert(N % 4 == 0, "float4 column segments");
+  static constexpr size_t FLOATS = (size_t)TN * N + (size_t)PB * TN, INTS = 2 * (size_t)N;
+  static constexpr size_t BYTES = sizeof(float) * FLOATS + sizeof(int) * INTS;
 };
 
-template <int K>
-__global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const float* __restrict__ blk,
-                                                              float* __restrict__ Kinv) {
-  using D = GjiDims<K>;
-  constexpr int NU = D::NU, TT = D::TT, TN = D::TN, PB = D::PB, RPL = D::RPL;
-  constexpr int NC = NU + 16 * (K + 1) + 1;              // row stride of the element block
+// In-place inverse of the N x N matrix Am (column j at Am + j * N, columns N..TN-1 zero)
+// by the 256 threads of the workgroup; on entry Tb is zero and pos[] = -1, and the caller
+// has synchronised.  On return (synchronised) A^-1[q][c] = Am[pos[c] * N + rp[q]].
+template <int N>
+__device__ __forceinline__ void gj_blocked(float* __restrict__ Am, float* __restrict__ Tb, int* __restrict__ rp,
+                           int* __restrict__ pos, int tid) {
+  using D = GjbDims<N>;
+  constexpr int TT = D::TT, TN = D::TN, PB = D::PB, RPL = D::RPL;
   constexpr int TPW = (TT + 3) / 4;                      // tile columns per wave
-  extern __shared__ __align__(16) float gji_lds[];
-  float* Am = gji_lds;                                   // column j at Am + j * NU
-  float* Tb = Am + (size_t)TN * NU;                      // [PB][TN]: T[:, r_t] - e_{r_t}
-  int* rp = reinterpret_cast<int*>(Tb + PB * TN);        // [NU] pivot row of pivot k
-  int* pos = rp + NU;                                    // [NU] pivot index of row r (-1: not yet)
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const float* bp = blk + (size_t)blockIdx.x * bs;
-  for (int idx = tid; idx < NU * NU; idx += 256) {
-    const int r = idx / NU, cc = idx - r * NU;
-    Am[cc * NU + r] = bp[(size_t)r * NC + cc];
-  }
-  for (int idx = tid; idx < (TN - NU) * NU; idx += 256) Am[NU * NU + idx] = 0.0f;
-  for (int idx = tid; idx < PB * TN; idx += 256) Tb[idx] = 0.0f;
-  for (int idx = tid; idx < NU; idx += 256) pos[idx] = -1;
-  __syncthreads();
-  for (int p0 = 0; p0 < NU; p0 += PB) {
-    const int nb = NU - p0 < PB ? NU - p0 : PB;
+  for (int p0 = 0; p0 < N; p0 += PB) {
+    const int nb = N - p0 < PB ? N - p0 : PB;
     const int owner = (p0 / 16) & 3;                     // the wave holding the panel's tile column
     float P[RPL][PB];
     int rpan[PB];
@@ -2127,9 +2118,9 @@ __global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const f
 #pragma unroll
       for (int s = 0; s < RPL; ++s) {
         const int row = lane + 64 * s;
-        avail[s] = row < NU && pos[row < NU ? row : 0] < 0;
+        avail[s] = row < N && pos[row < N ? row : 0] < 0;
 #pragma unroll
-        for (int cc = 0; cc < PB; ++cc) P[s][cc] = (row < NU && cc < nb) ? Am[(p0 + cc) * NU + row] : 0.0f;
+        for (int cc = 0; cc < PB; ++cc) P[s][cc] = (row < N && cc < nb) ? Am[(p0 + cc) * N + row] : 0.0f;
       }
 #pragma unroll
       for (int t = 0; t < PB; ++t) {
@@ -2176,7 +2167,7 @@ __global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const f
 #pragma unroll
       for (int s = 0; s < RPL; ++s) {
         const int row = lane + 64 * s;
-        if (row < NU) {
+        if (row < N) {
 #pragma unroll
           for (int cc = 0; cc < PB; ++cc)
             Tb[cc * TN + row] = (cc < nb) ? P[s][cc] - (row == rpan[cc] ? 1.0f : 0.0f) : 0.0f;
@@ -2198,7 +2189,7 @@ __global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const f
 #pragma unroll
       for (int ks = 0; ks < PB / 4; ++ks) {
         const int t = 4 * ks + lk;
-        bvs[q][ks] = (t < nb && wv + 4 * q < TT) ? Am[col * NU + rp[p0 + (t < nb ? t : 0)]] : 0.0f;
+        bvs[q][ks] = (t < nb && wv + 4 * q < TT) ? Am[col * N + rp[p0 + (t < nb ? t : 0)]] : 0.0f;
       }
     }
 #pragma unroll
@@ -2212,10 +2203,10 @@ __global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const f
 #pragma unroll
       for (int ti = 0; ti < TT; ++ti) {
         const int r0 = 16 * ti + 4 * lk;
-        const bool rows_ok = r0 < NU;
+        const bool rows_ok = r0 < N;
         mf_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if (rows_ok) {
-          const float4 cv = *reinterpret_cast<const float4*>(Am + col * NU + r0);
+          const float4 cv = *reinterpret_cast<const float4*>(Am + col * N + r0);
           acc = mf_f4{cv.x, cv.y, cv.z, cv.w};
         }
 #pragma unroll
@@ -2228,12 +2219,41 @@ __global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const f
             o = make_float4(tc[0] + (r0 == prow_t ? 1.0f : 0.0f), tc[1] + (r0 + 1 == prow_t ? 1.0f : 0.0f),
                             tc[2] + (r0 + 2 == prow_t ? 1.0f : 0.0f), tc[3] + (r0 + 3 == prow_t ? 1.0f : 0.0f));
           }
-          *reinterpret_cast<float4*>(Am + col * NU + r0) = o;
+          *reinterpret_cast<float4*>(Am + col * N + r0) = o;
         }
       }
     }
   }
   __syncthreads();
+}
+
+template <int K> struct GjiDims {
+  static constexpr int NU = 4 * (K + 1) * (K + 1);
+  static constexpr size_t LDS = GjbDims<NU>::BYTES;
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) hdg_invert_mfma_kernel(size_t bs, const float* __restrict__ blk,
+                                                              float* __restrict__ Kinv) {
+  using D = GjbDims<GjiDims<K>::NU>;
+  constexpr int NU = GjiDims<K>::NU, TN = D::TN, PB = D::PB;
+  constexpr int NC = NU + 16 * (K + 1) + 1;              // row stride of the element block
+  extern __shared__ __align__(16) float gji_lds[];
+  float* Am = gji_lds;                                   // column j at Am + j * NU
+  float* Tb = Am + (size_t)TN * NU;                      // [PB][TN]: T[:, r_t] - e_{r_t}
+  int* rp = reinterpret_cast<int*>(Tb + PB * TN);        // [NU] pivot row of pivot k
+  int* pos = rp + NU;                                    // [NU] pivot index of row r (-1: not yet)
+  const int tid = threadIdx.x;
+  const float* bp = blk + (size_t)blockIdx.x * bs;
+  for (int idx = tid; idx < NU * NU; idx += 256) {
+    const int r = idx / NU, cc = idx - r * NU;
+    Am[cc * NU + r] = bp[(size_t)r * NC + cc];
+  }
+  for (int idx = tid; idx < (TN - NU) * NU; idx += 256) Am[NU * NU + idx] = 0.0f;
+  for (int idx = tid; idx < PB * TN; idx += 256) Tb[idx] = 0.0f;
+  for (int idx = tid; idx < NU; idx += 256) pos[idx] = -1;
+  __syncthreads();
+  gj_blocked<NU>(Am, Tb, rp, pos, tid);
   float* Kp = Kinv + (size_t)blockIdx.x * NU * NU;
   for (int idx = tid; idx < NU * NU; idx += 256) {
     const int q = idx / NU, cc = idx - q * NU;
@@ -2311,7 +2331,8 @@ __device__ __forceinline__ T s_gather(const T* __restrict__ S, const long long* 
 // through the horizontal slots (first NH unknowns).  Forward block elimination
 // with explicit inverses: D_r = A_r - B_r D_{r-1}^-1 C_{r-1} on the NH x NH
 // corner, G_r = B_r D_{r-1}^-1.  The diagonal block lives in register tiles
-// (GJ<NB>), the previous inverse, B_r / G_r and C_{r-1} in LDS.  Stored for the
+// (GJ<NB>), the previous inverse, B_r / G_r and C_{r-1} in LDS; it is inverted by the
+// register Gauss-Jordan in FP64 and by the blocked one (gj_blocked) in FP32.  Stored for the
 // apply: D_r^-1, G_r and E_r = D_r^-1 C_r, each transposed for coalesced
 // matrix-vector products.
 template <int K, class T>
@@ -2481,22 +2502,53 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
             if (r0 + i < NH && c0 + j < NH) A[i][j] -= Us[(r0 + i) * NH + c0 + j];
       }
     }
-    G::invert(A, gsh, tid);
-    // D_r^-1: transposed to global, row-major (un-permuted) to LDS for the next super-row
     T* Dg = Wd + (size_t)g * NB * NB;
-    if (own) {
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32: the blocked Gauss-Jordan (pivots of a panel within one wave, rank-16 updates
+      // on the matrix cores) on the block column-major in LDS; one window per CU leaves the
+      // register Gauss-Jordan waiting on its barriers at every pivot
+      using GB = GjbDims<NB>;
+      float* Am = Us + NH * NH;
+      float* Tb = Am + (size_t)GB::TN * NB;
+      int* rpb = reinterpret_cast<int*>(Tb + GB::PB * GB::TN);
+      int* posb = rpb + NB;
+      if (own) {
 #pragma unroll
-      for (int i = 0; i < G::RT; ++i) {
-        const int row = gsh.pos[r0 + i];
+        for (int i = 0; i < G::RT; ++i)
 #pragma unroll
-        for (int j = 0; j < G::CT; ++j) {
-          const int col = gsh.rp[c0 + j];
-          Dg[(size_t)col * NB + row] = A[i][j];
-          Ds[row * NB + col] = A[i][j];
+          for (int j = 0; j < G::CT; ++j) Am[(c0 + j) * NB + r0 + i] = A[i][j];
+      }
+      for (int idx = tid; idx < (GB::TN - NB) * NB; idx += nt) Am[NB * NB + idx] = 0.0f;
+      for (int idx = tid; idx < GB::PB * GB::TN; idx += nt) Tb[idx] = 0.0f;
+      for (int idx = tid; idx < NB; idx += nt) posb[idx] = -1;
+      __syncthreads();
+      gj_blocked<NB>(Am, Tb, rpb, posb, tid);
+      // D_r^-1[q][c] = Am[pos[c]][rp[q]]: transposed to global (coalesced over q), row-major
+      // to LDS for the next super-row
+      for (int idx = tid; idx < NB * NB; idx += nt) {
+        const int c = idx / NB, q = idx - c * NB;
+        const float v = Am[posb[c] * NB + rpb[q]];
+        Dg[(size_t)c * NB + q] = v;
+        Ds[q * NB + c] = v;
+      }
+      __syncthreads();
+    } else {
+      G::invert(A, gsh, tid);
+      // D_r^-1: transposed to global, row-major (un-permuted) to LDS for the next super-row
+      if (own) {
+#pragma unroll
+        for (int i = 0; i < G::RT; ++i) {
+          const int row = gsh.pos[r0 + i];
+#pragma unroll
+          for (int j = 0; j < G::CT; ++j) {
+            const int col = gsh.rp[c0 + j];
+            Dg[(size_t)col * NB + row] = A[i][j];
+            Ds[row * NB + col] = A[i][j];
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -3851,7 +3903,9 @@ static hipError_t launch_ras_factor(imex_ctx* c) {
   Workspace& w = c->ws;
   HDG_DISPATCH(c->K, LA_DISPATCH(c, {
     constexpr int NFF = 4 * (KK + 1), NB = 5 * NFF, NH = 2 * NFF;
-    const size_t shm = sizeof(LT) * ((size_t)NB * NB + 2 * (size_t)NH * NB + (size_t)NH * NH);
+    // the FP32 kernel also holds the blocked Gauss-Jordan's block and tables
+    const size_t shm = sizeof(LT) * ((size_t)NB * NB + 2 * (size_t)NH * NB + (size_t)NH * NH) +
+                       (std::is_same<LT, float>::value ? GjbDims<NB>::BYTES : 0);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ras_factor_kernel<KK, LT>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((ras_factor_kernel<KK, LT>), dim3(c->n_win), dim3(256), shm, c->stream, c->dhdg(),
