@@ -999,123 +999,163 @@ __global__ void __launch_bounds__(256) CT_WAVES hdg_contract_kernel(DeviceMesh m
     for (int i = tid; i < 4 * NQ * 12; i += nt) (&sh.u.f.JLF[0][0][0][0])[i] = rp[R::JLF + i];
   }
   T* G = sh.u.f.G;
-  // G[((f * 4 + v) * NV2 + v2) * NN + x * NP + y] = sum_q TLL[q][x][y] JF[f][q][r0 + v][c0 + v2]
-  auto line_sums = [&](int NV2, int r0, int c0) {
-    const int n = 4 * 4 * NV2 * NN;
-    for (int i = tid; i < n; i += nt) {
-      const int xy = i % NN, x = xy / NP, y = xy % NP, fvv = i / NN, v2 = fvv % NV2, fv = fvv / NV2;
+  // G[((f * 4 + v) * NV2 + v2) * NN + x * NP + y] = sum_q TLL[q][x][y] JF[f][q][r0 + v][c0 + v2].
+  // A thread keeps one node pair (x, y), with its NQ table entries in registers, and
+  // forms the sums of several (f, v, v2).
+  auto line_sums = [&](auto nv2, int r0, int c0) {
+    constexpr int NV2 = decltype(nv2)::value;
+    const int TPX = nt / NN, xy = tid % NN, sl = tid / NN;
+    if (sl >= TPX) return;
+    const int x = xy / NP, y = xy % NP;
+    T tl[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tl[q] = sh.TLL[q][x][y];
+    for (int fvv = sl; fvv < 16 * NV2; fvv += TPX) {
+      const int v2 = fvv % NV2, fv = fvv / NV2;
       const T* j = &sh.u.f.JF[fv >> 2][0][r0 + (fv & 3)][c0 + v2];
       T acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) acc += sh.TLL[q][x][y] * j[q * 64];
-      G[i] = acc;
+      for (int q = 0; q < NQ; ++q) acc += tl[q] * j[q * 64];
+      G[fvv * NN + xy] = acc;
+    }
+  };
+  // Rows of the facet side (f, v, mm) against a column of the element side (w, a2, b2) with
+  // NW line sums per face row: a thread owns the column and takes whole (f, v) row groups,
+  // the NP rows mm of a group unrolled.  Entry = edge value of the column's basis function
+  // on face f (LE(s, a2) on x-faces, LE(s, b2) on y-faces) times the line sum over (mm, the
+  // other index).  Writes dst[(row0 + row) * ld + col].
+  auto face_rows = [&](auto nw, T* dst, int ld, int row0) {
+    constexpr int NW = decltype(nw)::value, NCOL = NW * NN;
+    const int lanes = nt / NCOL, lane = tid / NCOL, col = tid % NCOL;
+    if (lane >= lanes) return;
+    const int w = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
+    const T ex0 = wlx * sh.LE[0][a2], ex1 = wlx * sh.LE[1][a2];
+    const T ey0 = wly * sh.LE[0][b2], ey1 = wly * sh.LE[1][b2];
+    for (int fv = lane; fv < 16; fv += lanes) {
+      const int f = fv >> 2;
+      const T e = f == 0 ? ex0 : (f == 1 ? ex1 : (f == 2 ? ey0 : ey1));
+      const T* g = G + (fv * NW + w) * NN + (f < 2 ? b2 : a2);
+      T* d = dst + (size_t)(row0 + fv * NP) * ld + col;
+#pragma unroll
+      for (int mm = 0; mm < NP; ++mm) d[(size_t)mm * ld] = e * g[mm * NP];
     }
   };
   if (grp == 3) {
-    // C = dt_a dR/dUhat (NU x NF): row (v, a, b), column (f, v2, m2); the x-faces pair
-    // LE(a) with the line sum over (b, m2), the y-faces LE(b) with the sum over (a, m2)
+    // C = dt_a dR/dUhat (NU x NF): row (v, b, a), column (f, v2, m2); the x-faces pair
+    // LE(a) with the line sum over (b, m2), the y-faces LE(b) with the sum over (a, m2).
+    // A thread owns the column and takes whole (v, b) row groups, the rows a unrolled.
     __syncthreads();
-    line_sums(4, 0, 4);
+    line_sums(std::integral_constant<int, 4>{}, 0, 4);
     __syncthreads();
     {
       const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
       if (lane < lanes) {
         const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
-        const T sc = dta * ((f < 2) ? wlx : wly);
+        const bool xf = f < 2;
+        const T sc = dta * (xf ? wlx : wly);
+        T le[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) le[a] = sc * sh.LE[s][a];
         const T* g = G + (f * 16 + v2) * NN + m2;
-        for (int row = lane; row < NU; row += lanes) {
-          const int v = row / NN, n = row % NN, a = n % NP, b = n / NP;
-          const T val = (f < 2) ? sh.LE[s][a] * g[v * 4 * NN + b * NP] : sh.LE[s][b] * g[v * 4 * NN + a * NP];
-          bp[(size_t)row * NC + NU + col] = sc * val;
+        for (int vb = lane; vb < 4 * NP; vb += lanes) {
+          const int v = vb / NP, b = vb % NP;
+          const T lb = sc * sh.LE[s][b];
+          const T* gv = g + v * 4 * NN;
+          T* d = bp + (size_t)(v * NN + b * NP) * NC + NU + col;
+#pragma unroll
+          for (int a = 0; a < NP; ++a)
+            d[(size_t)a * NC] = xf ? le[a] * gv[b * NP] : lb * gv[a * NP];
         }
       }
     }
-    // D = dh/dU (NF x NU): row (f, v, mm), column (v2, a2, b2)
+    // D = dh/dU (NF x NU): row (f, v, mm), column (v2, b2, a2)
     __syncthreads();
-    line_sums(4, 4, 0);
+    line_sums(std::integral_constant<int, 4>{}, 4, 0);
     __syncthreads();
-    {
-      const int lanes = nt / NU, lane = tid / NU, col = tid % NU;
-      if (lane < lanes) {
-        const int v2 = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-        for (int row = lane; row < NF; row += lanes) {
-          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
-          const T* g = G + ((f * 4 + v) * 4 + v2) * NN + mm * NP;
-          const T val = (f < 2) ? wlx * sh.LE[s][a2] * g[b2] : wly * sh.LE[s][b2] * g[a2];
-          bp[(size_t)(NU + row) * NC + col] = val;
-        }
-      }
-    }
+    face_rows(std::integral_constant<int, 4>{}, bp, NC, NU);
     // E = dh/dUhat (NF x NF, block diagonal over the faces): row (f, v, mm), column (f2, v2, m2)
     __syncthreads();
-    line_sums(4, 4, 4);
+    line_sums(std::integral_constant<int, 4>{}, 4, 4);
     __syncthreads();
     {
       const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
       if (lane < lanes) {
         const int f2 = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP;
         const T wl = (f2 < 2) ? wlx : wly;
-        for (int row = lane; row < NF; row += lanes) {
-          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP;
-          const T val = (f == f2) ? wl * G[((f * 4 + v) * 4 + v2) * NN + mm * NP + m2] : T(0);
-          bp[(size_t)(NU + row) * NC + NU + col] = val;
+        for (int fv = lane; fv < 16; fv += lanes) {
+          const int f = fv >> 2;
+          const bool on = f == f2;
+          const T* g = G + (fv * 4 + v2) * NN + m2;
+          T* d = bp + (size_t)(NU + fv * NP) * NC + NU + col;
+#pragma unroll
+          for (int mm = 0; mm < NP; ++mm) d[(size_t)mm * NC] = on ? wl * g[mm * NP] : T(0);
         }
       }
     }
     return;
   }
   if constexpr (MX) {
-    // A32 = dh/dQ (NF x NQM, rows NU.. of Lm): row (f, v, mm), column (c, a2, b2)
+    // A32 = dh/dQ (NF x NQM, rows NU.. of Lm): row (f, v, mm), column (c, b2, a2)
     __syncthreads();
-    line_sums(5, 0, 0);
+    line_sums(std::integral_constant<int, 5>{}, 0, 0);
     __syncthreads();
-    {
-      const int lanes = nt / NQM, lane = tid / NQM, col = tid % NQM;
-      if (lane < lanes) {
-        const int c = col / NN, n2 = col % NN, a2 = n2 % NP, b2 = n2 / NP;
-        for (int row = lane; row < NF; row += lanes) {
-          const int f = row / NFF, v = (row % NFF) / NP, mm = row % NP, s = f & 1;
-          const T* g = G + ((f * 4 + v) * 5 + c) * NN + mm * NP;
-          const T val = (f < 2) ? wlx * sh.LE[s][a2] * g[b2] : wly * sh.LE[s][b2] * g[a2];
-          Lm[(size_t)(NU + row) * NQM + col] = val;
-        }
-      }
-    }
-    // A23 = M_Q^-1 dl/dUhat (NQM x NF, columns NU.. of Rm): row (c, a, b), column (f, v2, m2).
+    face_rows(std::integral_constant<int, 5>{}, Lm, NQM, NU);
+    // A23 = M_Q^-1 dl/dUhat (NQM x NF, columns NU.. of Rm): row (c, b, a), column (f, v2, m2).
     // The line sums take the lifted normal traces g_q = sum_p cn_p JLF[f][q][p][v2] with
-    // cn_p = cx_p n_x + cy_p n_y of component c:
+    // cn_p = cx_p n_x + cy_p n_y of component c (tabulated first):
     // G[((f * 5 + c) * 4 + v2) * NN + x * NP + y] = sum_q TLL[q][x][y] g_q
-    __syncthreads();
-    for (int i = tid; i < 4 * 5 * 4 * NN; i += nt) {
-      const int xy = i % NN, x = xy / NP, y = xy % NP, fcv = i / NN, v2 = fcv % 4, c = (fcv / 4) % 5, f = fcv / 20;
+    __shared__ T CN[4][5][3];
+    if (tid < 20) {
+      const int f = tid / 5, c = tid % 5;
       double nxd, nyd;
       fnormal(f, nxd, nyd);
-      const T nx = T(nxd), ny = T(nyd);
       T cx[3], cy[3];
       lift_coef(c, cx, cy);
-      T cn[3];
-      for (int pp = 0; pp < 3; ++pp) cn[pp] = cx[pp] * nx + cy[pp] * ny;
-      T acc = 0.0;
+      for (int pp = 0; pp < 3; ++pp) CN[f][c][pp] = cx[pp] * T(nxd) + cy[pp] * T(nyd);
+    }
+    __syncthreads();
+    {
+      const int TPX = nt / NN, xy = tid % NN, sl = tid / NN;
+      if (sl < TPX) {
+        const int x = xy / NP, y = xy % NP;
+        T tl[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const T gq = cn[0] * sh.u.f.JLF[f][q][0][v2] + cn[1] * sh.u.f.JLF[f][q][1][v2] +
-                     cn[2] * sh.u.f.JLF[f][q][2][v2];
-        acc += sh.TLL[q][x][y] * gq;
+        for (int q = 0; q < NQ; ++q) tl[q] = sh.TLL[q][x][y];
+        for (int fcv = sl; fcv < 80; fcv += TPX) {
+          const int v2 = fcv % 4, c = (fcv / 4) % 5, f = fcv / 20;
+          const T c0 = CN[f][c][0], c1 = CN[f][c][1], c2 = CN[f][c][2];
+          T acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            acc += tl[q] * (c0 * sh.u.f.JLF[f][q][0][v2] + c1 * sh.u.f.JLF[f][q][1][v2] +
+                            c2 * sh.u.f.JLF[f][q][2][v2]);
+          G[fcv * NN + xy] = acc;
+        }
       }
-      G[i] = acc;
     }
     __syncthreads();
     {
       const int lanes = nt / NF, lane = tid / NF, col = tid % NF;
       if (lane < lanes) {
         const int f = col / NFF, v2 = (col % NFF) / NP, m2 = col % NP, s = f & 1;
-        const T wl = (f < 2) ? wlx : wly;
-        for (int row = lane; row < NQM; row += lanes) {
-          const int c = row / NN, n = row % NN, a = n % NP, b = n / NP;
+        const bool xf = f < 2;
+        const T wl = xf ? wlx : wly;
+        T le[NP], mw[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          le[a] = wl * sh.LE[s][a];
+          mw[a] = T(1) / (sh.NW[a] * jac);
+        }
+        for (int cb = lane; cb < 5 * NP; cb += lanes) {
+          const int c = cb / NP, b = cb % NP;
+          const T lb = wl * sh.LE[s][b];
+          // -M_Q^-1 on row (c, a, b): M_Q is diagonal, NW(a) NW(b) |J| (twice that for c = 1)
+          const T mb = -((c == 1) ? T(0.5) : T(1)) / sh.NW[b];
           const T* g = G + ((f * 5 + c) * 4 + v2) * NN + m2;
-          const T edge = (f < 2) ? wl * sh.LE[s][a] * g[b * NP] : wl * sh.LE[s][b] * g[a * NP];
-          const T minv = T(1) / (((c == 1) ? T(2) : T(1)) * sh.NW[a] * sh.NW[b] * jac);
-          Rm[(size_t)row * NR + NU + col] = -minv * edge;
+          T* d = Rm + (size_t)(c * NN + b * NP) * NR + NU + col;
+#pragma unroll
+          for (int a = 0; a < NP; ++a)
+            d[(size_t)a * NR] = mb * mw[a] * (xf ? le[a] * g[b * NP] : lb * g[a * NP]);
         }
       }
     }
