@@ -2592,6 +2592,17 @@ __global__ void __launch_bounds__(256) ras_factor_kernel(DeviceHDG h, const T* _
   }
 }
 
+// Workgroup barrier for exchanges through LDS only.  __syncthreads() also orders global
+// memory, which makes every wave wait for all of its outstanding global loads, prefetches
+// included; the k = 4 Schwarz sweep exchanges only LDS values between threads (each thread
+// reads back only global values it wrote itself), so its barriers wait for LDS operations
+// alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sweep sizes of a super-row of the facet preconditioner's windows: NB unknowns (five
 // facet slots), the first NH of them (the two horizontal slots) coupling consecutive
 // super-rows; per super-row NSV doubles of Wy, of which the apply keeps w_r at offset NB.
@@ -2778,12 +2789,16 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
   const int gr0 = (t % RG) * V, gq = t / RG;                  // G
   const int e0 = (t % RE) * V, eq = t / RE;                   // E
   const bool dON = t < SD * RD, gON = t < SG * RG, eON = t < SE * RE;
-  auto xval = [&](int g, int i) -> double {
-    const int f = h.win_slot[5 * g + i / NFF];
-    return f >= 0 ? x[(size_t)f * NFF + i % NFF] : 0.0;
-  };
+  // The window slot of this thread's row is loaded a super-row before the vector value it
+  // addresses, and both before the factor prefetch: the vector memory counter completes in
+  // order, so waiting for a slot issued after the prefetch would wait for the prefetch too.
+  const int ta = t < NB ? t / NFF : 0;
+  auto slot = [&](int g) { return h.win_slot[5 * g + ta]; };
+  auto own = [&](int g) { return h.win_own[5 * g + ta]; };
+  auto xat = [&](int f) -> double { return (t < NB && f >= 0) ? x[(size_t)f * NFF + t % NFF] : 0.0; };
   T gr[CG][V], dr[CD][V];
-  // lanes without an entry read the block's first entry and take zero (branch-free loads)
+  // lanes without an entry read the block's first entry, which the products multiply by
+  // zero: selecting zero right after the load would wait for it and stall the prefetch
   auto load_fwd = [&](int g) {
     const T* Gg = Wg + (size_t)g * NH * NB;                  // Gg[k * NH + i] = G_r[i][k]
     const T* Dg = Wd + (size_t)g * NB * NB;                  // Dg[k * NB + i] = D_r^-1[i][k]
@@ -2792,23 +2807,20 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
       const int k = gq * CG + kk;
       const bool ok = gON && g > g0 && k < NB;
       L::get(Gg + (ok ? (size_t)k * NH + gr0 : 0), gr[kk]);
-#pragma unroll
-      for (int v = 0; v < V; ++v) gr[kk][v] = ok ? gr[kk][v] : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < CD; ++kk) {
       const int k = dq * CD + kk;
       const bool ok = dON && k < NB;
       L::get(Dg + (ok ? (size_t)k * NB + d0 : 0), dr[kk]);
-#pragma unroll
-      for (int v = 0; v < V; ++v) dr[kk][v] = ok ? dr[kk][v] : T(0);
     }
   };
+  double xn = xat(slot(g0));
+  int sn = slot(g0 + 1 < g1 ? g0 + 1 : g0);                 // slot of the next super-row
   load_fwd(g0);
-  double xn = t < NB ? xval(g0, t) : 0.0;
   for (int g = g0; g < g1; ++g) {
     if (t < NB) yv[t] = xn;
-    __syncthreads();
+    lds_barrier();
     T gc[CG][V], dc[CD][V];
 #pragma unroll
     for (int kk = 0; kk < CG; ++kk)
@@ -2818,9 +2830,13 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
     for (int kk = 0; kk < CD; ++kk)
 #pragma unroll
       for (int v = 0; v < V; ++v) dc[kk][v] = dr[kk][v];
+    // (the slot loads are unconditional, with the index clamped, so that the loaded
+    // register is the loop-carried one and no copy waits for it)
+    const int s1 = sn;
+    sn = slot(g + 2 < g1 ? g + 2 : g);
     if (g + 1 < g1) {
+      xn = xat(s1);
       load_fwd(g + 1);
-      xn = t < NB ? xval(g + 1, t) : 0.0;
     }
     if (g > g0) {
       if (gON) {
@@ -2837,14 +2853,14 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
 #pragma unroll
         for (int v = 0; v < V; ++v) pg[gq][gr0 + v] = a[v];
       }
-      __syncthreads();
+      lds_barrier();
       if (t < NH) {
         double a = 0.0;
 #pragma unroll
         for (int q = 0; q < SG; ++q) a += pg[q][t];
         yv[t] -= a;
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (dON) {
       double a[V];
@@ -2861,7 +2877,7 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
       for (int v = 0; v < V; ++v) pd[dq][d0 + v] = a[v];
     }
     if (t < NB) prev[t] = yv[t];
-    __syncthreads();
+    lds_barrier();
     if (t < NB) {
       double a = 0.0;
 #pragma unroll
@@ -2878,13 +2894,16 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
       const int k = eq * CE + kk;
       const bool ok = eON && k < NH;
       L::get(Eg + (ok ? (size_t)k * NB + e0 : 0), er[kk]);
-#pragma unroll
-      for (int v = 0; v < V; ++v) er[kk][v] = ok ? er[kk][v] : T(0);
     }
   };
+  // slot and ownership of the super-row, loaded a step ahead (before the E prefetch)
+  int bs = slot(g1 - 1), bo = own(g1 - 1);
   if (g1 - 2 >= g0) load_bwd(g1 - 2);
   for (int g = g1 - 1; g >= g0; --g) {
+    const int fs = bs, fo = bo;
     double v = t < NB ? Wy[(size_t)g * D::NSV + NB + t] : 0.0;
+    bs = slot(g - 1 >= g0 ? g - 1 : g);
+    bo = own(g - 1 >= g0 ? g - 1 : g);
     if (g < g1 - 1) {
       T ec[CE][V];
 #pragma unroll
@@ -2906,20 +2925,18 @@ __global__ void __launch_bounds__(256) ras_apply16_kernel(DeviceHDG h, const T* 
 #pragma unroll
         for (int u = 0; u < V; ++u) pe[eq][e0 + u] = a[u];
       }
-      __syncthreads();
+      lds_barrier();
       if (t < NB) {
 #pragma unroll
         for (int q = 0; q < SE; ++q) v -= pe[q][t];
       }
     }
-    __syncthreads();                                         // zn and pe free again
+    lds_barrier();                                           // zn and pe free again
     if (t < NB) {
       if (t < NH) zn[t] = v;
-      const int a = t / NFF;
-      const int f = h.win_slot[5 * g + a];
-      if (f >= 0 && h.win_own[5 * g + a]) z[(size_t)f * NFF + t % NFF] = v;
+      if (fs >= 0 && fo) z[(size_t)fs * NFF + t % NFF] = v;
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
