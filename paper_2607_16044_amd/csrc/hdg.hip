@@ -1520,23 +1520,22 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
   constexpr int NLA = BM * KB / NT, NLB = KB * BN / NT;
   float ra[NLA], rb[NLB];
   // branch-free loads: 32-bit offsets from the entry's base, lanes outside the matrix
-  // read its first element and take zero
+  // read its first element, zeroed when staged (a select right after the load would wait
+  // for it and keep the next panel's loads from overlapping the matrix products)
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NLA; ++u) {
       const int idx = tid + NT * u;
       const int r = m0 + idx / KB, gk = k0 + idx % KB;
       const bool ok = r < M && gk < Kd;
-      const float v = Ab[ok ? r * lda + gk : 0];
-      ra[u] = ok ? v : 0.0f;
+      ra[u] = Ab[ok ? r * lda + gk : 0];
     }
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
       const int idx = tid + NT * u;
       const int gk = k0 + idx / BN, cc = n0 + idx % BN;
       const bool ok = gk < Kd && cc < N;
-      const float v = Bb[ok ? gk * ldb + cc : 0];
-      rb[u] = ok ? v : 0.0f;
+      rb[u] = Bb[ok ? gk * ldb + cc : 0];
     }
   };
   typename MF::V acc[SM][SN];
@@ -1549,12 +1548,12 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_whole_kernel(int batch, int
 #pragma unroll
     for (int u = 0; u < NLA; ++u) {
       const int idx = tid + NT * u;
-      sa[idx / KB][idx % KB] = ra[u];
+      sa[idx / KB][idx % KB] = (m0 + idx / KB < M && k0 + idx % KB < Kd) ? ra[u] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
       const int idx = tid + NT * u;
-      sb[idx / BN][idx % BN] = rb[u];
+      sb[idx / BN][idx % BN] = (k0 + idx / BN < Kd && n0 + idx % BN < N) ? rb[u] : 0.0f;
     }
     __syncthreads();
     if (k0 + KB < Kd) fetch(k0 + KB);
@@ -1636,7 +1635,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M
   const float* Bb = B + bz * sB;
   float* Cb = C + bz * sC;
   // each thread stages pairs of consecutive k values (one packed conversion, one 32-bit
-  // LDS store per bf16 plane)
+  // LDS store per bf16 plane).  Entries outside the matrices are loaded from a clamped
+  // address and zeroed when staged, not when loaded: a select right after a load waits
+  // for it, which would keep the next panel's loads from overlapping the matrix products.
   constexpr int PA = BM * KB / 2, PBN = BN * KB / 2;
   constexpr int NLA = (PA + NT - 1) / NT, NLB = (PBN + NT - 1) / NT;
   float ra[NLA][2], rb[NLB][2];
@@ -1649,8 +1650,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const bool ok = in && gk + e < Kd;
-        const float v = Ab[ok ? r * lda + gk + e : 0];
-        ra[u][e] = ok ? v : 0.0f;
+        ra[u][e] = Ab[ok ? r * lda + gk + e : 0];
       }
     }
 #pragma unroll
@@ -1661,8 +1661,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const bool ok = in && gk + e < Kd;
-        const float v = Bb[ok ? (gk + e) * ldb + cc : 0];
-        rb[u][e] = ok ? v : 0.0f;
+        rb[u][e] = Bb[ok ? (gk + e) * ldb + cc : 0];
       }
     }
   };
@@ -1691,8 +1690,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M
       const int idx = tid + NT * u;
       if (idx < PA) {
         const int r = idx / (KB / 2), kk = 2 * (idx % (KB / 2));
+        const bool rin = m0 + r < M;
         unsigned int w[3];
-        split_pair(ra[u][0], ra[u][1], w);
+        split_pair(rin && k0 + kk < Kd ? ra[u][0] : 0.0f, rin && k0 + kk + 1 < Kd ? ra[u][1] : 0.0f, w);
 #pragma unroll
         for (int q = 0; q < 3; ++q) *reinterpret_cast<unsigned int*>(&sa[q][r][kk]) = w[q];
       }
@@ -1702,8 +1702,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_bf3_kernel(int batch, int M
       const int idx = tid + NT * u;
       if (idx < PBN) {
         const int kk = 2 * (idx / BN), cc = idx % BN;
+        const bool cin = n0 + cc < N;
         unsigned int w[3];
-        split_pair(rb[u][0], rb[u][1], w);
+        split_pair(cin && k0 + kk < Kd ? rb[u][0] : 0.0f, cin && k0 + kk + 1 < Kd ? rb[u][1] : 0.0f, w);
 #pragma unroll
         for (int q = 0; q < 3; ++q) *reinterpret_cast<unsigned int*>(&sb[q][cc][kk]) = w[q];
       }
